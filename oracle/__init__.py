@@ -1,0 +1,14 @@
+"""CPU reference implementation ("oracle") of the DtN / Jacobian hot path.
+
+TEST INFRASTRUCTURE ONLY: only tests/, the smoke check and the CPU-baseline leg of
+the benchmark may import it.  The product path (paper_1210_5672_amd) never does,
+and the two share no code.
+
+  ww_oracle.py : FP64 reference (numpy, numpy.fft, scipy LU), every function cites
+                 the passage of the paper it follows.
+  xprec.py     : the same reference run in 34-digit mpmath arithmetic, to measure
+                 the FP64 rounding floor on small problems.
+
+Parity status: every function is pinned by tests/test_oracle_pins.py (closed forms,
+printed linear periods, invariants, central differences, extended precision).
+"""
