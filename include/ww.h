@@ -1,0 +1,137 @@
+/*
+ * ww.h -- C ABI of the MI355X (gfx950) engine for the Dirichlet-Neumann / Jacobian hot
+ * path of the overdetermined shooting method for standing water waves
+ * (Wilkening & Yu, "Overdetermined shooting methods for computing standing water waves
+ * with spectral accuracy").
+ *
+ * Conventions shared by every entry point
+ * ----------------------------------------
+ *  - Grid: alpha_j = 2 pi j / N, j = 0..N-1 (uniform mesh, x = alpha); N even, of the
+ *    form 2^a 3^b, 16 <= N <= n_max <= 2048.
+ *  - Surface: `surface` / eta is the displacement from the still level.  At finite
+ *    mean depth h the surface height is h + eta and the bottom is y = 0 (App. A);
+ *    h = INFINITY (or h <= 0) selects infinite depth.
+ *  - Arrays are column-major doubles.  A state vector is 2N doubles [eta | phi].
+ *  - Pointers marked "device" are device memory of the GPU current when the context
+ *    was created; "host" pointers are host memory.  The caller owns every array it
+ *    passes; the library keeps no caller pointer after a call returns, except the
+ *    stream.  Input and output arrays must not alias.
+ *  - All GPU work is enqueued on the context's stream (the caller's, normally torch's
+ *    current stream).  Calls that return a host scalar (f, df/dT) or report a device
+ *    status (pivot guard, non-finite state) synchronise that stream; the others are
+ *    stream-ordered.
+ *  - Return value: 0 on success, a negative WW_E* code otherwise; ww_last_error()
+ *    returns a thread-local message for the last failure.
+ */
+#ifndef WW_H
+#define WW_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ww_ctx ww_ctx;
+
+/* status codes */
+#define WW_OK 0
+#define WW_EINVAL (-1)     /* bad argument: null pointer, N not even / not 2^a 3^b / > n_max,
+                              nrhs or M too large, non-explicit tableau */
+#define WW_ENOSETUP (-2)   /* dtn_solve_multi before dtn_setup, shoot_* before shoot_setup */
+#define WW_EHIP (-3)       /* HIP runtime failure; the message carries the HIP error string */
+#define WW_EDOMAIN (-4)    /* finite depth with surface height h + eta <= 0 somewhere */
+#define WW_ENONFINITE (-5) /* NaN or Inf in the marched state */
+#define WW_EPIVOT (-6)     /* a pivot of the unpivoted LU fell below the guard */
+#define WW_EREFINE (-7)    /* mixed precision: refinement did not reach its tolerance */
+
+/* context flags */
+#define WW_FP64 0u         /* LU, triangular solves, everything in FP64 */
+#define WW_MIXED 1u        /* LU and triangular solves in FP32 on MFMA, FP64 iterative
+                              refinement of every solve (residuals in FP64) */
+
+/*
+ * ww_create: allocate a context whose device workspace serves every N <= n_max and
+ * every right-hand-side count (M + 1) <= r_max.  `hip_stream` is a hipStream_t (NULL:
+ * the default stream).  The library owns the workspace until ww_destroy.
+ * The default time-stepping tableau is unset: ww_set_tableau must be called before
+ * shoot_eval / shoot_adjoint (the Python layer loads DOP853).
+ */
+int ww_create(ww_ctx **ctx, int n_max, int r_max, unsigned flags, void *hip_stream);
+void ww_destroy(ww_ctx *ctx);
+int ww_set_stream(ww_ctx *ctx, void *hip_stream);
+
+/*
+ * ww_set_tableau: explicit Runge-Kutta tableau used for the march (Sec. 2.2 uses the
+ * 12 stages of DOP853 for the 8th-order update).  a: s x s row-major (host), strictly
+ * lower triangular; b: s weights (host); c: s nodes (host, unused: the system is
+ * autonomous).  1 <= s <= 16.  Errors: WW_EINVAL if a is not strictly lower triangular.
+ */
+int ww_set_tableau(ww_ctx *ctx, int s, const double *a, const double *b, const double *c);
+
+/*
+ * dtn_setup (Sec. 2.1 eq. (fred), Sec. 2.2 eq. (K1K2), App. A): for the surface
+ * `surface` (device, N), assemble the collocation matrices A = I/2 + K/N and
+ * Gm = G/N of the second-kind boundary integral equation and of the normal-derivative
+ * formula, and factor A once (LU, Sec. 3.3).  `tau` is stored for reference only (it
+ * does not enter A or Gm).  Synchronises to check the pivot guard.
+ * Errors: WW_EINVAL, WW_EDOMAIN (finite depth, h + eta <= 0), WW_EPIVOT, WW_EHIP.
+ */
+int dtn_setup(ww_ctx *ctx, const double *surface, double h, double tau, int N);
+
+/*
+ * dtn_solve_multi (eq. (fred), (G)): for each of the nrhs columns psi of `rhs`
+ * (device, N x nrhs, ld N) solve A mu = psi with the factors of the last dtn_setup,
+ * form gamma = d mu / d alpha and return the Dirichlet-Neumann output
+ * G psi = (1/2) H gamma + Gm gamma in `dtn_out` (device, N x nrhs, ld N).  `mu_out`
+ * (device, N x nrhs, or NULL) receives mu.  nrhs <= r_max.
+ * Errors: WW_ENOSETUP, WW_EINVAL, WW_EREFINE (mixed mode), WW_EHIP.
+ */
+int dtn_solve_multi(ww_ctx *ctx, const double *rhs, int nrhs, double *dtn_out, double *mu_out);
+
+/*
+ * shoot_setup (Sec. 3.1 eq. (init:stand), Sec. 3.3 eq. (q:qdot)): define the initial
+ * state q0(c) = q_fixed + basis c, c in R^M, and the Jacobian seeds Qdot(0) = basis.
+ * basis: device, 2N x M, column k = (eta part; phi part).  q_fixed: device 2N or NULL
+ * (zero).  g: gravity, tau: surface tension / density.  M + 1 <= r_max.  The arrays are
+ * copied into the context.
+ */
+int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double *basis,
+                const double *q_fixed, int M);
+
+/*
+ * shoot_eval (Sec. 3.1 eq. (f:phi), Sec. 3.3 eq. (Jik), (q:qdot); Sec. 3.2 eq. (dfdT)):
+ * march (q, Qdot) with `nsteps` fixed steps of the tableau, dt = T / (4 nsteps), to
+ * T/4 (T is the full period), with the 36th-order filter on every right-hand side and
+ * after every step.  Outputs (device, caller-owned):
+ *   r    (N)      r_i = phi(alpha_i, T/4) / sqrt(N)
+ *   J    (N x M)  J_ik = phidot_k(alpha_i, T/4) / sqrt(N), or NULL (base only, R = 1)
+ *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
+ *   f    (host)   f = r.r / 2, or NULL
+ * Synchronises when f is requested and to check the status flags.
+ * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EHIP.
+ */
+int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *r, double *J,
+               double *drdT, double *f);
+
+/*
+ * shoot_adjoint (Sec. 3.2, App. B; discrete form): gradient of f = r.r/2 with respect
+ * to the parameters, grad = J^T r, by the exact transpose of the discretised
+ * variational march (reverse Runge-Kutta stages, transposed LU solves, transposed
+ * Gm, -d/dx, -H), with the base state recomputed from checkpoints taken every
+ * `ckpt_every` steps.  grad: device M.  dfdT (host or NULL): df/dT = r . drdT.
+ * f (host or NULL).  Synchronises.
+ * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EHIP.
+ */
+int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int ckpt_every,
+                  double *grad, double *dfdT, double *f);
+
+/* thread-local message of the last failure on this thread ("" if none) */
+const char *ww_last_error(void);
+
+/* library version string */
+const char *ww_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* WW_H */

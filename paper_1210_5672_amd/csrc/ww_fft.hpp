@@ -1,0 +1,157 @@
+// LDS-resident complex FP64 FFT for one workgroup, N = 2^a 3^b <= WW_NMAX.
+//
+// Used for every pseudo-spectral operation of the method (Sec. 2.2: d/dx, Hilbert
+// transform, zero-mean projection P and the 36th-order filter are all Fourier
+// multipliers).  Real signals are processed in pairs packed as one complex signal.
+//
+// Algorithm: Stockham autosort with radix 4, 3 and 2 passes, ping-pong between two
+// LDS buffers; twiddles exp(-2 pi i t / N) are read from an LDS copy of a host-computed
+// table (load_twiddles, once per kernel).  Forward transform uses exp(-i k x); the inverse
+// uses exp(+i k x) and scales by 1/N.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#ifndef WW_NMAX
+#define WW_NMAX 2048
+#endif
+
+struct cplx {
+  double x, y;
+};
+
+__device__ __forceinline__ cplx cmk(double a, double b) { return cplx{a, b}; }
+__device__ __forceinline__ cplx cadd(cplx a, cplx b) { return cplx{a.x + b.x, a.y + b.y}; }
+__device__ __forceinline__ cplx csub(cplx a, cplx b) { return cplx{a.x - b.x, a.y - b.y}; }
+__device__ __forceinline__ cplx cmul(cplx a, cplx b) {
+  return cplx{a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x};
+}
+__device__ __forceinline__ cplx cscale(cplx a, double s) { return cplx{a.x * s, a.y * s}; }
+__device__ __forceinline__ cplx cconj(cplx a) { return cplx{a.x, -a.y}; }
+// multiply by -i (forward) or +i (inverse): dir = -1 forward, +1 inverse
+__device__ __forceinline__ cplx cmul_i(cplx a, int dir) {
+  return dir < 0 ? cplx{a.y, -a.x} : cplx{-a.y, a.x};
+}
+
+// Plan: sequence of radices (4, then 3, then 2) whose product is N.
+struct FftPlan {
+  int n;
+  int npass;
+  int radix[16];
+};
+
+__host__ __device__ inline FftPlan make_plan(int n) {
+  FftPlan p;
+  p.n = n;
+  p.npass = 0;
+  int m = n;
+  while (m % 4 == 0) { p.radix[p.npass++] = 4; m /= 4; }
+  while (m % 3 == 0) { p.radix[p.npass++] = 3; m /= 3; }
+  while (m % 2 == 0) { p.radix[p.npass++] = 2; m /= 2; }
+  if (m != 1) p.npass = -1;
+  return p;
+}
+
+// Transform `a` (N complex in LDS) in place; `b` is LDS scratch of N complex.
+// tw: twiddle table in LDS, tw[t] = exp(-2 pi i t / N), t = 0..N-1 (load_twiddles).
+// dir = -1 forward, +1 inverse (inverse also scales by 1/N).
+// Must be called by all threads of the workgroup.  Ends with a barrier.
+__device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& P, int dir) {
+  const int N = P.n;
+  const int nt = blockDim.x;
+  const int tid = threadIdx.x;
+  cplx* src = a;
+  cplx* dst = b;
+  int Ns = 1;
+  __syncthreads();
+  for (int ps = 0; ps < P.npass; ++ps) {
+    const int r = P.radix[ps];
+    const int nb = N / r;
+    const int tstride = N / (Ns * r);
+    for (int j = tid; j < nb; j += nt) {
+      const int jm = j % Ns;
+      cplx v[4];
+      for (int q = 0; q < r; ++q) {
+        cplx x = src[j + q * nb];
+        if (q > 0 && jm > 0) {
+          cplx w = tw[(jm * q * tstride) % N];
+          if (dir > 0) w = cconj(w);
+          x = cmul(x, w);
+        }
+        v[q] = x;
+      }
+      if (r == 2) {
+        cplx t0 = cadd(v[0], v[1]);
+        cplx t1 = csub(v[0], v[1]);
+        v[0] = t0;
+        v[1] = t1;
+      } else if (r == 4) {
+        cplx s02 = cadd(v[0], v[2]);
+        cplx d02 = csub(v[0], v[2]);
+        cplx s13 = cadd(v[1], v[3]);
+        cplx d13 = cmul_i(csub(v[1], v[3]), dir);
+        v[0] = cadd(s02, s13);
+        v[2] = csub(s02, s13);
+        v[1] = cadd(d02, d13);
+        v[3] = csub(d02, d13);
+      } else {  // r == 3
+        const double c3 = -0.5;
+        const double s3 = 0.86602540378443864676;  // sin(2 pi / 3)
+        cplx s = cadd(v[1], v[2]);
+        cplx d = csub(v[1], v[2]);
+        cplx m0 = cadd(v[0], cscale(s, c3));
+        // forward: exp(-2 pi i/3) -> multiply d by -i s3 ; inverse: +i s3
+        cplx md = cscale(cmul_i(d, dir), s3);
+        v[0] = cadd(v[0], s);
+        v[1] = cadd(m0, md);
+        v[2] = csub(m0, md);
+      }
+      const int idxD = (j / Ns) * Ns * r + jm;
+      for (int q = 0; q < r; ++q) dst[idxD + q * Ns] = v[q];
+    }
+    Ns *= r;
+    __syncthreads();
+    cplx* t = src;
+    src = dst;
+    dst = t;
+  }
+  // result is in src; copy to a if needed and scale for the inverse
+  const double sc = dir > 0 ? 1.0 / (double)N : 1.0;
+  if (src != a) {
+    for (int t = tid; t < N; t += nt) a[t] = cscale(src[t], sc);
+  } else if (dir > 0) {
+    for (int t = tid; t < N; t += nt) a[t] = cscale(a[t], sc);
+  }
+  __syncthreads();
+}
+
+// Copy the global twiddle table into LDS (once per kernel, before the first FFT).
+__device__ inline void load_twiddles(cplx* tws, const cplx* __restrict__ twg, int N) {
+  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = twg[t];
+}
+
+// Signed wavenumber of FFT bin t (t = 0..N-1): t for t <= N/2, t - N otherwise.
+__device__ __forceinline__ int wavenum(int t, int N) { return t <= N / 2 ? t : t - N; }
+
+// Split the spectrum Z of z = a + i b into the spectra of the real signals a and b:
+// A_k = (Z_k + conj Z_{-k}) / 2,  B_k = (Z_k - conj Z_{-k}) / (2 i).
+__device__ __forceinline__ void split_pair(const cplx* Z, int t, int N, cplx& A, cplx& B) {
+  cplx zk = Z[t];
+  cplx zm = cconj(Z[(N - t) % N]);
+  A = cscale(cadd(zk, zm), 0.5);
+  cplx d = csub(zk, zm);  // = 2 i B
+  B = cplx{0.5 * d.y, -0.5 * d.x};
+}
+
+// Pack two Hermitian spectra C, D (of real signals c, d) as the spectrum of c + i d.
+__device__ __forceinline__ cplx pack_pair(cplx C, cplx D) { return cplx{C.x - D.y, C.y + D.x}; }
+
+// Fourier symbols (Sec. 2.2): derivative ik with the Nyquist mode set to zero, Hilbert
+// -i sgn(k) (zero at 0 and Nyquist), and the 36th-order filter exp(-36 (|k|/(N/2))^36).
+__device__ __forceinline__ cplx sym_deriv(cplx X, int k, int N) {
+  if (2 * k == N || 2 * k == -N) return cplx{0.0, 0.0};
+  return cplx{-(double)k * X.y, (double)k * X.x};
+}
+__device__ __forceinline__ cplx sym_hilbert(cplx X, int k, int N) {
+  if (k == 0 || 2 * k == N || 2 * k == -N) return cplx{0.0, 0.0};
+  return k > 0 ? cplx{X.y, -X.x} : cplx{-X.y, X.x};
+}

@@ -1,0 +1,186 @@
+"""Python binding of the gfx950 library (include/ww.h): argument marshalling only.
+
+Every step of the path runs in the HIP kernels of libwwdtn.so; torch supplies device
+memory and the stream.  The library must be built (paper_1210_5672_amd/build.py);
+there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import numpy as np
+import torch  # noqa: F401  (loads the HIP runtime the library shares)
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwwdtn.so")
+
+WW_FP64 = 0
+WW_MIXED = 1
+
+_ERRORS = {
+    -1: "WW_EINVAL", -2: "WW_ENOSETUP", -3: "WW_EHIP", -4: "WW_EDOMAIN",
+    -5: "WW_ENONFINITE", -6: "WW_EPIVOT", -7: "WW_EREFINE",
+}
+
+EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_setup",
+           "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
+           "ww_version"]
+
+
+class WWError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"{_ERRORS.get(code, code)}: {msg}")
+        self.code = code
+        self.name = _ERRORS.get(code, str(code))
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load libwwdtn.so (raises if it is missing: there is no fallback path)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1210_5672_amd/build.py")
+    lib = ctypes.CDLL(path)
+    P, I, D, U = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_uint
+    DP = ctypes.POINTER(ctypes.c_double)
+    lib.ww_create.argtypes = [ctypes.POINTER(P), I, I, U, P]
+    lib.ww_destroy.argtypes = [P]
+    lib.ww_destroy.restype = None
+    lib.ww_set_stream.argtypes = [P, P]
+    lib.ww_set_tableau.argtypes = [P, I, DP, DP, DP]
+    lib.dtn_setup.argtypes = [P, P, D, D, I]
+    lib.dtn_solve_multi.argtypes = [P, P, I, P, P]
+    lib.shoot_setup.argtypes = [P, I, D, D, D, P, P, I]
+    lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
+    lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]
+    lib.ww_last_error.restype = ctypes.c_char_p
+    lib.ww_version.restype = ctypes.c_char_p
+    for name in ["ww_create", "ww_set_stream", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
+                 "shoot_setup", "shoot_eval", "shoot_adjoint"]:
+        getattr(lib, name).restype = I
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise WWError(rc, _lib.ww_last_error().decode())
+
+
+def _ptr(t: torch.Tensor | None):
+    if t is None:
+        return None
+    assert t.is_cuda and t.dtype == torch.float64 and t.is_contiguous(), "need contiguous cuda float64"
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def dop853():
+    """Dormand-Prince 8(5,3) tableau, 12 stages of the 8th-order update, from SciPy's
+    published coefficient table."""
+    from scipy.integrate._ivp import dop853_coefficients as d
+    s = d.N_STAGES
+    return (np.ascontiguousarray(d.A[:s, :s], dtype=np.float64),
+            np.ascontiguousarray(d.B, dtype=np.float64),
+            np.ascontiguousarray(d.C[:s], dtype=np.float64))
+
+
+def _dp(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+class Context:
+    """One engine context on the current GPU, on torch's current stream."""
+
+    def __init__(self, n_max: int, r_max: int, mixed: bool = False, stream=None, tableau=None):
+        self.lib = load()
+        self.ptr = ctypes.c_void_p()
+        s = stream if stream is not None else torch.cuda.current_stream()
+        _check(self.lib.ww_create(ctypes.byref(self.ptr), n_max, r_max,
+                                  WW_MIXED if mixed else WW_FP64, ctypes.c_void_p(s.cuda_stream)))
+        self.n_max, self.r_max, self.mixed = n_max, r_max, mixed
+        a, b, c = tableau if tableau is not None else dop853()
+        self._tab = (a, b, c)
+        _check(self.lib.ww_set_tableau(self.ptr, len(b), _dp(a), _dp(b), _dp(c)))
+        self.N = None
+        self.M = None
+
+    def close(self):
+        if self.ptr:
+            self.lib.ww_destroy(self.ptr)
+            self.ptr = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_stream(self, stream):
+        _check(self.lib.ww_set_stream(self.ptr, ctypes.c_void_p(stream.cuda_stream)))
+
+    # ----- DtN -----
+    def dtn_setup(self, surface: torch.Tensor, h: float, tau: float = 0.0):
+        N = surface.numel()
+        _check(self.lib.dtn_setup(self.ptr, _ptr(surface), float(h), float(tau), N))
+        self.dN = N
+
+    def dtn_solve_multi(self, rhs: torch.Tensor, want_mu: bool = False):
+        """rhs: (N, nrhs) column-major -> pass as a (nrhs, N) contiguous tensor transposed.
+        Accepts a (N,) vector or an (N, nrhs) tensor; returns tensors of the same shape."""
+        vec = rhs.dim() == 1
+        cols = rhs.reshape(-1, 1) if vec else rhs
+        N, nrhs = cols.shape
+        cm = cols.t().contiguous()                     # column-major storage
+        out = torch.empty_like(cm)
+        mu = torch.empty_like(cm) if want_mu else None
+        _check(self.lib.dtn_solve_multi(self.ptr, _ptr(cm), nrhs, _ptr(out), _ptr(mu)))
+        o = out.t()
+        m = mu.t() if want_mu else None
+        if vec:
+            o = o.reshape(-1)
+            m = m.reshape(-1) if want_mu else None
+        return (o, m) if want_mu else o
+
+    # ----- shooting -----
+    def shoot_setup(self, N, h, tau, g, basis: torch.Tensor, q_fixed: torch.Tensor | None = None):
+        """basis: (2N, M) tensor (column k = eta part; phi part)."""
+        M = basis.shape[1]
+        bcm = basis.t().contiguous()
+        _check(self.lib.shoot_setup(self.ptr, N, float(h), float(tau), float(g), _ptr(bcm),
+                                    _ptr(q_fixed.contiguous()) if q_fixed is not None else None, M))
+        self._basis = bcm
+        self.N, self.M = N, M
+
+    def shoot_eval(self, params: torch.Tensor, T: float, nsteps: int, jacobian: bool = True,
+                   drdT: bool = True):
+        if self.N is None:      # let the library report WW_ENOSETUP
+            _check(self.lib.shoot_eval(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
+                                       _ptr(params), None, None, None))
+        N, M = self.N, self.M
+        dev = params.device
+        r = torch.empty(N, dtype=torch.float64, device=dev)
+        Jc = torch.empty((M, N), dtype=torch.float64, device=dev) if jacobian else None
+        d = torch.empty(N, dtype=torch.float64, device=dev) if drdT else None
+        f = ctypes.c_double(0.0)
+        _check(self.lib.shoot_eval(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
+                                   _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
+        return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
+
+    def shoot_adjoint(self, params: torch.Tensor, T: float, nsteps: int, ckpt_every: int = 16):
+        M = self.M
+        grad = torch.empty(M, dtype=torch.float64, device=params.device)
+        dfdT = ctypes.c_double(0.0)
+        f = ctypes.c_double(0.0)
+        _check(self.lib.shoot_adjoint(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
+                                      int(ckpt_every), _ptr(grad), ctypes.byref(dfdT), ctypes.byref(f)))
+        return dict(grad=grad, dfdT=dfdT.value, f=f.value)
+
+
+def to_dev(a, device="cuda") -> torch.Tensor:
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)

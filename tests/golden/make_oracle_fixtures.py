@@ -1,0 +1,42 @@
+"""Write full-size reference results of the CPU oracle for the parity tests.
+
+Calls only oracle/ (and the seeded input generators).  Run from the repository root:
+    python tests/golden/make_oracle_fixtures.py [c2] [c4] [c3]
+Each fixture stores r, drdT, f, J^T r (the gradient of f), the column norms of J and a
+sample of J columns, for the workload of the same name.  C3 takes about an hour on
+8 cores (7200 dense DtN solves at N = 1024).
+"""
+import os
+import sys
+import time
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+from oracle import ww_oracle as O                 # noqa: E402
+from paper_1210_5672_amd import workloads as W   # noqa: E402
+
+SAMPLE_COLS = {"c2": [0, 1, 2, 7, 15, 31, 63], "c3": [0, 1, 2, 15, 40, 63, 127],
+               "c4": [0, 1, 2, 15, 63, 127, 200, 255]}
+
+
+def make(name):
+    w = W.CONFIGS[name]()
+    t0 = time.time()
+    res = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
+    grad, dfdT = O.shoot_gradient(res)
+    cols = np.array(SAMPLE_COLS[name])
+    out = os.path.join(HERE, f"{name}_oracle.npz")
+    eta0, _ = W.initial_state(w)
+    np.savez_compressed(out, r=res["r"], drdT=res["drdT"], f=np.array(res["f"]), grad=grad,
+                        dfdT=np.array(dfdT), Jcols=res["J"][:, cols], cols=cols,
+                        Jnorms=np.linalg.norm(res["J"], axis=0), eta0max=np.array(np.abs(eta0).max()),
+                        seconds=np.array(time.time() - t0))
+    print(name, "done in", time.time() - t0, "s ->", out, flush=True)
+
+
+if __name__ == "__main__":
+    for n in (sys.argv[1:] or ["c2", "c4", "c3"]):
+        make(n)

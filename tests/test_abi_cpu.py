@@ -1,0 +1,55 @@
+"""Host-only checks of the C ABI: the library loads and exports every entry point
+declared in include/ww.h; argument errors are reported without touching the GPU."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ww.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[a-z_]+\s*\**\s*([a-z_][a-z0-9_]*)\s*\(", src, flags=re.M)
+    return sorted(set(names))
+
+
+def _lib():
+    from paper_1210_5672_amd import ww
+    if not os.path.exists(ww.LIB_PATH):
+        pytest.skip("library not built")
+    return ww, ww.load()
+
+
+def test_header_declares_the_boundary():
+    names = declared_functions()
+    for n in ["ww_create", "ww_destroy", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
+              "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error"]:
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    ww, lib = _lib()
+    for n in declared_functions():
+        assert hasattr(lib, n), n
+    assert set(declared_functions()) <= set(ww.EXPORTS)
+
+
+def test_argument_errors_without_gpu():
+    ww, lib = _lib()
+    a = (ctypes.c_double * 4)()
+    assert lib.ww_set_tableau(None, 2, a, a, a) == -1
+    assert b"null" in lib.ww_last_error()
+    assert lib.dtn_setup(None, None, 1.0, 0.0, 64) == -1
+    assert lib.dtn_solve_multi(None, None, 1, None, None) == -1
+    assert lib.shoot_setup(None, 64, 1.0, 0.0, 1.0, None, None, 4) == -1
+    assert lib.shoot_eval(None, None, 1.0, 1, None, None, None, None) == -1
+    assert lib.shoot_adjoint(None, None, 1.0, 1, 16, None, None, None) == -1
+    out = ctypes.c_void_p()
+    assert lib.ww_create(None, 64, 4, 0, None) == -1
+    assert lib.ww_create(ctypes.byref(out), 70, 4, 0, None) == -1      # 70 is not 2^a 3^b
+    assert lib.ww_create(ctypes.byref(out), 4096, 4, 0, None) == -1    # above 2048
+    assert lib.ww_create(ctypes.byref(out), 64, 4, 8, None) == -1      # unknown flag

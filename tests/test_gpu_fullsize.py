@@ -1,0 +1,97 @@
+"""GPU path at the full sizes of the benchmark workloads against stored oracle results
+(tests/golden/*_oracle.npz, written by tests/golden/make_oracle_fixtures.py, which
+calls only the CPU oracle)."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1210_5672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+TOL = 1e-12
+
+
+def _load(name):
+    p = os.path.join(GOLDEN, f"{name}_oracle.npz")
+    if not os.path.exists(p):
+        pytest.skip(f"fixture {p} not generated")
+    return np.load(p)
+
+
+def _run(name, mixed=False):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    w = W.CONFIGS[name]()
+    ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    res = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+    return w, {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+
+
+def lin_amp(w, k):
+    """Amplitude of column k of J over the march in linear theory: the seed cos(k x)
+    in eta oscillates with phidot amplitude sqrt((g + tau k^2) / (k tanh kh)), and
+    J carries the weight 1/sqrt(N) (norm sqrt(N/2) for cos(k x)).  Columns that are
+    small at T/4 (the mode is near a node of its oscillation there) are compared on
+    this scale; the Nyquist column (k = N/2, annihilated by d/dx) has none."""
+    if 2 * k >= w.N:
+        return 0.0
+    th = 1.0 if math.isinf(w.h) else math.tanh(k * w.h)
+    return math.sqrt(0.5 * (w.g + w.tau * k * k) / (k * th))
+
+
+def kappa_F(w):
+    """Operator scale of the right-hand side's linearisation: the DtN (~k) and the
+    gravity/tension terms (~ g + tau k^2), both filtered.  drdT = F(y(T/4)) w/4 carries
+    the final-state difference times this factor."""
+    N = w.N
+    return max(math.exp(-36.0 * (k / (N / 2)) ** 36) * max(k, (w.g + w.tau * k * k) / w.g)
+               for k in range(1, N // 2))
+
+
+def check(fx, w, res, tol):
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    J = res["J"]
+    cols = fx["cols"]
+    jmax = fx["Jnorms"].max()
+    jerr = 0.0
+    for n, c in enumerate(cols):
+        scale = max(fx["Jnorms"][c], lin_amp(w, c + 1), 1e-10 * jmax)
+        jerr = max(jerr, float(np.linalg.norm(J[:, c] - fx["Jcols"][:, n]) / scale))
+    e = {
+        "r": rel(res["r"], fx["r"]),
+        "f": abs(res["f"] - float(fx["f"])) / abs(float(fx["f"])),
+        "Jcols": jerr,
+        "Jnorms": float(np.abs(np.linalg.norm(J, axis=0) - fx["Jnorms"]).max() / jmax),
+        "grad": rel(J.T @ res["r"], fx["grad"]),
+    }
+    e_drdT = rel(res["drdT"], fx["drdT"])
+    print(w.name, e, "drdT", e_drdT, "kappa", kappa_F(w), flush=True)
+    assert max(e.values()) < tol, e
+    assert e_drdT < tol * kappa_F(w), e_drdT
+
+
+def test_config2_full_fp64():
+    fx = _load("c2")
+    print("full-size parity c2", flush=True)
+    w, res = _run("c2")
+    check(fx, w, res, TOL)
+
+
+def test_config4_full_fp64_jacobian():
+    fx = _load("c4")
+    print("full-size parity c4", flush=True)
+    w, res = _run("c4")
+    check(fx, w, res, TOL)
+
+
+def test_config3_full_fp64():
+    fx = _load("c3")
+    print("full-size parity c3", flush=True)
+    w, res = _run("c3")
+    check(fx, w, res, TOL)

@@ -1,0 +1,140 @@
+"""GPU path against the CPU reference, element by element, through the C ABI."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ww_oracle as O
+from paper_1210_5672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _ww():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    return ww, torch
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+@pytest.mark.parametrize("N,h,R", [(64, math.inf, 5), (96, 1.0, 70), (256, 0.3, 130), (144, 2.0, 1)])
+def test_dtn_setup_and_solve_multi(N, h, R):
+    ww, torch = _ww()
+    print(f"dtn parity N={N} h={h} R={R}", flush=True)
+    eta = W.random_surface(N, seed=N + R, amp=0.06)
+    rhs = W.random_rhs(N, R, seed=7 + N)
+    ctx = ww.Context(n_max=max(N, 64), r_max=max(R, 2))
+    ctx.dtn_setup(ww.to_dev(eta), h)
+    out, mu = ctx.dtn_solve_multi(ww.to_dev(rhs), want_mu=True)
+    torch.cuda.synchronize()
+    d = O.DtN(eta, h)
+    ref, mref = d.apply(rhs)
+    assert relerr(out.cpu().numpy(), ref) < TOL
+    assert relerr(mu.cpu().numpy(), mref) < TOL
+
+
+def _shoot(ww, w, jacobian=True, drdT=True, nsteps=None):
+    ctx = ww.Context(n_max=max(w.N, 64), r_max=w.M + 1)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    return ctx.shoot_eval(ww.to_dev(w.params), w.T, nsteps or w.nsteps, jacobian=jacobian, drdT=drdT)
+
+
+def drdT_scale(ref, g, tau):
+    """drdT = phi_t(T/4) w/4 is one right-hand-side evaluation at the final state.  Its
+    sensitivity to the rounding of that state is the size of phi_t's response to a
+    state of the march's amplitude, (w/4) max|eta_0| max_k sigma_k (g + tau k^2) (the
+    tension term is a second derivative); for these inputs it is also a near-
+    cancellation (the surface passes close to the still level at T/4).  Its error is
+    measured on that scale."""
+    N = len(ref["r"])
+    op = max(math.exp(-36.0 * (k / (N / 2)) ** 36) * (g + tau * k * k) for k in range(N // 2))
+    return max(np.abs(ref["drdT"]).max(), 0.25 * np.abs(ref["eta0"]).max() / math.sqrt(N) * op)
+
+
+def _cmp(res, ref, jac=True, g=1.0, tau=0.0):
+    er = relerr(res["r"].cpu().numpy(), ref["r"])
+    scale = drdT_scale(ref, g, tau)
+    ed = float(np.abs(res["drdT"].cpu().numpy() - ref["drdT"]).max() / scale)
+    ef = abs(res["f"] - ref["f"]) / abs(ref["f"])
+    out = dict(r=er, drdT=ed, f=ef)
+    if jac:
+        out["J"] = relerr(res["J"].cpu().numpy(), ref["J"])
+    return out
+
+
+def test_shoot_eval_config1_full():
+    ww, torch = _ww()
+    w = W.c1()
+    print(f"shoot parity {w.name}", flush=True)
+    res = _shoot(ww, w)
+    ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
+    ref["eta0"] = W.initial_state(w)[0]
+    e = _cmp(res, ref)
+    print(e)
+    assert max(e.values()) < TOL
+
+
+def test_shoot_eval_finite_depth_tension_padded_grid():
+    ww, torch = _ww()
+    rng = np.random.default_rng(5)
+    N, M, h, tau = 96, 5, 0.7, 0.02
+    p = np.zeros(M)
+    p[0] = 0.04
+    p[1:] = rng.normal(0, 1e-3, M - 1)
+    # 20 steps keep the fastest filtered mode inside the RK8 stability region
+    w = W.Workload("t", N, h, tau, 1.0, M, W.linear_period(h, tau), 20, p, W.cosine_basis(N, M), np.zeros(2 * N))
+    print(f"shoot parity N={N} h={h} tau={tau}", flush=True)
+    res = _shoot(ww, w)
+    ref = O.shoot_eval(N, h, tau, 1.0, w.basis, w.q_fixed, p, w.T, w.nsteps)
+    ref["eta0"] = W.initial_state(w)[0]
+    e = _cmp(res, ref, g=1.0, tau=tau)
+    print(e)
+    assert max(e.values()) < TOL
+
+
+def test_shoot_eval_base_only():
+    ww, torch = _ww()
+    w = W.c1()
+    res = _shoot(ww, w, jacobian=False, nsteps=8)
+    ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, 8, jacobian=False)
+    ref["eta0"] = W.initial_state(w)[0]
+    e = _cmp(res, ref, jac=False)
+    assert max(e.values()) < TOL
+
+
+def test_error_paths_on_gpu():
+    ww, torch = _ww()
+    ctx = ww.Context(n_max=64, r_max=4)
+    with pytest.raises(ww.WWError) as ei:
+        ctx.dtn_solve_multi(torch.zeros(64, 1, dtype=torch.float64, device="cuda"))
+    assert ei.value.name == "WW_ENOSETUP"
+    with pytest.raises(ww.WWError) as ei:
+        ctx.dtn_setup(torch.zeros(70, dtype=torch.float64, device="cuda"), 1.0)
+    assert ei.value.name == "WW_EINVAL"
+    with pytest.raises(ww.WWError) as ei:      # surface through the bottom
+        ctx.dtn_setup(torch.full((64,), -2.0, dtype=torch.float64, device="cuda"), 1.0)
+    assert ei.value.name == "WW_EDOMAIN"
+    with pytest.raises(ww.WWError) as ei:
+        ctx.shoot_eval(torch.zeros(3, dtype=torch.float64, device="cuda"), 6.0, 4)
+    assert ei.value.name == "WW_ENOSETUP"
+
+
+def test_unstable_step_reports_nonfinite():
+    """6 steps put the fastest filtered mode outside the stability region: the march
+    blows up and the library reports WW_ENONFINITE (values only; no kernel faults)."""
+    ww, torch = _ww()
+    N, M, h, tau = 96, 2, 0.7, 0.02
+    p = np.array([0.04, 0.001])
+    w = W.Workload("t", N, h, tau, 1.0, M, W.linear_period(h, tau), 6, p, W.cosine_basis(N, M), np.zeros(2 * N))
+    with pytest.raises(ww.WWError) as ei:
+        _shoot(ww, w)
+    assert ei.value.name in ("WW_ENONFINITE", "WW_EPIVOT")
