@@ -152,8 +152,26 @@ class Arith:
     def ge0(self, x):
         return x >= 0.0
 
+    def cosh_sinh(self, y):
+        """cosh y, sinh y from exp(y) and exp(-y)."""
+        ey = np.exp(y)
+        eyi = np.exp(-y)
+        return (ey + eyi) / 2, (ey - eyi) / 2
+
+
+class ArithAlt(Arith):
+    """The same FP64 arithmetic with cosh and sinh taken from the math library: a
+    second, equally valid rounding of the same formulas.  Used only to measure the
+    FP64 rounding floor of long marches (the spread between the two runs)."""
+
+    name = "f64alt"
+
+    def cosh_sinh(self, y):
+        return np.cosh(y), np.sinh(y)
+
 
 F64 = Arith()
+F64ALT = ArithAlt()
 
 
 # --------------------------------------------------------------------------------
@@ -185,10 +203,7 @@ def cot_half(x, y, ar=F64):
     Sec. 2.2:  (cos x + cosh y)/(sin x + i sinh y) when cos x >= 0, otherwise
     (sin x - i sinh y)/(cosh y - cos x)."""
     cx, sx = ar.cos(x), ar.sin(x)
-    ey = ar.exp(y)
-    eyi = ar.exp(-y)
-    chy = (ey + eyi) / 2
-    shy = (ey - eyi) / 2
+    chy, shy = ar.cosh_sinh(y)
     # branch 1: (cx + chy) (sx - i shy) / (sx^2 + shy^2)
     num = cx + chy
     d1 = sx * sx + shy * shy

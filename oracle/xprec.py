@@ -65,6 +65,11 @@ class MPArith:
     def sqrt(self, x):
         return self._sqrt(x)
 
+    def cosh_sinh(self, y):
+        ey = self._exp(y)
+        eyi = self._exp(-y)
+        return (ey + eyi) / 2, (ey - eyi) / 2
+
     @property
     def pi(self):
         return self.ctx.pi

@@ -55,7 +55,9 @@ struct ww_ctx {
   double ta[16 * 16], tb[16];
   // device buffers
   double *A = nullptr, *Gm = nullptr, *Xi = nullptr, *Zi = nullptr, *Vi = nullptr, *Dinv = nullptr;
-  float* A32 = nullptr;
+  float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
+  double *Rr = nullptr, *rr0 = nullptr;   // residuals of the refinement sweeps
+  int nref = 2;                            // refinement sweeps per solve (mixed mode)
   double *cosT = nullptr, *sinT = nullptr, *c0T = nullptr, *sig = nullptr;
   cplx* tw = nullptr;
   double* aux = nullptr;
@@ -156,7 +158,15 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->Zi, np * np * 8);
   AL(c->Vi, np * np * 8);
   AL(c->Dinv, (size_t)nbm * 4096 * 8);
-  if (flags & WW_MIXED) AL(c->A32, np * np * 4);
+  if (flags & WW_MIXED) {
+    AL(c->A32, np * np * 4);
+    AL(c->X32, np * np * 4);
+    AL(c->Z32, np * np * 4);
+    AL(c->V32, np * np * 4);
+    AL(c->Dinv32, (size_t)nbm * 4096 * 4);
+    AL(c->Rr, np * R * 8);
+    AL(c->rr0, np * 8);
+  }
   AL(c->cosT, nm * 8);
   AL(c->sinT, nm * 8);
   AL(c->c0T, nm * 8);
@@ -192,13 +202,19 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   {
     const char* ng = std::getenv("WW_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
+    const char* nr = std::getenv("WW_NREF");
+    if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
   }
   // kernels whose dynamic LDS can exceed the default 64 KiB
   const int big = 160 * 1024;
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_init, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_step, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_final, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_gemm_part, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_blu_init<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_blu_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_blu_final<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_gemm_part<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_blu_init<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_blu_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_blu_final<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_gemm_part<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_base_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -248,45 +264,57 @@ int ww_set_tableau(ww_ctx* c, int s, const double* a, const double* b, const dou
 static size_t fft_lds_bytes(int N, int nbuf) { return (size_t)nbuf * N * sizeof(cplx); }
 static const size_t TILE_BYTES = (size_t)TILE_DBL * 8;
 
-static BluBufs blu_bufs(ww_ctx* c) {
-  BluBufs b;
-  b.A = c->A;
-  b.X = c->Xi;
-  b.Z = c->Zi;
-  b.V = c->Vi;
-  b.Dinv = c->Dinv;
+template <typename T>
+static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D) {
+  BluBufs<T> b;
+  b.A = A;
+  b.X = X;
+  b.Z = Z;
+  b.V = V;
+  b.Dinv = D;
   b.status = c->status;
   b.Np = c->Np;
   b.pivguard = 1e-8;
   return b;
 }
 
-// assembly of A, Gm and the block LU of A with the block-triangular inverses
-static int enqueue_assemble_lu(ww_ctx* c) {
+template <typename T>
+static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
   const int nb = c->Np / WW_TB;
-  hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, c->aux, c->n_max, c->cosT, c->sinT,
-                     c->c0T, c->A, c->Gm, c->A32, c->N, c->Np, c->finite);
-  LAUNCHCHK();
-  const BluBufs b = blu_bufs(c);
-  hipLaunchKernelGGL(k_blu_init, dim3(1), dim3(WW_NT), TILE_BYTES + 256 * 8, c->stream, b);
+  const size_t es = sizeof(T);
+  hipLaunchKernelGGL(k_blu_init<T>, dim3(1), dim3(WW_NT), (TILE_DBL + 256) * es, c->stream, b);
   LAUNCHCHK();
   for (int k = 0; k + 1 < nb; ++k) {
     const int nt = nb - k - 1;
     const int nblk = nt * nt + 2 * nt * (k + 1);
-    hipLaunchKernelGGL(k_blu_step, dim3(nblk), dim3(WW_NT), 2 * TILE_BYTES + 256 * 8, c->stream, b, k);
+    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk), dim3(WW_NT), (4 * TILE_DBL + 256) * es, c->stream, b, k);
     LAUNCHCHK();
   }
   if (nb > 1) {
-    hipLaunchKernelGGL(k_blu_final, dim3(nb - 1), dim3(WW_NT), 2 * TILE_BYTES, c->stream, b);
+    hipLaunchKernelGGL(k_blu_final<T>, dim3(nb - 1), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, b);
     LAUNCHCHK();
   }
   return 0;
 }
 
-// out = add + T * B for R columns (ld Np), T taken as full (mode 0), strictly lower
+static bool mixed(const ww_ctx* c) { return (c->flags & WW_MIXED) != 0; }
+
+// assembly of A, Gm and the block LU of A (FP64, or of the FP32 copy in mixed mode)
+// with the block-triangular inverses
+static int enqueue_assemble_lu(ww_ctx* c) {
+  const int nb = c->Np / WW_TB;
+  hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, c->aux, c->n_max, c->cosT, c->sinT,
+                     c->c0T, c->A, c->Gm, mixed(c) ? c->A32 : nullptr, c->N, c->Np, c->finite);
+  LAUNCHCHK();
+  if (mixed(c)) return enqueue_blu<float>(c, blu_bufs<float>(c, c->A32, c->X32, c->Z32, c->V32, c->Dinv32));
+  return enqueue_blu<double>(c, blu_bufs<double>(c, c->A, c->Xi, c->Zi, c->Vi, c->Dinv));
+}
+
+// out = add + sgn * M B for R columns (ld Np), M taken as full (mode 0), strictly lower
 // (mode 1) or upper (mode 2) in 64-blocks.  Split-K partials, then a reduction.
-static int enqueue_gemm(ww_ctx* c, const double* T, int mode, const double* B, const double* add, double* out,
-                        int R) {
+template <typename T>
+static int enqueue_gemm(ww_ctx* c, const T* M, int mode, const double* B, const double* add, double sgn,
+                        double* out, int R) {
   const int nkt = c->Np / WW_TB;
   const int tiles = nkt * ((R + 63) / 64);
   int nsplit = (512 + tiles - 1) / tiles;
@@ -294,32 +322,45 @@ static int enqueue_gemm(ww_ctx* c, const double* T, int mode, const double* B, c
   if (nsplit < 1) nsplit = 1;
   const int kchunk = (nkt + nsplit - 1) / nsplit;
   nsplit = (nkt + kchunk - 1) / kchunk;
-  hipLaunchKernelGGL(k_gemm_part, dim3(nkt, (R + 63) / 64, nsplit), dim3(WW_NT), 2 * TILE_BYTES, c->stream, T,
-                     c->Np, mode, B, R, c->part, kchunk);
+  hipLaunchKernelGGL(k_gemm_part<T>, dim3(nkt, (R + 63) / 64, nsplit), dim3(WW_NT), 2 * TILE_DBL * sizeof(T),
+                     c->stream, M, c->Np, mode, B, R, c->part, kchunk);
   LAUNCHCHK();
   const size_t n = (size_t)c->Np * R;
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_gemm_reduce, dim3(blocks), dim3(256), 0, c->stream, c->part, nsplit, add, out, c->Np, R);
+  hipLaunchKernelGGL(k_gemm_reduce, dim3(blocks), dim3(256), 0, c->stream, c->part, nsplit, add, sgn, out, c->Np, R);
   LAUNCHCHK();
   return 0;
 }
 
-// X = A^{-1} B = Z (B + Xstrict B) for R columns (ld Np); Y is scratch.  B is kept.
-static int enqueue_solve(ww_ctx* c, double* B, double* Y, double* X, int R) {
+// X = A^{-1} B for R columns (ld Np); Y and Rs are scratch; B is kept.
+// FP64:  X = Z (B + Xs B).
+// mixed: X = Z32 (B + X32 B), then nref sweeps of  r = B - A X (FP64 residual with the
+//        FP64 matrix),  X += Z32 (r + X32 r)  (FP32 factors, FP64 accumulation).
+static int enqueue_solve(ww_ctx* c, double* B, double* Y, double* X, double* Rs, int R) {
   int rc;
-  if ((rc = enqueue_gemm(c, c->Xi, 1, B, B, Y, R))) return rc;
-  return enqueue_gemm(c, c->Zi, 2, Y, nullptr, X, R);
+  if (!mixed(c)) {
+    if ((rc = enqueue_gemm<double>(c, c->Xi, 1, B, B, 1.0, Y, R))) return rc;
+    return enqueue_gemm<double>(c, c->Zi, 2, Y, nullptr, 1.0, X, R);
+  }
+  if ((rc = enqueue_gemm<float>(c, c->X32, 1, B, B, 1.0, Y, R))) return rc;
+  if ((rc = enqueue_gemm<float>(c, c->Z32, 2, Y, nullptr, 1.0, X, R))) return rc;
+  for (int it = 0; it < c->nref; ++it) {
+    if ((rc = enqueue_gemm<double>(c, c->A, 0, X, B, -1.0, Rs, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, c->X32, 1, Rs, Rs, 1.0, Y, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, c->Z32, 2, Y, X, 1.0, X, R))) return rc;
+  }
+  return 0;
 }
 
-// DtN of R columns in B (ld Np, destroyed): out = G psi (ld Np); mu in Mu
+// DtN of R columns in B (ld Np): out = G psi (ld Np); mu in Mu; Rs residual scratch
 static int enqueue_dtn_cols(ww_ctx* c, double* B, double* Yt, double* Mu, double* Gam, double* HGm, double* out,
-                            int R) {
+                            double* Rs, int R) {
   int rc;
-  if ((rc = enqueue_solve(c, B, Yt, Mu, R))) return rc;
+  if ((rc = enqueue_solve(c, B, Yt, Mu, Rs, R))) return rc;
   hipLaunchKernelGGL(k_gamma, dim3((R + 1) / 2), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Mu, c->Np, R, Gam,
                      HGm, c->tw, c->N);
   LAUNCHCHK();
-  return enqueue_gemm(c, c->Gm, 0, Gam, HGm, out, R);
+  return enqueue_gemm<double>(c, c->Gm, 0, Gam, HGm, 1.0, out, R);
 }
 
 static size_t kstride(const ww_ctx* c) { return (size_t)2 * c->N * (c->M + 1); }
@@ -331,7 +372,7 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
                      s, kstride(c), c->aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf);
   LAUNCHCHK();
   if ((rc = enqueue_assemble_lu(c))) return rc;
-  if ((rc = enqueue_dtn_cols(c, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, 1))) return rc;
+  if ((rc = enqueue_dtn_cols(c, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
   hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, c->aux,
                      c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
@@ -346,7 +387,7 @@ static int enqueue_col_chain(ww_ctx* c, int s) {
   hipLaunchKernelGGL(k_col_pre, dim3(blocks), dim3(256), 0, c->stream, c->y, c->K, c->Ys, c->coef, s, kstride(c),
                      c->aux, c->n_max, c->Psi, c->Np, c->N, M);
   LAUNCHCHK();
-  if ((rc = enqueue_dtn_cols(c, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, M))) return rc;
+  if ((rc = enqueue_dtn_cols(c, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
   hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
                      c->aux, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
@@ -446,7 +487,7 @@ int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, dou
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs, N, c->Psi, Np, N, Np, nrhs);
   LAUNCHCHK();
   int rc;
-  if ((rc = enqueue_dtn_cols(c, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, nrhs))) return rc;
+  if ((rc = enqueue_dtn_cols(c, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, nrhs))) return rc;
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Gpsi, Np, dtn_out, N, Np, N, nrhs);
   LAUNCHCHK();
   if (mu_out) {

@@ -32,23 +32,72 @@ __device__ __forceinline__ cplx cmul_i(cplx a, int dir) {
   return dir < 0 ? cplx{a.y, -a.x} : cplx{-a.y, a.x};
 }
 
-// Plan: sequence of radices (4, then 3, then 2) whose product is N.
+// Plan: N = 4^n4 3^n3 2^n2; passes run radix 4 first, then 3, then 2.  Stored as
+// counts (no per-pass array) so that nothing is indexed dynamically in registers.
 struct FftPlan {
-  int n;
-  int npass;
-  int radix[16];
+  int n, n4, n3, n2;
 };
 
 __host__ __device__ inline FftPlan make_plan(int n) {
   FftPlan p;
   p.n = n;
-  p.npass = 0;
+  p.n4 = p.n3 = p.n2 = 0;
   int m = n;
-  while (m % 4 == 0) { p.radix[p.npass++] = 4; m /= 4; }
-  while (m % 3 == 0) { p.radix[p.npass++] = 3; m /= 3; }
-  while (m % 2 == 0) { p.radix[p.npass++] = 2; m /= 2; }
-  if (m != 1) p.npass = -1;
+  while (m % 4 == 0) { ++p.n4; m /= 4; }
+  while (m % 3 == 0) { ++p.n3; m /= 3; }
+  while (m % 2 == 0) { ++p.n2; m /= 2; }
+  if (m != 1) p.n4 = -1;
   return p;
+}
+
+// One Stockham pass of radix R (fully unrolled butterfly, static register arrays).
+template <int R>
+__device__ __forceinline__ void fft_pass(const cplx* src, cplx* dst, const cplx* tw, int N, int Ns, int dir) {
+  const int nb = N / R;
+  const int tstride = N / (Ns * R);
+  for (int j = threadIdx.x; j < nb; j += blockDim.x) {
+    const int jm = j % Ns;
+    cplx v[R];
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+      cplx x = src[j + q * nb];
+      if (q > 0) {
+        cplx w = tw[jm * q * tstride];
+        if (dir > 0) w = cconj(w);
+        x = cmul(x, w);
+      }
+      v[q] = x;
+    }
+    if (R == 2) {
+      cplx t0 = cadd(v[0], v[1]);
+      cplx t1 = csub(v[0], v[1]);
+      v[0] = t0;
+      v[1] = t1;
+    } else if (R == 4) {
+      cplx s02 = cadd(v[0], v[2]);
+      cplx d02 = csub(v[0], v[2]);
+      cplx s13 = cadd(v[1], v[3 % R]);
+      cplx d13 = cmul_i(csub(v[1], v[3 % R]), dir);
+      v[0] = cadd(s02, s13);
+      v[2 % R] = csub(s02, s13);
+      v[1] = cadd(d02, d13);
+      v[3 % R] = csub(d02, d13);
+    } else {  // R == 3
+      const double c3 = -0.5;
+      const double s3 = 0.86602540378443864676;  // sin(2 pi / 3)
+      cplx sm = cadd(v[1], v[2 % R]);
+      cplx d = csub(v[1], v[2 % R]);
+      cplx m0 = cadd(v[0], cscale(sm, c3));
+      // forward: exp(-2 pi i/3) -> multiply d by -i s3 ; inverse: +i s3
+      cplx md = cscale(cmul_i(d, dir), s3);
+      v[0] = cadd(v[0], sm);
+      v[1] = cadd(m0, md);
+      v[2 % R] = csub(m0, md);
+    }
+    const int idxD = (j / Ns) * Ns * R + jm;
+#pragma unroll
+    for (int q = 0; q < R; ++q) dst[idxD + q * Ns] = v[q];
+  }
 }
 
 // Transform `a` (N complex in LDS) in place; `b` is LDS scratch of N complex.
@@ -63,52 +112,18 @@ __device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& 
   cplx* dst = b;
   int Ns = 1;
   __syncthreads();
-  for (int ps = 0; ps < P.npass; ++ps) {
-    const int r = P.radix[ps];
-    const int nb = N / r;
-    const int tstride = N / (Ns * r);
-    for (int j = tid; j < nb; j += nt) {
-      const int jm = j % Ns;
-      cplx v[4];
-      for (int q = 0; q < r; ++q) {
-        cplx x = src[j + q * nb];
-        if (q > 0 && jm > 0) {
-          cplx w = tw[(jm * q * tstride) % N];
-          if (dir > 0) w = cconj(w);
-          x = cmul(x, w);
-        }
-        v[q] = x;
-      }
-      if (r == 2) {
-        cplx t0 = cadd(v[0], v[1]);
-        cplx t1 = csub(v[0], v[1]);
-        v[0] = t0;
-        v[1] = t1;
-      } else if (r == 4) {
-        cplx s02 = cadd(v[0], v[2]);
-        cplx d02 = csub(v[0], v[2]);
-        cplx s13 = cadd(v[1], v[3]);
-        cplx d13 = cmul_i(csub(v[1], v[3]), dir);
-        v[0] = cadd(s02, s13);
-        v[2] = csub(s02, s13);
-        v[1] = cadd(d02, d13);
-        v[3] = csub(d02, d13);
-      } else {  // r == 3
-        const double c3 = -0.5;
-        const double s3 = 0.86602540378443864676;  // sin(2 pi / 3)
-        cplx s = cadd(v[1], v[2]);
-        cplx d = csub(v[1], v[2]);
-        cplx m0 = cadd(v[0], cscale(s, c3));
-        // forward: exp(-2 pi i/3) -> multiply d by -i s3 ; inverse: +i s3
-        cplx md = cscale(cmul_i(d, dir), s3);
-        v[0] = cadd(v[0], s);
-        v[1] = cadd(m0, md);
-        v[2] = csub(m0, md);
-      }
-      const int idxD = (j / Ns) * Ns * r + jm;
-      for (int q = 0; q < r; ++q) dst[idxD + q * Ns] = v[q];
+  const int npass = P.n4 + P.n3 + P.n2;
+  for (int ps = 0; ps < npass; ++ps) {
+    if (ps < P.n4) {
+      fft_pass<4>(src, dst, tw, N, Ns, dir);
+      Ns *= 4;
+    } else if (ps < P.n4 + P.n3) {
+      fft_pass<3>(src, dst, tw, N, Ns, dir);
+      Ns *= 3;
+    } else {
+      fft_pass<2>(src, dst, tw, N, Ns, dir);
+      Ns *= 2;
     }
-    Ns *= r;
     __syncthreads();
     cplx* t = src;
     src = dst;
@@ -126,7 +141,21 @@ __device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& 
 
 // Copy the global twiddle table into LDS (once per kernel, before the first FFT).
 __device__ inline void load_twiddles(cplx* tws, const cplx* __restrict__ twg, int N) {
-  for (int t = threadIdx.x; t < N; t += blockDim.x) tws[t] = twg[t];
+  // clamped, unconditional loads first (all in flight), then the guarded LDS stores
+  cplx v[WW_NMAX / 256];
+#pragma unroll
+  for (int m = 0; m < WW_NMAX / 256; ++m) {
+    const int t = threadIdx.x + 256 * m;
+    v[m] = twg[t < N ? t : N - 1];
+  }
+  // keep the loads here, all in flight, instead of sunk into the guarded stores below
+#pragma unroll
+  for (int m = 0; m < WW_NMAX / 256; ++m) asm volatile("" ::"v"(v[m].x), "v"(v[m].y));
+#pragma unroll
+  for (int m = 0; m < WW_NMAX / 256; ++m) {
+    const int t = threadIdx.x + 256 * m;
+    if (t < N) tws[t] = v[m];
+  }
 }
 
 // Signed wavenumber of FFT bin t (t = 0..N-1): t for t <= N/2, t - N otherwise.

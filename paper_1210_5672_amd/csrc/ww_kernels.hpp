@@ -36,6 +36,70 @@ enum {
 #define COEF_DT 300
 #define COEF_SIZE 320
 
+// Per-thread element sets: thread x owns t = x + 256 m, m < NPT.  Global loads go
+// through clamped, unconditional register loads (all in flight at once); only the
+// stores are guarded by t < N.
+#define NPT (WW_NMAX / WW_NT)
+
+__device__ __forceinline__ int tidx(int m) { return threadIdx.x + WW_NT * m; }
+__device__ __forceinline__ int tclamp(int m, int N) {
+  const int t = tidx(m);
+  return t < N ? t : N - 1;
+}
+// Pin register values at this point (stops the compiler from sinking their loads into
+// later guarded blocks, which would serialise them).
+__device__ __forceinline__ void pin(const double (&v)[NPT]) {
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) asm volatile("" ::"v"(v[m]));
+}
+__device__ __forceinline__ void gload(double (&v)[NPT], const double* __restrict__ p, int N) {
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) v[m] = p[tclamp(m, N)];
+}
+
+// acc[m] = y[off + t_m] + sum_{j < stage} (a_sj dt) K[j][off + t_m]: stage values of the
+// thread's elements; the loads of two stages for all elements are issued together.
+// crow: the count weights (a_sj dt for a stage, b_s dt for the end of a step).
+__device__ __forceinline__ void stage_combine_vec(double (&acc)[NPT], const double* __restrict__ y,
+                                                  const double* __restrict__ K, size_t kstride, size_t off,
+                                                  const double* __restrict__ crow, int count, int N) {
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) acc[m] = y[off + tclamp(m, N)];
+  for (int j0 = 0; j0 < count; j0 += 2) {
+    const int j1 = (j0 + 1 < count) ? j0 + 1 : j0;
+    const double a0 = crow[j0];
+    const double a1 = (j0 + 1 < count) ? crow[j0 + 1] : 0.0;
+    double k0[NPT], k1[NPT];
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      k0[m] = K[(size_t)j0 * kstride + off + tclamp(m, N)];
+      k1[m] = K[(size_t)j1 * kstride + off + tclamp(m, N)];
+    }
+    pin(k0);
+    pin(k1);
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) acc[m] = fma(a1, k1[m], fma(a0, k0[m], acc[m]));
+  }
+}
+
+// Stage value at one element (column kernels: many threads, one element each).
+__device__ __forceinline__ double stage_combine(double y0, const double* __restrict__ K, size_t kstride,
+                                                size_t off, const double* __restrict__ coef, int stage) {
+  double acc = y0;
+  for (int j0 = 0; j0 < stage; j0 += 4) {
+    double kv[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int j = (j0 + q < stage) ? j0 + q : j0;
+      kv[q] = K[(size_t)j * kstride + off];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+      if (j0 + q < stage) acc = fma(coef[stage * 16 + j0 + q], kv[q], acc);
+  }
+  return acc;
+}
+
 // -------------------------------------------------------------------------------------
 // LDS helpers for real-signal pairs
 // -------------------------------------------------------------------------------------
@@ -84,13 +148,20 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
   const FftPlan P = make_plan(N);
   const int tid = threadIdx.x;
   load_twiddles(tws, tw, N);
-  for (int i = tid; i < 2 * N; i += WW_NT) {
-    double v = y[i];
-    for (int j = 0; j < stage; ++j) v += coef[stage * 16 + j] * K[(size_t)j * kstride + i];
-    Ys[i] = v;
+  double ev[NPT], pv[NPT];
+  stage_combine_vec(ev, y, K, kstride, 0, coef + stage * 16, stage, N);
+  stage_combine_vec(pv, y, K, kstride, N, coef + stage * 16, stage, N);
+  pin(ev);
+  pin(pv);
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int t = tidx(m);
+    if (t < N) {
+      Ys[t] = ev[m];
+      Ys[N + t] = pv[m];
+      Z[t] = cmk(ev[m], pv[m]);
+    }
   }
-  __syncthreads();
-  load_pair(Z, Ys, Ys + N, N);
   fft_lds(Z, S, tws, P, -1);   // spectrum of eta + i varphi
   for (int t = tid; t < N; t += WW_NT) {
     cplx E, F;
@@ -103,14 +174,18 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
   }
   fft_lds(W, Z, tws, P, +1);   // eta_x + i eta_xx
   fft_lds(S, Z, tws, P, +1);   // varphi' (imaginary part zero)
-  for (int i = tid; i < N; i += WW_NT) {
-    aux[AUX_EX * nmax + i] = W[i].x;
-    aux[AUX_EXX * nmax + i] = W[i].y;
-    aux[AUX_PHS * nmax + i] = S[i].x;
-    const double s = Ys[i] + hsurf;
-    aux[AUX_EP * nmax + i] = exp(s);
-    aux[AUX_EM * nmax + i] = exp(-s);
-    rhs0[i] = Ys[N + i];
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int i = tidx(m);
+    if (i < N) {
+      aux[AUX_EX * nmax + i] = W[i].x;
+      aux[AUX_EXX * nmax + i] = W[i].y;
+      aux[AUX_PHS * nmax + i] = S[i].x;
+      const double sh = ev[m] + hsurf;
+      aux[AUX_EP * nmax + i] = exp(sh);
+      aux[AUX_EM * nmax + i] = exp(-sh);
+      rhs0[i] = pv[m];
+    }
   }
   for (int i = N + tid; i < Np; i += WW_NT) rhs0[i] = 0.0;
 }
@@ -147,18 +222,36 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
     const double* __restrict__ aux, int nmax, const double* __restrict__ cosT,
     const double* __restrict__ sinT, const double* __restrict__ c0T, double* __restrict__ A,
     double* __restrict__ Gm, float* __restrict__ A32, int N, int Np, int finite) {
-  const int tx = threadIdx.x & 63;
-  const int ty = threadIdx.x >> 6;
-  const int i = blockIdx.x * WW_TB + tx;
-  const int j0 = blockIdx.y * WW_TB;
-  const double invN = 1.0 / (double)N;
-  double exi = 0, exxi = 0, epi = 0, emi = 0;
-  if (i < N) {
-    exi = aux[AUX_EX * nmax + i];
-    exxi = aux[AUX_EXX * nmax + i];
-    epi = aux[AUX_EP * nmax + i];
-    emi = aux[AUX_EM * nmax + i];
+  // stage the per-point quantities of the tile's 64 rows and 64 columns and the 127
+  // circulant table entries d = i - j it touches in LDS
+  __shared__ double rq[4][64];   // eta_x, eta_xx, exp(s), exp(-s) of rows
+  __shared__ double cq[3][64];   // eta_x, exp(s), exp(-s) of columns
+  __shared__ double tb[3][128];  // cos, sin, cot/2 of 2 pi d / N, d = i - j
+  const int i0 = blockIdx.x * WW_TB, j0 = blockIdx.y * WW_TB;
+  const int t = threadIdx.x;
+  {
+    const int q = t >> 6, r = t & 63;   // 4 x 64 row quantities
+    const int ir = i0 + r;
+    rq[q][r] = (ir < N) ? aux[(q == 0 ? AUX_EX : q == 1 ? AUX_EXX : q == 2 ? AUX_EP : AUX_EM) * nmax + ir] : 0.0;
+    if (q < 3) {
+      const int jc = j0 + r;
+      cq[q][r] = (jc < N) ? aux[(q == 0 ? AUX_EX : q == 1 ? AUX_EP : AUX_EM) * nmax + jc] : 0.0;
+    }
+    // table entries e = 0..126 <-> d = (i0 - j0 - 63 + e) mod N
+    for (int e = t; e < 3 * 127; e += WW_NT) {
+      const int which = e / 127, ee = e - which * 127;
+      int d = (i0 - j0 - 63 + ee) % N;
+      if (d < 0) d += N;
+      tb[which][ee] = which == 0 ? cosT[d] : which == 1 ? sinT[d] : c0T[d];
+    }
   }
+  __syncthreads();
+  const int tx = t & 63;
+  const int ty = t >> 6;
+  const int i = i0 + tx;
+  const double invN = 1.0 / (double)N;
+  const double exi = rq[0][tx], exxi = rq[1][tx], epi = rq[2][tx], emi = rq[3][tx];
+#pragma unroll 4
   for (int jj = ty; jj < WW_TB; jj += 4) {
     const int j = j0 + jj;
     double a, gm;
@@ -166,12 +259,9 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
       a = (i == j) ? 1.0 : 0.0;
       gm = 0.0;
     } else {
-      const double exj = aux[AUX_EX * nmax + j];
-      const double epj = aux[AUX_EP * nmax + j];
-      const double emj = aux[AUX_EM * nmax + j];
-      int d = i - j;
-      if (d < 0) d += N;
-      const double cx = cosT[d], sx = sinT[d];
+      const double exj = cq[0][jj], epj = cq[1][jj], emj = cq[2][jj];
+      const int e = tx - jj + 63;
+      const double cx = tb[0][e], sx = tb[1][e];
       double Kv, Gv;
       if (i != j) {
         const double e1 = epi * emj, e2 = emi * epj;   // exp(y), exp(-y), y = s_i - s_j
@@ -179,7 +269,7 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
         double cre, cim;
         cot_half_branch(cx, sx, chy, shy, cre, cim);
         Kv = 0.5 * (cim + exj * cre);
-        Gv = 0.5 * (cre - exi * cim) - c0T[d];
+        Gv = 0.5 * (cre - exi * cim) - tb[2][e];
       } else {
         const double den = 1.0 / (1.0 + exi * exi);
         Kv = -0.5 * exxi * den;
@@ -196,98 +286,111 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
       a = Kv * invN + (i == j ? 0.5 : 0.0);
       gm = Gv * invN;
     }
-    if (i < Np && j < Np) {
-      const size_t o = (size_t)j * Np + i;
-      A[o] = a;
-      Gm[o] = gm;
-      if (A32) A32[o] = (float)a;
-    }
+    const size_t o = (size_t)j * Np + i;
+    A[o] = a;
+    Gm[o] = gm;
+    if (A32) A32[o] = (float)a;
   }
 }
 
 // -------------------------------------------------------------------------------------
-// 64 x 64 tile routines.  LDS tiles are row-major with a pad column: T[r * TLD + c].
-// Every routine is called by all WW_NT = 256 threads of the workgroup.
+// 64 x 64 tile routines, templated on the element type T (double: FP64 path; float:
+// the factorisation of the mixed-precision path).  LDS tiles are row-major with a pad
+// column: T[r * TLD + c].  Every routine is called by all WW_NT = 256 threads.
 // -------------------------------------------------------------------------------------
 #define TLD 65
 #define TILE_DBL (64 * TLD)
 
-// global (column-major, ld) -> LDS tile; all 16 loads of a thread are issued first
-__device__ inline void tile_load(double* T, const double* __restrict__ G, size_t ld) {
-  double v[16];
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int idx = threadIdx.x + WW_NT * m;
-    v[m] = G[(size_t)(idx >> 6) * ld + (idx & 63)];
-  }
-#pragma unroll
-  for (int m = 0; m < 16; ++m) {
-    const int idx = threadIdx.x + WW_NT * m;
-    T[(idx & 63) * TLD + (idx >> 6)] = v[m];
-  }
-}
-// same for a tile of right-hand sides with ncol valid columns (the rest are zero)
-__device__ inline void rhs_tile_load(double* T, const double* __restrict__ G, size_t ld, int ncol) {
-  double v[16];
+// global (column-major, ld, element type S) -> LDS tile of T; ncol valid columns, the
+// rest zero; all 16 loads of a thread are issued before the stores
+template <typename T, typename S>
+__device__ inline void tile_load(T* Ts, const S* __restrict__ G, size_t ld, int ncol = 64) {
+  S v[16];
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int idx = threadIdx.x + WW_NT * m;
     const int c = idx >> 6;
-    v[m] = (c < ncol) ? G[(size_t)c * ld + (idx & 63)] : 0.0;
+    v[m] = (c < ncol) ? G[(size_t)c * ld + (idx & 63)] : S(0);
   }
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int idx = threadIdx.x + WW_NT * m;
-    T[(idx & 63) * TLD + (idx >> 6)] = v[m];
+    Ts[(idx & 63) * TLD + (idx >> 6)] = (T)v[m];
   }
 }
-__device__ inline void tile_store(const double* T, double* __restrict__ G, size_t ld, int ncol = 64,
-                                  double scale = 1.0) {
+template <typename T>
+__device__ inline void rhs_tile_load(T* Ts, const double* __restrict__ G, size_t ld, int ncol) {
+  tile_load<T, double>(Ts, G, ld, ncol);
+}
+template <typename T, typename S>
+__device__ inline void tile_store(const T* Ts, S* __restrict__ G, size_t ld, int ncol = 64, T scale = T(1)) {
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int idx = threadIdx.x + WW_NT * m;
     const int c = idx >> 6;
-    if (c < ncol) G[(size_t)c * ld + (idx & 63)] = scale * T[(idx & 63) * TLD + c];
+    if (c < ncol) G[(size_t)c * ld + (idx & 63)] = (S)(scale * Ts[(idx & 63) * TLD + c]);
   }
 }
 
 // -------------------------------------------------------------------------------------
-// MFMA 64 x 64 x 64 product of two LDS tiles: acc = As * Bs.
-// Wave w computes the 32 x 32 quadrant (w >> 1, w & 1) as 2 x 2 blocks of
-// v_mfma_f64_16x16x4f64.  Operand layout (lane l): A[row l%16][k l/16],
-// B[k l/16][col l%16]; result lane l holds column l%16, rows 4 i + l/16, i = 0..3.
+// MFMA 64 x 64 x 64 product of two LDS tiles: acc = As * Bs (accumulating).
+// Wave w computes the 32 x 32 quadrant (w >> 1, w & 1) as 2 x 2 blocks of 16 x 16 x 4
+// MFMAs (v_mfma_f64_16x16x4f64 / v_mfma_f32_16x16x4f32).  Operand layout (lane l):
+// A[row l%16][k l/16], B[k l/16][col l%16].  Result lane l holds column l%16 and rows
+// 4 i + l/16 (f64) or 4 (l/16) + i (f32), i = 0..3.
 // -------------------------------------------------------------------------------------
 typedef double dbl4 __attribute__((ext_vector_type(4)));
+typedef float flt4 __attribute__((ext_vector_type(4)));
 
-struct Acc64 {
-  dbl4 v[2][2];
+template <typename T> struct Mfma;
+template <> struct Mfma<double> {
+  typedef dbl4 V;
+  static __device__ __forceinline__ V step(double a, double b, V c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int rq) { return 4 * i + rq; }
+};
+template <> struct Mfma<float> {
+  typedef flt4 V;
+  static __device__ __forceinline__ V step(float a, float b, V c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int i, int rq) { return 4 * rq + i; }
 };
 
-__device__ inline void acc_zero(Acc64& acc) {
+template <typename T>
+struct Acc64 {
+  typename Mfma<T>::V v[2][2];
+};
+
+template <typename T>
+__device__ inline void acc_zero(Acc64<T>& acc) {
   for (int a = 0; a < 2; ++a)
-    for (int b = 0; b < 2; ++b) acc.v[a][b] = dbl4{0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < 2; ++b) acc.v[a][b] = typename Mfma<T>::V{T(0), T(0), T(0), T(0)};
 }
 
-__device__ inline void mfma_tile(const double* As, const double* Bs, Acc64& acc) {
+template <typename T>
+__device__ inline void mfma_tile(const T* As, const T* Bs, Acc64<T>& acc) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
 #pragma unroll 4
   for (int k = 0; k < 64; k += 4) {
-    const double a0 = As[(r0 + li) * TLD + k + lk];
-    const double a1 = As[(r0 + 16 + li) * TLD + k + lk];
-    const double b0 = Bs[(k + lk) * TLD + c0 + li];
-    const double b1 = Bs[(k + lk) * TLD + c0 + 16 + li];
-    acc.v[0][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b0, acc.v[0][0], 0, 0, 0);
-    acc.v[0][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a0, b1, acc.v[0][1], 0, 0, 0);
-    acc.v[1][0] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b0, acc.v[1][0], 0, 0, 0);
-    acc.v[1][1] = __builtin_amdgcn_mfma_f64_16x16x4f64(a1, b1, acc.v[1][1], 0, 0, 0);
+    const T a0 = As[(r0 + li) * TLD + k + lk];
+    const T a1 = As[(r0 + 16 + li) * TLD + k + lk];
+    const T b0 = Bs[(k + lk) * TLD + c0 + li];
+    const T b1 = Bs[(k + lk) * TLD + c0 + 16 + li];
+    acc.v[0][0] = Mfma<T>::step(a0, b0, acc.v[0][0]);
+    acc.v[0][1] = Mfma<T>::step(a0, b1, acc.v[0][1]);
+    acc.v[1][0] = Mfma<T>::step(a1, b0, acc.v[1][0]);
+    acc.v[1][1] = Mfma<T>::step(a1, b1, acc.v[1][1]);
   }
 }
 
 // acc into an LDS tile: T = s * acc (mode 0) or T += s * acc (mode 1)
-__device__ inline void acc_to_lds(const Acc64& acc, double* T, int mode, double s) {
+template <typename T>
+__device__ inline void acc_to_lds(const Acc64<T>& acc, T* Ts, int mode, T s) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
@@ -296,36 +399,54 @@ __device__ inline void acc_to_lds(const Acc64& acc, double* T, int mode, double 
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const int rr = r0 + 16 * a + 4 * i + rq;
+        const int rr = r0 + 16 * a + Mfma<T>::row(i, rq);
         const int cc = c0 + 16 * b + col;
-        if (mode == 0) T[rr * TLD + cc] = s * acc.v[a][b][i];
-        else T[rr * TLD + cc] += s * acc.v[a][b][i];
+        if (mode == 0) Ts[rr * TLD + cc] = s * acc.v[a][b][i];
+        else Ts[rr * TLD + cc] += s * acc.v[a][b][i];
       }
 }
 
 // -------------------------------------------------------------------------------------
-// In-place Gauss-Jordan inverse of the 64 x 64 LDS tile T (no pivoting).  Thread
-// (tr = tid & 15, tc = tid >> 4) keeps the 4 x 4 block rows 4tr.., columns 4tc.. in
-// registers; per elimination step the pivot row and pivot column are published in
-// LDS (double-buffered, one barrier per step).  Returns the smallest |pivot|.
-// `pub` is LDS scratch of 4 * 64 doubles.
+// In-place Gauss-Jordan inverse of the 64 x 64 LDS tile, without pivoting.  Thread
+// (tr = tid & 15, tc = tid >> 4) keeps the 4 x 4 block of rows 4tr.., columns 4tc.. in
+// registers.  For pivot p every entry follows one rule,  a_rc <- a_rc - kap_r rho_c,
+//   rho_c = a_pc / a_pp (c != p),  rho_p = 1 + 1/a_pp,
+//   kap_r = a_rp (r != p),         kap_p = a_pp - 1,
+// which yields A_QQ - a_Qp a_pQ / a_pp, a_pQ / a_pp, -a_Qp / a_pp and 1/a_pp on the four
+// parts.  The pivot row and column are published in LDS (double-buffered, one barrier
+// per pivot).  1/a_pp: hardware reciprocal refined by Newton steps.  `pub` is LDS
+// scratch of 256 elements.  Returns the smallest |pivot|.
 // -------------------------------------------------------------------------------------
-__device__ inline double lds_gj_inverse(double* T, double* pub) {
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+__device__ __forceinline__ float recip(float x) {
+  float r = __builtin_amdgcn_rcpf(x);
+  float e = fmaf(-x, r, 1.0f);
+  return fmaf(r, e, r);
+}
+
+template <typename T>
+__device__ inline double lds_gj_inverse(T* Ts, T* pub) {
   const int tr = threadIdx.x & 15, tc = threadIdx.x >> 4;
   const int R0 = 4 * tr, C0 = 4 * tc;
-  double v[4][4];
+  T v[4][4];
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) v[i][j] = T[(R0 + i) * TLD + C0 + j];
-  double minpiv = 1e300;
+    for (int j = 0; j < 4; ++j) v[i][j] = Ts[(R0 + i) * TLD + C0 + j];
+  T minpiv = T(1e30);
   for (int pb = 0; pb < 16; ++pb) {
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const int p = 4 * pb + q;
-      double* prow = pub + (p & 1) * 128;
-      double* pcol = prow + 64;
+      T* prow = pub + (q & 1) * 128;
+      T* pcol = prow + 64;
       if (tr == pb) {
 #pragma unroll
         for (int j = 0; j < 4; ++j) prow[C0 + j] = v[q][j];
@@ -335,35 +456,29 @@ __device__ inline double lds_gj_inverse(double* T, double* pub) {
         for (int i = 0; i < 4; ++i) pcol[R0 + i] = v[i][q];
       }
       __syncthreads();
-      const double piv = prow[p];
+      const T piv = prow[p];
       minpiv = fmin(minpiv, fabs(piv));
-      const double ip = 1.0 / piv;
-      double pr[4], pc[4];
+      const T ip = recip(piv);
+      T rho[4], kap[4];
 #pragma unroll
-      for (int j = 0; j < 4; ++j) pr[j] = prow[C0 + j] * ip;
+      for (int j = 0; j < 4; ++j) rho[j] = prow[C0 + j] * ip;
 #pragma unroll
-      for (int i = 0; i < 4; ++i) pc[i] = pcol[R0 + i];
+      for (int i = 0; i < 4; ++i) kap[i] = pcol[R0 + i];
+      if (tc == pb) rho[q] = T(1) + ip;
+      if (tr == pb) kap[q] = piv - T(1);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const bool prow_i = (R0 + i) == p;
+      for (int i = 0; i < 4; ++i)
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const bool pcol_j = (C0 + j) == p;
-          double x = v[i][j];
-          if (prow_i) x = pcol_j ? ip : pr[j];
-          else x = pcol_j ? -pc[i] * ip : x - pc[i] * pr[j];
-          v[i][j] = x;
-        }
-      }
+        for (int j = 0; j < 4; ++j) v[i][j] = fma(-kap[i], rho[j], v[i][j]);
     }
   }
   __syncthreads();
 #pragma unroll
   for (int i = 0; i < 4; ++i)
 #pragma unroll
-    for (int j = 0; j < 4; ++j) T[(R0 + i) * TLD + C0 + j] = v[i][j];
+    for (int j = 0; j < 4; ++j) Ts[(R0 + i) * TLD + C0 + j] = v[i][j];
   __syncthreads();
-  return minpiv;
+  return (double)minpiv;
 }
 
 // -------------------------------------------------------------------------------------
@@ -373,7 +488,7 @@ __device__ inline double lds_gj_inverse(double* T, double* pub) {
 //   Schur-complement blocks A_kk^(k); D_k = (A_kk^(k))^{-1} by Gauss-Jordan.
 // Step k:  Lt_ik = A_ik D_k (i > k),  A_ij -= Lt_ik A_kj (i, j > k).
 // The block-triangular inverses X = Lt^{-1} and Z = Ut^{-1} are accumulated in the
-// same launches, so every later solve A^{-1} B = Z (X B) is two MFMA GEMMs:
+// same launches, so every later solve A^{-1} B = Z (B + X B) is two MFMA GEMMs:
 //   X_ij (i > j) = -sum_{m=j}^{i-1} Lt_im X_mj     (rows of X final after step i-1)
 //   Z_kk = D_k,  Z_ik (i < k) = V_ik D_k,  V_ij = -sum_{m=i}^{j-1} Z_im Ut_mj.
 // Launch per step k (one workgroup per 64-tile task):
@@ -382,46 +497,81 @@ __device__ inline double lds_gj_inverse(double* T, double* pub) {
 //   role 2 (i > k, j <= k): L = A_ik D_k;  X_ik = -L (j = k) or X_ij -= L X_kj
 //   role 3 (i <= k, j > k): Z_ik = D_k (i = k) or V_ik D_k (stored when j = k+1);
 //                       V_kj = -D_k A_kj (i = k) or V_ij -= Z_ik A_kj
+// T = double (FP64 path) or float (mixed path: factor of an FP32 copy of A).
 // -------------------------------------------------------------------------------------
+template <typename T>
 struct BluBufs {
-  double* A;      // Np x Np, overwritten by the Schur complements
-  double* X;      // Lt^{-1}, strictly lower blocks (unit diagonal implicit)
-  double* Z;      // Ut^{-1}, upper blocks incl. diagonal
-  double* V;      // accumulators of Z (upper blocks)
-  double* Dinv;   // nb x 4096, D_k column-major
+  T* A;      // Np x Np, overwritten by the Schur complements
+  T* X;      // Lt^{-1}, strictly lower blocks (unit diagonal implicit)
+  T* Z;      // Ut^{-1}, upper blocks incl. diagonal
+  T* V;      // accumulators of Z (upper blocks)
+  T* Dinv;   // nb x 4096, D_k column-major
   int* status;
   int Np;
   double pivguard;
 };
 
-__device__ inline double* tileptr(double* M, int Np, int i, int j) {
+template <typename T>
+__device__ inline T* tileptr(T* M, int Np, int i, int j) {
   return M + (size_t)j * WW_TB * Np + (size_t)i * WW_TB;
 }
 
-__device__ inline void store_dinv(const double* T, double* D) {
+template <typename T>
+__device__ inline void store_dinv(const T* Ts, T* D) {
 #pragma unroll
   for (int m = 0; m < 16; ++m) {
     const int idx = threadIdx.x + WW_NT * m;
-    D[idx] = T[(idx & 63) * TLD + (idx >> 6)];
+    D[idx] = Ts[(idx & 63) * TLD + (idx >> 6)];
   }
 }
 
-__global__ __launch_bounds__(WW_NT) void k_blu_init(BluBufs b) {
-  extern __shared__ double sm[];
-  double* T = sm;
-  double* pub = sm + TILE_DBL;
-  tile_load(T, b.A, b.Np);
-  const double mp = lds_gj_inverse(T, pub);
+template <typename T>
+__global__ __launch_bounds__(WW_NT) void k_blu_init(BluBufs<T> b) {
+  extern __shared__ double sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
+  T* Ts = sm;
+  T* pub = sm + TILE_DBL;
+  tile_load<T, T>(Ts, b.A, b.Np);
+  const double mp = lds_gj_inverse<T>(Ts, pub);
   if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
-  store_dinv(T, b.Dinv);
-  tile_store(T, b.Z, b.Np);
+  store_dinv<T>(Ts, b.Dinv);
+  tile_store<T, T>(Ts, b.Z, b.Np);
 }
 
-__global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs b, int k) {
-  extern __shared__ double sm[];
-  double* As = sm;
-  double* Bs = sm + TILE_DBL;
-  double* pub = sm + 2 * TILE_DBL;
+// Load up to four 64 x 64 column-major tiles into LDS with all loads in flight at once
+// (null sources are skipped).
+template <typename T>
+__device__ inline void tiles_load4(T* const dst[4], const T* const src[4], const int ld[4]) {
+  T v[4][16];
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (src[q]) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int idx = threadIdx.x + WW_NT * m;
+        v[q][m] = src[q][(size_t)(idx >> 6) * ld[q] + (idx & 63)];
+      }
+    }
+#pragma unroll
+  for (int q = 0; q < 4; ++q)
+    if (src[q]) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int idx = threadIdx.x + WW_NT * m;
+        dst[q][(idx & 63) * TLD + (idx >> 6)] = v[q][m];
+      }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
+  extern __shared__ double sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
+  T* Ls = sm;                  // left factor source, then the left factor
+  T* Ds = sm + TILE_DBL;       // D_k
+  T* Rs = sm + 2 * TILE_DBL;   // right factor
+  T* Cs = sm + 3 * TILE_DBL;   // destination tile
+  T* pub = sm + 4 * TILE_DBL;
   const int Np = b.Np, nb = Np / WW_TB;
   const int nt = nb - k - 1;
   const int n1 = nt * nt, n2 = nt * (k + 1);
@@ -434,85 +584,88 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs b, int k) {
   } else {
     bid -= n1 + n2; role = 3; i = bid / nt; j = k + 1 + bid % nt;
   }
-  const double* Dk = b.Dinv + (size_t)k * 4096;
-  Acc64 acc;
-  // the left factor: L = A_ik D_k (roles 1, 2) or Z_ik (role 3) -> As
-  if (role == 3 && i == k) {
-    for (int idx = threadIdx.x; idx < 4096; idx += WW_NT) As[(idx & 63) * TLD + (idx >> 6)] = Dk[idx];
-    __syncthreads();
-  } else {
-    tile_load(As, role == 3 ? tileptr(b.V, Np, i, k) : tileptr(b.A, Np, i, k), Np);
-    for (int idx = threadIdx.x; idx < 4096; idx += WW_NT) Bs[(idx & 63) * TLD + (idx >> 6)] = Dk[idx];
-    __syncthreads();
-    acc_zero(acc);
-    mfma_tile(As, Bs, acc);
-    __syncthreads();
-    acc_to_lds(acc, As, 0, 1.0);
-    __syncthreads();
-    if (role == 3 && j == k + 1) tile_store(As, tileptr(b.Z, Np, i, k), Np);
+  const T* Dk = b.Dinv + (size_t)k * 4096;
+  const bool ldiag = (role == 3 && i == k);           // left factor is D_k itself
+  const bool xfirst = (role == 2 && j == k);          // X_ik = -A_ik D_k, no right factor
+  const bool vfirst = (role == 3 && i == k);          // V_kj = -D_k A_kj, no accumulation
+  T* dst = role == 1 ? tileptr(b.A, Np, i, j) : role == 2 ? tileptr(b.X, Np, i, j) : tileptr(b.V, Np, i, j);
+  {
+    T* const d4[4] = {Ls, Ds, Rs, Cs};
+    const T* const s4[4] = {
+        ldiag ? Dk : (role == 3 ? tileptr(b.V, Np, i, k) : tileptr(b.A, Np, i, k)),
+        ldiag ? nullptr : Dk,
+        xfirst ? nullptr : (role == 2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j)),
+        (xfirst || vfirst) ? nullptr : dst};
+    const int l4[4] = {ldiag ? 64 : Np, 64, Np, Np};
+    tiles_load4<T>(d4, s4, l4);
   }
-  if (role == 2 && j == k) {
-    tile_store(As, tileptr(b.X, Np, i, k), Np, 64, -1.0);
+  __syncthreads();
+  Acc64<T> acc;
+  if (!ldiag) {
+    acc_zero(acc);
+    mfma_tile(Ls, Ds, acc);
+    __syncthreads();
+    acc_to_lds(acc, Ls, 0, T(1));   // Ls = A_ik D_k (roles 1, 2) or V_ik D_k = Z_ik (role 3)
+    __syncthreads();
+    if (role == 3 && j == k + 1) tile_store<T, T>(Ls, tileptr(b.Z, Np, i, k), Np);
+  }
+  if (xfirst) {
+    tile_store<T, T>(Ls, tileptr(b.X, Np, i, k), Np, 64, T(-1));
     return;
   }
-  // right factor: A_kj (roles 1, 3) or X_kj (role 2)
-  tile_load(Bs, role == 2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j), Np);
-  __syncthreads();
   acc_zero(acc);
-  mfma_tile(As, Bs, acc);
+  mfma_tile(Ls, Rs, acc);
   __syncthreads();
-  double* dst = role == 1 ? tileptr(b.A, Np, i, j) : role == 2 ? tileptr(b.X, Np, i, j) : tileptr(b.V, Np, i, j);
-  if (role == 3 && i == k) {
-    acc_to_lds(acc, As, 0, -1.0);   // first contribution: V_kj = -D_k A_kj
-  } else {
-    tile_load(As, dst, Np);
-    __syncthreads();
-    acc_to_lds(acc, As, 1, -1.0);
-  }
+  if (vfirst) acc_to_lds(acc, Cs, 0, T(-1));
+  else acc_to_lds(acc, Cs, 1, T(-1));
   __syncthreads();
   if (role == 1 && i == k + 1 && j == k + 1) {
     // Schur complement block of the next step: invert it (D_{k+1} = Z_{k+1,k+1})
-    const double mp = lds_gj_inverse(As, pub);
+    const double mp = lds_gj_inverse<T>(Cs, pub);
     if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
-    store_dinv(As, b.Dinv + (size_t)(k + 1) * 4096);
-    tile_store(As, tileptr(b.Z, Np, k + 1, k + 1), Np);
+    store_dinv<T>(Cs, b.Dinv + (size_t)(k + 1) * 4096);
+    tile_store<T, T>(Cs, tileptr(b.Z, Np, k + 1, k + 1), Np);
     return;
   }
-  tile_store(As, dst, Np);
+  tile_store<T, T>(Cs, dst, Np);
 }
 
 // last column block of Z: Z_i,nb-1 = V_i,nb-1 D_nb-1 (i < nb - 1)
-__global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs b) {
-  extern __shared__ double sm[];
-  double* As = sm;
-  double* Bs = sm + TILE_DBL;
+template <typename T>
+__global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs<T> b) {
+  extern __shared__ double sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
+  T* As = sm;
+  T* Bs = sm + TILE_DBL;
   const int Np = b.Np, nb = Np / WW_TB;
   const int i = blockIdx.x, k = nb - 1;
-  tile_load(As, tileptr(b.V, Np, i, k), Np);
-  const double* Dk = b.Dinv + (size_t)k * 4096;
-  for (int idx = threadIdx.x; idx < 4096; idx += WW_NT) Bs[(idx & 63) * TLD + (idx >> 6)] = Dk[idx];
+  tile_load<T, T>(As, tileptr(b.V, Np, i, k), Np);
+  tile_load<T, T>(Bs, b.Dinv + (size_t)k * 4096, 64);
   __syncthreads();
-  Acc64 acc;
+  Acc64<T> acc;
   acc_zero(acc);
   mfma_tile(As, Bs, acc);
   __syncthreads();
-  acc_to_lds(acc, As, 0, 1.0);
+  acc_to_lds(acc, As, 0, T(1));
   __syncthreads();
-  tile_store(As, tileptr(b.Z, Np, i, k), Np);
+  tile_store<T, T>(As, tileptr(b.Z, Np, i, k), Np);
 }
 
 // -------------------------------------------------------------------------------------
 // Blocked GEMM with split K: part[s] = sum over the k-tiles of chunk s of
-// T(rb, kt) * B(kt, :), 64 x 64 output tiles.  mode 0: all k-tiles (Gm Gamma);
-// mode 1: kt < rb (strictly lower X); mode 2: kt >= rb (upper Z).
-// k_gemm_reduce: out = add + sum_s part[s]  (add may be null).
+// M(rb, kt) * B(kt, :), 64 x 64 output tiles; M has element type T (double, or float
+// for the FP32 factors), B and the partials are double (B is rounded to T on load).
+// mode 0: all k-tiles;  mode 1: kt < rb (strictly lower X);  mode 2: kt >= rb (upper Z).
+// k_gemm_reduce: out = add + sgn * sum_s part[s]  (add may be null).
 // -------------------------------------------------------------------------------------
-__global__ __launch_bounds__(WW_NT) void k_gemm_part(const double* __restrict__ T, int Np, int mode,
+template <typename T>
+__global__ __launch_bounds__(WW_NT) void k_gemm_part(const T* __restrict__ Mt, int Np, int mode,
                                                      const double* __restrict__ B, int R,
                                                      double* __restrict__ part, int kchunk) {
-  extern __shared__ double sm[];
-  double* As = sm;
-  double* Bs = sm + TILE_DBL;
+  extern __shared__ double sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
+  T* As = sm;
+  T* Bs = sm + TILE_DBL;
   const size_t ld = Np;
   const int rb = blockIdx.x;
   const int c0 = blockIdx.y * 64;
@@ -522,28 +675,47 @@ __global__ __launch_bounds__(WW_NT) void k_gemm_part(const double* __restrict__ 
   int lo = s * kchunk, hi = min(nkt, lo + kchunk);
   if (mode == 1) hi = min(hi, rb);
   if (mode == 2) lo = max(lo, rb);
-  Acc64 acc;
+  Acc64<T> acc;
   acc_zero(acc);
+  T ra[16];
+  double rbv[16];
+  auto fetch = [&](int kt) {
+    const T* Tt = Mt + (size_t)kt * WW_TB * ld + (size_t)rb * WW_TB;
+    const double* Bt = B + (size_t)c0 * ld + (size_t)kt * WW_TB;
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = threadIdx.x + WW_NT * m;
+      const int c = idx >> 6;
+      ra[m] = Tt[(size_t)c * ld + (idx & 63)];
+      rbv[m] = (c < ncol) ? Bt[(size_t)c * ld + (idx & 63)] : 0.0;
+    }
+  };
+  if (lo < hi) fetch(lo);
   for (int kt = lo; kt < hi; ++kt) {
     __syncthreads();
-    tile_load(As, T + (size_t)kt * WW_TB * ld + (size_t)rb * WW_TB, ld);
-    rhs_tile_load(Bs, B + (size_t)c0 * ld + (size_t)kt * WW_TB, ld, ncol);
+#pragma unroll
+    for (int m = 0; m < 16; ++m) {
+      const int idx = threadIdx.x + WW_NT * m;
+      As[(idx & 63) * TLD + (idx >> 6)] = ra[m];
+      Bs[(idx & 63) * TLD + (idx >> 6)] = (T)rbv[m];
+    }
     __syncthreads();
+    if (kt + 1 < hi) fetch(kt + 1);   // next tiles in flight during the MFMAs
     mfma_tile(As, Bs, acc);
   }
   __syncthreads();
-  acc_to_lds(acc, As, 0, 1.0);
+  acc_to_lds(acc, As, 0, T(1));
   __syncthreads();
-  tile_store(As, part + (size_t)s * ld * R + (size_t)c0 * ld + (size_t)rb * WW_TB, ld, ncol);
+  tile_store<T, double>(As, part + (size_t)s * ld * R + (size_t)c0 * ld + (size_t)rb * WW_TB, ld, ncol);
 }
 
 __global__ void k_gemm_reduce(const double* __restrict__ part, int nsplit, const double* __restrict__ add,
-                              double* __restrict__ out, int Np, int R) {
+                              double sgn, double* __restrict__ out, int Np, int R) {
   const size_t n = (size_t)Np * R;
   for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-    double s = add ? add[idx] : 0.0;
+    double s = 0.0;
     for (int p = 0; p < nsplit; ++p) s += part[(size_t)p * n + idx];
-    out[idx] = s;
+    out[idx] = (add ? add[idx] : 0.0) + sgn * s;
   }
 }
 
@@ -566,8 +738,18 @@ __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, 
   const int ca = 2 * blockIdx.x, cb = ca + 1;
   const bool hasb = cb < ncols;
   const int tid = threadIdx.x;
-  for (int t = tid; t < N; t += WW_NT)
-    Z[t] = cmk(Mu[(size_t)ca * Np + t], hasb ? Mu[(size_t)cb * Np + t] : 0.0);
+  {
+    double va[NPT], vb[NPT];
+    gload(va, Mu + (size_t)ca * Np, N);
+    gload(vb, Mu + (size_t)(hasb ? cb : ca) * Np, N);
+    pin(va);
+    pin(vb);
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int t = tidx(m);
+      if (t < N) Z[t] = cmk(va[m], hasb ? vb[m] : 0.0);
+    }
+  }
   fft_lds(Z, W, tws, P, -1);
   for (int t = tid; t < N; t += WW_NT) {
     cplx A, B;
@@ -609,19 +791,31 @@ __global__ __launch_bounds__(WW_NT) void k_base_rhs(const double* __restrict__ Y
   const FftPlan P = make_plan(N);
   const int tid = threadIdx.x;
   load_twiddles(tws, tw, N);
-  for (int t = tid; t < N; t += WW_NT) {
-    const double ex = aux[AUX_EX * nmax + t];
-    const double ps = aux[AUX_PHS * nmax + t];
-    const double G = Gphi[t];
-    const double den = 1.0 + ex * ex;
-    const double u = (ps - ex * G) / den;
-    const double v = (ex * ps + G) / den;
-    aux[AUX_U * nmax + t] = u;
-    aux[AUX_V * nmax + t] = v;
-    aux[AUX_W3 * nmax + t] = den * sqrt(den);
-    const double eta = Ys[t];
-    Z[t] = cmk(G, v * G - 0.5 * u * u - 0.5 * v * v - g * eta);
-    S[t] = cmk(tau * ex / sqrt(den), 0.0);
+  {
+    double exv[NPT], psv[NPT], Gv[NPT], etv[NPT];
+    gload(exv, aux + AUX_EX * nmax, N);
+    gload(psv, aux + AUX_PHS * nmax, N);
+    gload(Gv, Gphi, N);
+    gload(etv, Ys, N);
+    pin(exv);
+    pin(psv);
+    pin(Gv);
+    pin(etv);
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int t = tidx(m);
+      if (t < N) {
+        const double ex = exv[m], ps = psv[m], G = Gv[m];
+        const double den = 1.0 + ex * ex;
+        const double u = (ps - ex * G) / den;
+        const double v = (ex * ps + G) / den;
+        aux[AUX_U * nmax + t] = u;
+        aux[AUX_V * nmax + t] = v;
+        aux[AUX_W3 * nmax + t] = den * sqrt(den);
+        Z[t] = cmk(G, v * G - 0.5 * u * u - 0.5 * v * v - g * etv[m]);
+        S[t] = cmk(tau * ex / sqrt(den), 0.0);
+      }
+    }
   }
   fft_lds(Z, W, tws, P, -1);
   fft_lds(S, W, tws, P, -1);
@@ -660,12 +854,8 @@ __global__ void k_col_pre(const double* __restrict__ y, const double* __restrict
       continue;
     }
     const size_t oe = (size_t)c * n2 + i, op = oe + N;
-    double e = y[oe], p = y[op];
-    for (int j = 0; j < stage; ++j) {
-      const double a = coef[stage * 16 + j];
-      e += a * K[(size_t)j * kstride + oe];
-      p += a * K[(size_t)j * kstride + op];
-    }
+    const double e = stage_combine(y[oe], K, kstride, oe, coef, stage);
+    const double p = stage_combine(y[op], K, kstride, op, coef, stage);
     Ys[oe] = e;
     Ys[op] = p;
     Psi[idx] = p - aux[AUX_V * nmax + i] * e;
@@ -701,7 +891,25 @@ __global__ __launch_bounds__(WW_NT) void k_col_rhs(const double* __restrict__ Ys
   const double* av = aux + AUX_V * nmax;
   const double* aw = aux + AUX_W3 * nmax;
   // pass 1: d psidot, d etadot
-  for (int t = tid; t < N; t += WW_NT) Z[t] = cmk(yp[t] - av[t] * ye[t], ye[t]);
+  double ev[NPT], pv[NPT], vv[NPT];
+  gload(ev, ye, N);
+  gload(pv, yp, N);
+  gload(vv, av, N);
+  pin(ev);
+  pin(pv);
+  pin(vv);
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int t = tidx(m);
+    if (t < N) Z[t] = cmk(pv[m] - vv[m] * ev[m], ev[m]);
+  }
+  double uv[NPT], gv[NPT], wv[NPT];   // in flight during pass 1
+  gload(uv, au, N);
+  gload(gv, gp, N);
+  gload(wv, aw, N);
+  pin(uv);
+  pin(gv);
+  pin(wv);
   fft_lds(Z, W, tws, P, -1);
   for (int t = tid; t < N; t += WW_NT) {
     cplx A, B;
@@ -711,11 +919,15 @@ __global__ __launch_bounds__(WW_NT) void k_col_rhs(const double* __restrict__ Ys
   }
   fft_lds(W, Z, tws, P, +1);
   // pass 2
-  for (int t = tid; t < N; t += WW_NT) {
-    const double e = ye[t], u = au[t], v = av[t], G = gp[t];
-    const double dpsi = W[t].x, deta = W[t].y;
-    Z[t] = cmk(G, e * u);
-    S[t] = cmk(-u * dpsi + v * G - g * e, -e * u * v + tau * deta / aw[t]);
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int t = tidx(m);
+    if (t < N) {
+      const double e = ev[m], u = uv[m], v = vv[m], G = gv[m];
+      const double dpsi = W[t].x, deta = W[t].y;
+      Z[t] = cmk(G, e * u);
+      S[t] = cmk(-u * dpsi + v * G - g * e, -e * u * v + tau * deta / wv[m]);
+    }
   }
   fft_lds(Z, W, tws, P, -1);
   fft_lds(S, W, tws, P, -1);
@@ -754,16 +966,17 @@ __global__ __launch_bounds__(WW_NT) void k_step_end(double* __restrict__ y, cons
   const int c = c0 + blockIdx.x;
   double* yc = y + (size_t)c * 2 * N;
   const int tid = threadIdx.x;
-  for (int t = tid; t < N; t += WW_NT) {
-    double e = yc[t], p = yc[N + t];
-    for (int s = 0; s < nst; ++s) {
-      const double b = coef[COEF_B + s];
-      if (b != 0.0) {
-        e += b * K[(size_t)s * kstride + (size_t)c * 2 * N + t];
-        p += b * K[(size_t)s * kstride + (size_t)c * 2 * N + N + t];
-      }
+  {
+    double ev[NPT], pv[NPT];
+    stage_combine_vec(ev, y + (size_t)c * 2 * N, K + (size_t)c * 2 * N, kstride, 0, coef + COEF_B, nst, N);
+    stage_combine_vec(pv, y + (size_t)c * 2 * N, K + (size_t)c * 2 * N, kstride, N, coef + COEF_B, nst, N);
+    pin(ev);
+    pin(pv);
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int t = tidx(m);
+      if (t < N) Z[t] = cmk(ev[m], pv[m]);
     }
-    Z[t] = cmk(e, p);
   }
   fft_lds(Z, W, tws, P, -1);
   for (int t = tid; t < N; t += WW_NT) Z[t] = cscale(Z[t], sig[t]);

@@ -1,7 +1,10 @@
 """Write full-size reference results of the CPU oracle for the parity tests.
 
 Calls only oracle/ (and the seeded input generators).  Run from the repository root:
-    python tests/golden/make_oracle_fixtures.py [c2] [c4] [c3]
+    python tests/golden/make_oracle_fixtures.py [c2] [c4] [c3] [alt]
+With "alt", the runs use the oracle's alternative rounding of cosh/sinh (same formulas)
+and are written to <name>_oracle_alt.npz: the spread between the two oracle runs is the
+FP64 rounding floor of the march, to which the GPU path is compared.
 Each fixture stores r, drdT, f, J^T r (the gradient of f), the column norms of J and a
 sample of J columns, for the workload of the same name.  C3 takes about an hour on
 8 cores (7200 dense DtN solves at N = 1024).
@@ -22,13 +25,14 @@ SAMPLE_COLS = {"c2": [0, 1, 2, 7, 15, 31, 63], "c3": [0, 1, 2, 15, 40, 63, 127],
                "c4": [0, 1, 2, 15, 63, 127, 200, 255]}
 
 
-def make(name):
+def make(name, alt=False):
     w = W.CONFIGS[name]()
     t0 = time.time()
-    res = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
+    ar = O.F64ALT if alt else O.F64
+    res = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps, ar=ar)
     grad, dfdT = O.shoot_gradient(res)
     cols = np.array(SAMPLE_COLS[name])
-    out = os.path.join(HERE, f"{name}_oracle.npz")
+    out = os.path.join(HERE, f"{name}_oracle{'_alt' if alt else ''}.npz")
     eta0, _ = W.initial_state(w)
     np.savez_compressed(out, r=res["r"], drdT=res["drdT"], f=np.array(res["f"]), grad=grad,
                         dfdT=np.array(dfdT), Jcols=res["J"][:, cols], cols=cols,
@@ -38,5 +42,8 @@ def make(name):
 
 
 if __name__ == "__main__":
-    for n in (sys.argv[1:] or ["c2", "c4", "c3"]):
-        make(n)
+    args = sys.argv[1:]
+    alt = "alt" in args
+    names = [a for a in args if a != "alt"] or ["c2", "c4", "c3"]
+    for n in names:
+        make(n, alt=alt)

@@ -26,13 +26,16 @@ def relerr(a, b):
     return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
 
 
+@pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("N,h,R", [(64, math.inf, 5), (96, 1.0, 70), (256, 0.3, 130), (144, 2.0, 1)])
-def test_dtn_setup_and_solve_multi(N, h, R):
+def test_dtn_setup_and_solve_multi(N, h, R, mixed):
+    """FP64 and mixed form (FP32 block LU + 2 FP64 refinement sweeps) against the
+    oracle's partially pivoted FP64 LU; both to 1e-12."""
     ww, torch = _ww()
-    print(f"dtn parity N={N} h={h} R={R}", flush=True)
+    print(f"dtn parity N={N} h={h} R={R} mixed={mixed}", flush=True)
     eta = W.random_surface(N, seed=N + R, amp=0.06)
     rhs = W.random_rhs(N, R, seed=7 + N)
-    ctx = ww.Context(n_max=max(N, 64), r_max=max(R, 2))
+    ctx = ww.Context(n_max=max(N, 64), r_max=max(R, 2), mixed=mixed)
     ctx.dtn_setup(ww.to_dev(eta), h)
     out, mu = ctx.dtn_solve_multi(ww.to_dev(rhs), want_mu=True)
     torch.cuda.synchronize()
@@ -42,8 +45,8 @@ def test_dtn_setup_and_solve_multi(N, h, R):
     assert relerr(mu.cpu().numpy(), mref) < TOL
 
 
-def _shoot(ww, w, jacobian=True, drdT=True, nsteps=None):
-    ctx = ww.Context(n_max=max(w.N, 64), r_max=w.M + 1)
+def _shoot(ww, w, jacobian=True, drdT=True, nsteps=None, mixed=False):
+    ctx = ww.Context(n_max=max(w.N, 64), r_max=w.M + 1, mixed=mixed)
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     return ctx.shoot_eval(ww.to_dev(w.params), w.T, nsteps or w.nsteps, jacobian=jacobian, drdT=drdT)
 
@@ -71,11 +74,12 @@ def _cmp(res, ref, jac=True, g=1.0, tau=0.0):
     return out
 
 
-def test_shoot_eval_config1_full():
+@pytest.mark.parametrize("mixed", [False, True])
+def test_shoot_eval_config1_full(mixed):
     ww, torch = _ww()
     w = W.c1()
-    print(f"shoot parity {w.name}", flush=True)
-    res = _shoot(ww, w)
+    print(f"shoot parity {w.name} mixed={mixed}", flush=True)
+    res = _shoot(ww, w, mixed=mixed)
     ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
     ref["eta0"] = W.initial_state(w)[0]
     e = _cmp(res, ref)
