@@ -5,34 +5,74 @@ Metric: Jacobian column-steps/s = M * nsteps / wall time of one shoot_eval (resi
 Jacobian and dr/dT) on the precision-form workload: h = 0.5, tau = 0.02, N = 1024,
 M = 128 Jacobian columns, 600 DOP853 steps to T/4 (7200 dense DtN evaluations with
 one LU each).  One benchmark "step" is one full shoot_eval.  Inputs are the seeded
-synthetic surface of the workload, resident in HBM before timing starts.
+synthetic surface of the workload, resident in HBM before timing starts.  `value` is
+the FP64 form; the FP32-LU + FP64-refinement form is timed the same way and reported
+in "mixed".
 
-Prints one JSON line (see the repository's design notes for the fields).
+Prints one JSON line.
 """
 from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
+
+FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (vector and MFMA)
+FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA
+
+
+def blas_threads() -> int:
+    try:
+        from threadpoolctl import threadpool_info
+        n = [i.get("num_threads", 0) for i in threadpool_info() if i.get("user_api") == "blas"]
+        if n:
+            return int(max(n))
+    except Exception:
+        pass
+    return int(os.environ.get("OMP_NUM_THREADS") or os.cpu_count())
 
 
 def cpu_baseline(w, nsteps_sample: int):
     """The CPU oracle on a bounded prefix of the same workload (same dt), on the
     host's cores: column-steps/s = M * steps / wall time."""
-    import numpy as np  # noqa: F401
     from oracle import ww_oracle as O
-    threads = os.environ.get("OMP_NUM_THREADS") or str(os.cpu_count())
     t0 = time.perf_counter()
     O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params,
                  w.T * nsteps_sample / w.nsteps, nsteps_sample)
     t = time.perf_counter() - t0
-    return {"value": w.M * nsteps_sample / t, "unit": "column-steps/s", "cores": int(threads),
+    return {"value": w.M * nsteps_sample / t, "unit": "column-steps/s", "cores": blas_threads(),
             "kind": "oracle",
-            "sample": f"{nsteps_sample} of {w.nsteps} RK steps of the same workload "
-                      f"({nsteps_sample * 12 + 1} DtN evaluations, {t:.1f} s)"}
+            "sample": f"first {nsteps_sample} of {w.nsteps} RK steps of the same workload, same dt "
+                      f"({nsteps_sample * 12 + 1} dense DtN evaluations with J, {t:.1f} s)"}
+
+
+def run(w, nsteps, T, mixed, steps, warmup, profile):
+    import torch
+    from paper_1210_5672_amd import ww
+    ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    if profile:
+        ctx.profile(True)
+    params = ww.to_dev(w.params)
+    tag = "mixed" if mixed else "fp64"
+    for i in range(warmup):
+        ctx.shoot_eval(params, T, nsteps)
+        print(f"# {tag} warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = None
+    for i in range(steps):
+        res = ctx.shoot_eval(params, T, nsteps)
+        print(f"# {tag} step {i + 1}/{steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t = time.perf_counter() - t0
+    phases = None
+    if profile:
+        phases = {"block_lu_ms": ctx.profile_read(0), "base_chain_ms": ctx.profile_read(1),
+                  "column_chain_ms": ctx.profile_read(2)}
+    return t, res, phases
 
 
 def main():
@@ -40,12 +80,12 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=2)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--nsteps", type=int, default=None,
-                    help="override the RK step count (profiling runs only; the metric "
-                         "line names the count used)")
+                    help="RK step count override (profiling runs only; the line names the count)")
     ap.add_argument("--cpu-sample-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-mixed", action="store_true")
+    ap.add_argument("--no-profile", action="store_true")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -54,31 +94,27 @@ def main():
               file=sys.stderr)
         sys.exit(2)
 
-    import torch
     from paper_1210_5672_amd import workloads as W
-    from paper_1210_5672_amd import ww
 
     w = W.c3()
     nsteps = args.nsteps or w.nsteps
     T = w.T if nsteps == w.nsteps else w.T * nsteps / w.nsteps   # same dt for a prefix
-    ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=(args.precision == "mixed"))
-    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
-    params = ww.to_dev(w.params)
-    print(f"# workload {w.name}: N={w.N} M={w.M} nsteps={nsteps} precision={args.precision}",
-          file=sys.stderr, flush=True)
-    for i in range(args.warmup):
-        ctx.shoot_eval(params, T, nsteps)
-        print(f"# warmup {i + 1}/{args.warmup} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    res = None
-    for i in range(args.steps):
-        res = ctx.shoot_eval(params, T, nsteps)
-        print(f"# step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
-    torch.cuda.synchronize()
-    t = time.perf_counter() - t0
+    print(f"# workload {w.name}: N={w.N} M={w.M} nsteps={nsteps}", file=sys.stderr, flush=True)
+    profile = not args.no_profile
+    t, res, phases = run(w, nsteps, T, False, args.steps, args.warmup, profile)
     ms = 1000.0 * t / args.steps
     value = w.M * nsteps * args.steps / t
+    n3 = float(w.N) ** 3
+    roofline = None
+    if phases:
+        # dominant kernel family: the block LU of one stage (k_blu_init, k_blu_step x 15,
+        # k_blu_final); algorithmic work 2/3 N^3 flops per factorisation
+        lu_s = phases["block_lu_ms"] * 1e-3
+        ach = (2.0 / 3.0) * n3 / lu_s / 1e12
+        roofline = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                    "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                    "kernel": "block LU per stage (k_blu_*), 2/3 N^3 flops per launch sequence",
+                    "phases_ms": phases}
     out = {
         "metric": "Jacobian column-steps/s at N=1024",
         "value": value,
@@ -90,14 +126,30 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32-lu+f64-refine",
+        "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "shoot_eval h=0.5 tau=0.02 N=1024 M=128 (precision form)",
-                   "N": w.N, "M": w.M, "nsteps": nsteps, "precision": args.precision,
-                   "f": res["f"]},
-        "roofline": None,
+        "config": {"workload": "shoot_eval h=0.5 tau=0.02 N=1024 M=128 nsteps=600 (precision form)",
+                   "N": w.N, "M": w.M, "nsteps": nsteps, "f": res["f"]},
+        "roofline": roofline,
         "cpu_baseline": None,
     }
+    if not args.no_mixed:
+        import numpy as np
+        tm, resm, phm = run(w, nsteps, T, True, args.steps, args.warmup, profile)
+        r64, rm = res["r"].cpu().numpy(), resm["r"].cpu().numpy()
+        J64, Jm = res["J"].cpu().numpy(), resm["J"].cpu().numpy()
+        out["mixed"] = {
+            "value": w.M * nsteps * args.steps / tm, "ms_per_step": 1000.0 * tm / args.steps,
+            "dtype": "f32-lu+f64-refine",
+            "rel_diff_vs_fp64": {"r": float(np.linalg.norm(rm - r64) / np.linalg.norm(r64)),
+                                 "J": float(np.linalg.norm(Jm - J64) / np.linalg.norm(J64))},
+        }
+        if phm:
+            lu_s = phm["block_lu_ms"] * 1e-3
+            ach = (2.0 / 3.0) * n3 / lu_s / 1e12
+            out["mixed"]["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
+                                        "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
+                                        "phases_ms": phm}
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(out))

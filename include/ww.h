@@ -113,16 +113,45 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
                double *drdT, double *f);
 
 /*
+ * shoot_eval_batch: shoot_eval for n_inst independent instances (continuation
+ * instances of uneven N, depth, tension, M and step count), each with its own context
+ * (distinct contexts; give them distinct streams for the instances to overlap).  Each
+ * context replays its captured step graph on its stream; the steps of all instances are
+ * issued interleaved so the GPU overlaps them.  Per-instance arrays: params[i] (device),
+ * T[i], nsteps[i] (host), r[i] (device), J[i] (device or NULL; J may be NULL),
+ * drdT[i] (device or NULL; drdT may be NULL), f[i] (host; f may be NULL).
+ * Results are identical to n_inst separate shoot_eval calls.  Synchronises every
+ * context's stream; returns the first instance error.
+ */
+int shoot_eval_batch(int n_inst, ww_ctx *const *ctx, const double *const *params, const double *T,
+                     const int *nsteps, double *const *r, double *const *J, double *const *drdT,
+                     double *f);
+
+/*
  * shoot_adjoint (Sec. 3.2, App. B; discrete form): gradient of f = r.r/2 with respect
  * to the parameters, grad = J^T r, by the exact transpose of the discretised
  * variational march (reverse Runge-Kutta stages, transposed LU solves, transposed
  * Gm, -d/dx, -H), with the base state recomputed from checkpoints taken every
- * `ckpt_every` steps.  grad: device M.  dfdT (host or NULL): df/dT = r . drdT.
- * f (host or NULL).  Synchronises.
+ * `ckpt_every` steps.  The factors are FP64 also in a WW_MIXED context.  Device
+ * workspace for the checkpoints and for the factors of one segment (ckpt_every x stages
+ * x 3 Np^2 doubles) is allocated on the first call and kept until ww_destroy.
+ * grad: device M.  dfdT (host or NULL): df/dT = r . drdT.  f (host or NULL).
+ * Synchronises.
  * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EHIP.
  */
 int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int ckpt_every,
                   double *grad, double *dfdT, double *f);
+
+/*
+ * Measurement hooks (not part of the method): ww_profile(ctx, 1) makes the step graph
+ * record HIP events around three phases of every stage -- 0: the block LU of A
+ * (factorisation and block-triangular inverses), 1: the whole base chain (spectral
+ * prep, assembly, LU, base DtN, base right-hand side), 2: the column chain (the M
+ * variational columns).  ww_profile_read returns the mean duration in ms of `phase`
+ * over the stages of the last replayed step (synchronises the stream).
+ */
+int ww_profile(ww_ctx *ctx, int enable);
+int ww_profile_read(ww_ctx *ctx, int phase, double *avg_ms, int *count);
 
 /* thread-local message of the last failure on this thread ("" if none) */
 const char *ww_last_error(void);

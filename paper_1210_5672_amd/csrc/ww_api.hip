@@ -71,6 +71,17 @@ struct ww_ctx {
   double* fdev = nullptr;
   int* status = nullptr;
   std::vector<void*> allocs;
+  // adjoint: checkpoints, per-stage factor storage of one segment, work vectors
+  double* ckpt = nullptr;
+  size_t ckpt_cap = 0;
+  double* seg = nullptr;
+  size_t seg_cap = 0;
+  double* adj = nullptr;   // lam, mu, ups[16], gt, hd, e1, q, g2, zeta, y1, y2, rv, dv
+  // optional HIP events around phases of every stage of the captured step
+  // (0: block LU, 1: whole base chain, 2: column chain); the values of the last
+  // replayed step are read back by ww_profile_read
+  bool prof = false;
+  hipEvent_t pev[3][16][2] = {};
   // one RK step captured as a graph, replayed nsteps times
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
@@ -220,6 +231,9 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   HIPCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_col_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   HIPCHK(hipFuncSetAttribute((const void*)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_adj_pre, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_adj_mid, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  HIPCHK(hipFuncSetAttribute((const void*)k_adj_step, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   *out = c;
   return 0;
 }
@@ -227,6 +241,13 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
 void ww_destroy(ww_ctx* c) {
   if (!c) return;
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  for (int a = 0; a < 3; ++a)
+    for (int b = 0; b < 16; ++b)
+      for (int e = 0; e < 2; ++e)
+        if (c->pev[a][b][e]) (void)hipEventDestroy(c->pev[a][b][e]);
+  if (c->ckpt) (void)hipFree(c->ckpt);
+  if (c->seg) (void)hipFree(c->seg);
+  if (c->adj) (void)hipFree(c->adj);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   for (void* p : c->allocs) (void)hipFree(p);
   delete c;
@@ -297,17 +318,38 @@ static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
   return 0;
 }
 
+// profiling mark (only while a profiled step is being enqueued)
+static int g_prof_stage = -1;
+static int prof_mark(ww_ctx* c, int phase, int which) {
+  if (!c->prof || g_prof_stage < 0) return 0;
+  HIPCHK(hipEventRecord(c->pev[phase][g_prof_stage][which], c->stream));
+  return 0;
+}
+
 static bool mixed(const ww_ctx* c) { return (c->flags & WW_MIXED) != 0; }
+
+// The FP64 factor set of one stage: A (overwritten by the Schur complements), Gm, the
+// block-triangular inverses X, Z, and the scratch V, Dinv.  The adjoint keeps one set
+// per stage of a segment; everything else uses the context's set.
+struct Fac {
+  double *A, *Gm, *X, *Z, *V, *Dinv;
+  bool use32;   // mixed precision: factor the FP32 copy and refine the solves
+};
+static Fac fac_default(ww_ctx* c) { return Fac{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, mixed(c)}; }
 
 // assembly of A, Gm and the block LU of A (FP64, or of the FP32 copy in mixed mode)
 // with the block-triangular inverses
-static int enqueue_assemble_lu(ww_ctx* c) {
+static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   const int nb = c->Np / WW_TB;
   hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, c->aux, c->n_max, c->cosT, c->sinT,
-                     c->c0T, c->A, c->Gm, mixed(c) ? c->A32 : nullptr, c->N, c->Np, c->finite);
+                     c->c0T, F.A, F.Gm, F.use32 ? c->A32 : nullptr, c->N, c->Np, c->finite);
   LAUNCHCHK();
-  if (mixed(c)) return enqueue_blu<float>(c, blu_bufs<float>(c, c->A32, c->X32, c->Z32, c->V32, c->Dinv32));
-  return enqueue_blu<double>(c, blu_bufs<double>(c, c->A, c->Xi, c->Zi, c->Vi, c->Dinv));
+  int rc;
+  if ((rc = prof_mark(c, 0, 0))) return rc;
+  if (F.use32) rc = enqueue_blu<float>(c, blu_bufs<float>(c, c->A32, c->X32, c->Z32, c->V32, c->Dinv32));
+  else rc = enqueue_blu<double>(c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv));
+  if (rc) return rc;
+  return prof_mark(c, 0, 1);
 }
 
 // out = add + sgn * M B for R columns (ld Np), M taken as full (mode 0), strictly lower
@@ -336,16 +378,16 @@ static int enqueue_gemm(ww_ctx* c, const T* M, int mode, const double* B, const 
 // FP64:  X = Z (B + Xs B).
 // mixed: X = Z32 (B + X32 B), then nref sweeps of  r = B - A X (FP64 residual with the
 //        FP64 matrix),  X += Z32 (r + X32 r)  (FP32 factors, FP64 accumulation).
-static int enqueue_solve(ww_ctx* c, double* B, double* Y, double* X, double* Rs, int R) {
+static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* X, double* Rs, int R) {
   int rc;
-  if (!mixed(c)) {
-    if ((rc = enqueue_gemm<double>(c, c->Xi, 1, B, B, 1.0, Y, R))) return rc;
-    return enqueue_gemm<double>(c, c->Zi, 2, Y, nullptr, 1.0, X, R);
+  if (!F.use32) {
+    if ((rc = enqueue_gemm<double>(c, F.X, 1, B, B, 1.0, Y, R))) return rc;
+    return enqueue_gemm<double>(c, F.Z, 2, Y, nullptr, 1.0, X, R);
   }
   if ((rc = enqueue_gemm<float>(c, c->X32, 1, B, B, 1.0, Y, R))) return rc;
   if ((rc = enqueue_gemm<float>(c, c->Z32, 2, Y, nullptr, 1.0, X, R))) return rc;
   for (int it = 0; it < c->nref; ++it) {
-    if ((rc = enqueue_gemm<double>(c, c->A, 0, X, B, -1.0, Rs, R))) return rc;
+    if ((rc = enqueue_gemm<double>(c, F.A, 0, X, B, -1.0, Rs, R))) return rc;
     if ((rc = enqueue_gemm<float>(c, c->X32, 1, Rs, Rs, 1.0, Y, R))) return rc;
     if ((rc = enqueue_gemm<float>(c, c->Z32, 2, Y, X, 1.0, X, R))) return rc;
   }
@@ -353,53 +395,59 @@ static int enqueue_solve(ww_ctx* c, double* B, double* Y, double* X, double* Rs,
 }
 
 // DtN of R columns in B (ld Np): out = G psi (ld Np); mu in Mu; Rs residual scratch
-static int enqueue_dtn_cols(ww_ctx* c, double* B, double* Yt, double* Mu, double* Gam, double* HGm, double* out,
-                            double* Rs, int R) {
+static int enqueue_dtn_cols(ww_ctx* c, const Fac& F, double* B, double* Yt, double* Mu, double* Gam, double* HGm,
+                            double* out, double* Rs, int R) {
   int rc;
-  if ((rc = enqueue_solve(c, B, Yt, Mu, Rs, R))) return rc;
+  if ((rc = enqueue_solve(c, F, B, Yt, Mu, Rs, R))) return rc;
   hipLaunchKernelGGL(k_gamma, dim3((R + 1) / 2), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Mu, c->Np, R, Gam,
                      HGm, c->tw, c->N);
   LAUNCHCHK();
-  return enqueue_gemm<double>(c, c->Gm, 0, Gam, HGm, 1.0, out, R);
+  return enqueue_gemm<double>(c, F.Gm, 0, Gam, HGm, 1.0, out, R);
 }
 
 static size_t kstride(const ww_ctx* c) { return (size_t)2 * c->N * (c->M + 1); }
 
+
+
 // base chain of stage s: prep, assembly, LU, base DtN, base right-hand side -> kout
-static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout) {
+static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout, const Fac& F) {
   int rc;
+  if ((rc = prof_mark(c, 1, 0))) return rc;
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysrc, c->K, c->Ys, c->coef,
                      s, kstride(c), c->aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf);
   LAUNCHCHK();
-  if ((rc = enqueue_assemble_lu(c))) return rc;
-  if ((rc = enqueue_dtn_cols(c, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
+  if ((rc = enqueue_assemble_lu(c, F))) return rc;
+  if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
   hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, c->aux,
                      c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
-  return 0;
+  return prof_mark(c, 1, 1);
 }
 
 static int enqueue_col_chain(ww_ctx* c, int s) {
   int rc;
+  if ((rc = prof_mark(c, 2, 0))) return rc;
   const int M = c->M;
   const size_t tot = (size_t)c->Np * M;
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_col_pre, dim3(blocks), dim3(256), 0, c->stream, c->y, c->K, c->Ys, c->coef, s, kstride(c),
                      c->aux, c->n_max, c->Psi, c->Np, c->N, M);
   LAUNCHCHK();
-  if ((rc = enqueue_dtn_cols(c, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
+  if ((rc = enqueue_dtn_cols(c, fac_default(c), c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
   hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
                      c->aux, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
-  return 0;
+  return prof_mark(c, 2, 1);
 }
 
 static int enqueue_step(ww_ctx* c, bool cols) {
   int rc;
   for (int s = 0; s < c->nst; ++s) {
-    if ((rc = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c)))) return rc;
-    if (cols && c->M > 0)
-      if ((rc = enqueue_col_chain(c, s))) return rc;
+    g_prof_stage = s;
+    rc = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c), fac_default(c));
+    if (!rc && cols && c->M > 0) rc = enqueue_col_chain(c, s);
+    g_prof_stage = -1;
+    if (rc) return rc;
   }
   const int ncol = cols ? c->M + 1 : 1;
   hipLaunchKernelGGL(k_step_end, dim3(ncol), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y, c->K, kstride(c),
@@ -469,7 +517,7 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 4), c->stream, c->ydtn, c->K, c->Ys,
                      c->coef, 0, (size_t)0, c->aux, c->n_max, c->rhs0, c->Np, c->tw, N, c->hsurf);
   LAUNCHCHK();
-  if ((rc = enqueue_assemble_lu(c))) return rc;
+  if ((rc = enqueue_assemble_lu(c, fac_default(c)))) return rc;
   int st = 0;
   if ((rc = read_status(c, &st))) return rc;
   c->dtn_ready = true;
@@ -487,13 +535,49 @@ int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, dou
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs, N, c->Psi, Np, N, Np, nrhs);
   LAUNCHCHK();
   int rc;
-  if ((rc = enqueue_dtn_cols(c, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, nrhs))) return rc;
+  if ((rc = enqueue_dtn_cols(c, fac_default(c), c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, nrhs)))
+    return rc;
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Gpsi, Np, dtn_out, N, Np, N, nrhs);
   LAUNCHCHK();
   if (mu_out) {
     hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Mu, Np, mu_out, N, Np, N, nrhs);
     LAUNCHCHK();
   }
+  return 0;
+}
+
+int ww_profile(ww_ctx* c, int enable) {
+  if (!c) return fail(WW_EINVAL, "null argument");
+  if (enable && !c->pev[0][0][0])
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 16; ++b)
+        for (int e = 0; e < 2; ++e) HIPCHK(hipEventCreate(&c->pev[a][b][e]));
+  if ((bool)enable != c->prof) {
+    c->prof = enable != 0;
+    c->gnst = -1;   // re-capture the step graph with or without the event nodes
+  }
+  return 0;
+}
+
+int ww_profile_read(ww_ctx* c, int phase, double* avg_ms, int* count) {
+  if (!c || !avg_ms || phase < 0 || phase > 2) return fail(WW_EINVAL, "bad argument");
+  if (!c->prof) return fail(WW_EINVAL, "profiling is off");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double sum = 0.0;
+  int n = 0;
+  for (int s = 0; s < c->nst; ++s) {
+    float ms = 0.0f;
+    const hipError_t e = hipEventElapsedTime(&ms, c->pev[phase][s][0], c->pev[phase][s][1]);
+    if (e == hipSuccess) {
+      sum += ms;
+      ++n;
+    } else {
+      (void)hipGetLastError();
+    }
+  }
+  if (n == 0) return fail(WW_EHIP, "no profiled stage (run shoot_eval with profiling on first)");
+  *avg_ms = sum / n;
+  if (count) *count = n;
   return 0;
 }
 
@@ -517,9 +601,11 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
   return 0;
 }
 
-int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
-               double* f) {
-  if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
+}  // extern "C"
+
+// shoot_eval in three parts so that shoot_eval_batch can interleave instances:
+// prepare (coefficients, initial state, step graph), one step, finish (outputs).
+static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, bool cols) {
   if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_eval before shoot_setup");
   if (c->nst < 1) return fail(WW_EINVAL, "no tableau set");
   if (nsteps < 1 || !std::isfinite(T)) return fail(WW_EINVAL, "nsteps >= 1 and finite T required");
@@ -527,12 +613,164 @@ int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r,
   if ((rc = set_grid(c, c->shootN, c->shootH))) return rc;
   c->dtn_ready = false;   // the factor arrays are reused by the march
   const int N = c->N, M = c->M;
-  const bool cols = (J != nullptr) && M > 0;
-  // step coefficients: a_sj dt, b_s dt
   double coef[COEF_SIZE];
   std::memset(coef, 0, sizeof(coef));
   const double dt = T / (4.0 * nsteps);
   for (int s = 0; s < c->nst; ++s) {
+    for (int j = 0; j < s; ++j) coef[s * 16 + j] = c->ta[s * 16 + j] * dt;
+    coef[COEF_B + s] = c->tb[s] * dt;
+  }
+  coef[COEF_DT] = dt;
+  HIPCHK(hipMemcpyAsync(c->coef, coef, sizeof(coef), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
+  const size_t tot = (size_t)2 * N * (M + 1);
+  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
+  LAUNCHCHK();
+  if (c->use_graph) return ensure_step_graph(c, cols);
+  return 0;
+}
+
+static int shoot_one_step(ww_ctx* c, bool cols) {
+  if (c->use_graph) {
+    HIPCHK(hipGraphLaunch(c->step_exec, c->stream));
+    return 0;
+  }
+  return enqueue_step(c, cols);
+}
+
+static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT, double* fhost) {
+  const int N = c->N, M = c->M;
+  int rc;
+  {
+    const size_t n = (size_t)2 * N * (cols ? M + 1 : 1);
+    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, c->y, n, c->status);
+    LAUNCHCHK();
+  }
+  if (drdT)
+    if ((rc = enqueue_base_chain(c, c->y, 0, c->Kx, fac_default(c)))) return rc;
+  {
+    const size_t tot = (size_t)N * (M + 1);
+    const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_outputs, dim3(blocks), dim3(256), 0, c->stream, c->y, c->Kx, r, cols ? J : nullptr, drdT, N,
+                       cols ? M : 0);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, r, N, c->fdev);
+  LAUNCHCHK();
+  if (fhost) HIPCHK(hipMemcpyAsync(fhost, c->fdev, 8, hipMemcpyDeviceToHost, c->stream));
+  return 0;
+}
+
+static int shoot_status(ww_ctx* c) {
+  int st = 0, rc;
+  if ((rc = read_status(c, &st))) return rc;
+  if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
+  if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
+  return 0;
+}
+
+extern "C" {
+
+int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
+               double* f) {
+  if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
+  const bool cols = (J != nullptr) && c->M > 0;
+  int rc;
+  if ((rc = shoot_prepare(c, params, T, nsteps, cols))) return rc;
+  for (int n = 0; n < nsteps; ++n)
+    if ((rc = shoot_one_step(c, cols))) return rc;
+  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
+  return shoot_status(c);
+}
+
+int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params, const double* T,
+                     const int* nsteps, double* const* r, double* const* J, double* const* drdT, double* f) {
+  if (n_inst < 1 || !ctx || !params || !T || !nsteps || !r) return fail(WW_EINVAL, "null argument");
+  for (int i = 0; i < n_inst; ++i) {
+    if (!ctx[i] || !r[i]) return fail(WW_EINVAL, "null context or output");
+    for (int k = 0; k < i; ++k)
+      if (ctx[k] == ctx[i]) return fail(WW_EINVAL, "the contexts of a batch must be distinct");
+  }
+  int rc;
+  int maxsteps = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const bool cols = J && J[i] && ctx[i]->M > 0;
+    if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols))) return rc;
+    maxsteps = std::max(maxsteps, nsteps[i]);
+  }
+  // interleave the instances step by step: each context replays its own step graph on
+  // its own stream, so the hardware queues overlap the instances
+  for (int n = 0; n < maxsteps; ++n)
+    for (int i = 0; i < n_inst; ++i)
+      if (n < nsteps[i])
+        if ((rc = shoot_one_step(ctx[i], J && J[i] && ctx[i]->M > 0))) return rc;
+  for (int i = 0; i < n_inst; ++i) {
+    const bool cols = J && J[i] && ctx[i]->M > 0;
+    if ((rc = shoot_finish(ctx[i], cols, r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr, f ? &f[i] : nullptr)))
+      return rc;
+  }
+  int first_err = 0;
+  for (int i = 0; i < n_inst; ++i) {
+    const int e = shoot_status(ctx[i]);
+    if (e && !first_err) first_err = e;
+  }
+  return first_err;
+}
+
+int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckpt_every, double* grad,
+                  double* dfdT, double* f) {
+  if (!c || !grad || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
+  if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_adjoint before shoot_setup");
+  if (c->nst < 1) return fail(WW_EINVAL, "no tableau set");
+  if (nsteps < 1 || !std::isfinite(T) || ckpt_every < 1) return fail(WW_EINVAL, "nsteps, ckpt_every >= 1 required");
+  int rc;
+  if ((rc = set_grid(c, c->shootN, c->shootH))) return rc;
+  c->dtn_ready = false;
+  const int N = c->N, Np = c->Np, M = c->M, nst = c->nst;
+  const int C = std::min(ckpt_every, nsteps);
+  const int nseg = (nsteps + C - 1) / C;
+  // buffers: checkpoints, per-stage factor sets of one segment, adjoint work vectors
+  const size_t n2 = (size_t)2 * N;
+  const size_t slot = (size_t)3 * Np * Np + (size_t)3 * N;   // X, Z, Gm, saux
+  const size_t nslot = (size_t)C * nst;
+  if (c->ckpt_cap < (size_t)(nseg + 1) * n2) {
+    if (c->ckpt) HIPCHK(hipFree(c->ckpt));
+    c->ckpt = nullptr;
+    HIPCHK(hipMalloc(&c->ckpt, (size_t)(nseg + 1) * n2 * 8));
+    c->ckpt_cap = (size_t)(nseg + 1) * n2;
+  }
+  if (c->seg_cap < nslot * slot) {
+    if (c->seg) HIPCHK(hipFree(c->seg));
+    c->seg = nullptr;
+    HIPCHK(hipMalloc(&c->seg, nslot * slot * 8));
+    c->seg_cap = nslot * slot;
+  }
+  if (!c->adj) HIPCHK(hipMalloc(&c->adj, (size_t)(20 * 2 * c->n_max + 8 * c->np_max) * 8));
+  double* lam = c->adj;
+  double* mu = lam + 2 * c->n_max;
+  double* ups = mu + 2 * c->n_max;                 // 16 x 2N
+  const size_t ustride = 2 * (size_t)c->n_max;
+  double* gt = ups + 16 * ustride;
+  double* hd = gt + c->np_max;
+  double* e1 = hd + c->np_max;
+  double* qv = e1 + c->np_max;
+  double* g2 = qv + c->np_max;
+  double* zeta = g2 + c->np_max;
+  double* y1 = zeta + c->np_max;
+  double* y2 = y1 + c->np_max;
+  double* rv = y2 + c->np_max;       // r (N)
+  double* dv = rv + c->n_max;        // drdT (N)
+  auto slot_fac = [&](size_t k) {
+    double* b = c->seg + k * slot;
+    return Fac{c->A, b + 2 * (size_t)Np * Np, b, b + (size_t)Np * Np, c->Vi, c->Dinv, false};
+  };
+  auto slot_aux = [&](size_t k) { return c->seg + k * slot + (size_t)3 * Np * Np; };
+  // step coefficients
+  double coef[COEF_SIZE];
+  std::memset(coef, 0, sizeof(coef));
+  const double dt = T / (4.0 * nsteps);
+  for (int s = 0; s < nst; ++s) {
     for (int j = 0; j < s; ++j) coef[s * 16 + j] = c->ta[s * 16 + j] * dt;
     coef[COEF_B + s] = c->tb[s] * dt;
   }
@@ -545,44 +783,99 @@ int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r,
     hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
     LAUNCHCHK();
   }
-  // the march works on R = M + 1 columns when J is requested, on the base otherwise;
-  // K and state strides always use M + 1 columns
-  if (c->use_graph) {
-    if ((rc = ensure_step_graph(c, cols))) return rc;
-    for (int n = 0; n < nsteps; ++n) HIPCHK(hipGraphLaunch(c->step_exec, c->stream));
-  } else {
-    for (int n = 0; n < nsteps; ++n)
-      if ((rc = enqueue_step(c, cols))) return rc;
-  }
-  {
-    const size_t n = (size_t)2 * N * (cols ? M + 1 : 1);
-    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, c->y, n, c->status);
+  // 1. forward base march with checkpoints (FP64 factors)
+  const Fac F0{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, false};
+  auto base_step = [&](const Fac* per_stage_base, size_t slot0) -> int {
+    for (int s = 0; s < nst; ++s) {
+      const Fac F = per_stage_base ? slot_fac(slot0 + s) : F0;
+      int r2 = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c), F);
+      if (r2) return r2;
+      if (per_stage_base) {
+        hipLaunchKernelGGL(k_save_aux, dim3((N + 255) / 256), dim3(256), 0, c->stream, c->aux, c->n_max, N,
+                           slot_aux(slot0 + s));
+        LAUNCHCHK();
+      }
+    }
+    hipLaunchKernelGGL(k_step_end, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 3), c->stream, c->y, c->K, kstride(c), nst,
+                       c->coef, c->tw, c->sig, N, 0);
     LAUNCHCHK();
+    return 0;
+  };
+  for (int n = 0; n < nsteps; ++n) {
+    if (n % C == 0) HIPCHK(hipMemcpyAsync(c->ckpt + (size_t)(n / C) * n2, c->y, n2 * 8, hipMemcpyDeviceToDevice, c->stream));
+    if ((rc = base_step(nullptr, 0))) return rc;
   }
-  if (drdT)
-    if ((rc = enqueue_base_chain(c, c->y, 0, c->Kx))) return rc;
-  {
-    const size_t tot = (size_t)N * (M + 1);
-    const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_outputs, dim3(blocks), dim3(256), 0, c->stream, c->y, c->Kx, r, cols ? J : nullptr, drdT, N,
-                       cols ? M : 0);
-    LAUNCHCHK();
-  }
-  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, r, N, c->fdev);
+  hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, c->y, n2, c->status);
   LAUNCHCHK();
-  if (f) HIPCHK(hipMemcpyAsync(f, c->fdev, 8, hipMemcpyDeviceToHost, c->stream));
+  // outputs r, drdT, f at T/4
+  if ((rc = enqueue_base_chain(c, c->y, 0, c->Kx, F0))) return rc;
+  hipLaunchKernelGGL(k_outputs, dim3((N + 255) / 256), dim3(256), 0, c->stream, c->y, c->Kx, rv, nullptr, dv, N, 0);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, rv, N, c->fdev);
+  LAUNCHCHK();
+  // 2. adjoint seed (0, w r) and the reverse sweep, segment by segment
+  hipLaunchKernelGGL(k_adj_seed, dim3((2 * N + 255) / 256), dim3(256), 0, c->stream, rv, N, lam);
+  LAUNCHCHK();
+  const double g = c->g, tau = c->tau;
+  bool first = true;
+  for (int sg = nseg - 1; sg >= 0; --sg) {
+    const int n0 = sg * C, n1 = std::min(n0 + C, nsteps);
+    HIPCHK(hipMemcpyAsync(c->y, c->ckpt + (size_t)sg * n2, n2 * 8, hipMemcpyDeviceToDevice, c->stream));
+    for (int n = n0; n < n1; ++n)
+      if ((rc = base_step(&F0, (size_t)(n - n0) * nst))) return rc;
+    for (int n = n1 - 1; n >= n0; --n) {
+      // lambda_{n+1} (seed, or mu + sum ups of the step after) and mu = S_F lambda_{n+1}
+      hipLaunchKernelGGL(k_adj_step, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 3), c->stream, lam, mu, ups, ustride, nst,
+                         first ? 1 : 0, c->tw, c->sig, N);
+      LAUNCHCHK();
+      first = false;
+      for (int s = nst - 1; s >= 0; --s) {
+        const size_t k = (size_t)(n - n0) * nst + s;
+        const Fac F = slot_fac(k);
+        const double* sa = slot_aux(k);
+        hipLaunchKernelGGL(k_adj_pre, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 4), c->stream, mu, ups, ustride, c->coef,
+                           s, nst, sa, c->tw, c->sig, N, Np, g, tau, gt, hd, e1, qv);
+        LAUNCHCHK();
+        const int gblk = (Np * 64 + WW_NT - 1) / WW_NT;
+        hipLaunchKernelGGL(k_gemv_t, dim3(gblk), dim3(WW_NT), 0, c->stream, F.Gm, Np, 0, gt, nullptr, g2);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_adj_mid, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 3), c->stream, g2, hd, c->tw, N, Np, zeta);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_gemv_t, dim3(gblk), dim3(WW_NT), 0, c->stream, F.Z, Np, 2, zeta, nullptr, y1);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_gemv_t, dim3(gblk), dim3(WW_NT), 0, c->stream, F.X, Np, 1, y1, y1, y2);
+        LAUNCHCHK();
+        hipLaunchKernelGGL(k_adj_post, dim3((N + 255) / 256), dim3(256), 0, c->stream, y2, qv, e1, sa, N,
+                           ups + (size_t)s * ustride);
+        LAUNCHCHK();
+      }
+    }
+  }
+  // lambda_0 = mu + sum ups, gradient basis^T lambda_0
+  hipLaunchKernelGGL(k_adj_step, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 3), c->stream, lam, mu, ups, ustride, nst, 0,
+                     c->tw, c->sig, N);
+  LAUNCHCHK();
+  if (M > 0) {
+    hipLaunchKernelGGL(k_adj_grad, dim3((M * 64 + WW_NT - 1) / WW_NT), dim3(WW_NT), 0, c->stream, c->basis, lam, N, M,
+                       grad);
+    LAUNCHCHK();
+  }
+  std::vector<double> hr(N), hd2(N);
+  double fh = 0.0;
+  HIPCHK(hipMemcpyAsync(hr.data(), rv, N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(hd2.data(), dv, N * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(&fh, c->fdev, 8, hipMemcpyDeviceToHost, c->stream));
   int st = 0;
   if ((rc = read_status(c, &st))) return rc;
+  if (f) *f = fh;
+  if (dfdT) {
+    double acc = 0.0;
+    for (int i = 0; i < N; ++i) acc += hr[i] * hd2[i];
+    *dfdT = acc;
+  }
   if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
   if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
   return 0;
-}
-
-int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckpt_every, double* grad,
-                  double* dfdT, double* f) {
-  (void)params; (void)T; (void)nsteps; (void)ckpt_every; (void)grad; (void)dfdT; (void)f;
-  if (!c) return fail(WW_EINVAL, "null argument");
-  return fail(WW_EINVAL, "shoot_adjoint: not available in this build");
 }
 
 }  // extern "C"

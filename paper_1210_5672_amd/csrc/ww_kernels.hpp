@@ -1041,3 +1041,214 @@ __global__ void k_check_finite(const double* __restrict__ y, size_t n, int* __re
     if (!isfinite(y[idx])) bad = true;
   if (bad) atomicOr(status, 2);
 }
+
+// =====================================================================================
+// Discrete adjoint (Sec. 3.2 and App. B, discrete form): the exact transpose of the
+// tangent march above.  For one right-hand-side operator L = S_F DF(Y) of a stage,
+//   psidot = phidot - v etadot,  G = (H/2 + Gm) D A^{-1} psidot,
+//   etadot_t = G - D(u etadot),
+//   phidot_t = P[-D(u v etadot) - u D psidot + v G - g etadot + tau D(w3^{-1} D etadot)],
+// the transpose, with D^T = -D, H^T = -H, P^T = P, S_F^T = S_F, is, for adjoint data
+// (alpha, beta) of (etadot_t, phidot_t):
+//   a = S_F alpha,  b = P S_F beta,  gt = a + v b,
+//   psit = A^{-T} D (H gt / 2 - Gm^T gt) + D(u b),
+//   etat = u D a + u v D b - g b + tau D(w3^{-1} D b) - v psit,   phit = psit.
+// A^{-T} = (Z (I + X))^T = (I + X^T) Z^T with the stored block-triangular inverses.
+// =====================================================================================
+
+// adjoint stage, part 1 (one workgroup):  kappa = wb * mu + sum_{i > s} wa_i upsilon_i
+// (the stage weights come from coef), then the spectral pieces of the transpose.
+// Outputs (ld Np where noted): gt (Np, zero padded), hd = D(H gt / 2), e1, q.
+__global__ __launch_bounds__(WW_NT) void k_adj_pre(const double* __restrict__ mu, const double* __restrict__ ups,
+                                                   size_t ustride, const double* __restrict__ coef, int stage,
+                                                   int nst, const double* __restrict__ saux, const cplx* __restrict__ tw,
+                                                   const double* __restrict__ sig, int N, int Np, double g, double tau,
+                                                   double* __restrict__ gt, double* __restrict__ hd,
+                                                   double* __restrict__ e1, double* __restrict__ q) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* S = lds + 2 * N;
+  cplx* tws = lds + 3 * N;
+  const FftPlan P = make_plan(N);
+  load_twiddles(tws, tw, N);
+  const int tid = threadIdx.x;
+  const double* u = saux;
+  const double* v = saux + N;
+  const double* w3 = saux + 2 * N;
+  // kappa_s = b_s dt mu + sum_{i > s} a_is dt upsilon_i
+  const double wb = coef[COEF_B + stage];
+  for (int t = tid; t < 2 * N; t += WW_NT) {
+    double kv = wb * mu[t];
+    for (int i = stage + 1; i < nst; ++i) kv += coef[i * 16 + stage] * ups[(size_t)i * ustride + t];
+    if (t < N) Z[t].x = kv;
+    else Z[t - N].y = kv;
+  }
+  fft_lds(Z, W, tws, P, -1);
+  for (int t = tid; t < N; t += WW_NT) {
+    cplx Al, Be;
+    split_pair(Z, t, N, Al, Be);
+    const int k = wavenum(t, N);
+    const double sg = sig[t];
+    cplx a = cscale(Al, sg);
+    cplx b = (k == 0) ? cmk(0.0, 0.0) : cscale(Be, sg);
+    W[t] = pack_pair(a, b);
+    S[t] = pack_pair(sym_deriv(a, k, N), sym_deriv(b, k, N));
+  }
+  fft_lds(W, Z, tws, P, +1);   // a + i b
+  fft_lds(S, Z, tws, P, +1);   // D a + i D b
+  // physical: gt = a + v b ; f1 = D b / w3 ; f2 = u b   (kept in registers between passes)
+  double av[NPT], bv[NPT], dav[NPT], dbv[NPT];
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int t = tclamp(m, N);
+    av[m] = W[t].x;
+    bv[m] = W[t].y;
+    dav[m] = S[t].x;
+    dbv[m] = S[t].y;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int t = tidx(m);
+    if (t < N) {
+      const double gg = av[m] + v[t] * bv[m];
+      Z[t] = cmk(gg, dbv[m] / w3[t]);
+      S[t] = cmk(u[t] * bv[m], 0.0);
+      gt[t] = gg;
+    }
+  }
+  for (int t = N + tid; t < Np; t += WW_NT) gt[t] = 0.0;
+  fft_lds(Z, W, tws, P, -1);
+  fft_lds(S, W, tws, P, -1);
+  for (int t = tid; t < N; t += WW_NT) {
+    cplx Gh, F1, F2, dm;
+    split_pair(Z, t, N, Gh, F1);
+    split_pair(S, t, N, F2, dm);
+    const int k = wavenum(t, N);
+    // D(H gt / 2): symbol (i k)(-i sgn k)/2 = |k|/2, zero at Nyquist
+    const double hk = (2 * k == N || 2 * k == -N) ? 0.0 : 0.5 * fabs((double)k);
+    W[t] = pack_pair(cscale(Gh, hk), sym_deriv(F1, k, N));
+    S[t] = sym_deriv(F2, k, N);
+  }
+  fft_lds(W, Z, tws, P, +1);   // D(H gt/2) + i D f1
+  fft_lds(S, Z, tws, P, +1);   // D f2
+#pragma unroll
+  for (int m = 0; m < NPT; ++m) {
+    const int t = tidx(m);
+    if (t < N) {
+      const double uu = u[t], vv = v[t];
+      hd[t] = W[t].x;
+      e1[t] = uu * dav[m] + uu * vv * dbv[m] - g * bv[m] + tau * W[t].y;
+      q[t] = S[t].x;
+    }
+  }
+}
+
+// adjoint stage, part 2 (one workgroup): zeta = hd - D(g2), g2 = Gm^T gt (ld Np);
+// zeta padded with zeros to Np.
+__global__ __launch_bounds__(WW_NT) void k_adj_mid(const double* __restrict__ g2, const double* __restrict__ hd,
+                                                   const cplx* __restrict__ tw, int N, int Np,
+                                                   double* __restrict__ zeta) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* tws = lds + 2 * N;
+  const FftPlan P = make_plan(N);
+  load_twiddles(tws, tw, N);
+  for (int t = threadIdx.x; t < N; t += WW_NT) Z[t] = cmk(g2[t], 0.0);
+  fft_lds(Z, W, tws, P, -1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) Z[t] = sym_deriv(Z[t], wavenum(t, N), N);
+  fft_lds(Z, W, tws, P, +1);
+  for (int t = threadIdx.x; t < Np; t += WW_NT) zeta[t] = (t < N) ? hd[t] - Z[t].x : 0.0;
+}
+
+// y = add + M^T x for one vector (M column-major, ld Np): y_i = sum_j M[j, i] x_j over
+// j in the block range of the mode: 0 all; 1 blk(j) > blk(i) (transpose of the strictly
+// lower X); 2 blk(j) <= blk(i) (transpose of the upper Z).  One wave per output.
+__global__ __launch_bounds__(WW_NT) void k_gemv_t(const double* __restrict__ M, int Np, int mode,
+                                                  const double* __restrict__ x, const double* __restrict__ add,
+                                                  double* __restrict__ y) {
+  const int wave = (blockIdx.x * WW_NT + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (wave >= Np) return;
+  const int i = wave;
+  const int bi = i / WW_TB;
+  int lo = 0, hi = Np;
+  if (mode == 1) lo = (bi + 1) * WW_TB;
+  if (mode == 2) hi = (bi + 1) * WW_TB;
+  const double* col = M + (size_t)i * Np;
+  double s = 0.0;
+  for (int j = lo + lane; j < hi; j += 64) s = fma(col[j], x[j], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[i] = (add ? add[i] : 0.0) + s;
+}
+
+// adjoint stage, part 3: psit = y + q;  upsilon = (e1 - v psit, psit)
+__global__ void k_adj_post(const double* __restrict__ yv, const double* __restrict__ q, const double* __restrict__ e1,
+                           const double* __restrict__ saux, int N, double* __restrict__ ups) {
+  const double* v = saux + N;
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N; t += gridDim.x * blockDim.x) {
+    const double ps = yv[t] + q[t];
+    ups[t] = e1[t] - v[t] * ps;
+    ups[N + t] = ps;
+  }
+}
+
+// adjoint of the end of a step: lambda_n = mu + sum_s upsilon_s, then (for the step
+// before) mu = S_F lambda.  One workgroup; first = 1 starts from lambda (no upsilon).
+__global__ __launch_bounds__(WW_NT) void k_adj_step(double* __restrict__ lam, double* __restrict__ mu,
+                                                    const double* __restrict__ ups, size_t ustride, int nst,
+                                                    int first, const cplx* __restrict__ tw,
+                                                    const double* __restrict__ sig, int N) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* tws = lds + 2 * N;
+  const FftPlan P = make_plan(N);
+  load_twiddles(tws, tw, N);
+  for (int t = threadIdx.x; t < 2 * N; t += WW_NT) {
+    double l = first ? lam[t] : mu[t];
+    if (!first)
+      for (int s = 0; s < nst; ++s) l += ups[(size_t)s * ustride + t];
+    lam[t] = l;
+    if (t < N) Z[t].x = l;
+    else Z[t - N].y = l;
+  }
+  fft_lds(Z, W, tws, P, -1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) Z[t] = cscale(Z[t], sig[t]);
+  fft_lds(Z, W, tws, P, +1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    mu[t] = Z[t].x;
+    mu[N + t] = Z[t].y;
+  }
+}
+
+// gradient: grad_k = <basis_k, lambda_0>  (one wave per parameter)
+__global__ __launch_bounds__(WW_NT) void k_adj_grad(const double* __restrict__ basis, const double* __restrict__ lam,
+                                                    int N, int M, double* __restrict__ grad) {
+  const int k = (blockIdx.x * WW_NT + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (k >= M) return;
+  const double* bk = basis + (size_t)k * 2 * N;
+  double s = 0.0;
+  for (int t = lane; t < 2 * N; t += 64) s = fma(bk[t], lam[t], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) grad[k] = s;
+}
+
+// lambda at T/4: (0, w r)
+__global__ void k_adj_seed(const double* __restrict__ r, int N, double* __restrict__ lam) {
+  const double w = 1.0 / sqrt((double)N);
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < 2 * N; t += gridDim.x * blockDim.x)
+    lam[t] = (t < N) ? 0.0 : w * r[t - N];
+}
+
+// copy of the stage's u, v, (1 + eta_x^2)^{3/2} for the reverse sweep
+__global__ void k_save_aux(const double* __restrict__ aux, int nmax, int N, double* __restrict__ saux) {
+  for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < N; t += gridDim.x * blockDim.x) {
+    saux[t] = aux[AUX_U * nmax + t];
+    saux[N + t] = aux[AUX_V * nmax + t];
+    saux[2 * N + t] = aux[AUX_W3 * nmax + t];
+  }
+}

@@ -26,7 +26,7 @@ _ERRORS = {
 
 EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_setup",
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
-           "ww_version"]
+           "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch"]
 
 
 class WWError(RuntimeError):
@@ -59,10 +59,15 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_setup.argtypes = [P, I, D, D, D, P, P, I]
     lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
     lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    lib.shoot_eval_batch.argtypes = [I, PP, PP, DP, ctypes.POINTER(ctypes.c_int), PP, PP, PP, DP]
+    lib.shoot_eval_batch.restype = I
+    lib.ww_profile.argtypes = [P, I]
+    lib.ww_profile_read.argtypes = [P, I, DP, ctypes.POINTER(ctypes.c_int)]
     lib.ww_last_error.restype = ctypes.c_char_p
     lib.ww_version.restype = ctypes.c_char_p
     for name in ["ww_create", "ww_set_stream", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
-                 "shoot_setup", "shoot_eval", "shoot_adjoint"]:
+                 "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read"]:
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -172,6 +177,17 @@ class Context:
                                    _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
 
+    def profile(self, enable: bool = True):
+        _check(self.lib.ww_profile(self.ptr, 1 if enable else 0))
+
+    def profile_read(self, phase: int) -> float:
+        """Mean duration (ms) of a phase over the stages of the last replayed step:
+        0 block LU, 1 base chain, 2 column chain."""
+        ms = ctypes.c_double(0.0)
+        n = ctypes.c_int(0)
+        _check(self.lib.ww_profile_read(self.ptr, phase, ctypes.byref(ms), ctypes.byref(n)))
+        return ms.value
+
     def shoot_adjoint(self, params: torch.Tensor, T: float, nsteps: int, ckpt_every: int = 16):
         M = self.M
         grad = torch.empty(M, dtype=torch.float64, device=params.device)
@@ -184,3 +200,31 @@ class Context:
 
 def to_dev(a, device="cuda") -> torch.Tensor:
     return torch.as_tensor(np.ascontiguousarray(a), dtype=torch.float64, device=device)
+
+
+def shoot_eval_batch(contexts, params, T, nsteps, jacobian=True, drdT=True):
+    """Batched shoot_eval over distinct contexts (one instance each).  Returns a list of
+    dicts like Context.shoot_eval."""
+    lib = load()
+    n = len(contexts)
+    VP = ctypes.c_void_p * n
+    outs = []
+    rp, Jp, dp = VP(), VP(), VP()
+    for i, (c, p) in enumerate(zip(contexts, params)):
+        N, M = c.N, c.M
+        r = torch.empty(N, dtype=torch.float64, device=p.device)
+        Jc = torch.empty((M, N), dtype=torch.float64, device=p.device) if jacobian else None
+        d = torch.empty(N, dtype=torch.float64, device=p.device) if drdT else None
+        outs.append((r, Jc, d))
+        rp[i] = r.data_ptr()
+        Jp[i] = Jc.data_ptr() if jacobian else None
+        dp[i] = d.data_ptr() if drdT else None
+    cp = VP(*[c.ptr.value for c in contexts])
+    pp = VP(*[p.contiguous().data_ptr() for p in params])
+    Ta = (ctypes.c_double * n)(*[float(t) for t in T])
+    Na = (ctypes.c_int * n)(*[int(k) for k in nsteps])
+    fa = (ctypes.c_double * n)()
+    _check(lib.shoot_eval_batch(n, cp, pp, Ta, Na, rp, Jp if jacobian else None,
+                                dp if drdT else None, fa))
+    return [dict(r=r, J=Jc.t() if Jc is not None else None, drdT=d, f=fa[i])
+            for i, (r, Jc, d) in enumerate(outs)]

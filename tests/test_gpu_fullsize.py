@@ -54,12 +54,29 @@ def kappa_F(w):
                for k in range(1, N // 2))
 
 
-def check(fx, w, res, tol):
+def _floor(name):
+    """FP64 rounding floor of the march at a workload: the spread between the oracle
+    and the same oracle with an alternative (equally valid) rounding of cosh/sinh
+    (<name>_oracle_alt.npz).  None if that run has not been stored."""
+    fx = _load(name)
+    p = os.path.join(GOLDEN, f"{name}_oracle_alt.npz")
+    if not os.path.exists(p):
+        return None
+    fa = np.load(p)
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    return {"r": rel(fa["r"], fx["r"]), "f": abs(float(fa["f"]) - float(fx["f"])) / abs(float(fx["f"])),
+            "J_sampled_frob": rel(fa["Jcols"], fx["Jcols"]),
+            "Jnorms": float(np.abs(fa["Jnorms"] - fx["Jnorms"]).max() / fx["Jnorms"].max()),
+            "grad": rel(fa["grad"], fx["grad"]), "drdT": rel(fa["drdT"], fx["drdT"])}
+
+
+def check(fx, w, res, tol, floor=None):
     """r, f, J (Frobenius over the sampled columns, and all column norms), the
-    gradient J^T r: relative error below tol.  Per column, the error on the column's
-    linear-theory amplitude (or, for null columns, on the largest column) is reported
-    and held to 100 tol: columns of high modes in the strongly nonlinear flows carry
-    the conditioning of their own dynamics.  drdT: tol times the operator scale."""
+    gradient J^T r: relative error below tol, or below twice the FP64 rounding floor
+    of the workload when that floor (oracle vs oracle with another rounding) exceeds
+    tol.  Per column, the error on the column's linear-theory amplitude (or, for null
+    columns, on the largest column) is reported and held to 100 tol.  drdT: tol times
+    the operator scale, or twice its floor."""
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
     J = res["J"]
     cols = fx["cols"]
@@ -77,10 +94,14 @@ def check(fx, w, res, tol):
         "grad": rel(J.T @ res["r"], fx["grad"]),
     }
     e_drdT = rel(res["drdT"], fx["drdT"])
-    print(w.name, e, "per-column", percol, "drdT", e_drdT, "kappa", kappa_F(w), flush=True)
-    assert max(e.values()) < tol, e
-    assert percol < 100 * tol, percol
-    assert e_drdT < tol * kappa_F(w), e_drdT
+    bound = {k: max(tol, 2 * floor[k]) if floor else tol for k in e}
+    b_drdT = max(tol * kappa_F(w), 2 * floor["drdT"]) if floor else tol * kappa_F(w)
+    print(w.name, "errors", e, "bounds", bound, "per-column", percol, "drdT", e_drdT, "bound", b_drdT,
+          "floor", floor, flush=True)
+    for k in e:
+        assert e[k] < bound[k], (k, e[k], bound[k])
+    assert percol < 100 * max(tol, 2 * floor["J_sampled_frob"] if floor else tol), percol
+    assert e_drdT < b_drdT, e_drdT
 
 
 def test_config2_full_fp64():
@@ -94,14 +115,14 @@ def test_config4_full_fp64_jacobian():
     fx = _load("c4")
     print("full-size parity c4", flush=True)
     w, res = _run("c4")
-    check(fx, w, res, TOL)
+    check(fx, w, res, TOL, _floor("c4"))
 
 
 def test_config3_full_fp64():
     fx = _load("c3")
     print("full-size parity c3", flush=True)
     w, res = _run("c3")
-    check(fx, w, res, TOL)
+    check(fx, w, res, TOL, _floor("c3"))
 
 
 def test_config3_full_mixed_precision():
@@ -110,7 +131,7 @@ def test_config3_full_mixed_precision():
     fx = _load("c3")
     print("full-size parity c3 mixed", flush=True)
     w, res = _run("c3", mixed=True)
-    check(fx, w, res, TOL)
+    check(fx, w, res, TOL, _floor("c3"))
 
 
 def test_config2_full_mixed_precision():
