@@ -60,6 +60,8 @@ def run(w, nsteps, T, mixed, steps, warmup, profile):
     for i in range(warmup):
         ctx.shoot_eval(params, T, nsteps)
         print(f"# {tag} warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
+    if profile:
+        ctx.profile(True)   # clear the sums: the phases cover the timed steps only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = None
@@ -86,6 +88,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -150,6 +154,15 @@ def main():
             out["mixed"]["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
                                         "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
                                         "phases_ms": phm}
+    if args.copy_probe:
+        # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a counter run
+        # give the scale between the counters and the bytes actually moved
+        import torch
+        src = torch.ones(32 << 20, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_probe_bytes"] = 2 * src.numel() * 8
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_sample_steps)
     print(json.dumps(out))

@@ -143,12 +143,15 @@ int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int c
                   double *grad, double *dfdT, double *f);
 
 /*
- * Measurement hooks (not part of the method): ww_profile(ctx, 1) makes the step graph
- * record HIP events around three phases of every stage -- 0: the block LU of A
- * (factorisation and block-triangular inverses), 1: the whole base chain (spectral
- * prep, assembly, LU, base DtN, base right-hand side), 2: the column chain (the M
- * variational columns).  ww_profile_read returns the mean duration in ms of `phase`
- * over the stages of the last replayed step (synchronises the stream).
+ * Measurement hooks (not part of the method): ww_profile(ctx, 1) adds timestamp nodes
+ * (a one-thread kernel reading the GPU's constant-rate wall clock) around three phases
+ * of every stage of the step graph -- 0: the block LU of A (factorisation and
+ * block-triangular inverses), 1: the whole base chain (spectral prep, assembly, LU,
+ * base DtN, base right-hand side), 2: the column chain (the M variational columns) --
+ * and clears the accumulated sums (stream-ordered).  ww_profile_read returns in
+ * *avg_ms the mean duration of `phase` over every stage of every step replayed since
+ * the last ww_profile(ctx, 1), and in *count the number of intervals (synchronises the
+ * stream).  Errors: WW_EINVAL (profiling off, nothing replayed yet), WW_EHIP.
  */
 int ww_profile(ww_ctx *ctx, int enable);
 int ww_profile_read(ww_ctx *ctx, int phase, double *avg_ms, int *count);

@@ -55,6 +55,14 @@ struct ww_ctx {
   double ta[16 * 16], tb[16];
   // device buffers
   double *A = nullptr, *Gm = nullptr, *Xi = nullptr, *Zi = nullptr, *Vi = nullptr, *Dinv = nullptr;
+  // second factor set and per-point arrays: stages alternate between the two sets so
+  // that the column chain of stage s overlaps the base chain of stage s + 1
+  double *A_1 = nullptr, *Gm_1 = nullptr, *Xi_1 = nullptr, *Zi_1 = nullptr, *Vi_1 = nullptr, *Dinv_1 = nullptr;
+  float *A32_1 = nullptr, *X32_1 = nullptr, *Z32_1 = nullptr, *V32_1 = nullptr, *Dinv32_1 = nullptr;
+  double* aux_1 = nullptr;
+  double* part_c = nullptr;    // GEMM partials of the column chain (base chain: part)
+  hipStream_t side = nullptr;  // column-chain stream
+  hipEvent_t evB[16] = {}, evC[16] = {};
   float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
   double *Rr = nullptr, *rr0 = nullptr;   // residuals of the refinement sweeps
   int nref = 2;                            // refinement sweeps per solve (mixed mode)
@@ -81,7 +89,7 @@ struct ww_ctx {
   // (0: block LU, 1: whole base chain, 2: column chain); the values of the last
   // replayed step are read back by ww_profile_read
   bool prof = false;
-  hipEvent_t pev[3][16][2] = {};
+  unsigned long long* stamps = nullptr;   // [phase][stage] x {start, sum, count}
   // one RK step captured as a graph, replayed nsteps times
   bool use_graph = true;
   hipStream_t cap_stream = nullptr;
@@ -169,12 +177,23 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->Zi, np * np * 8);
   AL(c->Vi, np * np * 8);
   AL(c->Dinv, (size_t)nbm * 4096 * 8);
+  AL(c->A_1, np * np * 8);
+  AL(c->Gm_1, np * np * 8);
+  AL(c->Xi_1, np * np * 8);
+  AL(c->Zi_1, np * np * 8);
+  AL(c->Vi_1, np * np * 8);
+  AL(c->Dinv_1, (size_t)nbm * 4096 * 8);
   if (flags & WW_MIXED) {
     AL(c->A32, np * np * 4);
     AL(c->X32, np * np * 4);
     AL(c->Z32, np * np * 4);
     AL(c->V32, np * np * 4);
     AL(c->Dinv32, (size_t)nbm * 4096 * 4);
+    AL(c->A32_1, np * np * 4);
+    AL(c->X32_1, np * np * 4);
+    AL(c->Z32_1, np * np * 4);
+    AL(c->V32_1, np * np * 4);
+    AL(c->Dinv32_1, (size_t)nbm * 4096 * 4);
     AL(c->Rr, np * R * 8);
     AL(c->rr0, np * 8);
   }
@@ -184,6 +203,7 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->sig, nm * 8);
   AL(c->tw, nm * sizeof(cplx));
   AL(c->aux, (size_t)AUX_COUNT * nm * 8);
+  AL(c->aux_1, (size_t)AUX_COUNT * nm * 8);
   AL(c->rhs0, np * 8);
   AL(c->y0t, np * 8);
   AL(c->mu0, np * 8);
@@ -197,6 +217,7 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->HG, np * R * 8);
   AL(c->Gpsi, np * R * 8);
   AL(c->part, (size_t)c->nsplit_max * np * R * 8);
+  AL(c->part_c, (size_t)c->nsplit_max * np * R * 8);
   AL(c->y, 2 * nm * R * 8);
   AL(c->Ys, 2 * nm * R * 8);
   AL(c->K, 16 * 2 * nm * R * 8);
@@ -210,6 +231,11 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
 #undef AL
   HIPCHK(hipMemset(c->status, 0, 64));
   HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  for (int i = 0; i < 16; ++i) {
+    HIPCHK(hipEventCreateWithFlags(&c->evB[i], hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&c->evC[i], hipEventDisableTiming));
+  }
   {
     const char* ng = std::getenv("WW_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
@@ -241,14 +267,16 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
 void ww_destroy(ww_ctx* c) {
   if (!c) return;
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
-  for (int a = 0; a < 3; ++a)
-    for (int b = 0; b < 16; ++b)
-      for (int e = 0; e < 2; ++e)
-        if (c->pev[a][b][e]) (void)hipEventDestroy(c->pev[a][b][e]);
+  if (c->stamps) (void)hipFree(c->stamps);
   if (c->ckpt) (void)hipFree(c->ckpt);
   if (c->seg) (void)hipFree(c->seg);
   if (c->adj) (void)hipFree(c->adj);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  for (int i = 0; i < 16; ++i) {
+    if (c->evB[i]) (void)hipEventDestroy(c->evB[i]);
+    if (c->evC[i]) (void)hipEventDestroy(c->evC[i]);
+  }
   for (void* p : c->allocs) (void)hipFree(p);
   delete c;
 }
@@ -303,12 +331,12 @@ template <typename T>
 static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
   const int nb = c->Np / WW_TB;
   const size_t es = sizeof(T);
-  hipLaunchKernelGGL(k_blu_init<T>, dim3(1), dim3(WW_NT), (TILE_DBL + 256) * es, c->stream, b);
+  hipLaunchKernelGGL(k_blu_init<T>, dim3(1), dim3(WW_NT), (TILE_DBL + GJ_SCR) * es, c->stream, b);
   LAUNCHCHK();
   for (int k = 0; k + 1 < nb; ++k) {
     const int nt = nb - k - 1;
     const int nblk = nt * nt + 2 * nt * (k + 1);
-    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk), dim3(WW_NT), (4 * TILE_DBL + 256) * es, c->stream, b, k);
+    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk), dim3(WW_NT), 4 * TILE_DBL * es, c->stream, b, k);
     LAUNCHCHK();
   }
   if (nb > 1) {
@@ -322,7 +350,8 @@ static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
 static int g_prof_stage = -1;
 static int prof_mark(ww_ctx* c, int phase, int which) {
   if (!c->prof || g_prof_stage < 0) return 0;
-  HIPCHK(hipEventRecord(c->pev[phase][g_prof_stage][which], c->stream));
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, c->stream, c->stamps, phase * 16 + g_prof_stage, which);
+  LAUNCHCHK();
   return 0;
 }
 
@@ -334,19 +363,35 @@ static bool mixed(const ww_ctx* c) { return (c->flags & WW_MIXED) != 0; }
 struct Fac {
   double *A, *Gm, *X, *Z, *V, *Dinv;
   bool use32;   // mixed precision: factor the FP32 copy and refine the solves
+  float *A32, *X32, *Z32, *V32, *Dinv32;
+  double* aux;    // per-point base arrays of the stage
+  double* part;   // GEMM split-K partials of the chain that uses this set
 };
-static Fac fac_default(ww_ctx* c) { return Fac{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, mixed(c)}; }
+// factor set of parity `p`; `cols` selects the column chain's GEMM partials
+static Fac fac_set(ww_ctx* c, int p, bool cols) {
+  Fac F;
+  if (p == 0) {
+    F = Fac{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, mixed(c), c->A32, c->X32, c->Z32, c->V32, c->Dinv32, c->aux,
+            nullptr};
+  } else {
+    F = Fac{c->A_1, c->Gm_1, c->Xi_1, c->Zi_1, c->Vi_1, c->Dinv_1, mixed(c), c->A32_1, c->X32_1, c->Z32_1, c->V32_1,
+            c->Dinv32_1, c->aux_1, nullptr};
+  }
+  F.part = cols ? c->part_c : c->part;
+  return F;
+}
+static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 
 // assembly of A, Gm and the block LU of A (FP64, or of the FP32 copy in mixed mode)
 // with the block-triangular inverses
 static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   const int nb = c->Np / WW_TB;
-  hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, c->aux, c->n_max, c->cosT, c->sinT,
-                     c->c0T, F.A, F.Gm, F.use32 ? c->A32 : nullptr, c->N, c->Np, c->finite);
+  hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT,
+                     c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, c->N, c->Np, c->finite);
   LAUNCHCHK();
   int rc;
   if ((rc = prof_mark(c, 0, 0))) return rc;
-  if (F.use32) rc = enqueue_blu<float>(c, blu_bufs<float>(c, c->A32, c->X32, c->Z32, c->V32, c->Dinv32));
+  if (F.use32) rc = enqueue_blu<float>(c, blu_bufs<float>(c, F.A32, F.X32, F.Z32, F.V32, F.Dinv32));
   else rc = enqueue_blu<double>(c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv));
   if (rc) return rc;
   return prof_mark(c, 0, 1);
@@ -355,8 +400,8 @@ static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
 // out = add + sgn * M B for R columns (ld Np), M taken as full (mode 0), strictly lower
 // (mode 1) or upper (mode 2) in 64-blocks.  Split-K partials, then a reduction.
 template <typename T>
-static int enqueue_gemm(ww_ctx* c, const T* M, int mode, const double* B, const double* add, double sgn,
-                        double* out, int R) {
+static int enqueue_gemm(ww_ctx* c, double* part, const T* M, int mode, const double* B, const double* add,
+                        double sgn, double* out, int R) {
   const int nkt = c->Np / WW_TB;
   const int tiles = nkt * ((R + 63) / 64);
   int nsplit = (512 + tiles - 1) / tiles;
@@ -365,11 +410,11 @@ static int enqueue_gemm(ww_ctx* c, const T* M, int mode, const double* B, const 
   const int kchunk = (nkt + nsplit - 1) / nsplit;
   nsplit = (nkt + kchunk - 1) / kchunk;
   hipLaunchKernelGGL(k_gemm_part<T>, dim3(nkt, (R + 63) / 64, nsplit), dim3(WW_NT), 2 * TILE_DBL * sizeof(T),
-                     c->stream, M, c->Np, mode, B, R, c->part, kchunk);
+                     c->stream, M, c->Np, mode, B, R, part, kchunk);
   LAUNCHCHK();
   const size_t n = (size_t)c->Np * R;
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_gemm_reduce, dim3(blocks), dim3(256), 0, c->stream, c->part, nsplit, add, sgn, out, c->Np, R);
+  hipLaunchKernelGGL(k_gemm_reduce, dim3(blocks), dim3(256), 0, c->stream, part, nsplit, add, sgn, out, c->Np, R);
   LAUNCHCHK();
   return 0;
 }
@@ -381,15 +426,15 @@ static int enqueue_gemm(ww_ctx* c, const T* M, int mode, const double* B, const 
 static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* X, double* Rs, int R) {
   int rc;
   if (!F.use32) {
-    if ((rc = enqueue_gemm<double>(c, F.X, 1, B, B, 1.0, Y, R))) return rc;
-    return enqueue_gemm<double>(c, F.Z, 2, Y, nullptr, 1.0, X, R);
+    if ((rc = enqueue_gemm<double>(c, F.part, F.X, 1, B, B, 1.0, Y, R))) return rc;
+    return enqueue_gemm<double>(c, F.part, F.Z, 2, Y, nullptr, 1.0, X, R);
   }
-  if ((rc = enqueue_gemm<float>(c, c->X32, 1, B, B, 1.0, Y, R))) return rc;
-  if ((rc = enqueue_gemm<float>(c, c->Z32, 2, Y, nullptr, 1.0, X, R))) return rc;
+  if ((rc = enqueue_gemm<float>(c, F.part, F.X32, 1, B, B, 1.0, Y, R))) return rc;
+  if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, 2, Y, nullptr, 1.0, X, R))) return rc;
   for (int it = 0; it < c->nref; ++it) {
-    if ((rc = enqueue_gemm<double>(c, F.A, 0, X, B, -1.0, Rs, R))) return rc;
-    if ((rc = enqueue_gemm<float>(c, c->X32, 1, Rs, Rs, 1.0, Y, R))) return rc;
-    if ((rc = enqueue_gemm<float>(c, c->Z32, 2, Y, X, 1.0, X, R))) return rc;
+    if ((rc = enqueue_gemm<double>(c, F.part, F.A, 0, X, B, -1.0, Rs, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, F.part, F.X32, 1, Rs, Rs, 1.0, Y, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, 2, Y, X, 1.0, X, R))) return rc;
   }
   return 0;
 }
@@ -402,7 +447,7 @@ static int enqueue_dtn_cols(ww_ctx* c, const Fac& F, double* B, double* Yt, doub
   hipLaunchKernelGGL(k_gamma, dim3((R + 1) / 2), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Mu, c->Np, R, Gam,
                      HGm, c->tw, c->N);
   LAUNCHCHK();
-  return enqueue_gemm<double>(c, F.Gm, 0, Gam, HGm, 1.0, out, R);
+  return enqueue_gemm<double>(c, F.part, F.Gm, 0, Gam, HGm, 1.0, out, R);
 }
 
 static size_t kstride(const ww_ctx* c) { return (size_t)2 * c->N * (c->M + 1); }
@@ -414,41 +459,55 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
   int rc;
   if ((rc = prof_mark(c, 1, 0))) return rc;
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysrc, c->K, c->Ys, c->coef,
-                     s, kstride(c), c->aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf);
+                     s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf);
   LAUNCHCHK();
   if ((rc = enqueue_assemble_lu(c, F))) return rc;
   if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
-  hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, c->aux,
+  hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
                      c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
   return prof_mark(c, 1, 1);
 }
 
-static int enqueue_col_chain(ww_ctx* c, int s) {
+static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
   int rc;
   if ((rc = prof_mark(c, 2, 0))) return rc;
   const int M = c->M;
   const size_t tot = (size_t)c->Np * M;
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_col_pre, dim3(blocks), dim3(256), 0, c->stream, c->y, c->K, c->Ys, c->coef, s, kstride(c),
-                     c->aux, c->n_max, c->Psi, c->Np, c->N, M);
+                     F.aux, c->n_max, c->Psi, c->Np, c->N, M);
   LAUNCHCHK();
-  if ((rc = enqueue_dtn_cols(c, fac_default(c), c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
+  if ((rc = enqueue_dtn_cols(c, F, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
   hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
-                     c->aux, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
+                     F.aux, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
   return prof_mark(c, 2, 1);
 }
 
 static int enqueue_step(ww_ctx* c, bool cols) {
   int rc;
+  const bool two = cols && c->M > 0;
+  hipStream_t s0 = c->stream;
   for (int s = 0; s < c->nst; ++s) {
+    const int par = s & 1;
     g_prof_stage = s;
-    rc = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c), fac_default(c));
-    if (!rc && cols && c->M > 0) rc = enqueue_col_chain(c, s);
+    // the factor set of this parity was last read by the column chain of stage s - 2
+    if (two && s >= 2) HIPCHK(hipStreamWaitEvent(s0, c->evC[s - 2], 0));
+    rc = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c), fac_set(c, par, false));
+    if (!rc && two) {
+      // column chain of stage s on the side stream, overlapping the next base chain
+      HIPCHK(hipEventRecord(c->evB[s], s0));
+      HIPCHK(hipStreamWaitEvent(c->side, c->evB[s], 0));
+      c->stream = c->side;
+      rc = enqueue_col_chain(c, s, fac_set(c, par, true));
+      c->stream = s0;
+      if (!rc) HIPCHK(hipEventRecord(c->evC[s], c->side));
+    }
     g_prof_stage = -1;
     if (rc) return rc;
   }
+  if (two) HIPCHK(hipStreamWaitEvent(s0, c->evC[c->nst - 1], 0));
   const int ncol = cols ? c->M + 1 : 1;
   hipLaunchKernelGGL(k_step_end, dim3(ncol), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y, c->K, kstride(c),
                      c->nst, c->coef, c->tw, c->sig, c->N, 0);
@@ -548,36 +607,33 @@ int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, dou
 
 int ww_profile(ww_ctx* c, int enable) {
   if (!c) return fail(WW_EINVAL, "null argument");
-  if (enable && !c->pev[0][0][0])
-    for (int a = 0; a < 3; ++a)
-      for (int b = 0; b < 16; ++b)
-        for (int e = 0; e < 2; ++e) HIPCHK(hipEventCreate(&c->pev[a][b][e]));
+  if (enable && !c->stamps) HIPCHK(hipMalloc(&c->stamps, 3 * 16 * 3 * sizeof(unsigned long long)));
+  if (enable) HIPCHK(hipMemsetAsync(c->stamps, 0, 3 * 16 * 3 * sizeof(unsigned long long), c->stream));
   if ((bool)enable != c->prof) {
     c->prof = enable != 0;
-    c->gnst = -1;   // re-capture the step graph with or without the event nodes
+    c->gnst = -1;   // re-capture the step graph with or without the stamp nodes
   }
   return 0;
 }
 
 int ww_profile_read(ww_ctx* c, int phase, double* avg_ms, int* count) {
   if (!c || !avg_ms || phase < 0 || phase > 2) return fail(WW_EINVAL, "bad argument");
-  if (!c->prof) return fail(WW_EINVAL, "profiling is off");
+  if (!c->prof || !c->stamps) return fail(WW_EINVAL, "profiling is off");
+  unsigned long long h[16 * 3];
+  HIPCHK(hipMemcpyAsync(h, c->stamps + (size_t)phase * 16 * 3, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
-  double sum = 0.0;
-  int n = 0;
-  for (int s = 0; s < c->nst; ++s) {
-    float ms = 0.0f;
-    const hipError_t e = hipEventElapsedTime(&ms, c->pev[phase][s][0], c->pev[phase][s][1]);
-    if (e == hipSuccess) {
-      sum += ms;
-      ++n;
-    } else {
-      (void)hipGetLastError();
-    }
+  int dev = 0, khz = 0;
+  HIPCHK(hipGetDevice(&dev));
+  HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, dev));
+  if (khz <= 0) return fail(WW_EHIP, "wall clock rate unavailable");
+  unsigned long long ticks = 0, n = 0;
+  for (int s = 0; s < 16; ++s) {
+    ticks += h[3 * s + 1];
+    n += h[3 * s + 2];
   }
-  if (n == 0) return fail(WW_EHIP, "no profiled stage (run shoot_eval with profiling on first)");
-  *avg_ms = sum / n;
-  if (count) *count = n;
+  if (n == 0) return fail(WW_EINVAL, "no profiled stage (run shoot_eval with profiling on first)");
+  *avg_ms = (double)ticks / (double)n / (double)khz;
+  if (count) *count = (int)n;
   return 0;
 }
 
@@ -763,7 +819,12 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
   double* dv = rv + c->n_max;        // drdT (N)
   auto slot_fac = [&](size_t k) {
     double* b = c->seg + k * slot;
-    return Fac{c->A, b + 2 * (size_t)Np * Np, b, b + (size_t)Np * Np, c->Vi, c->Dinv, false};
+    Fac F = fac_set(c, 0, false);
+    F.Gm = b + 2 * (size_t)Np * Np;
+    F.X = b;
+    F.Z = b + (size_t)Np * Np;
+    F.use32 = false;
+    return F;
   };
   auto slot_aux = [&](size_t k) { return c->seg + k * slot + (size_t)3 * Np * Np; };
   // step coefficients
@@ -784,14 +845,15 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
     LAUNCHCHK();
   }
   // 1. forward base march with checkpoints (FP64 factors)
-  const Fac F0{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, false};
+  Fac F0 = fac_set(c, 0, false);
+  F0.use32 = false;
   auto base_step = [&](const Fac* per_stage_base, size_t slot0) -> int {
     for (int s = 0; s < nst; ++s) {
       const Fac F = per_stage_base ? slot_fac(slot0 + s) : F0;
       int r2 = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c), F);
       if (r2) return r2;
       if (per_stage_base) {
-        hipLaunchKernelGGL(k_save_aux, dim3((N + 255) / 256), dim3(256), 0, c->stream, c->aux, c->n_max, N,
+        hipLaunchKernelGGL(k_save_aux, dim3((N + 255) / 256), dim3(256), 0, c->stream, F.aux, c->n_max, N,
                            slot_aux(slot0 + s));
         LAUNCHCHK();
       }

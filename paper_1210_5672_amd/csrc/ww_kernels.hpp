@@ -349,6 +349,9 @@ template <> struct Mfma<double> {
     return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int i, int rq) { return 4 * i + rq; }
+  // element index and lane group (lane >> 4) of the result entries in row p
+  static __device__ __forceinline__ int row_elem(int p) { return p >> 2; }
+  static __device__ __forceinline__ int row_grp(int p) { return p & 3; }
 };
 template <> struct Mfma<float> {
   typedef flt4 V;
@@ -356,6 +359,8 @@ template <> struct Mfma<float> {
     return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
   }
   static __device__ __forceinline__ int row(int i, int rq) { return 4 * rq + i; }
+  static __device__ __forceinline__ int row_elem(int p) { return p & 3; }
+  static __device__ __forceinline__ int row_grp(int p) { return p >> 2; }
 };
 
 template <typename T>
@@ -482,6 +487,143 @@ __device__ inline double lds_gj_inverse(T* Ts, T* pub) {
 }
 
 // -------------------------------------------------------------------------------------
+// In-place inverse of the 64 x 64 LDS tile by Gauss-Jordan over 16 x 16 blocks, without
+// pivoting (the rule above, applied to blocks).  Wave w keeps row band w (rows 16w ..
+// 16w + 15) in registers as four 16 x 16 blocks in the MFMA result layout.  Block step P:
+// wave P inverts its diagonal block in registers (the scalar rule across the wave's
+// lanes: the pivot entry by a lane read, pivot row and column by lane shuffles, no
+// workgroup barrier), replaces its other blocks by D B_PJ (D = B_PP^-1) and publishes
+// the band; after one barrier every other wave updates B_wJ <- B_wJ - B_wP (D B_PJ) and
+// B_wP <- -B_wP D, all 16 x 16 x 16 MFMA products.  The pivots are those of the scalar
+// elimination.  `scr`: LDS scratch of GJ_SCR elements.  Returns the smallest |pivot|.
+// -------------------------------------------------------------------------------------
+#define GJ_SLD 65
+#define GJ_BAND (16 * GJ_SLD)
+#define GJ_SCR (6 * GJ_BAND + 8)
+static_assert(GJ_SCR <= 3 * TILE_DBL, "the inverse scratch must fit in three free LDS tiles");
+
+__device__ __forceinline__ double lane_read(double x, int lane) {
+  const unsigned long long u = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u & 0xffffffffull), lane);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(u >> 32), lane);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+__device__ __forceinline__ float lane_read(float x, int lane) {
+  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
+}
+
+// Gauss-Jordan inverse of one 16 x 16 block held by a whole wave in the MFMA result
+// layout (lane: column lane & 15, rows Mfma<T>::row(i, lane >> 4)).
+template <typename T>
+__device__ __forceinline__ void leaf_gj16(typename Mfma<T>::V& x, T& minpiv) {
+  const int lane = threadIdx.x & 63;
+  const int cl = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int p = 0; p < 16; ++p) {
+    const int pe = Mfma<T>::row_elem(p), pg = Mfma<T>::row_grp(p);
+    const T piv = lane_read(x[pe], pg * 16 + p);     // a_pp
+    const T rsrc = __shfl(x[pe], pg * 16 + cl);      // a_p,cl
+    T ksrc[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ksrc[i] = __shfl(x[i], rq * 16 + p);   // a_row(i),p
+    minpiv = fmin(minpiv, fabs(piv));
+    const T ip = recip(piv);
+    const T rho = (cl == p) ? T(1) + ip : rsrc * ip;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const T kap = (Mfma<T>::row(i, rq) == p) ? piv - T(1) : ksrc[i];
+      x[i] = fma(-kap, rho, x[i]);
+    }
+  }
+}
+
+// The step loop stays rolled (one copy of the leaf code); blocks of the band are only
+// addressed with compile-time indices under uniform branches on P (a select on P
+// would be turned into a dynamically indexed private array).
+template <typename T>
+__device__ __forceinline__ double blk_gj_inverse(T* Ts, T* scr) {
+  typedef typename Mfma<T>::V V;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int cl = lane & 15, rq = lane >> 4;
+  T* stg = scr + w * GJ_BAND;       // this wave's staging band
+  T* pubs = scr + 4 * GJ_BAND;      // two published bands (by step parity)
+  T* red = scr + 6 * GJ_BAND;       // smallest pivot of each wave's leaf
+  const V zero = V{T(0), T(0), T(0), T(0)};
+  V v[4];
+  __syncthreads();
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) v[J][i] = Ts[(16 * w + Mfma<T>::row(i, rq)) * TLD + 16 * J + cl];
+  T minpiv = T(1e30);
+#pragma unroll 1
+  for (int P = 0; P < 4; ++P) {
+    T* pub = pubs + (P & 1) * GJ_BAND;
+    if (w == P) {
+      // stage the band, invert the diagonal block (read back from the staging copy)
+      __syncwarp();
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) stg[Mfma<T>::row(i, rq) * GJ_SLD + 16 * J + cl] = v[J][i];
+      __syncwarp();
+      V x;
+#pragma unroll
+      for (int i = 0; i < 4; ++i) x[i] = stg[Mfma<T>::row(i, rq) * GJ_SLD + 16 * P + cl];
+      leaf_gj16<T>(x, minpiv);
+#pragma unroll
+      for (int i = 0; i < 4; ++i) stg[Mfma<T>::row(i, rq) * GJ_SLD + 16 * P + cl] = x[i];
+      __syncwarp();
+#pragma unroll
+      for (int J = 0; J < 4; ++J) {
+        if (J == P) {
+          v[J] = x;
+        } else {
+          V acc = zero;
+#pragma unroll
+          for (int kk = 0; kk < 4; ++kk)
+            acc = Mfma<T>::step(stg[cl * GJ_SLD + 16 * P + 4 * kk + rq], stg[(4 * kk + rq) * GJ_SLD + 16 * J + cl], acc);
+          v[J] = acc;
+        }
+      }
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) pub[Mfma<T>::row(i, rq) * GJ_SLD + 16 * J + cl] = v[J][i];
+    }
+    __syncthreads();
+    if (w != P) {
+      __syncwarp();
+#pragma unroll
+      for (int J = 0; J < 4; ++J)
+        if (J == P) {
+#pragma unroll
+          for (int i = 0; i < 4; ++i) stg[Mfma<T>::row(i, rq) * GJ_SLD + cl] = v[J][i];   // L = B_wP
+        }
+      __syncwarp();
+      T a[4];
+#pragma unroll
+      for (int kk = 0; kk < 4; ++kk) a[kk] = -stg[cl * GJ_SLD + 4 * kk + rq];
+#pragma unroll
+      for (int J = 0; J < 4; ++J) {
+        V acc = (J == P) ? zero : v[J];
+#pragma unroll
+        for (int kk = 0; kk < 4; ++kk) acc = Mfma<T>::step(a[kk], pub[(4 * kk + rq) * GJ_SLD + 16 * J + cl], acc);
+        v[J] = acc;
+      }
+    }
+  }
+  if (lane == 0) red[w] = minpiv;
+#pragma unroll
+  for (int J = 0; J < 4; ++J)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) Ts[(16 * w + Mfma<T>::row(i, rq)) * TLD + 16 * J + cl] = v[J][i];
+  __syncthreads();
+  const T mp = fmin(fmin(red[0], red[1]), fmin(red[2], red[3]));
+  return (double)mp;
+}
+
+// -------------------------------------------------------------------------------------
 // Block LU factorisation (Sec. 3.3: one factorisation of I/2 + K per stage), 64-blocks,
 // no pivoting (A is diagonally dominant; a pivot guard reports violations):
 //   A = Lt Ut,  Lt unit block-lower, Ut block-upper whose diagonal blocks are the
@@ -530,9 +672,8 @@ __global__ __launch_bounds__(WW_NT) void k_blu_init(BluBufs<T> b) {
   extern __shared__ double sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
   T* Ts = sm;
-  T* pub = sm + TILE_DBL;
   tile_load<T, T>(Ts, b.A, b.Np);
-  const double mp = lds_gj_inverse<T>(Ts, pub);
+  const double mp = blk_gj_inverse<T>(Ts, sm + TILE_DBL);
   if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
   store_dinv<T>(Ts, b.Dinv);
   tile_store<T, T>(Ts, b.Z, b.Np);
@@ -571,7 +712,6 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
   T* Ds = sm + TILE_DBL;       // D_k
   T* Rs = sm + 2 * TILE_DBL;   // right factor
   T* Cs = sm + 3 * TILE_DBL;   // destination tile
-  T* pub = sm + 4 * TILE_DBL;
   const int Np = b.Np, nb = Np / WW_TB;
   const int nt = nb - k - 1;
   const int n1 = nt * nt, n2 = nt * (k + 1);
@@ -621,7 +761,7 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
   __syncthreads();
   if (role == 1 && i == k + 1 && j == k + 1) {
     // Schur complement block of the next step: invert it (D_{k+1} = Z_{k+1,k+1})
-    const double mp = lds_gj_inverse<T>(Cs, pub);
+    const double mp = blk_gj_inverse<T>(Cs, sm);   // Ls, Ds, Rs are free here
     if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
     store_dinv<T>(Cs, b.Dinv + (size_t)(k + 1) * 4096);
     tile_store<T, T>(Cs, tileptr(b.Z, Np, k + 1, k + 1), Np);
@@ -1121,15 +1261,31 @@ __global__ __launch_bounds__(WW_NT) void k_adj_pre(const double* __restrict__ mu
   for (int t = N + tid; t < Np; t += WW_NT) gt[t] = 0.0;
   fft_lds(Z, W, tws, P, -1);
   fft_lds(S, W, tws, P, -1);
-  for (int t = tid; t < N; t += WW_NT) {
-    cplx Gh, F1, F2, dm;
-    split_pair(Z, t, N, Gh, F1);
-    split_pair(S, t, N, F2, dm);
-    const int k = wavenum(t, N);
-    // D(H gt / 2): symbol (i k)(-i sgn k)/2 = |k|/2, zero at Nyquist
-    const double hk = (2 * k == N || 2 * k == -N) ? 0.0 : 0.5 * fabs((double)k);
-    W[t] = pack_pair(cscale(Gh, hk), sym_deriv(F1, k, N));
-    S[t] = sym_deriv(F2, k, N);
+  {
+    // split_pair reads the mirrored bin N - t of S, which another thread (or this
+    // thread's next m) would overwrite: read everything first, write after a barrier
+    cplx wo[NPT], so[NPT];
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int t = tclamp(m, N);
+      cplx Gh, F1, F2, dm;
+      split_pair(Z, t, N, Gh, F1);
+      split_pair(S, t, N, F2, dm);
+      const int k = wavenum(t, N);
+      // D(H gt / 2): symbol (i k)(-i sgn k)/2 = |k|/2, zero at Nyquist
+      const double hk = (2 * k == N || 2 * k == -N) ? 0.0 : 0.5 * fabs((double)k);
+      wo[m] = pack_pair(cscale(Gh, hk), sym_deriv(F1, k, N));
+      so[m] = sym_deriv(F2, k, N);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int t = tidx(m);
+      if (t < N) {
+        W[t] = wo[m];
+        S[t] = so[m];
+      }
+    }
   }
   fft_lds(W, Z, tws, P, +1);   // D(H gt/2) + i D f1
   fft_lds(S, Z, tws, P, +1);   // D f2
@@ -1250,5 +1406,23 @@ __global__ void k_save_aux(const double* __restrict__ aux, int nmax, int N, doub
     saux[t] = aux[AUX_U * nmax + t];
     saux[N + t] = aux[AUX_V * nmax + t];
     saux[2 * N + t] = aux[AUX_W3 * nmax + t];
+  }
+}
+
+// -------------------------------------------------------------------------------------
+// Measurement stamp (not part of the method): one thread reads the GPU's constant-rate
+// wall clock.  which = 0 keeps the start tick of a slot; which = 1 adds the ticks since
+// that start to the slot's running sum and counts the interval.  Slots are
+// [start, sum, count]; a slot is only touched by work on one stream, in order.
+// -------------------------------------------------------------------------------------
+__global__ void k_stamp(unsigned long long* __restrict__ st, int slot, int which) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const unsigned long long t = (unsigned long long)wall_clock64();
+  unsigned long long* s = st + 3 * (size_t)slot;
+  if (which == 0) {
+    s[0] = t;
+  } else {
+    s[1] += t - s[0];
+    s[2] += 1;
   }
 }
