@@ -61,6 +61,10 @@ struct ww_ctx {
   float *A32_1 = nullptr, *X32_1 = nullptr, *Z32_1 = nullptr, *V32_1 = nullptr, *Dinv32_1 = nullptr;
   double* aux_1 = nullptr;
   double* part_c = nullptr;    // GEMM partials of the column chain (base chain: part)
+  // row-major copies (per parity) read by the one-vector products of the base chain
+  double *Xr = nullptr, *Zr = nullptr, *Gmr = nullptr, *Xr_1 = nullptr, *Zr_1 = nullptr, *Gmr_1 = nullptr;
+  float *X32r = nullptr, *Z32r = nullptr, *X32r_1 = nullptr, *Z32r_1 = nullptr;
+  double *Ar = nullptr, *Ar_1 = nullptr;   // mixed mode: FP64 A for the residuals
   hipStream_t side = nullptr;  // column-chain stream
   hipEvent_t evB[16] = {}, evC[16] = {};
   float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
@@ -183,7 +187,19 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->Zi_1, np * np * 8);
   AL(c->Vi_1, np * np * 8);
   AL(c->Dinv_1, (size_t)nbm * 4096 * 8);
+  AL(c->Xr, np * np * 8);
+  AL(c->Zr, np * np * 8);
+  AL(c->Gmr, np * np * 8);
+  AL(c->Xr_1, np * np * 8);
+  AL(c->Zr_1, np * np * 8);
+  AL(c->Gmr_1, np * np * 8);
   if (flags & WW_MIXED) {
+    AL(c->X32r, np * np * 4);
+    AL(c->Z32r, np * np * 4);
+    AL(c->X32r_1, np * np * 4);
+    AL(c->Z32r_1, np * np * 4);
+    AL(c->Ar, np * np * 8);
+    AL(c->Ar_1, np * np * 8);
     AL(c->A32, np * np * 4);
     AL(c->X32, np * np * 4);
     AL(c->Z32, np * np * 4);
@@ -314,13 +330,15 @@ static size_t fft_lds_bytes(int N, int nbuf) { return (size_t)nbuf * N * sizeof(
 static const size_t TILE_BYTES = (size_t)TILE_DBL * 8;
 
 template <typename T>
-static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D) {
+static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, T* Xr, T* Zr) {
   BluBufs<T> b;
   b.A = A;
   b.X = X;
   b.Z = Z;
   b.V = V;
   b.Dinv = D;
+  b.Xr = Xr;
+  b.Zr = Zr;
   b.status = c->status;
   b.Np = c->Np;
   b.pivguard = 1e-8;
@@ -366,6 +384,10 @@ struct Fac {
   float *A32, *X32, *Z32, *V32, *Dinv32;
   double* aux;    // per-point base arrays of the stage
   double* part;   // GEMM split-K partials of the chain that uses this set
+  // row-major copies for the one-vector products (Xr, Zr: FP64 factors; X32r, Z32r:
+  // FP32 factors; Ar: FP64 A for the mixed-mode residuals)
+  double *Xr, *Zr, *Gmr, *Ar;
+  float *X32r, *Z32r;
 };
 // factor set of parity `p`; `cols` selects the column chain's GEMM partials
 static Fac fac_set(ww_ctx* c, int p, bool cols) {
@@ -378,6 +400,12 @@ static Fac fac_set(ww_ctx* c, int p, bool cols) {
             c->Dinv32_1, c->aux_1, nullptr};
   }
   F.part = cols ? c->part_c : c->part;
+  F.Xr = p ? c->Xr_1 : c->Xr;
+  F.Zr = p ? c->Zr_1 : c->Zr;
+  F.Gmr = p ? c->Gmr_1 : c->Gmr;
+  F.Ar = p ? c->Ar_1 : c->Ar;
+  F.X32r = p ? c->X32r_1 : c->X32r;
+  F.Z32r = p ? c->Z32r_1 : c->Z32r;
   return F;
 }
 static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
@@ -387,22 +415,30 @@ static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   const int nb = c->Np / WW_TB;
   hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT,
-                     c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, c->N, c->Np, c->finite);
+                     c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, F.use32 ? F.Ar : nullptr, c->N, c->Np,
+                     c->finite);
   LAUNCHCHK();
   int rc;
   if ((rc = prof_mark(c, 0, 0))) return rc;
-  if (F.use32) rc = enqueue_blu<float>(c, blu_bufs<float>(c, F.A32, F.X32, F.Z32, F.V32, F.Dinv32));
-  else rc = enqueue_blu<double>(c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv));
+  if (F.use32) rc = enqueue_blu<float>(c, blu_bufs<float>(c, F.A32, F.X32, F.Z32, F.V32, F.Dinv32, F.X32r, F.Z32r));
+  else rc = enqueue_blu<double>(c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv, F.Xr, F.Zr));
   if (rc) return rc;
   return prof_mark(c, 0, 1);
 }
 
 // out = add + sgn * M B for R columns (ld Np), M taken as full (mode 0), strictly lower
-// (mode 1) or upper (mode 2) in 64-blocks.  Split-K partials, then a reduction.
+// (mode 1) or upper (mode 2) in 64-blocks.  Split-K partials, then a reduction; one
+// column (R = 1) uses the row-major copy Mr, one wave per row.
 template <typename T>
-static int enqueue_gemm(ww_ctx* c, double* part, const T* M, int mode, const double* B, const double* add,
-                        double sgn, double* out, int R) {
+static int enqueue_gemm(ww_ctx* c, double* part, const T* M, const T* Mr, int mode, const double* B,
+                        const double* add, double sgn, double* out, int R) {
   const int nkt = c->Np / WW_TB;
+  if (R == 1 && Mr) {
+    hipLaunchKernelGGL(k_gemv_row<T>, dim3(c->Np * 64 / WW_NT), dim3(WW_NT), 0, c->stream, Mr, c->Np, mode, B, add,
+                       sgn, out);
+    LAUNCHCHK();
+    return 0;
+  }
   const int tiles = nkt * ((R + 63) / 64);
   int nsplit = (512 + tiles - 1) / tiles;
   if (nsplit > nkt) nsplit = nkt;
@@ -426,15 +462,15 @@ static int enqueue_gemm(ww_ctx* c, double* part, const T* M, int mode, const dou
 static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* X, double* Rs, int R) {
   int rc;
   if (!F.use32) {
-    if ((rc = enqueue_gemm<double>(c, F.part, F.X, 1, B, B, 1.0, Y, R))) return rc;
-    return enqueue_gemm<double>(c, F.part, F.Z, 2, Y, nullptr, 1.0, X, R);
+    if ((rc = enqueue_gemm<double>(c, F.part, F.X, F.Xr, 1, B, B, 1.0, Y, R))) return rc;
+    return enqueue_gemm<double>(c, F.part, F.Z, F.Zr, 2, Y, nullptr, 1.0, X, R);
   }
-  if ((rc = enqueue_gemm<float>(c, F.part, F.X32, 1, B, B, 1.0, Y, R))) return rc;
-  if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, 2, Y, nullptr, 1.0, X, R))) return rc;
+  if ((rc = enqueue_gemm<float>(c, F.part, F.X32, F.X32r, 1, B, B, 1.0, Y, R))) return rc;
+  if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, F.Z32r, 2, Y, nullptr, 1.0, X, R))) return rc;
   for (int it = 0; it < c->nref; ++it) {
-    if ((rc = enqueue_gemm<double>(c, F.part, F.A, 0, X, B, -1.0, Rs, R))) return rc;
-    if ((rc = enqueue_gemm<float>(c, F.part, F.X32, 1, Rs, Rs, 1.0, Y, R))) return rc;
-    if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, 2, Y, X, 1.0, X, R))) return rc;
+    if ((rc = enqueue_gemm<double>(c, F.part, F.A, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, F.part, F.X32, F.X32r, 1, Rs, Rs, 1.0, Y, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, F.Z32r, 2, Y, X, 1.0, X, R))) return rc;
   }
   return 0;
 }
@@ -447,7 +483,7 @@ static int enqueue_dtn_cols(ww_ctx* c, const Fac& F, double* B, double* Yt, doub
   hipLaunchKernelGGL(k_gamma, dim3((R + 1) / 2), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Mu, c->Np, R, Gam,
                      HGm, c->tw, c->N);
   LAUNCHCHK();
-  return enqueue_gemm<double>(c, F.part, F.Gm, 0, Gam, HGm, 1.0, out, R);
+  return enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, Gam, HGm, 1.0, out, R);
 }
 
 static size_t kstride(const ww_ctx* c) { return (size_t)2 * c->N * (c->M + 1); }

@@ -221,9 +221,11 @@ __device__ __forceinline__ void cot_half_branch(double cx, double sx, double chy
 __global__ __launch_bounds__(WW_NT) void k_assemble(
     const double* __restrict__ aux, int nmax, const double* __restrict__ cosT,
     const double* __restrict__ sinT, const double* __restrict__ c0T, double* __restrict__ A,
-    double* __restrict__ Gm, float* __restrict__ A32, int N, int Np, int finite) {
+    double* __restrict__ Gm, float* __restrict__ A32, double* __restrict__ Gmr, double* __restrict__ Ar, int N,
+    int Np, int finite) {
   // stage the per-point quantities of the tile's 64 rows and 64 columns and the 127
   // circulant table entries d = i - j it touches in LDS
+  __shared__ double rt[64][65];   // the tile of Gm (then A) for the row-major copies
   __shared__ double rq[4][64];   // eta_x, eta_xx, exp(s), exp(-s) of rows
   __shared__ double cq[3][64];   // eta_x, exp(s), exp(-s) of columns
   __shared__ double tb[3][128];  // cos, sin, cot/2 of 2 pi d / N, d = i - j
@@ -290,6 +292,21 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
     A[o] = a;
     Gm[o] = gm;
     if (A32) A32[o] = (float)a;
+    rt[tx][jj] = gm;
+  }
+  // row-major copies (Gmr always, Ar when given), coalesced along the rows
+  __syncthreads();
+  for (int idx = t; idx < WW_TB * WW_TB; idx += WW_NT) {
+    const int r = idx >> 6, cc = idx & 63;
+    Gmr[(size_t)(i0 + r) * Np + j0 + cc] = rt[r][cc];
+  }
+  if (!Ar) return;
+  __syncthreads();
+  for (int jj = ty; jj < WW_TB; jj += 4) rt[tx][jj] = A[(size_t)(j0 + jj) * Np + i];
+  __syncthreads();
+  for (int idx = t; idx < WW_TB * WW_TB; idx += WW_NT) {
+    const int r = idx >> 6, cc = idx & 63;
+    Ar[(size_t)(i0 + r) * Np + j0 + cc] = rt[r][cc];
   }
 }
 
@@ -329,6 +346,18 @@ __device__ inline void tile_store(const T* Ts, S* __restrict__ G, size_t ld, int
     const int idx = threadIdx.x + WW_NT * m;
     const int c = idx >> 6;
     if (c < ncol) G[(size_t)c * ld + (idx & 63)] = (S)(scale * Ts[(idx & 63) * TLD + c]);
+  }
+}
+
+// LDS tile -> row-major global copy (the row-major matrix pointer already offset to the
+// tile), coalesced along the rows
+template <typename T>
+__device__ inline void tile_store_rm(const T* Ts, T* __restrict__ G, size_t ld, T scale = T(1)) {
+#pragma unroll
+  for (int m = 0; m < 16; ++m) {
+    const int idx = threadIdx.x + WW_NT * m;
+    const int r = idx >> 6, c = idx & 63;
+    G[(size_t)r * ld + c] = scale * Ts[r * TLD + c];
   }
 }
 
@@ -638,6 +667,8 @@ __device__ __forceinline__ double blk_gj_inverse(T* Ts, T* scr) {
 //                       inverts its updated tile: D_{k+1}
 //   role 2 (i > k, j <= k): L = A_ik D_k;  X_ik = -L (j = k) or X_ij -= L X_kj
 //   role 3 (i <= k, j > k): Z_ik = D_k (i = k) or V_ik D_k (stored when j = k+1);
+//                       the diagonal Z_kk = D_k is stored here (step k), not by the
+//                       workgroup that inverted the block (k_blu_final stores the last)
 //                       V_kj = -D_k A_kj (i = k) or V_ij -= Z_ik A_kj
 // T = double (FP64 path) or float (mixed path: factor of an FP32 copy of A).
 // -------------------------------------------------------------------------------------
@@ -648,6 +679,8 @@ struct BluBufs {
   T* Z;      // Ut^{-1}, upper blocks incl. diagonal
   T* V;      // accumulators of Z (upper blocks)
   T* Dinv;   // nb x 4096, D_k column-major
+  T* Xr;     // row-major copies of X and Z (one-vector solves read rows), or null
+  T* Zr;
   int* status;
   int Np;
   double pivguard;
@@ -656,6 +689,11 @@ struct BluBufs {
 template <typename T>
 __device__ inline T* tileptr(T* M, int Np, int i, int j) {
   return M + (size_t)j * WW_TB * Np + (size_t)i * WW_TB;
+}
+
+template <typename T>
+__device__ inline T* rmptr(T* M, int Np, int i, int j) {
+  return M + (size_t)i * WW_TB * Np + (size_t)j * WW_TB;
 }
 
 template <typename T>
@@ -676,7 +714,10 @@ __global__ __launch_bounds__(WW_NT) void k_blu_init(BluBufs<T> b) {
   const double mp = blk_gj_inverse<T>(Ts, sm + TILE_DBL);
   if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
   store_dinv<T>(Ts, b.Dinv);
-  tile_store<T, T>(Ts, b.Z, b.Np);
+  if (b.Np == WW_TB) {   // one block: no step launch stores Z_00
+    tile_store<T, T>(Ts, b.Z, b.Np);
+    if (b.Zr) tile_store_rm<T>(Ts, b.Zr, b.Np);
+  }
 }
 
 // Load up to four 64 x 64 column-major tiles into LDS with all loads in flight at once
@@ -740,6 +781,11 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
     tiles_load4<T>(d4, s4, l4);
   }
   __syncthreads();
+  if (ldiag && j == k + 1) {
+    // Z_kk = D_k (kept off the workgroup that inverted it, which is on the critical path)
+    tile_store<T, T>(Ls, tileptr(b.Z, Np, k, k), Np);
+    if (b.Zr) tile_store_rm<T>(Ls, rmptr(b.Zr, Np, k, k), Np);
+  }
   Acc64<T> acc;
   if (!ldiag) {
     acc_zero(acc);
@@ -747,10 +793,14 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
     __syncthreads();
     acc_to_lds(acc, Ls, 0, T(1));   // Ls = A_ik D_k (roles 1, 2) or V_ik D_k = Z_ik (role 3)
     __syncthreads();
-    if (role == 3 && j == k + 1) tile_store<T, T>(Ls, tileptr(b.Z, Np, i, k), Np);
+    if (role == 3 && j == k + 1) {
+      tile_store<T, T>(Ls, tileptr(b.Z, Np, i, k), Np);
+      if (b.Zr) tile_store_rm<T>(Ls, rmptr(b.Zr, Np, i, k), Np);
+    }
   }
   if (xfirst) {
     tile_store<T, T>(Ls, tileptr(b.X, Np, i, k), Np, 64, T(-1));
+    if (b.Xr && i == k + 1) tile_store_rm<T>(Ls, rmptr(b.Xr, Np, i, k), Np, T(-1));   // final
     return;
   }
   acc_zero(acc);
@@ -763,11 +813,11 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
     // Schur complement block of the next step: invert it (D_{k+1} = Z_{k+1,k+1})
     const double mp = blk_gj_inverse<T>(Cs, sm);   // Ls, Ds, Rs are free here
     if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
-    store_dinv<T>(Cs, b.Dinv + (size_t)(k + 1) * 4096);
-    tile_store<T, T>(Cs, tileptr(b.Z, Np, k + 1, k + 1), Np);
+    store_dinv<T>(Cs, b.Dinv + (size_t)(k + 1) * 4096);   // Z_{k+1,k+1} is stored one step later
     return;
   }
   tile_store<T, T>(Cs, dst, Np);
+  if (role == 2 && b.Xr && i == k + 1) tile_store_rm<T>(Cs, rmptr(b.Xr, Np, i, j), Np);   // final
 }
 
 // last column block of Z: Z_i,nb-1 = V_i,nb-1 D_nb-1 (i < nb - 1)
@@ -782,6 +832,10 @@ __global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs<T> b) {
   tile_load<T, T>(As, tileptr(b.V, Np, i, k), Np);
   tile_load<T, T>(Bs, b.Dinv + (size_t)k * 4096, 64);
   __syncthreads();
+  if (i == 0) {   // Z of the last diagonal block = D_{nb-1}
+    tile_store<T, T>(Bs, tileptr(b.Z, Np, k, k), Np);
+    if (b.Zr) tile_store_rm<T>(Bs, rmptr(b.Zr, Np, k, k), Np);
+  }
   Acc64<T> acc;
   acc_zero(acc);
   mfma_tile(As, Bs, acc);
@@ -789,6 +843,46 @@ __global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs<T> b) {
   acc_to_lds(acc, As, 0, T(1));
   __syncthreads();
   tile_store<T, T>(As, tileptr(b.Z, Np, i, k), Np);
+  if (b.Zr) tile_store_rm<T>(As, rmptr(b.Zr, Np, i, k), Np);
+}
+
+// -------------------------------------------------------------------------------------
+// One right-hand side: y = add + sgn * M x over the 64-block range of `mode` (0 all,
+// 1 strictly lower, 2 upper incl. diagonal), from the row-major copy Mr (element type
+// T, accumulation in double).  One wave per row: contiguous row reads, eight loads in
+// flight per lane, a fixed-order shuffle reduction (no cross-workgroup reduction).
+// -------------------------------------------------------------------------------------
+template <typename T>
+__global__ __launch_bounds__(WW_NT) void k_gemv_row(const T* __restrict__ Mr, int Np, int mode,
+                                                    const double* __restrict__ x, const double* __restrict__ add,
+                                                    double sgn, double* __restrict__ y) {
+  const int row = (blockIdx.x * WW_NT + threadIdx.x) >> 6;
+  const int lane = threadIdx.x & 63;
+  if (row >= Np) return;
+  const int rb = row / WW_TB;
+  const int lo = (mode == 2) ? rb * WW_TB : 0;
+  const int hi = (mode == 1) ? rb * WW_TB : Np;
+  const T* mr = Mr + (size_t)row * Np;
+  double s0 = 0.0, s1 = 0.0;
+  int j = lo + lane;
+  for (; j + 7 * 64 < hi; j += 8 * 64) {
+    T m[8];
+    double xv[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      m[q] = mr[j + 64 * q];
+      xv[q] = x[j + 64 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 8; q += 2) {
+      s0 = fma((double)m[q], xv[q], s0);
+      s1 = fma((double)m[q + 1], xv[q + 1], s1);
+    }
+  }
+  for (; j < hi; j += 64) s0 = fma((double)mr[j], x[j], s0);
+  double s = s0 + s1;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[row] = (add ? add[row] : 0.0) + sgn * s;
 }
 
 // -------------------------------------------------------------------------------------
