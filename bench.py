@@ -22,6 +22,24 @@ import time
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (vector and MFMA)
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA
 
+# HBM bytes of one FP64 block-LU launch sequence (N = 1024), from the FETCH_SIZE and
+# WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md, calibrated with a
+# plain 256 MiB copy.  Valid only for the kernel source it was measured on: reported as
+# null once the kernels header changes.
+LU_TRAFFIC_BYTES = 266.6e6
+LU_TRAFFIC_SOURCE_SHA256 = "2bbe881c0883f773a0e490630563d3d2ae9c9a794f3dcd04b0fa59c4de03b579"
+
+
+def lu_traffic():
+    import hashlib
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1210_5672_amd", "csrc", "ww_kernels.hpp")
+    try:
+        with open(path, "rb") as fh:
+            ok = hashlib.sha256(fh.read()).hexdigest() == LU_TRAFFIC_SOURCE_SHA256
+    except OSError:
+        ok = False
+    return LU_TRAFFIC_BYTES if ok else None
+
 
 def blas_threads() -> int:
     try:
@@ -116,7 +134,7 @@ def main():
         lu_s = phases["block_lu_ms"] * 1e-3
         ach = (2.0 / 3.0) * n3 / lu_s / 1e12
         roofline = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": ach / FP64_PEAK_TFLOPS, "traffic": None,
+                    "frac": ach / FP64_PEAK_TFLOPS, "traffic": lu_traffic() if w.N == 1024 else None,
                     "kernel": "block LU per stage (k_blu_*), 2/3 N^3 flops per launch sequence",
                     "phases_ms": phases}
     out = {
