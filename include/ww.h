@@ -46,7 +46,12 @@ typedef struct ww_ctx ww_ctx;
 /* context flags */
 #define WW_FP64 0u         /* LU, triangular solves, everything in FP64 */
 #define WW_MIXED 1u        /* LU and triangular solves in FP32 on MFMA, FP64 iterative
-                              refinement of every solve (residuals in FP64) */
+                              refinement of every solve (residuals in FP64): a fixed number
+                              of sweeps (2; environment WW_NREF, 0..8; 0 leaves the FP32
+                              solve, which then fails the test), then the FP64
+                              residual of the final solution must be at most 2^-43 of
+                              the right-hand side in every column (max norm), else
+                              WW_EREFINE */
 
 /*
  * ww_create: allocate a context whose device workspace serves every N <= n_max and
@@ -82,7 +87,8 @@ int dtn_setup(ww_ctx *ctx, const double *surface, double h, double tau, int N);
  * (device, N x nrhs, ld N) solve A mu = psi with the factors of the last dtn_setup,
  * form gamma = d mu / d alpha and return the Dirichlet-Neumann output
  * G psi = (1/2) H gamma + Gm gamma in `dtn_out` (device, N x nrhs, ld N).  `mu_out`
- * (device, N x nrhs, or NULL) receives mu.  nrhs <= r_max.
+ * (device, N x nrhs, or NULL) receives mu.  nrhs <= r_max.  Stream-ordered, except in a
+ * WW_MIXED context, where it synchronises to report the refinement test.
  * Errors: WW_ENOSETUP, WW_EINVAL, WW_EREFINE (mixed mode), WW_EHIP.
  */
 int dtn_solve_multi(ww_ctx *ctx, const double *rhs, int nrhs, double *dtn_out, double *mu_out);
@@ -107,7 +113,7 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
  *   f    (host)   f = r.r / 2, or NULL
  * Synchronises when f is requested and to check the status flags.
- * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EHIP.
+ * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EREFINE (mixed mode), WW_EHIP.
  */
 int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *r, double *J,
                double *drdT, double *f);

@@ -455,6 +455,11 @@ static int enqueue_gemm(ww_ctx* c, double* part, const T* M, const T* Mr, int mo
   return 0;
 }
 
+// Convergence test of the mixed-precision refinement: per column, the FP64 residual
+// of the final solution must be at most 2^-43 of the right-hand side (max norm); the
+// solution's relative error is then at most about cond(A) * 2^-43.
+static const double REFINE_TOL = 1.1368683772161603e-13;
+
 // X = A^{-1} B for R columns (ld Np); Y and Rs are scratch; B is kept.
 // FP64:  X = Z (B + Xs B).
 // mixed: X = Z32 (B + X32 B), then nref sweeps of  r = B - A X (FP64 residual with the
@@ -471,6 +476,13 @@ static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* 
     if ((rc = enqueue_gemm<double>(c, F.part, F.A, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
     if ((rc = enqueue_gemm<float>(c, F.part, F.X32, F.X32r, 1, Rs, Rs, 1.0, Y, R))) return rc;
     if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, F.Z32r, 2, Y, X, 1.0, X, R))) return rc;
+  }
+  {
+    // convergence test on the FP64 residual of the final solution (also with no sweep)
+    if ((rc = enqueue_gemm<double>(c, F.part, F.A, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
+    hipLaunchKernelGGL(k_refine_check, dim3(R), dim3(WW_NT), 0, c->stream, Rs, B, c->Np, c->N, REFINE_TOL,
+                       c->status);
+    LAUNCHCHK();
   }
   return 0;
 }
@@ -638,6 +650,11 @@ int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, dou
     hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Mu, Np, mu_out, N, Np, N, nrhs);
     LAUNCHCHK();
   }
+  if (mixed(c)) {   // report the refinement test
+    int st = 0;
+    if ((rc = read_status(c, &st))) return rc;
+    if (st & 4) return fail(WW_EREFINE, "mixed precision: relative residual of the refined solution above 2^-43");
+  }
   return 0;
 }
 
@@ -759,6 +776,7 @@ static int shoot_status(ww_ctx* c) {
   if ((rc = read_status(c, &st))) return rc;
   if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
   if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
+  if (st & 4) return fail(WW_EREFINE, "mixed precision: relative residual of the refined solution above 2^-43");
   return 0;
 }
 

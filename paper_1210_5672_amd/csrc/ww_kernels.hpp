@@ -1504,6 +1504,36 @@ __global__ void k_save_aux(const double* __restrict__ aux, int nmax, int N, doub
 }
 
 // -------------------------------------------------------------------------------------
+// Convergence test of a mixed-precision solve (one workgroup per column): with the
+// FP64 residual r = B - A X of the final X, max|r| <= tol * max|B| over the N rows
+// (a relative residual, which bounds the normwise backward error); a column that
+// fails, or a NaN, sets status bit 4 (reported as WW_EREFINE).
+// -------------------------------------------------------------------------------------
+__global__ __launch_bounds__(WW_NT) void k_refine_check(const double* __restrict__ r, const double* __restrict__ B,
+                                                        int Np, int N, double tol, int* __restrict__ status) {
+  __shared__ double rr[WW_NT], rb[WW_NT];
+  const double* rc = r + (size_t)blockIdx.x * Np;
+  const double* bc = B + (size_t)blockIdx.x * Np;
+  double mr = 0.0, mb = 0.0;
+  for (int i = threadIdx.x; i < N; i += WW_NT) {
+    mr = fmax(mr, fabs(rc[i]));
+    mb = fmax(mb, fabs(bc[i]));
+    if (rc[i] != rc[i]) mr = INFINITY;
+  }
+  rr[threadIdx.x] = mr;
+  rb[threadIdx.x] = mb;
+  __syncthreads();
+  for (int off = WW_NT / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) {
+      rr[threadIdx.x] = fmax(rr[threadIdx.x], rr[threadIdx.x + off]);
+      rb[threadIdx.x] = fmax(rb[threadIdx.x], rb[threadIdx.x + off]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0 && !(rr[0] <= tol * rb[0])) atomicOr(status, 4);
+}
+
+// -------------------------------------------------------------------------------------
 // Measurement stamp (not part of the method): one thread reads the GPU's constant-rate
 // wall clock.  which = 0 keeps the start tick of a slot; which = 1 adds the ticks since
 // that start to the slot's running sum and counts the interval.  Slots are
