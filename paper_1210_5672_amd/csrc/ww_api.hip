@@ -135,7 +135,24 @@ static int set_tables(ww_ctx* c, int N) {
   HIPCHK(hipMemcpy(c->sinT, si.data(), N * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->c0T, c0.data(), N * 8, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->sig, sg.data(), N * 8, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(c->tw, tw.data(), N * sizeof(cplx), hipMemcpyHostToDevice));
+  // FFT twiddles in pass order (radix 4, then 3, then 2): the pass of radix R starting
+  // at span Ns takes exp(-2 pi i jm q / (Ns R)) = tw[jm q N / (Ns R)] at offset
+  // Ns - 1 + (q - 1) Ns + jm
+  std::vector<cplx> twp(N, cplx{0.0, 0.0});
+  {
+    int m = N, Ns = 1;
+    auto add_pass = [&](int R) {
+      const int tstride = N / (Ns * R);
+      for (int q = 1; q < R; ++q)
+        for (int jm = 0; jm < Ns; ++jm) twp[Ns - 1 + (q - 1) * Ns + jm] = tw[(size_t)jm * q * tstride];
+      Ns *= R;
+      m /= R;
+    };
+    while (m % 4 == 0) add_pass(4);
+    while (m % 3 == 0) add_pass(3);
+    while (m % 2 == 0) add_pass(2);
+  }
+  HIPCHK(hipMemcpy(c->tw, twp.data(), N * sizeof(cplx), hipMemcpyHostToDevice));
   c->tables_N = N;
   return 0;
 }

@@ -5,8 +5,8 @@
 // multipliers).  Real signals are processed in pairs packed as one complex signal.
 //
 // Algorithm: Stockham autosort with radix 4, 3 and 2 passes, ping-pong between two
-// LDS buffers; twiddles exp(-2 pi i t / N) are read from an LDS copy of a host-computed
-// table (load_twiddles, once per kernel).  Forward transform uses exp(-i k x); the inverse
+// LDS buffers; twiddles are read from an LDS copy of a host-computed table laid out
+// pass by pass (load_twiddles, once per kernel).  Forward transform uses exp(-i k x); the inverse
 // uses exp(+i k x) and scales by 1/N.
 #pragma once
 #include <hip/hip_runtime.h>
@@ -51,57 +51,84 @@ __host__ __device__ inline FftPlan make_plan(int n) {
 }
 
 // One Stockham pass of radix R (fully unrolled butterfly, static register arrays).
+// lgNs >= 0: Ns = 2^lgNs, so the index split j -> (j / Ns, j % Ns) is a shift and a
+// mask (the radix-4 passes, which run first); lgNs < 0: general Ns (integer division).
+// Intermediate buffers between passes use the layout x -> x ^ ((x >> 3) & 7) (a
+// permutation inside each aligned group of 8 elements, used when 8 | N): the strided
+// writes of the first pass then hit distinct LDS bank groups.  The first pass reads and
+// the last pass writes the natural layout.
+__device__ __forceinline__ int fft_swz(int x, bool on) { return on ? (x ^ ((x >> 3) & 7)) : x; }
+
+// Butterfly of radix R on v (twiddles already applied); dir = -1 forward, +1 inverse.
 template <int R>
-__device__ __forceinline__ void fft_pass(const cplx* src, cplx* dst, const cplx* tw, int N, int Ns, int dir) {
+__device__ __forceinline__ void fft_bfly(cplx (&v)[R], int dir) {
+  if (R == 2) {
+    cplx t0 = cadd(v[0], v[1]);
+    cplx t1 = csub(v[0], v[1]);
+    v[0] = t0;
+    v[1] = t1;
+  } else if (R == 4) {
+    cplx s02 = cadd(v[0], v[2 % R]);
+    cplx d02 = csub(v[0], v[2 % R]);
+    cplx s13 = cadd(v[1], v[3 % R]);
+    cplx d13 = cmul_i(csub(v[1], v[3 % R]), dir);
+    v[0] = cadd(s02, s13);
+    v[2 % R] = csub(s02, s13);
+    v[1] = cadd(d02, d13);
+    v[3 % R] = csub(d02, d13);
+  } else {  // R == 3
+    const double c3 = -0.5;
+    const double s3 = 0.86602540378443864676;  // sin(2 pi / 3)
+    cplx sm = cadd(v[1], v[2 % R]);
+    cplx d = csub(v[1], v[2 % R]);
+    cplx m0 = cadd(v[0], cscale(sm, c3));
+    // forward: exp(-2 pi i/3) -> multiply d by -i s3 ; inverse: +i s3
+    cplx md = cscale(cmul_i(d, dir), s3);
+    v[0] = cadd(v[0], sm);
+    v[1] = cadd(m0, md);
+    v[2 % R] = csub(m0, md);
+  }
+}
+
+// Inputs of butterfly j of a pass: v[q] = src[j + q nb] times the pass twiddle.
+// twp: this pass's twiddles, twp[(q - 1) Ns + jm] = exp(-2 pi i jm q / (Ns R)), so that
+// neighbouring lanes read neighbouring entries.
+template <int R>
+__device__ __forceinline__ void fft_load(const cplx* src, const cplx* twp, int nb, int j, int jm, int Ns, int dir,
+                                         bool rsw, cplx (&v)[R]) {
+#pragma unroll
+  for (int q = 0; q < R; ++q) {
+    cplx x = src[fft_swz(j + q * nb, rsw)];
+    if (q > 0) {
+      cplx w = twp[(q - 1) * Ns + jm];
+      if (dir > 0) w = cconj(w);
+      x = cmul(x, w);
+    }
+    v[q] = x;
+  }
+}
+
+// One Stockham pass src -> dst; outputs scaled by sc (the last pass of an inverse).
+template <int R>
+__device__ __forceinline__ void fft_pass(const cplx* src, cplx* dst, const cplx* twp, int N, int Ns, int dir,
+                                         int lgNs, bool rsw, bool wsw, double sc) {
   const int nb = N / R;
-  const int tstride = N / (Ns * R);
   for (int j = threadIdx.x; j < nb; j += blockDim.x) {
-    const int jm = j % Ns;
+    const int jq = lgNs >= 0 ? (j >> lgNs) : j / Ns;
+    const int jm = j - jq * Ns;
     cplx v[R];
+    fft_load<R>(src, twp, nb, j, jm, Ns, dir, rsw, v);
+    fft_bfly<R>(v, dir);
+    const int idxD = jq * Ns * R + jm;
 #pragma unroll
-    for (int q = 0; q < R; ++q) {
-      cplx x = src[j + q * nb];
-      if (q > 0) {
-        cplx w = tw[jm * q * tstride];
-        if (dir > 0) w = cconj(w);
-        x = cmul(x, w);
-      }
-      v[q] = x;
-    }
-    if (R == 2) {
-      cplx t0 = cadd(v[0], v[1]);
-      cplx t1 = csub(v[0], v[1]);
-      v[0] = t0;
-      v[1] = t1;
-    } else if (R == 4) {
-      cplx s02 = cadd(v[0], v[2]);
-      cplx d02 = csub(v[0], v[2]);
-      cplx s13 = cadd(v[1], v[3 % R]);
-      cplx d13 = cmul_i(csub(v[1], v[3 % R]), dir);
-      v[0] = cadd(s02, s13);
-      v[2 % R] = csub(s02, s13);
-      v[1] = cadd(d02, d13);
-      v[3 % R] = csub(d02, d13);
-    } else {  // R == 3
-      const double c3 = -0.5;
-      const double s3 = 0.86602540378443864676;  // sin(2 pi / 3)
-      cplx sm = cadd(v[1], v[2 % R]);
-      cplx d = csub(v[1], v[2 % R]);
-      cplx m0 = cadd(v[0], cscale(sm, c3));
-      // forward: exp(-2 pi i/3) -> multiply d by -i s3 ; inverse: +i s3
-      cplx md = cscale(cmul_i(d, dir), s3);
-      v[0] = cadd(v[0], sm);
-      v[1] = cadd(m0, md);
-      v[2 % R] = csub(m0, md);
-    }
-    const int idxD = (j / Ns) * Ns * R + jm;
-#pragma unroll
-    for (int q = 0; q < R; ++q) dst[idxD + q * Ns] = v[q];
+    for (int q = 0; q < R; ++q) dst[fft_swz(idxD + q * Ns, wsw)] = cscale(v[q], sc);
   }
 }
 
 // Transform `a` (N complex in LDS) in place; `b` is LDS scratch of N complex.
-// tw: twiddle table in LDS, tw[t] = exp(-2 pi i t / N), t = 0..N-1 (load_twiddles).
+// tw: twiddle table in LDS (load_twiddles) in pass order: the pass with radix R that
+// starts at span Ns reads the N_s R - N_s entries from offset Ns - 1 (the offsets
+// telescope: the table holds N - 1 entries).
 // dir = -1 forward, +1 inverse (inverse also scales by 1/N).
 // Must be called by all threads of the workgroup.  Ends with a barrier.
 __device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& P, int dir) {
@@ -113,15 +140,18 @@ __device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& 
   int Ns = 1;
   __syncthreads();
   const int npass = P.n4 + P.n3 + P.n2;
+  const bool sw = (N & 7) == 0;
   for (int ps = 0; ps < npass; ++ps) {
+    const bool rsw = sw && ps > 0, wsw = sw && ps + 1 < npass;
+    const cplx* twp = tw + (Ns - 1);
     if (ps < P.n4) {
-      fft_pass<4>(src, dst, tw, N, Ns, dir);
+      fft_pass<4>(src, dst, twp, N, Ns, dir, 2 * ps, rsw, wsw, 1.0);   // Ns = 4^ps
       Ns *= 4;
     } else if (ps < P.n4 + P.n3) {
-      fft_pass<3>(src, dst, tw, N, Ns, dir);
+      fft_pass<3>(src, dst, twp, N, Ns, dir, -1, rsw, wsw, 1.0);
       Ns *= 3;
     } else {
-      fft_pass<2>(src, dst, tw, N, Ns, dir);
+      fft_pass<2>(src, dst, twp, N, Ns, dir, -1, rsw, wsw, 1.0);
       Ns *= 2;
     }
     __syncthreads();
