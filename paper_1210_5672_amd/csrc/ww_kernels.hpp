@@ -541,8 +541,48 @@ __device__ __forceinline__ float lane_read(float x, int lane) {
   return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), lane));
 }
 
+// Broadcast of lane n of each 16-lane row to the whole row (DPP row_newbcast on the
+// 64-bit move of CDNA3/4; a float travels in the low half).  n must fold to a
+// constant (unrolled loops): the switch then reduces to one move.
+template <int CTRL>
+__device__ __forceinline__ long long dpp64(long long v) {
+  return __builtin_amdgcn_update_dpp(0LL, v, CTRL, 0xf, 0xf, false);
+}
+__device__ __forceinline__ long long bits64(double v) { return __double_as_longlong(v); }
+__device__ __forceinline__ long long bits64(float v) { return (long long)(unsigned)__float_as_int(v); }
+__device__ __forceinline__ void from_bits64(long long u, double& v) { v = __longlong_as_double(u); }
+__device__ __forceinline__ void from_bits64(long long u, float& v) { v = __int_as_float((int)(unsigned)u); }
+template <typename T>
+__device__ __forceinline__ T row_bcast(T v, int n) {
+  const long long u = bits64(v);
+  long long r;
+  switch (n & 15) {
+    case 0: r = dpp64<0x150>(u); break;
+    case 1: r = dpp64<0x151>(u); break;
+    case 2: r = dpp64<0x152>(u); break;
+    case 3: r = dpp64<0x153>(u); break;
+    case 4: r = dpp64<0x154>(u); break;
+    case 5: r = dpp64<0x155>(u); break;
+    case 6: r = dpp64<0x156>(u); break;
+    case 7: r = dpp64<0x157>(u); break;
+    case 8: r = dpp64<0x158>(u); break;
+    case 9: r = dpp64<0x159>(u); break;
+    case 10: r = dpp64<0x15a>(u); break;
+    case 11: r = dpp64<0x15b>(u); break;
+    case 12: r = dpp64<0x15c>(u); break;
+    case 13: r = dpp64<0x15d>(u); break;
+    case 14: r = dpp64<0x15e>(u); break;
+    default: r = dpp64<0x15f>(u); break;
+  }
+  T out;
+  from_bits64(r, out);
+  return out;
+}
+
 // Gauss-Jordan inverse of one 16 x 16 block held by a whole wave in the MFMA result
-// layout (lane: column lane & 15, rows Mfma<T>::row(i, lane >> 4)).
+// layout (lane: column lane & 15, rows Mfma<T>::row(i, lane >> 4)).  The pivot column
+// entries a lane needs sit in lane p of its own 16-lane row (row broadcasts); the
+// pivot row entry sits in another row (one lane shuffle); the pivot by a lane read.
 template <typename T>
 __device__ __forceinline__ void leaf_gj16(typename Mfma<T>::V& x, T& minpiv) {
   const int lane = threadIdx.x & 63;
@@ -554,7 +594,7 @@ __device__ __forceinline__ void leaf_gj16(typename Mfma<T>::V& x, T& minpiv) {
     const T rsrc = __shfl(x[pe], pg * 16 + cl);      // a_p,cl
     T ksrc[4];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) ksrc[i] = __shfl(x[i], rq * 16 + p);   // a_row(i),p
+    for (int i = 0; i < 4; ++i) ksrc[i] = row_bcast(x[i], p);   // a_row(i),p
     minpiv = fmin(minpiv, fabs(piv));
     const T ip = recip(piv);
     const T rho = (cl == p) ? T(1) + ip : rsrc * ip;
