@@ -26,8 +26,8 @@ FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA
 # WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md, calibrated with a
 # plain 256 MiB copy.  Valid only for the kernel source it was measured on: reported as
 # null once the kernels header changes.
-LU_TRAFFIC_BYTES = 266.6e6
-LU_TRAFFIC_SOURCE_SHA256 = "2bbe881c0883f773a0e490630563d3d2ae9c9a794f3dcd04b0fa59c4de03b579"
+LU_TRAFFIC_BYTES = 266.9e6
+LU_TRAFFIC_SOURCE_SHA256 = "2ef8fcc212a36ea80c17a9bfd507064a4e5a4466b047e3a30564555111177f47"
 
 
 def lu_traffic():
