@@ -122,8 +122,10 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
  * shoot_eval_batch: shoot_eval for n_inst independent instances (continuation
  * instances of uneven N, depth, tension, M and step count), each with its own context
  * (distinct contexts; give them distinct streams for the instances to overlap).  Each
- * context replays its captured step graph on its stream; the steps of all instances are
- * issued interleaved so the GPU overlaps them.  Per-instance arrays: params[i] (device),
+ * context replays a captured step graph on its stream and the steps of all instances
+ * are issued interleaved.  With more than one instance the step graphs keep each
+ * instance on its one stream (the column chain follows the base chain), which lets the
+ * GPU overlap the instances; a single instance uses the two-stream graph of shoot_eval.  Per-instance arrays: params[i] (device),
  * T[i], nsteps[i] (host), r[i] (device), J[i] (device or NULL; J may be NULL),
  * drdT[i] (device or NULL; drdT may be NULL), f[i] (host; f may be NULL).
  * Results are identical to n_inst separate shoot_eval calls.  Synchronises every

@@ -96,9 +96,10 @@ struct ww_ctx {
   unsigned long long* stamps = nullptr;   // [phase][stage] x {start, sum, count}
   // one RK step captured as a graph, replayed nsteps times
   bool use_graph = true;
+  bool overlap = true;   // column chain on the side stream (environment WW_NO_OVERLAP=1: one stream)
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t step_exec = nullptr;
-  int gN = -1, gM = -1, gcols = -1, gnst = -1;
+  int gN = -1, gM = -1, gcols = -1, gnst = -1, gtwo = -1;
 };
 
 static bool valid_n(int N) {
@@ -272,6 +273,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   {
     const char* ng = std::getenv("WW_NO_GRAPH");
     c->use_graph = !(ng && ng[0] == '1');
+    const char* no = std::getenv("WW_NO_OVERLAP");
+    c->overlap = !(no && no[0] == '1');
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
   }
@@ -550,9 +553,12 @@ static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
   return prof_mark(c, 2, 1);
 }
 
-static int enqueue_step(ww_ctx* c, bool cols) {
+// two_streams: the column chain of stage s runs on the side stream while stage s + 1
+// refactors (single instances); otherwise it follows the base chain on one stream
+// (batches, where the instances overlap each other instead).
+static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
   int rc;
-  const bool two = cols && c->M > 0;
+  const bool two = cols && c->M > 0 && two_streams;
   hipStream_t s0 = c->stream;
   for (int s = 0; s < c->nst; ++s) {
     const int par = s & 1;
@@ -568,6 +574,8 @@ static int enqueue_step(ww_ctx* c, bool cols) {
       rc = enqueue_col_chain(c, s, fac_set(c, par, true));
       c->stream = s0;
       if (!rc) HIPCHK(hipEventRecord(c->evC[s], c->side));
+    } else if (!rc && cols && c->M > 0) {
+      rc = enqueue_col_chain(c, s, fac_set(c, par, true));   // one stream: after the base chain
     }
     g_prof_stage = -1;
     if (rc) return rc;
@@ -583,8 +591,10 @@ static int enqueue_step(ww_ctx* c, bool cols) {
 // Capture one step (all stages + end of step) into a graph on the private capture
 // stream; the graph is reused while (N, M, columns, stages) are unchanged.  Step
 // coefficients live in device memory, so T and the parameters may change freely.
-static int ensure_step_graph(ww_ctx* c, bool cols) {
-  if (c->step_exec && c->gN == c->N && c->gM == c->M && c->gcols == (int)cols && c->gnst == c->nst) return 0;
+static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
+  if (c->step_exec && c->gN == c->N && c->gM == c->M && c->gcols == (int)cols && c->gnst == c->nst &&
+      c->gtwo == (int)two_streams)
+    return 0;
   if (c->step_exec) {
     HIPCHK(hipGraphExecDestroy(c->step_exec));
     c->step_exec = nullptr;
@@ -592,7 +602,7 @@ static int ensure_step_graph(ww_ctx* c, bool cols) {
   hipStream_t user = c->stream;
   c->stream = c->cap_stream;
   HIPCHK(hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-  const int rc = enqueue_step(c, cols);
+  const int rc = enqueue_step(c, cols, two_streams);
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
   c->stream = user;
@@ -607,6 +617,7 @@ static int ensure_step_graph(ww_ctx* c, bool cols) {
   c->gN = c->N;
   c->gM = c->M;
   c->gcols = (int)cols;
+  c->gtwo = (int)two_streams;
   c->gnst = c->nst;
   return 0;
 }
@@ -731,7 +742,7 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
 
 // shoot_eval in three parts so that shoot_eval_batch can interleave instances:
 // prepare (coefficients, initial state, step graph), one step, finish (outputs).
-static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, bool cols) {
+static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, bool cols, bool two_streams) {
   if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_eval before shoot_setup");
   if (c->nst < 1) return fail(WW_EINVAL, "no tableau set");
   if (nsteps < 1 || !std::isfinite(T)) return fail(WW_EINVAL, "nsteps >= 1 and finite T required");
@@ -753,16 +764,16 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
   LAUNCHCHK();
-  if (c->use_graph) return ensure_step_graph(c, cols);
+  if (c->use_graph) return ensure_step_graph(c, cols, two_streams);
   return 0;
 }
 
-static int shoot_one_step(ww_ctx* c, bool cols) {
+static int shoot_one_step(ww_ctx* c, bool cols, bool two_streams) {
   if (c->use_graph) {
     HIPCHK(hipGraphLaunch(c->step_exec, c->stream));
     return 0;
   }
-  return enqueue_step(c, cols);
+  return enqueue_step(c, cols, two_streams);
 }
 
 static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT, double* fhost) {
@@ -804,9 +815,9 @@ int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r,
   if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
   const bool cols = (J != nullptr) && c->M > 0;
   int rc;
-  if ((rc = shoot_prepare(c, params, T, nsteps, cols))) return rc;
+  if ((rc = shoot_prepare(c, params, T, nsteps, cols, c->overlap))) return rc;
   for (int n = 0; n < nsteps; ++n)
-    if ((rc = shoot_one_step(c, cols))) return rc;
+    if ((rc = shoot_one_step(c, cols, c->overlap))) return rc;
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
   return shoot_status(c);
 }
@@ -821,9 +832,13 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   }
   int rc;
   int maxsteps = 0;
+  // one instance: the two-stream step graph of shoot_eval; several: one-stream graphs,
+  // which the hardware overlaps across instances (two-stream graphs of several
+  // instances run one after the other)
+  const bool two = n_inst == 1 && ctx[0]->overlap;
   for (int i = 0; i < n_inst; ++i) {
     const bool cols = J && J[i] && ctx[i]->M > 0;
-    if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols))) return rc;
+    if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols, two))) return rc;
     maxsteps = std::max(maxsteps, nsteps[i]);
   }
   // interleave the instances step by step: each context replays its own step graph on
@@ -831,7 +846,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   for (int n = 0; n < maxsteps; ++n)
     for (int i = 0; i < n_inst; ++i)
       if (n < nsteps[i])
-        if ((rc = shoot_one_step(ctx[i], J && J[i] && ctx[i]->M > 0))) return rc;
+        if ((rc = shoot_one_step(ctx[i], J && J[i] && ctx[i]->M > 0, two))) return rc;
   for (int i = 0; i < n_inst; ++i) {
     const bool cols = J && J[i] && ctx[i]->M > 0;
     if ((rc = shoot_finish(ctx[i], cols, r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr, f ? &f[i] : nullptr)))
