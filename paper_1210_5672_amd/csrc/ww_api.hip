@@ -434,7 +434,7 @@ static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 // with the block-triangular inverses
 static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   const int nb = c->Np / WW_TB;
-  hipLaunchKernelGGL(k_assemble, dim3(nb, nb), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT,
+  hipLaunchKernelGGL(k_assemble, dim3(nb, c->Np / ASM_CW), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT,
                      c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, F.use32 ? F.Ar : nullptr, c->N, c->Np,
                      c->finite);
   LAUNCHCHK();

@@ -202,7 +202,8 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
 //   D = cot((zeta_i - conj zeta_j)/2), K -= Im{conj(zeta'_j) D}/2, G -= Re{zeta'_i D}/2
 // with zeta' = 1 + i eta_x, zeta'' = i eta_xx.  The image terms enter with a minus
 // sign (the bracket of eq. (Phi) / (plemelj:1)-(plemelj:2)).
-// One 64 x 64 tile per workgroup; thread (tx, ty) owns row tx and columns ty + 4m.
+// One strip of 64 rows x 16 columns per workgroup; thread (tx, ty) owns row tx and
+// columns ty + 4m.
 // -------------------------------------------------------------------------------------
 __device__ __forceinline__ void cot_half_branch(double cx, double sx, double chy, double shy,
                                                 double& re, double& im) {
@@ -218,31 +219,36 @@ __device__ __forceinline__ void cot_half_branch(double cx, double sx, double chy
   }
 }
 
+// Launch: grid (Np / 64, Np / 16): one workgroup per strip of 64 rows x 16 columns,
+// four workgroups per 64-tile, so that enough waves are resident to hide the latency
+// of the dependent FP64 chains (divisions of the cot branch formula).
+#define ASM_CW 16   // columns per assembly workgroup
 __global__ __launch_bounds__(WW_NT) void k_assemble(
     const double* __restrict__ aux, int nmax, const double* __restrict__ cosT,
     const double* __restrict__ sinT, const double* __restrict__ c0T, double* __restrict__ A,
     double* __restrict__ Gm, float* __restrict__ A32, double* __restrict__ Gmr, double* __restrict__ Ar, int N,
     int Np, int finite) {
-  // stage the per-point quantities of the tile's 64 rows and 64 columns and the 127
+  // stage the per-point quantities of the strip's 64 rows and 16 columns and the 79
   // circulant table entries d = i - j it touches in LDS
-  __shared__ double rt[64][65];   // the tile of Gm (then A) for the row-major copies
-  __shared__ double rq[4][64];   // eta_x, eta_xx, exp(s), exp(-s) of rows
-  __shared__ double cq[3][64];   // eta_x, exp(s), exp(-s) of columns
-  __shared__ double tb[3][128];  // cos, sin, cot/2 of 2 pi d / N, d = i - j
-  const int i0 = blockIdx.x * WW_TB, j0 = blockIdx.y * WW_TB;
+  __shared__ double rt[WW_TB][ASM_CW + 1];   // the strip of Gm (then A) for the row-major copies
+  __shared__ double rq[4][WW_TB];            // eta_x, eta_xx, exp(s), exp(-s) of rows
+  __shared__ double cq[3][ASM_CW];           // eta_x, exp(s), exp(-s) of columns
+  __shared__ double tb[3][WW_TB + ASM_CW];   // cos, sin, cot/2 of 2 pi d / N, d = i - j
+  const int i0 = blockIdx.x * WW_TB, j0 = blockIdx.y * ASM_CW;
   const int t = threadIdx.x;
   {
     const int q = t >> 6, r = t & 63;   // 4 x 64 row quantities
     const int ir = i0 + r;
     rq[q][r] = (ir < N) ? aux[(q == 0 ? AUX_EX : q == 1 ? AUX_EXX : q == 2 ? AUX_EP : AUX_EM) * nmax + ir] : 0.0;
-    if (q < 3) {
+    if (q < 3 && r < ASM_CW) {
       const int jc = j0 + r;
       cq[q][r] = (jc < N) ? aux[(q == 0 ? AUX_EX : q == 1 ? AUX_EP : AUX_EM) * nmax + jc] : 0.0;
     }
-    // table entries e = 0..126 <-> d = (i0 - j0 - 63 + e) mod N
-    for (int e = t; e < 3 * 127; e += WW_NT) {
-      const int which = e / 127, ee = e - which * 127;
-      int d = (i0 - j0 - 63 + ee) % N;
+    // table entries e = 0..78 <-> d = (i0 - j0 - 15 + e) mod N
+    constexpr int NE = WW_TB + ASM_CW - 1;
+    for (int e = t; e < 3 * NE; e += WW_NT) {
+      const int which = e / NE, ee = e - which * NE;
+      int d = (i0 - j0 - (ASM_CW - 1) + ee) % N;
       if (d < 0) d += N;
       tb[which][ee] = which == 0 ? cosT[d] : which == 1 ? sinT[d] : c0T[d];
     }
@@ -253,8 +259,8 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
   const int i = i0 + tx;
   const double invN = 1.0 / (double)N;
   const double exi = rq[0][tx], exxi = rq[1][tx], epi = rq[2][tx], emi = rq[3][tx];
-#pragma unroll 4
-  for (int jj = ty; jj < WW_TB; jj += 4) {
+#pragma unroll
+  for (int jj = ty; jj < ASM_CW; jj += 4) {
     const int j = j0 + jj;
     double a, gm;
     if (i >= N || j >= N) {
@@ -262,7 +268,7 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
       gm = 0.0;
     } else {
       const double exj = cq[0][jj], epj = cq[1][jj], emj = cq[2][jj];
-      const int e = tx - jj + 63;
+      const int e = tx - jj + (ASM_CW - 1);
       const double cx = tb[0][e], sx = tb[1][e];
       double Kv, Gv;
       if (i != j) {
@@ -294,18 +300,18 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
     if (A32) A32[o] = (float)a;
     rt[tx][jj] = gm;
   }
-  // row-major copies (Gmr always, Ar when given), coalesced along the rows
+  // row-major copies (Gmr always, Ar when given): 16 contiguous doubles per row
   __syncthreads();
-  for (int idx = t; idx < WW_TB * WW_TB; idx += WW_NT) {
-    const int r = idx >> 6, cc = idx & 63;
+  for (int idx = t; idx < WW_TB * ASM_CW; idx += WW_NT) {
+    const int r = idx / ASM_CW, cc = idx % ASM_CW;
     Gmr[(size_t)(i0 + r) * Np + j0 + cc] = rt[r][cc];
   }
   if (!Ar) return;
   __syncthreads();
-  for (int jj = ty; jj < WW_TB; jj += 4) rt[tx][jj] = A[(size_t)(j0 + jj) * Np + i];
+  for (int jj = ty; jj < ASM_CW; jj += 4) rt[tx][jj] = A[(size_t)(j0 + jj) * Np + i];
   __syncthreads();
-  for (int idx = t; idx < WW_TB * WW_TB; idx += WW_NT) {
-    const int r = idx >> 6, cc = idx & 63;
+  for (int idx = t; idx < WW_TB * ASM_CW; idx += WW_NT) {
+    const int r = idx / ASM_CW, cc = idx % ASM_CW;
     Ar[(size_t)(i0 + r) * Np + j0 + cc] = rt[r][cc];
   }
 }
