@@ -106,6 +106,7 @@ class Context:
         self.lib = load()
         self.ptr = ctypes.c_void_p()
         s = stream if stream is not None else torch.cuda.current_stream()
+        self._stream = s            # the library keeps the handle: keep the stream alive
         _check(self.lib.ww_create(ctypes.byref(self.ptr), n_max, r_max,
                                   WW_MIXED if mixed else WW_FP64, ctypes.c_void_p(s.cuda_stream)))
         self.n_max, self.r_max, self.mixed = n_max, r_max, mixed
@@ -128,6 +129,14 @@ class Context:
 
     def set_stream(self, stream):
         _check(self.lib.ww_set_stream(self.ptr, ctypes.c_void_p(stream.cuda_stream)))
+        self._stream = stream
+
+    def _keep(self, t: torch.Tensor):
+        """A temporary read by stream-ordered work on the context's stream must not be
+        reused by torch's allocator before that work has run."""
+        if self._stream != torch.cuda.current_stream(t.device):
+            t.record_stream(self._stream)
+        return t
 
     # ----- DtN -----
     def dtn_setup(self, surface: torch.Tensor, h: float, tau: float = 0.0):
@@ -141,7 +150,7 @@ class Context:
         vec = rhs.dim() == 1
         cols = rhs.reshape(-1, 1) if vec else rhs
         N, nrhs = cols.shape
-        cm = cols.t().contiguous()                     # column-major storage
+        cm = self._keep(cols.t().contiguous())         # column-major storage
         out = torch.empty_like(cm)
         mu = torch.empty_like(cm) if want_mu else None
         _check(self.lib.dtn_solve_multi(self.ptr, _ptr(cm), nrhs, _ptr(out), _ptr(mu)))
@@ -181,8 +190,8 @@ class Context:
         _check(self.lib.ww_profile(self.ptr, 1 if enable else 0))
 
     def profile_read(self, phase: int) -> float:
-        """Mean duration (ms) of a phase over the stages of the last replayed step:
-        0 block LU, 1 base chain, 2 column chain."""
+        """Mean duration (ms) of a phase over every stage of every step replayed since
+        the last profile(True): 0 block LU, 1 base chain, 2 column chain."""
         ms = ctypes.c_double(0.0)
         n = ctypes.c_int(0)
         _check(self.lib.ww_profile_read(self.ptr, phase, ctypes.byref(ms), ctypes.byref(n)))
@@ -196,6 +205,13 @@ class Context:
         _check(self.lib.shoot_adjoint(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
                                       int(ckpt_every), _ptr(grad), ctypes.byref(dfdT), ctypes.byref(f)))
         return dict(grad=grad, dfdT=dfdT.value, f=f.value)
+
+
+def shoot(ctx: Context, params: torch.Tensor, T: float, nsteps: int, jacobian: bool = True):
+    """(r, J, drdT, f) of one shoot_eval: r = phi(T/4)/sqrt(N), J its Jacobian in the
+    parameters (None when jacobian=False), drdT = dr/dT, f = r.r/2."""
+    out = ctx.shoot_eval(params, T, nsteps, jacobian=jacobian, drdT=True)
+    return out["r"], out["J"], out["drdT"], out["f"]
 
 
 def to_dev(a, device="cuda") -> torch.Tensor:
@@ -220,7 +236,8 @@ def shoot_eval_batch(contexts, params, T, nsteps, jacobian=True, drdT=True):
         Jp[i] = Jc.data_ptr() if jacobian else None
         dp[i] = d.data_ptr() if drdT else None
     cp = VP(*[c.ptr.value for c in contexts])
-    pp = VP(*[p.contiguous().data_ptr() for p in params])
+    pc = [p.contiguous() for p in params]   # held until the call has synchronised
+    pp = VP(*[p.data_ptr() for p in pc])
     Ta = (ctypes.c_double * n)(*[float(t) for t in T])
     Na = (ctypes.c_int * n)(*[int(k) for k in nsteps])
     fa = (ctypes.c_double * n)()

@@ -69,3 +69,29 @@ def test_batch_rejects_repeated_context():
     with pytest.raises(ww.WWError) as ei:
         ww.shoot_eval_batch([c, c], [p, p], [w.T, w.T], [2, 2])
     assert ei.value.name == "WW_EINVAL"
+
+
+def test_batch_non_contiguous_params_and_shoot_tuple():
+    """Parameter views that are not contiguous are copied and kept alive for the call;
+    ww.shoot returns (r, J, drdT, f) of shoot_eval."""
+    ww, torch = _ww()
+    ws = _instances()[:2]
+    ctxs, views, plain = [], [], []
+    for w in ws:
+        c = ww.Context(n_max=max(64, w.N), r_max=w.M + 1, stream=torch.cuda.Stream())
+        c.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        ctxs.append(c)
+        pd = ww.to_dev(w.params)
+        views.append(torch.stack([pd, pd], dim=1)[:, 0])   # stride 2
+        plain.append(pd)
+    assert not views[0].is_contiguous()
+    torch.cuda.synchronize()
+    ov = ww.shoot_eval_batch(ctxs, views, [w.T for w in ws], [w.nsteps for w in ws])
+    op = ww.shoot_eval_batch(ctxs, plain, [w.T for w in ws], [w.nsteps for w in ws])
+    torch.cuda.synchronize()
+    for a, b in zip(ov, op):
+        for k in ("r", "J", "drdT"):
+            assert torch.equal(a[k], b[k])
+    r, J, drdT, f = ww.shoot(ctxs[0], plain[0], ws[0].T, ws[0].nsteps)
+    torch.cuda.synchronize()
+    assert torch.equal(r, op[0]["r"]) and torch.equal(J, op[0]["J"]) and f == op[0]["f"]
