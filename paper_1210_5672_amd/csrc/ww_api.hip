@@ -120,6 +120,8 @@ static int dalloc(ww_ctx* c, void** p, size_t bytes) {
 // circulant and spectral tables for grid size N (host-computed in double)
 static int set_tables(ww_ctx* c, int N) {
   if (c->tables_N == N) return 0;
+  // queued work of the previous grid may still read the tables
+  HIPCHK(hipStreamSynchronize(c->stream));
   std::vector<double> co(N), si(N), c0(N), sg(N);
   std::vector<cplx> tw(N);
   const double two_pi = 2.0 * M_PI;
@@ -181,7 +183,16 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   if (r_max < 1 || r_max > 4096) return fail(WW_EINVAL, "r_max out of range");
   if (flags & ~WW_MIXED) return fail(WW_EINVAL, "unknown flags");
   ww_ctx* c = new ww_ctx();
-  HIPCHK(hipGetDevice(&c->dev));
+  // a failure after this point releases what was created so far
+#define CCHK(x)                                                                        \
+  do {                                                                                 \
+    const hipError_t e_ = (x);                                                         \
+    if (e_ != hipSuccess) {                                                            \
+      ww_destroy(c);                                                                   \
+      return fail(WW_EHIP, std::string(#x) + ": " + hipGetErrorString(e_));             \
+    }                                                                                  \
+  } while (0)
+  CCHK(hipGetDevice(&c->dev));
   c->stream = (hipStream_t)hip_stream;
   c->flags = flags;
   c->n_max = n_max;
@@ -263,12 +274,12 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->fdev, 64);
   AL(c->status, 64);
 #undef AL
-  HIPCHK(hipMemset(c->status, 0, 64));
-  HIPCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+  CCHK(hipMemset(c->status, 0, 64));
+  CCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
+  CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   for (int i = 0; i < 16; ++i) {
-    HIPCHK(hipEventCreateWithFlags(&c->evB[i], hipEventDisableTiming));
-    HIPCHK(hipEventCreateWithFlags(&c->evC[i], hipEventDisableTiming));
+    CCHK(hipEventCreateWithFlags(&c->evB[i], hipEventDisableTiming));
+    CCHK(hipEventCreateWithFlags(&c->evC[i], hipEventDisableTiming));
   }
   {
     const char* ng = std::getenv("WW_NO_GRAPH");
@@ -280,22 +291,23 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   }
   // kernels whose dynamic LDS can exceed the default 64 KiB
   const int big = 160 * 1024;
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_init<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_final<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_gemm_part<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_init<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_blu_final<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_gemm_part<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_base_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_col_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_adj_pre, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_adj_mid, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  HIPCHK(hipFuncSetAttribute((const void*)k_adj_step, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_blu_init<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_blu_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_blu_final<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_gemm_part<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_blu_init<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_blu_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_blu_final<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_gemm_part<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_base_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_col_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_adj_pre, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_adj_mid, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_adj_step, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+#undef CCHK
   *out = c;
   return 0;
 }
@@ -643,6 +655,7 @@ extern "C" {
 
 int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   if (!c || !surface) return fail(WW_EINVAL, "null argument");
+  c->dtn_ready = false;   // until this surface is factored
   int rc;
   if ((rc = set_grid(c, N, h))) return rc;
   c->tau = tau;
@@ -655,8 +668,8 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   if ((rc = enqueue_assemble_lu(c, fac_default(c)))) return rc;
   int st = 0;
   if ((rc = read_status(c, &st))) return rc;
-  c->dtn_ready = true;
   if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
+  c->dtn_ready = true;
   return 0;
 }
 
@@ -724,6 +737,7 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
   if (M < 0 || M + 1 > c->r_max) return fail(WW_EINVAL, "M + 1 must be <= r_max");
   int rc;
   if ((rc = set_grid(c, N, h))) return rc;
+  c->dtn_ready = false;   // the grid of a previous dtn_setup is gone
   c->tau = tau;
   c->g = g;
   c->M = M;
@@ -879,12 +893,14 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
   if (c->ckpt_cap < (size_t)(nseg + 1) * n2) {
     if (c->ckpt) HIPCHK(hipFree(c->ckpt));
     c->ckpt = nullptr;
+    c->ckpt_cap = 0;
     HIPCHK(hipMalloc(&c->ckpt, (size_t)(nseg + 1) * n2 * 8));
     c->ckpt_cap = (size_t)(nseg + 1) * n2;
   }
   if (c->seg_cap < nslot * slot) {
     if (c->seg) HIPCHK(hipFree(c->seg));
     c->seg = nullptr;
+    c->seg_cap = 0;
     HIPCHK(hipMalloc(&c->seg, nslot * slot * 8));
     c->seg_cap = nslot * slot;
   }

@@ -165,10 +165,9 @@ class Context:
     def shoot_setup(self, N, h, tau, g, basis: torch.Tensor, q_fixed: torch.Tensor | None = None):
         """basis: (2N, M) tensor (column k = eta part; phi part)."""
         M = basis.shape[1]
-        bcm = basis.t().contiguous()
-        _check(self.lib.shoot_setup(self.ptr, N, float(h), float(tau), float(g), _ptr(bcm),
-                                    _ptr(q_fixed.contiguous()) if q_fixed is not None else None, M))
-        self._basis = bcm
+        bcm = self._keep(basis.t().contiguous())
+        qf = self._keep(q_fixed.contiguous()) if q_fixed is not None else None
+        _check(self.lib.shoot_setup(self.ptr, N, float(h), float(tau), float(g), _ptr(bcm), _ptr(qf), M))
         self.N, self.M = N, M
 
     def shoot_eval(self, params: torch.Tensor, T: float, nsteps: int, jacobian: bool = True,

@@ -132,6 +132,33 @@ def test_error_paths_on_gpu():
     assert ei.value.name == "WW_ENOSETUP"
 
 
+def test_dtn_factors_invalidated_by_a_new_grid_or_a_failed_setup():
+    """Factors belong to the surface and grid of the last successful dtn_setup: a
+    shoot_setup on another grid, or a dtn_setup that fails its domain check, leaves
+    dtn_solve_multi with nothing to solve (WW_ENOSETUP), and a new dtn_setup restores it."""
+    ww, torch = _ww()
+    N = 64
+    eta = W.random_surface(N, seed=3, amp=0.05)
+    rhs = W.random_rhs(N, 2, seed=4)
+    ctx = ww.Context(n_max=N, r_max=3)
+    ctx.dtn_setup(ww.to_dev(eta), 1.0)
+    ctx.dtn_solve_multi(ww.to_dev(rhs))
+    ctx.shoot_setup(32, 1.0, 0.0, 1.0, ww.to_dev(W.cosine_basis(32, 2)))
+    with pytest.raises(ww.WWError) as ei:
+        ctx.dtn_solve_multi(ww.to_dev(rhs))
+    assert ei.value.name == "WW_ENOSETUP"
+    ctx.dtn_setup(ww.to_dev(eta), 1.0)
+    got = ctx.dtn_solve_multi(ww.to_dev(rhs)).cpu().numpy()
+    ref, _ = O.DtN(eta, 1.0).apply(rhs)
+    assert relerr(got, ref) < TOL
+    with pytest.raises(ww.WWError) as ei:      # surface through the bottom
+        ctx.dtn_setup(torch.full((N,), -2.0, dtype=torch.float64, device="cuda"), 1.0)
+    assert ei.value.name == "WW_EDOMAIN"
+    with pytest.raises(ww.WWError) as ei:
+        ctx.dtn_solve_multi(ww.to_dev(rhs))
+    assert ei.value.name == "WW_ENOSETUP"
+
+
 def test_unstable_step_reports_nonfinite():
     """6 steps put the fastest filtered mode outside the stability region: the march
     blows up and the library reports WW_ENONFINITE (values only; no kernel faults)."""
