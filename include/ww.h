@@ -40,8 +40,11 @@ typedef struct ww_ctx ww_ctx;
 #define WW_EHIP (-3)       /* HIP runtime failure; the message carries the HIP error string */
 #define WW_EDOMAIN (-4)    /* finite depth with surface height h + eta <= 0 somewhere */
 #define WW_ENONFINITE (-5) /* NaN or Inf in the marched state */
-#define WW_EPIVOT (-6)     /* a pivot of the unpivoted LU fell below the guard */
-#define WW_EREFINE (-7)    /* mixed precision: refinement did not reach its tolerance */
+#define WW_EPIVOT (-6)     /* a pivot fell below the guard: of the unpivoted LU in a
+                              WW_STRICT context, else of the partially pivoted fallback
+                              (A numerically singular) */
+#define WW_EREFINE (-7)    /* mixed precision, WW_STRICT context: refinement did not reach
+                              its tolerance (without WW_STRICT the FP64 fallback runs) */
 
 /* context flags */
 #define WW_FP64 0u         /* LU, triangular solves, everything in FP64 */
@@ -51,7 +54,26 @@ typedef struct ww_ctx ww_ctx;
                               solve, which then fails the test), then the FP64
                               residual of the final solution must be at most 2^-43 of
                               the right-hand side in every column (max norm), else
-                              WW_EREFINE */
+                              the call is redone with FP64 factors (WW_FB_FP64), or
+                              fails with WW_EREFINE in a WW_STRICT context */
+#define WW_STRICT 2u       /* no fallbacks: report WW_EPIVOT / WW_EREFINE instead */
+
+/*
+ * Fallbacks.  The block LU of A runs without row interchanges (A = I/2 + K/N is
+ * diagonally dominant for graph surfaces; Sec. 3.3 does not discuss pivoting) behind a
+ * guard on its pivots: every pivot must be at least 1e-8 in magnitude (environment
+ * WW_PIVOT_GUARD, read by ww_create, replaces that bound for the unpivoted LU only; a
+ * test hook for the fallback path).  When a pivot falls below the guard, the call is
+ * redone with partial pivoting: Gaussian elimination with row interchanges (largest
+ * magnitude in the column) fixes a row order P on the GPU, the block LU factors P A in
+ * FP64, and every solve gathers its right-hand side by P (the adjoint scatters its
+ * transposed solve by P^T).  A march is redone whole, without a step graph, on one
+ * stream.  If a pivot of the pivoted factorisation is also below 1e-8 the call fails
+ * with WW_EPIVOT.
+ */
+#define WW_FB_PIVOTED 1u   /* the results come from partially pivoted FP64 factors */
+#define WW_FB_FP64 2u      /* the results come from FP64 factors after the mixed-precision
+                              refinement test failed */
 
 /*
  * ww_create: allocate a context whose device workspace serves every N <= n_max and
@@ -77,7 +99,9 @@ int ww_set_tableau(ww_ctx *ctx, int s, const double *a, const double *b, const d
  * `surface` (device, N), assemble the collocation matrices A = I/2 + K/N and
  * Gm = G/N of the second-kind boundary integral equation and of the normal-derivative
  * formula, and factor A once (LU, Sec. 3.3).  `tau` is stored for reference only (it
- * does not enter A or Gm).  Synchronises to check the pivot guard.
+ * does not enter A or Gm).  Synchronises to check the pivot guard; a pivot below it
+ * refactors with partial pivoting (WW_FB_PIVOTED).  The factors serve dtn_solve_multi
+ * until the next dtn_setup, shoot_setup, shoot_eval or shoot_adjoint on the context.
  * Errors: WW_EINVAL, WW_EDOMAIN (finite depth, h + eta <= 0), WW_EPIVOT, WW_EHIP.
  */
 int dtn_setup(ww_ctx *ctx, const double *surface, double h, double tau, int N);
@@ -88,8 +112,9 @@ int dtn_setup(ww_ctx *ctx, const double *surface, double h, double tau, int N);
  * form gamma = d mu / d alpha and return the Dirichlet-Neumann output
  * G psi = (1/2) H gamma + Gm gamma in `dtn_out` (device, N x nrhs, ld N).  `mu_out`
  * (device, N x nrhs, or NULL) receives mu.  nrhs <= r_max.  Stream-ordered, except in a
- * WW_MIXED context, where it synchronises to report the refinement test.
- * Errors: WW_ENOSETUP, WW_EINVAL, WW_EREFINE (mixed mode), WW_EHIP.
+ * WW_MIXED context, where it synchronises to check the refinement test; a failed test
+ * refactors A in FP64 (kept for later calls) and solves again (WW_FB_FP64).
+ * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_EREFINE (WW_STRICT), WW_EHIP.
  */
 int dtn_solve_multi(ww_ctx *ctx, const double *rhs, int nrhs, double *dtn_out, double *mu_out);
 
@@ -112,8 +137,10 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  *   J    (N x M)  J_ik = phidot_k(alpha_i, T/4) / sqrt(N), or NULL (base only, R = 1)
  *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
  *   f    (host)   f = r.r / 2, or NULL
- * Synchronises when f is requested and to check the status flags.
- * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EREFINE (mixed mode), WW_EHIP.
+ * Synchronises to check the status flags.  A pivot below the guard anywhere in the
+ * march redoes it with partial pivoting; a failed refinement test (WW_MIXED) redoes it
+ * with FP64 factors (see ww_fallbacks).
+ * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EREFINE (WW_STRICT), WW_EHIP.
  */
 int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *r, double *J,
                double *drdT, double *f);
@@ -128,8 +155,9 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
  * GPU overlap the instances; a single instance uses the two-stream graph of shoot_eval.  Per-instance arrays: params[i] (device),
  * T[i], nsteps[i] (host), r[i] (device), J[i] (device or NULL; J may be NULL),
  * drdT[i] (device or NULL; drdT may be NULL), f[i] (host; f may be NULL).
- * Results are identical to n_inst separate shoot_eval calls.  Synchronises every
- * context's stream; returns the first instance error.
+ * Results are identical to n_inst separate shoot_eval calls: an instance whose march
+ * needs a fallback is redone alone as shoot_eval would.  Synchronises every context's
+ * stream; returns the first instance error.
  */
 int shoot_eval_batch(int n_inst, ww_ctx *const *ctx, const double *const *params, const double *T,
                      const int *nsteps, double *const *r, double *const *J, double *const *drdT,
@@ -144,7 +172,7 @@ int shoot_eval_batch(int n_inst, ww_ctx *const *ctx, const double *const *params
  * workspace for the checkpoints and for the factors of one segment (ckpt_every x stages
  * x 3 Np^2 doubles) is allocated on the first call and kept until ww_destroy.
  * grad: device M.  dfdT (host or NULL): df/dT = r . drdT.  f (host or NULL).
- * Synchronises.
+ * Synchronises.  A pivot below the guard redoes the call with partial pivoting.
  * Errors: WW_ENOSETUP, WW_EINVAL, WW_EPIVOT, WW_ENONFINITE, WW_EHIP.
  */
 int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int ckpt_every,
@@ -163,6 +191,14 @@ int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int c
  */
 int ww_profile(ww_ctx *ctx, int enable);
 int ww_profile_read(ww_ctx *ctx, int phase, double *avg_ms, int *count);
+
+/*
+ * ww_fallbacks: in *bits, the fallbacks behind the results of the last successful
+ * dtn_setup, dtn_solve_multi, shoot_eval or shoot_adjoint on this context (for
+ * shoot_eval_batch: of that context's instance): WW_FB_PIVOTED, WW_FB_FP64, or 0 when
+ * the results come from the context's own path.  Host only.  Errors: WW_EINVAL.
+ */
+int ww_fallbacks(ww_ctx *ctx, unsigned *bits);
 
 /* thread-local message of the last failure on this thread ("" if none) */
 const char *ww_last_error(void);

@@ -100,6 +100,18 @@ struct ww_ctx {
   hipStream_t cap_stream = nullptr;
   hipGraphExec_t step_exec = nullptr;
   int gN = -1, gM = -1, gcols = -1, gnst = -1, gtwo = -1;
+  unsigned gfb = ~0u;
+  // fallbacks: fb is the mode the factor sets are built in (WW_FB_* bits), fb_last what
+  // the results of the last call came from; guard is the unpivoted LU's pivot bound
+  unsigned fb = 0, fb_last = 0;
+  double guard = 1e-8;
+  // partial-pivoting buffers, allocated on the first fallback: row order, elimination
+  // workspace (Np x Np), gathered right-hand sides (Np x r_max); the adjoint keeps one
+  // row order per stored stage
+  int* perm = nullptr;
+  double *pw = nullptr, *pb = nullptr;
+  int* seg_perm = nullptr;
+  size_t seg_perm_cap = 0;
 };
 
 static bool valid_n(int N) {
@@ -181,7 +193,7 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   *out = nullptr;
   if (!valid_n(n_max) || n_max > WW_NMAX) return fail(WW_EINVAL, "n_max must be even, 2^a 3^b, 16..2048");
   if (r_max < 1 || r_max > 4096) return fail(WW_EINVAL, "r_max out of range");
-  if (flags & ~WW_MIXED) return fail(WW_EINVAL, "unknown flags");
+  if (flags & ~(WW_MIXED | WW_STRICT)) return fail(WW_EINVAL, "unknown flags");
   ww_ctx* c = new ww_ctx();
   // a failure after this point releases what was created so far
 #define CCHK(x)                                                                        \
@@ -288,6 +300,11 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->overlap = !(no && no[0] == '1');
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
+    const char* pg = std::getenv("WW_PIVOT_GUARD");
+    if (pg) {
+      const double v = std::atof(pg);
+      if (std::isfinite(v) && v >= 0.0) c->guard = v;
+    }
   }
   // kernels whose dynamic LDS can exceed the default 64 KiB
   const int big = 160 * 1024;
@@ -319,6 +336,7 @@ void ww_destroy(ww_ctx* c) {
   if (c->ckpt) (void)hipFree(c->ckpt);
   if (c->seg) (void)hipFree(c->seg);
   if (c->adj) (void)hipFree(c->adj);
+  if (c->seg_perm) (void)hipFree(c->seg_perm);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->side) (void)hipStreamDestroy(c->side);
   for (int i = 0; i < 16; ++i) {
@@ -362,7 +380,7 @@ static size_t fft_lds_bytes(int N, int nbuf) { return (size_t)nbuf * N * sizeof(
 static const size_t TILE_BYTES = (size_t)TILE_DBL * 8;
 
 template <typename T>
-static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, T* Xr, T* Zr) {
+static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, T* Xr, T* Zr, double guard) {
   BluBufs<T> b;
   b.A = A;
   b.X = X;
@@ -373,7 +391,7 @@ static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, T* Xr, T* Zr
   b.Zr = Zr;
   b.status = c->status;
   b.Np = c->Np;
-  b.pivguard = 1e-8;
+  b.pivguard = guard;
   return b;
 }
 
@@ -406,6 +424,12 @@ static int prof_mark(ww_ctx* c, int phase, int which) {
 }
 
 static bool mixed(const ww_ctx* c) { return (c->flags & WW_MIXED) != 0; }
+static bool strict(const ww_ctx* c) { return (c->flags & WW_STRICT) != 0; }
+// FP32 factors only on the context's own path (every fallback factors in FP64)
+static bool use32(const ww_ctx* c) { return mixed(c) && c->fb == 0; }
+static bool pivoted(const ww_ctx* c) { return (c->fb & WW_FB_PIVOTED) != 0; }
+// pivot bound of the pivoted factorisation (near singularity)
+static const double PIVOTED_GUARD = 1e-8;
 
 // The FP64 factor set of one stage: A (overwritten by the Schur complements), Gm, the
 // block-triangular inverses X, Z, and the scratch V, Dinv.  The adjoint keeps one set
@@ -420,15 +444,16 @@ struct Fac {
   // FP32 factors; Ar: FP64 A for the mixed-mode residuals)
   double *Xr, *Zr, *Gmr, *Ar;
   float *X32r, *Z32r;
+  int* perm;   // partial-pivoting row order of this set, or null (no interchanges)
 };
 // factor set of parity `p`; `cols` selects the column chain's GEMM partials
 static Fac fac_set(ww_ctx* c, int p, bool cols) {
   Fac F;
   if (p == 0) {
-    F = Fac{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, mixed(c), c->A32, c->X32, c->Z32, c->V32, c->Dinv32, c->aux,
+    F = Fac{c->A, c->Gm, c->Xi, c->Zi, c->Vi, c->Dinv, use32(c), c->A32, c->X32, c->Z32, c->V32, c->Dinv32, c->aux,
             nullptr};
   } else {
-    F = Fac{c->A_1, c->Gm_1, c->Xi_1, c->Zi_1, c->Vi_1, c->Dinv_1, mixed(c), c->A32_1, c->X32_1, c->Z32_1, c->V32_1,
+    F = Fac{c->A_1, c->Gm_1, c->Xi_1, c->Zi_1, c->Vi_1, c->Dinv_1, use32(c), c->A32_1, c->X32_1, c->Z32_1, c->V32_1,
             c->Dinv32_1, c->aux_1, nullptr};
   }
   F.part = cols ? c->part_c : c->part;
@@ -438,7 +463,45 @@ static Fac fac_set(ww_ctx* c, int p, bool cols) {
   F.Ar = p ? c->Ar_1 : c->Ar;
   F.X32r = p ? c->X32r_1 : c->X32r;
   F.Z32r = p ? c->Z32r_1 : c->Z32r;
+  F.perm = pivoted(c) ? c->perm : nullptr;
   return F;
+}
+
+// buffers of the pivoting fallback (first use)
+static int ensure_pivot_buffers(ww_ctx* c) {
+  if (c->perm) return 0;
+  int rc;
+  const size_t np = c->np_max;
+  if ((rc = dalloc(c, (void**)&c->perm, np * sizeof(int)))) return rc;
+  if ((rc = dalloc(c, (void**)&c->pw, np * np * 8))) return rc;
+  return dalloc(c, (void**)&c->pb, np * (size_t)c->r_max * 8);
+}
+
+// Row order of partial pivoting for the assembled A of F (column-major, ld Np), then
+// A := P A.  Elimination runs on a copy in the workspace; the padding rows keep their
+// place (the padding of A is the identity).
+static int enqueue_pivot_order(ww_ctx* c, const Fac& F) {
+  const int N = c->N, Np = c->Np;
+  const int cblk = (int)std::min<size_t>(((size_t)Np * Np + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pad_copy, dim3(cblk), dim3(256), 0, c->stream, F.A, Np, c->pw, Np, Np, Np, Np);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_iota, dim3((Np + 255) / 256), dim3(256), 0, c->stream, F.perm, Np);
+  LAUNCHCHK();
+  for (int k = 0; k < N; ++k) {
+    hipLaunchKernelGGL(k_plu_pivot, dim3(1), dim3(PLU_NT), 0, c->stream, c->pw, Np, N, k, F.perm, PIVOTED_GUARD,
+                       c->status);
+    LAUNCHCHK();
+    const int n = N - k - 1;
+    if (n > 0) {
+      hipLaunchKernelGGL(k_plu_update, dim3((n + 63) / 64, (n + 15) / 16), dim3(256), 0, c->stream, c->pw, Np, N, k);
+      LAUNCHCHK();
+    }
+  }
+  hipLaunchKernelGGL(k_permute_rows, dim3(cblk), dim3(256), 0, c->stream, F.A, c->pw, F.perm, Np, Np, 0);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_pad_copy, dim3(cblk), dim3(256), 0, c->stream, c->pw, Np, F.A, Np, Np, Np, Np);
+  LAUNCHCHK();
+  return 0;
 }
 static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 
@@ -452,8 +515,12 @@ static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   LAUNCHCHK();
   int rc;
   if ((rc = prof_mark(c, 0, 0))) return rc;
-  if (F.use32) rc = enqueue_blu<float>(c, blu_bufs<float>(c, F.A32, F.X32, F.Z32, F.V32, F.Dinv32, F.X32r, F.Z32r));
-  else rc = enqueue_blu<double>(c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv, F.Xr, F.Zr));
+  if (F.perm && (rc = enqueue_pivot_order(c, F))) return rc;
+  if (F.use32)
+    rc = enqueue_blu<float>(c, blu_bufs<float>(c, F.A32, F.X32, F.Z32, F.V32, F.Dinv32, F.X32r, F.Z32r, c->guard));
+  else
+    rc = enqueue_blu<double>(
+        c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv, F.Xr, F.Zr, F.perm ? PIVOTED_GUARD : c->guard));
   if (rc) return rc;
   return prof_mark(c, 0, 1);
 }
@@ -498,6 +565,13 @@ static const double REFINE_TOL = 1.1368683772161603e-13;
 //        FP64 matrix),  X += Z32 (r + X32 r)  (FP32 factors, FP64 accumulation).
 static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* X, double* Rs, int R) {
   int rc;
+  if (F.perm) {   // P A = Lt Ut: solve with P B
+    const size_t n = (size_t)c->Np * R;
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_permute_rows, dim3(blocks), dim3(256), 0, c->stream, B, c->pb, F.perm, c->Np, R, 0);
+    LAUNCHCHK();
+    B = c->pb;
+  }
   if (!F.use32) {
     if ((rc = enqueue_gemm<double>(c, F.part, F.X, F.Xr, 1, B, B, 1.0, Y, R))) return rc;
     return enqueue_gemm<double>(c, F.part, F.Z, F.Zr, 2, Y, nullptr, 1.0, X, R);
@@ -605,7 +679,7 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
 // coefficients live in device memory, so T and the parameters may change freely.
 static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   if (c->step_exec && c->gN == c->N && c->gM == c->M && c->gcols == (int)cols && c->gnst == c->nst &&
-      c->gtwo == (int)two_streams)
+      c->gtwo == (int)two_streams && c->gfb == c->fb)
     return 0;
   if (c->step_exec) {
     HIPCHK(hipGraphExecDestroy(c->step_exec));
@@ -631,6 +705,7 @@ static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   c->gcols = (int)cols;
   c->gtwo = (int)two_streams;
   c->gnst = c->nst;
+  c->gfb = c->fb;
   return 0;
 }
 
@@ -639,6 +714,26 @@ static int read_status(ww_ctx* c, int* st) {
   HIPCHK(hipMemcpy(st, c->status, sizeof(int), hipMemcpyDeviceToHost));
   HIPCHK(hipMemset(c->status, 0, sizeof(int)));
   return 0;
+}
+
+static const char* const MSG_PIVOT = "pivot below the guard (unpivoted LU, WW_STRICT)";
+static const char* const MSG_PIVOT2 = "pivot below the guard also with partial pivoting (A numerically singular)";
+static const char* const MSG_REFINE = "mixed precision: relative residual of the refined solution above 2^-43";
+
+// Assemble and factor the DtN matrices of the surface prepared in aux, with the
+// pivoting fallback when a pivot falls below the guard.
+static int dtn_factor(ww_ctx* c) {
+  for (;;) {
+    int rc;
+    if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
+    if ((rc = enqueue_assemble_lu(c, fac_default(c)))) return rc;
+    int st = 0;
+    if ((rc = read_status(c, &st))) return rc;
+    if (!(st & (1 | 8))) return 0;
+    if (pivoted(c)) return fail(WW_EPIVOT, MSG_PIVOT2);
+    if (strict(c)) return fail(WW_EPIVOT, MSG_PIVOT);
+    c->fb |= WW_FB_PIVOTED | WW_FB_FP64;
+  }
 }
 
 static int check_domain(ww_ctx* c, const double* surface) {
@@ -656,6 +751,7 @@ extern "C" {
 int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   if (!c || !surface) return fail(WW_EINVAL, "null argument");
   c->dtn_ready = false;   // until this surface is factored
+  c->fb = 0;
   int rc;
   if ((rc = set_grid(c, N, h))) return rc;
   c->tau = tau;
@@ -665,11 +761,9 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 4), c->stream, c->ydtn, c->K, c->Ys,
                      c->coef, 0, (size_t)0, c->aux, c->n_max, c->rhs0, c->Np, c->tw, N, c->hsurf);
   LAUNCHCHK();
-  if ((rc = enqueue_assemble_lu(c, fac_default(c)))) return rc;
-  int st = 0;
-  if ((rc = read_status(c, &st))) return rc;
-  if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
+  if ((rc = dtn_factor(c))) return rc;
   c->dtn_ready = true;
+  c->fb_last = c->fb;
   return 0;
 }
 
@@ -683,19 +777,26 @@ int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, dou
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs, N, c->Psi, Np, N, Np, nrhs);
   LAUNCHCHK();
   int rc;
-  if ((rc = enqueue_dtn_cols(c, fac_default(c), c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, nrhs)))
-    return rc;
+  for (;;) {
+    if ((rc = enqueue_dtn_cols(c, fac_default(c), c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, nrhs)))
+      return rc;
+    if (!use32(c)) break;
+    int st = 0;   // the refinement test of the mixed path
+    if ((rc = read_status(c, &st))) return rc;
+    if (!(st & 4)) break;
+    if (strict(c)) return fail(WW_EREFINE, MSG_REFINE);
+    c->fb |= WW_FB_FP64;   // refactor in FP64 (kept for the later calls) and solve again
+    c->dtn_ready = false;
+    if ((rc = dtn_factor(c))) return rc;
+    c->dtn_ready = true;
+  }
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Gpsi, Np, dtn_out, N, Np, N, nrhs);
   LAUNCHCHK();
   if (mu_out) {
     hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Mu, Np, mu_out, N, Np, N, nrhs);
     LAUNCHCHK();
   }
-  if (mixed(c)) {   // report the refinement test
-    int st = 0;
-    if ((rc = read_status(c, &st))) return rc;
-    if (st & 4) return fail(WW_EREFINE, "mixed precision: relative residual of the refined solution above 2^-43");
-  }
+  c->fb_last = c->fb;
   return 0;
 }
 
@@ -754,6 +855,9 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
 
 }  // extern "C"
 
+// the pivoting fallback launches two kernels per column of A and runs without a graph
+static bool graphed(const ww_ctx* c) { return c->use_graph && !pivoted(c); }
+
 // shoot_eval in three parts so that shoot_eval_batch can interleave instances:
 // prepare (coefficients, initial state, step graph), one step, finish (outputs).
 static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, bool cols, bool two_streams) {
@@ -778,12 +882,12 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
   LAUNCHCHK();
-  if (c->use_graph) return ensure_step_graph(c, cols, two_streams);
+  if (graphed(c)) return ensure_step_graph(c, cols, two_streams);
   return 0;
 }
 
 static int shoot_one_step(ww_ctx* c, bool cols, bool two_streams) {
-  if (c->use_graph) {
+  if (graphed(c)) {
     HIPCHK(hipGraphLaunch(c->step_exec, c->stream));
     return 0;
   }
@@ -813,13 +917,52 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
   return 0;
 }
 
-static int shoot_status(ww_ctx* c) {
-  int st = 0, rc;
-  if ((rc = read_status(c, &st))) return rc;
-  if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
-  if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
-  if (st & 4) return fail(WW_EREFINE, "mixed precision: relative residual of the refined solution above 2^-43");
+// Status bits of a march: 1 pivot below the guard (unpivoted LU), 8 pivot below the
+// guard (pivoted LU), 2 non-finite state, 4 failed refinement test.  The fallback that
+// a redo of the call takes, or 0.
+static unsigned next_fallback(const ww_ctx* c, int st) {
+  if (strict(c)) return 0;
+  if ((st & (1 | 8)) && !pivoted(c)) return WW_FB_PIVOTED | WW_FB_FP64;
+  if ((st & 4) && !(c->fb & WW_FB_FP64)) return WW_FB_FP64;
   return 0;
+}
+
+static int status_error(const ww_ctx* c, int st) {
+  if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
+  if (st & (1 | 8)) return fail(WW_EPIVOT, pivoted(c) ? MSG_PIVOT2 : MSG_PIVOT);
+  if (st & 4) return fail(WW_EREFINE, MSG_REFINE);
+  return 0;
+}
+
+// one march in the current fallback mode; *st receives the status bits
+static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
+                     double* f, int* st) {
+  const bool cols = (J != nullptr) && c->M > 0;
+  const bool two = c->overlap && !pivoted(c);
+  int rc;
+  if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
+  if ((rc = shoot_prepare(c, params, T, nsteps, cols, two))) return rc;
+  for (int n = 0; n < nsteps; ++n)
+    if ((rc = shoot_one_step(c, cols, two))) return rc;
+  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
+  return read_status(c, st);
+}
+
+// marches from fallback mode fb0 until the status needs no further fallback
+static int shoot_eval_fb(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
+                         double* f, unsigned fb0) {
+  c->fb = fb0;
+  for (;;) {
+    int st = 0, rc;
+    if ((rc = shoot_run(c, params, T, nsteps, r, J, drdT, f, &st))) return rc;
+    const unsigned nf = next_fallback(c, st);
+    if (!nf) {
+      if ((rc = status_error(c, st))) return rc;
+      c->fb_last = c->fb;
+      return 0;
+    }
+    c->fb |= nf;
+  }
 }
 
 extern "C" {
@@ -827,13 +970,7 @@ extern "C" {
 int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
                double* f) {
   if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
-  const bool cols = (J != nullptr) && c->M > 0;
-  int rc;
-  if ((rc = shoot_prepare(c, params, T, nsteps, cols, c->overlap))) return rc;
-  for (int n = 0; n < nsteps; ++n)
-    if ((rc = shoot_one_step(c, cols, c->overlap))) return rc;
-  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
-  return shoot_status(c);
+  return shoot_eval_fb(c, params, T, nsteps, r, J, drdT, f, 0);
 }
 
 int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params, const double* T,
@@ -852,6 +989,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   const bool two = n_inst == 1 && ctx[0]->overlap;
   for (int i = 0; i < n_inst; ++i) {
     const bool cols = J && J[i] && ctx[i]->M > 0;
+    ctx[i]->fb = 0;
     if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols, two))) return rc;
     maxsteps = std::max(maxsteps, nsteps[i]);
   }
@@ -868,18 +1006,26 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   }
   int first_err = 0;
   for (int i = 0; i < n_inst; ++i) {
-    const int e = shoot_status(ctx[i]);
+    ww_ctx* c = ctx[i];
+    int st = 0, e;
+    if ((e = read_status(c, &st)) == 0) {
+      const unsigned nf = next_fallback(c, st);
+      if (nf)   // this instance alone, in its fallback mode
+        e = shoot_eval_fb(c, params[i], T[i], nsteps[i], r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr,
+                          f ? &f[i] : nullptr, nf);
+      else if ((e = status_error(c, st)) == 0)
+        c->fb_last = c->fb;
+    }
     if (e && !first_err) first_err = e;
   }
   return first_err;
 }
 
-int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckpt_every, double* grad,
-                  double* dfdT, double* f) {
-  if (!c || !grad || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
-  if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_adjoint before shoot_setup");
-  if (c->nst < 1) return fail(WW_EINVAL, "no tableau set");
-  if (nsteps < 1 || !std::isfinite(T) || ckpt_every < 1) return fail(WW_EINVAL, "nsteps, ckpt_every >= 1 required");
+}  // extern "C"
+
+// one adjoint evaluation in the current fallback mode; *stout receives the status bits
+static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, int ckpt_every, double* grad,
+                       double* dfdT, double* f, int* stout) {
   int rc;
   if ((rc = set_grid(c, c->shootN, c->shootH))) return rc;
   c->dtn_ready = false;
@@ -904,7 +1050,17 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
     HIPCHK(hipMalloc(&c->seg, nslot * slot * 8));
     c->seg_cap = nslot * slot;
   }
-  if (!c->adj) HIPCHK(hipMalloc(&c->adj, (size_t)(20 * 2 * c->n_max + 8 * c->np_max) * 8));
+  if (pivoted(c)) {
+    if ((rc = ensure_pivot_buffers(c))) return rc;
+    if (c->seg_perm_cap < nslot * c->np_max) {
+      if (c->seg_perm) HIPCHK(hipFree(c->seg_perm));
+      c->seg_perm = nullptr;
+      c->seg_perm_cap = 0;
+      HIPCHK(hipMalloc(&c->seg_perm, nslot * c->np_max * sizeof(int)));
+      c->seg_perm_cap = nslot * c->np_max;
+    }
+  }
+  if (!c->adj) HIPCHK(hipMalloc(&c->adj, (size_t)(20 * 2 * c->n_max + 9 * c->np_max) * 8));
   double* lam = c->adj;
   double* mu = lam + 2 * c->n_max;
   double* ups = mu + 2 * c->n_max;                 // 16 x 2N
@@ -919,6 +1075,7 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
   double* y2 = y1 + c->np_max;
   double* rv = y2 + c->np_max;       // r (N)
   double* dv = rv + c->n_max;        // drdT (N)
+  double* y2p = dv + c->n_max;       // P^T y2 (Np), pivoted factors
   auto slot_fac = [&](size_t k) {
     double* b = c->seg + k * slot;
     Fac F = fac_set(c, 0, false);
@@ -926,6 +1083,7 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
     F.X = b;
     F.Z = b + (size_t)Np * Np;
     F.use32 = false;
+    F.perm = pivoted(c) ? c->seg_perm + k * c->np_max : nullptr;
     return F;
   };
   auto slot_aux = [&](size_t k) { return c->seg + k * slot + (size_t)3 * Np * Np; };
@@ -1009,7 +1167,14 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
         LAUNCHCHK();
         hipLaunchKernelGGL(k_gemv_t, dim3(gblk), dim3(WW_NT), 0, c->stream, F.X, Np, 1, y1, y1, y2);
         LAUNCHCHK();
-        hipLaunchKernelGGL(k_adj_post, dim3((N + 255) / 256), dim3(256), 0, c->stream, y2, qv, e1, sa, N,
+        const double* yt = y2;   // A^{-T} zeta; with P A = Lt Ut it is P^T (Lt Ut)^{-T} zeta
+        if (F.perm) {
+          hipLaunchKernelGGL(k_permute_rows, dim3((Np + 255) / 256), dim3(256), 0, c->stream, y2, y2p, F.perm, Np, 1,
+                             1);
+          LAUNCHCHK();
+          yt = y2p;
+        }
+        hipLaunchKernelGGL(k_adj_post, dim3((N + 255) / 256), dim3(256), 0, c->stream, yt, qv, e1, sa, N,
                            ups + (size_t)s * ustride);
         LAUNCHCHK();
       }
@@ -1037,8 +1202,35 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
     for (int i = 0; i < N; ++i) acc += hr[i] * hd2[i];
     *dfdT = acc;
   }
-  if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
-  if (st & 1) return fail(WW_EPIVOT, "unpivoted LU: pivot below guard");
+  *stout = st;
+  return 0;
+}
+
+extern "C" {
+
+int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckpt_every, double* grad,
+                  double* dfdT, double* f) {
+  if (!c || !grad || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
+  if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_adjoint before shoot_setup");
+  if (c->nst < 1) return fail(WW_EINVAL, "no tableau set");
+  if (nsteps < 1 || !std::isfinite(T) || ckpt_every < 1) return fail(WW_EINVAL, "nsteps, ckpt_every >= 1 required");
+  c->fb = 0;
+  for (;;) {
+    int st = 0, rc;
+    if ((rc = adjoint_run(c, params, T, nsteps, ckpt_every, grad, dfdT, f, &st))) return rc;
+    const unsigned nf = next_fallback(c, st & ~4);   // FP64 factors throughout
+    if (!nf) {
+      if ((rc = status_error(c, st))) return rc;
+      c->fb_last = c->fb;
+      return 0;
+    }
+    c->fb |= nf;
+  }
+}
+
+int ww_fallbacks(ww_ctx* c, unsigned* bits) {
+  if (!c || !bits) return fail(WW_EINVAL, "null argument");
+  *bits = c->fb_last;
   return 0;
 }
 

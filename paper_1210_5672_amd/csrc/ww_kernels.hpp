@@ -893,6 +893,111 @@ __global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs<T> b) {
 }
 
 // -------------------------------------------------------------------------------------
+// Pivoting fallback.  The paper factors A without discussing pivoting (Sec. 3.3); A is
+// diagonally dominant for the surfaces it treats, and the block LU above runs without
+// interchanges behind a pivot guard.  When a pivot falls below the guard, Gaussian
+// elimination with partial pivoting (largest magnitude in the column, first row on
+// ties) fixes a row order P; the block LU then factors P A, whose elimination pivots
+// are the partial-pivoting ones, and every solve gathers its right-hand side by P.
+// Two launches per column of the leading N x N block of W (column-major, ld Np):
+// k_plu_pivot (one workgroup) picks the pivot, interchanges the two rows over all
+// columns, records the interchange in perm ((P A) row i = A row perm[i]) and forms the
+// multipliers; k_plu_update subtracts the rank-one update from the trailing block.
+// Status bit 8: the largest candidate of a column is below the guard.
+// -------------------------------------------------------------------------------------
+#define PLU_NT 1024
+__global__ __launch_bounds__(PLU_NT) void k_plu_pivot(double* __restrict__ W, int Np, int N, int k,
+                                                       int* __restrict__ perm, double guard, int* __restrict__ status) {
+  __shared__ double sv[PLU_NT / 64];
+  __shared__ int si[PLU_NT / 64];
+  __shared__ int sp;
+  double* col = W + (size_t)k * Np;
+  double bv = -1.0;
+  int bi = N;
+  for (int i = k + (int)threadIdx.x; i < N; i += PLU_NT) {   // rising rows: ties keep the first
+    const double v = fabs(col[i]);
+    if (v > bv) {
+      bv = v;
+      bi = i;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    const double ov = __shfl_xor(bv, off);
+    const int oi = __shfl_xor(bi, off);
+    if (ov > bv || (ov == bv && oi < bi)) {
+      bv = ov;
+      bi = oi;
+    }
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (lane == 0) {
+    sv[w] = bv;
+    si[w] = bi;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double v = sv[0];
+    int p = si[0];
+    for (int q = 1; q < PLU_NT / 64; ++q)
+      if (sv[q] > v || (sv[q] == v && si[q] < p)) {
+        v = sv[q];
+        p = si[q];
+      }
+    if (!(v >= guard)) atomicOr(status, 8);
+    if (p < k || p >= N) p = k;   // no finite candidate (NaN column): keep the order
+    sp = p;
+    if (p != k) {
+      const int t = perm[k];
+      perm[k] = perm[p];
+      perm[p] = t;
+    }
+  }
+  __syncthreads();
+  const int p = sp;
+  if (p != k)
+    for (int j = threadIdx.x; j < Np; j += PLU_NT) {
+      double* cj = W + (size_t)j * Np;
+      const double t = cj[k];
+      cj[k] = cj[p];
+      cj[p] = t;
+    }
+  __syncthreads();
+  const double piv = col[k];
+  for (int i = k + 1 + (int)threadIdx.x; i < N; i += PLU_NT) col[i] = col[i] / piv;
+}
+
+// W[i][j] -= W[i][k] W[k][j] for k < i, j < N: 64 rows x 16 columns per workgroup
+__global__ __launch_bounds__(256) void k_plu_update(double* __restrict__ W, int Np, int N, int k) {
+  const int i = k + 1 + blockIdx.x * 64 + (threadIdx.x & 63);
+  if (i >= N) return;
+  const double l = W[(size_t)k * Np + i];
+  const int j0 = k + 1 + blockIdx.y * 16 + (threadIdx.x >> 6) * 4;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int j = j0 + q;
+    if (j < N) W[(size_t)j * Np + i] -= l * W[(size_t)j * Np + k];
+  }
+}
+
+__global__ void k_iota(int* __restrict__ p, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = i;
+}
+
+// rows of an Np x ncols column-major array (ld Np) by perm: gather dst[i] = src[perm[i]]
+// (P x), or scatter dst[perm[i]] = src[i] (P^T x)
+__global__ void k_permute_rows(const double* __restrict__ src, double* __restrict__ dst, const int* __restrict__ perm,
+                               int Np, int ncols, int scatter) {
+  const size_t tot = (size_t)Np * ncols;
+  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < tot; idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t c = idx / Np;
+    const int i = (int)(idx - c * Np);
+    const int q = perm[i];
+    if (scatter) dst[c * Np + q] = src[c * Np + i];
+    else dst[c * Np + i] = src[c * Np + q];
+  }
+}
+
+// -------------------------------------------------------------------------------------
 // One right-hand side: y = add + sgn * M x over the 64-block range of `mode` (0 all,
 // 1 strictly lower, 2 upper incl. diagonal), from the row-major copy Mr (element type
 // T, accumulation in double).  One wave per row: contiguous row reads, eight loads in

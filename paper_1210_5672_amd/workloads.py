@@ -182,6 +182,14 @@ def random_surface(N: int, seed: int, amp: float = 0.05, kmax: int = 12) -> np.n
     return eta
 
 
+def steep_surface(N: int, amp: float = 0.15, k: int = 20) -> np.ndarray:
+    """Under-resolved steep surface amp cos(k a) + 0.02 sin(3 a): at N = 64 the slopes
+    reach 3 and A loses column dominance, so that elimination with partial pivoting
+    interchanges rows (the pivoting fallback's test input)."""
+    a = grid(N)
+    return amp * np.cos(k * a) + 0.02 * np.sin(3 * a)
+
+
 def random_rhs(N: int, R: int, seed: int) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.asfortranarray(rng.standard_normal((N, R)))

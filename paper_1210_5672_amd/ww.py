@@ -18,6 +18,9 @@ LIB_PATH = os.path.join(_HERE, "libwwdtn.so")
 
 WW_FP64 = 0
 WW_MIXED = 1
+WW_STRICT = 2
+WW_FB_PIVOTED = 1
+WW_FB_FP64 = 2
 
 _ERRORS = {
     -1: "WW_EINVAL", -2: "WW_ENOSETUP", -3: "WW_EHIP", -4: "WW_EDOMAIN",
@@ -26,7 +29,7 @@ _ERRORS = {
 
 EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_setup",
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
-           "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch"]
+           "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks"]
 
 
 class WWError(RuntimeError):
@@ -64,10 +67,11 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_eval_batch.restype = I
     lib.ww_profile.argtypes = [P, I]
     lib.ww_profile_read.argtypes = [P, I, DP, ctypes.POINTER(ctypes.c_int)]
+    lib.ww_fallbacks.argtypes = [P, ctypes.POINTER(U)]
     lib.ww_last_error.restype = ctypes.c_char_p
     lib.ww_version.restype = ctypes.c_char_p
     for name in ["ww_create", "ww_set_stream", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
-                 "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read"]:
+                 "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read", "ww_fallbacks"]:
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -100,15 +104,19 @@ def _dp(a: np.ndarray):
 
 
 class Context:
-    """One engine context on the current GPU, on torch's current stream."""
+    """One engine context on the current GPU, on torch's current stream.  strict=True
+    disables the fallbacks (pivoted LU, FP64 after a failed refinement test): the
+    calls then raise WW_EPIVOT / WW_EREFINE instead."""
 
-    def __init__(self, n_max: int, r_max: int, mixed: bool = False, stream=None, tableau=None):
+    def __init__(self, n_max: int, r_max: int, mixed: bool = False, stream=None, tableau=None,
+                 strict: bool = False):
         self.lib = load()
         self.ptr = ctypes.c_void_p()
         s = stream if stream is not None else torch.cuda.current_stream()
         self._stream = s            # the library keeps the handle: keep the stream alive
-        _check(self.lib.ww_create(ctypes.byref(self.ptr), n_max, r_max,
-                                  WW_MIXED if mixed else WW_FP64, ctypes.c_void_p(s.cuda_stream)))
+        flags = (WW_MIXED if mixed else WW_FP64) | (WW_STRICT if strict else 0)
+        _check(self.lib.ww_create(ctypes.byref(self.ptr), n_max, r_max, flags,
+                                  ctypes.c_void_p(s.cuda_stream)))
         self.n_max, self.r_max, self.mixed = n_max, r_max, mixed
         a, b, c = tableau if tableau is not None else dop853()
         self._tab = (a, b, c)
@@ -184,6 +192,12 @@ class Context:
         _check(self.lib.shoot_eval(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
                                    _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
+
+    def fallbacks(self) -> int:
+        """WW_FB_* bits behind the results of the last call on this context."""
+        b = ctypes.c_uint(0)
+        _check(self.lib.ww_fallbacks(self.ptr, ctypes.byref(b)))
+        return b.value
 
     def profile(self, enable: bool = True):
         _check(self.lib.ww_profile(self.ptr, 1 if enable else 0))

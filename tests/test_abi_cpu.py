@@ -53,3 +53,4 @@ def test_argument_errors_without_gpu():
     assert lib.ww_create(ctypes.byref(out), 70, 4, 0, None) == -1      # 70 is not 2^a 3^b
     assert lib.ww_create(ctypes.byref(out), 4096, 4, 0, None) == -1    # above 2048
     assert lib.ww_create(ctypes.byref(out), 64, 4, 8, None) == -1      # unknown flag
+    assert lib.ww_fallbacks(None, None) == -1

@@ -1,0 +1,226 @@
+"""Fallbacks of the GPU path against the oracle, through the C ABI.
+
+The pivot guard of the unpivoted block LU is raised from the host (environment
+WW_PIVOT_GUARD, read when a context is created) above the smallest unpivoted pivot of a
+steep surface on which elimination with partial pivoting interchanges rows; the
+library then redoes the call with the partially pivoted factorisation, whose results
+must agree with the oracle (LAPACK partial pivoting) to the FP64 bar.  Without
+refinement sweeps (WW_NREF = 0) the mixed form fails its refinement test and falls
+back to FP64 factors.  WW_STRICT contexts report the conditions instead.  Every
+kernel exits normally: the conditions are values, not faults.
+"""
+import math
+
+import numpy as np
+import pytest
+import scipy.linalg as sl
+
+from oracle import ww_oracle as O
+from paper_1210_5672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+N = 64
+GUARD = "0.05"      # above the smallest unpivoted pivot of the steep surface (about 0.027)
+
+
+def _ww():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    return ww, torch
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _interchanges(eta, h):
+    """Row interchanges of LAPACK's partial pivoting on the oracle's A."""
+    A = O.assemble(eta, h)[0]
+    piv = sl.lu_factor(A)[1]
+    return int((piv != np.arange(len(piv))).sum())
+
+
+def _min_unpivoted_pivot(eta, h):
+    U = np.array(O.assemble(eta, h)[0], dtype=np.float64)
+    m = math.inf
+    for j in range(U.shape[0]):
+        m = min(m, abs(U[j, j]))
+        U[j + 1:, j] /= U[j, j]
+        U[j + 1:, j + 1:] -= np.outer(U[j + 1:, j], U[j, j + 1:])
+    return m
+
+
+@pytest.mark.parametrize("h", [1.0, math.inf])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_dtn_pivoted_fallback_with_row_interchanges(monkeypatch, h, mixed):
+    ww, torch = _ww()
+    print(f"dtn pivoted fallback h={h} mixed={mixed}", flush=True)
+    eta = W.steep_surface(N)
+    assert _interchanges(eta, h) > 0                       # the input exercises interchanges
+    assert 1e-8 < _min_unpivoted_pivot(eta, h) < float(GUARD)
+    rhs = W.random_rhs(N, 3, seed=11)
+    ref, mref = O.DtN(eta, h).apply(rhs)
+    # default guard: the unpivoted factors are used
+    c0 = ww.Context(n_max=N, r_max=4, mixed=mixed)
+    c0.dtn_setup(ww.to_dev(eta), h)
+    out0 = c0.dtn_solve_multi(ww.to_dev(rhs)).cpu().numpy()
+    assert c0.fallbacks() == 0
+    assert relerr(out0, ref) < TOL
+    # raised guard: the call is redone with partial pivoting
+    monkeypatch.setenv("WW_PIVOT_GUARD", GUARD)
+    c1 = ww.Context(n_max=N, r_max=4, mixed=mixed)
+    c1.dtn_setup(ww.to_dev(eta), h)
+    assert c1.fallbacks() == ww.WW_FB_PIVOTED | ww.WW_FB_FP64
+    out1, mu1 = c1.dtn_solve_multi(ww.to_dev(rhs), want_mu=True)
+    torch.cuda.synchronize()
+    assert c1.fallbacks() == ww.WW_FB_PIVOTED | ww.WW_FB_FP64
+    assert relerr(out1.cpu().numpy(), ref) < TOL
+    assert relerr(mu1.cpu().numpy(), mref) < TOL
+    # a second solve with other columns reuses the pivoted factors
+    rhs2 = W.random_rhs(N, 4, seed=12)
+    ref2, _ = O.DtN(eta, h).apply(rhs2)
+    assert relerr(c1.dtn_solve_multi(ww.to_dev(rhs2)).cpu().numpy(), ref2) < TOL
+    # strict: the guard failure is reported
+    c2 = ww.Context(n_max=N, r_max=4, mixed=mixed, strict=True)
+    with pytest.raises(ww.WWError) as ei:
+        c2.dtn_setup(ww.to_dev(eta), h)
+    assert ei.value.name == "WW_EPIVOT"
+    with pytest.raises(ww.WWError) as ei:
+        c2.dtn_solve_multi(ww.to_dev(rhs))
+    assert ei.value.name == "WW_ENOSETUP"
+
+
+def test_dtn_pivoted_fallback_padded_grid(monkeypatch):
+    """N = 96 (padded to 128): the row order leaves the identity padding in place."""
+    ww, torch = _ww()
+    n = 96
+    eta = W.random_surface(n, seed=21, amp=0.08)
+    rhs = W.random_rhs(n, 5, seed=22)
+    ref, _ = O.DtN(eta, 0.7).apply(rhs)
+    monkeypatch.setenv("WW_PIVOT_GUARD", "1.0")      # above every pivot (about 0.5)
+    c = ww.Context(n_max=n, r_max=5)
+    c.dtn_setup(ww.to_dev(eta), 0.7)
+    assert c.fallbacks() == ww.WW_FB_PIVOTED | ww.WW_FB_FP64
+    assert relerr(c.dtn_solve_multi(ww.to_dev(rhs)).cpu().numpy(), ref) < TOL
+
+
+def test_mixed_refinement_fallback_to_fp64(monkeypatch):
+    ww, torch = _ww()
+    n, R = 96, 3
+    eta = W.random_surface(n, seed=5, amp=0.06)
+    rhs = W.random_rhs(n, R, seed=6)
+    ref, _ = O.DtN(eta, 1.0).apply(rhs)
+    monkeypatch.setenv("WW_NREF", "0")
+    c = ww.Context(n_max=n, r_max=R, mixed=True)
+    c.dtn_setup(ww.to_dev(eta), 1.0)
+    assert c.fallbacks() == 0
+    out = c.dtn_solve_multi(ww.to_dev(rhs)).cpu().numpy()
+    assert c.fallbacks() == ww.WW_FB_FP64
+    assert relerr(out, ref) < TOL
+    out2 = c.dtn_solve_multi(ww.to_dev(rhs)).cpu().numpy()     # FP64 factors kept
+    assert c.fallbacks() == ww.WW_FB_FP64
+    assert relerr(out2, ref) < TOL
+    c.dtn_setup(ww.to_dev(eta), 1.0)                           # a new setup starts mixed again
+    assert c.fallbacks() == 0
+
+
+def _steep_case():
+    M = 3
+    eta = W.steep_surface(N)
+    return dict(N=N, h=1.0, tau=0.0, g=1.0, M=M, basis=W.cosine_basis(N, M),
+                q=np.concatenate([eta, np.zeros(N)]), p=np.array([0.01, 0.005, 0.002]), T=0.1, nsteps=4)
+
+
+def _shoot_ctx(ww, w, mixed=False, strict=False):
+    c = ww.Context(n_max=w["N"], r_max=w["M"] + 1, mixed=mixed, strict=strict)
+    c.shoot_setup(w["N"], w["h"], w["tau"], w["g"], ww.to_dev(w["basis"]), ww.to_dev(w["q"]))
+    return c
+
+
+def _cmp(out, ref):
+    return dict(r=relerr(out["r"].cpu().numpy(), ref["r"]), J=relerr(out["J"].cpu().numpy(), ref["J"]),
+                drdT=relerr(out["drdT"].cpu().numpy(), ref["drdT"]), f=abs(out["f"] - ref["f"]) / abs(ref["f"]))
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_shoot_eval_pivoted_fallback(monkeypatch, mixed):
+    """A short march from the steep surface (every stage factors a matrix on which
+    partial pivoting interchanges rows): the march is redone with pivoted factors."""
+    ww, torch = _ww()
+    w = _steep_case()
+    print(f"shoot pivoted fallback mixed={mixed}", flush=True)
+    ref = O.shoot_eval(w["N"], w["h"], w["tau"], w["g"], w["basis"], w["q"], w["p"], w["T"], w["nsteps"])
+    c0 = _shoot_ctx(ww, w, mixed=mixed)
+    e0 = _cmp(c0.shoot_eval(ww.to_dev(w["p"]), w["T"], w["nsteps"]), ref)
+    assert c0.fallbacks() == 0
+    assert max(e0.values()) < TOL, e0
+    monkeypatch.setenv("WW_PIVOT_GUARD", GUARD)
+    c1 = _shoot_ctx(ww, w, mixed=mixed)
+    e1 = _cmp(c1.shoot_eval(ww.to_dev(w["p"]), w["T"], w["nsteps"]), ref)
+    assert c1.fallbacks() == ww.WW_FB_PIVOTED | ww.WW_FB_FP64
+    assert max(e1.values()) < TOL, e1
+    c2 = _shoot_ctx(ww, w, mixed=mixed, strict=True)
+    with pytest.raises(ww.WWError) as ei:
+        c2.shoot_eval(ww.to_dev(w["p"]), w["T"], w["nsteps"])
+    assert ei.value.name == "WW_EPIVOT"
+
+
+def test_shoot_adjoint_pivoted_fallback(monkeypatch):
+    ww, torch = _ww()
+    w = _steep_case()
+    ref = O.shoot_eval(w["N"], w["h"], w["tau"], w["g"], w["basis"], w["q"], w["p"], w["T"], w["nsteps"])
+    gref, dref = O.shoot_gradient(ref)
+    monkeypatch.setenv("WW_PIVOT_GUARD", GUARD)
+    c = _shoot_ctx(ww, w)
+    out = c.shoot_adjoint(ww.to_dev(w["p"]), w["T"], w["nsteps"], ckpt_every=3)
+    assert c.fallbacks() == ww.WW_FB_PIVOTED | ww.WW_FB_FP64
+    assert relerr(out["grad"].cpu().numpy(), gref) < TOL
+    assert abs(out["dfdT"] - dref) / abs(dref) < TOL
+    c2 = _shoot_ctx(ww, w, strict=True)
+    with pytest.raises(ww.WWError) as ei:
+        c2.shoot_adjoint(ww.to_dev(w["p"]), w["T"], w["nsteps"], ckpt_every=3)
+    assert ei.value.name == "WW_EPIVOT"
+
+
+def test_shoot_eval_mixed_refinement_fallback(monkeypatch):
+    """drdT of this march is a near-cancellation (the surface passes close to the still
+    level at T/4); as in the FP64 parity tests its error is measured on the scale of
+    one right-hand-side evaluation at the march's amplitude."""
+    ww, torch = _ww()
+    w = W.c1()
+    ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, 4)
+    monkeypatch.setenv("WW_NREF", "0")
+    c = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=True)
+    c.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    out = c.shoot_eval(ww.to_dev(w.params), w.T, 4)
+    assert c.fallbacks() == ww.WW_FB_FP64
+    e = _cmp(out, ref)
+    op = max(math.exp(-36.0 * (k / (w.N / 2)) ** 36) * (w.g + w.tau * k * k) for k in range(w.N // 2))
+    eta0 = W.initial_state(w)[0]
+    scale = max(np.abs(ref["drdT"]).max(), 0.25 * np.abs(eta0).max() / math.sqrt(w.N) * op)
+    e["drdT"] = float(np.abs(out["drdT"].cpu().numpy() - ref["drdT"]).max() / scale)
+    assert max(e.values()) < TOL, e
+
+
+def test_batch_with_one_instance_falling_back(monkeypatch):
+    """Two instances in one batch, one of them behind a raised guard: that instance is
+    redone alone with pivoted factors; both match their single-instance results."""
+    ww, torch = _ww()
+    w = _steep_case()
+    ref = O.shoot_eval(w["N"], w["h"], w["tau"], w["g"], w["basis"], w["q"], w["p"], w["T"], w["nsteps"])
+    ca = _shoot_ctx(ww, w)
+    monkeypatch.setenv("WW_PIVOT_GUARD", GUARD)
+    cb = _shoot_ctx(ww, w)
+    p = ww.to_dev(w["p"])
+    outs = ww.shoot_eval_batch([ca, cb], [p, p], [w["T"]] * 2, [w["nsteps"]] * 2)
+    assert ca.fallbacks() == 0
+    assert cb.fallbacks() == ww.WW_FB_PIVOTED | ww.WW_FB_FP64
+    for o in outs:
+        e = _cmp(o, ref)
+        assert max(e.values()) < TOL, e

@@ -173,21 +173,21 @@ def test_unstable_step_reports_nonfinite():
 
 def test_mixed_refinement_test_reports_nonconvergence(monkeypatch):
     """Without refinement sweeps (WW_NREF = 0) the FP32 solve leaves a relative residual
-    far above 2^-43: the library reports WW_EREFINE (the condition is computed by a
-    kernel that exits normally).  With the default two sweeps the same solve passes the
-    test and matches the oracle."""
+    far above 2^-43: a WW_STRICT context reports WW_EREFINE (the condition is computed
+    by a kernel that exits normally).  With the default two sweeps the same solve passes
+    the test and matches the oracle."""
     ww, torch = _ww()
     N, R = 96, 3
     eta = W.random_surface(N, seed=5, amp=0.06)
     rhs = W.random_rhs(N, R, seed=6)
     monkeypatch.setenv("WW_NREF", "0")
-    ctx = ww.Context(n_max=N, r_max=R, mixed=True)
+    ctx = ww.Context(n_max=N, r_max=R, mixed=True, strict=True)
     ctx.dtn_setup(ww.to_dev(eta), 1.0)
     with pytest.raises(ww.WWError) as ei:
         ctx.dtn_solve_multi(ww.to_dev(rhs))
     assert ei.value.name == "WW_EREFINE"
     w = W.c1()
-    c1 = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=True)
+    c1 = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=True, strict=True)
     c1.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     with pytest.raises(ww.WWError) as ei:
         c1.shoot_eval(ww.to_dev(w.params), w.T, 4)
