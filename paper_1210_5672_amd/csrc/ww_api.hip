@@ -613,7 +613,7 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
   int rc;
   if ((rc = prof_mark(c, 1, 0))) return rc;
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysrc, c->K, c->Ys, c->coef,
-                     s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf);
+                     s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
   LAUNCHCHK();
   if ((rc = enqueue_assemble_lu(c, F))) return rc;
   if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
@@ -669,7 +669,7 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
   if (two) HIPCHK(hipStreamWaitEvent(s0, c->evC[c->nst - 1], 0));
   const int ncol = cols ? c->M + 1 : 1;
   hipLaunchKernelGGL(k_step_end, dim3(ncol), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y, c->K, kstride(c),
-                     c->nst, c->coef, c->tw, c->sig, c->N, 0);
+                     c->nst, c->coef, c->tw, c->sig, c->N, 0, c->status);
   LAUNCHCHK();
   return 0;
 }
@@ -709,10 +709,15 @@ static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   return 0;
 }
 
-static int read_status(ww_ctx* c, int* st) {
+// status bits (clears them); *where (optional) receives 16 step + stage of the first
+// non-finite or bed-crossing stage state of a march (INT_MAX if none)
+static int read_status(ww_ctx* c, int* st, int* where = nullptr) {
+  int h[3] = {0, 0, 0};
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(st, c->status, sizeof(int), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(h, c->status, sizeof(h), hipMemcpyDeviceToHost));
   HIPCHK(hipMemset(c->status, 0, sizeof(int)));
+  *st = h[0];
+  if (where) *where = h[2];
   return 0;
 }
 
@@ -729,6 +734,7 @@ static int dtn_factor(ww_ctx* c) {
     if ((rc = enqueue_assemble_lu(c, fac_default(c)))) return rc;
     int st = 0;
     if ((rc = read_status(c, &st))) return rc;
+    if (st & 2) return fail(WW_ENONFINITE, "non-finite surface");
     if (!(st & (1 | 8))) return 0;
     if (pivoted(c)) return fail(WW_EPIVOT, MSG_PIVOT2);
     if (strict(c)) return fail(WW_EPIVOT, MSG_PIVOT);
@@ -758,8 +764,10 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   if ((rc = check_domain(c, surface))) return rc;
   HIPCHK(hipMemcpyAsync(c->ydtn, surface, N * 8, hipMemcpyDeviceToDevice, c->stream));
   HIPCHK(hipMemsetAsync(c->ydtn + N, 0, N * 8, c->stream));
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 4), c->stream, c->ydtn, c->K, c->Ys,
-                     c->coef, 0, (size_t)0, c->aux, c->n_max, c->rhs0, c->Np, c->tw, N, c->hsurf);
+                     c->coef, 0, (size_t)0, c->aux, c->n_max, c->rhs0, c->Np, c->tw, N, c->hsurf, c->status);
   LAUNCHCHK();
   if ((rc = dtn_factor(c))) return rc;
   c->dtn_ready = true;
@@ -877,7 +885,8 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   }
   coef[COEF_DT] = dt;
   HIPCHK(hipMemcpyAsync(c->coef, coef, sizeof(coef), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
   const size_t tot = (size_t)2 * N * (M + 1);
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
@@ -921,14 +930,18 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
 // guard (pivoted LU), 2 non-finite state, 4 failed refinement test.  The fallback that
 // a redo of the call takes, or 0.
 static unsigned next_fallback(const ww_ctx* c, int st) {
-  if (strict(c)) return 0;
+  if (strict(c) || (st & 16)) return 0;   // a surface through the bottom is no factorisation issue
   if ((st & (1 | 8)) && !pivoted(c)) return WW_FB_PIVOTED | WW_FB_FP64;
   if ((st & 4) && !(c->fb & WW_FB_FP64)) return WW_FB_FP64;
   return 0;
 }
 
-static int status_error(const ww_ctx* c, int st) {
-  if (st & 2) return fail(WW_ENONFINITE, "non-finite value in the marched state");
+static int status_error(const ww_ctx* c, int st, int where) {
+  std::string at;
+  if (where != 0x7fffffff) at = " at step " + std::to_string(where / 16) + ", stage " + std::to_string(where % 16);
+  if (st & 16) return fail(WW_EDOMAIN, "finite depth: surface height h + eta <= 0 in the march" + at);
+  if (st & 2)
+    return fail(WW_ENONFINITE, "non-finite value in the marched state" + (at.empty() ? std::string(" (at T/4)") : at));
   if (st & (1 | 8)) return fail(WW_EPIVOT, pivoted(c) ? MSG_PIVOT2 : MSG_PIVOT);
   if (st & 4) return fail(WW_EREFINE, MSG_REFINE);
   return 0;
@@ -936,7 +949,7 @@ static int status_error(const ww_ctx* c, int st) {
 
 // one march in the current fallback mode; *st receives the status bits
 static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
-                     double* f, int* st) {
+                     double* f, int* st, int* where) {
   const bool cols = (J != nullptr) && c->M > 0;
   const bool two = c->overlap && !pivoted(c);
   int rc;
@@ -945,7 +958,7 @@ static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, doub
   for (int n = 0; n < nsteps; ++n)
     if ((rc = shoot_one_step(c, cols, two))) return rc;
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
-  return read_status(c, st);
+  return read_status(c, st, where);
 }
 
 // marches from fallback mode fb0 until the status needs no further fallback
@@ -953,11 +966,11 @@ static int shoot_eval_fb(ww_ctx* c, const double* params, double T, int nsteps, 
                          double* f, unsigned fb0) {
   c->fb = fb0;
   for (;;) {
-    int st = 0, rc;
-    if ((rc = shoot_run(c, params, T, nsteps, r, J, drdT, f, &st))) return rc;
+    int st = 0, where = 0, rc;
+    if ((rc = shoot_run(c, params, T, nsteps, r, J, drdT, f, &st, &where))) return rc;
     const unsigned nf = next_fallback(c, st);
     if (!nf) {
-      if ((rc = status_error(c, st))) return rc;
+      if ((rc = status_error(c, st, where))) return rc;
       c->fb_last = c->fb;
       return 0;
     }
@@ -1007,13 +1020,13 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   int first_err = 0;
   for (int i = 0; i < n_inst; ++i) {
     ww_ctx* c = ctx[i];
-    int st = 0, e;
-    if ((e = read_status(c, &st)) == 0) {
+    int st = 0, where = 0, e;
+    if ((e = read_status(c, &st, &where)) == 0) {
       const unsigned nf = next_fallback(c, st);
       if (nf)   // this instance alone, in its fallback mode
         e = shoot_eval_fb(c, params[i], T[i], nsteps[i], r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr,
                           f ? &f[i] : nullptr, nf);
-      else if ((e = status_error(c, st)) == 0)
+      else if ((e = status_error(c, st, where)) == 0)
         c->fb_last = c->fb;
     }
     if (e && !first_err) first_err = e;
@@ -1025,7 +1038,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
 
 // one adjoint evaluation in the current fallback mode; *stout receives the status bits
 static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, int ckpt_every, double* grad,
-                       double* dfdT, double* f, int* stout) {
+                       double* dfdT, double* f, int* stout, int* where) {
   int rc;
   if ((rc = set_grid(c, c->shootN, c->shootH))) return rc;
   c->dtn_ready = false;
@@ -1097,7 +1110,8 @@ static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, in
   }
   coef[COEF_DT] = dt;
   HIPCHK(hipMemcpyAsync(c->coef, coef, sizeof(coef), hipMemcpyHostToDevice, c->stream));
-  HIPCHK(hipMemsetAsync(c->status, 0, sizeof(int), c->stream));
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
   {
     const size_t tot = (size_t)2 * N * (M + 1);
     const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
@@ -1119,7 +1133,7 @@ static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, in
       }
     }
     hipLaunchKernelGGL(k_step_end, dim3(1), dim3(WW_NT), fft_lds_bytes(N, 3), c->stream, c->y, c->K, kstride(c), nst,
-                       c->coef, c->tw, c->sig, N, 0);
+                       c->coef, c->tw, c->sig, N, 0, c->status);
     LAUNCHCHK();
     return 0;
   };
@@ -1195,7 +1209,7 @@ static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, in
   HIPCHK(hipMemcpyAsync(hd2.data(), dv, N * 8, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipMemcpyAsync(&fh, c->fdev, 8, hipMemcpyDeviceToHost, c->stream));
   int st = 0;
-  if ((rc = read_status(c, &st))) return rc;
+  if ((rc = read_status(c, &st, where))) return rc;
   if (f) *f = fh;
   if (dfdT) {
     double acc = 0.0;
@@ -1216,11 +1230,11 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
   if (nsteps < 1 || !std::isfinite(T) || ckpt_every < 1) return fail(WW_EINVAL, "nsteps, ckpt_every >= 1 required");
   c->fb = 0;
   for (;;) {
-    int st = 0, rc;
-    if ((rc = adjoint_run(c, params, T, nsteps, ckpt_every, grad, dfdT, f, &st))) return rc;
+    int st = 0, where = 0, rc;
+    if ((rc = adjoint_run(c, params, T, nsteps, ckpt_every, grad, dfdT, f, &st, &where))) return rc;
     const unsigned nf = next_fallback(c, st & ~4);   // FP64 factors throughout
     if (!nf) {
-      if ((rc = status_error(c, st))) return rc;
+      if ((rc = status_error(c, st, where))) return rc;
       c->fb_last = c->fb;
       return 0;
     }

@@ -139,7 +139,7 @@ __global__ void k_init_state(double* __restrict__ y, const double* __restrict__ 
 __global__ __launch_bounds__(WW_NT) void k_base_prep(
     const double* __restrict__ y, const double* __restrict__ K, double* __restrict__ Ys,
     const double* __restrict__ coef, int stage, size_t kstride, double* __restrict__ aux, int nmax,
-    double* __restrict__ rhs0, int Np, const cplx* __restrict__ tw, int N, double hsurf) {
+    double* __restrict__ rhs0, int Np, const cplx* __restrict__ tw, int N, double hsurf, int* __restrict__ status) {
   extern __shared__ cplx lds[];
   cplx* Z = lds;
   cplx* W = lds + N;
@@ -174,6 +174,7 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
   }
   fft_lds(W, Z, tws, P, +1);   // eta_x + i eta_xx
   fft_lds(S, Z, tws, P, +1);   // varphi' (imaginary part zero)
+  bool bad = false, bed = false;
 #pragma unroll
   for (int m = 0; m < NPT; ++m) {
     const int i = tidx(m);
@@ -185,9 +186,18 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
       aux[AUX_EP * nmax + i] = exp(sh);
       aux[AUX_EM * nmax + i] = exp(-sh);
       rhs0[i] = pv[m];
+      bad |= !isfinite(ev[m]) || !isfinite(pv[m]);
+      bed |= hsurf > 0.0 && sh <= 0.0;   // (a NaN height is reported as non-finite)
     }
   }
   for (int i = N + tid; i < Np; i += WW_NT) rhs0[i] = 0.0;
+  // failure detection: non-finite stage state (bit 2) or, at finite depth, a surface
+  // through the bottom (bit 16); status[2] keeps the first 16 step + stage (status[1]
+  // counts the completed steps)
+  if (status && (bad || bed)) {
+    atomicOr(status, (bad ? 2 : 0) | (bed ? 16 : 0));
+    atomicMin(status + 2, status[1] * 16 + stage);
+  }
 }
 
 // -------------------------------------------------------------------------------------
@@ -1341,7 +1351,7 @@ __global__ __launch_bounds__(WW_NT) void k_col_rhs(const double* __restrict__ Ys
 __global__ __launch_bounds__(WW_NT) void k_step_end(double* __restrict__ y, const double* __restrict__ K,
                                                     size_t kstride, int nst, const double* __restrict__ coef,
                                                     const cplx* __restrict__ tw, const double* __restrict__ sig,
-                                                    int N, int c0) {
+                                                    int N, int c0, int* __restrict__ status) {
   extern __shared__ cplx lds[];
   cplx* Z = lds;
   cplx* W = lds + N;
@@ -1369,6 +1379,16 @@ __global__ __launch_bounds__(WW_NT) void k_step_end(double* __restrict__ y, cons
   for (int t = tid; t < N; t += WW_NT) {
     yc[t] = Z[t].x;
     yc[N + t] = Z[t].y;
+  }
+  if (status && blockIdx.x == 0 && tid == 0) status[1] += 1;   // steps completed
+}
+
+// status word of a call: bits, step counter, first failing 16 step + stage
+__global__ void k_status_reset(int* __restrict__ status) {
+  if (threadIdx.x == 0) {
+    status[0] = 0;
+    status[1] = 0;
+    status[2] = 0x7fffffff;
   }
 }
 

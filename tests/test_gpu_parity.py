@@ -159,16 +159,49 @@ def test_dtn_factors_invalidated_by_a_new_grid_or_a_failed_setup():
     assert ei.value.name == "WW_ENOSETUP"
 
 
+def test_march_failures_name_the_step_and_stage():
+    """Failure detection per stage (the stage state is checked where it is formed):
+    NaN parameters fail at step 0, stage 0; a surface that the flow drives through the
+    bottom (h = 0.1) is reported as WW_EDOMAIN at the step where the oracle's state
+    crosses (its end-of-step states stay above the bed through step 10 and are below it
+    after step 11); a NaN surface in dtn_setup is reported as non-finite."""
+    import re
+    ww, torch = _ww()
+    N, M = 32, 2
+    w = W.Workload("t", N, 1.0, 0.0, 1.0, M, W.linear_period(1.0, 0.0), 8, np.array([0.01, np.nan]),
+                   W.cosine_basis(N, M), np.zeros(2 * N))
+    with pytest.raises(ww.WWError) as ei:
+        _shoot(ww, w)
+    assert ei.value.name == "WW_ENONFINITE"
+    assert "step 0, stage 0" in str(ei.value)
+    a = W.grid(N)
+    q = np.concatenate([-0.08 * np.cos(a), 0.3 * np.cos(a)])
+    w = W.Workload("t", N, 0.1, 0.0, 1.0, M, 2.0, 20, np.zeros(M), W.cosine_basis(N, M), q)
+    with pytest.raises(ww.WWError) as ei:
+        _shoot(ww, w)
+    assert ei.value.name == "WW_EDOMAIN"
+    step = int(re.search(r"at step (\d+), stage (\d+)", str(ei.value)).group(1))
+    assert step in (9, 10), str(ei.value)
+    ctx = ww.Context(n_max=64, r_max=2)
+    eta = np.zeros(64)
+    eta[5] = np.nan
+    with pytest.raises(ww.WWError) as ei:
+        ctx.dtn_setup(ww.to_dev(eta), math.inf)
+    assert ei.value.name == "WW_ENONFINITE"
+
+
 def test_unstable_step_reports_nonfinite():
     """6 steps put the fastest filtered mode outside the stability region: the march
-    blows up and the library reports WW_ENONFINITE (values only; no kernel faults)."""
+    blows up and the library reports it (values only; no kernel faults)."""
     ww, torch = _ww()
     N, M, h, tau = 96, 2, 0.7, 0.02
     p = np.array([0.04, 0.001])
     w = W.Workload("t", N, h, tau, 1.0, M, W.linear_period(h, tau), 6, p, W.cosine_basis(N, M), np.zeros(2 * N))
     with pytest.raises(ww.WWError) as ei:
         _shoot(ww, w)
-    assert ei.value.name in ("WW_ENONFINITE", "WW_EPIVOT")
+    # at this depth (0.7) the growing oscillation first drives the surface through
+    # the bottom, which is reported before the values overflow
+    assert ei.value.name in ("WW_ENONFINITE", "WW_EPIVOT", "WW_EDOMAIN")
 
 
 def test_mixed_refinement_test_reports_nonconvergence(monkeypatch):
