@@ -16,11 +16,13 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import statistics
 import sys
 import time
 
 FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (vector and MFMA)
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA
+HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 
 # HBM bytes of one FP64 block-LU launch sequence (N = 1024), from the FETCH_SIZE and
 # WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md, calibrated with a
@@ -75,16 +77,24 @@ def run(w, nsteps, T, mixed, steps, warmup, profile):
         ctx.profile(True)
     params = ww.to_dev(w.params)
     tag = "mixed" if mixed else "fp64"
+    first_ms = None
     for i in range(warmup):
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
         ctx.shoot_eval(params, T, nsteps)
+        if i == 0:   # the first call captures and instantiates the step graph
+            first_ms = 1e3 * (time.perf_counter() - ta)
         print(f"# {tag} warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
     if profile:
         ctx.profile(True)   # clear the sums: the phases cover the timed steps only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = None
+    each = []
     for i in range(steps):
-        res = ctx.shoot_eval(params, T, nsteps)
+        ta = time.perf_counter()
+        res = ctx.shoot_eval(params, T, nsteps)   # synchronises (status check)
+        each.append(1e3 * (time.perf_counter() - ta))
         print(f"# {tag} step {i + 1}/{steps} done", file=sys.stderr, flush=True)
     torch.cuda.synchronize()
     t = time.perf_counter() - t0
@@ -92,7 +102,24 @@ def run(w, nsteps, T, mixed, steps, warmup, profile):
     if profile:
         phases = {"block_lu_ms": ctx.profile_read(0), "base_chain_ms": ctx.profile_read(1),
                   "column_chain_ms": ctx.profile_read(2)}
-    return t, res, phases
+    timing = {"median_ms": statistics.median(each), "min_ms": min(each), "max_ms": max(each),
+              "first_call_ms": first_ms}
+    return t, res, phases, timing
+
+
+def stage_roofline(N, M, nst, stage_ms):
+    """Whole-stage roofline: the algorithmic work of one stage at the FP64 MFMA peak and
+    the HBM bandwidth, summed phase by phase (each phase at its own bound), against the
+    measured stage time.  Flops: LU 2/3 N^3, solve 2 N^2 R, Gm product 2 N^2 R (R = M + 1).
+    Bytes: assembly writes of A and Gm (2 N^2 x 8) and the stage combination (on average
+    (nst - 1)/2 earlier stage slopes and the state read, the stage state written: 2 N R x 8
+    each)."""
+    R = M + 1
+    t_flop = ((2.0 / 3.0) * N ** 3 + 4.0 * N * N * R) / (FP64_PEAK_TFLOPS * 1e12)
+    bytes_ = 2.0 * N * N * 8 + ((nst - 1) / 2.0 + 2.0) * 2.0 * N * R * 8
+    t_hbm = bytes_ / (HBM_PEAK_GBS * 1e9)
+    t_roof = t_flop + t_hbm
+    return {"t_roof_us": 1e6 * t_roof, "t_meas_us": 1e3 * stage_ms, "frac": t_roof / (stage_ms * 1e-3)}
 
 
 def run_batch(window: int = 64, reps: int = 1):
@@ -159,7 +186,7 @@ def main():
     T = w.T if nsteps == w.nsteps else w.T * nsteps / w.nsteps   # same dt for a prefix
     print(f"# workload {w.name}: N={w.N} M={w.M} nsteps={nsteps}", file=sys.stderr, flush=True)
     profile = not args.no_profile
-    t, res, phases = run(w, nsteps, T, False, args.steps, args.warmup, profile)
+    t, res, phases, timing = run(w, nsteps, T, False, args.steps, args.warmup, profile)
     ms = 1000.0 * t / args.steps
     value = w.M * nsteps * args.steps / t
     n3 = float(w.N) ** 3
@@ -190,15 +217,17 @@ def main():
                    "N": w.N, "M": w.M, "nsteps": nsteps, "f": res["f"]},
         "roofline": roofline,
         "cpu_baseline": None,
+        "timing": timing,
+        "stage_roofline": stage_roofline(w.N, w.M, 12, timing["median_ms"] / (nsteps * 12)),
     }
     if not args.no_mixed:
         import numpy as np
-        tm, resm, phm = run(w, nsteps, T, True, args.steps, args.warmup, profile)
+        tm, resm, phm, timm = run(w, nsteps, T, True, args.steps, args.warmup, profile)
         r64, rm = res["r"].cpu().numpy(), resm["r"].cpu().numpy()
         J64, Jm = res["J"].cpu().numpy(), resm["J"].cpu().numpy()
         out["mixed"] = {
             "value": w.M * nsteps * args.steps / tm, "ms_per_step": 1000.0 * tm / args.steps,
-            "dtype": "f32-lu+f64-refine",
+            "dtype": "f32-lu+f64-refine", "timing": timm,
             "rel_diff_vs_fp64": {"r": float(np.linalg.norm(rm - r64) / np.linalg.norm(r64)),
                                  "J": float(np.linalg.norm(Jm - J64) / np.linalg.norm(J64))},
         }

@@ -74,6 +74,9 @@ typedef struct ww_ctx ww_ctx;
 #define WW_FB_PIVOTED 1u   /* the results come from partially pivoted FP64 factors */
 #define WW_FB_FP64 2u      /* the results come from FP64 factors after the mixed-precision
                               refinement test failed */
+#define WW_FB_DIRECT 4u    /* the lagged-factor solves of a single-instance march (see
+                              shoot_eval) failed their refinement test; the march was
+                              redone with every stage's own factors */
 
 /*
  * ww_create: allocate a context whose device workspace serves every N <= n_max and
@@ -137,6 +140,13 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  *   J    (N x M)  J_ik = phidot_k(alpha_i, T/4) / sqrt(N), or NULL (base only, R = 1)
  *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
  *   f    (host)   f = r.r / 2, or NULL
+ * Lagged factors (opt-in: environment WW_PIPE_LAG = L, 1..4, read by ww_create; off by
+ * default): in a march of one instance, the base chain of stage s (the march's
+ * critical path) solves with the factors of stage s - L and refines the solution with
+ * the FP64 residual of its own matrix (the same number of sweeps and the same
+ * convergence test as WW_MIXED), while the LU of its own matrix runs concurrently on one
+ * of L streams; the column chain of stage s uses that stage's own factors.  A failed
+ * test redoes the march with every stage's own factors (WW_FB_DIRECT).
  * Synchronises to check the status flags.  A pivot below the guard anywhere in the
  * march redoes it with partial pivoting; a failed refinement test (WW_MIXED) redoes it
  * with FP64 factors (see ww_fallbacks).

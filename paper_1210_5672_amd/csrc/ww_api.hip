@@ -33,6 +33,15 @@ static int fail(int code, const std::string& msg) {
       return fail(WW_EHIP, std::string("kernel launch: ") + hipGetErrorString(e_));     \
   } while (0)
 
+// One stage's factor set of the lagged-factor pipeline (all Np x Np unless noted)
+struct RingSet {
+  double *A = nullptr, *Gm = nullptr, *X = nullptr, *Z = nullptr, *V = nullptr, *Dinv = nullptr;
+  double *Xr = nullptr, *Zr = nullptr, *Gmr = nullptr, *Ar = nullptr, *aux = nullptr;
+  float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
+  float *X32r = nullptr, *Z32r = nullptr;
+};
+#define PIPE_MAXLAG 4
+
 struct ww_ctx {
   int dev = 0;
   hipStream_t stream = nullptr;
@@ -112,6 +121,14 @@ struct ww_ctx {
   double *pw = nullptr, *pb = nullptr;
   int* seg_perm = nullptr;
   size_t seg_perm_cap = 0;
+  // lagged-factor pipeline of single-instance marches: the base solve of stage s uses
+  // the factors of stage s - lag (refined against its own matrix) while the LU of
+  // stage s runs on one of `lag` streams; the column chain of stage s waits for it
+  int lag = 0;   // environment WW_PIPE_LAG, 1..4 (default 0: every solve uses its own factors)
+  int ring_n = 0;          // factor sets allocated (one per stage)
+  RingSet ring[16];
+  hipStream_t lus[PIPE_MAXLAG] = {};
+  hipEvent_t evA[16] = {}, evL[16] = {};
 };
 
 static bool valid_n(int N) {
@@ -252,8 +269,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     AL(c->V32_1, np * np * 4);
     AL(c->Dinv32_1, (size_t)nbm * 4096 * 4);
     AL(c->Rr, np * R * 8);
-    AL(c->rr0, np * 8);
   }
+  AL(c->rr0, np * 8);   // residual of the one-vector solves (mixed form, lagged factors)
   AL(c->cosT, nm * 8);
   AL(c->sinT, nm * 8);
   AL(c->c0T, nm * 8);
@@ -300,6 +317,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->overlap = !(no && no[0] == '1');
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
+    const char* pl = std::getenv("WW_PIPE_LAG");
+    if (pl) c->lag = std::max(0, std::min(PIPE_MAXLAG, std::atoi(pl)));
     const char* pg = std::getenv("WW_PIVOT_GUARD");
     if (pg) {
       const double v = std::atof(pg);
@@ -331,12 +350,20 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
 
 void ww_destroy(ww_ctx* c) {
   if (!c) return;
+  // no work of this context (stream-ordered calls, graph branches) may still run
+  (void)hipDeviceSynchronize();
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
   if (c->stamps) (void)hipFree(c->stamps);
   if (c->ckpt) (void)hipFree(c->ckpt);
   if (c->seg) (void)hipFree(c->seg);
   if (c->adj) (void)hipFree(c->adj);
   if (c->seg_perm) (void)hipFree(c->seg_perm);
+  for (int i = 0; i < PIPE_MAXLAG; ++i)
+    if (c->lus[i]) (void)hipStreamDestroy(c->lus[i]);
+  for (int i = 0; i < 16; ++i) {
+    if (c->evA[i]) (void)hipEventDestroy(c->evA[i]);
+    if (c->evL[i]) (void)hipEventDestroy(c->evL[i]);
+  }
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->side) (void)hipStreamDestroy(c->side);
   for (int i = 0; i < 16; ++i) {
@@ -505,14 +532,20 @@ static int enqueue_pivot_order(ww_ctx* c, const Fac& F) {
 }
 static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 
-// assembly of A, Gm and the block LU of A (FP64, or of the FP32 copy in mixed mode)
-// with the block-triangular inverses
-static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
+// assembly of A, Gm (and the row-major FP64 copy Ar when the solves refine: mixed
+// mode, or lagged factors)
+static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar) {
   const int nb = c->Np / WW_TB;
   hipLaunchKernelGGL(k_assemble, dim3(nb, c->Np / ASM_CW), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT,
-                     c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, F.use32 ? F.Ar : nullptr, c->N, c->Np,
-                     c->finite);
+                     c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, (F.use32 || want_ar) ? F.Ar : nullptr, c->N,
+                     c->Np, c->finite);
   LAUNCHCHK();
+  return 0;
+}
+
+// block LU of A (FP64, or of the FP32 copy in mixed mode) with the block-triangular
+// inverses; with a row order, first the partial-pivoting order and A := P A
+static int enqueue_lu(ww_ctx* c, const Fac& F) {
   int rc;
   if ((rc = prof_mark(c, 0, 0))) return rc;
   if (F.perm && (rc = enqueue_pivot_order(c, F))) return rc;
@@ -523,6 +556,12 @@ static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
         c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv, F.Xr, F.Zr, F.perm ? PIVOTED_GUARD : c->guard));
   if (rc) return rc;
   return prof_mark(c, 0, 1);
+}
+
+static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
+  int rc;
+  if ((rc = enqueue_assemble(c, F, false))) return rc;
+  return enqueue_lu(c, F);
 }
 
 // out = add + sgn * M B for R columns (ld Np), M taken as full (mode 0), strictly lower
@@ -563,6 +602,35 @@ static const double REFINE_TOL = 1.1368683772161603e-13;
 // FP64:  X = Z (B + Xs B).
 // mixed: X = Z32 (B + X32 B), then nref sweeps of  r = B - A X (FP64 residual with the
 //        FP64 matrix),  X += Z32 (r + X32 r)  (FP32 factors, FP64 accumulation).
+// Lagged factors (one vector): the factors of F are those of an earlier stage and Fa
+// holds this stage's matrix (row-major Ar): X = Z (B + Xs B), nref sweeps of
+// r = B - A X, X += Z (r + Xs r), and the same convergence test as the mixed form.
+static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* B, double* Y, double* X, double* Rs) {
+  int rc;
+  if (F.use32) {
+    if ((rc = enqueue_gemm<float>(c, nullptr, F.X32, F.X32r, 1, B, B, 1.0, Y, 1))) return rc;
+    if ((rc = enqueue_gemm<float>(c, nullptr, F.Z32, F.Z32r, 2, Y, nullptr, 1.0, X, 1))) return rc;
+  } else {
+    if ((rc = enqueue_gemm<double>(c, nullptr, F.X, F.Xr, 1, B, B, 1.0, Y, 1))) return rc;
+    if ((rc = enqueue_gemm<double>(c, nullptr, F.Z, F.Zr, 2, Y, nullptr, 1.0, X, 1))) return rc;
+  }
+  for (int it = 0; it <= c->nref; ++it) {
+    if ((rc = enqueue_gemm<double>(c, nullptr, Fa.A, Fa.Ar, 0, X, B, -1.0, Rs, 1))) return rc;
+    if (it == c->nref) break;   // the last residual is the convergence test's
+    if (F.use32) {
+      if ((rc = enqueue_gemm<float>(c, nullptr, F.X32, F.X32r, 1, Rs, Rs, 1.0, Y, 1))) return rc;
+      if ((rc = enqueue_gemm<float>(c, nullptr, F.Z32, F.Z32r, 2, Y, X, 1.0, X, 1))) return rc;
+    } else {
+      if ((rc = enqueue_gemm<double>(c, nullptr, F.X, F.Xr, 1, Rs, Rs, 1.0, Y, 1))) return rc;
+      if ((rc = enqueue_gemm<double>(c, nullptr, F.Z, F.Zr, 2, Y, X, 1.0, X, 1))) return rc;
+    }
+  }
+  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(WW_NT), 0, c->stream, Rs, B, c->Np, c->N, REFINE_TOL, c->status,
+                     32);
+  LAUNCHCHK();
+  return 0;
+}
+
 static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* X, double* Rs, int R) {
   int rc;
   if (F.perm) {   // P A = Lt Ut: solve with P B
@@ -587,7 +655,7 @@ static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* 
     // convergence test on the FP64 residual of the final solution (also with no sweep)
     if ((rc = enqueue_gemm<double>(c, F.part, F.A, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
     hipLaunchKernelGGL(k_refine_check, dim3(R), dim3(WW_NT), 0, c->stream, Rs, B, c->Np, c->N, REFINE_TOL,
-                       c->status);
+                       c->status, 4);
     LAUNCHCHK();
   }
   return 0;
@@ -639,10 +707,161 @@ static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
   return prof_mark(c, 2, 1);
 }
 
+// ----- lagged-factor pipeline -----
+// A changes little between nearby stages (a second-kind operator of a surface that
+// moves by O(dt)): with the factors of stage s - lag, one refinement sweep with the
+// FP64 residual of stage s's own matrix already reaches the rounding level.  The base
+// chain (the march's critical path) therefore solves with lagged factors while the
+// LU of its own matrix runs concurrently; the column chain, which lags behind anyway,
+// uses the exact factors of its stage.
+static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
+  return c->lag > 0 && cols && two_streams && c->fb == 0 && c->M > 0 && c->nst > c->lag;
+}
+
+static int ensure_pipe(ww_ctx* c) {
+  int rc;
+  for (int i = 0; i < c->lag; ++i)
+    if (!c->lus[i]) HIPCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
+  for (int i = 0; i < 16; ++i) {
+    if (!c->evA[i]) HIPCHK(hipEventCreateWithFlags(&c->evA[i], hipEventDisableTiming));
+    if (!c->evL[i]) HIPCHK(hipEventCreateWithFlags(&c->evL[i], hipEventDisableTiming));
+  }
+  const size_t np = c->np_max, nn = np * np;
+  const size_t nbm = np / WW_TB;
+  while (c->ring_n < c->nst) {
+    RingSet& r = c->ring[c->ring_n];
+    double** d[] = {&r.A, &r.Gm, &r.X, &r.Z, &r.V, &r.Xr, &r.Zr, &r.Gmr, &r.Ar};
+    for (double** q : d)
+      if ((rc = dalloc(c, (void**)q, nn * 8))) return rc;
+    if ((rc = dalloc(c, (void**)&r.Dinv, nbm * 4096 * 8))) return rc;
+    if ((rc = dalloc(c, (void**)&r.aux, (size_t)AUX_COUNT * c->n_max * 8))) return rc;
+    if (mixed(c)) {
+      float** f[] = {&r.A32, &r.X32, &r.Z32, &r.V32, &r.X32r, &r.Z32r};
+      for (float** q : f)
+        if ((rc = dalloc(c, (void**)q, nn * 4))) return rc;
+      if ((rc = dalloc(c, (void**)&r.Dinv32, nbm * 4096 * 4))) return rc;
+    }
+    ++c->ring_n;
+  }
+  return 0;
+}
+
+static Fac pipe_set(ww_ctx* c, int s, bool cols) {
+  const RingSet& r = c->ring[s];
+  Fac F = Fac{r.A, r.Gm, r.X, r.Z, r.V, r.Dinv, use32(c), r.A32, r.X32, r.Z32, r.V32, r.Dinv32, r.aux, nullptr};
+  F.part = cols ? c->part_c : c->part;
+  F.Xr = r.Xr;
+  F.Zr = r.Zr;
+  F.Gmr = r.Gmr;
+  F.Ar = r.Ar;
+  F.X32r = r.X32r;
+  F.Z32r = r.Z32r;
+  F.perm = nullptr;
+  return F;
+}
+
+// Before the first step: the factors of the initial surface in the sets that the first
+// `lag` stages read (those of the last stages of a previous step).
+static int pipe_prologue(ww_ctx* c) {
+  int rc;
+  const int nst = c->nst, L = c->lag;
+  const Fac P0 = pipe_set(c, nst - L, false);
+  hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys, c->coef,
+                     0, kstride(c), P0.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
+  LAUNCHCHK();
+  if ((rc = enqueue_assemble(c, P0, true))) return rc;
+  if ((rc = enqueue_lu(c, P0))) return rc;
+  const size_t nn = (size_t)c->Np * c->Np;
+  for (int q = nst - L + 1; q < nst; ++q) {
+    const RingSet &a = c->ring[nst - L], &b = c->ring[q];
+    if (use32(c)) {
+      HIPCHK(hipMemcpyAsync(b.X32r, a.X32r, nn * 4, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(b.Z32r, a.Z32r, nn * 4, hipMemcpyDeviceToDevice, c->stream));
+    } else {
+      HIPCHK(hipMemcpyAsync(b.Xr, a.Xr, nn * 8, hipMemcpyDeviceToDevice, c->stream));
+      HIPCHK(hipMemcpyAsync(b.Zr, a.Zr, nn * 8, hipMemcpyDeviceToDevice, c->stream));
+    }
+  }
+  return 0;
+}
+
+static int enqueue_step_pipe(ww_ctx* c) {
+  int rc = 0;
+  const int nst = c->nst, L = c->lag;
+  hipStream_t s0 = c->stream;
+  for (int s = 0; s < nst && !rc; ++s) {
+    g_prof_stage = s;
+    const Fac F = pipe_set(c, s, false);
+    const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
+    hipStream_t ls = c->lus[s % L];
+    if ((rc = prof_mark(c, 1, 0))) break;
+    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->y, c->K, c->Ys, c->coef, s,
+                       kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
+    if (hipGetLastError() != hipSuccess) {
+      rc = fail(WW_EHIP, "kernel launch: k_base_prep");
+      break;
+    }
+    if ((rc = enqueue_assemble(c, F, true))) break;
+    // the LU of this stage on its stream
+    if (hipEventRecord(c->evA[s], s0) != hipSuccess || hipStreamWaitEvent(ls, c->evA[s], 0) != hipSuccess) {
+      rc = fail(WW_EHIP, "pipeline: event record / wait");
+      break;
+    }
+    c->stream = ls;
+    rc = enqueue_lu(c, F);
+    c->stream = s0;
+    if (rc) break;
+    if (hipEventRecord(c->evL[s], ls) != hipSuccess) {
+      rc = fail(WW_EHIP, "pipeline: event record");
+      break;
+    }
+    // base solve with the factors of stage s - L (of the previous step for s < L)
+    if (s >= L && hipStreamWaitEvent(s0, c->evL[s - L], 0) != hipSuccess) {
+      rc = fail(WW_EHIP, "pipeline: event wait");
+      break;
+    }
+    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0))) break;
+    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->mu0, c->Np, 1, c->gam0, c->hg0,
+                       c->tw, c->N);
+    if (hipGetLastError() != hipSuccess) {
+      rc = fail(WW_EHIP, "kernel launch: k_gamma");
+      break;
+    }
+    if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) break;
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->Ys, c->gphi0, F.aux, c->n_max,
+                       c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
+    if (hipGetLastError() != hipSuccess) {
+      rc = fail(WW_EHIP, "kernel launch: k_base_rhs");
+      break;
+    }
+    if ((rc = prof_mark(c, 1, 1))) break;
+    // the column chain with this stage's own factors
+    if (hipEventRecord(c->evB[s], s0) != hipSuccess || hipStreamWaitEvent(c->side, c->evB[s], 0) != hipSuccess ||
+        hipStreamWaitEvent(c->side, c->evL[s], 0) != hipSuccess) {
+      rc = fail(WW_EHIP, "pipeline: event record / wait");
+      break;
+    }
+    c->stream = c->side;
+    rc = enqueue_col_chain(c, s, pipe_set(c, s, true));
+    c->stream = s0;
+    if (rc) break;
+    if (hipEventRecord(c->evC[s], c->side) != hipSuccess) rc = fail(WW_EHIP, "pipeline: event record");
+  }
+  g_prof_stage = -1;
+  if (rc) return rc;
+  // the column chains waited for every LU: one wait joins all streams
+  HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
+  hipLaunchKernelGGL(k_step_end, dim3(c->M + 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), s0, c->y, c->K, kstride(c), nst,
+                     c->coef, c->tw, c->sig, c->N, 0, c->status);
+  LAUNCHCHK();
+  return 0;
+}
+
 // two_streams: the column chain of stage s runs on the side stream while stage s + 1
 // refactors (single instances); otherwise it follows the base chain on one stream
 // (batches, where the instances overlap each other instead).
 static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
+  if (pipelined(c, cols, two_streams)) return enqueue_step_pipe(c);
   int rc;
   const bool two = cols && c->M > 0 && two_streams;
   hipStream_t s0 = c->stream;
@@ -682,6 +901,7 @@ static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
       c->gtwo == (int)two_streams && c->gfb == c->fb)
     return 0;
   if (c->step_exec) {
+    HIPCHK(hipDeviceSynchronize());   // every branch of its last replay has ended
     HIPCHK(hipGraphExecDestroy(c->step_exec));
     c->step_exec = nullptr;
   }
@@ -891,6 +1111,10 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
   LAUNCHCHK();
+  if (pipelined(c, cols, two_streams)) {
+    if ((rc = ensure_pipe(c))) return rc;
+    if ((rc = pipe_prologue(c))) return rc;
+  }
   if (graphed(c)) return ensure_step_graph(c, cols, two_streams);
   return 0;
 }
@@ -927,11 +1151,13 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
 }
 
 // Status bits of a march: 1 pivot below the guard (unpivoted LU), 8 pivot below the
-// guard (pivoted LU), 2 non-finite state, 4 failed refinement test.  The fallback that
-// a redo of the call takes, or 0.
+// guard (pivoted LU), 2 non-finite state, 4 failed refinement test (mixed form), 16
+// surface through the bottom, 32 failed refinement test of a lagged-factor solve.  The
+// fallback that a redo of the call takes, or 0.
 static unsigned next_fallback(const ww_ctx* c, int st) {
   if (strict(c) || (st & 16)) return 0;   // a surface through the bottom is no factorisation issue
   if ((st & (1 | 8)) && !pivoted(c)) return WW_FB_PIVOTED | WW_FB_FP64;
+  if ((st & 32) && !(c->fb & WW_FB_DIRECT)) return WW_FB_DIRECT;
   if ((st & 4) && !(c->fb & WW_FB_FP64)) return WW_FB_FP64;
   return 0;
 }
@@ -944,6 +1170,7 @@ static int status_error(const ww_ctx* c, int st, int where) {
     return fail(WW_ENONFINITE, "non-finite value in the marched state" + (at.empty() ? std::string(" (at T/4)") : at));
   if (st & (1 | 8)) return fail(WW_EPIVOT, pivoted(c) ? MSG_PIVOT2 : MSG_PIVOT);
   if (st & 4) return fail(WW_EREFINE, MSG_REFINE);
+  if (st & 32) return fail(WW_EREFINE, "lagged-factor solves: relative residual above 2^-43 (WW_STRICT)");
   return 0;
 }
 
@@ -952,11 +1179,21 @@ static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, doub
                      double* f, int* st, int* where) {
   const bool cols = (J != nullptr) && c->M > 0;
   const bool two = c->overlap && !pivoted(c);
+  const bool pipe = pipelined(c, cols, two);
   int rc;
   if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
   if ((rc = shoot_prepare(c, params, T, nsteps, cols, two))) return rc;
-  for (int n = 0; n < nsteps; ++n)
+  for (int n = 0; n < nsteps; ++n) {
     if ((rc = shoot_one_step(c, cols, two))) return rc;
+    if (pipe && n == 0 && nsteps > 1) {
+      // lagged factors that do not converge show in the first step: stop there (the
+      // caller redoes the march in its fallback mode or reports the status)
+      int peek = 0;
+      HIPCHK(hipStreamSynchronize(c->stream));
+      HIPCHK(hipMemcpy(&peek, c->status, sizeof(int), hipMemcpyDeviceToHost));
+      if (peek) return read_status(c, st, where);
+    }
+  }
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
   return read_status(c, st, where);
 }

@@ -1681,7 +1681,8 @@ __global__ void k_save_aux(const double* __restrict__ aux, int nmax, int N, doub
 // fails, or a NaN, sets status bit 4 (reported as WW_EREFINE).
 // -------------------------------------------------------------------------------------
 __global__ __launch_bounds__(WW_NT) void k_refine_check(const double* __restrict__ r, const double* __restrict__ B,
-                                                        int Np, int N, double tol, int* __restrict__ status) {
+                                                        int Np, int N, double tol, int* __restrict__ status,
+                                                        int flag) {
   __shared__ double rr[WW_NT], rb[WW_NT];
   const double* rc = r + (size_t)blockIdx.x * Np;
   const double* bc = B + (size_t)blockIdx.x * Np;
@@ -1701,7 +1702,7 @@ __global__ __launch_bounds__(WW_NT) void k_refine_check(const double* __restrict
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0 && !(rr[0] <= tol * rb[0])) atomicOr(status, 4);
+  if (threadIdx.x == 0 && !(rr[0] <= tol * rb[0])) atomicOr(status, flag);
 }
 
 // -------------------------------------------------------------------------------------

@@ -21,6 +21,7 @@ WW_MIXED = 1
 WW_STRICT = 2
 WW_FB_PIVOTED = 1
 WW_FB_FP64 = 2
+WW_FB_DIRECT = 4
 
 _ERRORS = {
     -1: "WW_EINVAL", -2: "WW_ENOSETUP", -3: "WW_EHIP", -4: "WW_EDOMAIN",
