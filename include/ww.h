@@ -45,6 +45,7 @@ typedef struct ww_ctx ww_ctx;
                               (A numerically singular) */
 #define WW_EREFINE (-7)    /* mixed precision, WW_STRICT context: refinement did not reach
                               its tolerance (without WW_STRICT the FP64 fallback runs) */
+#define WW_ENOCONV (-8)    /* an iteration did not converge (thin SVD) */
 
 /* context flags */
 #define WW_FP64 0u         /* LU, triangular solves, everything in FP64 */
@@ -209,6 +210,59 @@ int ww_profile_read(ww_ctx *ctx, int phase, double *avg_ms, int *count);
  * the results come from the context's own path.  Host only.  Errors: WW_EINVAL.
  */
 int ww_fallbacks(ww_ctx *ctx, unsigned *bits);
+
+/*
+ * ww_thin_svd (App. C: J = U S V^T): thin singular value decomposition of the tall
+ * matrix A (device, N x n column-major, ld N; 1 <= n <= N <= n_max, n <= r_max) by
+ * one-sided Jacobi rotations on the GPU (sweeps until every column pair is orthogonal
+ * to 1e-15 relative).  sigma (host, n): singular values in descending order.  V (host,
+ * n x n column-major, or NULL): right singular vectors.  U (device, N x n, or NULL):
+ * left singular vectors (zero column for a zero singular value).  A is not modified.
+ * Synchronises.  Errors: WW_EINVAL, WW_ENONFINITE (non-finite entry), WW_ENOCONV,
+ * WW_EHIP.
+ */
+int ww_thin_svd(ww_ctx *ctx, const double *A, int N, int n, double *sigma, double *V, double *U);
+
+/*
+ * Levenberg-Marquardt trust-region driver with delayed Jacobian updates (Sec. 3.3,
+ * App. C) on the shooting problem of shoot_setup: it minimises f(c) = r.r/2 over
+ * c = (T, params[0..M-1]), with the residual r and the Jacobian [dr/dT | dr/dparams]
+ * from shoot_eval (nsteps steps, dt = T / (4 nsteps)).  Each trust-region subproblem is
+ * solved through the thin SVD of J (eq. (trust:tilde)) by Newton's method on
+ * tau(lambda) = 1/||p~|| - 1/Delta; J is re-used over accepted steps and re-computed
+ * by the rules of App. C (1-4) with the parameters of ww_lm_opts.  Singular values below
+ * (M + 1) eps sigma_max count as zero.
+ * c (host, M + 1): T, then the parameters; the starting point on entry, the result on
+ * return.  opts: NULL for the defaults (ww_lm_default_opts).  rep (or NULL): the final
+ * f and radius, evaluation counts, the reason of termination (WW_LM_*), and optionally
+ * the history of tried steps: rows of (c_new[M + 1], f(c_new), accepted) in
+ * history (host, hist_cap rows of M + 3 doubles; n_hist counts every tried step).
+ * Synchronises.  Errors: those of shoot_eval and ww_thin_svd, WW_ENOSETUP, WW_EINVAL.
+ */
+typedef struct ww_lm_opts {
+  double f_tol;       /* roundoff regime when f < f_tol (App. C: 1e-26) */
+  double g_tol;       /* ... or Delta < g_tol, or on a fresh J ||g|| < g_tol (1e-13) */
+  double df_tol;      /* ... or on a fresh J |df|/f < df_tol; J re-computation (1e-5) */
+  double delta0;      /* initial trust-region radius (0.1) */
+  int max_steps_J;    /* accepted steps per Jacobian (10) */
+  int max_evals;      /* cap on residual + Jacobian evaluations (200) */
+} ww_lm_opts;
+
+typedef struct ww_lm_report {
+  double f, delta;
+  int evals_r, evals_J, reason, n_hist;
+  double *history;    /* host, or NULL */
+  int hist_cap;
+} ww_lm_report;
+
+#define WW_LM_F_ZERO 1
+#define WW_LM_C_UNCHANGED 2
+#define WW_LM_ROUNDOFF_REJECTED 3
+#define WW_LM_ROUNDOFF_MAX_STEPS_J 4
+#define WW_LM_MAX_EVALS 5
+
+int ww_lm_default_opts(ww_lm_opts *opts);
+int ww_levmar(ww_ctx *ctx, double *c, int nsteps, const ww_lm_opts *opts, ww_lm_report *rep);
 
 /* thread-local message of the last failure on this thread ("" if none) */
 const char *ww_last_error(void);

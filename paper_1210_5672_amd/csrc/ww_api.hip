@@ -11,6 +11,10 @@
 
 #include "ww.h"
 #include "ww_kernels.hpp"
+#include "ww_svd.hpp"
+
+#include <algorithm>
+#include <numeric>
 
 static thread_local std::string g_err;
 
@@ -129,6 +133,11 @@ struct ww_ctx {
   RingSet ring[16];
   hipStream_t lus[PIPE_MAXLAG] = {};
   hipEvent_t evA[16] = {}, evL[16] = {};
+  // thin SVD / Levenberg-Marquardt workspace (first use): W (n_max x r_max), residuals,
+  // parameters, V (r_max^2), column norms and dots, convergence flag, column order
+  double *lmW = nullptr, *lmr = nullptr, *lmrn = nullptr, *lmp = nullptr, *lmV = nullptr;
+  double *lmsig = nullptr, *lmdot = nullptr;
+  int *lmflag = nullptr, *lmperm = nullptr;
 };
 
 static bool valid_n(int N) {
@@ -1482,6 +1491,281 @@ int shoot_adjoint(ww_ctx* c, const double* params, double T, int nsteps, int ckp
 int ww_fallbacks(ww_ctx* c, unsigned* bits) {
   if (!c || !bits) return fail(WW_EINVAL, "null argument");
   *bits = c->fb_last;
+  return 0;
+}
+
+}  // extern "C"
+
+// ----- thin SVD and the Levenberg-Marquardt driver (App. C) -----
+static const double SVD_TOL = 1e-15;     // pair orthogonality |w_a.w_b| <= tol ||w_a|| ||w_b||
+static const int SVD_MAX_SWEEPS = 60;
+
+static int ensure_lm(ww_ctx* c) {
+  if (c->lmW) return 0;
+  int rc;
+  const size_t nm = c->n_max, R = c->r_max;
+  if ((rc = dalloc(c, (void**)&c->lmW, nm * R * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmr, nm * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmrn, nm * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmp, R * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmV, R * R * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmsig, R * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmdot, R * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->lmflag, 64))) return rc;
+  return dalloc(c, (void**)&c->lmperm, R * sizeof(int));
+}
+
+// One-sided Jacobi on W (N x n, device) with V := rotations (device); sweeps until no
+// pair rotates.  Non-finite input: WW_ENONFINITE.
+static int jacobi_svd(ww_ctx* c, double* W, int N, int n, double* V) {
+  {
+    hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, W, (size_t)N * n, c->status);
+    LAUNCHCHK();
+    int st = 0;
+    int rc;
+    if ((rc = read_status(c, &st))) return rc;
+    if (st & 2) return fail(WW_ENONFINITE, "thin SVD: non-finite matrix entry");
+  }
+  const int n2 = (n + 1) & ~1;
+  hipLaunchKernelGGL(k_svd_eye, dim3(std::max(1, std::min(1024, (n * n + 255) / 256))), dim3(256), 0, c->stream, V, n);
+  LAUNCHCHK();
+  if (n < 2) return 0;
+  for (int sw = 0; sw < SVD_MAX_SWEEPS; ++sw) {
+    HIPCHK(hipMemsetAsync(c->lmflag, 0, sizeof(int), c->stream));
+    for (int rd = 0; rd + 1 < n2; ++rd) {
+      hipLaunchKernelGGL(k_jacobi_round, dim3(n2 / 2), dim3(SVD_NT), 0, c->stream, W, N, V, n, n2, rd, SVD_TOL,
+                         c->lmflag);
+      LAUNCHCHK();
+    }
+    int h = 0;
+    HIPCHK(hipMemcpyAsync(&h, c->lmflag, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    if (!h) return 0;
+  }
+  return fail(WW_ENOCONV, "thin SVD: Jacobi sweeps did not converge");
+}
+
+// Levenberg-Marquardt state on the host: the SVD of the current Jacobian (sigma, V) and
+// the residual r on the device (c->lmr).
+struct LmSvd {
+  int n = 0;
+  std::vector<double> s, V;   // singular values (small ones zeroed), V column-major
+};
+
+// Jacobian at cv: r -> c->lmr, J = [dr/dT | dr/dparams] -> c->lmW, then its SVD
+static int lm_jacobian(ww_ctx* c, const std::vector<double>& cv, int nsteps, double* f, LmSvd& sv) {
+  const int N = c->N, M = c->M, n = M + 1;
+  int rc;
+  if (M > 0) HIPCHK(hipMemcpyAsync(c->lmp, cv.data() + 1, (size_t)M * 8, hipMemcpyHostToDevice, c->stream));
+  if ((rc = shoot_eval(c, c->lmp, cv[0], nsteps, c->lmr, M > 0 ? c->lmW + N : nullptr, c->lmW, f))) return rc;
+  if ((rc = jacobi_svd(c, c->lmW, N, n, c->lmV))) return rc;
+  hipLaunchKernelGGL(k_svd_cols, dim3(n), dim3(SVD_NT), 0, c->stream, c->lmW, N, nullptr, c->lmsig, nullptr);
+  LAUNCHCHK();
+  sv.n = n;
+  sv.s.assign(n, 0.0);
+  sv.V.assign((size_t)n * n, 0.0);
+  HIPCHK(hipMemcpyAsync(sv.s.data(), c->lmsig, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(sv.V.data(), c->lmV, (size_t)n * n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  const double smax = *std::max_element(sv.s.begin(), sv.s.end());
+  const double cut = n * 2.220446049250313e-16 * smax;   // small singular values count as zero
+  for (double& x : sv.s)
+    if (x < cut) x = 0.0;
+  return 0;
+}
+
+// r~ = U^T r = (W^T r) / sigma for the residual on the device at rdev
+static int lm_rtilde(ww_ctx* c, const double* rdev, const LmSvd& sv, std::vector<double>& rt) {
+  const int n = sv.n;
+  hipLaunchKernelGGL(k_svd_cols, dim3(n), dim3(SVD_NT), 0, c->stream, c->lmW, c->N, rdev, nullptr, c->lmdot);
+  LAUNCHCHK();
+  rt.assign(n, 0.0);
+  HIPCHK(hipMemcpyAsync(rt.data(), c->lmdot, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  for (int k = 0; k < n; ++k) rt[k] = sv.s[k] > 0.0 ? rt[k] / sv.s[k] : 0.0;
+  return 0;
+}
+
+// eq. (trust:tilde): p~ = -sigma r~ / (sigma^2 + lambda), lambda by Newton's method on
+// tau(lambda) = 1/||p~|| - 1/Delta from lambda = 0 (the Newton step of tau divides by
+// p~^T (S^2 + lambda)^{-1} p~)
+static void trust_subproblem(const std::vector<double>& s, const std::vector<double>& rt, double delta,
+                             std::vector<double>& p) {
+  const int n = (int)s.size();
+  auto step = [&](double lam) {
+    for (int k = 0; k < n; ++k) p[k] = s[k] > 0.0 ? -s[k] * rt[k] / (s[k] * s[k] + lam) : 0.0;
+  };
+  auto norm = [&]() {
+    double a = 0.0;
+    for (double x : p) a += x * x;
+    return std::sqrt(a);
+  };
+  p.assign(n, 0.0);
+  step(0.0);
+  if (norm() <= delta) return;
+  double lam = 0.0;
+  for (int it = 0; it < 200; ++it) {
+    const double pn = norm();
+    if (std::fabs(pn - delta) / delta <= 1e-12) break;
+    double q = 0.0;
+    for (int k = 0; k < n; ++k)
+      if (s[k] > 0.0) q += p[k] * p[k] / (s[k] * s[k] + lam);
+    lam += (pn * pn / q) * ((pn - delta) / delta);
+    step(lam);
+  }
+}
+
+extern "C" {
+
+int ww_thin_svd(ww_ctx* c, const double* A, int N, int n, double* sigma, double* V, double* U) {
+  if (!c || !A || !sigma) return fail(WW_EINVAL, "null argument");
+  if (N < 1 || n < 1 || n > N || N > c->n_max || n > c->r_max)
+    return fail(WW_EINVAL, "thin SVD: need 1 <= n <= N, N <= n_max, n <= r_max");
+  int rc;
+  if ((rc = ensure_lm(c))) return rc;
+  HIPCHK(hipMemcpyAsync(c->lmW, A, (size_t)N * n * 8, hipMemcpyDeviceToDevice, c->stream));
+  if ((rc = jacobi_svd(c, c->lmW, N, n, c->lmV))) return rc;
+  hipLaunchKernelGGL(k_svd_cols, dim3(n), dim3(SVD_NT), 0, c->stream, c->lmW, N, nullptr, c->lmsig, nullptr);
+  LAUNCHCHK();
+  std::vector<double> s(n), v((size_t)n * n);
+  HIPCHK(hipMemcpyAsync(s.data(), c->lmsig, (size_t)n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(v.data(), c->lmV, (size_t)n * n * 8, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<int> perm(n);
+  std::iota(perm.begin(), perm.end(), 0);
+  std::stable_sort(perm.begin(), perm.end(), [&](int a, int b) { return s[a] > s[b]; });
+  for (int k = 0; k < n; ++k) sigma[k] = s[perm[k]];
+  if (V)
+    for (int k = 0; k < n; ++k) std::memcpy(V + (size_t)k * n, v.data() + (size_t)perm[k] * n, (size_t)n * 8);
+  if (U) {
+    HIPCHK(hipMemcpyAsync(c->lmperm, perm.data(), (size_t)n * sizeof(int), hipMemcpyHostToDevice, c->stream));
+    const size_t tot = (size_t)N * n;
+    hipLaunchKernelGGL(k_svd_u, dim3((int)std::min<size_t>((tot + 255) / 256, 4096)), dim3(256), 0, c->stream, c->lmW,
+                       N, c->lmsig, c->lmperm, n, U);
+    LAUNCHCHK();
+    HIPCHK(hipStreamSynchronize(c->stream));   // perm is a host temporary of this call
+  }
+  return 0;
+}
+
+int ww_levmar(ww_ctx* c, double* cvec, int nsteps, const ww_lm_opts* opts, ww_lm_report* rep) {
+  if (!c || !cvec) return fail(WW_EINVAL, "null argument");
+  if (!c->shoot_ready) return fail(WW_ENOSETUP, "ww_levmar before shoot_setup");
+  if (nsteps < 1) return fail(WW_EINVAL, "nsteps >= 1 required");
+  ww_lm_opts o;
+  ww_lm_default_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.delta0 > 0.0) || o.max_steps_J < 1 || o.max_evals < 1) return fail(WW_EINVAL, "bad options");
+  int rc;
+  if ((rc = ensure_lm(c))) return rc;
+  const int M = c->M, n = M + 1;
+  const double RHO0 = 0.25, RHO1 = 0.85, A0 = 3.0 / 8.0, A1 = 1.875, A2 = 0.2;
+  std::vector<double> cv(cvec, cvec + n), cn(n), rt, pt, p(n), g(n);
+  LmSvd sv;
+  double f = 0.0, fn = 0.0;
+  if ((rc = lm_jacobian(c, cv, nsteps, &f, sv))) return rc;
+  int evals_r = 0, evals_J = 1, steps_J = 0, nh = 0, reason = 0;
+  double delta = o.delta0, dfr = -1.0;   // dfr < 0: delta_first_rejected undefined
+  bool roundoff = false, acc_since_J = false;
+  for (;;) {
+    if (f == 0.0) {
+      reason = WW_LM_F_ZERO;
+      break;
+    }
+    if (evals_r + evals_J >= o.max_evals) {
+      reason = WW_LM_MAX_EVALS;
+      break;
+    }
+    if ((rc = lm_rtilde(c, c->lmr, sv, rt))) return rc;
+    trust_subproblem(sv.s, rt, delta, pt);
+    double df = 0.0, gn = 0.0, pn = 0.0;
+    for (int k = 0; k < n; ++k) df += sv.s[k] * rt[k] * pt[k] + 0.5 * (sv.s[k] * pt[k]) * (sv.s[k] * pt[k]);
+    for (int i = 0; i < n; ++i) {
+      double a = 0.0, b = 0.0;
+      for (int k = 0; k < n; ++k) {
+        a += sv.V[(size_t)k * n + i] * pt[k];
+        b += sv.V[(size_t)k * n + i] * sv.s[k] * rt[k];
+      }
+      p[i] = a;
+      g[i] = b;
+      pn += a * a;
+      gn += b * b;
+    }
+    pn = std::sqrt(pn);
+    gn = std::sqrt(gn);
+    if (f < o.f_tol || delta < o.g_tol) roundoff = true;
+    if (steps_J == 0 && (gn < o.g_tol || std::fabs(df) / f < o.df_tol)) roundoff = true;
+    bool same = true;
+    for (int i = 0; i < n; ++i) {
+      cn[i] = cv[i] + p[i];
+      if (cn[i] != cv[i]) same = false;
+    }
+    if (same) {
+      reason = WW_LM_C_UNCHANGED;
+      break;
+    }
+    if (M > 0) HIPCHK(hipMemcpyAsync(c->lmp, cn.data() + 1, (size_t)M * 8, hipMemcpyHostToDevice, c->stream));
+    if ((rc = shoot_eval(c, c->lmp, cn[0], nsteps, c->lmrn, nullptr, nullptr, &fn))) return rc;
+    ++evals_r;
+    const double rho = df != 0.0 ? (fn - f) / df : -1.0;
+    const bool accepted = rho > 0.0;
+    if (rep && rep->history && nh < rep->hist_cap) {
+      double* h = rep->history + (size_t)nh * (n + 2);
+      for (int i = 0; i < n; ++i) h[i] = cn[i];
+      h[n] = fn;
+      h[n + 1] = accepted ? 1.0 : 0.0;
+    }
+    ++nh;
+    if (accepted) acc_since_J = true;
+    if (rho < RHO0) {
+      if (dfr < 0.0 && acc_since_J) dfr = delta;
+      delta = A0 * pn;
+    } else if (rho > RHO1 && pn > 0.9 * delta) {
+      delta = A1 * delta;
+    }
+    if (accepted) {
+      cv = cn;
+      f = fn;
+      std::swap(c->lmr, c->lmrn);
+      ++steps_J;
+    }
+    if (roundoff && (!accepted || steps_J >= o.max_steps_J)) {
+      reason = accepted ? WW_LM_ROUNDOFF_MAX_STEPS_J : WW_LM_ROUNDOFF_REJECTED;
+      break;
+    }
+    const double trigger = dfr >= 0.0 ? A2 * dfr : -INFINITY;
+    if (!roundoff && (steps_J >= o.max_steps_J || (steps_J > 0 && delta < trigger) ||
+                      (steps_J > 0 && f > 0.0 && std::fabs(df) / f < o.df_tol))) {
+      if (dfr >= 0.0) delta = dfr / A1;
+      if ((rc = lm_jacobian(c, cv, nsteps, &f, sv))) return rc;
+      ++evals_J;
+      steps_J = 0;
+      dfr = -1.0;
+      acc_since_J = false;
+    }
+  }
+  for (int i = 0; i < n; ++i) cvec[i] = cv[i];
+  if (rep) {
+    rep->f = f;
+    rep->delta = delta;
+    rep->evals_r = evals_r;
+    rep->evals_J = evals_J;
+    rep->reason = reason;
+    rep->n_hist = nh;
+  }
+  return 0;
+}
+
+int ww_lm_default_opts(ww_lm_opts* o) {
+  if (!o) return fail(WW_EINVAL, "null argument");
+  o->f_tol = 1e-26;
+  o->g_tol = 1e-13;
+  o->df_tol = 1e-5;
+  o->delta0 = 0.1;
+  o->max_steps_J = 10;
+  o->max_evals = 200;
   return 0;
 }
 

@@ -25,12 +25,26 @@ WW_FB_DIRECT = 4
 
 _ERRORS = {
     -1: "WW_EINVAL", -2: "WW_ENOSETUP", -3: "WW_EHIP", -4: "WW_EDOMAIN",
-    -5: "WW_ENONFINITE", -6: "WW_EPIVOT", -7: "WW_EREFINE",
+    -5: "WW_ENONFINITE", -6: "WW_EPIVOT", -7: "WW_EREFINE", -8: "WW_ENOCONV",
 }
+LM_REASONS = {1: "f=0", 2: "c unchanged", 3: "roundoff: rejected", 4: "roundoff: max_stepsJ",
+              5: "max_evals"}
+
+
+class LmOpts(ctypes.Structure):
+    _fields_ = [("f_tol", ctypes.c_double), ("g_tol", ctypes.c_double), ("df_tol", ctypes.c_double),
+                ("delta0", ctypes.c_double), ("max_steps_J", ctypes.c_int), ("max_evals", ctypes.c_int)]
+
+
+class LmReport(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_double), ("delta", ctypes.c_double), ("evals_r", ctypes.c_int),
+                ("evals_J", ctypes.c_int), ("reason", ctypes.c_int), ("n_hist", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int)]
 
 EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_setup",
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
-           "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks"]
+           "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
+           "ww_thin_svd", "ww_levmar", "ww_lm_default_opts"]
 
 
 class WWError(RuntimeError):
@@ -69,10 +83,14 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ww_profile.argtypes = [P, I]
     lib.ww_profile_read.argtypes = [P, I, DP, ctypes.POINTER(ctypes.c_int)]
     lib.ww_fallbacks.argtypes = [P, ctypes.POINTER(U)]
+    lib.ww_thin_svd.argtypes = [P, P, I, I, DP, DP, P]
+    lib.ww_levmar.argtypes = [P, DP, I, ctypes.POINTER(LmOpts), ctypes.POINTER(LmReport)]
+    lib.ww_lm_default_opts.argtypes = [ctypes.POINTER(LmOpts)]
     lib.ww_last_error.restype = ctypes.c_char_p
     lib.ww_version.restype = ctypes.c_char_p
     for name in ["ww_create", "ww_set_stream", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
-                 "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read", "ww_fallbacks"]:
+                 "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read", "ww_fallbacks",
+                 "ww_thin_svd", "ww_levmar", "ww_lm_default_opts"]:
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -199,6 +217,37 @@ class Context:
         b = ctypes.c_uint(0)
         _check(self.lib.ww_fallbacks(self.ptr, ctypes.byref(b)))
         return b.value
+
+    def thin_svd(self, A: torch.Tensor, want_u: bool = False):
+        """A: (N, n) tensor (column-major storage is made here).  Returns (sigma, V, U):
+        sigma (n,) descending and V (n, n) as NumPy arrays, U (N, n) on the device or None."""
+        N, n = A.shape
+        cm = self._keep(A.t().contiguous())
+        sig = np.zeros(n)
+        V = np.zeros((n, n), order="F")
+        U = torch.empty((n, N), dtype=torch.float64, device=A.device) if want_u else None
+        _check(self.lib.ww_thin_svd(self.ptr, _ptr(cm), N, n, _dp(sig), _dp(V), _ptr(U)))
+        return sig, V, (U.t() if want_u else None)
+
+    def levmar(self, c0, nsteps: int, opts: dict | None = None, hist_cap: int = 0):
+        """Levenberg-Marquardt with delayed Jacobian updates on the shooting problem of
+        shoot_setup.  c0 = (T, params...).  Returns dict(c, f, delta, evals_r, evals_J,
+        reason, history) -- history rows (c_new, f_new, accepted) of the tried steps."""
+        n = self.M + 1
+        c = np.ascontiguousarray(np.array(c0, dtype=np.float64))
+        assert c.shape == (n,)
+        o = LmOpts()
+        _check(self.lib.ww_lm_default_opts(ctypes.byref(o)))
+        for k, v in (opts or {}).items():
+            setattr(o, k, v)
+        h = np.zeros((max(hist_cap, 1), n + 2))
+        rep = LmReport()
+        rep.history = _dp(h) if hist_cap > 0 else None
+        rep.hist_cap = hist_cap
+        _check(self.lib.ww_levmar(self.ptr, _dp(c), int(nsteps), ctypes.byref(o), ctypes.byref(rep)))
+        return dict(c=c, f=rep.f, delta=rep.delta, evals_r=rep.evals_r, evals_J=rep.evals_J,
+                    reason=LM_REASONS.get(rep.reason, rep.reason),
+                    history=h[:min(rep.n_hist, hist_cap)] if hist_cap > 0 else None)
 
     def profile(self, enable: bool = True):
         _check(self.lib.ww_profile(self.ptr, 1 if enable else 0))

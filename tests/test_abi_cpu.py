@@ -54,3 +54,13 @@ def test_argument_errors_without_gpu():
     assert lib.ww_create(ctypes.byref(out), 4096, 4, 0, None) == -1    # above 2048
     assert lib.ww_create(ctypes.byref(out), 64, 4, 8, None) == -1      # unknown flag
     assert lib.ww_fallbacks(None, None) == -1
+    assert lib.ww_levmar(None, None, 1, None, None) == -1
+    assert lib.ww_thin_svd(None, None, 4, 2, None, None, None) == -1
+
+
+def test_levenberg_marquardt_defaults_are_the_papers():
+    """App. C: f_tol = 1e-26, g_tol = 1e-13, max_stepsJ = 10, df_tol = 1e-5 (host only)."""
+    ww, lib = _lib()
+    o = ww.LmOpts()
+    assert lib.ww_lm_default_opts(ctypes.byref(o)) == 0
+    assert (o.f_tol, o.g_tol, o.df_tol, o.max_steps_J) == (1e-26, 1e-13, 1e-5, 10)

@@ -1,0 +1,124 @@
+"""Pins of the Levenberg-Marquardt oracle (App. C) against mathematics that does not
+pass through its own formulas: the trust-region subproblem against bisection on
+||p(lambda)|| = Delta and the normal equations (J^T J + lambda I) p = -J^T r; the
+driver against least squares (lstsq) and against a zero-residual nonlinear fit with a
+known solution; a small standing wave against the linear period."""
+import math
+
+import numpy as np
+import pytest
+import scipy.optimize as so
+
+from oracle import lm_oracle as L
+
+
+def test_trust_subproblem_interior_and_boundary():
+    rng = np.random.default_rng(1)
+    s = np.sort(rng.uniform(0.01, 3.0, 12))[::-1]
+    rt = rng.standard_normal(12)
+    big = 10 * np.linalg.norm(rt / s)
+    p, lam = L.trust_subproblem(s, rt, big)
+    assert lam == 0.0
+    assert np.allclose(p, -rt / s, rtol=1e-15, atol=0)
+    for delta in (1e-3, 0.1, 0.5 * np.linalg.norm(rt / s)):
+        p, lam = L.trust_subproblem(s, rt, delta)
+        assert abs(np.linalg.norm(p) - delta) <= 1e-11 * delta
+        # the root of ||p(lambda)|| - Delta by bisection (no Newton, no derivative)
+        h = lambda x: np.linalg.norm(-s * rt / (s * s + x)) - delta
+        lb = so.brentq(h, 0.0, 1e12, xtol=1e-15, rtol=1e-15)
+        assert abs(lam - lb) <= 1e-9 * max(lb, 1.0)
+
+
+def test_full_space_step_satisfies_the_normal_equations():
+    rng = np.random.default_rng(2)
+    J = rng.standard_normal((40, 7)) @ np.diag([3, 2, 1, 0.5, 0.1, 0.01, 1e-3])
+    r = rng.standard_normal(40)
+    U, s, V = L.thin_svd(J)
+    delta = 0.05
+    pt, lam = L.trust_subproblem(s, U.T @ r, delta)
+    p = V @ pt
+    assert lam > 0
+    assert abs(np.linalg.norm(p) - delta) <= 1e-11 * delta
+    lhs = (J.T @ J + lam * np.eye(7)) @ p
+    assert np.allclose(lhs, -J.T @ r, rtol=1e-9, atol=1e-12 * np.abs(J.T @ r).max())
+
+
+def test_levmar_linear_least_squares():
+    rng = np.random.default_rng(3)
+    A = rng.standard_normal((30, 5))
+    cstar = rng.standard_normal(5)
+    b = A @ cstar                                  # consistent: f* = 0
+    res = L.levmar(lambda c: A @ c - b, lambda c: (A @ c - b, A), np.zeros(5), delta0=0.1)
+    assert np.allclose(res.c, np.linalg.lstsq(A, b, rcond=None)[0], rtol=1e-12, atol=1e-13)
+    assert res.f < 1e-26
+    b2 = b + 0.1 * rng.standard_normal(30)        # inconsistent: f* > 0
+    res2 = L.levmar(lambda c: A @ c - b2, lambda c: (A @ c - b2, A), np.zeros(5), delta0=0.1)
+    c2 = np.linalg.lstsq(A, b2, rcond=None)[0]
+    assert np.allclose(res2.c, c2, rtol=1e-10, atol=1e-12)
+    assert abs(res2.f - 0.5 * np.sum((A @ c2 - b2) ** 2)) <= 1e-12 * res2.f
+
+
+def test_levmar_nonlinear_zero_residual_fit_reuses_the_jacobian():
+    t = np.linspace(0, 2, 25)
+    cstar = np.array([1.5, -0.7, 0.3])
+    y = cstar[0] * np.exp(cstar[1] * t) + cstar[2]
+
+    def res(c):
+        return c[0] * np.exp(c[1] * t) + c[2] - y
+
+    def jac(c):
+        e = np.exp(c[1] * t)
+        return res(c), np.stack([e, c[0] * t * e, np.ones_like(t)], axis=1)
+
+    out = L.levmar(res, jac, np.array([1.0, -0.5, 0.0]), delta0=0.5)
+    assert np.allclose(out.c, cstar, rtol=1e-12, atol=1e-13)
+    assert out.f < 1e-26
+    assert out.evals_J < out.evals_r          # delayed Jacobian updates (App. C)
+
+
+def standing_wave_problem(N=32, nsteps=12, a1=1e-3, nmodes=6):
+    """The paper's standing-wave parametrisation (eq. (init:stand), reading R4): eta
+    even modes, phi odd modes, basis 2 cos(k alpha); c_1 = phi^_1 fixed (amplitude);
+    unknowns T and c_2..c_nmodes; infinite depth, g = 1, tau = 0."""
+    from oracle import ww_oracle as O
+    a = 2 * np.pi * np.arange(N) / N
+    ks = list(range(2, nmodes + 1))
+    basis = np.zeros((2 * N, len(ks)))
+    for j, k in enumerate(ks):
+        if k % 2 == 0:
+            basis[:N, j] = 2 * np.cos(k * a)
+        else:
+            basis[N:, j] = 2 * np.cos(k * a)
+    qf = np.concatenate([np.zeros(N), 2 * a1 * np.cos(a)])
+
+    def jac(c):
+        out = O.shoot_eval(N, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], nsteps, jacobian=True)
+        return out["r"], np.concatenate([out["drdT"][:, None], out["J"]], axis=1)
+
+    def res(c):
+        return O.shoot_eval(N, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], nsteps, jacobian=False)["r"]
+
+    return res, jac, np.concatenate([[2 * np.pi], np.zeros(len(ks))])
+
+
+def test_levmar_small_standing_wave_converges_near_the_linear_period():
+    """At amplitude c_1 = 1e-3 the period differs from the linear one (2 pi) by O(c_1^2);
+    the driver reaches f below 1e-26 from the linear guess."""
+    res, jac, c0 = standing_wave_problem()
+    out = L.levmar(res, jac, c0, delta0=0.1, max_evals=60)
+    assert out.f < 1e-26, (out.f, out.reason)
+    assert abs(out.c[0] - 2 * np.pi) < 1e-4
+    assert np.abs(out.c[1:]).max() < 1e-5
+
+
+def test_standing_wave_period_shift_is_second_order_in_amplitude():
+    """The frequency of a standing wave is even in its amplitude: the period shift found
+    by the driver at c_1 = 2e-3 is four times the one at 1e-3 (to 2 %)."""
+    shifts = []
+    for a1 in (1e-3, 2e-3):
+        res, jac, c0 = standing_wave_problem(a1=a1)
+        out = L.levmar(res, jac, c0, delta0=0.1, max_evals=60)
+        assert out.f < 1e-24
+        shifts.append(out.c[0] - 2 * np.pi)
+    assert shifts[0] > 0
+    assert abs(shifts[1] / shifts[0] - 4.0) < 0.08
