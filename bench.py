@@ -157,6 +157,71 @@ def run_batch(window: int = 64, reps: int = 1):
             "N": [w.N for w in ws], "M": [w.M for w in ws]}
 
 
+def _standing_wave(N, a1, nmodes):
+    """Standing-wave shooting problem (eta even / phi odd modes, basis 2 cos(k alpha),
+    c_1 = phi^_1 = a1 fixed; unknowns T and c_2..c_nmodes; infinite depth, g = 1)."""
+    import numpy as np
+    a = 2 * np.pi * np.arange(N) / N
+    ks = list(range(2, nmodes + 1))
+    basis = np.zeros((2 * N, len(ks)))
+    for j, k in enumerate(ks):
+        basis[(0 if k % 2 == 0 else N):(N if k % 2 == 0 else 2 * N), j] = 2 * np.cos(k * a)
+    qf = np.concatenate([np.zeros(N), 2 * a1 * np.cos(a)])
+    return basis, qf, np.concatenate([[2 * np.pi], np.zeros(len(ks))])
+
+
+def run_lm(with_oracle: bool):
+    """Levenberg-Marquardt row: the thin SVD of a Jacobian of the precision-form shape
+    (1024 x 129), a standing-wave solve at N = 256 (nsteps 128, 31 unknown modes and T),
+    and the GPU driver against the oracle driver on a small standing wave (N = 64)."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1210_5672_amd import ww
+    rng = np.random.default_rng(1210)
+    A = ww.to_dev(rng.standard_normal((1024, 129)))
+    cs = ww.Context(n_max=1024, r_max=129)
+    cs.thin_svd(A)
+    t0 = time.perf_counter()
+    for _ in range(3):
+        cs.thin_svd(A)
+    svd_ms = 1e3 * (time.perf_counter() - t0) / 3
+    out = {"svd_1024x129_ms": svd_ms}
+    solves = {}
+    for (N, nsteps, nmodes) in [(256, 128, 32), (64, 32, 10)]:
+        basis, qf, c0 = _standing_wave(N, 0.05, nmodes)
+        ctx = ww.Context(n_max=N, r_max=nmodes)
+        ctx.shoot_setup(N, math.inf, 0.0, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.levmar(c0, nsteps, opts={"delta0": 0.1, "max_evals": 80})
+        dt = time.perf_counter() - t0
+        solves[N] = {"N": N, "nsteps": nsteps, "unknowns": nmodes, "ms": 1e3 * dt, "f": res["f"],
+                     "evals_r": res["evals_r"], "evals_J": res["evals_J"], "reason": res["reason"],
+                     "T": float(res["c"][0])}
+        print(f"# lm N={N} done", file=sys.stderr, flush=True)
+    out["standing_wave_n256"] = solves[256]
+    out["standing_wave_n64"] = solves[64]
+    if with_oracle:
+        from oracle import lm_oracle as L
+        from oracle import ww_oracle as O
+        N, nsteps, nmodes = 64, 32, 10
+        basis, qf, c0 = _standing_wave(N, 0.05, nmodes)
+
+        def jac(c):
+            o = O.shoot_eval(N, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], nsteps, jacobian=True)
+            return o["r"], np.concatenate([o["drdT"][:, None], o["J"]], axis=1)
+
+        def resid(c):
+            return O.shoot_eval(N, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], nsteps, jacobian=False)["r"]
+
+        t0 = time.perf_counter()
+        ref = L.levmar(resid, jac, c0, delta0=0.1, max_evals=80)
+        out["oracle_n64"] = {"ms": 1e3 * (time.perf_counter() - t0), "f": ref.f, "evals_r": ref.evals_r,
+                             "evals_J": ref.evals_J, "cores": blas_threads(), "kind": "oracle"}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -169,6 +234,7 @@ def main():
     ap.add_argument("--no-mixed", action="store_true")
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
+    ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -239,6 +305,8 @@ def main():
                                         "phases_ms": phm}
     if not args.no_batch:
         out["batch"] = run_batch()
+    if not args.no_lm:
+        out["lm"] = run_lm(with_oracle=not args.no_cpu_baseline)
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a counter run
         # give the scale between the counters and the bytes actually moved
