@@ -58,6 +58,14 @@ typedef struct ww_ctx ww_ctx;
                               the call is redone with FP64 factors (WW_FB_FP64), or
                               fails with WW_EREFINE in a WW_STRICT context */
 #define WW_STRICT 2u       /* no fallbacks: report WW_EPIVOT / WW_EREFINE instead */
+#define WW_GMRES 4u        /* marches without Jacobian columns (shoot_eval with J = NULL,
+                              the residual evaluations of ww_levmar) solve eq. (fred) for
+                              the base state by GMRES (Sec. 2.2) instead of an LU: one cycle
+                              of at most 24 Arnoldi steps (environment WW_GMRES_ITERS,
+                              2..32) with classical Gram-Schmidt twice, stopping when the
+                              residual estimate is below 1e-15 ||psi||; the FP64 residual
+                              must then pass the test of WW_MIXED, else the march is redone
+                              with LU factors (WW_FB_DIRECT) */
 
 /*
  * Fallbacks.  The block LU of A runs without row interchanges (A = I/2 + K/N is
@@ -76,8 +84,9 @@ typedef struct ww_ctx ww_ctx;
 #define WW_FB_FP64 2u      /* the results come from FP64 factors after the mixed-precision
                               refinement test failed */
 #define WW_FB_DIRECT 4u    /* the lagged-factor solves of a single-instance march (see
-                              shoot_eval) failed their refinement test; the march was
-                              redone with every stage's own factors */
+                              shoot_eval), or the GMRES solves (WW_GMRES), failed their
+                              residual test; the march was redone with every stage's own
+                              LU factors */
 
 /*
  * ww_create: allocate a context whose device workspace serves every N <= n_max and

@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libwwdtn.so")
 SOURCES = ["ww_api.hip"]
-HEADERS = ["ww_kernels.hpp", "ww_fft.hpp", "ww_svd.hpp"]
+HEADERS = ["ww_kernels.hpp", "ww_fft.hpp", "ww_svd.hpp", "ww_gmres.hpp"]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",

@@ -12,6 +12,7 @@
 #include "ww.h"
 #include "ww_kernels.hpp"
 #include "ww_svd.hpp"
+#include "ww_gmres.hpp"
 
 #include <algorithm>
 #include <numeric>
@@ -138,6 +139,13 @@ struct ww_ctx {
   double *lmW = nullptr, *lmr = nullptr, *lmrn = nullptr, *lmp = nullptr, *lmV = nullptr;
   double *lmsig = nullptr, *lmdot = nullptr;
   int *lmflag = nullptr, *lmperm = nullptr;
+  // GMRES base solves of marches without columns (flag WW_GMRES): at most gm_m Arnoldi
+  // steps per solve (environment WW_GMRES_ITERS); buffers on first use
+  int gm_m = 24;
+  bool gm_active = false;
+  double *gmV = nullptr, *gmw = nullptr, *gmH = nullptr, *gmcs = nullptr, *gmsn = nullptr, *gmg = nullptr;
+  double* gmbeta = nullptr;
+  int* gmstate = nullptr;
 };
 
 static bool valid_n(int N) {
@@ -219,7 +227,7 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   *out = nullptr;
   if (!valid_n(n_max) || n_max > WW_NMAX) return fail(WW_EINVAL, "n_max must be even, 2^a 3^b, 16..2048");
   if (r_max < 1 || r_max > 4096) return fail(WW_EINVAL, "r_max out of range");
-  if (flags & ~(WW_MIXED | WW_STRICT)) return fail(WW_EINVAL, "unknown flags");
+  if (flags & ~(WW_MIXED | WW_STRICT | WW_GMRES)) return fail(WW_EINVAL, "unknown flags");
   ww_ctx* c = new ww_ctx();
   // a failure after this point releases what was created so far
 #define CCHK(x)                                                                        \
@@ -326,6 +334,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->overlap = !(no && no[0] == '1');
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
+    const char* gi = std::getenv("WW_GMRES_ITERS");
+    if (gi) c->gm_m = std::max(2, std::min(GM_MAXM, std::atoi(gi)));
     const char* pl = std::getenv("WW_PIPE_LAG");
     if (pl) c->lag = std::max(0, std::min(PIPE_MAXLAG, std::atoi(pl)));
     const char* pg = std::getenv("WW_PIVOT_GUARD");
@@ -580,6 +590,7 @@ template <typename T>
 static int enqueue_gemm(ww_ctx* c, double* part, const T* M, const T* Mr, int mode, const double* B,
                         const double* add, double sgn, double* out, int R) {
   const int nkt = c->Np / WW_TB;
+  if (!(R == 1 && Mr) && (!part || !M)) return fail(WW_EHIP, "internal: product without its matrix or partials");
   if (R == 1 && Mr) {
     hipLaunchKernelGGL(k_gemv_row<T>, dim3(c->Np * 64 / WW_NT), dim3(WW_NT), 0, c->stream, Mr, c->Np, mode, B, add,
                        sgn, out);
@@ -615,6 +626,8 @@ static const double REFINE_TOL = 1.1368683772161603e-13;
 // holds this stage's matrix (row-major Ar): X = Z (B + Xs B), nref sweeps of
 // r = B - A X, X += Z (r + Xs r), and the same convergence test as the mixed form.
 static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* B, double* Y, double* X, double* Rs) {
+  if (!Fa.Ar || !(F.use32 ? (F.X32r && F.Z32r) : (F.Xr && F.Zr)))
+    return fail(WW_EHIP, "internal: lagged solve without row-major operands");
   int rc;
   if (F.use32) {
     if ((rc = enqueue_gemm<float>(c, nullptr, F.X32, F.X32r, 1, B, B, 1.0, Y, 1))) return rc;
@@ -685,15 +698,81 @@ static size_t kstride(const ww_ctx* c) { return (size_t)2 * c->N * (c->M + 1); }
 
 
 
+static int ensure_gmres(ww_ctx* c) {
+  int rc;
+  const size_t np = c->np_max, m = GM_MAXM;
+  // the row-major FP64 A that GMRES multiplies by (allocated with the mixed form only)
+  if (!c->Ar && (rc = dalloc(c, (void**)&c->Ar, np * np * 8))) return rc;
+  if (!c->Ar_1 && (rc = dalloc(c, (void**)&c->Ar_1, np * np * 8))) return rc;
+  if (c->gmV) return 0;
+  if ((rc = dalloc(c, (void**)&c->gmV, np * (m + 1) * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->gmw, np * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->gmH, (m + 1) * m * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->gmcs, m * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->gmsn, m * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->gmg, (m + 1) * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->gmbeta, 8))) return rc;
+  return dalloc(c, (void**)&c->gmstate, 64);
+}
+
+// Convergence bound of the GMRES residual estimate (relative to ||psi||)
+static const double GMRES_TOL = 1e-15;
+
+// mu = A^{-1} psi by GMRES with the row-major Ar of F (one cycle of gm_m steps, see
+// ww_gmres.hpp), then the FP64 residual test of the mixed form (status bit 64)
+static int enqueue_gmres(ww_ctx* c, const Fac& F, double* psi, double* mu, double* rs) {
+  if (!F.Ar || !c->gmV || !c->gmstate) return fail(WW_EHIP, "internal: GMRES buffers missing");
+  GmBufs b;
+  b.Ar = F.Ar;
+  b.Np = c->Np;
+  b.N = c->N;
+  b.m = c->gm_m;
+  b.V = c->gmV;
+  b.w = c->gmw;
+  b.H = c->gmH;
+  b.cs = c->gmcs;
+  b.sn = c->gmsn;
+  b.g = c->gmg;
+  b.beta = c->gmbeta;
+  b.state = c->gmstate;
+  hipLaunchKernelGGL(k_gm_init, dim3(1), dim3(GM_NT), 0, c->stream, b, (const double*)psi);
+  LAUNCHCHK();
+  const int rows_per = GM_NT / 64;
+  for (int k = 0; k < b.m; ++k) {
+    hipLaunchKernelGGL(k_gm_matvec, dim3((c->N + rows_per - 1) / rows_per), dim3(GM_NT), 0, c->stream, b, k);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_gm_arnoldi, dim3(1), dim3(GM_NT), 0, c->stream, b, k, GMRES_TOL);
+    LAUNCHCHK();
+  }
+  hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(GM_NT), 0, c->stream, b, mu);
+  LAUNCHCHK();
+  int rc;
+  if ((rc = enqueue_gemm<double>(c, nullptr, F.A, F.Ar, 0, mu, psi, -1.0, rs, 1))) return rc;
+  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(WW_NT), 0, c->stream, rs, psi, c->Np, c->N, REFINE_TOL, c->status,
+                     64);
+  LAUNCHCHK();
+  return 0;
+}
+
 // base chain of stage s: prep, assembly, LU, base DtN, base right-hand side -> kout
+// (GMRES marches: assembly and a GMRES solve in place of the LU and its solve)
 static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout, const Fac& F) {
   int rc;
   if ((rc = prof_mark(c, 1, 0))) return rc;
   hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysrc, c->K, c->Ys, c->coef,
                      s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
   LAUNCHCHK();
-  if ((rc = enqueue_assemble_lu(c, F))) return rc;
-  if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
+  if (c->gm_active) {
+    if ((rc = enqueue_assemble(c, F, true))) return rc;
+    if ((rc = enqueue_gmres(c, F, c->rhs0, c->mu0, c->rr0))) return rc;
+    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->mu0, c->Np, 1, c->gam0,
+                       c->hg0, c->tw, c->N);
+    LAUNCHCHK();
+    if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
+  } else {
+    if ((rc = enqueue_assemble_lu(c, F))) return rc;
+    if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
+  }
   hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
                      c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
@@ -987,6 +1066,7 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   if (!c || !surface) return fail(WW_EINVAL, "null argument");
   c->dtn_ready = false;   // until this surface is factored
   c->fb = 0;
+  c->gm_active = false;
   int rc;
   if ((rc = set_grid(c, N, h))) return rc;
   c->tau = tau;
@@ -1120,6 +1200,8 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
   LAUNCHCHK();
+  c->gm_active = (c->flags & WW_GMRES) && !cols && c->fb == 0;
+  if (c->gm_active && (rc = ensure_gmres(c))) return rc;
   if (pipelined(c, cols, two_streams)) {
     if ((rc = ensure_pipe(c))) return rc;
     if ((rc = pipe_prologue(c))) return rc;
@@ -1166,7 +1248,7 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
 static unsigned next_fallback(const ww_ctx* c, int st) {
   if (strict(c) || (st & 16)) return 0;   // a surface through the bottom is no factorisation issue
   if ((st & (1 | 8)) && !pivoted(c)) return WW_FB_PIVOTED | WW_FB_FP64;
-  if ((st & 32) && !(c->fb & WW_FB_DIRECT)) return WW_FB_DIRECT;
+  if ((st & (32 | 64)) && !(c->fb & WW_FB_DIRECT)) return WW_FB_DIRECT;
   if ((st & 4) && !(c->fb & WW_FB_FP64)) return WW_FB_FP64;
   return 0;
 }
@@ -1180,6 +1262,7 @@ static int status_error(const ww_ctx* c, int st, int where) {
   if (st & (1 | 8)) return fail(WW_EPIVOT, pivoted(c) ? MSG_PIVOT2 : MSG_PIVOT);
   if (st & 4) return fail(WW_EREFINE, MSG_REFINE);
   if (st & 32) return fail(WW_EREFINE, "lagged-factor solves: relative residual above 2^-43 (WW_STRICT)");
+  if (st & 64) return fail(WW_EREFINE, "GMRES base solves: relative residual above 2^-43 (WW_STRICT)");
   return 0;
 }
 
@@ -1288,6 +1371,7 @@ static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, in
   int rc;
   if ((rc = set_grid(c, c->shootN, c->shootH))) return rc;
   c->dtn_ready = false;
+  c->gm_active = false;   // the transposed solves need the factors
   const int N = c->N, Np = c->Np, M = c->M, nst = c->nst;
   const int C = std::min(ckpt_every, nsteps);
   const int nseg = (nsteps + C - 1) / C;

@@ -1,0 +1,150 @@
+// GMRES for the base-state solve A mu = psi of eq. (fred) (Sec. 2.2 solves it by GMRES;
+// the second-kind operator converges in a few iterations): the f-only fast path of a
+// march without Jacobian columns, in place of the LU.
+//
+// One cycle of at most m Arnoldi steps (no restart) with classical Gram-Schmidt applied
+// twice, Givens rotations on the Hessenberg columns, and the residual estimate |g_{k+1}|.
+// The iteration count is fixed so that the sequence can be captured in a step graph:
+// once the estimate is below tol ||psi|| (or the Krylov space is exhausted) a device
+// flag turns the remaining steps into no-ops.  The caller checks the true FP64 residual
+// afterwards.  Vectors have length N (the grid), ld Np; A is the row-major copy Ar.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#define GM_NT 256
+#define GM_MAXM 32
+
+// state: [0] converged (0/1), [1] Arnoldi steps taken
+struct GmBufs {
+  const double* Ar;   // Np x Np row-major
+  int Np, N, m;
+  double* V;          // Np x (m + 1), column-major (basis)
+  double* w;          // Np
+  double* H;          // (m + 1) x m, column-major, rotated to upper triangular
+  double* cs;         // m
+  double* sn;         // m
+  double* g;          // m + 1
+  double* beta;       // ||psi||
+  int* state;
+};
+
+__device__ inline double gm_block_sum(double v, double* sh) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+// v0 = psi / ||psi||, g = (beta, 0, ...); psi = 0 gives mu = 0 (converged, no steps)
+__global__ __launch_bounds__(GM_NT) void k_gm_init(GmBufs b, const double* __restrict__ psi) {
+  __shared__ double sh[4];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < b.N; i += GM_NT) s += psi[i] * psi[i];
+  const double beta = sqrt(gm_block_sum(s, sh));
+  const double inv = beta > 0.0 ? 1.0 / beta : 0.0;
+  for (int i = threadIdx.x; i < b.Np; i += GM_NT) b.V[i] = i < b.N ? psi[i] * inv : 0.0;
+  for (int i = threadIdx.x; i <= b.m; i += GM_NT) b.g[i] = i == 0 ? beta : 0.0;
+  if (threadIdx.x == 0) {
+    b.beta[0] = beta;
+    b.state[0] = beta > 0.0 ? 0 : 1;
+    b.state[1] = 0;
+  }
+}
+
+// w = A v_k, one wave per row (a no-op once converged)
+__global__ __launch_bounds__(GM_NT) void k_gm_matvec(GmBufs b, int k) {
+  if (b.state[0]) return;
+  const int lane = threadIdx.x & 63;
+  const int row = blockIdx.x * (GM_NT / 64) + (threadIdx.x >> 6);
+  if (row >= b.N) return;
+  const double* a = b.Ar + (size_t)row * b.Np;
+  const double* v = b.V + (size_t)k * b.Np;
+  double s = 0.0;
+  for (int j = lane; j < b.N; j += 64) s = fma(a[j], v[j], s);
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) b.w[row] = s;
+}
+
+// Arnoldi step k: orthogonalise w against v_0..v_k (twice), Hessenberg column k,
+// Givens rotations, residual estimate; v_{k+1} = w / h_{k+1,k}
+__global__ __launch_bounds__(GM_NT) void k_gm_arnoldi(GmBufs b, int k, double tol) {
+  __shared__ double sh[4];
+  __shared__ double hs[GM_MAXM + 1];
+  if (b.state[0]) return;
+  const int N = b.N, Np = b.Np;
+  double* hcol = b.H + (size_t)k * (b.m + 1);
+  for (int i = threadIdx.x; i <= k; i += GM_NT) hs[i] = 0.0;
+  __syncthreads();
+  for (int pass = 0; pass < 2; ++pass) {
+    for (int i = 0; i <= k; ++i) {   // h_i = v_i . w (classical: w fixed during the pass)
+      const double* v = b.V + (size_t)i * Np;
+      double s = 0.0;
+      for (int r = threadIdx.x; r < N; r += GM_NT) s = fma(v[r], b.w[r], s);
+      const double h = gm_block_sum(s, sh);   // the same sum in every thread
+      if (threadIdx.x == 0) {
+        hs[i] += h;
+        hcol[i] = h;   // this pass's products, for the update below
+      }
+    }
+    __syncthreads();
+    for (int r = threadIdx.x; r < N; r += GM_NT) {
+      double x = b.w[r];
+      for (int i = 0; i <= k; ++i) x = fma(-hcol[i], b.V[(size_t)i * Np + r], x);
+      b.w[r] = x;
+    }
+    __syncthreads();
+  }
+  double s = 0.0;
+  for (int r = threadIdx.x; r < N; r += GM_NT) s = fma(b.w[r], b.w[r], s);
+  const double hn = sqrt(gm_block_sum(s, sh));
+  if (threadIdx.x == 0) {
+    // the Hessenberg column (sum of both passes), rotated by the previous rotations
+    for (int i = 0; i <= k; ++i) hcol[i] = hs[i];
+    for (int i = 0; i < k; ++i) {
+      const double t = b.cs[i] * hcol[i] + b.sn[i] * hcol[i + 1];
+      hcol[i + 1] = -b.sn[i] * hcol[i] + b.cs[i] * hcol[i + 1];
+      hcol[i] = t;
+    }
+    const double a = hcol[k], c2 = hn;
+    const double den = sqrt(a * a + c2 * c2);
+    const double c = den > 0.0 ? a / den : 1.0, sv = den > 0.0 ? c2 / den : 0.0;
+    b.cs[k] = c;
+    b.sn[k] = sv;
+    hcol[k] = den;
+    hcol[k + 1] = 0.0;
+    const double gk = b.g[k];
+    b.g[k] = c * gk;
+    b.g[k + 1] = -sv * gk;
+    b.state[1] = k + 1;
+    const bool done = !(fabs(b.g[k + 1]) > tol * b.beta[0]) || !(hn > 0.0) || k + 1 >= b.m;
+    if (done) b.state[0] = 1;
+    hs[0] = done ? 0.0 : 1.0 / hn;   // broadcast of the scale
+  }
+  __syncthreads();
+  const double inv = hs[0];
+  double* vn = b.V + (size_t)(k + 1) * Np;
+  if (inv != 0.0)
+    for (int r = threadIdx.x; r < N; r += GM_NT) vn[r] = b.w[r] * inv;
+}
+
+// mu = V_k y with R y = g (back substitution on the rotated Hessenberg matrix)
+__global__ __launch_bounds__(GM_NT) void k_gm_finish(GmBufs b, double* __restrict__ mu) {
+  __shared__ double y[GM_MAXM];
+  const int kk = b.state[1];
+  if (threadIdx.x == 0) {
+    for (int i = kk - 1; i >= 0; --i) {
+      double t = b.g[i];
+      for (int j = i + 1; j < kk; ++j) t -= b.H[(size_t)j * (b.m + 1) + i] * y[j];
+      const double d = b.H[(size_t)i * (b.m + 1) + i];
+      y[i] = d != 0.0 ? t / d : 0.0;
+    }
+  }
+  __syncthreads();
+  for (int r = threadIdx.x; r < b.Np; r += GM_NT) {
+    double x = 0.0;
+    if (r < b.N)
+      for (int j = 0; j < kk; ++j) x = fma(y[j], b.V[(size_t)j * b.Np + r], x);
+    mu[r] = x;
+  }
+}

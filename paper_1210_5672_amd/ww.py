@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libwwdtn.so")
 WW_FP64 = 0
 WW_MIXED = 1
 WW_STRICT = 2
+WW_GMRES = 4
 WW_FB_PIVOTED = 1
 WW_FB_FP64 = 2
 WW_FB_DIRECT = 4
@@ -128,12 +129,12 @@ class Context:
     calls then raise WW_EPIVOT / WW_EREFINE instead."""
 
     def __init__(self, n_max: int, r_max: int, mixed: bool = False, stream=None, tableau=None,
-                 strict: bool = False):
+                 strict: bool = False, gmres: bool = False):
         self.lib = load()
         self.ptr = ctypes.c_void_p()
         s = stream if stream is not None else torch.cuda.current_stream()
         self._stream = s            # the library keeps the handle: keep the stream alive
-        flags = (WW_MIXED if mixed else WW_FP64) | (WW_STRICT if strict else 0)
+        flags = (WW_MIXED if mixed else WW_FP64) | (WW_STRICT if strict else 0) | (WW_GMRES if gmres else 0)
         _check(self.lib.ww_create(ctypes.byref(self.ptr), n_max, r_max, flags,
                                   ctypes.c_void_p(s.cuda_stream)))
         self.n_max, self.r_max, self.mixed = n_max, r_max, mixed
