@@ -157,6 +157,32 @@ def run_batch(window: int = 64, reps: int = 1):
             "N": [w.N for w in ws], "M": [w.M for w in ws]}
 
 
+def run_f_only(w, nsteps, T):
+    """f-only fast path: one march of the precision-form workload without Jacobian
+    columns (r, dr/dT, f), with LU base solves and with GMRES base solves (WW_GMRES).
+    Returns the times of the second call of each (the first captures the step graph)."""
+    import numpy as np
+    import torch
+    from paper_1210_5672_amd import ww
+    out = {"workload": f"base-only march, N={w.N}, nsteps={nsteps} ({12 * nsteps} DtN solves)"}
+    rs = {}
+    for name, gm in (("lu", False), ("gmres", True)):
+        ctx = ww.Context(n_max=w.N, r_max=w.M + 1, gmres=gm)
+        ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        params = ww.to_dev(w.params)
+        ctx.shoot_eval(params, T, nsteps, jacobian=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = ctx.shoot_eval(params, T, nsteps, jacobian=False)
+        dt = time.perf_counter() - t0
+        rs[name] = res["r"].cpu().numpy()
+        out[name] = {"ms": 1e3 * dt, "us_per_stage": 1e6 * dt / (12 * nsteps), "fallbacks": ctx.fallbacks()}
+        print(f"# f-only {name} done", file=sys.stderr, flush=True)
+    out["r_rel_diff"] = float(np.abs(rs["gmres"] - rs["lu"]).max() / np.abs(rs["lu"]).max())
+    out["speedup"] = out["lu"]["ms"] / out["gmres"]["ms"]
+    return out
+
+
 def _standing_wave(N, a1, nmodes):
     """Standing-wave shooting problem (eta even / phi odd modes, basis 2 cos(k alpha),
     c_1 = phi^_1 = a1 fixed; unknowns T and c_2..c_nmodes; infinite depth, g = 1)."""
@@ -235,6 +261,7 @@ def main():
     ap.add_argument("--no-profile", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt measurement")
+    ap.add_argument("--no-f-only", action="store_true", help="skip the f-only (GMRES) measurement")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -307,6 +334,8 @@ def main():
         out["batch"] = run_batch()
     if not args.no_lm:
         out["lm"] = run_lm(with_oracle=not args.no_cpu_baseline)
+    if not args.no_f_only:
+        out["f_only"] = run_f_only(w, nsteps, T)
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a counter run
         # give the scale between the counters and the bytes actually moved

@@ -61,9 +61,11 @@ typedef struct ww_ctx ww_ctx;
 #define WW_GMRES 4u        /* marches without Jacobian columns (shoot_eval with J = NULL,
                               the residual evaluations of ww_levmar) solve eq. (fred) for
                               the base state by GMRES (Sec. 2.2) instead of an LU: one cycle
-                              of at most 24 Arnoldi steps (environment WW_GMRES_ITERS,
-                              2..32) with classical Gram-Schmidt twice, stopping when the
-                              residual estimate is below 1e-15 ||psi||; the FP64 residual
+                              of Arnoldi steps with classical Gram-Schmidt twice, stopping
+                              when the residual estimate is below 1e-15 ||psi||; the step
+                              budget is the count one solve of a rough right-hand side
+                              takes on the initial surface, plus 4 (at most 32; environment
+                              WW_GMRES_ITERS, 2..32, fixes it instead); the FP64 residual
                               must then pass the test of WW_MIXED, else the march is redone
                               with LU factors (WW_FB_DIRECT) */
 

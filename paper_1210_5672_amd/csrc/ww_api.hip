@@ -115,6 +115,7 @@ struct ww_ctx {
   hipGraphExec_t step_exec = nullptr;
   int gN = -1, gM = -1, gcols = -1, gnst = -1, gtwo = -1;
   unsigned gfb = ~0u;
+  int ggm = -1;   // GMRES step budget captured in the graph (0: no GMRES)
   // fallbacks: fb is the mode the factor sets are built in (WW_FB_* bits), fb_last what
   // the results of the last call came from; guard is the unpivoted LU's pivot bound
   unsigned fb = 0, fb_last = 0;
@@ -142,6 +143,7 @@ struct ww_ctx {
   // GMRES base solves of marches without columns (flag WW_GMRES): at most gm_m Arnoldi
   // steps per solve (environment WW_GMRES_ITERS); buffers on first use
   int gm_m = 24;
+  bool gm_fixed = false;   // WW_GMRES_ITERS given: no calibration
   bool gm_active = false;
   double *gmV = nullptr, *gmw = nullptr, *gmH = nullptr, *gmcs = nullptr, *gmsn = nullptr, *gmg = nullptr;
   double* gmbeta = nullptr;
@@ -335,7 +337,10 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
     const char* gi = std::getenv("WW_GMRES_ITERS");
-    if (gi) c->gm_m = std::max(2, std::min(GM_MAXM, std::atoi(gi)));
+    if (gi) {
+      c->gm_m = std::max(2, std::min(GM_MAXM, std::atoi(gi)));
+      c->gm_fixed = true;
+    }
     const char* pl = std::getenv("WW_PIPE_LAG");
     if (pl) c->lag = std::max(0, std::min(PIPE_MAXLAG, std::atoi(pl)));
     const char* pg = std::getenv("WW_PIVOT_GUARD");
@@ -754,6 +759,34 @@ static int enqueue_gmres(ww_ctx* c, const Fac& F, double* psi, double* mu, doubl
   return 0;
 }
 
+static int read_status(ww_ctx* c, int* st, int* where = nullptr);
+
+// Step budget of a GMRES march: one solve of a rough right-hand side with the largest
+// budget on the surface at the start of the march, then the steps it took plus 4 (the operator changes slowly along
+// the march; a stage that needs more fails the residual test and the march falls back
+// to LU factors).
+static int gmres_calibrate(ww_ctx* c) {
+  const Fac F = fac_default(c);
+  hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys, c->coef,
+                     0, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
+  LAUNCHCHK();
+  int rc;
+  if ((rc = enqueue_assemble(c, F, true))) return rc;
+  // a rough right-hand side (the initial potential is often zero, which GMRES solves in
+  // no step)
+  hipLaunchKernelGGL(k_gm_probe_rhs, dim3((c->Np + 255) / 256), dim3(256), 0, c->stream, c->y0t, c->N, c->Np);
+  LAUNCHCHK();
+  c->gm_m = GM_MAXM;
+  if ((rc = enqueue_gmres(c, F, c->y0t, c->mu0, c->rr0))) return rc;
+  int used[2] = {0, 0}, st = 0;
+  HIPCHK(hipMemcpyAsync(used, c->gmstate, sizeof(used), hipMemcpyDeviceToHost, c->stream));
+  if ((rc = read_status(c, &st))) return rc;   // (synchronises; the march checks again)
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
+  c->gm_m = std::max(4, std::min(GM_MAXM, used[1] + 4));
+  return 0;
+}
+
 // base chain of stage s: prep, assembly, LU, base DtN, base right-hand side -> kout
 // (GMRES marches: assembly and a GMRES solve in place of the LU and its solve)
 static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout, const Fac& F) {
@@ -986,7 +1019,7 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
 // coefficients live in device memory, so T and the parameters may change freely.
 static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   if (c->step_exec && c->gN == c->N && c->gM == c->M && c->gcols == (int)cols && c->gnst == c->nst &&
-      c->gtwo == (int)two_streams && c->gfb == c->fb)
+      c->gtwo == (int)two_streams && c->gfb == c->fb && c->ggm == (c->gm_active ? c->gm_m : 0))
     return 0;
   if (c->step_exec) {
     HIPCHK(hipDeviceSynchronize());   // every branch of its last replay has ended
@@ -1014,12 +1047,13 @@ static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   c->gtwo = (int)two_streams;
   c->gnst = c->nst;
   c->gfb = c->fb;
+  c->ggm = c->gm_active ? c->gm_m : 0;
   return 0;
 }
 
 // status bits (clears them); *where (optional) receives 16 step + stage of the first
 // non-finite or bed-crossing stage state of a march (INT_MAX if none)
-static int read_status(ww_ctx* c, int* st, int* where = nullptr) {
+static int read_status(ww_ctx* c, int* st, int* where) {
   int h[3] = {0, 0, 0};
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(h, c->status, sizeof(h), hipMemcpyDeviceToHost));
@@ -1201,7 +1235,10 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
   LAUNCHCHK();
   c->gm_active = (c->flags & WW_GMRES) && !cols && c->fb == 0;
-  if (c->gm_active && (rc = ensure_gmres(c))) return rc;
+  if (c->gm_active) {
+    if ((rc = ensure_gmres(c))) return rc;
+    if (!c->gm_fixed && (rc = gmres_calibrate(c))) return rc;
+  }
   if (pipelined(c, cols, two_streams)) {
     if ((rc = ensure_pipe(c))) return rc;
     if ((rc = pipe_prologue(c))) return rc;

@@ -36,6 +36,20 @@ __device__ inline double gm_block_sum(double v, double* sh) {
   return sh[0] + sh[1] + sh[2] + sh[3];
 }
 
+// A rough deterministic right-hand side for calibrating the step budget: entries in
+// [-0.5, 0.5) from an integer hash of the index (padding rows zero).
+__global__ void k_gm_probe_rhs(double* __restrict__ psi, int N, int Np) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < Np; i += gridDim.x * blockDim.x) {
+    unsigned h = (unsigned)i * 2654435761u + 0x9e3779b9u;
+    h ^= h >> 16;
+    h *= 0x85ebca6bu;
+    h ^= h >> 13;
+    h *= 0xc2b2ae35u;
+    h ^= h >> 16;
+    psi[i] = i < N ? (double)h * (1.0 / 4294967296.0) - 0.5 : 0.0;
+  }
+}
+
 // v0 = psi / ||psi||, g = (beta, 0, ...); psi = 0 gives mu = 0 (converged, no steps)
 __global__ __launch_bounds__(GM_NT) void k_gm_init(GmBufs b, const double* __restrict__ psi) {
   __shared__ double sh[4];
@@ -66,31 +80,44 @@ __global__ __launch_bounds__(GM_NT) void k_gm_matvec(GmBufs b, int k) {
   if (lane == 0) b.w[row] = s;
 }
 
+__device__ inline double gm_wave_sum(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+  return v;
+}
+
 // Arnoldi step k: orthogonalise w against v_0..v_k (twice), Hessenberg column k,
-// Givens rotations, residual estimate; v_{k+1} = w / h_{k+1,k}
+// Givens rotations, residual estimate; v_{k+1} = w / h_{k+1,k}.  Each pass reduces its
+// k + 1 products together: wave sums into an LDS table, one barrier, one thread per
+// product adds the four wave sums.
 __global__ __launch_bounds__(GM_NT) void k_gm_arnoldi(GmBufs b, int k, double tol) {
+  __shared__ double red[(GM_MAXM + 1) * 4];
+  __shared__ double hp[GM_MAXM + 1];   // products of the current pass
+  __shared__ double hs[GM_MAXM + 1];   // sums over both passes
   __shared__ double sh[4];
-  __shared__ double hs[GM_MAXM + 1];
+  __shared__ double bscale;            // 1 / h_{k+1,k}, or 0 when done
   if (b.state[0]) return;
   const int N = b.N, Np = b.Np;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   double* hcol = b.H + (size_t)k * (b.m + 1);
   for (int i = threadIdx.x; i <= k; i += GM_NT) hs[i] = 0.0;
-  __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    for (int i = 0; i <= k; ++i) {   // h_i = v_i . w (classical: w fixed during the pass)
+    for (int i = 0; i <= k; ++i) {   // classical: w is fixed during the products
       const double* v = b.V + (size_t)i * Np;
       double s = 0.0;
       for (int r = threadIdx.x; r < N; r += GM_NT) s = fma(v[r], b.w[r], s);
-      const double h = gm_block_sum(s, sh);   // the same sum in every thread
-      if (threadIdx.x == 0) {
-        hs[i] += h;
-        hcol[i] = h;   // this pass's products, for the update below
-      }
+      s = gm_wave_sum(s);
+      if (lane == 0) red[i * 4 + wv] = s;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= k; i += GM_NT) {
+      const double h = red[i * 4] + red[i * 4 + 1] + red[i * 4 + 2] + red[i * 4 + 3];
+      hp[i] = h;
+      hs[i] += h;
     }
     __syncthreads();
     for (int r = threadIdx.x; r < N; r += GM_NT) {
       double x = b.w[r];
-      for (int i = 0; i <= k; ++i) x = fma(-hcol[i], b.V[(size_t)i * Np + r], x);
+      for (int i = 0; i <= k; ++i) x = fma(-hp[i], b.V[(size_t)i * Np + r], x);
       b.w[r] = x;
     }
     __syncthreads();
@@ -119,10 +146,10 @@ __global__ __launch_bounds__(GM_NT) void k_gm_arnoldi(GmBufs b, int k, double to
     b.state[1] = k + 1;
     const bool done = !(fabs(b.g[k + 1]) > tol * b.beta[0]) || !(hn > 0.0) || k + 1 >= b.m;
     if (done) b.state[0] = 1;
-    hs[0] = done ? 0.0 : 1.0 / hn;   // broadcast of the scale
+    bscale = done ? 0.0 : 1.0 / hn;
   }
   __syncthreads();
-  const double inv = hs[0];
+  const double inv = bscale;
   double* vn = b.V + (size_t)(k + 1) * Np;
   if (inv != 0.0)
     for (int r = threadIdx.x; r < N; r += GM_NT) vn[r] = b.w[r] * inv;
