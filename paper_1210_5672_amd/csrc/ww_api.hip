@@ -107,6 +107,7 @@ struct ww_ctx {
   // (0: block LU, 1: whole base chain, 2: column chain); the values of the last
   // replayed step are read back by ww_profile_read
   bool prof = false;
+  int prof_stage = -1;   // stage being enqueued (marks are taken only inside a step)
   unsigned long long* stamps = nullptr;   // [phase][stage] x {start, sum, count}
   // one RK step captured as a graph, replayed nsteps times
   bool use_graph = true;
@@ -466,10 +467,9 @@ static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
 }
 
 // profiling mark (only while a profiled step is being enqueued)
-static int g_prof_stage = -1;
 static int prof_mark(ww_ctx* c, int phase, int which) {
-  if (!c->prof || g_prof_stage < 0) return 0;
-  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, c->stream, c->stamps, phase * 16 + g_prof_stage, which);
+  if (!c->prof || c->prof_stage < 0) return 0;
+  hipLaunchKernelGGL(k_stamp, dim3(1), dim3(64), 0, c->stream, c->stamps, phase * 16 + c->prof_stage, which);
   LAUNCHCHK();
   return 0;
 }
@@ -911,7 +911,7 @@ static int enqueue_step_pipe(ww_ctx* c) {
   const int nst = c->nst, L = c->lag;
   hipStream_t s0 = c->stream;
   for (int s = 0; s < nst && !rc; ++s) {
-    g_prof_stage = s;
+    c->prof_stage = s;
     const Fac F = pipe_set(c, s, false);
     const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
     hipStream_t ls = c->lus[s % L];
@@ -968,7 +968,7 @@ static int enqueue_step_pipe(ww_ctx* c) {
     if (rc) break;
     if (hipEventRecord(c->evC[s], c->side) != hipSuccess) rc = fail(WW_EHIP, "pipeline: event record");
   }
-  g_prof_stage = -1;
+  c->prof_stage = -1;
   if (rc) return rc;
   // the column chains waited for every LU: one wait joins all streams
   HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
@@ -988,7 +988,7 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
   hipStream_t s0 = c->stream;
   for (int s = 0; s < c->nst; ++s) {
     const int par = s & 1;
-    g_prof_stage = s;
+    c->prof_stage = s;
     // the factor set of this parity was last read by the column chain of stage s - 2
     if (two && s >= 2) HIPCHK(hipStreamWaitEvent(s0, c->evC[s - 2], 0));
     rc = enqueue_base_chain(c, c->y, s, c->K + (size_t)s * kstride(c), fac_set(c, par, false));
@@ -1003,7 +1003,7 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
     } else if (!rc && cols && c->M > 0) {
       rc = enqueue_col_chain(c, s, fac_set(c, par, true));   // one stream: after the base chain
     }
-    g_prof_stage = -1;
+    c->prof_stage = -1;
     if (rc) return rc;
   }
   if (two) HIPCHK(hipStreamWaitEvent(s0, c->evC[c->nst - 1], 0));
