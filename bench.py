@@ -228,6 +228,15 @@ def run_lm(with_oracle: bool):
         print(f"# lm N={N} done", file=sys.stderr, flush=True)
     out["standing_wave_n256"] = solves[256]
     out["standing_wave_n64"] = solves[64]
+    # BFGS with the adjoint gradient (Sec. 3.2) on a small standing wave
+    basis, qf, c0 = _standing_wave(32, 0.05, 10)
+    ctx = ww.Context(n_max=32, r_max=10)
+    ctx.shoot_setup(32, math.inf, 0.0, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    bres = ctx.bfgs(c0, 12, opts={"delta0": 0.1, "max_iter": 80, "ckpt_every": 4})
+    out["bfgs_n32"] = {"N": 32, "nsteps": 12, "unknowns": 10, "ms": 1e3 * (time.perf_counter() - t0), "f": bres["f"],
+                       "iters": bres["iters"], "evals": bres["evals"], "reason": bres["reason"]}
     if with_oracle:
         from oracle import lm_oracle as L
         from oracle import ww_oracle as O
@@ -245,6 +254,18 @@ def run_lm(with_oracle: bool):
         ref = L.levmar(resid, jac, c0, delta0=0.1, max_evals=80)
         out["oracle_n64"] = {"ms": 1e3 * (time.perf_counter() - t0), "f": ref.f, "evals_r": ref.evals_r,
                              "evals_J": ref.evals_J, "cores": blas_threads(), "kind": "oracle"}
+        from oracle import bfgs_oracle as B
+        basis, qf, c0 = _standing_wave(32, 0.05, 10)
+
+        def fg(c):
+            o = O.shoot_eval(32, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], 12, jacobian=True)
+            J = np.concatenate([o["drdT"][:, None], o["J"]], axis=1)
+            return 0.5 * float(o["r"] @ o["r"]), J.T @ o["r"]
+
+        t0 = time.perf_counter()
+        bref = B.bfgs(fg, c0, delta0=0.1, max_iter=80)
+        out["oracle_bfgs_n32"] = {"ms": 1e3 * (time.perf_counter() - t0), "f": bref.f, "evals": bref.evals,
+                                  "cores": blas_threads(), "kind": "oracle"}
     return out
 
 

@@ -275,6 +275,46 @@ typedef struct ww_lm_report {
 int ww_lm_default_opts(ww_lm_opts *opts);
 int ww_levmar(ww_ctx *ctx, double *c, int nsteps, const ww_lm_opts *opts, ww_lm_report *rep);
 
+/*
+ * BFGS minimiser with the adjoint gradient (the ACM of Sec. 3.2) on the shooting
+ * problem of shoot_setup: it minimises f(c) = r.r/2 over c = (T, params[0..M-1]) with
+ * f and grad f = (df/dT, grad_params f) from shoot_adjoint (checkpoints every
+ * ckpt_every steps).  The paper names BFGS with line searches; its parameters here:
+ * inverse-Hessian update H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T (skipped when
+ * y.s <= 0), H_0 = I scaled by s.y / y.y at the first update; strong Wolfe line search
+ * (c1 = 1e-4, c2 = 0.9) with first trial step 1 (capped at a length delta0 on the first
+ * iteration), bracketing by doubling (at most 20) and zoom by bisection (at most 30); a
+ * search without the conditions takes the best point met if it lowers f, else stops.
+ * c (host, M + 1): start on entry, result on return.  opts: NULL for the defaults.  rep
+ * (or NULL): final f and ||g||, iterations, evaluations (f and gradient), reason
+ * (WW_BFGS_*), and optionally rows of (c[M + 1], f) after every iteration in history
+ * (host, hist_cap rows of M + 2 doubles).  Synchronises.  Errors: those of
+ * shoot_adjoint, WW_ENOSETUP, WW_EINVAL.
+ */
+typedef struct ww_bfgs_opts {
+  double f_tol;     /* stop when f < f_tol (1e-26) */
+  double g_tol;     /* ... or ||grad f|| < g_tol (1e-13) */
+  double delta0;    /* length cap of the first step (0.1) */
+  int max_iter;     /* (200) */
+  int ckpt_every;   /* adjoint checkpoints (16) */
+} ww_bfgs_opts;
+
+typedef struct ww_bfgs_report {
+  double f, gnorm;
+  int iters, evals, reason, n_hist;
+  double *history;  /* host, or NULL */
+  int hist_cap;
+} ww_bfgs_report;
+
+#define WW_BFGS_F_TOL 1
+#define WW_BFGS_G_TOL 2
+#define WW_BFGS_C_UNCHANGED 3
+#define WW_BFGS_LINE_SEARCH 4
+#define WW_BFGS_MAX_ITER 5
+
+int ww_bfgs_default_opts(ww_bfgs_opts *opts);
+int ww_bfgs(ww_ctx *ctx, double *c, int nsteps, const ww_bfgs_opts *opts, ww_bfgs_report *rep);
+
 /* thread-local message of the last failure on this thread ("" if none) */
 const char *ww_last_error(void);
 

@@ -1879,6 +1879,220 @@ int ww_levmar(ww_ctx* c, double* cvec, int nsteps, const ww_lm_opts* opts, ww_lm
   return 0;
 }
 
+}  // extern "C"
+
+// ----- BFGS with a strong-Wolfe line search (the adjoint minimiser of Sec. 3.2) -----
+// f and its gradient g = (df/dT, grad_params f) from one shoot_adjoint call
+static int bfgs_fg(ww_ctx* c, const std::vector<double>& cv, int nsteps, int ckpt, double* f, std::vector<double>& g) {
+  const int M = c->M;
+  if (M > 0) HIPCHK(hipMemcpyAsync(c->lmp, cv.data() + 1, (size_t)M * 8, hipMemcpyHostToDevice, c->stream));
+  double dfdT = 0.0;
+  int rc;
+  if ((rc = shoot_adjoint(c, c->lmp, cv[0], nsteps, ckpt, c->lmdot, &dfdT, f))) return rc;
+  g.assign(M + 1, 0.0);
+  g[0] = dfdT;
+  if (M > 0) {
+    HIPCHK(hipMemcpyAsync(g.data() + 1, c->lmdot, (size_t)M * 8, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+  }
+  return 0;
+}
+
+static double dotv(const std::vector<double>& a, const std::vector<double>& b) {
+  double s = 0.0;
+  for (size_t i = 0; i < a.size(); ++i) s += a[i] * b[i];
+  return s;
+}
+
+// Strong Wolfe conditions (c1 = 1e-4, c2 = 0.9): bracketing by doubling, zoom by
+// bisection.  On return: *a the step, *fa, ga the values there, *ok whether the
+// conditions hold (else the best point met).
+static int bfgs_line_search(ww_ctx* c, int nsteps, int ckpt, const std::vector<double>& cv, double f0,
+                            const std::vector<double>& g0, const std::vector<double>& p, double a1, double* a_out,
+                            double* f_out, std::vector<double>& g_out, int* evals, bool* ok) {
+  const double C1 = 1e-4, C2 = 0.9;
+  const int n = (int)cv.size();
+  const double d0 = dotv(g0, p);
+  std::vector<double> x(n), g;
+  double f = 0.0;
+  int rc;
+  auto eval = [&](double a) -> int {
+    for (int i = 0; i < n; ++i) x[i] = cv[i] + a * p[i];
+    ++*evals;
+    return bfgs_fg(c, x, nsteps, ckpt, &f, g);
+  };
+  double best_a = 0.0, best_f = f0;
+  std::vector<double> best_g = g0;
+  auto keep = [&](double a) {
+    if (f < best_f) {
+      best_a = a;
+      best_f = f;
+      best_g = g;
+    }
+  };
+  auto done = [&](double a, bool good) {
+    *a_out = a;
+    *f_out = good ? f : best_f;
+    g_out = good ? g : best_g;
+    if (!good) *a_out = best_a;
+    *ok = good;
+    return 0;
+  };
+  double a_prev = 0.0, f_prev = f0, a = a1, lo = 0.0, hi = 0.0, flo = 0.0;
+  bool bracket = false;
+  for (int i = 0; i < 20; ++i) {
+    if ((rc = eval(a))) return rc;
+    keep(a);
+    if (f > f0 + C1 * a * d0 || (i > 0 && f >= f_prev)) {
+      lo = a_prev;
+      flo = f_prev;
+      hi = a;
+      bracket = true;
+      break;
+    }
+    const double d = dotv(g, p);
+    if (std::fabs(d) <= -C2 * d0) return done(a, true);
+    if (d >= 0.0) {
+      lo = a;
+      flo = f;
+      hi = a_prev;
+      bracket = true;
+      break;
+    }
+    a_prev = a;
+    f_prev = f;
+    a = 2.0 * a;
+  }
+  if (!bracket) return done(0.0, false);
+  for (int j = 0; j < 30; ++j) {
+    a = 0.5 * (lo + hi);
+    if ((rc = eval(a))) return rc;
+    keep(a);
+    if (f > f0 + C1 * a * d0 || f >= flo) {
+      hi = a;
+    } else {
+      const double d = dotv(g, p);
+      if (std::fabs(d) <= -C2 * d0) return done(a, true);
+      if (d * (hi - lo) >= 0.0) hi = lo;
+      lo = a;
+      flo = f;
+    }
+  }
+  return done(0.0, false);
+}
+
+extern "C" {
+
+int ww_bfgs_default_opts(ww_bfgs_opts* o) {
+  if (!o) return fail(WW_EINVAL, "null argument");
+  o->f_tol = 1e-26;
+  o->g_tol = 1e-13;
+  o->delta0 = 0.1;
+  o->max_iter = 200;
+  o->ckpt_every = 16;
+  return 0;
+}
+
+int ww_bfgs(ww_ctx* c, double* cvec, int nsteps, const ww_bfgs_opts* opts, ww_bfgs_report* rep) {
+  if (!c || !cvec) return fail(WW_EINVAL, "null argument");
+  if (!c->shoot_ready) return fail(WW_ENOSETUP, "ww_bfgs before shoot_setup");
+  if (nsteps < 1) return fail(WW_EINVAL, "nsteps >= 1 required");
+  ww_bfgs_opts o;
+  ww_bfgs_default_opts(&o);
+  if (opts) o = *opts;
+  if (!(o.delta0 > 0.0) || o.max_iter < 1 || o.ckpt_every < 1) return fail(WW_EINVAL, "bad options");
+  int rc;
+  if ((rc = ensure_lm(c))) return rc;
+  const int n = c->M + 1;
+  std::vector<double> cv(cvec, cvec + n), g, gn, p(n), cn(n), s(n), y(n), Hy(n);
+  std::vector<double> H((size_t)n * n, 0.0);
+  for (int i = 0; i < n; ++i) H[(size_t)i * n + i] = 1.0;
+  double f = 0.0, fn = 0.0;
+  if ((rc = bfgs_fg(c, cv, nsteps, o.ckpt_every, &f, g))) return rc;
+  int evals = 1, iters = 0, nh = 0, reason = WW_BFGS_MAX_ITER;
+  bool first = true;
+  for (iters = 0; iters < o.max_iter; ++iters) {
+    if (f < o.f_tol) {
+      reason = WW_BFGS_F_TOL;
+      break;
+    }
+    if (std::sqrt(dotv(g, g)) < o.g_tol) {
+      reason = WW_BFGS_G_TOL;
+      break;
+    }
+    for (int i = 0; i < n; ++i) {
+      double a = 0.0;
+      for (int j = 0; j < n; ++j) a += H[(size_t)i * n + j] * g[j];
+      p[i] = -a;
+    }
+    if (dotv(g, p) >= 0.0) {   // not a descent direction: steepest descent
+      std::fill(H.begin(), H.end(), 0.0);
+      for (int i = 0; i < n; ++i) {
+        H[(size_t)i * n + i] = 1.0;
+        p[i] = -g[i];
+      }
+    }
+    const double a1 = first ? std::min(1.0, o.delta0 / std::sqrt(dotv(p, p))) : 1.0;
+    double a = 0.0;
+    bool ok = false;
+    if ((rc = bfgs_line_search(c, nsteps, o.ckpt_every, cv, f, g, p, a1, &a, &fn, gn, &evals, &ok))) return rc;
+    if (!ok && !(fn < f)) {
+      reason = WW_BFGS_LINE_SEARCH;
+      break;
+    }
+    bool same = true;
+    for (int i = 0; i < n; ++i) {
+      cn[i] = cv[i] + a * p[i];
+      if (cn[i] != cv[i]) same = false;
+      s[i] = cn[i] - cv[i];
+      y[i] = gn[i] - g[i];
+    }
+    if (same) {
+      reason = WW_BFGS_C_UNCHANGED;
+      break;
+    }
+    const double sy = dotv(s, y);
+    if (sy > 0.0) {
+      if (first) {
+        const double sc = sy / dotv(y, y);
+        for (int i = 0; i < n; ++i)
+          for (int j = 0; j < n; ++j) H[(size_t)i * n + j] = i == j ? sc : 0.0;
+      }
+      // H <- (I - rho s y^T) H (I - rho y s^T) + rho s s^T, expanded
+      const double rho = 1.0 / sy;
+      for (int i = 0; i < n; ++i) {
+        double a2 = 0.0;
+        for (int j = 0; j < n; ++j) a2 += H[(size_t)i * n + j] * y[j];
+        Hy[i] = a2;
+      }
+      const double yHy = dotv(y, Hy);
+      for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+          H[(size_t)i * n + j] += -rho * (s[i] * Hy[j] + Hy[i] * s[j]) + (rho * rho * yHy + rho) * s[i] * s[j];
+      first = false;
+    }
+    cv = cn;
+    f = fn;
+    g = gn;
+    if (rep && rep->history && nh < rep->hist_cap) {
+      double* h = rep->history + (size_t)nh * (n + 1);
+      for (int i = 0; i < n; ++i) h[i] = cv[i];
+      h[n] = f;
+    }
+    ++nh;
+  }
+  for (int i = 0; i < n; ++i) cvec[i] = cv[i];
+  if (rep) {
+    rep->f = f;
+    rep->gnorm = std::sqrt(dotv(g, g));
+    rep->iters = iters;
+    rep->evals = evals;
+    rep->reason = reason;
+    rep->n_hist = nh;
+  }
+  return 0;
+}
+
 int ww_lm_default_opts(ww_lm_opts* o) {
   if (!o) return fail(WW_EINVAL, "null argument");
   o->f_tol = 1e-26;

@@ -37,6 +37,20 @@ class LmOpts(ctypes.Structure):
                 ("delta0", ctypes.c_double), ("max_steps_J", ctypes.c_int), ("max_evals", ctypes.c_int)]
 
 
+class BfgsOpts(ctypes.Structure):
+    _fields_ = [("f_tol", ctypes.c_double), ("g_tol", ctypes.c_double), ("delta0", ctypes.c_double),
+                ("max_iter", ctypes.c_int), ("ckpt_every", ctypes.c_int)]
+
+
+class BfgsReport(ctypes.Structure):
+    _fields_ = [("f", ctypes.c_double), ("gnorm", ctypes.c_double), ("iters", ctypes.c_int),
+                ("evals", ctypes.c_int), ("reason", ctypes.c_int), ("n_hist", ctypes.c_int),
+                ("history", ctypes.POINTER(ctypes.c_double)), ("hist_cap", ctypes.c_int)]
+
+
+BFGS_REASONS = {1: "f_tol", 2: "g_tol", 3: "c unchanged", 4: "line search", 5: "max_iter"}
+
+
 class LmReport(ctypes.Structure):
     _fields_ = [("f", ctypes.c_double), ("delta", ctypes.c_double), ("evals_r", ctypes.c_int),
                 ("evals_J", ctypes.c_int), ("reason", ctypes.c_int), ("n_hist", ctypes.c_int),
@@ -45,7 +59,7 @@ class LmReport(ctypes.Structure):
 EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_setup",
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
-           "ww_thin_svd", "ww_levmar", "ww_lm_default_opts"]
+           "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts"]
 
 
 class WWError(RuntimeError):
@@ -87,11 +101,13 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ww_thin_svd.argtypes = [P, P, I, I, DP, DP, P]
     lib.ww_levmar.argtypes = [P, DP, I, ctypes.POINTER(LmOpts), ctypes.POINTER(LmReport)]
     lib.ww_lm_default_opts.argtypes = [ctypes.POINTER(LmOpts)]
+    lib.ww_bfgs.argtypes = [P, DP, I, ctypes.POINTER(BfgsOpts), ctypes.POINTER(BfgsReport)]
+    lib.ww_bfgs_default_opts.argtypes = [ctypes.POINTER(BfgsOpts)]
     lib.ww_last_error.restype = ctypes.c_char_p
     lib.ww_version.restype = ctypes.c_char_p
     for name in ["ww_create", "ww_set_stream", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
                  "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read", "ww_fallbacks",
-                 "ww_thin_svd", "ww_levmar", "ww_lm_default_opts"]:
+                 "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts"]:
         getattr(lib, name).restype = I
     _lib = lib
     return lib
@@ -248,6 +264,26 @@ class Context:
         _check(self.lib.ww_levmar(self.ptr, _dp(c), int(nsteps), ctypes.byref(o), ctypes.byref(rep)))
         return dict(c=c, f=rep.f, delta=rep.delta, evals_r=rep.evals_r, evals_J=rep.evals_J,
                     reason=LM_REASONS.get(rep.reason, rep.reason),
+                    history=h[:min(rep.n_hist, hist_cap)] if hist_cap > 0 else None)
+
+    def bfgs(self, c0, nsteps: int, opts: dict | None = None, hist_cap: int = 0):
+        """BFGS with the adjoint gradient (Sec. 3.2) on the shooting problem of
+        shoot_setup.  c0 = (T, params...).  Returns dict(c, f, gnorm, iters, evals,
+        reason, history) -- history rows (c, f) after every iteration."""
+        n = self.M + 1
+        c = np.ascontiguousarray(np.array(c0, dtype=np.float64))
+        assert c.shape == (n,)
+        o = BfgsOpts()
+        _check(self.lib.ww_bfgs_default_opts(ctypes.byref(o)))
+        for k, v in (opts or {}).items():
+            setattr(o, k, v)
+        h = np.zeros((max(hist_cap, 1), n + 1))
+        rep = BfgsReport()
+        rep.history = _dp(h) if hist_cap > 0 else None
+        rep.hist_cap = hist_cap
+        _check(self.lib.ww_bfgs(self.ptr, _dp(c), int(nsteps), ctypes.byref(o), ctypes.byref(rep)))
+        return dict(c=c, f=rep.f, gnorm=rep.gnorm, iters=rep.iters, evals=rep.evals,
+                    reason=BFGS_REASONS.get(rep.reason, rep.reason),
                     history=h[:min(rep.n_hist, hist_cap)] if hist_cap > 0 else None)
 
     def profile(self, enable: bool = True):

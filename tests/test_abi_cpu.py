@@ -64,3 +64,11 @@ def test_levenberg_marquardt_defaults_are_the_papers():
     o = ww.LmOpts()
     assert lib.ww_lm_default_opts(ctypes.byref(o)) == 0
     assert (o.f_tol, o.g_tol, o.df_tol, o.max_steps_J) == (1e-26, 1e-13, 1e-5, 10)
+
+
+def test_bfgs_defaults():
+    ww, lib = _lib()
+    o = ww.BfgsOpts()
+    assert lib.ww_bfgs_default_opts(ctypes.byref(o)) == 0
+    assert (o.f_tol, o.g_tol, o.ckpt_every) == (1e-26, 1e-13, 16)
+    assert lib.ww_bfgs(None, None, 1, None, None) == -1

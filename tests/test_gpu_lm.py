@@ -147,3 +147,40 @@ def test_levmar_against_the_oracle_driver(a1):
     # of J, so the GPU's point is checked for being a solution by the oracle itself
     assert abs(out["c"][0] - ref.c[0]) <= 1e-11 * ref.c[0]
     assert 0.5 * float(np.sum(res(out["c"]) ** 2)) < 1e-24
+
+
+def test_bfgs_against_the_oracle_driver():
+    """BFGS with the discrete adjoint gradient (GPU) against the oracle's BFGS with the
+    gradient J^T r of the forward Jacobian (the same gradient to rounding, reading R9):
+    the same iterates while f is well above the rounding of r (f > 1e-12: below that the
+    gradient carries the absolute rounding of r, and the two drivers part), the same
+    period, and a final point that is a solution for the oracle too."""
+    from oracle import bfgs_oracle as B
+    ww, torch = _ww()
+    N, nsteps, nmodes, a1 = 32, 12, 10, 0.05
+    basis, qf, c0 = _standing_wave(N, nsteps, a1, nmodes)
+
+    def fg(c):
+        out = O.shoot_eval(N, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], nsteps, jacobian=True)
+        J = np.concatenate([out["drdT"][:, None], out["J"]], axis=1)
+        return 0.5 * float(out["r"] @ out["r"]), J.T @ out["r"]
+
+    ref = B.bfgs(fg, c0, delta0=0.1, max_iter=80)
+    ctx = ww.Context(n_max=64, r_max=nmodes)
+    ctx.shoot_setup(N, math.inf, 0.0, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    out = ctx.bfgs(c0, nsteps, opts={"delta0": 0.1, "max_iter": 80, "ckpt_every": 4}, hist_cap=100)
+    print("oracle", ref.f, ref.reason, len(ref.history), ref.evals, "gpu", out["f"], out["reason"], out["iters"],
+          out["evals"])
+    assert out["f"] < 1e-24 and ref.f < 1e-24
+    compared = 0
+    for k, (cn, fn) in enumerate(ref.history):
+        if fn < 1e-12 or k >= len(out["history"]):
+            break
+        h = out["history"][k]
+        assert np.abs(h[:-1] - cn).max() <= 1e-9 * np.abs(cn).max(), (k, h[:-1] - cn)
+        assert abs(h[-1] - fn) <= 1e-7 * fn, (k, h[-1], fn)
+        compared += 1
+    assert compared >= 8
+    assert abs(out["c"][0] - ref.c[0]) <= 1e-11 * ref.c[0]
+    res = lambda c: O.shoot_eval(N, math.inf, 0.0, 1.0, basis, qf, c[1:], c[0], nsteps, jacobian=False)["r"]
+    assert 0.5 * float(np.sum(res(out["c"]) ** 2)) < 1e-22

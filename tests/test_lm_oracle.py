@@ -122,3 +122,46 @@ def test_standing_wave_period_shift_is_second_order_in_amplitude():
         shifts.append(out.c[0] - 2 * np.pi)
     assert shifts[0] > 0
     assert abs(shifts[1] / shifts[0] - 4.0) < 0.08
+
+
+# ----- BFGS (ACM minimiser, Sec. 3.2) -----
+from oracle import bfgs_oracle as B
+
+
+def test_bfgs_minimises_a_convex_quadratic_exactly():
+    """On f = x^T A x / 2 - b^T x the minimiser is A^{-1} b (solve), reached to rounding."""
+    rng = np.random.default_rng(4)
+    Q = rng.standard_normal((6, 6))
+    A = Q @ Q.T + 6 * np.eye(6)
+    b = rng.standard_normal(6)
+    out = B.bfgs(lambda x: (0.5 * x @ A @ x - b @ x, A @ x - b), np.zeros(6), f_tol=-np.inf, g_tol=1e-13)
+    assert np.allclose(out.c, np.linalg.solve(A, b), rtol=1e-11, atol=1e-13)
+    assert out.reason == "g_tol"
+
+
+def test_bfgs_rosenbrock_reaches_the_minimum():
+    """The Rosenbrock valley's unique minimiser (1, 1), against scipy's BFGS reaching it too."""
+    import scipy.optimize as so
+
+    def fg(x):
+        a, b_ = x
+        return (1 - a) ** 2 + 100 * (b_ - a * a) ** 2, np.array([-2 * (1 - a) - 400 * a * (b_ - a * a),
+                                                                 200 * (b_ - a * a)])
+    out = B.bfgs(fg, np.array([-1.2, 1.0]), delta0=1.0, f_tol=1e-24, g_tol=1e-12)
+    assert np.allclose(out.c, [1.0, 1.0], atol=1e-9)
+    ref = so.minimize(lambda x: fg(x)[0], np.array([-1.2, 1.0]), jac=lambda x: fg(x)[1], method="BFGS",
+                      options={"gtol": 1e-10})
+    assert np.allclose(ref.x, out.c, atol=1e-6)
+
+
+def test_bfgs_line_search_meets_the_strong_wolfe_conditions():
+    rng = np.random.default_rng(5)
+    A = np.diag(rng.uniform(0.5, 5.0, 5))
+    fg = lambda x: (0.5 * x @ A @ x + np.sum(np.cos(x)), A @ x - np.sin(x))
+    c = rng.standard_normal(5)
+    f0, g0 = fg(c)
+    p = -g0
+    a, f, g, _, ok = B.line_search(fg, c, f0, g0, p, 1.0)
+    assert ok
+    assert f <= f0 + B.C1 * a * (g0 @ p)
+    assert abs(g @ p) <= -B.C2 * (g0 @ p)
