@@ -72,3 +72,26 @@ def test_bfgs_defaults():
     assert lib.ww_bfgs_default_opts(ctypes.byref(o)) == 0
     assert (o.f_tol, o.g_tol, o.ckpt_every) == (1e-26, 1e-13, 16)
     assert lib.ww_bfgs(None, None, 1, None, None) == -1
+
+
+def test_jacobi_round_schedule_covers_every_pair_once():
+    """The circle-method pairing of the one-sided Jacobi SVD (round rd, pair q: players
+    rd and n2 - 1 for q = 0, else (rd + q) and (rd - q) mod (n2 - 1)) visits every pair of
+    the n columns exactly once per sweep and never a column twice in one round (the
+    pairs of a round run in parallel); players >= n are padding."""
+    for n in (1, 2, 3, 8, 33, 129, 257):
+        n2 = (n + 1) & ~1
+        m = n2 - 1
+        seen = {}
+        for rd in range(max(m, 0)):
+            used = set()
+            for q in range(n2 // 2):
+                a = rd if q == 0 else (rd + q) % m
+                b = m if q == 0 else (rd - q + m) % m
+                a, b = min(a, b), max(a, b)
+                assert a != b
+                assert a not in used and b not in used
+                used.update((a, b))
+                if b < n:
+                    seen[(a, b)] = seen.get((a, b), 0) + 1
+        assert len(seen) == n * (n - 1) // 2 and all(v == 1 for v in seen.values()), n
