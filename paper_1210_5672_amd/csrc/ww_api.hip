@@ -136,6 +136,11 @@ struct ww_ctx {
   RingSet ring[16];
   hipStream_t lus[PIPE_MAXLAG] = {};
   hipEvent_t evA[16] = {}, evL[16] = {};
+  // one graph per branch and stage of the lagged-factor march (prep, LU, base, columns)
+  // and the step end, replayed on their own streams; pkey: what they were captured for
+  hipGraphExec_t pgx[16][4] = {};
+  hipGraphExec_t pgend = nullptr;
+  long long pkey = -1;
   // thin SVD / Levenberg-Marquardt workspace (first use): W (n_max x r_max), residuals,
   // parameters, V (r_max^2), column norms and dots, convergence flag, column order
   double *lmW = nullptr, *lmr = nullptr, *lmrn = nullptr, *lmp = nullptr, *lmV = nullptr;
@@ -378,6 +383,10 @@ void ww_destroy(ww_ctx* c) {
   // no work of this context (stream-ordered calls, graph branches) may still run
   (void)hipDeviceSynchronize();
   if (c->step_exec) (void)hipGraphExecDestroy(c->step_exec);
+  for (int s = 0; s < 16; ++s)
+    for (int q = 0; q < 4; ++q)
+      if (c->pgx[s][q]) (void)hipGraphExecDestroy(c->pgx[s][q]);
+  if (c->pgend) (void)hipGraphExecDestroy(c->pgend);
   if (c->stamps) (void)hipFree(c->stamps);
   if (c->ckpt) (void)hipFree(c->ckpt);
   if (c->seg) (void)hipFree(c->seg);
@@ -906,6 +915,121 @@ static int pipe_prologue(ww_ctx* c) {
   return 0;
 }
 
+// The parts of stage s of the lagged-factor march, each captured alone: 0 spectral prep
+// and assembly (main stream), 1 the LU of the stage (LU stream s % lag), 2 the lagged
+// base solve to the base right-hand side (main), 3 the column chain (side stream).
+enum { PP_PREP = 0, PP_LU = 1, PP_BASE = 2, PP_COL = 3 };
+
+static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
+  const int nst = c->nst, L = c->lag;
+  const Fac F = pipe_set(c, s, false);
+  int rc = 0;
+  if (part == PP_PREP) {
+    if ((rc = prof_mark(c, 1, 0))) return rc;
+    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys, c->coef,
+                       s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
+    LAUNCHCHK();
+    return enqueue_assemble(c, F, true);
+  }
+  if (part == PP_LU) return enqueue_lu(c, F);
+  if (part == PP_BASE) {
+    const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
+    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0))) return rc;
+    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->mu0, c->Np, 1, c->gam0,
+                       c->hg0, c->tw, c->N);
+    LAUNCHCHK();
+    if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
+                       c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
+    LAUNCHCHK();
+    return prof_mark(c, 1, 1);
+  }
+  return enqueue_col_chain(c, s, pipe_set(c, s, true));
+}
+
+static int enqueue_pipe_end(ww_ctx* c) {
+  hipLaunchKernelGGL(k_step_end, dim3(c->M + 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y, c->K, kstride(c),
+                     c->nst, c->coef, c->tw, c->sig, c->N, 0, c->status);
+  LAUNCHCHK();
+  return 0;
+}
+
+// capture one part (part < 0: the step end) on the capture stream, alone
+static int capture_part(ww_ctx* c, int s, int part, hipGraphExec_t* out) {
+  hipStream_t user = c->stream;
+  const hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
+  if (eb != hipSuccess) return fail(WW_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
+  c->stream = c->cap_stream;
+  c->prof_stage = part < 0 ? -1 : s;
+  const int rc = part < 0 ? enqueue_pipe_end(c) : enqueue_pipe_part(c, s, part);
+  c->prof_stage = -1;
+  hipGraph_t g = nullptr;
+  const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
+  c->stream = user;
+  if (rc) {
+    if (e == hipSuccess && g) (void)hipGraphDestroy(g);
+    return rc;
+  }
+  HIPCHK(e);
+  const hipError_t ei = hipGraphInstantiate(out, g, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(g);
+  HIPCHK(ei);
+  return 0;
+}
+
+static long long pipe_key(const ww_ctx* c) {
+  return (((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 8 + c->lag) * 2 + (c->prof ? 1 : 0)) * 16 + c->fb;
+}
+
+static int ensure_pipe_graphs(ww_ctx* c) {
+  if (c->pkey == pipe_key(c) && c->pgend) return 0;
+  HIPCHK(hipDeviceSynchronize());   // no replay of the old graphs may still run
+  for (int s = 0; s < 16; ++s)
+    for (int q = 0; q < 4; ++q)
+      if (c->pgx[s][q]) {
+        HIPCHK(hipGraphExecDestroy(c->pgx[s][q]));
+        c->pgx[s][q] = nullptr;
+      }
+  if (c->pgend) {
+    HIPCHK(hipGraphExecDestroy(c->pgend));
+    c->pgend = nullptr;
+  }
+  c->pkey = -1;
+  int rc;
+  for (int s = 0; s < c->nst; ++s)
+    for (int q = 0; q < 4; ++q)
+      if ((rc = capture_part(c, s, q, &c->pgx[s][q]))) return rc;
+  if ((rc = capture_part(c, 0, -1, &c->pgend))) return rc;
+  c->pkey = pipe_key(c);
+  return 0;
+}
+
+// One step of the lagged-factor march from the per-branch graphs: each branch on its
+// own stream (so on its own queue), the dependencies of the step as events.  The end of
+// the previous step waited for every column chain and, through them, every LU.
+static int pipe_step(ww_ctx* c) {
+  const int nst = c->nst, L = c->lag;
+  hipStream_t s0 = c->stream;
+  for (int s = 0; s < nst; ++s) {
+    hipStream_t ls = c->lus[s % L];
+    HIPCHK(hipGraphLaunch(c->pgx[s][PP_PREP], s0));
+    HIPCHK(hipEventRecord(c->evA[s], s0));
+    HIPCHK(hipStreamWaitEvent(ls, c->evA[s], 0));
+    HIPCHK(hipGraphLaunch(c->pgx[s][PP_LU], ls));
+    HIPCHK(hipEventRecord(c->evL[s], ls));
+    if (s >= L) HIPCHK(hipStreamWaitEvent(s0, c->evL[s - L], 0));
+    HIPCHK(hipGraphLaunch(c->pgx[s][PP_BASE], s0));
+    HIPCHK(hipEventRecord(c->evB[s], s0));
+    HIPCHK(hipStreamWaitEvent(c->side, c->evB[s], 0));
+    HIPCHK(hipStreamWaitEvent(c->side, c->evL[s], 0));
+    HIPCHK(hipGraphLaunch(c->pgx[s][PP_COL], c->side));
+    HIPCHK(hipEventRecord(c->evC[s], c->side));
+  }
+  HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
+  HIPCHK(hipGraphLaunch(c->pgend, s0));
+  return 0;
+}
+
 static int enqueue_step_pipe(ww_ctx* c) {
   int rc = 0;
   const int nst = c->nst, L = c->lag;
@@ -1190,6 +1314,9 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
   int rc;
   if ((rc = set_grid(c, N, h))) return rc;
   c->dtn_ready = false;   // the grid of a previous dtn_setup is gone
+  // the step graphs hold depth, tension and gravity as kernel arguments: capture again
+  c->gnst = -1;
+  c->pkey = -1;
   c->tau = tau;
   c->g = g;
   c->M = M;
@@ -1242,12 +1369,15 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   if (pipelined(c, cols, two_streams)) {
     if ((rc = ensure_pipe(c))) return rc;
     if ((rc = pipe_prologue(c))) return rc;
+    if (graphed(c)) return ensure_pipe_graphs(c);
+    return 0;
   }
   if (graphed(c)) return ensure_step_graph(c, cols, two_streams);
   return 0;
 }
 
 static int shoot_one_step(ww_ctx* c, bool cols, bool two_streams) {
+  if (graphed(c) && pipelined(c, cols, two_streams)) return pipe_step(c);
   if (graphed(c)) {
     HIPCHK(hipGraphLaunch(c->step_exec, c->stream));
     return 0;

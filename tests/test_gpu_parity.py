@@ -129,6 +129,25 @@ def test_lagged_factor_march_matches_direct(monkeypatch, case, mixed):
         assert relerr(res["4"][k].cpu().numpy(), res["0"][k].cpu().numpy()) < TOL
 
 
+def test_new_shoot_setup_recaptures_the_step_graph():
+    """A second shoot_setup on the same context with another depth and tension (same N,
+    M) gives exactly the results of a fresh context: the captured step kernels hold depth,
+    tension and gravity by value, so the graph must be captured again."""
+    ww, torch = _ww()
+    N, M = 64, 4
+    p = np.array([0.01, 0.0, 0.001, 0.0])
+    wa = W.Workload("a", N, math.inf, 0.0, 1.0, M, 2 * math.pi, 8, p, W.cosine_basis(N, M), np.zeros(2 * N))
+    wb = W.Workload("b", N, 0.7, 0.02, 1.3, M, W.linear_period(0.7, 0.02), 8, p, W.cosine_basis(N, M),
+                    np.zeros(2 * N))
+    ctx = ww.Context(n_max=N, r_max=M + 1)
+    for w in (wa, wb):
+        ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        out = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+    fresh = _shoot(ww, wb)
+    assert np.array_equal(out["r"].cpu().numpy(), fresh["r"].cpu().numpy())
+    assert np.array_equal(out["J"].cpu().numpy(), fresh["J"].cpu().numpy())
+
+
 def test_shoot_eval_finite_depth_tension_padded_grid():
     ww, torch = _ww()
     rng = np.random.default_rng(5)

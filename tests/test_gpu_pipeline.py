@@ -1,0 +1,77 @@
+"""The lagged-factor march (opt-in, WW_PIPE_LAG) in its per-branch-graph form: every
+stage's base chain solves with the factors of the stage `lag` stages earlier, refined
+against its own matrix, while its own LU runs on one of `lag` streams; each branch of a
+stage is a graph of its own, replayed on its own stream.  Held against the oracle and
+against the march that solves every stage with its own factors."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import ww_oracle as O
+from paper_1210_5672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL = 1e-12
+
+
+def _ww():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    return ww, torch
+
+
+def relerr(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+def _run(ww, w, lag, mixed=False):
+    import os
+    os.environ["WW_PIPE_LAG"] = str(lag)
+    try:
+        ctx = ww.Context(n_max=max(w.N, 64), r_max=w.M + 1, mixed=mixed)
+    finally:
+        del os.environ["WW_PIPE_LAG"]
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    out = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+    return ctx, out
+
+
+@pytest.mark.parametrize("lag", [2, 4])
+@pytest.mark.parametrize("mixed", [False, True])
+def test_lagged_march_c1(lag, mixed):
+    """C1 (64 steps): ||A_old^{-1} A_new - I|| is about 6e-6 per step, so the lagged
+    solves converge in the two sweeps: no fallback, the oracle's r and J to 1e-12, and
+    the direct march's to 1e-12."""
+    ww, torch = _ww()
+    w = W.c1()
+    print(f"lagged march c1 lag={lag} mixed={mixed}", flush=True)
+    ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
+    ctx, out = _run(ww, w, lag, mixed)
+    assert ctx.fallbacks() == 0
+    assert relerr(out["r"].cpu().numpy(), ref["r"]) < TOL
+    assert relerr(out["J"].cpu().numpy(), ref["J"]) < TOL
+    assert abs(out["f"] - ref["f"]) <= TOL * ref["f"]
+    ctx0, out0 = _run(ww, w, 0, mixed)
+    assert relerr(out["J"].cpu().numpy(), out0["J"].cpu().numpy()) < TOL
+
+
+def test_lagged_march_falls_back_on_a_fast_changing_surface():
+    """The steep surface changes too fast for factors four stages old (0.03 to 0.13 per
+    step): the first step's check sends the march to each stage's own factors
+    (WW_FB_DIRECT), which match the oracle."""
+    ww, torch = _ww()
+    N, M = 64, 3
+    eta = W.steep_surface(N)
+    w = W.Workload("t", N, 1.0, 0.0, 1.0, M, 0.1, 4, np.array([0.01, 0.005, 0.002]), W.cosine_basis(N, M),
+                   np.concatenate([eta, np.zeros(N)]))
+    ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
+    ctx, out = _run(ww, w, 4)
+    assert ctx.fallbacks() == ww.WW_FB_DIRECT
+    assert relerr(out["r"].cpu().numpy(), ref["r"]) < TOL
+    assert relerr(out["J"].cpu().numpy(), ref["J"]) < TOL
