@@ -158,7 +158,9 @@ def test_shoot_eval_pivoted_fallback(monkeypatch, mixed):
     ref = O.shoot_eval(w["N"], w["h"], w["tau"], w["g"], w["basis"], w["q"], w["p"], w["T"], w["nsteps"])
     c0 = _shoot_ctx(ww, w, mixed=mixed)
     e0 = _cmp(c0.shoot_eval(ww.to_dev(w["p"]), w["T"], w["nsteps"]), ref)
-    assert c0.fallbacks() == 0
+    # no pivoting needed; with lagged factors (WW_PIPE_LAG) this fast-changing surface
+    # falls back to each stage's own factors
+    assert c0.fallbacks() in (0, ww.WW_FB_DIRECT)
     assert max(e0.values()) < TOL, e0
     monkeypatch.setenv("WW_PIVOT_GUARD", GUARD)
     c1 = _shoot_ctx(ww, w, mixed=mixed)

@@ -32,11 +32,15 @@ def relerr(a, b):
 
 def _run(ww, w, lag, mixed=False):
     import os
+    old = os.environ.get("WW_PIPE_LAG")
     os.environ["WW_PIPE_LAG"] = str(lag)
     try:
         ctx = ww.Context(n_max=max(w.N, 64), r_max=w.M + 1, mixed=mixed)
     finally:
-        del os.environ["WW_PIPE_LAG"]
+        if old is None:
+            del os.environ["WW_PIPE_LAG"]
+        else:
+            os.environ["WW_PIPE_LAG"] = old
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     out = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
     return ctx, out
