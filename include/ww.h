@@ -88,7 +88,7 @@ typedef struct ww_ctx ww_ctx;
 #define WW_FB_DIRECT 4u    /* the lagged-factor solves of a single-instance march (see
                               shoot_eval), or the GMRES solves (WW_GMRES), failed their
                               residual test; the march was redone with every stage's own
-                              LU factors */
+                              LU factors, in the context's precision form */
 
 /*
  * ww_create: allocate a context whose device workspace serves every N <= n_max and
@@ -152,13 +152,16 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  *   J    (N x M)  J_ik = phidot_k(alpha_i, T/4) / sqrt(N), or NULL (base only, R = 1)
  *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
  *   f    (host)   f = r.r / 2, or NULL
- * Lagged factors (opt-in: environment WW_PIPE_LAG = L, 1..4, read by ww_create; off by
- * default): in a march of one instance, the base chain of stage s (the march's
- * critical path) solves with the factors of stage s - L and refines the solution with
+ * Lagged factors (L = 4; environment WW_PIPE_LAG, 0..4, read by ww_create; 0 turns them
+ * off): in a march of one instance, the base chain of stage s (the march's critical
+ * path) solves with the factors of stage s - L and refines the solution with
  * the FP64 residual of its own matrix (the same number of sweeps and the same
  * convergence test as WW_MIXED), while the LU of its own matrix runs concurrently on one
- * of L streams; the column chain of stage s uses that stage's own factors.  A failed
- * test redoes the march with every stage's own factors (WW_FB_DIRECT).
+ * of L streams; the column chain of stage s uses that stage's own factors.  Each branch
+ * of a stage (spectral prep and assembly; the LU; the lagged base solve to the base
+ * right-hand side; the column chain) is a graph of its own, replayed on its own stream
+ * with the dependencies as events.  A failed test (checked after the first step, and at
+ * the end) redoes the march with every stage's own factors (WW_FB_DIRECT).
  * Synchronises to check the status flags.  A pivot below the guard anywhere in the
  * march redoes it with partial pivoting; a failed refinement test (WW_MIXED) redoes it
  * with FP64 factors (see ww_fallbacks).
@@ -174,7 +177,7 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
  * context replays a captured step graph on its stream and the steps of all instances
  * are issued interleaved.  With more than one instance the step graphs keep each
  * instance on its one stream (the column chain follows the base chain), which lets the
- * GPU overlap the instances; a single instance uses the two-stream graph of shoot_eval.  Per-instance arrays: params[i] (device),
+ * GPU overlap the instances; a single instance is marched as by shoot_eval.  Per-instance arrays: params[i] (device),
  * T[i], nsteps[i] (host), r[i] (device), J[i] (device or NULL; J may be NULL),
  * drdT[i] (device or NULL; drdT may be NULL), f[i] (host; f may be NULL).
  * Results are identical to n_inst separate shoot_eval calls: an instance whose march

@@ -131,7 +131,7 @@ struct ww_ctx {
   // lagged-factor pipeline of single-instance marches: the base solve of stage s uses
   // the factors of stage s - lag (refined against its own matrix) while the LU of
   // stage s runs on one of `lag` streams; the column chain of stage s waits for it
-  int lag = 0;   // environment WW_PIPE_LAG, 1..4 (default 0: every solve uses its own factors)
+  int lag = PIPE_MAXLAG;   // environment WW_PIPE_LAG, 0..4 (0: every solve uses its own factors)
   int ring_n = 0;          // factor sets allocated (one per stage)
   RingSet ring[16];
   hipStream_t lus[PIPE_MAXLAG] = {};
@@ -485,8 +485,9 @@ static int prof_mark(ww_ctx* c, int phase, int which) {
 
 static bool mixed(const ww_ctx* c) { return (c->flags & WW_MIXED) != 0; }
 static bool strict(const ww_ctx* c) { return (c->flags & WW_STRICT) != 0; }
-// FP32 factors only on the context's own path (every fallback factors in FP64)
-static bool use32(const ww_ctx* c) { return mixed(c) && c->fb == 0; }
+// FP32 factors in the mixed form, except after the FP64 or the pivoting fallback (the
+// fallback to each stage's own factors keeps the precision form)
+static bool use32(const ww_ctx* c) { return mixed(c) && !(c->fb & (WW_FB_FP64 | WW_FB_PIVOTED)); }
 static bool pivoted(const ww_ctx* c) { return (c->fb & WW_FB_PIVOTED) != 0; }
 // pivot bound of the pivoted factorisation (near singularity)
 static const double PIVOTED_GUARD = 1e-8;
