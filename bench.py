@@ -28,7 +28,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md, calibrated with a
 # plain 256 MiB copy.  Valid only for the kernel source it was measured on: reported as
 # null once the kernels header changes.
-LU_TRAFFIC_BYTES = 266.8e6
+LU_TRAFFIC_BYTES = 266.9e6
 LU_TRAFFIC_SOURCE_SHA256 = "f9c501e9e60f05c0eb88029565cf0f2b3c86e0d6d96135f657260eb6b3426ad3"
 
 
