@@ -79,3 +79,24 @@ def test_lagged_march_falls_back_on_a_fast_changing_surface():
     assert ctx.fallbacks() == ww.WW_FB_DIRECT
     assert relerr(out["r"].cpu().numpy(), ref["r"]) < TOL
     assert relerr(out["J"].cpu().numpy(), ref["J"]) < TOL
+
+
+def test_phase_profile_in_the_lagged_march():
+    """ww_profile's timestamp nodes sit inside the per-branch graphs: every phase of every
+    stage is counted once per step, and the phases are positive."""
+    ww, torch = _ww()
+    w = W.c1()
+    import os
+    old = os.environ.pop("WW_PIPE_LAG", None)
+    try:
+        ctx = ww.Context(n_max=64, r_max=w.M + 1)
+    finally:
+        if old is not None:
+            os.environ["WW_PIPE_LAG"] = old
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    ctx.profile(True)
+    ctx.shoot_eval(ww.to_dev(w.params), w.T, 6)
+    ph = [ctx.profile_read(k) for k in range(3)]
+    print("phases ms", ph)
+    assert all(p > 0 for p in ph)
+    assert ctx.fallbacks() == 0
