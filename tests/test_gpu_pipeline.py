@@ -82,8 +82,8 @@ def test_lagged_march_falls_back_on_a_fast_changing_surface():
 
 
 def test_phase_profile_in_the_lagged_march():
-    """ww_profile's timestamp nodes sit inside the per-branch graphs: every phase of every
-    stage is counted once per step, and the phases are positive."""
+    """ww_profile's timestamp nodes sit inside the per-branch graphs (the LU phase on the
+    LU streams, the base and column chains on theirs): every phase reads a positive mean."""
     ww, torch = _ww()
     w = W.c1()
     import os
