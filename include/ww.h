@@ -152,7 +152,7 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  *   J    (N x M)  J_ik = phidot_k(alpha_i, T/4) / sqrt(N), or NULL (base only, R = 1)
  *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
  *   f    (host)   f = r.r / 2, or NULL
- * Lagged factors (L = 4; environment WW_PIPE_LAG, 0..4, read by ww_create; 0 turns them
+ * Lagged factors (L = 5; environment WW_PIPE_LAG, 0..6, read by ww_create; 0 turns them
  * off): in a march of one instance, the base chain of stage s (the march's critical
  * path) solves with the factors of stage s - L and refines the solution with
  * the FP64 residual of its own matrix (the same number of sweeps and the same

@@ -45,7 +45,7 @@ struct RingSet {
   float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
   float *X32r = nullptr, *Z32r = nullptr;
 };
-#define PIPE_MAXLAG 4
+#define PIPE_MAXLAG 6
 
 struct ww_ctx {
   int dev = 0;
@@ -131,7 +131,7 @@ struct ww_ctx {
   // lagged-factor pipeline of single-instance marches: the base solve of stage s uses
   // the factors of stage s - lag (refined against its own matrix) while the LU of
   // stage s runs on one of `lag` streams; the column chain of stage s waits for it
-  int lag = PIPE_MAXLAG;   // environment WW_PIPE_LAG, 0..4 (0: every solve uses its own factors)
+  int lag = 5;   // environment WW_PIPE_LAG, 0..PIPE_MAXLAG (0: every solve uses its own factors)
   int ring_n = 0;          // factor sets allocated (one per stage)
   RingSet ring[16];
   hipStream_t lus[PIPE_MAXLAG] = {};
