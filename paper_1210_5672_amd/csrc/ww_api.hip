@@ -137,9 +137,13 @@ struct ww_ctx {
   hipStream_t lus[PIPE_MAXLAG] = {};
   hipEvent_t evA[16] = {}, evL[16] = {};
   // one graph per branch and stage of the lagged-factor march (prep, LU, base, columns)
-  // and the step end, replayed on their own streams; pkey: what they were captured for
+  // and the two halves of the step end (base column: main stream; Jacobian columns:
+  // column stream), replayed on their own streams; pkey: what they were captured for.
+  // evE: the column stream's step end; pjoin: the main stream has not yet waited for it
   hipGraphExec_t pgx[16][4] = {};
-  hipGraphExec_t pgend = nullptr;
+  hipGraphExec_t pgend = nullptr, pgendc = nullptr;
+  hipEvent_t evE = nullptr;
+  bool pjoin = false;
   long long pkey = -1;
   // thin SVD / Levenberg-Marquardt workspace (first use): W (n_max x r_max), residuals,
   // parameters, V (r_max^2), column norms and dots, convergence flag, column order
@@ -387,6 +391,8 @@ void ww_destroy(ww_ctx* c) {
     for (int q = 0; q < 4; ++q)
       if (c->pgx[s][q]) (void)hipGraphExecDestroy(c->pgx[s][q]);
   if (c->pgend) (void)hipGraphExecDestroy(c->pgend);
+  if (c->pgendc) (void)hipGraphExecDestroy(c->pgendc);
+  if (c->evE) (void)hipEventDestroy(c->evE);
   if (c->stamps) (void)hipFree(c->stamps);
   if (c->ckpt) (void)hipFree(c->ckpt);
   if (c->seg) (void)hipFree(c->seg);
@@ -465,7 +471,7 @@ static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
   for (int k = 0; k + 1 < nb; ++k) {
     const int nt = nb - k - 1;
     const int nblk = nt * nt + 2 * nt * (k + 1);
-    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk), dim3(WW_NT), 4 * TILE_DBL * es, c->stream, b, k);
+    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, b, k);
     LAUNCHCHK();
   }
   if (nb > 1) {
@@ -857,6 +863,7 @@ static int ensure_pipe(ww_ctx* c) {
     if (!c->evA[i]) HIPCHK(hipEventCreateWithFlags(&c->evA[i], hipEventDisableTiming));
     if (!c->evL[i]) HIPCHK(hipEventCreateWithFlags(&c->evL[i], hipEventDisableTiming));
   }
+  if (!c->evE) HIPCHK(hipEventCreateWithFlags(&c->evE, hipEventDisableTiming));
   const size_t np = c->np_max, nn = np * np;
   const size_t nbm = np / WW_TB;
   while (c->ring_n < c->nst) {
@@ -913,6 +920,12 @@ static int pipe_prologue(ww_ctx* c) {
       HIPCHK(hipMemcpyAsync(b.Zr, a.Zr, nn * 8, hipMemcpyDeviceToDevice, c->stream));
     }
   }
+  // the first step of the per-branch graphs waits, at stage s, for the column chain of
+  // stage s and the LU of stage s - lag of the step before: here, for this prologue
+  for (int q = 0; q < nst; ++q) {
+    HIPCHK(hipEventRecord(c->evC[q], c->stream));
+    HIPCHK(hipEventRecord(c->evL[q], c->stream));
+  }
   return 0;
 }
 
@@ -948,21 +961,24 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
   return enqueue_col_chain(c, s, pipe_set(c, s, true));
 }
 
-static int enqueue_pipe_end(ww_ctx* c) {
-  hipLaunchKernelGGL(k_step_end, dim3(c->M + 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y, c->K, kstride(c),
-                     c->nst, c->coef, c->tw, c->sig, c->N, 0, c->status);
+// the step end of the base column (cols false; it counts the step) or of the Jacobian
+// columns 1..M (cols true)
+static int enqueue_pipe_end(ww_ctx* c, bool cols) {
+  hipLaunchKernelGGL(k_step_end, dim3(cols ? c->M : 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y, c->K,
+                     kstride(c), c->nst, c->coef, c->tw, c->sig, c->N, cols ? 1 : 0, cols ? nullptr : c->status);
   LAUNCHCHK();
   return 0;
 }
 
-// capture one part (part < 0: the step end) on the capture stream, alone
+// capture one part on the capture stream, alone (part -1: the step end of the base
+// column, -2: that of the Jacobian columns)
 static int capture_part(ww_ctx* c, int s, int part, hipGraphExec_t* out) {
   hipStream_t user = c->stream;
   const hipError_t eb = hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal);
   if (eb != hipSuccess) return fail(WW_EHIP, std::string("hipStreamBeginCapture: ") + hipGetErrorString(eb));
   c->stream = c->cap_stream;
   c->prof_stage = part < 0 ? -1 : s;
-  const int rc = part < 0 ? enqueue_pipe_end(c) : enqueue_pipe_part(c, s, part);
+  const int rc = part < 0 ? enqueue_pipe_end(c, part == -2) : enqueue_pipe_part(c, s, part);
   c->prof_stage = -1;
   hipGraph_t g = nullptr;
   const hipError_t e = hipStreamEndCapture(c->cap_stream, &g);
@@ -983,7 +999,7 @@ static long long pipe_key(const ww_ctx* c) {
 }
 
 static int ensure_pipe_graphs(ww_ctx* c) {
-  if (c->pkey == pipe_key(c) && c->pgend) return 0;
+  if (c->pkey == pipe_key(c) && c->pgend && c->pgendc) return 0;
   HIPCHK(hipDeviceSynchronize());   // no replay of the old graphs may still run
   for (int s = 0; s < 16; ++s)
     for (int q = 0; q < 4; ++q)
@@ -991,34 +1007,43 @@ static int ensure_pipe_graphs(ww_ctx* c) {
         HIPCHK(hipGraphExecDestroy(c->pgx[s][q]));
         c->pgx[s][q] = nullptr;
       }
-  if (c->pgend) {
-    HIPCHK(hipGraphExecDestroy(c->pgend));
-    c->pgend = nullptr;
-  }
+  for (hipGraphExec_t* g : {&c->pgend, &c->pgendc})
+    if (*g) {
+      HIPCHK(hipGraphExecDestroy(*g));
+      *g = nullptr;
+    }
   c->pkey = -1;
   int rc;
   for (int s = 0; s < c->nst; ++s)
     for (int q = 0; q < 4; ++q)
       if ((rc = capture_part(c, s, q, &c->pgx[s][q]))) return rc;
   if ((rc = capture_part(c, 0, -1, &c->pgend))) return rc;
+  if ((rc = capture_part(c, 0, -2, &c->pgendc))) return rc;
   c->pkey = pipe_key(c);
   return 0;
 }
 
 // One step of the lagged-factor march from the per-branch graphs: each branch on its
-// own stream (so on its own queue), the dependencies of the step as events.  The end of
-// the previous step waited for every column chain and, through them, every LU.
+// own stream (so on its own queue), the dependencies as events.  The step ends in two
+// halves: the base column's on the main stream, right after the last base chain, and
+// the Jacobian columns' on the column stream, so that the next step's base chain does
+// not wait for the last LU and column chain of this one.  What crosses the step
+// boundary is explicit: stage s rewrites its factor set only after the column chain of
+// stage s of the step before has read it, and the base solve of stage s < lag reads
+// the factors of the LU of stage s - lag + nst of the step before.  The main stream
+// joins the column stream (pipe_join) before the march's outputs are read.
 static int pipe_step(ww_ctx* c) {
   const int nst = c->nst, L = c->lag;
   hipStream_t s0 = c->stream;
   for (int s = 0; s < nst; ++s) {
     hipStream_t ls = c->lus[s % L];
+    HIPCHK(hipStreamWaitEvent(s0, c->evC[s], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_PREP], s0));
     HIPCHK(hipEventRecord(c->evA[s], s0));
     HIPCHK(hipStreamWaitEvent(ls, c->evA[s], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_LU], ls));
     HIPCHK(hipEventRecord(c->evL[s], ls));
-    if (s >= L) HIPCHK(hipStreamWaitEvent(s0, c->evL[s - L], 0));
+    HIPCHK(hipStreamWaitEvent(s0, c->evL[(s - L + nst) % nst], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_BASE], s0));
     HIPCHK(hipEventRecord(c->evB[s], s0));
     HIPCHK(hipStreamWaitEvent(c->side, c->evB[s], 0));
@@ -1026,8 +1051,19 @@ static int pipe_step(ww_ctx* c) {
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_COL], c->side));
     HIPCHK(hipEventRecord(c->evC[s], c->side));
   }
-  HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
   HIPCHK(hipGraphLaunch(c->pgend, s0));
+  HIPCHK(hipGraphLaunch(c->pgendc, c->side));
+  HIPCHK(hipEventRecord(c->evE, c->side));
+  c->pjoin = true;
+  return 0;
+}
+
+// the main stream waits for the column stream's last step end (and through it for
+// every LU and column chain of the march)
+static int pipe_join(ww_ctx* c) {
+  if (!c->pjoin) return 0;
+  HIPCHK(hipStreamWaitEvent(c->stream, c->evE, 0));
+  c->pjoin = false;
   return 0;
 }
 
@@ -1340,6 +1376,7 @@ static bool graphed(const ww_ctx* c) { return c->use_graph && !pivoted(c); }
 // shoot_eval in three parts so that shoot_eval_batch can interleave instances:
 // prepare (coefficients, initial state, step graph), one step, finish (outputs).
 static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, bool cols, bool two_streams) {
+  if (int rj = pipe_join(c)) return rj;   // a march that ended early (an error) left its streams unjoined
   if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_eval before shoot_setup");
   if (c->nst < 1) return fail(WW_EINVAL, "no tableau set");
   if (nsteps < 1 || !std::isfinite(T)) return fail(WW_EINVAL, "nsteps >= 1 and finite T required");
@@ -1389,6 +1426,7 @@ static int shoot_one_step(ww_ctx* c, bool cols, bool two_streams) {
 static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT, double* fhost) {
   const int N = c->N, M = c->M;
   int rc;
+  if ((rc = pipe_join(c))) return rc;
   {
     const size_t n = (size_t)2 * N * (cols ? M + 1 : 1);
     hipLaunchKernelGGL(k_check_finite, dim3(64), dim3(256), 0, c->stream, c->y, n, c->status);
@@ -1449,6 +1487,7 @@ static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, doub
       // lagged factors that do not converge show in the first step: stop there (the
       // caller redoes the march in its fallback mode or reports the status)
       int peek = 0;
+      if ((rc = pipe_join(c))) return rc;
       HIPCHK(hipStreamSynchronize(c->stream));
       HIPCHK(hipMemcpy(&peek, c->status, sizeof(int), hipMemcpyDeviceToHost));
       if (peek) return read_status(c, st, where);

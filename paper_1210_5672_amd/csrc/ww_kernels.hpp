@@ -540,12 +540,13 @@ __device__ inline double lds_gj_inverse(T* Ts, T* pub) {
 // workgroup barrier), replaces its other blocks by D B_PJ (D = B_PP^-1) and publishes
 // the band; after one barrier every other wave updates B_wJ <- B_wJ - B_wP (D B_PJ) and
 // B_wP <- -B_wP D, all 16 x 16 x 16 MFMA products.  The pivots are those of the scalar
-// elimination.  `scr`: LDS scratch of GJ_SCR elements.  Returns the smallest |pivot|.
+// elimination.  `scr`: LDS scratch of GJ_SCR elements; it may start at Ts (each wave
+// keeps its rows in registers in between).  Returns the smallest |pivot|.
 // -------------------------------------------------------------------------------------
 #define GJ_SLD 65
 #define GJ_BAND (16 * GJ_SLD)
 #define GJ_SCR (6 * GJ_BAND + 8)
-static_assert(GJ_SCR <= 3 * TILE_DBL, "the inverse scratch must fit in three free LDS tiles");
+static_assert(GJ_SCR <= 2 * TILE_DBL, "the inverse scratch must fit in two LDS tiles");
 
 __device__ __forceinline__ double lane_read(double x, int lane) {
   const unsigned long long u = (unsigned long long)__double_as_longlong(x);
@@ -640,6 +641,7 @@ __device__ __forceinline__ double blk_gj_inverse(T* Ts, T* scr) {
   for (int J = 0; J < 4; ++J)
 #pragma unroll
     for (int i = 0; i < 4; ++i) v[J][i] = Ts[(16 * w + Mfma<T>::row(i, rq)) * TLD + 16 * J + cl];
+  __syncthreads();   // the tile is in registers: scr may overlay Ts
   T minpiv = T(1e30);
 #pragma unroll 1
   for (int P = 0; P < 4; ++P) {
@@ -699,6 +701,7 @@ __device__ __forceinline__ double blk_gj_inverse(T* Ts, T* scr) {
     }
   }
   if (lane == 0) red[w] = minpiv;
+  __syncthreads();   // every wave is done with the bands before Ts is rewritten
 #pragma unroll
   for (int J = 0; J < 4; ++J)
 #pragma unroll
@@ -776,39 +779,56 @@ __global__ __launch_bounds__(WW_NT) void k_blu_init(BluBufs<T> b) {
   }
 }
 
-// Load up to four 64 x 64 column-major tiles into LDS with all loads in flight at once
-// (null sources are skipped).
+// One 64 x 64 column-major tile into registers (thread t holds entries t + 256 m, m =
+// 0..15, of the column-major order), then into an LDS tile; the same thread owns the
+// same entries in tile_put, tile_store and tile_store_sum, so a tile kept in registers
+// can be combined with an LDS tile without a barrier.
 template <typename T>
-__device__ inline void tiles_load4(T* const dst[4], const T* const src[4], const int ld[4]) {
-  T v[4][16];
+__device__ inline void tile_fetch(T (&v)[16], const T* __restrict__ G, size_t ld) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (src[q]) {
+  for (int m = 0; m < 16; ++m) {
+    const int idx = threadIdx.x + WW_NT * m;
+    v[m] = G[(size_t)(idx >> 6) * ld + (idx & 63)];
+  }
+}
+template <typename T>
+__device__ inline void tile_put(T* Ts, const T (&v)[16]) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int idx = threadIdx.x + WW_NT * m;
-        v[q][m] = src[q][(size_t)(idx >> 6) * ld[q] + (idx & 63)];
-      }
-    }
+  for (int m = 0; m < 16; ++m) {
+    const int idx = threadIdx.x + WW_NT * m;
+    Ts[(idx & 63) * TLD + (idx >> 6)] = v[m];
+  }
+}
+// Ts += v (each thread its own entries)
+template <typename T>
+__device__ inline void tile_add_own(T* Ts, const T (&v)[16]) {
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    if (src[q]) {
+  for (int m = 0; m < 16; ++m) {
+    const int idx = threadIdx.x + WW_NT * m;
+    Ts[(idx & 63) * TLD + (idx >> 6)] += v[m];
+  }
+}
+// G = Ts + v
+template <typename T>
+__device__ inline void tile_store_sum(const T* Ts, const T (&v)[16], T* __restrict__ G, size_t ld) {
 #pragma unroll
-      for (int m = 0; m < 16; ++m) {
-        const int idx = threadIdx.x + WW_NT * m;
-        dst[q][(idx & 63) * TLD + (idx >> 6)] = v[q][m];
-      }
-    }
+  for (int m = 0; m < 16; ++m) {
+    const int idx = threadIdx.x + WW_NT * m;
+    G[(size_t)(idx >> 6) * ld + (idx & 63)] = Ts[(idx & 63) * TLD + (idx >> 6)] + v[m];
+  }
 }
 
+// Two LDS tiles per workgroup (so that two workgroups share a CU): S0 holds the left
+// factor and then the left product, S1 holds D_k and then the right factor.  The right
+// factor and the destination tile are fetched into registers with the other two tiles
+// at the start and enter LDS (or the final sum) when their slot is free.  The result
+// is C + (-(L R)), the same rounding as C - L R accumulated into C.
 template <typename T>
 __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
   extern __shared__ double sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
-  T* Ls = sm;                  // left factor source, then the left factor
-  T* Ds = sm + TILE_DBL;       // D_k
-  T* Rs = sm + 2 * TILE_DBL;   // right factor
-  T* Cs = sm + 3 * TILE_DBL;   // destination tile
+  T* S0 = sm;
+  T* S1 = sm + TILE_DBL;
   const int Np = b.Np, nb = Np / WW_TB;
   const int nt = nb - k - 1;
   const int n1 = nt * nt, n2 = nt * (k + 1);
@@ -824,56 +844,69 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
   const T* Dk = b.Dinv + (size_t)k * 4096;
   const bool ldiag = (role == 3 && i == k);           // left factor is D_k itself
   const bool xfirst = (role == 2 && j == k);          // X_ik = -A_ik D_k, no right factor
-  const bool vfirst = (role == 3 && i == k);          // V_kj = -D_k A_kj, no accumulation
+  const bool vfirst = ldiag;                          // V_kj = -D_k A_kj, no accumulation
+  const bool diag = (role == 1 && i == k + 1 && j == k + 1);   // inverts its tile: D_{k+1}
+  const bool rmcopy = (role == 2 && b.Xr && i == k + 1);       // row of X final: row-major copy
   T* dst = role == 1 ? tileptr(b.A, Np, i, j) : role == 2 ? tileptr(b.X, Np, i, j) : tileptr(b.V, Np, i, j);
-  {
-    T* const d4[4] = {Ls, Ds, Rs, Cs};
-    const T* const s4[4] = {
-        ldiag ? Dk : (role == 3 ? tileptr(b.V, Np, i, k) : tileptr(b.A, Np, i, k)),
-        ldiag ? nullptr : Dk,
-        xfirst ? nullptr : (role == 2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j)),
-        (xfirst || vfirst) ? nullptr : dst};
-    const int l4[4] = {ldiag ? 64 : Np, 64, Np, Np};
-    tiles_load4<T>(d4, s4, l4);
-  }
+  T vl[16], vd[16], vr[16], vc[16];
+  tile_fetch<T>(vl, ldiag ? Dk : (role == 3 ? tileptr(b.V, Np, i, k) : tileptr(b.A, Np, i, k)), ldiag ? 64 : Np);
+  if (!ldiag) tile_fetch<T>(vd, Dk, 64);
+  if (!xfirst) tile_fetch<T>(vr, role == 2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j), Np);
+  if (!xfirst && !vfirst) tile_fetch<T>(vc, dst, Np);
+  tile_put<T>(S0, vl);
+  if (!ldiag) tile_put<T>(S1, vd);
   __syncthreads();
   if (ldiag && j == k + 1) {
     // Z_kk = D_k (kept off the workgroup that inverted it, which is on the critical path)
-    tile_store<T, T>(Ls, tileptr(b.Z, Np, k, k), Np);
-    if (b.Zr) tile_store_rm<T>(Ls, rmptr(b.Zr, Np, k, k), Np);
+    tile_store<T, T>(S0, tileptr(b.Z, Np, k, k), Np);
+    if (b.Zr) tile_store_rm<T>(S0, rmptr(b.Zr, Np, k, k), Np);
   }
   Acc64<T> acc;
   if (!ldiag) {
     acc_zero(acc);
-    mfma_tile(Ls, Ds, acc);
+    mfma_tile(S0, S1, acc);
     __syncthreads();
-    acc_to_lds(acc, Ls, 0, T(1));   // Ls = A_ik D_k (roles 1, 2) or V_ik D_k = Z_ik (role 3)
-    __syncthreads();
-    if (role == 3 && j == k + 1) {
-      tile_store<T, T>(Ls, tileptr(b.Z, Np, i, k), Np);
-      if (b.Zr) tile_store_rm<T>(Ls, rmptr(b.Zr, Np, i, k), Np);
-    }
+    acc_to_lds(acc, S0, 0, T(1));   // S0 = A_ik D_k (roles 1, 2) or V_ik D_k = Z_ik (role 3)
+  }
+  if (!xfirst) tile_put<T>(S1, vr);
+  __syncthreads();
+  if (!ldiag && role == 3 && j == k + 1) {
+    tile_store<T, T>(S0, tileptr(b.Z, Np, i, k), Np);
+    if (b.Zr) tile_store_rm<T>(S0, rmptr(b.Zr, Np, i, k), Np);
   }
   if (xfirst) {
-    tile_store<T, T>(Ls, tileptr(b.X, Np, i, k), Np, 64, T(-1));
-    if (b.Xr && i == k + 1) tile_store_rm<T>(Ls, rmptr(b.Xr, Np, i, k), Np, T(-1));   // final
+    tile_store<T, T>(S0, tileptr(b.X, Np, i, k), Np, 64, T(-1));
+    if (b.Xr && i == k + 1) tile_store_rm<T>(S0, rmptr(b.Xr, Np, i, k), Np, T(-1));   // final
     return;
   }
   acc_zero(acc);
-  mfma_tile(Ls, Rs, acc);
+  mfma_tile(S0, S1, acc);
   __syncthreads();
-  if (vfirst) acc_to_lds(acc, Cs, 0, T(-1));
-  else acc_to_lds(acc, Cs, 1, T(-1));
-  __syncthreads();
-  if (role == 1 && i == k + 1 && j == k + 1) {
-    // Schur complement block of the next step: invert it (D_{k+1} = Z_{k+1,k+1})
-    const double mp = blk_gj_inverse<T>(Cs, sm);   // Ls, Ds, Rs are free here
-    if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
-    store_dinv<T>(Cs, b.Dinv + (size_t)(k + 1) * 4096);   // Z_{k+1,k+1} is stored one step later
+  acc_to_lds(acc, S0, 0, T(-1));   // S0 = -L R
+  if (vfirst) {
+    __syncthreads();
+    tile_store<T, T>(S0, dst, Np);
     return;
   }
-  tile_store<T, T>(Cs, dst, Np);
-  if (role == 2 && b.Xr && i == k + 1) tile_store_rm<T>(Cs, rmptr(b.Xr, Np, i, j), Np);   // final
+  if (diag || rmcopy) {
+    // the updated tile is needed in LDS: S0 += C (own entries), then one barrier
+    __syncthreads();
+    tile_add_own<T>(S0, vc);
+    __syncthreads();
+    if (diag) {
+      // Schur complement block of the next step: invert it (D_{k+1} = Z_{k+1,k+1});
+      // the inverse's scratch overlays both slots (S1 is free here)
+      const double mp = blk_gj_inverse<T>(S0, sm);
+      if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
+      store_dinv<T>(S0, b.Dinv + (size_t)(k + 1) * 4096);   // Z_{k+1,k+1} is stored one step later
+      return;
+    }
+    tile_store<T, T>(S0, dst, Np);
+    tile_store_rm<T>(S0, rmptr(b.Xr, Np, i, j), Np);   // final
+    return;
+  }
+  __syncthreads();
+  tile_store_sum<T>(S0, vc, dst, Np);
 }
 
 // last column block of Z: Z_i,nb-1 = V_i,nb-1 D_nb-1 (i < nb - 1)
@@ -1380,7 +1413,7 @@ __global__ __launch_bounds__(WW_NT) void k_step_end(double* __restrict__ y, cons
     yc[t] = Z[t].x;
     yc[N + t] = Z[t].y;
   }
-  if (status && blockIdx.x == 0 && tid == 0) status[1] += 1;   // steps completed
+  if (status && c == 0 && tid == 0) status[1] += 1;   // steps completed (with the base column)
 }
 
 // status word of a call: bits, step counter, first failing 16 step + stage
