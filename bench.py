@@ -28,8 +28,8 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md, calibrated with a
 # plain 256 MiB copy.  Valid only for the kernel source it was measured on: reported as
 # null once the kernels header changes.
-LU_TRAFFIC_BYTES = 266.9e6
-LU_TRAFFIC_SOURCE_SHA256 = "f9c501e9e60f05c0eb88029565cf0f2b3c86e0d6d96135f657260eb6b3426ad3"
+LU_TRAFFIC_BYTES = 266.5e6
+LU_TRAFFIC_SOURCE_SHA256 = "7e7723d28c5d97cb6cd41e0522bdcbd27cb1b88e57fe816e4a5729f4ed255872"
 
 
 def lu_traffic():

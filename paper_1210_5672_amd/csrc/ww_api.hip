@@ -132,6 +132,7 @@ struct ww_ctx {
   // the factors of stage s - lag (refined against its own matrix) while the LU of
   // stage s runs on one of `lag` streams; the column chain of stage s waits for it
   int lag = 5;   // environment WW_PIPE_LAG, 0..PIPE_MAXLAG (0: every solve uses its own factors)
+  int nlus = 2;  // LU streams (stage s on stream s mod nlus), at most lag; environment WW_LU_STREAMS
   int ring_n = 0;          // factor sets allocated (one per stage)
   RingSet ring[16];
   hipStream_t lus[PIPE_MAXLAG] = {};
@@ -333,8 +334,6 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->status, 64);
 #undef AL
   CCHK(hipMemset(c->status, 0, 64));
-  CCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
-  CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   for (int i = 0; i < 16; ++i) {
     CCHK(hipEventCreateWithFlags(&c->evB[i], hipEventDisableTiming));
     CCHK(hipEventCreateWithFlags(&c->evC[i], hipEventDisableTiming));
@@ -353,6 +352,17 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     }
     const char* pl = std::getenv("WW_PIPE_LAG");
     if (pl) c->lag = std::max(0, std::min(PIPE_MAXLAG, std::atoi(pl)));
+    const char* ns = std::getenv("WW_LU_STREAMS");
+    if (ns) c->nlus = std::max(1, std::min(PIPE_MAXLAG, std::atoi(ns)));
+    // streams: the working ones first, the capture stream (which never executes) last.
+    // HIP shares its few hardware queues among a process's streams, each new stream
+    // taking the least-used queue: created in this order, the caller's stream, the
+    // column stream and the two LU streams of a march each get a queue of their own
+    // (with four), and no LU waits in the base chain's in-order queue.
+    CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    for (int i = 0; i < (c->lag > 0 ? std::min(c->nlus, c->lag) : 0); ++i)
+      CCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
+    CCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const char* pg = std::getenv("WW_PIVOT_GUARD");
     if (pg) {
       const double v = std::atof(pg);
@@ -855,9 +865,12 @@ static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
   return c->lag > 0 && cols && two_streams && c->fb == 0 && c->M > 0 && c->nst > c->lag;
 }
 
+static int lu_count(const ww_ctx* c) { return std::min(c->nlus, c->lag); }
+static hipStream_t lu_stream(const ww_ctx* c, int s) { return c->lus[s % lu_count(c)]; }
+
 static int ensure_pipe(ww_ctx* c) {
   int rc;
-  for (int i = 0; i < c->lag; ++i)
+  for (int i = 0; i < lu_count(c); ++i)
     if (!c->lus[i]) HIPCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
   for (int i = 0; i < 16; ++i) {
     if (!c->evA[i]) HIPCHK(hipEventCreateWithFlags(&c->evA[i], hipEventDisableTiming));
@@ -1036,7 +1049,7 @@ static int pipe_step(ww_ctx* c) {
   const int nst = c->nst, L = c->lag;
   hipStream_t s0 = c->stream;
   for (int s = 0; s < nst; ++s) {
-    hipStream_t ls = c->lus[s % L];
+    hipStream_t ls = lu_stream(c, s);
     HIPCHK(hipStreamWaitEvent(s0, c->evC[s], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_PREP], s0));
     HIPCHK(hipEventRecord(c->evA[s], s0));
@@ -1075,7 +1088,7 @@ static int enqueue_step_pipe(ww_ctx* c) {
     c->prof_stage = s;
     const Fac F = pipe_set(c, s, false);
     const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
-    hipStream_t ls = c->lus[s % L];
+    hipStream_t ls = lu_stream(c, s);
     if ((rc = prof_mark(c, 1, 0))) break;
     hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->y, c->K, c->Ys, c->coef, s,
                        kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
