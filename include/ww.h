@@ -157,11 +157,15 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  * path) solves with the factors of stage s - L and refines the solution with
  * the FP64 residual of its own matrix (the same number of sweeps and the same
  * convergence test as WW_MIXED), while the LU of its own matrix runs concurrently on one
- * of L streams; the column chain of stage s uses that stage's own factors.  Each branch
- * of a stage (spectral prep and assembly; the LU; the lagged base solve to the base
- * right-hand side; the column chain) is a graph of its own, replayed on its own stream
- * with the dependencies as events.  A failed test (checked after the first step, and at
- * the end) redoes the march with every stage's own factors (WW_FB_DIRECT).
+ * of the context's LU streams (stage s on stream s mod K, K = 2; environment
+ * WW_LU_STREAMS, 1..L); the column chain of stage s uses that stage's own factors.  Each
+ * branch of a stage (spectral prep and assembly; the LU; the lagged base solve to the
+ * base right-hand side; the column chain) is a graph of its own, replayed on its own
+ * stream with the dependencies as events; the step end of the base column and that of
+ * the Jacobian columns run on the caller's and the column stream, and the caller's
+ * stream joins the others before the outputs.  The results do not depend on K.  A
+ * failed test (checked after the first step, and at the end) redoes the march with
+ * every stage's own factors (WW_FB_DIRECT).
  * Synchronises to check the status flags.  A pivot below the guard anywhere in the
  * march redoes it with partial pivoting; a failed refinement test (WW_MIXED) redoes it
  * with FP64 factors (see ww_fallbacks).

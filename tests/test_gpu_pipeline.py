@@ -1,8 +1,9 @@
-"""The lagged-factor march (opt-in, WW_PIPE_LAG) in its per-branch-graph form: every
-stage's base chain solves with the factors of the stage `lag` stages earlier, refined
-against its own matrix, while its own LU runs on one of `lag` streams; each branch of a
-stage is a graph of its own, replayed on its own stream.  Held against the oracle and
-against the march that solves every stage with its own factors."""
+"""The lagged-factor march (the default for one instance; WW_PIPE_LAG sets the lag) in
+its per-branch-graph form: every stage's base chain solves with the factors of the stage
+`lag` stages earlier, refined against its own matrix, while its own LU runs on one of the
+LU streams (WW_LU_STREAMS); each branch of a stage is a graph of its own, replayed on its
+own stream.  Held against the oracle, against the march that solves every stage with its
+own factors, and against itself under other stream layouts."""
 import math
 
 import numpy as np
@@ -100,3 +101,42 @@ def test_phase_profile_in_the_lagged_march():
     print("phases ms", ph)
     assert all(p > 0 for p in ph)
     assert ctx.fallbacks() == 0
+
+
+def test_lagged_march_is_bitwise_independent_of_the_lu_streams():
+    """The lagged march's arithmetic does not depend on how its branches are scheduled:
+    with 1, 2 or 5 LU streams (WW_LU_STREAMS), and on a second evaluation by the same
+    context, r and J are bitwise the same.  N = 256 (four 64-blocks) and 20 steps, so
+    that the LUs of different stages and the split step end really overlap; a missing
+    dependency between the streams would show as a difference."""
+    ww, torch = _ww()
+    import os
+    w2 = W.c2()
+    N, M, nsteps = w2.N, 16, 20
+    w = W.Workload("c2_short", N, w2.h, w2.tau, w2.g, M, w2.T * nsteps / w2.nsteps, nsteps, w2.params[:M],
+                   W.cosine_basis(N, M), w2.q_fixed)
+    outs = []
+    for k in (1, 2, 5):
+        print(f"lagged march N=256 M=16 lag=5 LU streams={k}", flush=True)
+        old = {v: os.environ.get(v) for v in ("WW_PIPE_LAG", "WW_LU_STREAMS")}
+        os.environ["WW_PIPE_LAG"] = "5"
+        os.environ["WW_LU_STREAMS"] = str(k)
+        try:
+            ctx = ww.Context(n_max=N, r_max=M + 1)
+        finally:
+            for v, x in old.items():
+                if x is None:
+                    os.environ.pop(v, None)
+                else:
+                    os.environ[v] = x
+        ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        for rep in range(2):
+            out = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+            assert ctx.fallbacks() == 0
+            outs.append((out["r"].cpu().numpy(), out["J"].cpu().numpy()))
+        del ctx
+    r0, J0 = outs[0]
+    assert np.isfinite(J0).all() and np.abs(J0).max() > 0
+    for r, J in outs[1:]:
+        assert np.array_equal(r, r0)
+        assert np.array_equal(J, J0)
