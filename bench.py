@@ -224,7 +224,7 @@ def run_lm(with_oracle: bool):
         dt = time.perf_counter() - t0
         solves[N] = {"N": N, "nsteps": nsteps, "unknowns": nmodes, "ms": 1e3 * dt, "f": res["f"],
                      "evals_r": res["evals_r"], "evals_J": res["evals_J"], "reason": res["reason"],
-                     "T": float(res["c"][0])}
+                     "T": float(res["c"][0]), "last_fallbacks": ctx.fallbacks()}
         print(f"# lm N={N} done", file=sys.stderr, flush=True)
     out["standing_wave_n256"] = solves[256]
     out["standing_wave_n64"] = solves[64]

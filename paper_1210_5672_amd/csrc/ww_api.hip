@@ -120,6 +120,9 @@ struct ww_ctx {
   // fallbacks: fb is the mode the factor sets are built in (WW_FB_* bits), fb_last what
   // the results of the last call came from; guard is the unpivoted LU's pivot bound
   unsigned fb = 0, fb_last = 0;
+  // a march on lagged factors failed its refinement test: the context's later marches
+  // (until the next shoot_setup) start on each stage's own factors (WW_FB_DIRECT)
+  bool lag_off = false;
   double guard = 1e-8;
   // partial-pivoting buffers, allocated on the first fallback: row order, elimination
   // workspace (Np x Np), gathered right-hand sides (Np x r_max); the adjoint keeps one
@@ -145,6 +148,7 @@ struct ww_ctx {
   hipGraphExec_t pgend = nullptr, pgendc = nullptr;
   hipEvent_t evE = nullptr;
   bool pjoin = false;
+  bool pcols = true;   // the current lagged march has Jacobian columns (column chains)
   long long pkey = -1;
   // thin SVD / Levenberg-Marquardt workspace (first use): W (n_max x r_max), residuals,
   // parameters, V (r_max^2), column norms and dots, convergence flag, column order
@@ -862,7 +866,8 @@ static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
 // LU of its own matrix runs concurrently; the column chain, which lags behind anyway,
 // uses the exact factors of its stage.
 static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
-  return c->lag > 0 && cols && two_streams && c->fb == 0 && c->M > 0 && c->nst > c->lag;
+  (void)cols;   // with or without Jacobian columns (c->pcols)
+  return c->lag > 0 && two_streams && c->fb == 0 && c->nst > c->lag && !c->gm_active;
 }
 
 static int lu_count(const ww_ctx* c) { return std::min(c->nlus, c->lag); }
@@ -1012,7 +1017,14 @@ static long long pipe_key(const ww_ctx* c) {
 }
 
 static int ensure_pipe_graphs(ww_ctx* c) {
-  if (c->pkey == pipe_key(c) && c->pgend && c->pgendc) return 0;
+  int rc;
+  if (c->pkey == pipe_key(c) && c->pgend) {
+    if (!c->pcols || c->pgendc) return 0;
+    // the column branches (first march with columns on these graphs)
+    for (int s = 0; s < c->nst; ++s)
+      if ((rc = capture_part(c, s, PP_COL, &c->pgx[s][PP_COL]))) return rc;
+    return capture_part(c, 0, -2, &c->pgendc);
+  }
   HIPCHK(hipDeviceSynchronize());   // no replay of the old graphs may still run
   for (int s = 0; s < 16; ++s)
     for (int q = 0; q < 4; ++q)
@@ -1026,12 +1038,11 @@ static int ensure_pipe_graphs(ww_ctx* c) {
       *g = nullptr;
     }
   c->pkey = -1;
-  int rc;
   for (int s = 0; s < c->nst; ++s)
     for (int q = 0; q < 4; ++q)
-      if ((rc = capture_part(c, s, q, &c->pgx[s][q]))) return rc;
+      if ((q != PP_COL || c->pcols) && (rc = capture_part(c, s, q, &c->pgx[s][q]))) return rc;
   if ((rc = capture_part(c, 0, -1, &c->pgend))) return rc;
-  if ((rc = capture_part(c, 0, -2, &c->pgendc))) return rc;
+  if (c->pcols && (rc = capture_part(c, 0, -2, &c->pgendc))) return rc;
   c->pkey = pipe_key(c);
   return 0;
 }
@@ -1041,16 +1052,17 @@ static int ensure_pipe_graphs(ww_ctx* c) {
 // halves: the base column's on the main stream, right after the last base chain, and
 // the Jacobian columns' on the column stream, so that the next step's base chain does
 // not wait for the last LU and column chain of this one.  What crosses the step
-// boundary is explicit: stage s rewrites its factor set only after the column chain of
-// stage s of the step before has read it, and the base solve of stage s < lag reads
-// the factors of the LU of stage s - lag + nst of the step before.  The main stream
-// joins the column stream (pipe_join) before the march's outputs are read.
+// boundary is explicit: stage s rewrites its factor set only after the step before has
+// finished with it (its column chain of stage s; without columns, its LU of stage s),
+// and the base solve of stage s < lag reads the factors of the LU of stage
+// s - lag + nst of the step before.  The main stream joins the other streams
+// (pipe_join) before the march's outputs are read.
 static int pipe_step(ww_ctx* c) {
   const int nst = c->nst, L = c->lag;
   hipStream_t s0 = c->stream;
   for (int s = 0; s < nst; ++s) {
     hipStream_t ls = lu_stream(c, s);
-    HIPCHK(hipStreamWaitEvent(s0, c->evC[s], 0));
+    HIPCHK(hipStreamWaitEvent(s0, c->pcols ? c->evC[s] : c->evL[s], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_PREP], s0));
     HIPCHK(hipEventRecord(c->evA[s], s0));
     HIPCHK(hipStreamWaitEvent(ls, c->evA[s], 0));
@@ -1058,6 +1070,7 @@ static int pipe_step(ww_ctx* c) {
     HIPCHK(hipEventRecord(c->evL[s], ls));
     HIPCHK(hipStreamWaitEvent(s0, c->evL[(s - L + nst) % nst], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_BASE], s0));
+    if (!c->pcols) continue;
     HIPCHK(hipEventRecord(c->evB[s], s0));
     HIPCHK(hipStreamWaitEvent(c->side, c->evB[s], 0));
     HIPCHK(hipStreamWaitEvent(c->side, c->evL[s], 0));
@@ -1065,17 +1078,24 @@ static int pipe_step(ww_ctx* c) {
     HIPCHK(hipEventRecord(c->evC[s], c->side));
   }
   HIPCHK(hipGraphLaunch(c->pgend, s0));
-  HIPCHK(hipGraphLaunch(c->pgendc, c->side));
-  HIPCHK(hipEventRecord(c->evE, c->side));
+  if (c->pcols) {
+    HIPCHK(hipGraphLaunch(c->pgendc, c->side));
+    HIPCHK(hipEventRecord(c->evE, c->side));
+  }
   c->pjoin = true;
   return 0;
 }
 
 // the main stream waits for the column stream's last step end (and through it for
-// every LU and column chain of the march)
+// every LU and column chain of the march); without columns, for the LUs of the last
+// step (each LU stream's last LU ends after its earlier ones)
 static int pipe_join(ww_ctx* c) {
   if (!c->pjoin) return 0;
-  HIPCHK(hipStreamWaitEvent(c->stream, c->evE, 0));
+  if (c->pcols) {
+    HIPCHK(hipStreamWaitEvent(c->stream, c->evE, 0));
+  } else {
+    for (int s = 0; s < c->nst; ++s) HIPCHK(hipStreamWaitEvent(c->stream, c->evL[s], 0));
+  }
   c->pjoin = false;
   return 0;
 }
@@ -1130,6 +1150,7 @@ static int enqueue_step_pipe(ww_ctx* c) {
       break;
     }
     if ((rc = prof_mark(c, 1, 1))) break;
+    if (!c->pcols) continue;
     // the column chain with this stage's own factors
     if (hipEventRecord(c->evB[s], s0) != hipSuccess || hipStreamWaitEvent(c->side, c->evB[s], 0) != hipSuccess ||
         hipStreamWaitEvent(c->side, c->evL[s], 0) != hipSuccess) {
@@ -1144,10 +1165,15 @@ static int enqueue_step_pipe(ww_ctx* c) {
   }
   c->prof_stage = -1;
   if (rc) return rc;
-  // the column chains waited for every LU: one wait joins all streams
-  HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
-  hipLaunchKernelGGL(k_step_end, dim3(c->M + 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), s0, c->y, c->K, kstride(c), nst,
-                     c->coef, c->tw, c->sig, c->N, 0, c->status);
+  // the column chains waited for every LU: one wait joins all streams (without columns,
+  // one wait per LU)
+  if (c->pcols) {
+    HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
+  } else {
+    for (int s = 0; s < nst; ++s) HIPCHK(hipStreamWaitEvent(s0, c->evL[s], 0));
+  }
+  hipLaunchKernelGGL(k_step_end, dim3(c->pcols ? c->M + 1 : 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), s0, c->y, c->K,
+                     kstride(c), nst, c->coef, c->tw, c->sig, c->N, 0, c->status);
   LAUNCHCHK();
   return 0;
 }
@@ -1367,6 +1393,7 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
   // the step graphs hold depth, tension and gravity as kernel arguments: capture again
   c->gnst = -1;
   c->pkey = -1;
+  c->lag_off = false;
   c->tau = tau;
   c->g = g;
   c->M = M;
@@ -1418,6 +1445,7 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
     if (!c->gm_fixed && (rc = gmres_calibrate(c))) return rc;
   }
   if (pipelined(c, cols, two_streams)) {
+    c->pcols = cols && c->M > 0;
     if ((rc = ensure_pipe(c))) return rc;
     if ((rc = pipe_prologue(c))) return rc;
     if (graphed(c)) return ensure_pipe_graphs(c);
@@ -1490,10 +1518,10 @@ static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, doub
                      double* f, int* st, int* where) {
   const bool cols = (J != nullptr) && c->M > 0;
   const bool two = c->overlap && !pivoted(c);
-  const bool pipe = pipelined(c, cols, two);
   int rc;
   if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
   if ((rc = shoot_prepare(c, params, T, nsteps, cols, two))) return rc;
+  const bool pipe = pipelined(c, cols, two);   // after the set-up, which decides on GMRES
   for (int n = 0; n < nsteps; ++n) {
     if ((rc = shoot_one_step(c, cols, two))) return rc;
     if (pipe && n == 0 && nsteps > 1) {
@@ -1518,6 +1546,7 @@ static int shoot_eval_fb(ww_ctx* c, const double* params, double T, int nsteps, 
     int st = 0, where = 0, rc;
     if ((rc = shoot_run(c, params, T, nsteps, r, J, drdT, f, &st, &where))) return rc;
     const unsigned nf = next_fallback(c, st);
+    if (st & 32) c->lag_off = true;
     if (!nf) {
       if ((rc = status_error(c, st, where))) return rc;
       c->fb_last = c->fb;
@@ -1532,7 +1561,7 @@ extern "C" {
 int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
                double* f) {
   if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
-  return shoot_eval_fb(c, params, T, nsteps, r, J, drdT, f, 0);
+  return shoot_eval_fb(c, params, T, nsteps, r, J, drdT, f, c->lag_off ? WW_FB_DIRECT : 0);
 }
 
 int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params, const double* T,
@@ -1551,7 +1580,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   const bool two = n_inst == 1 && ctx[0]->overlap;
   for (int i = 0; i < n_inst; ++i) {
     const bool cols = J && J[i] && ctx[i]->M > 0;
-    ctx[i]->fb = 0;
+    ctx[i]->fb = ctx[i]->lag_off ? WW_FB_DIRECT : 0;
     if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols, two))) return rc;
     maxsteps = std::max(maxsteps, nsteps[i]);
   }
@@ -1571,6 +1600,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
     ww_ctx* c = ctx[i];
     int st = 0, where = 0, e;
     if ((e = read_status(c, &st, &where)) == 0) {
+      if (st & 32) c->lag_off = true;
       const unsigned nf = next_fallback(c, st);
       if (nf)   // this instance alone, in its fallback mode
         e = shoot_eval_fb(c, params[i], T[i], nsteps[i], r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr,

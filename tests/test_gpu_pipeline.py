@@ -69,7 +69,7 @@ def test_lagged_march_c1(lag, mixed):
 def test_lagged_march_falls_back_on_a_fast_changing_surface():
     """The steep surface changes too fast for factors four stages old (0.03 to 0.13 per
     step): the first step's check sends the march to each stage's own factors
-    (WW_FB_DIRECT), which match the oracle."""
+    (WW_FB_DIRECT), which match the oracle; later marches on the context start there."""
     ww, torch = _ww()
     N, M = 64, 3
     eta = W.steep_surface(N)
@@ -80,6 +80,16 @@ def test_lagged_march_falls_back_on_a_fast_changing_surface():
     assert ctx.fallbacks() == ww.WW_FB_DIRECT
     assert relerr(out["r"].cpu().numpy(), ref["r"]) < TOL
     assert relerr(out["J"].cpu().numpy(), ref["J"]) < TOL
+    # the context's next march starts on each stage's own factors (the same march again,
+    # so bitwise the same results); shoot_setup forgets it, and the march falls back anew
+    out2 = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+    assert ctx.fallbacks() == ww.WW_FB_DIRECT
+    assert np.array_equal(out2["r"].cpu().numpy(), out["r"].cpu().numpy())
+    assert np.array_equal(out2["J"].cpu().numpy(), out["J"].cpu().numpy())
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    out3 = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+    assert ctx.fallbacks() == ww.WW_FB_DIRECT
+    assert np.array_equal(out3["r"].cpu().numpy(), out["r"].cpu().numpy())
 
 
 def test_phase_profile_in_the_lagged_march():
@@ -103,6 +113,27 @@ def test_phase_profile_in_the_lagged_march():
     assert ctx.fallbacks() == 0
 
 
+def _ctx_env(ww, n_max, r_max, env):
+    """A context created under the given environment variables (read by ww_create)."""
+    import os
+    old = {v: os.environ.get(v) for v in env}
+    os.environ.update({v: str(x) for v, x in env.items()})
+    try:
+        return ww.Context(n_max=n_max, r_max=r_max)
+    finally:
+        for v, x in old.items():
+            if x is None:
+                os.environ.pop(v, None)
+            else:
+                os.environ[v] = x
+
+
+def _c2_short(M=16, nsteps=20):
+    w2 = W.c2()
+    return W.Workload("c2_short", w2.N, w2.h, w2.tau, w2.g, M, w2.T * nsteps / w2.nsteps, nsteps, w2.params[:M],
+                      W.cosine_basis(w2.N, M), w2.q_fixed)
+
+
 def test_lagged_march_is_bitwise_independent_of_the_lu_streams():
     """The lagged march's arithmetic does not depend on how its branches are scheduled:
     with 1, 2 or 5 LU streams (WW_LU_STREAMS), and on a second evaluation by the same
@@ -110,25 +141,12 @@ def test_lagged_march_is_bitwise_independent_of_the_lu_streams():
     that the LUs of different stages and the split step end really overlap; a missing
     dependency between the streams would show as a difference."""
     ww, torch = _ww()
-    import os
-    w2 = W.c2()
-    N, M, nsteps = w2.N, 16, 20
-    w = W.Workload("c2_short", N, w2.h, w2.tau, w2.g, M, w2.T * nsteps / w2.nsteps, nsteps, w2.params[:M],
-                   W.cosine_basis(N, M), w2.q_fixed)
+    w = _c2_short()
+    N, M = w.N, w.M
     outs = []
     for k in (1, 2, 5):
         print(f"lagged march N=256 M=16 lag=5 LU streams={k}", flush=True)
-        old = {v: os.environ.get(v) for v in ("WW_PIPE_LAG", "WW_LU_STREAMS")}
-        os.environ["WW_PIPE_LAG"] = "5"
-        os.environ["WW_LU_STREAMS"] = str(k)
-        try:
-            ctx = ww.Context(n_max=N, r_max=M + 1)
-        finally:
-            for v, x in old.items():
-                if x is None:
-                    os.environ.pop(v, None)
-                else:
-                    os.environ[v] = x
+        ctx = _ctx_env(ww, N, M + 1, {"WW_PIPE_LAG": 5, "WW_LU_STREAMS": k})
         ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
         for rep in range(2):
             out = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
@@ -140,3 +158,37 @@ def test_lagged_march_is_bitwise_independent_of_the_lu_streams():
     for r, J in outs[1:]:
         assert np.array_equal(r, r0)
         assert np.array_equal(J, J0)
+
+
+def test_lagged_march_without_columns():
+    """A march without Jacobian columns (the residual evaluations of the LM driver) also
+    solves on lagged factors.  Its base chain is the same arithmetic as in the march with
+    columns, so on one context r and f are bitwise those of the march with columns, in
+    either order (the first f-only march's graphs lack the column branches, which the
+    march with columns then adds); r is within 1e-12 of the march on every stage's own
+    factors (lag 0) and of the oracle; no fallback."""
+    ww, torch = _ww()
+    w = _c2_short()
+    N, M = w.N, w.M
+    print("lagged march without columns N=256 M=16 lag=5", flush=True)
+    ctx = _ctx_env(ww, N, M + 1, {"WW_PIPE_LAG": 5})
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    p = ww.to_dev(w.params)
+    outs = [ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False)]
+    assert ctx.fallbacks() == 0
+    outs.append(ctx.shoot_eval(p, w.T, w.nsteps))
+    assert ctx.fallbacks() == 0
+    outs.append(ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False))
+    assert ctx.fallbacks() == 0
+    r0 = outs[0]["r"].cpu().numpy()
+    for o in outs[1:]:
+        assert np.array_equal(o["r"].cpu().numpy(), r0)
+        assert o["f"] == outs[0]["f"]
+        assert np.array_equal(o["drdT"].cpu().numpy(), outs[0]["drdT"].cpu().numpy())
+    print("lag 0 without columns", flush=True)
+    ctx0 = _ctx_env(ww, N, M + 1, {"WW_PIPE_LAG": 0})
+    ctx0.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    out0 = ctx0.shoot_eval(p, w.T, w.nsteps, jacobian=False)
+    assert relerr(r0, out0["r"].cpu().numpy()) < TOL
+    ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
+    assert relerr(r0, ref["r"]) < TOL
