@@ -192,3 +192,27 @@ def test_lagged_march_without_columns():
     assert relerr(r0, out0["r"].cpu().numpy()) < TOL
     ref = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps)
     assert relerr(r0, ref["r"]) < TOL
+
+
+def test_lagged_march_without_graphs_matches_the_graphs():
+    """WW_NO_GRAPH=1 enqueues the same kernels in the same order on the same streams
+    directly instead of replaying the per-branch graphs: r, J and the f-only r are
+    bitwise the graphed march's."""
+    ww, torch = _ww()
+    w = _c2_short(M=8, nsteps=12)
+    N, M = w.N, w.M
+    outs = []
+    for env in ({"WW_PIPE_LAG": 5}, {"WW_PIPE_LAG": 5, "WW_NO_GRAPH": 1}):
+        print(f"lagged march N=256 M=8 {env}", flush=True)
+        ctx = _ctx_env(ww, N, M + 1, env)
+        ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        p = ww.to_dev(w.params)
+        a = ctx.shoot_eval(p, w.T, w.nsteps)
+        assert ctx.fallbacks() == 0
+        b = ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False)
+        assert ctx.fallbacks() == 0
+        outs.append((a["r"].cpu().numpy(), a["J"].cpu().numpy(), b["r"].cpu().numpy()))
+        del ctx
+    for x, y in zip(outs[0], outs[1]):
+        assert np.array_equal(x, y)
+    assert np.array_equal(outs[0][0], outs[0][2])
