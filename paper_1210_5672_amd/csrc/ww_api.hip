@@ -121,7 +121,8 @@ struct ww_ctx {
   // the results of the last call came from; guard is the unpivoted LU's pivot bound
   unsigned fb = 0, fb_last = 0;
   // a march on lagged factors failed its refinement test: the context's later marches
-  // (until the next shoot_setup) start on each stage's own factors (WW_FB_DIRECT)
+  // (until the next shoot_setup) start on each stage's own factors (WW_FB_DIRECT); not
+  // for WW_STRICT contexts, which report every failure instead
   bool lag_off = false;
   double guard = 1e-8;
   // partial-pivoting buffers, allocated on the first fallback: row order, elimination
@@ -1020,9 +1021,15 @@ static int ensure_pipe_graphs(ww_ctx* c) {
   int rc;
   if (c->pkey == pipe_key(c) && c->pgend) {
     if (!c->pcols || c->pgendc) return 0;
-    // the column branches (first march with columns on these graphs)
-    for (int s = 0; s < c->nst; ++s)
+    // the column branches (first march with columns on these graphs; an exec left by a
+    // capture that failed part-way has never been replayed)
+    for (int s = 0; s < c->nst; ++s) {
+      if (c->pgx[s][PP_COL]) {
+        HIPCHK(hipGraphExecDestroy(c->pgx[s][PP_COL]));
+        c->pgx[s][PP_COL] = nullptr;
+      }
       if ((rc = capture_part(c, s, PP_COL, &c->pgx[s][PP_COL]))) return rc;
+    }
     return capture_part(c, 0, -2, &c->pgendc);
   }
   HIPCHK(hipDeviceSynchronize());   // no replay of the old graphs may still run
@@ -1546,7 +1553,7 @@ static int shoot_eval_fb(ww_ctx* c, const double* params, double T, int nsteps, 
     int st = 0, where = 0, rc;
     if ((rc = shoot_run(c, params, T, nsteps, r, J, drdT, f, &st, &where))) return rc;
     const unsigned nf = next_fallback(c, st);
-    if (st & 32) c->lag_off = true;
+    if ((st & 32) && !strict(c)) c->lag_off = true;
     if (!nf) {
       if ((rc = status_error(c, st, where))) return rc;
       c->fb_last = c->fb;
@@ -1600,7 +1607,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
     ww_ctx* c = ctx[i];
     int st = 0, where = 0, e;
     if ((e = read_status(c, &st, &where)) == 0) {
-      if (st & 32) c->lag_off = true;
+      if ((st & 32) && !strict(c)) c->lag_off = true;
       const unsigned nf = next_fallback(c, st);
       if (nf)   // this instance alone, in its fallback mode
         e = shoot_eval_fb(c, params[i], T[i], nsteps[i], r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr,

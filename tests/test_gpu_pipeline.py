@@ -90,6 +90,22 @@ def test_lagged_march_falls_back_on_a_fast_changing_surface():
     out3 = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
     assert ctx.fallbacks() == ww.WW_FB_DIRECT
     assert np.array_equal(out3["r"].cpu().numpy(), out["r"].cpu().numpy())
+    # a WW_STRICT context reports the failure on every march (it remembers nothing)
+    import os
+    old = os.environ.get("WW_PIPE_LAG")
+    os.environ["WW_PIPE_LAG"] = "4"
+    try:
+        cs = ww.Context(n_max=64, r_max=M + 1, strict=True)
+    finally:
+        if old is None:
+            del os.environ["WW_PIPE_LAG"]
+        else:
+            os.environ["WW_PIPE_LAG"] = old
+    cs.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    for _ in range(2):
+        with pytest.raises(ww.WWError) as ei:
+            cs.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
+        assert ei.value.name == "WW_EREFINE"
 
 
 def test_phase_profile_in_the_lagged_march():
