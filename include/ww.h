@@ -157,13 +157,16 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  * path) solves with the factors of stage s - L and refines the solution with
  * the FP64 residual of its own matrix (the same number of sweeps and the same
  * convergence test as WW_MIXED), while the LU of its own matrix runs concurrently on one
- * of the context's LU streams (stage s on stream s mod K, K = 2; environment
- * WW_LU_STREAMS, 1..L); the column chain of stage s uses that stage's own factors.  Each
- * branch of a stage (spectral prep and assembly; the LU; the lagged base solve to the
- * base right-hand side; the column chain) is a graph of its own, replayed on its own
- * stream with the dependencies as events; the step end of the base column and that of
- * the Jacobian columns run on the caller's and the column stream, and the caller's
- * stream joins the others before the outputs.  The results do not depend on K.  A
+ * of the context's LU streams (stage s on stream s mod K, K = 3; environment
+ * WW_LU_STREAMS, 1..L); the column chain of stage s uses that stage's own factors and
+ * runs on the same LU stream after the LU, the column chains in stage order
+ * (WW_COLS_ON_LU=0: on a column stream of their own, with K = 2).  Each branch of a
+ * stage (spectral prep and assembly; the LU; the lagged base solve to the base
+ * right-hand side; the column chain) is a graph of its own, replayed on its stream with
+ * the dependencies as events; the step end of the base column runs on the caller's
+ * stream, that of the Jacobian columns after the last column chain, and the caller's
+ * stream joins the others before the outputs.  The results do not depend on K or on
+ * where the column chains run.  A
  * failed test (checked after the first step, and at the end) redoes the march with
  * every stage's own factors (WW_FB_DIRECT); the context's later marches then start that
  * way, until the next shoot_setup (not with WW_STRICT, which reports every failure).  Marches with and without J (M > 0 or J NULL) both

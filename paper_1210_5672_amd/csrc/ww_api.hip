@@ -136,7 +136,12 @@ struct ww_ctx {
   // the factors of stage s - lag (refined against its own matrix) while the LU of
   // stage s runs on one of `lag` streams; the column chain of stage s waits for it
   int lag = 5;   // environment WW_PIPE_LAG, 0..PIPE_MAXLAG (0: every solve uses its own factors)
-  int nlus = 2;  // LU streams (stage s on stream s mod nlus), at most lag; environment WW_LU_STREAMS
+  // LU streams (stage s on stream s mod nlus), at most lag; environment WW_LU_STREAMS,
+  // by default 3 with the column chains on them, 2 beside the column stream
+  int nlus = 3;
+  // the column chain of stage s runs on the LU stream of stage s, after its LU, instead
+  // of on the column stream (environment WW_COLS_ON_LU=0 turns it off)
+  bool cols_on_lu = true;
   int ring_n = 0;          // factor sets allocated (one per stage)
   RingSet ring[16];
   hipStream_t lus[PIPE_MAXLAG] = {};
@@ -357,16 +362,21 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     }
     const char* pl = std::getenv("WW_PIPE_LAG");
     if (pl) c->lag = std::max(0, std::min(PIPE_MAXLAG, std::atoi(pl)));
+    const char* cl = std::getenv("WW_COLS_ON_LU");
+    c->cols_on_lu = !(cl && cl[0] == '0');
+    if (!c->cols_on_lu) c->nlus = 2;
     const char* ns = std::getenv("WW_LU_STREAMS");
     if (ns) c->nlus = std::max(1, std::min(PIPE_MAXLAG, std::atoi(ns)));
     // streams: the working ones first, the capture stream (which never executes) last.
     // HIP shares its few hardware queues among a process's streams, each new stream
-    // taking the least-used queue: created in this order, the caller's stream, the
-    // column stream and the two LU streams of a march each get a queue of their own
-    // (with four), and no LU waits in the base chain's in-order queue.
-    CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
-    for (int i = 0; i < (c->lag > 0 ? std::min(c->nlus, c->lag) : 0); ++i)
-      CCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
+    // taking the least-used queue: created in this order, the caller's stream and the
+    // three LU streams of a march (or the column stream and two LU streams) each get a
+    // queue of their own (with four), and no LU waits in the base chain's in-order queue.
+    const int nls = c->lag > 0 ? std::min(c->nlus, c->lag) : 0;
+    // with the column chains on the LU streams, the LU streams take the queues first
+    if (!c->cols_on_lu) CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
+    for (int i = 0; i < nls; ++i) CCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
+    if (c->cols_on_lu) CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     CCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const char* pg = std::getenv("WW_PIVOT_GUARD");
     if (pg) {
@@ -945,6 +955,7 @@ static int pipe_prologue(ww_ctx* c) {
     HIPCHK(hipEventRecord(c->evC[q], c->stream));
     HIPCHK(hipEventRecord(c->evL[q], c->stream));
   }
+  HIPCHK(hipEventRecord(c->evE, c->stream));
   return 0;
 }
 
@@ -1079,6 +1090,15 @@ static int pipe_step(ww_ctx* c) {
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_BASE], s0));
     if (!c->pcols) continue;
     HIPCHK(hipEventRecord(c->evB[s], s0));
+    if (c->cols_on_lu) {
+      // after its own LU (same stream), the base chain of its stage, and the column
+      // chain before it (stage order; the first waits for the last step's column end)
+      HIPCHK(hipStreamWaitEvent(ls, c->evB[s], 0));
+      HIPCHK(hipStreamWaitEvent(ls, s == 0 ? c->evE : c->evC[s - 1], 0));
+      HIPCHK(hipGraphLaunch(c->pgx[s][PP_COL], ls));
+      HIPCHK(hipEventRecord(c->evC[s], ls));
+      continue;
+    }
     HIPCHK(hipStreamWaitEvent(c->side, c->evB[s], 0));
     HIPCHK(hipStreamWaitEvent(c->side, c->evL[s], 0));
     HIPCHK(hipGraphLaunch(c->pgx[s][PP_COL], c->side));
@@ -1086,8 +1106,9 @@ static int pipe_step(ww_ctx* c) {
   }
   HIPCHK(hipGraphLaunch(c->pgend, s0));
   if (c->pcols) {
-    HIPCHK(hipGraphLaunch(c->pgendc, c->side));
-    HIPCHK(hipEventRecord(c->evE, c->side));
+    hipStream_t cs = c->cols_on_lu ? lu_stream(c, nst - 1) : c->side;   // after the last column chain
+    HIPCHK(hipGraphLaunch(c->pgendc, cs));
+    HIPCHK(hipEventRecord(c->evE, cs));
   }
   c->pjoin = true;
   return 0;

@@ -152,17 +152,18 @@ def _c2_short(M=16, nsteps=20):
 
 def test_lagged_march_is_bitwise_independent_of_the_lu_streams():
     """The lagged march's arithmetic does not depend on how its branches are scheduled:
-    with 1, 2 or 5 LU streams (WW_LU_STREAMS), and on a second evaluation by the same
-    context, r and J are bitwise the same.  N = 256 (four 64-blocks) and 20 steps, so
+    with 1, 2 or 5 LU streams (WW_LU_STREAMS), with the column chains on the LU streams
+    (WW_COLS_ON_LU) and on a second evaluation by the same context, r and J are bitwise
+    the same.  N = 256 (four 64-blocks) and 20 steps, so
     that the LUs of different stages and the split step end really overlap; a missing
     dependency between the streams would show as a difference."""
     ww, torch = _ww()
     w = _c2_short()
     N, M = w.N, w.M
     outs = []
-    for k in (1, 2, 5):
-        print(f"lagged march N=256 M=16 lag=5 LU streams={k}", flush=True)
-        ctx = _ctx_env(ww, N, M + 1, {"WW_PIPE_LAG": 5, "WW_LU_STREAMS": k})
+    for k, col_on_lu in ((1, 0), (2, 0), (5, 0), (2, 1), (3, 1)):
+        print(f"lagged march N=256 M=16 lag=5 LU streams={k} columns on LU streams={col_on_lu}", flush=True)
+        ctx = _ctx_env(ww, N, M + 1, {"WW_PIPE_LAG": 5, "WW_LU_STREAMS": k, "WW_COLS_ON_LU": col_on_lu})
         ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
         for rep in range(2):
             out = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
