@@ -351,12 +351,14 @@ def main():
             out["mixed"]["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
                                         "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
                                         "phases_ms": phm}
-    if not args.no_batch:
-        out["batch"] = run_batch()
+    # single-instance sections first: the batch creates torch's stream pool, and every
+    # stream a process holds changes the hardware queues that later streams are given
     if not args.no_lm:
         out["lm"] = run_lm(with_oracle=not args.no_cpu_baseline)
     if not args.no_f_only:
         out["f_only"] = run_f_only(w, nsteps, T)
+    if not args.no_batch:
+        out["batch"] = run_batch()
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a counter run
         # give the scale between the counters and the bytes actually moved

@@ -373,10 +373,10 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     // three LU streams of a march (or the column stream and two LU streams) each get a
     // queue of their own (with four), and no LU waits in the base chain's in-order queue.
     const int nls = c->lag > 0 ? std::min(c->nlus, c->lag) : 0;
-    // with the column chains on the LU streams, the LU streams take the queues first
+    // the column stream only where it is used (created on first need otherwise: every
+    // stream a context holds shifts the queues of the streams created after it)
     if (!c->cols_on_lu) CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     for (int i = 0; i < nls; ++i) CCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
-    if (c->cols_on_lu) CCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
     CCHK(hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking));
     const char* pg = std::getenv("WW_PIVOT_GUARD");
     if (pg) {
@@ -881,7 +881,9 @@ static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
   return c->lag > 0 && two_streams && c->fb == 0 && c->nst > c->lag && !c->gm_active;
 }
 
-static int lu_count(const ww_ctx* c) { return std::min(c->nlus, c->lag); }
+// a march without columns keeps to two LU streams: they carry its LUs, and a third
+// concurrent LU only slows its base chain
+static int lu_count(const ww_ctx* c) { return std::min(c->pcols ? c->nlus : std::min(c->nlus, 2), c->lag); }
 static hipStream_t lu_stream(const ww_ctx* c, int s) { return c->lus[s % lu_count(c)]; }
 
 static int ensure_pipe(ww_ctx* c) {
@@ -1471,6 +1473,13 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   if (c->gm_active) {
     if ((rc = ensure_gmres(c))) return rc;
     if (!c->gm_fixed && (rc = gmres_calibrate(c))) return rc;
+  }
+  {
+    // the column stream: two-stream step graphs, and lagged marches whose column chains
+    // do not run on the LU streams
+    const bool pipe = pipelined(c, cols, two_streams);
+    if (cols && c->M > 0 && two_streams && !(pipe && graphed(c) && c->cols_on_lu) && !c->side)
+      HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   }
   if (pipelined(c, cols, two_streams)) {
     c->pcols = cols && c->M > 0;
