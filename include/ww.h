@@ -169,8 +169,9 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  * where the column chains run.  A
  * failed test (checked after the first step, and at the end) redoes the march with
  * every stage's own factors (WW_FB_DIRECT); the context's later marches then start that
- * way, until the next shoot_setup (not with WW_STRICT, which reports every failure).  Marches with and without J (M > 0 or J NULL) both
- * use lagged factors.
+ * way, until the next shoot_setup (not with WW_STRICT, which reports every failure).
+ * Marches with and without J (M > 0 or J NULL) both use lagged factors; without J, on
+ * at most two of the LU streams.
  * Synchronises to check the status flags.  A pivot below the guard anywhere in the
  * march redoes it with partial pivoting; a failed refinement test (WW_MIXED) redoes it
  * with FP64 factors (see ww_fallbacks).
