@@ -156,7 +156,8 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  * off): in a march of one instance, the base chain of stage s (the march's critical
  * path) solves with the factors of stage s - L and refines the solution with
  * the FP64 residual of its own matrix (the same number of sweeps and the same
- * convergence test as WW_MIXED), while the LU of its own matrix runs concurrently on one
+ * convergence test as WW_MIXED; environment WW_NREF_LAG, 1..8, sets the sweeps of
+ * these solves alone), while the LU of its own matrix runs concurrently on one
  * of the context's LU streams (stage s on stream s mod K, K = 3; environment
  * WW_LU_STREAMS, 1..L); the column chain of stage s uses that stage's own factors and
  * runs on the same LU stream after the LU, the column chains in stage order

@@ -84,6 +84,7 @@ struct ww_ctx {
   float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
   double *Rr = nullptr, *rr0 = nullptr;   // residuals of the refinement sweeps
   int nref = 2;                            // refinement sweeps per solve (mixed mode)
+  int nref_lag = -1;                       // sweeps of a lagged-factor solve (-1: nref)
   double *cosT = nullptr, *sinT = nullptr, *c0T = nullptr, *sig = nullptr;
   cplx* tw = nullptr;
   double* aux = nullptr;
@@ -355,6 +356,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->overlap = !(no && no[0] == '1');
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
+    const char* nl = std::getenv("WW_NREF_LAG");
+    if (nl) c->nref_lag = std::max(1, std::min(8, std::atoi(nl)));
     const char* gi = std::getenv("WW_GMRES_ITERS");
     if (gi) {
       c->gm_m = std::max(2, std::min(GM_MAXM, std::atoi(gi)));
@@ -682,9 +685,10 @@ static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* 
     if ((rc = enqueue_gemm<double>(c, nullptr, F.X, F.Xr, 1, B, B, 1.0, Y, 1))) return rc;
     if ((rc = enqueue_gemm<double>(c, nullptr, F.Z, F.Zr, 2, Y, nullptr, 1.0, X, 1))) return rc;
   }
-  for (int it = 0; it <= c->nref; ++it) {
+  const int nref = c->nref_lag >= 0 ? c->nref_lag : c->nref;
+  for (int it = 0; it <= nref; ++it) {
     if ((rc = enqueue_gemm<double>(c, nullptr, Fa.A, Fa.Ar, 0, X, B, -1.0, Rs, 1))) return rc;
-    if (it == c->nref) break;   // the last residual is the convergence test's
+    if (it == nref) break;   // the last residual is the convergence test's
     if (F.use32) {
       if ((rc = enqueue_gemm<float>(c, nullptr, F.X32, F.X32r, 1, Rs, Rs, 1.0, Y, 1))) return rc;
       if ((rc = enqueue_gemm<float>(c, nullptr, F.Z32, F.Z32r, 2, Y, X, 1.0, X, 1))) return rc;
