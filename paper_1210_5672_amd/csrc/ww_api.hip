@@ -398,7 +398,13 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   CCHK(hipFuncSetAttribute((const void*)k_blu_final<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_gemm_part<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  CCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  {
+    // k_gamma holds static LDS too (the folded refinement test): dynamic + static <= big
+    hipFuncAttributes fa;
+    CCHK(hipFuncGetAttributes(&fa, (const void*)k_gamma));
+    CCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize,
+                             big - (int)fa.sharedSizeBytes));
+  }
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_col_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -674,7 +680,9 @@ static const double REFINE_TOL = 1.1368683772161603e-13;
 // Lagged factors (one vector): the factors of F are those of an earlier stage and Fa
 // holds this stage's matrix (row-major Ar): X = Z (B + Xs B), nref sweeps of
 // r = B - A X, X += Z (r + Xs r), and the same convergence test as the mixed form.
-static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* B, double* Y, double* X, double* Rs) {
+// check: launch the convergence test here (false: the caller folds it into k_gamma)
+static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* B, double* Y, double* X, double* Rs,
+                                bool check) {
   if (!Fa.Ar || !(F.use32 ? (F.X32r && F.Z32r) : (F.Xr && F.Zr)))
     return fail(WW_EHIP, "internal: lagged solve without row-major operands");
   int rc;
@@ -697,6 +705,7 @@ static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* 
       if ((rc = enqueue_gemm<double>(c, nullptr, F.Z, F.Zr, 2, Y, X, 1.0, X, 1))) return rc;
     }
   }
+  if (!check) return 0;
   hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(WW_NT), 0, c->stream, Rs, B, c->Np, c->N, REFINE_TOL, c->status,
                      32);
   LAUNCHCHK();
@@ -739,7 +748,7 @@ static int enqueue_dtn_cols(ww_ctx* c, const Fac& F, double* B, double* Yt, doub
   int rc;
   if ((rc = enqueue_solve(c, F, B, Yt, Mu, Rs, R))) return rc;
   hipLaunchKernelGGL(k_gamma, dim3((R + 1) / 2), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Mu, c->Np, R, Gam,
-                     HGm, c->tw, c->N);
+                     HGm, c->tw, c->N, nullptr, nullptr, 0.0, nullptr, 0);
   LAUNCHCHK();
   return enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, Gam, HGm, 1.0, out, R);
 }
@@ -844,7 +853,7 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
     if ((rc = enqueue_assemble(c, F, true))) return rc;
     if ((rc = enqueue_gmres(c, F, c->rhs0, c->mu0, c->rr0))) return rc;
     hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->mu0, c->Np, 1, c->gam0,
-                       c->hg0, c->tw, c->N);
+                       c->hg0, c->tw, c->N, nullptr, nullptr, 0.0, nullptr, 0);
     LAUNCHCHK();
     if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
   } else {
@@ -984,9 +993,9 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
   if (part == PP_LU) return enqueue_lu(c, F);
   if (part == PP_BASE) {
     const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
-    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0))) return rc;
+    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0, false))) return rc;
     hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->mu0, c->Np, 1, c->gam0,
-                       c->hg0, c->tw, c->N);
+                       c->hg0, c->tw, c->N, c->rr0, c->rhs0, REFINE_TOL, c->status, 32);
     LAUNCHCHK();
     if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
     hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
@@ -1169,9 +1178,9 @@ static int enqueue_step_pipe(ww_ctx* c) {
       rc = fail(WW_EHIP, "pipeline: event wait");
       break;
     }
-    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0))) break;
+    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0, false))) break;
     hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->mu0, c->Np, 1, c->gam0, c->hg0,
-                       c->tw, c->N);
+                       c->tw, c->N, c->rr0, c->rhs0, REFINE_TOL, c->status, 32);
     if (hipGetLastError() != hipSuccess) {
       rc = fail(WW_EHIP, "kernel launch: k_gamma");
       break;

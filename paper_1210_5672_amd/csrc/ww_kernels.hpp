@@ -1153,9 +1153,17 @@ __global__ void k_gemm_reduce(const double* __restrict__ part, int nsplit, const
 // (both zero at k = 0 and at Nyquist).  Rows N..Np-1 of the outputs are zero.
 // Dynamic LDS: 4 N complex (three work buffers and the twiddles).
 // -------------------------------------------------------------------------------------
+__device__ inline void refine_check_col(const double* __restrict__ rc, const double* __restrict__ bc, int N,
+                                        double tol, int* __restrict__ status, int flag);
+
 __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, int Np, int ncols,
                                                  double* __restrict__ Gam, double* __restrict__ HG,
-                                                 const cplx* __restrict__ tw, int N) {
+                                                 const cplx* __restrict__ tw, int N,
+                                                 const double* __restrict__ chk_r, const double* __restrict__ chk_b,
+                                                 double chk_tol, int* __restrict__ status, int chk_flag) {
+  // the refinement test of the solve that produced Mu's first column, when chk_r is
+  // given (the check kernel's work, folded into this launch)
+  if (chk_r && blockIdx.x == 0) refine_check_col(chk_r, chk_b, N, chk_tol, status, chk_flag);
   extern __shared__ cplx lds[];
   cplx* Z = lds;
   cplx* W = lds + N;
@@ -1713,12 +1721,9 @@ __global__ void k_save_aux(const double* __restrict__ aux, int nmax, int N, doub
 // (a relative residual, which bounds the normwise backward error); a column that
 // fails, or a NaN, sets status bit 4 (reported as WW_EREFINE).
 // -------------------------------------------------------------------------------------
-__global__ __launch_bounds__(WW_NT) void k_refine_check(const double* __restrict__ r, const double* __restrict__ B,
-                                                        int Np, int N, double tol, int* __restrict__ status,
-                                                        int flag) {
+__device__ inline void refine_check_col(const double* __restrict__ rc, const double* __restrict__ bc, int N,
+                                        double tol, int* __restrict__ status, int flag) {
   __shared__ double rr[WW_NT], rb[WW_NT];
-  const double* rc = r + (size_t)blockIdx.x * Np;
-  const double* bc = B + (size_t)blockIdx.x * Np;
   double mr = 0.0, mb = 0.0;
   for (int i = threadIdx.x; i < N; i += WW_NT) {
     mr = fmax(mr, fabs(rc[i]));
@@ -1736,6 +1741,12 @@ __global__ __launch_bounds__(WW_NT) void k_refine_check(const double* __restrict
     __syncthreads();
   }
   if (threadIdx.x == 0 && !(rr[0] <= tol * rb[0])) atomicOr(status, flag);
+}
+
+__global__ __launch_bounds__(WW_NT) void k_refine_check(const double* __restrict__ r, const double* __restrict__ B,
+                                                        int Np, int N, double tol, int* __restrict__ status,
+                                                        int flag) {
+  refine_check_col(r + (size_t)blockIdx.x * Np, B + (size_t)blockIdx.x * Np, N, tol, status, flag);
 }
 
 // -------------------------------------------------------------------------------------
