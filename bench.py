@@ -29,7 +29,7 @@ HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 # plain 256 MiB copy.  Valid only for the kernel source it was measured on: reported as
 # null once the kernels header changes.
 LU_TRAFFIC_BYTES = 266.5e6
-LU_TRAFFIC_SOURCE_SHA256 = "7e7723d28c5d97cb6cd41e0522bdcbd27cb1b88e57fe816e4a5729f4ed255872"
+LU_TRAFFIC_SOURCE_SHA256 = "a51d552ad83d578b6f25c53177e7249737797ba829ade75408df29f1d991d6ff"
 
 
 def lu_traffic():
