@@ -170,8 +170,50 @@ class ArithAlt(Arith):
         return np.cosh(y), np.sinh(y)
 
 
+class ArithAltFFT(Arith):
+    """The same FP64 arithmetic with every Fourier multiplier applied through the full
+    complex FFT (numpy.fft.fft / ifft) instead of the real-input transforms: the same
+    operator, another rounding.  Used only to measure the FP64 rounding floor."""
+
+    name = "f64altfft"
+
+    def spectral(self, kind: str, f):
+        N = f.shape[0]
+        key = ("full", kind, N)
+        if key not in self._mult:
+            k = np.arange(N)
+            k = np.where(k <= N // 2, k, k - N)          # signed wavenumber of each bin
+            m = multiplier(kind, N, np.abs(k).astype(float))
+            self._mult[key] = np.where(k >= 0, m, np.conj(m))
+        m = self._mult[key]
+        fh = np.fft.fft(f, axis=0)
+        fh = fh * (m[:, None] if f.ndim == 2 else m)
+        return np.fft.ifft(fh, axis=0).real
+
+
+class ArithAltSum(Arith):
+    """The same FP64 arithmetic with the summation order of the products and of the
+    dense solve reversed: matrix products sum over the inner index from the last term
+    to the first, and A x = b is solved as (J A J)(J x) = J b with J the reversal, so
+    that elimination runs from the last unknown to the first.  Used only to measure
+    the FP64 rounding floor."""
+
+    name = "f64altsum"
+
+    def matmul(self, A, B):
+        return A[:, ::-1] @ B[::-1]
+
+    def lu_factor(self, A):
+        return scipy.linalg.lu_factor(np.ascontiguousarray(A[::-1, ::-1]))
+
+    def lu_solve(self, lu, B):
+        return scipy.linalg.lu_solve(lu, np.ascontiguousarray(B[::-1]))[::-1]
+
+
 F64 = Arith()
 F64ALT = ArithAlt()
+F64ALT_FFT = ArithAltFFT()
+F64ALT_SUM = ArithAltSum()
 
 
 # --------------------------------------------------------------------------------
