@@ -165,3 +165,77 @@ def test_bfgs_line_search_meets_the_strong_wolfe_conditions():
     assert ok
     assert f <= f0 + B.C1 * a * (g0 @ p)
     assert abs(g @ p) <= -B.C2 * (g0 @ p)
+
+
+def _scripted(c_star, K=None, bad_calls=()):
+    """A residual whose quadratic model is exact, r(c) = [c - c*; K] with J = [I; 0],
+    except on the residual calls listed in bad_calls, which return a residual far from
+    the model (the step is then rejected)."""
+    calls = {"n": 0}
+    extra = [] if K is None else [K]
+
+    def res(c):
+        calls["n"] += 1
+        r = np.concatenate([c - c_star, extra])
+        if calls["n"] in bad_calls:
+            r = r + 10.0
+        return r
+
+    def jac(c):
+        n = len(c)
+        J = np.vstack([np.eye(n), np.zeros((len(extra), n))])
+        return np.concatenate([c - c_star, extra]), J
+
+    return res, jac
+
+
+def test_levmar_rule2_delta_trigger_and_radius_reset():
+    """App. C rule 2 with hand-computed radii: from c = 0 toward c* = (1, 0), Delta_0 =
+    0.1.  Step 1 (model exact, rho = 1, full radius) is accepted and the radius grows
+    by alpha_1 to 0.1875.  Steps 2 and 3 are rejected: the first rejected radius after
+    an accepted step, 0.1875, becomes delta_first_rejected, and each rejection shrinks
+    the radius to alpha_0 ||p|| (0.0703125, then 0.0263672).  The second falls below
+    delta_trigger = alpha_2 * 0.1875 = 0.0375, so J is recomputed and the radius reset to
+    delta_first_rejected / alpha_1 = 0.1, which the fourth step uses."""
+    res, jac = _scripted(np.array([1.0, 0.0]), bad_calls=(2, 3))
+    out = L.levmar(res, jac, np.zeros(2), delta0=0.1, max_evals=6)
+    radii = [h[3] for h in out.history]
+    acc = [h[2] for h in out.history]
+    assert acc[:4] == [True, False, False, True]
+    assert np.allclose(radii[:4], [0.1, 0.1875, 0.0703125, 0.1], rtol=1e-14, atol=0)
+    # J evaluations: the first, then the recomputation after step 3
+    res2, jac2 = _scripted(np.array([1.0, 0.0]), bad_calls=(2, 3))
+    out3 = L.levmar(res2, jac2, np.zeros(2), delta0=0.1, max_evals=4)
+    assert (out3.evals_r, out3.evals_J) == (3, 2)
+    # one rejection only: 0.0703125 stays above the trigger, J is kept, and the next
+    # radius is the shrunk one
+    res1, jac1 = _scripted(np.array([1.0, 0.0]), bad_calls=(2,))
+    out1 = L.levmar(res1, jac1, np.zeros(2), delta0=0.1, max_evals=4)
+    assert [h[3] for h in out1.history[:3]] == pytest.approx([0.1, 0.1875, 0.0703125], rel=1e-14)
+    assert out1.evals_J == 1
+
+
+def test_levmar_rule2_first_rejection_before_any_acceptance_is_not_remembered():
+    """Reading L2: a rejection before the first accepted step of a Jacobian does not set
+    delta_first_rejected, so no trigger fires however small the radius gets."""
+    res, jac = _scripted(np.array([1.0, 0.0]), bad_calls=(1, 2, 3))
+    out = L.levmar(res, jac, np.zeros(2), delta0=0.1, max_evals=4)
+    radii = [h[3] for h in out.history]
+    assert [h[2] for h in out.history] == [False, False, False]
+    assert np.allclose(radii, [0.1, 0.0375, 0.0140625], rtol=1e-14, atol=0)
+    assert out.evals_J == 1
+
+
+def test_levmar_rule3_small_predicted_decrease_recomputes_the_jacobian():
+    """App. C rule 3 (reading L3): with a constant residual part K = 100 (f ~ 5000),
+    step 1 predicts |df|/f = 0.495/5000.5 ~ 1e-4 >= df_tol (no roundoff regime); step 2
+    lands on the minimiser with |df|/f = 0.005/5000.005 ~ 1e-6 < df_tol, so J is
+    recomputed after two residual evaluations; at the fresh J the step is zero and the
+    driver stops with c unchanged, at c*."""
+    res, jac = _scripted(np.array([1.0, 0.0]), K=100.0)
+    out = L.levmar(res, jac, np.zeros(2), delta0=0.9)
+    assert (out.evals_r, out.evals_J) == (2, 2)
+    assert out.reason == "c unchanged"
+    assert np.allclose(out.c, [1.0, 0.0], rtol=0, atol=1e-15)
+    assert [h[2] for h in out.history] == [True, True]
+    assert np.allclose([h[3] for h in out.history], [0.9, 1.6875], rtol=1e-14, atol=0)
