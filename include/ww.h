@@ -329,6 +329,21 @@ typedef struct ww_bfgs_report {
 int ww_bfgs_default_opts(ww_bfgs_opts *opts);
 int ww_bfgs(ww_ctx *ctx, double *c, int nsteps, const ww_bfgs_opts *opts, ww_bfgs_report *rep);
 
+/*
+ * ww_next_fallback (host only, no context): the decision a march takes from its status
+ * bits -- 1 pivot below the guard (unpivoted LU), 8 pivot below the guard (pivoted LU),
+ * 2 non-finite state, 4 failed refinement test (mixed form), 16 surface through the
+ * bottom, 32 failed test of a lagged-factor solve, 64 failed test of a GMRES solve --
+ * for a context with `flags` (WW_STRICT matters) whose current results came from the
+ * fallbacks `fb` (WW_FB_* bits): the WW_FB_* bits to add and redo the march with, or 0
+ * (report the status as an error, or succeed).  A small pivot is redone with pivoted
+ * factors first (every stage then solves with its own factors).  A failed lagged or
+ * GMRES solve is redone on each stage's own factors before a bed crossing is reported
+ * (the crossing may come from the unconverged solves); a crossing on those factors
+ * ends the call with WW_EDOMAIN.  Exposed for tests of the host logic.
+ */
+unsigned ww_next_fallback(unsigned flags, unsigned fb, int status);
+
 /* thread-local message of the last failure on this thread ("" if none) */
 const char *ww_last_error(void);
 

@@ -1540,14 +1540,28 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
 
 // Status bits of a march: 1 pivot below the guard (unpivoted LU), 8 pivot below the
 // guard (pivoted LU), 2 non-finite state, 4 failed refinement test (mixed form), 16
-// surface through the bottom, 32 failed refinement test of a lagged-factor solve.  The
-// fallback that a redo of the call takes, or 0.
-static unsigned next_fallback(const ww_ctx* c, int st) {
-  if (strict(c) || (st & 16)) return 0;   // a surface through the bottom is no factorisation issue
-  if ((st & (1 | 8)) && !pivoted(c)) return WW_FB_PIVOTED | WW_FB_FP64;
-  if ((st & (32 | 64)) && !(c->fb & WW_FB_DIRECT)) return WW_FB_DIRECT;
-  if ((st & 4) && !(c->fb & WW_FB_FP64)) return WW_FB_FP64;
+// surface through the bottom, 32 failed refinement test of a lagged-factor solve, 64
+// failed residual test of a GMRES solve.  The fallback that a redo of the call takes,
+// or 0.  A small pivot redoes the march with pivoted factors first (which also ends
+// the lagged and GMRES solves: every stage then solves with its own factors).
+// Unconverged lagged or GMRES solves are redone on each stage's own factors: the state
+// they produced, a bed crossing included, is not the method's.  A crossing on a march
+// without such solves is reported, not redone (small pivots there come from the
+// crossing).
+static unsigned fallback_decision(unsigned flags, unsigned fb, int st) {
+  if (flags & WW_STRICT) return 0;
+  const bool unconverged = (st & (32 | 64)) && !(fb & WW_FB_DIRECT);
+  if ((st & (1 | 8)) && !(fb & WW_FB_PIVOTED) && (!(st & 16) || unconverged)) return WW_FB_PIVOTED | WW_FB_FP64;
+  if (unconverged) return WW_FB_DIRECT;
+  if (st & 16) return 0;   // a surface through the bottom is no factorisation issue
+  if ((st & 4) && !(fb & WW_FB_FP64)) return WW_FB_FP64;
   return 0;
+}
+
+static unsigned next_fallback(const ww_ctx* c, int st) { return fallback_decision(c->flags, c->fb, st); }
+
+extern "C" unsigned ww_next_fallback(unsigned flags, unsigned fb, int status) {
+  return fallback_decision(flags, fb, status);
 }
 
 static int status_error(const ww_ctx* c, int st, int where) {
@@ -1584,7 +1598,14 @@ static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, doub
       if (peek) return read_status(c, st, where);
     }
   }
-  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) return rc;
+  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
+    // work already enqueued may still write the caller's outputs (and f on the host)
+    const std::string msg = g_err;
+    (void)pipe_join(c);
+    (void)hipStreamSynchronize(c->stream);
+    g_err = msg;
+    return rc;
+  }
   return read_status(c, st, where);
 }
 
@@ -1624,6 +1645,20 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   }
   int rc;
   int maxsteps = 0;
+  // An error part-way leaves work of the instances enqueued so far (writes into the
+  // caller's r, J, drdT and, for f, a host copy into the caller's array): wait for all
+  // of it before returning, so that no write lands after the caller has freed them.
+  auto settle = [&](int code) {
+    const std::string msg = g_err;
+    for (int i = 0; i < n_inst; ++i) {
+      (void)pipe_join(ctx[i]);
+      (void)hipStreamSynchronize(ctx[i]->stream);
+      int st = 0;
+      (void)read_status(ctx[i], &st);
+    }
+    g_err = msg;
+    return code;
+  };
   // one instance: the two-stream step graph of shoot_eval; several: one-stream graphs,
   // which the hardware overlaps across instances (two-stream graphs of several
   // instances run one after the other)
@@ -1631,7 +1666,7 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   for (int i = 0; i < n_inst; ++i) {
     const bool cols = J && J[i] && ctx[i]->M > 0;
     ctx[i]->fb = ctx[i]->lag_off ? WW_FB_DIRECT : 0;
-    if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols, two))) return rc;
+    if ((rc = shoot_prepare(ctx[i], params[i], T[i], nsteps[i], cols, two))) return settle(rc);
     maxsteps = std::max(maxsteps, nsteps[i]);
   }
   // interleave the instances step by step: each context replays its own step graph on
@@ -1639,11 +1674,11 @@ int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params
   for (int n = 0; n < maxsteps; ++n)
     for (int i = 0; i < n_inst; ++i)
       if (n < nsteps[i])
-        if ((rc = shoot_one_step(ctx[i], J && J[i] && ctx[i]->M > 0, two))) return rc;
+        if ((rc = shoot_one_step(ctx[i], J && J[i] && ctx[i]->M > 0, two))) return settle(rc);
   for (int i = 0; i < n_inst; ++i) {
     const bool cols = J && J[i] && ctx[i]->M > 0;
     if ((rc = shoot_finish(ctx[i], cols, r[i], J ? J[i] : nullptr, drdT ? drdT[i] : nullptr, f ? &f[i] : nullptr)))
-      return rc;
+      return settle(rc);
   }
   int first_err = 0;
   for (int i = 0; i < n_inst; ++i) {

@@ -59,7 +59,8 @@ class LmReport(ctypes.Structure):
 EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_setup",
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
-           "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts"]
+           "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
+           "ww_next_fallback"]
 
 
 class WWError(RuntimeError):
@@ -89,6 +90,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ww_set_tableau.argtypes = [P, I, DP, DP, DP]
     lib.dtn_setup.argtypes = [P, P, D, D, I]
     lib.dtn_solve_multi.argtypes = [P, P, I, P, P]
+    lib.ww_next_fallback.argtypes = [U, U, I]
+    lib.ww_next_fallback.restype = U
     lib.shoot_setup.argtypes = [P, I, D, D, D, P, P, I]
     lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
     lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]

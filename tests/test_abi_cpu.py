@@ -95,3 +95,34 @@ def test_jacobi_round_schedule_covers_every_pair_once():
                 if b < n:
                     seen[(a, b)] = seen.get((a, b), 0) + 1
         assert len(seen) == n * (n - 1) // 2 and all(v == 1 for v in seen.values()), n
+
+
+def test_fallback_decision_table():
+    """The redo a march takes from its status bits (host logic, no GPU): a small pivot
+    (1, 8) redoes pivoted (also FP64; every stage then uses its own factors);
+    unconverged lagged-factor (32) or GMRES (64) solves are redone on each stage's own
+    factors, also when the surface crossed the bed (16), since that state came from
+    the unconverged solves; a crossing on those factors, or without such solves, is
+    reported (its small pivots too); a failed mixed refinement test redoes in FP64;
+    WW_STRICT contexts never redo."""
+    ww, lib = _lib()
+    F = lib.ww_next_fallback
+    PIV, FP64, DIRECT, STRICT = ww.WW_FB_PIVOTED, ww.WW_FB_FP64, ww.WW_FB_DIRECT, ww.WW_STRICT
+    assert F(0, 0, 0) == 0
+    assert F(0, 0, 32) == DIRECT and F(0, 0, 64) == DIRECT
+    assert F(0, 0, 32 | 16) == DIRECT            # crossing on lagged factors: redo first
+    assert F(0, 0, 64 | 16 | 2) == DIRECT
+    assert F(0, DIRECT, 32 | 16) == 0           # crossing on the direct factors: report
+    assert F(0, 0, 16) == 0 and F(0, 0, 16 | 1) == 0
+    assert F(0, 0, 1) == PIV | FP64 and F(0, 0, 8) == PIV | FP64
+    assert F(0, PIV | FP64, 8) == 0              # the pivoted factors failed too: report
+    assert F(0, DIRECT, 1 | 32) == PIV | FP64
+    assert F(0, 0, 1 | 32) == PIV | FP64         # pivots first: it also ends the lagging
+    assert F(0, 0, 1 | 32 | 16) == PIV | FP64
+    assert F(0, PIV | FP64, 32) == DIRECT
+    assert F(ww.WW_MIXED, 0, 4) == FP64 and F(ww.WW_MIXED, FP64, 4) == 0
+    assert F(0, 0, 2) == 0                       # non-finite state: report
+    for st in (1, 4, 8, 16, 32, 64, 32 | 16):
+        assert F(STRICT, 0, st) == 0
+        assert F(STRICT | ww.WW_MIXED, 0, st) == 0
+
