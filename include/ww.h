@@ -134,6 +134,25 @@ int dtn_setup(ww_ctx *ctx, const double *surface, double h, double tau, int N);
 int dtn_solve_multi(ww_ctx *ctx, const double *rhs, int nrhs, double *dtn_out, double *mu_out);
 
 /*
+ * dtn_solve_multi_noalloc: dtn_solve_multi for callers that cannot allocate device
+ * memory -- code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation.  Same arguments, results and errors as dtn_solve_multi (with the factors
+ * of the last dtn_setup on the context), but its per-call work arrays (the padded
+ * right-hand sides, the intermediate solves, gamma, (1/2) H gamma, the DtN output, the
+ * mixed-form residuals and the split-K partials of the products) live in one fixed
+ * device array of WW_SCRATCH_BYTES per GPU instead of the context's workspace; the
+ * call itself allocates nothing.  Limit: 8 Np nrhs doubles must fit that array (Np = N
+ * rounded up to 64; e.g. N = 1024 with nrhs <= 512), else WW_EINVAL; the products
+ * split their inner dimension at most as often as the rest of the array allows, so
+ * results can differ from dtn_solve_multi by rounding only.  Every call on a GPU uses
+ * that GPU's one array, which keeps the last call's contents: calls that overlap on
+ * one GPU (on different streams, or from different threads) race; calls ordered on
+ * one stream do not.  The array is held until the process ends.
+ */
+#define WW_SCRATCH_BYTES (32u << 20)
+int dtn_solve_multi_noalloc(ww_ctx *ctx, const double *rhs, int nrhs, double *dtn_out, double *mu_out);
+
+/*
  * shoot_setup (Sec. 3.1 eq. (init:stand), Sec. 3.3 eq. (q:qdot)): define the initial
  * state q0(c) = q_fixed + basis c, c in R^M, and the Jacobian seeds Qdot(0) = basis.
  * basis: device, 2N x M, column k = (eta part; phi part).  q_fixed: device 2N or NULL

@@ -15,7 +15,18 @@
 #include "ww_gmres.hpp"
 
 #include <algorithm>
+#include <mutex>
 #include <numeric>
+
+// Fixed device workspace of the allocation-free solve (dtn_solve_multi_noalloc): one
+// array per GPU, held until the process ends.  Host code never uses its name as an
+// address: ww_create resolves the address on each device once (hipGetSymbolAddress,
+// with that device current) and every use goes through that pointer.
+#define WW_SCRATCH_DOUBLES ((size_t)WW_SCRATCH_BYTES / 8)
+static __device__ __align__(256) double scratch[WW_SCRATCH_DOUBLES];
+static std::mutex g_scratch_mu;
+static const int SCRATCH_MAX_DEV = 64;
+static double* g_scratch_dev[SCRATCH_MAX_DEV] = {};
 
 static thread_local std::string g_err;
 
@@ -126,6 +137,10 @@ struct ww_ctx {
   // for WW_STRICT contexts, which report every failure instead
   bool lag_off = false;
   double guard = 1e-8;
+  // split-K count cap of the products (0: none); set only inside the allocation-free
+  // solve, whose partials must fit the fixed workspace
+  int split_cap = 0;
+  double* scratch = nullptr;   // this device's fixed workspace (address resolved at create)
   // partial-pivoting buffers, allocated on the first fallback: row order, elimination
   // workspace (Np x Np), gathered right-hand sides (Np x r_max); the adjoint keeps one
   // row order per stored stage
@@ -263,6 +278,25 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     }                                                                                  \
   } while (0)
   CCHK(hipGetDevice(&c->dev));
+  {
+    // the fixed workspace of the allocation-free solve: its address on this device,
+    // resolved once per device with the device current
+    if (c->dev < 0 || c->dev >= SCRATCH_MAX_DEV) {
+      ww_destroy(c);
+      return fail(WW_EINVAL, "device index out of range");
+    }
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[c->dev]) {
+      void* sp = nullptr;
+      const hipError_t e = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+      if (e != hipSuccess || !sp) {
+        ww_destroy(c);
+        return fail(WW_EHIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(e));
+      }
+      g_scratch_dev[c->dev] = (double*)sp;
+    }
+    c->scratch = g_scratch_dev[c->dev];
+  }
   c->stream = (hipStream_t)hip_stream;
   c->flags = flags;
   c->n_max = n_max;
@@ -655,6 +689,7 @@ static int enqueue_gemm(ww_ctx* c, double* part, const T* M, const T* Mr, int mo
   const int tiles = nkt * ((R + 63) / 64);
   int nsplit = (512 + tiles - 1) / tiles;
   if (nsplit > nkt) nsplit = nkt;
+  if (c->split_cap > 0 && nsplit > c->split_cap) nsplit = c->split_cap;
   if (nsplit < 1) nsplit = 1;
   const int kchunk = (nkt + nsplit - 1) / nsplit;
   nsplit = (nkt + kchunk - 1) / kchunk;
@@ -1361,19 +1396,26 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
   return 0;
 }
 
-int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, double* mu_out) {
-  if (!c || !rhs || !dtn_out) return fail(WW_EINVAL, "null argument");
-  if (!c->dtn_ready) return fail(WW_ENOSETUP, "dtn_solve_multi before dtn_setup");
-  if (nrhs < 1 || nrhs > c->r_max) return fail(WW_EINVAL, "nrhs out of range");
+}  // extern "C"
+
+// work arrays of one dtn_solve_multi call (each Np x nrhs, ld Np; Rr only in the mixed
+// form) and the split-K partials of its products
+struct SolveWork {
+  double *Psi, *Ytmp, *Mu, *Gam, *HG, *Gpsi, *Rr, *part;
+};
+
+static int dtn_solve_impl(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, double* mu_out,
+                          const SolveWork& w) {
   const int N = c->N, Np = c->Np;
   const size_t tot = (size_t)Np * nrhs;
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs, N, c->Psi, Np, N, Np, nrhs);
+  hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs, N, w.Psi, Np, N, Np, nrhs);
   LAUNCHCHK();
   int rc;
   for (;;) {
-    if ((rc = enqueue_dtn_cols(c, fac_default(c), c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, nrhs)))
-      return rc;
+    Fac F = fac_default(c);
+    F.part = w.part;
+    if ((rc = enqueue_dtn_cols(c, F, w.Psi, w.Ytmp, w.Mu, w.Gam, w.HG, w.Gpsi, w.Rr, nrhs))) return rc;
     if (!use32(c)) break;
     int st = 0;   // the refinement test of the mixed path
     if ((rc = read_status(c, &st))) return rc;
@@ -1384,14 +1426,50 @@ int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, dou
     if ((rc = dtn_factor(c))) return rc;
     c->dtn_ready = true;
   }
-  hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Gpsi, Np, dtn_out, N, Np, N, nrhs);
+  hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, w.Gpsi, Np, dtn_out, N, Np, N, nrhs);
   LAUNCHCHK();
   if (mu_out) {
-    hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, c->Mu, Np, mu_out, N, Np, N, nrhs);
+    hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, w.Mu, Np, mu_out, N, Np, N, nrhs);
     LAUNCHCHK();
   }
   c->fb_last = c->fb;
   return 0;
+}
+
+static int dtn_solve_check(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out) {
+  if (!c || !rhs || !dtn_out) return fail(WW_EINVAL, "null argument");
+  if (!c->dtn_ready) return fail(WW_ENOSETUP, "dtn_solve_multi before dtn_setup");
+  if (nrhs < 1 || nrhs > c->r_max) return fail(WW_EINVAL, "nrhs out of range");
+  return 0;
+}
+
+extern "C" {
+
+int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, double* mu_out) {
+  int rc;
+  if ((rc = dtn_solve_check(c, rhs, nrhs, dtn_out))) return rc;
+  const SolveWork w{c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, c->part};
+  return dtn_solve_impl(c, rhs, nrhs, dtn_out, mu_out, w);
+}
+
+int dtn_solve_multi_noalloc(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, double* mu_out) {
+  int rc;
+  if ((rc = dtn_solve_check(c, rhs, nrhs, dtn_out))) return rc;
+  if (!c->scratch) return fail(WW_EHIP, "internal: fixed workspace address not resolved");
+  // layout: Psi, Ytmp, Mu, Gam, HG, Gpsi, Rr (Np x nrhs each), then the split-K
+  // partials; the products split K at most as often as the rest of the array allows
+  const size_t blk = (size_t)c->Np * nrhs;
+  const size_t nbuf = 7;
+  if ((nbuf + 1) * blk > WW_SCRATCH_DOUBLES)
+    return fail(WW_EINVAL, "dtn_solve_multi_noalloc: 8 Np nrhs doubles exceed the fixed workspace (" +
+                               std::to_string(WW_SCRATCH_BYTES >> 20) + " MiB); use dtn_solve_multi");
+  double* s = c->scratch;
+  const SolveWork w{s, s + blk, s + 2 * blk, s + 3 * blk, s + 4 * blk, s + 5 * blk, s + 6 * blk, s + nbuf * blk};
+  const int cap = (int)std::min<size_t>((WW_SCRATCH_DOUBLES - nbuf * blk) / blk, (size_t)c->nsplit_max);
+  c->split_cap = cap;
+  rc = dtn_solve_impl(c, rhs, nrhs, dtn_out, mu_out, w);
+  c->split_cap = 0;
+  return rc;
 }
 
 int ww_profile(ww_ctx* c, int enable) {

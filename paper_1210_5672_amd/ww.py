@@ -60,7 +60,7 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
-           "ww_next_fallback"]
+           "dtn_solve_multi_noalloc", "ww_next_fallback"]
 
 
 class WWError(RuntimeError):
@@ -90,6 +90,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ww_set_tableau.argtypes = [P, I, DP, DP, DP]
     lib.dtn_setup.argtypes = [P, P, D, D, I]
     lib.dtn_solve_multi.argtypes = [P, P, I, P, P]
+    lib.dtn_solve_multi_noalloc.argtypes = [P, P, I, P, P]
     lib.ww_next_fallback.argtypes = [U, U, I]
     lib.ww_next_fallback.restype = U
     lib.shoot_setup.argtypes = [P, I, D, D, D, P, P, I]
@@ -109,6 +110,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.ww_last_error.restype = ctypes.c_char_p
     lib.ww_version.restype = ctypes.c_char_p
     for name in ["ww_create", "ww_set_stream", "ww_set_tableau", "dtn_setup", "dtn_solve_multi",
+                 "dtn_solve_multi_noalloc",
                  "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_profile", "ww_profile_read", "ww_fallbacks",
                  "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts"]:
         getattr(lib, name).restype = I
@@ -191,16 +193,19 @@ class Context:
         _check(self.lib.dtn_setup(self.ptr, _ptr(surface), float(h), float(tau), N))
         self.dN = N
 
-    def dtn_solve_multi(self, rhs: torch.Tensor, want_mu: bool = False):
+    def dtn_solve_multi(self, rhs: torch.Tensor, want_mu: bool = False, noalloc: bool = False):
         """rhs: (N, nrhs) column-major -> pass as a (nrhs, N) contiguous tensor transposed.
-        Accepts a (N,) vector or an (N, nrhs) tensor; returns tensors of the same shape."""
+        Accepts a (N,) vector or an (N, nrhs) tensor; returns tensors of the same shape.
+        noalloc=True calls dtn_solve_multi_noalloc (work arrays in the library's fixed
+        per-GPU workspace; the outputs are still allocated here)."""
         vec = rhs.dim() == 1
         cols = rhs.reshape(-1, 1) if vec else rhs
         N, nrhs = cols.shape
         cm = self._keep(cols.t().contiguous())         # column-major storage
         out = torch.empty_like(cm)
         mu = torch.empty_like(cm) if want_mu else None
-        _check(self.lib.dtn_solve_multi(self.ptr, _ptr(cm), nrhs, _ptr(out), _ptr(mu)))
+        fn = self.lib.dtn_solve_multi_noalloc if noalloc else self.lib.dtn_solve_multi
+        _check(fn(self.ptr, _ptr(cm), nrhs, _ptr(out), _ptr(mu)))
         o = out.t()
         m = mu.t() if want_mu else None
         if vec:

@@ -126,3 +126,8 @@ def test_fallback_decision_table():
         assert F(STRICT, 0, st) == 0
         assert F(STRICT | ww.WW_MIXED, 0, st) == 0
 
+
+def test_noalloc_solve_rejects_bad_arguments_without_gpu():
+    ww, lib = _lib()
+    assert lib.dtn_solve_multi_noalloc(None, None, 1, None, None) == -1
+    assert b"null" in lib.ww_last_error()
