@@ -69,12 +69,13 @@ def cpu_baseline(w, nsteps_sample: int):
 
 
 def run(w, nsteps, T, mixed, steps, warmup, profile):
+    """Time `steps` evaluations of shoot_eval after `warmup` ones, without the profiling
+    stamps; then, when asked, one more evaluation with the in-graph timestamp nodes for
+    the phase durations (which the stamps themselves lengthen a little)."""
     import torch
     from paper_1210_5672_amd import ww
     ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
-    if profile:
-        ctx.profile(True)
     params = ww.to_dev(w.params)
     tag = "mixed" if mixed else "fp64"
     first_ms = None
@@ -82,11 +83,9 @@ def run(w, nsteps, T, mixed, steps, warmup, profile):
         torch.cuda.synchronize()
         ta = time.perf_counter()
         ctx.shoot_eval(params, T, nsteps)
-        if i == 0:   # the first call captures and instantiates the step graph
+        if i == 0:   # the first call captures and instantiates the step graphs
             first_ms = 1e3 * (time.perf_counter() - ta)
         print(f"# {tag} warmup {i + 1}/{warmup} done", file=sys.stderr, flush=True)
-    if profile:
-        ctx.profile(True)   # clear the sums: the phases cover the timed steps only
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = None
@@ -100,11 +99,81 @@ def run(w, nsteps, T, mixed, steps, warmup, profile):
     t = time.perf_counter() - t0
     phases = None
     if profile:
-        phases = {"block_lu_ms": ctx.profile_read(0), "base_chain_ms": ctx.profile_read(1),
-                  "column_chain_ms": ctx.profile_read(2)}
+        ctx.profile(True)
+        ctx.shoot_eval(params, T, nsteps)   # captures the graphs with the stamp nodes
+        ctx.profile(True)                   # clear the sums
+        ta = time.perf_counter()
+        ctx.shoot_eval(params, T, nsteps)
+        prof_ms = 1e3 * (time.perf_counter() - ta)
+        lu_ms, lu_n = ctx.profile_stats(0)
+        phases = {"block_lu_ms": lu_ms, "base_chain_ms": ctx.profile_read(1),
+                  "column_chain_ms": ctx.profile_read(2),
+                  "host_enqueue_ms_per_step": ctx.profile_read(3),
+                  # stages factored per LU launch sequence (the lagged march factors
+                  # consecutive stages together)
+                  "lu_stages_per_sequence": nsteps * 12 / lu_n,
+                  "profiled_eval_ms": prof_ms}
+        print(f"# {tag} profiled evaluation done", file=sys.stderr, flush=True)
     timing = {"median_ms": statistics.median(each), "min_ms": min(each), "max_ms": max(each),
               "first_call_ms": first_ms}
     return t, res, phases, timing
+
+
+def oracle_fixture(name):
+    """Stored FP64 oracle results of a workload (tests/golden/<name>_oracle.npz, written by
+    tests/golden/make_oracle_fixtures.py from the CPU oracle), or None."""
+    import numpy as np
+    p = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tests", "golden", f"{name}_oracle.npz")
+    if not os.path.exists(p):
+        return None
+    fx = np.load(p)
+    return fx if "J" in fx.files else None
+
+
+def err_vs_oracle(res, fx):
+    """Relative errors against the stored oracle: r, J (Frobenius, and the largest
+    column error on the column's own norm), dr/dT, f; with the oracle's FP64 rounding
+    floor (largest spread of its alternate roundings) beside each."""
+    import numpy as np
+    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
+    J, Jo = res["J"].cpu().numpy(), fx["J"]
+    r, d = res["r"].cpu().numpy(), res["drdT"].cpu().numpy()
+    out = {"r": rel(r, fx["r"]), "J": rel(J, Jo), "drdT": rel(d, fx["drdT"]),
+           "f": abs(res["f"] - float(fx["f"])) / abs(float(fx["f"]))}
+    if "alt_r" in fx.files:
+        out["floor"] = {"r": float(np.max(fx["alt_r"])), "J": float(np.max(fx["alt_Jfro"])),
+                        "drdT": float(np.max(fx["alt_drdT"])), "f": float(np.max(fx["alt_f"]))}
+    return out
+
+
+def run_adjoint(reps: int = 2):
+    """Differentiation form (the C4 workload: infinite depth, N = 512, 256 parameters,
+    800 steps, checkpoints every 16): time of the gradient by the discrete adjoint
+    (shoot_adjoint: forward march with checkpoints, then the reverse sweep with the
+    segments recomputed) against the time of the forward f alone (shoot_eval without
+    the Jacobian), the ratio the paper discusses for the adjoint method (Sec. 3.2)."""
+    import torch
+    from paper_1210_5672_amd import workloads as W
+    from paper_1210_5672_amd import ww
+    w = W.c4()
+    ctx = ww.Context(n_max=w.N, r_max=w.M + 1)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    p = ww.to_dev(w.params)
+    ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False)
+    ctx.shoot_adjoint(p, w.T, w.nsteps, w.ckpt_every)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False)
+    tf = (time.perf_counter() - t0) / reps
+    print("# adjoint: forward f timed", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        ctx.shoot_adjoint(p, w.T, w.nsteps, w.ckpt_every)
+    tg = (time.perf_counter() - t0) / reps
+    print("# adjoint: gradient timed", file=sys.stderr, flush=True)
+    return {"workload": f"C4: N={w.N}, M={w.M}, nsteps={w.nsteps}, checkpoints every {w.ckpt_every}",
+            "f_ms": 1e3 * tf, "grad_ms": 1e3 * tg, "grad_over_f": tg / tf}
 
 
 def stage_roofline(N, M, nst, stage_ms):
@@ -283,6 +352,7 @@ def main():
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances measurement")
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt measurement")
     ap.add_argument("--no-f-only", action="store_true", help="skip the f-only (GMRES) measurement")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (C4)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -306,13 +376,17 @@ def main():
     n3 = float(w.N) ** 3
     roofline = None
     if phases:
-        # dominant kernel family: the block LU of one stage (k_blu_init, k_blu_step x 15,
-        # k_blu_final); algorithmic work 2/3 N^3 flops per factorisation
+        # dominant kernel family: the block LU (k_blu_init, k_blu_step x 15, k_blu_final,
+        # k_minv), one launch sequence factoring G consecutive stages; algorithmic work
+        # 2/3 N^3 flops per factorisation
         lu_s = phases["block_lu_ms"] * 1e-3
-        ach = (2.0 / 3.0) * n3 / lu_s / 1e12
+        G = phases["lu_stages_per_sequence"]
+        ach = G * (2.0 / 3.0) * n3 / lu_s / 1e12
+        tr = lu_traffic() if w.N == 1024 else None
         roofline = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": ach / FP64_PEAK_TFLOPS, "traffic": lu_traffic() if w.N == 1024 else None,
-                    "kernel": "block LU per stage (k_blu_*), 2/3 N^3 flops per launch sequence",
+                    "frac": ach / FP64_PEAK_TFLOPS, "traffic": tr * G if tr else None,
+                    "kernel": f"block LU launch sequence (k_blu_*, k_minv) factoring {G:g} stages, "
+                              "2/3 N^3 flops per factorisation",
                     "phases_ms": phases}
     out = {
         "metric": "Jacobian column-steps/s at N=1024",
@@ -334,6 +408,9 @@ def main():
         "timing": timing,
         "stage_roofline": stage_roofline(w.N, w.M, 12, timing["median_ms"] / (nsteps * 12)),
     }
+    fx = oracle_fixture("c3") if nsteps == w.nsteps else None
+    if fx is not None:
+        out["err_vs_oracle"] = err_vs_oracle(res, fx)
     if not args.no_mixed:
         import numpy as np
         tm, resm, phm, timm = run(w, nsteps, T, True, args.steps, args.warmup, profile)
@@ -345,9 +422,11 @@ def main():
             "rel_diff_vs_fp64": {"r": float(np.linalg.norm(rm - r64) / np.linalg.norm(r64)),
                                  "J": float(np.linalg.norm(Jm - J64) / np.linalg.norm(J64))},
         }
+        if fx is not None:
+            out["mixed"]["err_vs_oracle"] = err_vs_oracle(resm, fx)
         if phm:
             lu_s = phm["block_lu_ms"] * 1e-3
-            ach = (2.0 / 3.0) * n3 / lu_s / 1e12
+            ach = phm["lu_stages_per_sequence"] * (2.0 / 3.0) * n3 / lu_s / 1e12
             out["mixed"]["roofline"] = {"bound": "mfma", "achieved": ach, "peak": FP32_PEAK_TFLOPS,
                                         "unit": "TFLOP/s", "frac": ach / FP32_PEAK_TFLOPS,
                                         "phases_ms": phm}
@@ -357,6 +436,8 @@ def main():
         out["lm"] = run_lm(with_oracle=not args.no_cpu_baseline)
     if not args.no_f_only:
         out["f_only"] = run_f_only(w, nsteps, T)
+    if not args.no_adjoint:
+        out["adjoint"] = run_adjoint()
     if not args.no_batch:
         out["batch"] = run_batch()
     if args.copy_probe:

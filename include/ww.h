@@ -138,13 +138,12 @@ int dtn_solve_multi(ww_ctx *ctx, const double *rhs, int nrhs, double *dtn_out, d
  * memory -- code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation.  Same arguments, results and errors as dtn_solve_multi (with the factors
  * of the last dtn_setup on the context), but its per-call work arrays (the padded
- * right-hand sides, the intermediate solves, gamma, (1/2) H gamma, the DtN output, the
- * mixed-form residuals and the split-K partials of the products) live in one fixed
- * device array of WW_SCRATCH_BYTES per GPU instead of the context's workspace; the
- * call itself allocates nothing.  Limit: 8 Np nrhs doubles must fit that array (Np = N
- * rounded up to 64; e.g. N = 1024 with nrhs <= 512), else WW_EINVAL; the products
- * split their inner dimension at most as often as the rest of the array allows, so
- * results can differ from dtn_solve_multi by rounding only.  Every call on a GPU uses
+ * right-hand sides, the intermediate solves, gamma, (1/2) H gamma, the DtN output and
+ * the mixed-form residuals) live in one fixed device array of WW_SCRATCH_BYTES per GPU
+ * instead of the context's workspace; the call itself allocates nothing.  Limit:
+ * 7 Np nrhs doubles must fit that array (Np = N rounded up to 64; e.g. N = 1024 with
+ * nrhs <= 585, N = 2048 with nrhs <= 292), else WW_EINVAL.  The results are those of
+ * dtn_solve_multi, bit for bit (the same kernels in the same order).  Every call on a GPU uses
  * that GPU's one array, which keeps the last call's contents: calls that overlap on
  * one GPU (on different streams, or from different threads) race; calls ordered on
  * one stream do not.  The array is held until the process ends.
@@ -171,22 +170,24 @@ int shoot_setup(ww_ctx *ctx, int N, double h, double tau, double g, const double
  *   J    (N x M)  J_ik = phidot_k(alpha_i, T/4) / sqrt(N), or NULL (base only, R = 1)
  *   drdT (N)      dr/dT = phi_t(alpha_i, T/4) / (4 sqrt(N)), or NULL
  *   f    (host)   f = r.r / 2, or NULL
- * Lagged factors (L = 5; environment WW_PIPE_LAG, 0..6, read by ww_create; 0 turns them
- * off): in a march of one instance, the base chain of stage s (the march's critical
- * path) solves with the factors of stage s - L and refines the solution with
+ * Lagged factors (L = 8; environment WW_PIPE_LAG, 0..11, read by ww_create; 0 turns
+ * them off): in a march of one instance, the base chain of stage s (the march's
+ * critical path) solves with the explicit inverse of stage s - L (the first product in
+ * the same launch as the assembly of its own matrix) and refines the solution with
  * the FP64 residual of its own matrix (the same number of sweeps and the same
  * convergence test as WW_MIXED; environment WW_NREF_LAG, 1..8, sets the sweeps of
- * these solves alone), while the LU of its own matrix runs concurrently on one
- * of the context's LU streams (stage s on stream s mod K, K = 3; environment
- * WW_LU_STREAMS, 1..L); the column chain of stage s uses that stage's own factors and
- * runs on the same LU stream after the LU, the column chains in stage order
- * (WW_COLS_ON_LU=0: on a column stream of their own, with K = 2).  Each branch of a
- * stage (spectral prep and assembly; the LU; the lagged base solve to the base
- * right-hand side; the column chain) is a graph of its own, replayed on its stream with
- * the dependencies as events; the step end of the base column runs on the caller's
- * stream, that of the Jacobian columns after the last column chain, and the caller's
- * stream joins the others before the outputs.  The results do not depend on K or on
- * where the column chains run.  A
+ * these solves alone), while its own matrix is factored concurrently: the LUs of G
+ * consecutive stages (G = 2, at most L; environment WW_LU_GROUP, 1..4) share one
+ * launch sequence, on one of the context's LU streams (group g on stream g mod K,
+ * K = 3; environment WW_LU_STREAMS, 1..L).  The column chain of stage s uses that
+ * stage's own factors and runs on the LU stream of its group after the group's LU,
+ * the column chains in stage order (WW_COLS_ON_LU=0: on a column stream of their own,
+ * with K = 2).  Each branch of a stage (spectral prep and assembly; the LU of a group;
+ * the lagged base solve to the base right-hand side; the column chain) is a graph of
+ * its own, replayed on its stream with the dependencies as events; the step end of the
+ * base column runs on the caller's stream, that of the Jacobian columns after the last
+ * column chain, and the caller's stream joins the others before the outputs.  The
+ * results do not depend on K or on where the column chains run.  A
  * failed test (checked after the first step, and at the end) redoes the march with
  * every stage's own factors (WW_FB_DIRECT); the context's later marches then start that
  * way, until the next shoot_setup (not with WW_STRICT, which reports every failure).
@@ -236,13 +237,16 @@ int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int c
 /*
  * Measurement hooks (not part of the method): ww_profile(ctx, 1) adds timestamp nodes
  * (a one-thread kernel reading the GPU's constant-rate wall clock) around three phases
- * of every stage of the step graph -- 0: the block LU of A (factorisation and
- * block-triangular inverses), 1: the whole base chain (spectral prep, assembly, LU,
- * base DtN, base right-hand side), 2: the column chain (the M variational columns) --
- * and clears the accumulated sums (stream-ordered).  ww_profile_read returns in
- * *avg_ms the mean duration of `phase` over every stage of every step replayed since
- * the last ww_profile(ctx, 1), and in *count the number of intervals (synchronises the
- * stream).  Errors: WW_EINVAL (profiling off, nothing replayed yet), WW_EHIP.
+ * of every stage of the step graph -- 0: the block LU of A (a launch sequence, which in
+ * a lagged-factor march factors a group of stages, with the block-triangular inverses
+ * and the explicit inverse), 1: the whole base chain (spectral prep, assembly, base
+ * solve, base DtN, base right-hand side), 2: the column chain (the M variational
+ * columns) -- and clears the accumulated sums (stream-ordered); phase 3 is the host
+ * time spent enqueueing one step (graph launches and event operations).
+ * ww_profile_read returns in *avg_ms the mean duration of `phase` over every interval
+ * since the last ww_profile(ctx, 1) (per step for phase 3), and in *count the number of
+ * intervals (synchronises the stream).  Errors: WW_EINVAL (profiling off, nothing
+ * replayed yet), WW_EHIP.
  */
 int ww_profile(ww_ctx *ctx, int enable);
 int ww_profile_read(ww_ctx *ctx, int phase, double *avg_ms, int *count);

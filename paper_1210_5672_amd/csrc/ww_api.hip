@@ -15,6 +15,7 @@
 #include "ww_gmres.hpp"
 
 #include <algorithm>
+#include <chrono>
 #include <mutex>
 #include <numeric>
 
@@ -52,11 +53,12 @@ static int fail(int code, const std::string& msg) {
 // One stage's factor set of the lagged-factor pipeline (all Np x Np unless noted)
 struct RingSet {
   double *A = nullptr, *Gm = nullptr, *X = nullptr, *Z = nullptr, *V = nullptr, *Dinv = nullptr;
-  double *Xr = nullptr, *Zr = nullptr, *Gmr = nullptr, *Ar = nullptr, *aux = nullptr;
+  double *Mi = nullptr, *Gmr = nullptr, *Ar = nullptr, *aux = nullptr;
   float *A32 = nullptr, *X32 = nullptr, *Z32 = nullptr, *V32 = nullptr, *Dinv32 = nullptr;
-  float *X32r = nullptr, *Z32r = nullptr;
+  float* Mi32 = nullptr;
 };
-#define PIPE_MAXLAG 6
+#define PIPE_MAXLAG 11
+#define PIPE_MAXLUS 6
 
 struct ww_ctx {
   int dev = 0;
@@ -85,10 +87,11 @@ struct ww_ctx {
   double *A_1 = nullptr, *Gm_1 = nullptr, *Xi_1 = nullptr, *Zi_1 = nullptr, *Vi_1 = nullptr, *Dinv_1 = nullptr;
   float *A32_1 = nullptr, *X32_1 = nullptr, *Z32_1 = nullptr, *V32_1 = nullptr, *Dinv32_1 = nullptr;
   double* aux_1 = nullptr;
-  double* part_c = nullptr;    // GEMM partials of the column chain (base chain: part)
-  // row-major copies (per parity) read by the one-vector products of the base chain
-  double *Xr = nullptr, *Zr = nullptr, *Gmr = nullptr, *Xr_1 = nullptr, *Zr_1 = nullptr, *Gmr_1 = nullptr;
-  float *X32r = nullptr, *Z32r = nullptr, *X32r_1 = nullptr, *Z32r_1 = nullptr;
+  // row-major explicit inverses A^{-1} (per parity; FP32 in the mixed form) and
+  // row-major Gm, read by the one-vector products of the base chain and (the inverse)
+  // by the column solves
+  double *Mi = nullptr, *Gmr = nullptr, *Mi_1 = nullptr, *Gmr_1 = nullptr;
+  float *Mi32 = nullptr, *Mi32_1 = nullptr;
   double *Ar = nullptr, *Ar_1 = nullptr;   // mixed mode: FP64 A for the residuals
   hipStream_t side = nullptr;  // column-chain stream
   hipEvent_t evB[16] = {}, evC[16] = {};
@@ -101,8 +104,6 @@ struct ww_ctx {
   double* aux = nullptr;
   double *rhs0 = nullptr, *y0t = nullptr, *mu0 = nullptr, *gam0 = nullptr, *hg0 = nullptr, *gphi0 = nullptr;
   double *Psi = nullptr, *Ytmp = nullptr, *Mu = nullptr, *Gam = nullptr, *HG = nullptr, *Gpsi = nullptr;
-  double* part = nullptr;
-  int nsplit_max = 0;
   double *y = nullptr, *Ys = nullptr, *K = nullptr, *Kx = nullptr, *ydtn = nullptr;
   double *basis = nullptr, *qfix = nullptr;
   double* coef = nullptr;
@@ -121,6 +122,9 @@ struct ww_ctx {
   bool prof = false;
   int prof_stage = -1;   // stage being enqueued (marks are taken only inside a step)
   unsigned long long* stamps = nullptr;   // [phase][stage] x {start, sum, count}
+  // host time spent enqueueing the steps of profiled marches (phase 3), and their count
+  double host_enq_ms = 0.0;
+  long long host_enq_steps = 0;
   // one RK step captured as a graph, replayed nsteps times
   bool use_graph = true;
   bool overlap = true;   // column chain on the side stream (environment WW_NO_OVERLAP=1: one stream)
@@ -137,9 +141,6 @@ struct ww_ctx {
   // for WW_STRICT contexts, which report every failure instead
   bool lag_off = false;
   double guard = 1e-8;
-  // split-K count cap of the products (0: none); set only inside the allocation-free
-  // solve, whose partials must fit the fixed workspace
-  int split_cap = 0;
   double* scratch = nullptr;   // this device's fixed workspace (address resolved at create)
   // partial-pivoting buffers, allocated on the first fallback: row order, elimination
   // workspace (Np x Np), gathered right-hand sides (Np x r_max); the adjoint keeps one
@@ -151,7 +152,10 @@ struct ww_ctx {
   // lagged-factor pipeline of single-instance marches: the base solve of stage s uses
   // the factors of stage s - lag (refined against its own matrix) while the LU of
   // stage s runs on one of `lag` streams; the column chain of stage s waits for it
-  int lag = 5;   // environment WW_PIPE_LAG, 0..PIPE_MAXLAG (0: every solve uses its own factors)
+  int lag = 8;   // environment WW_PIPE_LAG, 0..PIPE_MAXLAG (0: every solve uses its own factors)
+  // stages factored together by one LU launch sequence (environment WW_LU_GROUP,
+  // 1..BLU_GMAX; at most the lag)
+  int lu_group = 2;
   // LU streams (stage s on stream s mod nlus), at most lag; environment WW_LU_STREAMS,
   // by default 3 with the column chains on them, 2 beside the column stream
   int nlus = 3;
@@ -160,7 +164,7 @@ struct ww_ctx {
   bool cols_on_lu = true;
   int ring_n = 0;          // factor sets allocated (one per stage)
   RingSet ring[16];
-  hipStream_t lus[PIPE_MAXLAG] = {};
+  hipStream_t lus[PIPE_MAXLUS] = {};
   hipEvent_t evA[16] = {}, evL[16] = {};
   // one graph per branch and stage of the lagged-factor march (prep, LU, base, columns)
   // and the two halves of the step end (base column: main stream; Jacobian columns:
@@ -304,7 +308,6 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   c->np_max = (n_max + WW_TB - 1) / WW_TB * WW_TB;
   const size_t np = c->np_max, nm = n_max, R = r_max;
   const int nbm = (int)(np / WW_TB);
-  c->nsplit_max = nbm;
   int rc = 0;
 #define AL(ptr, bytes) \
   if ((rc = dalloc(c, (void**)&(ptr), (bytes))) != 0) { ww_destroy(c); return rc; }
@@ -320,17 +323,13 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->Zi_1, np * np * 8);
   AL(c->Vi_1, np * np * 8);
   AL(c->Dinv_1, (size_t)nbm * 4096 * 8);
-  AL(c->Xr, np * np * 8);
-  AL(c->Zr, np * np * 8);
+  AL(c->Mi, np * np * 8);
   AL(c->Gmr, np * np * 8);
-  AL(c->Xr_1, np * np * 8);
-  AL(c->Zr_1, np * np * 8);
+  AL(c->Mi_1, np * np * 8);
   AL(c->Gmr_1, np * np * 8);
   if (flags & WW_MIXED) {
-    AL(c->X32r, np * np * 4);
-    AL(c->Z32r, np * np * 4);
-    AL(c->X32r_1, np * np * 4);
-    AL(c->Z32r_1, np * np * 4);
+    AL(c->Mi32, np * np * 4);
+    AL(c->Mi32_1, np * np * 4);
     AL(c->Ar, np * np * 8);
     AL(c->Ar_1, np * np * 8);
     AL(c->A32, np * np * 4);
@@ -365,8 +364,6 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   AL(c->Gam, np * R * 8);
   AL(c->HG, np * R * 8);
   AL(c->Gpsi, np * R * 8);
-  AL(c->part, (size_t)c->nsplit_max * np * R * 8);
-  AL(c->part_c, (size_t)c->nsplit_max * np * R * 8);
   AL(c->y, 2 * nm * R * 8);
   AL(c->Ys, 2 * nm * R * 8);
   AL(c->K, 16 * 2 * nm * R * 8);
@@ -403,7 +400,9 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->cols_on_lu = !(cl && cl[0] == '0');
     if (!c->cols_on_lu) c->nlus = 2;
     const char* ns = std::getenv("WW_LU_STREAMS");
-    if (ns) c->nlus = std::max(1, std::min(PIPE_MAXLAG, std::atoi(ns)));
+    if (ns) c->nlus = std::max(1, std::min(PIPE_MAXLUS, std::atoi(ns)));
+    const char* lg = std::getenv("WW_LU_GROUP");
+    if (lg) c->lu_group = std::max(1, std::min(BLU_GMAX, std::atoi(lg)));
     // streams: the working ones first, the capture stream (which never executes) last.
     // HIP shares its few hardware queues among a process's streams, each new stream
     // taking the least-used queue: created in this order, the caller's stream and the
@@ -426,11 +425,11 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   CCHK(hipFuncSetAttribute((const void*)k_blu_init<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_blu_step<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_blu_final<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  CCHK(hipFuncSetAttribute((const void*)k_gemm_part<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_minv<double>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_minv<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_blu_init<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_blu_step<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_blu_final<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  CCHK(hipFuncSetAttribute((const void*)k_gemm_part<float>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   {
     // k_gamma holds static LDS too (the folded refinement test): dynamic + static <= big
@@ -440,6 +439,7 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
                              big - (int)fa.sharedSizeBytes));
   }
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_base_dtn, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_col_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_adj_pre, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -466,7 +466,7 @@ void ww_destroy(ww_ctx* c) {
   if (c->seg) (void)hipFree(c->seg);
   if (c->adj) (void)hipFree(c->adj);
   if (c->seg_perm) (void)hipFree(c->seg_perm);
-  for (int i = 0; i < PIPE_MAXLAG; ++i)
+  for (int i = 0; i < PIPE_MAXLUS; ++i)
     if (c->lus[i]) (void)hipStreamDestroy(c->lus[i]);
   for (int i = 0; i < 16; ++i) {
     if (c->evA[i]) (void)hipEventDestroy(c->evA[i]);
@@ -515,15 +515,15 @@ static size_t fft_lds_bytes(int N, int nbuf) { return (size_t)nbuf * N * sizeof(
 static const size_t TILE_BYTES = (size_t)TILE_DBL * 8;
 
 template <typename T>
-static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, T* Xr, T* Zr, double guard) {
+static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, double guard) {
   BluBufs<T> b;
   b.A = A;
   b.X = X;
   b.Z = Z;
   b.V = V;
   b.Dinv = D;
-  b.Xr = Xr;
-  b.Zr = Zr;
+  b.Xr = nullptr;   // the solves use the explicit inverse (k_minv), not row-major factors
+  b.Zr = nullptr;
   b.status = c->status;
   b.Np = c->Np;
   b.pivguard = guard;
@@ -531,19 +531,18 @@ static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, T* Xr, T* Zr
 }
 
 template <typename T>
-static int enqueue_blu(ww_ctx* c, const BluBufs<T>& b) {
+static int enqueue_blu(ww_ctx* c, const BluGroup<T>& g) {
   const int nb = c->Np / WW_TB;
   const size_t es = sizeof(T);
-  hipLaunchKernelGGL(k_blu_init<T>, dim3(1), dim3(WW_NT), (TILE_DBL + GJ_SCR) * es, c->stream, b);
+  hipLaunchKernelGGL(k_blu_init<T>, dim3(g.count), dim3(WW_NT), (TILE_DBL + GJ_SCR) * es, c->stream, g);
   LAUNCHCHK();
   for (int k = 0; k + 1 < nb; ++k) {
-    const int nt = nb - k - 1;
-    const int nblk = nt * nt + 2 * nt * (k + 1);
-    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, b, k);
+    const int nblk = blu_step_tasks(nb, k);
+    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk * g.count), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, g, k);
     LAUNCHCHK();
   }
   if (nb > 1) {
-    hipLaunchKernelGGL(k_blu_final<T>, dim3(nb - 1), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, b);
+    hipLaunchKernelGGL(k_blu_final<T>, dim3((nb - 1) * g.count), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, g);
     LAUNCHCHK();
   }
   return 0;
@@ -574,11 +573,10 @@ struct Fac {
   bool use32;   // mixed precision: factor the FP32 copy and refine the solves
   float *A32, *X32, *Z32, *V32, *Dinv32;
   double* aux;    // per-point base arrays of the stage
-  double* part;   // GEMM split-K partials of the chain that uses this set
-  // row-major copies for the one-vector products (Xr, Zr: FP64 factors; X32r, Z32r:
-  // FP32 factors; Ar: FP64 A for the mixed-mode residuals)
-  double *Xr, *Zr, *Gmr, *Ar;
-  float *X32r, *Z32r;
+  // row-major arrays: Mi = A^{-1} from the FP64 factors, Mi32 from the FP32 factors
+  // (every solve is one product with it), Gm, and the FP64 A of the residuals
+  double *Mi, *Gmr, *Ar;
+  float* Mi32;
   int* perm;   // partial-pivoting row order of this set, or null (no interchanges)
 };
 // factor set of parity `p`; `cols` selects the column chain's GEMM partials
@@ -591,13 +589,10 @@ static Fac fac_set(ww_ctx* c, int p, bool cols) {
     F = Fac{c->A_1, c->Gm_1, c->Xi_1, c->Zi_1, c->Vi_1, c->Dinv_1, use32(c), c->A32_1, c->X32_1, c->Z32_1, c->V32_1,
             c->Dinv32_1, c->aux_1, nullptr};
   }
-  F.part = cols ? c->part_c : c->part;
-  F.Xr = p ? c->Xr_1 : c->Xr;
-  F.Zr = p ? c->Zr_1 : c->Zr;
+  F.Mi = p ? c->Mi_1 : c->Mi;
   F.Gmr = p ? c->Gmr_1 : c->Gmr;
   F.Ar = p ? c->Ar_1 : c->Ar;
-  F.X32r = p ? c->X32r_1 : c->X32r;
-  F.Z32r = p ? c->Z32r_1 : c->Z32r;
+  F.Mi32 = p ? c->Mi32_1 : c->Mi32;
   F.perm = pivoted(c) ? c->perm : nullptr;
   return F;
 }
@@ -642,29 +637,65 @@ static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 
 // assembly of A, Gm (and the row-major FP64 copy Ar when the solves refine: mixed
 // mode, or lagged factors)
-static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar) {
+// The lagged inverse Fo (optional): the same launch forms x0 = Fo.Mi psi (the first
+// solve of a lagged-factor base chain) in 16 more rows of workgroups.
+static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar, const Fac* Fo = nullptr,
+                            const double* psi = nullptr, double* x0 = nullptr) {
   const int nb = c->Np / WW_TB;
-  hipLaunchKernelGGL(k_assemble, dim3(nb, c->Np / ASM_CW), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT,
-                     c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, (F.use32 || want_ar) ? F.Ar : nullptr, c->N,
-                     c->Np, c->finite);
+  const double* mx64 = (Fo && !Fo->use32) ? Fo->Mi : nullptr;
+  const float* mx32 = (Fo && Fo->use32) ? Fo->Mi32 : nullptr;
+  if (Fo && !(mx64 || mx32)) return fail(WW_EHIP, "internal: lagged first solve without its inverse");
+  const int gy = c->Np / ASM_CW + (Fo ? 16 : 0);
+  hipLaunchKernelGGL(k_assemble, dim3(nb, gy), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT, c->c0T,
+                     F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, (F.use32 || want_ar) ? F.Ar : nullptr, c->N, c->Np,
+                     c->finite, mx64, mx32, psi, x0);
   LAUNCHCHK();
   return 0;
 }
 
 // block LU of A (FP64, or of the FP32 copy in mixed mode) with the block-triangular
-// inverses; with a row order, first the partial-pivoting order and A := P A
-static int enqueue_lu(ww_ctx* c, const Fac& F) {
+// inverses and the explicit inverse Mi = Z (I + X); with a row order, first the
+// partial-pivoting order and A := P A.  A group (count > 1: consecutive stages of a
+// lagged-factor march, never pivoted) shares every launch of the sequence.
+static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
   int rc;
+  if (count < 1 || count > BLU_GMAX) return fail(WW_EHIP, "internal: LU group size");
   if ((rc = prof_mark(c, 0, 0))) return rc;
-  if (F.perm && (rc = enqueue_pivot_order(c, F))) return rc;
-  if (F.use32)
-    rc = enqueue_blu<float>(c, blu_bufs<float>(c, F.A32, F.X32, F.Z32, F.V32, F.Dinv32, F.X32r, F.Z32r, c->guard));
-  else
-    rc = enqueue_blu<double>(
-        c, blu_bufs<double>(c, F.A, F.X, F.Z, F.V, F.Dinv, F.Xr, F.Zr, F.perm ? PIVOTED_GUARD : c->guard));
-  if (rc) return rc;
+  if (count == 1 && F[0].perm && (rc = enqueue_pivot_order(c, F[0]))) return rc;
+  const int nb = c->Np / WW_TB;
+  if (F[0].use32) {
+    BluGroup<float> g{};
+    MinvGroup<float> mg{};
+    for (int q = 0; q < count; ++q) {
+      if (!F[q].Mi32) return fail(WW_EHIP, "internal: LU without its inverse buffer");
+      g.m[q] = blu_bufs<float>(c, F[q].A32, F[q].X32, F[q].Z32, F[q].V32, F[q].Dinv32, c->guard);
+      mg.Z[q] = F[q].Z32;
+      mg.X[q] = F[q].X32;
+      mg.Mr[q] = F[q].Mi32;
+    }
+    g.count = count;
+    if ((rc = enqueue_blu<float>(c, g))) return rc;
+    hipLaunchKernelGGL(k_minv<float>, dim3(nb, nb, count), dim3(WW_NT), 2 * TILE_DBL * sizeof(float), c->stream, mg,
+                       c->Np);
+  } else {
+    BluGroup<double> g{};
+    MinvGroup<double> mg{};
+    for (int q = 0; q < count; ++q) {
+      if (!F[q].Mi) return fail(WW_EHIP, "internal: LU without its inverse buffer");
+      g.m[q] = blu_bufs<double>(c, F[q].A, F[q].X, F[q].Z, F[q].V, F[q].Dinv, F[q].perm ? PIVOTED_GUARD : c->guard);
+      mg.Z[q] = F[q].Z;
+      mg.X[q] = F[q].X;
+      mg.Mr[q] = F[q].Mi;
+    }
+    g.count = count;
+    if ((rc = enqueue_blu<double>(c, g))) return rc;
+    hipLaunchKernelGGL(k_minv<double>, dim3(nb, nb, count), dim3(WW_NT), 2 * TILE_DBL * sizeof(double), c->stream,
+                       mg, c->Np);
+  }
+  LAUNCHCHK();
   return prof_mark(c, 0, 1);
 }
+static int enqueue_lu(ww_ctx* c, const Fac& F) { return enqueue_lu_group(c, &F, 1); }
 
 static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   int rc;
@@ -672,33 +703,23 @@ static int enqueue_assemble_lu(ww_ctx* c, const Fac& F) {
   return enqueue_lu(c, F);
 }
 
-// out = add + sgn * M B for R columns (ld Np), M taken as full (mode 0), strictly lower
-// (mode 1) or upper (mode 2) in 64-blocks.  Split-K partials, then a reduction; one
-// column (R = 1) uses the row-major copy Mr, one wave per row.
+// out = add + sgn * M B for R columns (ld Np) with the row-major M (element type T).
+// One column: one wave per row (mode: the 64-block range, 0 all, 1 strictly lower, 2
+// upper with the diagonal); several: 32 x 32 output tiles over the whole inner
+// dimension (the full matrix).
 template <typename T>
-static int enqueue_gemm(ww_ctx* c, double* part, const T* M, const T* Mr, int mode, const double* B,
-                        const double* add, double sgn, double* out, int R) {
-  const int nkt = c->Np / WW_TB;
-  if (!(R == 1 && Mr) && (!part || !M)) return fail(WW_EHIP, "internal: product without its matrix or partials");
-  if (R == 1 && Mr) {
+static int enqueue_gemm(ww_ctx* c, const T* Mr, int mode, const double* B, const double* add, double sgn,
+                        double* out, int R) {
+  if (!Mr) return fail(WW_EHIP, "internal: product without its matrix");
+  if (R == 1) {
     hipLaunchKernelGGL(k_gemv_row<T>, dim3(c->Np * 64 / WW_NT), dim3(WW_NT), 0, c->stream, Mr, c->Np, mode, B, add,
                        sgn, out);
     LAUNCHCHK();
     return 0;
   }
-  const int tiles = nkt * ((R + 63) / 64);
-  int nsplit = (512 + tiles - 1) / tiles;
-  if (nsplit > nkt) nsplit = nkt;
-  if (c->split_cap > 0 && nsplit > c->split_cap) nsplit = c->split_cap;
-  if (nsplit < 1) nsplit = 1;
-  const int kchunk = (nkt + nsplit - 1) / nsplit;
-  nsplit = (nkt + kchunk - 1) / kchunk;
-  hipLaunchKernelGGL(k_gemm_part<T>, dim3(nkt, (R + 63) / 64, nsplit), dim3(WW_NT), 2 * TILE_DBL * sizeof(T),
-                     c->stream, M, c->Np, mode, B, R, part, kchunk);
-  LAUNCHCHK();
-  const size_t n = (size_t)c->Np * R;
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 2048);
-  hipLaunchKernelGGL(k_gemm_reduce, dim3(blocks), dim3(256), 0, c->stream, part, nsplit, add, sgn, out, c->Np, R);
+  if (mode & 3) return fail(WW_EHIP, "internal: triangular product of several columns");
+  hipLaunchKernelGGL(k_gemm_rm<T>, dim3(c->Np / GT, (R + GT - 1) / GT), dim3(GEMM_NT), 0, c->stream, Mr, c->Np, B, R,
+                     add, sgn, out);
   LAUNCHCHK();
   return 0;
 }
@@ -708,46 +729,13 @@ static int enqueue_gemm(ww_ctx* c, double* part, const T* M, const T* Mr, int mo
 // solution's relative error is then at most about cond(A) * 2^-43.
 static const double REFINE_TOL = 1.1368683772161603e-13;
 
-// X = A^{-1} B for R columns (ld Np); Y and Rs are scratch; B is kept.
-// FP64:  X = Z (B + Xs B).
-// mixed: X = Z32 (B + X32 B), then nref sweeps of  r = B - A X (FP64 residual with the
-//        FP64 matrix),  X += Z32 (r + X32 r)  (FP32 factors, FP64 accumulation).
-// Lagged factors (one vector): the factors of F are those of an earlier stage and Fa
-// holds this stage's matrix (row-major Ar): X = Z (B + Xs B), nref sweeps of
-// r = B - A X, X += Z (r + Xs r), and the same convergence test as the mixed form.
-// check: launch the convergence test here (false: the caller folds it into k_gamma)
-static int enqueue_solve_lagged(ww_ctx* c, const Fac& F, const Fac& Fa, double* B, double* Y, double* X, double* Rs,
-                                bool check) {
-  if (!Fa.Ar || !(F.use32 ? (F.X32r && F.Z32r) : (F.Xr && F.Zr)))
-    return fail(WW_EHIP, "internal: lagged solve without row-major operands");
-  int rc;
-  if (F.use32) {
-    if ((rc = enqueue_gemm<float>(c, nullptr, F.X32, F.X32r, 1, B, B, 1.0, Y, 1))) return rc;
-    if ((rc = enqueue_gemm<float>(c, nullptr, F.Z32, F.Z32r, 2, Y, nullptr, 1.0, X, 1))) return rc;
-  } else {
-    if ((rc = enqueue_gemm<double>(c, nullptr, F.X, F.Xr, 1, B, B, 1.0, Y, 1))) return rc;
-    if ((rc = enqueue_gemm<double>(c, nullptr, F.Z, F.Zr, 2, Y, nullptr, 1.0, X, 1))) return rc;
-  }
-  const int nref = c->nref_lag >= 0 ? c->nref_lag : c->nref;
-  for (int it = 0; it <= nref; ++it) {
-    if ((rc = enqueue_gemm<double>(c, nullptr, Fa.A, Fa.Ar, 0, X, B, -1.0, Rs, 1))) return rc;
-    if (it == nref) break;   // the last residual is the convergence test's
-    if (F.use32) {
-      if ((rc = enqueue_gemm<float>(c, nullptr, F.X32, F.X32r, 1, Rs, Rs, 1.0, Y, 1))) return rc;
-      if ((rc = enqueue_gemm<float>(c, nullptr, F.Z32, F.Z32r, 2, Y, X, 1.0, X, 1))) return rc;
-    } else {
-      if ((rc = enqueue_gemm<double>(c, nullptr, F.X, F.Xr, 1, Rs, Rs, 1.0, Y, 1))) return rc;
-      if ((rc = enqueue_gemm<double>(c, nullptr, F.Z, F.Zr, 2, Y, X, 1.0, X, 1))) return rc;
-    }
-  }
-  if (!check) return 0;
-  hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(WW_NT), 0, c->stream, Rs, B, c->Np, c->N, REFINE_TOL, c->status,
-                     32);
-  LAUNCHCHK();
-  return 0;
-}
-
+// X = A^{-1} B for R columns (ld Np); Rs is scratch; B is kept.  Mi is the explicit
+// inverse Z (I + X) of the block LU (row-major).
+// FP64:  X = Mi B.
+// mixed: X = Mi32 B, then nref sweeps of  r = B - A X (FP64 residual with the FP64
+//        matrix),  X += Mi32 r  (FP32 inverse, FP64 accumulation).
 static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* X, double* Rs, int R) {
+  (void)Y;
   int rc;
   if (F.perm) {   // P A = Lt Ut: solve with P B
     const size_t n = (size_t)c->Np * R;
@@ -756,20 +744,15 @@ static int enqueue_solve(ww_ctx* c, const Fac& F, double* B, double* Y, double* 
     LAUNCHCHK();
     B = c->pb;
   }
-  if (!F.use32) {
-    if ((rc = enqueue_gemm<double>(c, F.part, F.X, F.Xr, 1, B, B, 1.0, Y, R))) return rc;
-    return enqueue_gemm<double>(c, F.part, F.Z, F.Zr, 2, Y, nullptr, 1.0, X, R);
-  }
-  if ((rc = enqueue_gemm<float>(c, F.part, F.X32, F.X32r, 1, B, B, 1.0, Y, R))) return rc;
-  if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, F.Z32r, 2, Y, nullptr, 1.0, X, R))) return rc;
+  if (!F.use32) return enqueue_gemm<double>(c, F.Mi, 0, B, nullptr, 1.0, X, R);
+  if ((rc = enqueue_gemm<float>(c, F.Mi32, 0, B, nullptr, 1.0, X, R))) return rc;
   for (int it = 0; it < c->nref; ++it) {
-    if ((rc = enqueue_gemm<double>(c, F.part, F.A, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
-    if ((rc = enqueue_gemm<float>(c, F.part, F.X32, F.X32r, 1, Rs, Rs, 1.0, Y, R))) return rc;
-    if ((rc = enqueue_gemm<float>(c, F.part, F.Z32, F.Z32r, 2, Y, X, 1.0, X, R))) return rc;
+    if ((rc = enqueue_gemm<double>(c, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
+    if ((rc = enqueue_gemm<float>(c, F.Mi32, 0, Rs, X, 1.0, X, R))) return rc;
   }
   {
     // convergence test on the FP64 residual of the final solution (also with no sweep)
-    if ((rc = enqueue_gemm<double>(c, F.part, F.A, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
+    if ((rc = enqueue_gemm<double>(c, F.Ar, 0, X, B, -1.0, Rs, R))) return rc;
     hipLaunchKernelGGL(k_refine_check, dim3(R), dim3(WW_NT), 0, c->stream, Rs, B, c->Np, c->N, REFINE_TOL,
                        c->status, 4);
     LAUNCHCHK();
@@ -785,7 +768,7 @@ static int enqueue_dtn_cols(ww_ctx* c, const Fac& F, double* B, double* Yt, doub
   hipLaunchKernelGGL(k_gamma, dim3((R + 1) / 2), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Mu, c->Np, R, Gam,
                      HGm, c->tw, c->N, nullptr, nullptr, 0.0, nullptr, 0);
   LAUNCHCHK();
-  return enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, Gam, HGm, 1.0, out, R);
+  return enqueue_gemm<double>(c, F.Gmr, 0, Gam, HGm, 1.0, out, R);
 }
 
 static size_t kstride(const ww_ctx* c) { return (size_t)2 * c->N * (c->M + 1); }
@@ -841,7 +824,7 @@ static int enqueue_gmres(ww_ctx* c, const Fac& F, double* psi, double* mu, doubl
   hipLaunchKernelGGL(k_gm_finish, dim3(1), dim3(GM_NT), 0, c->stream, b, mu);
   LAUNCHCHK();
   int rc;
-  if ((rc = enqueue_gemm<double>(c, nullptr, F.A, F.Ar, 0, mu, psi, -1.0, rs, 1))) return rc;
+  if ((rc = enqueue_gemm<double>(c, F.Ar, 0, mu, psi, -1.0, rs, 1))) return rc;
   hipLaunchKernelGGL(k_refine_check, dim3(1), dim3(WW_NT), 0, c->stream, rs, psi, c->Np, c->N, REFINE_TOL, c->status,
                      64);
   LAUNCHCHK();
@@ -890,13 +873,14 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
     hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->mu0, c->Np, 1, c->gam0,
                        c->hg0, c->tw, c->N, nullptr, nullptr, 0.0, nullptr, 0);
     LAUNCHCHK();
-    if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
+    if ((rc = enqueue_gemm<double>(c, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
   } else {
     if ((rc = enqueue_assemble_lu(c, F))) return rc;
     if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
   }
   hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
-                     c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+                     c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
+                     c->tau);
   LAUNCHCHK();
   return prof_mark(c, 1, 1);
 }
@@ -932,7 +916,13 @@ static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
 // a march without columns keeps to two LU streams: they carry its LUs, and a third
 // concurrent LU only slows its base chain
 static int lu_count(const ww_ctx* c) { return std::min(c->pcols ? c->nlus : std::min(c->nlus, 2), c->lag); }
-static hipStream_t lu_stream(const ww_ctx* c, int s) { return c->lus[s % lu_count(c)]; }
+// LU groups: consecutive stages g G .. g G + G - 1 (the last group of a step may be
+// shorter) are factored by one launch sequence, on LU stream g mod (LU streams); the
+// group is at most the lag, so that a base solve never waits for its own group
+static int lu_group(const ww_ctx* c) { return std::max(1, std::min(c->lu_group, c->lag)); }
+static int grp_first(const ww_ctx* c, int s) { return s / lu_group(c) * lu_group(c); }
+static int grp_last(const ww_ctx* c, int s) { return std::min(c->nst, grp_first(c, s) + lu_group(c)) - 1; }
+static hipStream_t lu_stream(const ww_ctx* c, int s) { return c->lus[(s / lu_group(c)) % lu_count(c)]; }
 
 static int ensure_pipe(ww_ctx* c) {
   int rc;
@@ -947,13 +937,13 @@ static int ensure_pipe(ww_ctx* c) {
   const size_t nbm = np / WW_TB;
   while (c->ring_n < c->nst) {
     RingSet& r = c->ring[c->ring_n];
-    double** d[] = {&r.A, &r.Gm, &r.X, &r.Z, &r.V, &r.Xr, &r.Zr, &r.Gmr, &r.Ar};
+    double** d[] = {&r.A, &r.Gm, &r.X, &r.Z, &r.V, &r.Mi, &r.Gmr, &r.Ar};
     for (double** q : d)
       if ((rc = dalloc(c, (void**)q, nn * 8))) return rc;
     if ((rc = dalloc(c, (void**)&r.Dinv, nbm * 4096 * 8))) return rc;
     if ((rc = dalloc(c, (void**)&r.aux, (size_t)AUX_COUNT * c->n_max * 8))) return rc;
     if (mixed(c)) {
-      float** f[] = {&r.A32, &r.X32, &r.Z32, &r.V32, &r.X32r, &r.Z32r};
+      float** f[] = {&r.A32, &r.X32, &r.Z32, &r.V32, &r.Mi32};
       for (float** q : f)
         if ((rc = dalloc(c, (void**)q, nn * 4))) return rc;
       if ((rc = dalloc(c, (void**)&r.Dinv32, nbm * 4096 * 4))) return rc;
@@ -966,13 +956,10 @@ static int ensure_pipe(ww_ctx* c) {
 static Fac pipe_set(ww_ctx* c, int s, bool cols) {
   const RingSet& r = c->ring[s];
   Fac F = Fac{r.A, r.Gm, r.X, r.Z, r.V, r.Dinv, use32(c), r.A32, r.X32, r.Z32, r.V32, r.Dinv32, r.aux, nullptr};
-  F.part = cols ? c->part_c : c->part;
-  F.Xr = r.Xr;
-  F.Zr = r.Zr;
+  F.Mi = r.Mi;
   F.Gmr = r.Gmr;
   F.Ar = r.Ar;
-  F.X32r = r.X32r;
-  F.Z32r = r.Z32r;
+  F.Mi32 = r.Mi32;
   F.perm = nullptr;
   return F;
 }
@@ -991,13 +978,10 @@ static int pipe_prologue(ww_ctx* c) {
   const size_t nn = (size_t)c->Np * c->Np;
   for (int q = nst - L + 1; q < nst; ++q) {
     const RingSet &a = c->ring[nst - L], &b = c->ring[q];
-    if (use32(c)) {
-      HIPCHK(hipMemcpyAsync(b.X32r, a.X32r, nn * 4, hipMemcpyDeviceToDevice, c->stream));
-      HIPCHK(hipMemcpyAsync(b.Z32r, a.Z32r, nn * 4, hipMemcpyDeviceToDevice, c->stream));
-    } else {
-      HIPCHK(hipMemcpyAsync(b.Xr, a.Xr, nn * 8, hipMemcpyDeviceToDevice, c->stream));
-      HIPCHK(hipMemcpyAsync(b.Zr, a.Zr, nn * 8, hipMemcpyDeviceToDevice, c->stream));
-    }
+    if (use32(c))
+      HIPCHK(hipMemcpyAsync(b.Mi32, a.Mi32, nn * 4, hipMemcpyDeviceToDevice, c->stream));
+    else
+      HIPCHK(hipMemcpyAsync(b.Mi, a.Mi, nn * 8, hipMemcpyDeviceToDevice, c->stream));
   }
   // the first step of the per-branch graphs waits, at stage s, for the column chain of
   // stage s and the LU of stage s - lag of the step before: here, for this prologue
@@ -1018,23 +1002,42 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
   const int nst = c->nst, L = c->lag;
   const Fac F = pipe_set(c, s, false);
   int rc = 0;
+  const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);   // the lagged factor set
   if (part == PP_PREP) {
+    // spectral prep; assembly, and in the same launch the first lagged solve
+    // x0 = Mi_old psi, which does not need this stage's matrix
     if ((rc = prof_mark(c, 1, 0))) return rc;
     hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys, c->coef,
                        s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
     LAUNCHCHK();
-    return enqueue_assemble(c, F, true);
+    return enqueue_assemble(c, F, true, &Fo, c->rhs0, c->mu0);
   }
-  if (part == PP_LU) return enqueue_lu(c, F);
+  if (part == PP_LU) {
+    // the group that ends at this stage (stages of a group are never pivoted)
+    if (s != grp_last(c, s)) return 0;
+    const int f = grp_first(c, s);
+    Fac Fs[BLU_GMAX];
+    for (int q = f; q <= s; ++q) Fs[q - f] = pipe_set(c, q, false);
+    return enqueue_lu_group(c, Fs, s - f + 1);
+  }
   if (part == PP_BASE) {
-    const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
-    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0, false))) return rc;
-    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->mu0, c->Np, 1, c->gam0,
-                       c->hg0, c->tw, c->N, c->rr0, c->rhs0, REFINE_TOL, c->status, 32);
+    // refinement sweeps against this stage's matrix: r = psi - A x, x += Mi_old r
+    const int nref = c->nref_lag >= 0 ? c->nref_lag : c->nref;
+    for (int it = 0; it < nref; ++it) {
+      if ((rc = enqueue_gemm<double>(c, F.Ar, 0, c->mu0, c->rhs0, -1.0, c->rr0, 1))) return rc;
+      rc = Fo.use32 ? enqueue_gemm<float>(c, Fo.Mi32, 0, c->rr0, c->mu0, 1.0, c->mu0, 1)
+                    : enqueue_gemm<double>(c, Fo.Mi, 0, c->rr0, c->mu0, 1.0, c->mu0, 1);
+      if (rc) return rc;
+    }
+    // gamma, (1/2) H gamma, G phi and the residual of the convergence test in one
+    // launch; the test's decision is taken at the start of k_base_rhs
+    unsigned long long* chk = (unsigned long long*)(c->status + 4);
+    hipLaunchKernelGGL(k_base_dtn, dim3((c->Np + DTN_ROWS - 1) / DTN_ROWS), dim3(WW_NT), fft_lds_bytes(c->N, 4),
+                       c->stream, c->mu0, c->rhs0, F.Gmr, F.Ar, c->Np, c->tw, c->N, c->gphi0, chk);
     LAUNCHCHK();
-    if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) return rc;
     hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
-                       c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
+                       c->n_max, c->K + (size_t)s * kstride(c), chk, REFINE_TOL, c->status, c->tw, c->sig, c->N,
+                       c->g, c->tau);
     LAUNCHCHK();
     return prof_mark(c, 1, 1);
   }
@@ -1075,7 +1078,8 @@ static int capture_part(ww_ctx* c, int s, int part, hipGraphExec_t* out) {
 }
 
 static long long pipe_key(const ww_ctx* c) {
-  return (((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 8 + c->lag) * 2 + (c->prof ? 1 : 0)) * 16 + c->fb;
+  return ((((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 16 + c->lag) * 8 + lu_group(c)) * 2 + (c->prof ? 1 : 0)) *
+             16 + c->fb;
 }
 
 static int ensure_pipe_graphs(ww_ctx* c) {
@@ -1107,8 +1111,11 @@ static int ensure_pipe_graphs(ww_ctx* c) {
     }
   c->pkey = -1;
   for (int s = 0; s < c->nst; ++s)
-    for (int q = 0; q < 4; ++q)
-      if ((q != PP_COL || c->pcols) && (rc = capture_part(c, s, q, &c->pgx[s][q]))) return rc;
+    for (int q = 0; q < 4; ++q) {
+      if (q == PP_COL && !c->pcols) continue;
+      if (q == PP_LU && s != grp_last(c, s)) continue;   // one LU graph per group
+      if ((rc = capture_part(c, s, q, &c->pgx[s][q]))) return rc;
+    }
   if ((rc = capture_part(c, 0, -1, &c->pgend))) return rc;
   if (c->pcols && (rc = capture_part(c, 0, -2, &c->pgendc))) return rc;
   c->pkey = pipe_key(c);
@@ -1125,39 +1132,58 @@ static int ensure_pipe_graphs(ww_ctx* c) {
 // and the base solve of stage s < lag reads the factors of the LU of stage
 // s - lag + nst of the step before.  The main stream joins the other streams
 // (pipe_join) before the march's outputs are read.
-static int pipe_step(ww_ctx* c) {
+static int pipe_launch(ww_ctx* c, int s, int part, hipStream_t st, bool graphed) {
+  if (graphed) {
+    HIPCHK(hipGraphLaunch(part < 0 ? (part == -1 ? c->pgend : c->pgendc) : c->pgx[s][part], st));
+    return 0;
+  }
+  hipStream_t user = c->stream;
+  c->stream = st;
+  c->prof_stage = part < 0 ? -1 : s;
+  const int rc = part < 0 ? enqueue_pipe_end(c, part == -2) : enqueue_pipe_part(c, s, part);
+  c->prof_stage = -1;
+  c->stream = user;
+  return rc;
+}
+
+static int pipe_step(ww_ctx* c, bool graphed) {
   const int nst = c->nst, L = c->lag;
   hipStream_t s0 = c->stream;
+  int rc;
   for (int s = 0; s < nst; ++s) {
     hipStream_t ls = lu_stream(c, s);
+    const bool last = s == grp_last(c, s);
     HIPCHK(hipStreamWaitEvent(s0, c->pcols ? c->evC[s] : c->evL[s], 0));
-    HIPCHK(hipGraphLaunch(c->pgx[s][PP_PREP], s0));
-    HIPCHK(hipEventRecord(c->evA[s], s0));
-    HIPCHK(hipStreamWaitEvent(ls, c->evA[s], 0));
-    HIPCHK(hipGraphLaunch(c->pgx[s][PP_LU], ls));
-    HIPCHK(hipEventRecord(c->evL[s], ls));
+    // the prep part already applies the lagged inverse (the first solve)
     HIPCHK(hipStreamWaitEvent(s0, c->evL[(s - L + nst) % nst], 0));
-    HIPCHK(hipGraphLaunch(c->pgx[s][PP_BASE], s0));
+    if ((rc = pipe_launch(c, s, PP_PREP, s0, graphed))) return rc;
+    if (last) {
+      // the LU group of stages grp_first .. s, once the last of them is assembled
+      HIPCHK(hipEventRecord(c->evA[s], s0));
+      HIPCHK(hipStreamWaitEvent(ls, c->evA[s], 0));
+      if ((rc = pipe_launch(c, s, PP_LU, ls, graphed))) return rc;
+      for (int q = grp_first(c, s); q <= s; ++q) HIPCHK(hipEventRecord(c->evL[q], ls));
+    }
+    if ((rc = pipe_launch(c, s, PP_BASE, s0, graphed))) return rc;
     if (!c->pcols) continue;
     HIPCHK(hipEventRecord(c->evB[s], s0));
-    if (c->cols_on_lu) {
-      // after its own LU (same stream), the base chain of its stage, and the column
-      // chain before it (stage order; the first waits for the last step's column end)
-      HIPCHK(hipStreamWaitEvent(ls, c->evB[s], 0));
-      HIPCHK(hipStreamWaitEvent(ls, s == 0 ? c->evE : c->evC[s - 1], 0));
-      HIPCHK(hipGraphLaunch(c->pgx[s][PP_COL], ls));
-      HIPCHK(hipEventRecord(c->evC[s], ls));
-      continue;
+    if (!last) continue;
+    // the column chains of the group, after its LU, each after the base chain of its
+    // stage and the column chain before it (stage order; the first of a step waits
+    // for the last step's Jacobian step end)
+    for (int q = grp_first(c, s); q <= s; ++q) {
+      hipStream_t cs = c->cols_on_lu ? ls : c->side;
+      if (!c->cols_on_lu) HIPCHK(hipStreamWaitEvent(cs, c->evL[q], 0));
+      HIPCHK(hipStreamWaitEvent(cs, c->evB[q], 0));
+      HIPCHK(hipStreamWaitEvent(cs, q == 0 ? c->evE : c->evC[q - 1], 0));
+      if ((rc = pipe_launch(c, q, PP_COL, cs, graphed))) return rc;
+      HIPCHK(hipEventRecord(c->evC[q], cs));
     }
-    HIPCHK(hipStreamWaitEvent(c->side, c->evB[s], 0));
-    HIPCHK(hipStreamWaitEvent(c->side, c->evL[s], 0));
-    HIPCHK(hipGraphLaunch(c->pgx[s][PP_COL], c->side));
-    HIPCHK(hipEventRecord(c->evC[s], c->side));
   }
-  HIPCHK(hipGraphLaunch(c->pgend, s0));
+  if ((rc = pipe_launch(c, 0, -1, s0, graphed))) return rc;
   if (c->pcols) {
     hipStream_t cs = c->cols_on_lu ? lu_stream(c, nst - 1) : c->side;   // after the last column chain
-    HIPCHK(hipGraphLaunch(c->pgendc, cs));
+    if ((rc = pipe_launch(c, 0, -2, cs, graphed))) return rc;
     HIPCHK(hipEventRecord(c->evE, cs));
   }
   c->pjoin = true;
@@ -1178,89 +1204,11 @@ static int pipe_join(ww_ctx* c) {
   return 0;
 }
 
-static int enqueue_step_pipe(ww_ctx* c) {
-  int rc = 0;
-  const int nst = c->nst, L = c->lag;
-  hipStream_t s0 = c->stream;
-  for (int s = 0; s < nst && !rc; ++s) {
-    c->prof_stage = s;
-    const Fac F = pipe_set(c, s, false);
-    const Fac Fo = pipe_set(c, (s - L + nst) % nst, false);
-    hipStream_t ls = lu_stream(c, s);
-    if ((rc = prof_mark(c, 1, 0))) break;
-    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->y, c->K, c->Ys, c->coef, s,
-                       kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
-    if (hipGetLastError() != hipSuccess) {
-      rc = fail(WW_EHIP, "kernel launch: k_base_prep");
-      break;
-    }
-    if ((rc = enqueue_assemble(c, F, true))) break;
-    // the LU of this stage on its stream
-    if (hipEventRecord(c->evA[s], s0) != hipSuccess || hipStreamWaitEvent(ls, c->evA[s], 0) != hipSuccess) {
-      rc = fail(WW_EHIP, "pipeline: event record / wait");
-      break;
-    }
-    c->stream = ls;
-    rc = enqueue_lu(c, F);
-    c->stream = s0;
-    if (rc) break;
-    if (hipEventRecord(c->evL[s], ls) != hipSuccess) {
-      rc = fail(WW_EHIP, "pipeline: event record");
-      break;
-    }
-    // base solve with the factors of stage s - L (of the previous step for s < L)
-    if (s >= L && hipStreamWaitEvent(s0, c->evL[s - L], 0) != hipSuccess) {
-      rc = fail(WW_EHIP, "pipeline: event wait");
-      break;
-    }
-    if ((rc = enqueue_solve_lagged(c, Fo, F, c->rhs0, c->y0t, c->mu0, c->rr0, false))) break;
-    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->mu0, c->Np, 1, c->gam0, c->hg0,
-                       c->tw, c->N, c->rr0, c->rhs0, REFINE_TOL, c->status, 32);
-    if (hipGetLastError() != hipSuccess) {
-      rc = fail(WW_EHIP, "kernel launch: k_gamma");
-      break;
-    }
-    if ((rc = enqueue_gemm<double>(c, F.part, F.Gm, F.Gmr, 0, c->gam0, c->hg0, 1.0, c->gphi0, 1))) break;
-    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), s0, c->Ys, c->gphi0, F.aux, c->n_max,
-                       c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
-    if (hipGetLastError() != hipSuccess) {
-      rc = fail(WW_EHIP, "kernel launch: k_base_rhs");
-      break;
-    }
-    if ((rc = prof_mark(c, 1, 1))) break;
-    if (!c->pcols) continue;
-    // the column chain with this stage's own factors
-    if (hipEventRecord(c->evB[s], s0) != hipSuccess || hipStreamWaitEvent(c->side, c->evB[s], 0) != hipSuccess ||
-        hipStreamWaitEvent(c->side, c->evL[s], 0) != hipSuccess) {
-      rc = fail(WW_EHIP, "pipeline: event record / wait");
-      break;
-    }
-    c->stream = c->side;
-    rc = enqueue_col_chain(c, s, pipe_set(c, s, true));
-    c->stream = s0;
-    if (rc) break;
-    if (hipEventRecord(c->evC[s], c->side) != hipSuccess) rc = fail(WW_EHIP, "pipeline: event record");
-  }
-  c->prof_stage = -1;
-  if (rc) return rc;
-  // the column chains waited for every LU: one wait joins all streams (without columns,
-  // one wait per LU)
-  if (c->pcols) {
-    HIPCHK(hipStreamWaitEvent(s0, c->evC[nst - 1], 0));
-  } else {
-    for (int s = 0; s < nst; ++s) HIPCHK(hipStreamWaitEvent(s0, c->evL[s], 0));
-  }
-  hipLaunchKernelGGL(k_step_end, dim3(c->pcols ? c->M + 1 : 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), s0, c->y, c->K,
-                     kstride(c), nst, c->coef, c->tw, c->sig, c->N, 0, c->status);
-  LAUNCHCHK();
-  return 0;
-}
-
 // two_streams: the column chain of stage s runs on the side stream while stage s + 1
 // refactors (single instances); otherwise it follows the base chain on one stream
 // (batches, where the instances overlap each other instead).
 static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
-  if (pipelined(c, cols, two_streams)) return enqueue_step_pipe(c);
+  if (pipelined(c, cols, two_streams)) return pipe_step(c, false);
   int rc;
   const bool two = cols && c->M > 0 && two_streams;
   hipStream_t s0 = c->stream;
@@ -1401,7 +1349,7 @@ int dtn_setup(ww_ctx* c, const double* surface, double h, double tau, int N) {
 // work arrays of one dtn_solve_multi call (each Np x nrhs, ld Np; Rr only in the mixed
 // form) and the split-K partials of its products
 struct SolveWork {
-  double *Psi, *Ytmp, *Mu, *Gam, *HG, *Gpsi, *Rr, *part;
+  double *Psi, *Ytmp, *Mu, *Gam, *HG, *Gpsi, *Rr;
 };
 
 static int dtn_solve_impl(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, double* mu_out,
@@ -1413,8 +1361,7 @@ static int dtn_solve_impl(ww_ctx* c, const double* rhs, int nrhs, double* dtn_ou
   LAUNCHCHK();
   int rc;
   for (;;) {
-    Fac F = fac_default(c);
-    F.part = w.part;
+    const Fac F = fac_default(c);
     if ((rc = enqueue_dtn_cols(c, F, w.Psi, w.Ytmp, w.Mu, w.Gam, w.HG, w.Gpsi, w.Rr, nrhs))) return rc;
     if (!use32(c)) break;
     int st = 0;   // the refinement test of the mixed path
@@ -1448,7 +1395,7 @@ extern "C" {
 int dtn_solve_multi(ww_ctx* c, const double* rhs, int nrhs, double* dtn_out, double* mu_out) {
   int rc;
   if ((rc = dtn_solve_check(c, rhs, nrhs, dtn_out))) return rc;
-  const SolveWork w{c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, c->part};
+  const SolveWork w{c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr};
   return dtn_solve_impl(c, rhs, nrhs, dtn_out, mu_out, w);
 }
 
@@ -1456,26 +1403,25 @@ int dtn_solve_multi_noalloc(ww_ctx* c, const double* rhs, int nrhs, double* dtn_
   int rc;
   if ((rc = dtn_solve_check(c, rhs, nrhs, dtn_out))) return rc;
   if (!c->scratch) return fail(WW_EHIP, "internal: fixed workspace address not resolved");
-  // layout: Psi, Ytmp, Mu, Gam, HG, Gpsi, Rr (Np x nrhs each), then the split-K
-  // partials; the products split K at most as often as the rest of the array allows
+  // layout: Psi, Ytmp, Mu, Gam, HG, Gpsi, Rr, Np x nrhs each
   const size_t blk = (size_t)c->Np * nrhs;
   const size_t nbuf = 7;
-  if ((nbuf + 1) * blk > WW_SCRATCH_DOUBLES)
-    return fail(WW_EINVAL, "dtn_solve_multi_noalloc: 8 Np nrhs doubles exceed the fixed workspace (" +
+  if (nbuf * blk > WW_SCRATCH_DOUBLES)
+    return fail(WW_EINVAL, "dtn_solve_multi_noalloc: 7 Np nrhs doubles exceed the fixed workspace (" +
                                std::to_string(WW_SCRATCH_BYTES >> 20) + " MiB); use dtn_solve_multi");
   double* s = c->scratch;
-  const SolveWork w{s, s + blk, s + 2 * blk, s + 3 * blk, s + 4 * blk, s + 5 * blk, s + 6 * blk, s + nbuf * blk};
-  const int cap = (int)std::min<size_t>((WW_SCRATCH_DOUBLES - nbuf * blk) / blk, (size_t)c->nsplit_max);
-  c->split_cap = cap;
-  rc = dtn_solve_impl(c, rhs, nrhs, dtn_out, mu_out, w);
-  c->split_cap = 0;
-  return rc;
+  const SolveWork w{s, s + blk, s + 2 * blk, s + 3 * blk, s + 4 * blk, s + 5 * blk, s + 6 * blk};
+  return dtn_solve_impl(c, rhs, nrhs, dtn_out, mu_out, w);
 }
 
 int ww_profile(ww_ctx* c, int enable) {
   if (!c) return fail(WW_EINVAL, "null argument");
   if (enable && !c->stamps) HIPCHK(hipMalloc(&c->stamps, 3 * 16 * 3 * sizeof(unsigned long long)));
   if (enable) HIPCHK(hipMemsetAsync(c->stamps, 0, 3 * 16 * 3 * sizeof(unsigned long long), c->stream));
+  if (enable) {
+    c->host_enq_ms = 0.0;
+    c->host_enq_steps = 0;
+  }
   if ((bool)enable != c->prof) {
     c->prof = enable != 0;
     c->gnst = -1;   // re-capture the step graph with or without the stamp nodes
@@ -1484,8 +1430,14 @@ int ww_profile(ww_ctx* c, int enable) {
 }
 
 int ww_profile_read(ww_ctx* c, int phase, double* avg_ms, int* count) {
-  if (!c || !avg_ms || phase < 0 || phase > 2) return fail(WW_EINVAL, "bad argument");
+  if (!c || !avg_ms || phase < 0 || phase > 3) return fail(WW_EINVAL, "bad argument");
   if (!c->prof || !c->stamps) return fail(WW_EINVAL, "profiling is off");
+  if (phase == 3) {
+    if (c->host_enq_steps == 0) return fail(WW_EINVAL, "no profiled step");
+    *avg_ms = c->host_enq_ms / (double)c->host_enq_steps;
+    if (count) *count = (int)c->host_enq_steps;
+    return 0;
+  }
   unsigned long long h[16 * 3];
   HIPCHK(hipMemcpyAsync(h, c->stamps + (size_t)phase * 16 * 3, sizeof(h), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -1584,7 +1536,7 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
 }
 
 static int shoot_one_step(ww_ctx* c, bool cols, bool two_streams) {
-  if (graphed(c) && pipelined(c, cols, two_streams)) return pipe_step(c);
+  if (graphed(c) && pipelined(c, cols, two_streams)) return pipe_step(c, true);
   if (graphed(c)) {
     HIPCHK(hipGraphLaunch(c->step_exec, c->stream));
     return 0;
@@ -1610,7 +1562,7 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
                        cols ? M : 0);
     LAUNCHCHK();
   }
-  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, r, N, c->fdev);
+  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, r, N, c->fdev, (const double*)nullptr);
   LAUNCHCHK();
   if (fhost) HIPCHK(hipMemcpyAsync(fhost, c->fdev, 8, hipMemcpyDeviceToHost, c->stream));
   return 0;
@@ -1665,7 +1617,12 @@ static int shoot_run(ww_ctx* c, const double* params, double T, int nsteps, doub
   if ((rc = shoot_prepare(c, params, T, nsteps, cols, two))) return rc;
   const bool pipe = pipelined(c, cols, two);   // after the set-up, which decides on GMRES
   for (int n = 0; n < nsteps; ++n) {
+    const auto h0 = std::chrono::steady_clock::now();
     if ((rc = shoot_one_step(c, cols, two))) return rc;
+    if (c->prof) {
+      c->host_enq_ms += std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - h0).count();
+      ++c->host_enq_steps;
+    }
     if (pipe && n == 0 && nsteps > 1) {
       // lagged factors that do not converge show in the first step: stop there (the
       // caller redoes the march in its fallback mode or reports the status)
@@ -1890,7 +1847,7 @@ static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, in
   if ((rc = enqueue_base_chain(c, c->y, 0, c->Kx, F0))) return rc;
   hipLaunchKernelGGL(k_outputs, dim3((N + 255) / 256), dim3(256), 0, c->stream, c->y, c->Kx, rv, nullptr, dv, N, 0);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, rv, N, c->fdev);
+  hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, rv, N, c->fdev, (const double*)dv);
   LAUNCHCHK();
   // 2. adjoint seed (0, w r) and the reverse sweep, segment by segment
   hipLaunchKernelGGL(k_adj_seed, dim3((2 * N + 255) / 256), dim3(256), 0, c->stream, rv, N, lam);
@@ -1946,19 +1903,12 @@ static int adjoint_run(ww_ctx* c, const double* params, double T, int nsteps, in
                        grad);
     LAUNCHCHK();
   }
-  std::vector<double> hr(N), hd2(N);
-  double fh = 0.0;
-  HIPCHK(hipMemcpyAsync(hr.data(), rv, N * 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(hd2.data(), dv, N * 8, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(hipMemcpyAsync(&fh, c->fdev, 8, hipMemcpyDeviceToHost, c->stream));
+  double fh[2] = {0.0, 0.0};   // f and df/dT = r . dr/dT, reduced on the device
+  HIPCHK(hipMemcpyAsync(fh, c->fdev, sizeof(fh), hipMemcpyDeviceToHost, c->stream));
   int st = 0;
   if ((rc = read_status(c, &st, where))) return rc;
-  if (f) *f = fh;
-  if (dfdT) {
-    double acc = 0.0;
-    for (int i = 0; i < N; ++i) acc += hr[i] * hd2[i];
-    *dfdT = acc;
-  }
+  if (f) *f = fh[0];
+  if (dfdT) *dfdT = fh[1];
   *stout = st;
   return 0;
 }

@@ -201,6 +201,43 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
 }
 
 // -------------------------------------------------------------------------------------
+// One row of y = add + sgn * M x over the 64-block range of `mode` (0 all, 1 strictly
+// lower, 2 upper incl. diagonal) from the row-major M (element type T, accumulation in
+// double), by one wave: contiguous row reads, sixteen loads in flight per lane, a
+// fixed-order shuffle reduction.
+// -------------------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void gemv_row_wave(const T* __restrict__ Mr, int Np, int mode, const double* __restrict__ x,
+                                              const double* __restrict__ add, double sgn, double* __restrict__ y,
+                                              int row, int lane) {
+  const int rb = row / WW_TB;
+  const int tri = mode & 3;
+  const int lo = (tri == 2) ? rb * WW_TB : 0;
+  const int hi = (tri == 1) ? rb * WW_TB : Np;
+  const T* mr = Mr + (size_t)row * Np;
+  double s0 = 0.0, s1 = 0.0;
+  int j = lo + lane;
+  for (; j + 15 * 64 < hi; j += 16 * 64) {   // sixteen loads of the row in flight per lane
+    T m[16];
+    double xv[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      m[q] = mr[j + 64 * q];
+      xv[q] = x[j + 64 * q];
+    }
+#pragma unroll
+    for (int q = 0; q < 16; q += 2) {
+      s0 = fma((double)m[q], xv[q], s0);
+      s1 = fma((double)m[q + 1], xv[q + 1], s1);
+    }
+  }
+  for (; j < hi; j += 64) s0 = fma((double)mr[j], x[j], s0);
+  double s = s0 + s1;
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+  if (lane == 0) y[row] = (add ? add[row] : 0.0) + sgn * s;
+}
+
+// -------------------------------------------------------------------------------------
 // Kernel matrix assembly (Sec. 2.2 eq. (K1K2), App. A): A = I/2 + K/N, Gm = G/N.
 //
 // Entry (i, j), alpha_i - alpha_j = 2 pi d / N, d = (i - j) mod N:
@@ -233,11 +270,26 @@ __device__ __forceinline__ void cot_half_branch(double cx, double sx, double chy
 // four workgroups per 64-tile, so that enough waves are resident to hide the latency
 // of the dependent FP64 chains (divisions of the cot branch formula).
 #define ASM_CW 16   // columns per assembly workgroup
+// With a lagged inverse (Mx64 or Mx32, row-major), 16 more rows of workgroups follow
+// the assembly grid: they form x0 = Mx psi (the first solve of the lagged-factor base
+// chain, which does not need this stage's matrix), one wave per row.
 __global__ __launch_bounds__(WW_NT) void k_assemble(
     const double* __restrict__ aux, int nmax, const double* __restrict__ cosT,
     const double* __restrict__ sinT, const double* __restrict__ c0T, double* __restrict__ A,
     double* __restrict__ Gm, float* __restrict__ A32, double* __restrict__ Gmr, double* __restrict__ Ar, int N,
-    int Np, int finite) {
+    int Np, int finite, const double* __restrict__ Mx64, const float* __restrict__ Mx32,
+    const double* __restrict__ psi, double* __restrict__ x0) {
+  if (blockIdx.y >= (unsigned)(Np / ASM_CW)) {
+    // (uniform per workgroup: no barrier below is reached by these blocks)
+    const int g = (blockIdx.y - Np / ASM_CW) * gridDim.x + blockIdx.x;
+    const int row = g * (WW_NT / 64) + (threadIdx.x >> 6);
+    if (row >= Np) return;
+    if (Mx32)
+      gemv_row_wave<float>(Mx32, Np, 0, psi, nullptr, 1.0, x0, row, threadIdx.x & 63);
+    else if (Mx64)
+      gemv_row_wave<double>(Mx64, Np, 0, psi, nullptr, 1.0, x0, row, threadIdx.x & 63);
+    return;
+  }
   // stage the per-point quantities of the strip's 64 rows and 16 columns and the 79
   // circulant table entries d = i - j it touches in LDS
   __shared__ double rt[WW_TB][ASM_CW + 1];   // the strip of Gm (then A) for the row-major copies
@@ -306,7 +358,7 @@ __global__ __launch_bounds__(WW_NT) void k_assemble(
     }
     const size_t o = (size_t)j * Np + i;
     A[o] = a;
-    Gm[o] = gm;
+    if (Gm) Gm[o] = gm;
     if (A32) A32[o] = (float)a;
     rt[tx][jj] = gm;
   }
@@ -745,6 +797,21 @@ struct BluBufs {
   double pivguard;
 };
 
+// Several matrices factored by one launch sequence (the lagged-factor march factors
+// consecutive stages together): block b of a launch works on matrix b % count, task
+// b / count, so the critical tasks (the next diagonal block of every matrix) come first.
+#define BLU_GMAX 4
+template <typename T>
+struct BluGroup {
+  BluBufs<T> m[BLU_GMAX];
+  int count;
+};
+template <typename T>
+__device__ __forceinline__ BluBufs<T> blu_pick(const BluGroup<T>& g, int m) {
+  // uniform selection (no dynamically indexed copy of the argument block)
+  return m == 0 ? g.m[0] : m == 1 ? g.m[1] : m == 2 ? g.m[2] : g.m[3];
+}
+
 template <typename T>
 __device__ inline T* tileptr(T* M, int Np, int i, int j) {
   return M + (size_t)j * WW_TB * Np + (size_t)i * WW_TB;
@@ -765,7 +832,8 @@ __device__ inline void store_dinv(const T* Ts, T* D) {
 }
 
 template <typename T>
-__global__ __launch_bounds__(WW_NT) void k_blu_init(BluBufs<T> b) {
+__global__ __launch_bounds__(WW_NT) void k_blu_init(BluGroup<T> g) {
+  const BluBufs<T> b = blu_pick(g, blockIdx.x);
   extern __shared__ double sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
   T* Ts = sm;
@@ -818,106 +886,147 @@ __device__ inline void tile_store_sum(const T* Ts, const T (&v)[16], T* __restri
   }
 }
 
-// Two LDS tiles per workgroup (so that two workgroups share a CU): S0 holds the left
-// factor and then the left product, S1 holds D_k and then the right factor.  The right
-// factor and the destination tile are fetched into registers with the other two tiles
-// at the start and enter LDS (or the final sum) when their slot is free.  The result
-// is C + (-(L R)), the same rounding as C - L R accumulated into C.
+// Tasks of step k (per matrix of a group).  Task 0 updates the next diagonal tile
+// (k+1, k+1) and inverts it (the critical path of the factorisation).  Every other task
+// is a strip of at most BLU_STRIP tiles of one row i: it forms the row's left factor
+// once (A_ik D_k for i > k; V_ik D_k for i < k; D_k itself for i = k) and applies it to
+// each tile of its strip, so no product is repeated across the tiles of a row.  Row i
+// > k runs over j = k+1 .. nb-1 (role 1: A_ij -= L A_kj; row k+1 without the diagonal
+// tile) and then j = 0 .. k (role 2: X_ik = -L, X_ij -= L X_kj); row i <= k over
+// j = k+1 .. nb-1 (role 3: V_ij -= L A_kj, V_kj = -D_k A_kj; the strip starting at
+// j = k+1 also stores Z_ik = L).
+#define BLU_STRIP 4
+__host__ __device__ inline int blu_row_len(int nb, int k, int i) {
+  return i > k ? (i == k + 1 ? nb - 1 : nb) : nb - k - 1;
+}
+__host__ __device__ inline int blu_step_tasks(int nb, int k) {
+  int n = 1;
+  for (int i = 0; i < nb; ++i) n += (blu_row_len(nb, k, i) + BLU_STRIP - 1) / BLU_STRIP;
+  return n;
+}
+
+// Two LDS tiles per workgroup (two workgroups share a CU): S0 holds the left factor,
+// S1 the right factor of the current tile and then the product.  The result is
+// C + (-(L R)), the same rounding as C - L R accumulated into C.
 template <typename T>
-__global__ __launch_bounds__(WW_NT) void k_blu_step(BluBufs<T> b, int k) {
+__global__ __launch_bounds__(WW_NT) void k_blu_step(BluGroup<T> g, int k) {
   extern __shared__ double sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
   T* S0 = sm;
   T* S1 = sm + TILE_DBL;
+  const BluBufs<T> b = blu_pick(g, (int)(blockIdx.x % g.count));
   const int Np = b.Np, nb = Np / WW_TB;
   const int nt = nb - k - 1;
-  const int n1 = nt * nt, n2 = nt * (k + 1);
-  int bid = blockIdx.x;
-  int role, i, j;
-  if (bid < n1) {
-    role = 1; i = k + 1 + bid / nt; j = k + 1 + bid % nt;
-  } else if (bid < n1 + n2) {
-    bid -= n1; role = 2; i = k + 1 + bid / (k + 1); j = bid % (k + 1);
-  } else {
-    bid -= n1 + n2; role = 3; i = bid / nt; j = k + 1 + bid % nt;
-  }
   const T* Dk = b.Dinv + (size_t)k * 4096;
-  const bool ldiag = (role == 3 && i == k);           // left factor is D_k itself
-  const bool xfirst = (role == 2 && j == k);          // X_ik = -A_ik D_k, no right factor
-  const bool vfirst = ldiag;                          // V_kj = -D_k A_kj, no accumulation
-  const bool diag = (role == 1 && i == k + 1 && j == k + 1);   // inverts its tile: D_{k+1}
-  const bool rmcopy = (role == 2 && b.Xr && i == k + 1);       // row of X final: row-major copy
-  T* dst = role == 1 ? tileptr(b.A, Np, i, j) : role == 2 ? tileptr(b.X, Np, i, j) : tileptr(b.V, Np, i, j);
-  T vl[16], vd[16], vr[16], vc[16];
-  tile_fetch<T>(vl, ldiag ? Dk : (role == 3 ? tileptr(b.V, Np, i, k) : tileptr(b.A, Np, i, k)), ldiag ? 64 : Np);
-  if (!ldiag) tile_fetch<T>(vd, Dk, 64);
-  if (!xfirst) tile_fetch<T>(vr, role == 2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j), Np);
-  if (!xfirst && !vfirst) tile_fetch<T>(vc, dst, Np);
-  tile_put<T>(S0, vl);
-  if (!ldiag) tile_put<T>(S1, vd);
-  __syncthreads();
-  if (ldiag && j == k + 1) {
-    // Z_kk = D_k (kept off the workgroup that inverted it, which is on the critical path)
-    tile_store<T, T>(S0, tileptr(b.Z, Np, k, k), Np);
-    if (b.Zr) tile_store_rm<T>(S0, rmptr(b.Zr, Np, k, k), Np);
-  }
+  int q = blockIdx.x / g.count;
   Acc64<T> acc;
-  if (!ldiag) {
+  if (q == 0) {
+    // the next diagonal tile: L = A_{k+1,k} D_k, A_{k+1,k+1} -= L A_{k,k+1}, then its
+    // inverse D_{k+1} (the inverse's scratch overlays both slots)
+    T vl[16], vd[16], vr[16], vc[16];
+    tile_fetch<T>(vl, tileptr(b.A, Np, k + 1, k), Np);
+    tile_fetch<T>(vd, Dk, 64);
+    tile_fetch<T>(vr, tileptr(b.A, Np, k, k + 1), Np);
+    tile_fetch<T>(vc, tileptr(b.A, Np, k + 1, k + 1), Np);
+    tile_put<T>(S0, vl);
+    tile_put<T>(S1, vd);
+    __syncthreads();
     acc_zero(acc);
     mfma_tile(S0, S1, acc);
     __syncthreads();
-    acc_to_lds(acc, S0, 0, T(1));   // S0 = A_ik D_k (roles 1, 2) or V_ik D_k = Z_ik (role 3)
-  }
-  if (!xfirst) tile_put<T>(S1, vr);
-  __syncthreads();
-  if (!ldiag && role == 3 && j == k + 1) {
-    tile_store<T, T>(S0, tileptr(b.Z, Np, i, k), Np);
-    if (b.Zr) tile_store_rm<T>(S0, rmptr(b.Zr, Np, i, k), Np);
-  }
-  if (xfirst) {
-    tile_store<T, T>(S0, tileptr(b.X, Np, i, k), Np, 64, T(-1));
-    if (b.Xr && i == k + 1) tile_store_rm<T>(S0, rmptr(b.Xr, Np, i, k), Np, T(-1));   // final
-    return;
-  }
-  acc_zero(acc);
-  mfma_tile(S0, S1, acc);
-  __syncthreads();
-  acc_to_lds(acc, S0, 0, T(-1));   // S0 = -L R
-  if (vfirst) {
+    acc_to_lds(acc, S0, 0, T(1));
+    tile_put<T>(S1, vr);
     __syncthreads();
-    tile_store<T, T>(S0, dst, Np);
-    return;
-  }
-  if (diag || rmcopy) {
-    // the updated tile is needed in LDS: S0 += C (own entries), then one barrier
+    acc_zero(acc);
+    mfma_tile(S0, S1, acc);
+    __syncthreads();
+    acc_to_lds(acc, S0, 0, T(-1));
     __syncthreads();
     tile_add_own<T>(S0, vc);
     __syncthreads();
-    if (diag) {
-      // Schur complement block of the next step: invert it (D_{k+1} = Z_{k+1,k+1});
-      // the inverse's scratch overlays both slots (S1 is free here)
-      const double mp = blk_gj_inverse<T>(S0, sm);
-      if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
-      store_dinv<T>(S0, b.Dinv + (size_t)(k + 1) * 4096);   // Z_{k+1,k+1} is stored one step later
-      return;
-    }
-    tile_store<T, T>(S0, dst, Np);
-    tile_store_rm<T>(S0, rmptr(b.Xr, Np, i, j), Np);   // final
+    const double mp = blk_gj_inverse<T>(S0, sm);
+    if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
+    store_dinv<T>(S0, b.Dinv + (size_t)(k + 1) * 4096);   // Z_{k+1,k+1} is stored one step later
     return;
   }
-  __syncthreads();
-  tile_store_sum<T>(S0, vc, dst, Np);
+  // the strip: row i, positions p0 .. p0 + len - 1 of the row's tile list
+  q -= 1;
+  int i = -1, p0 = 0, len = 0;
+  for (int r = 0; r < nb; ++r) {
+    const int n = blu_row_len(nb, k, r);
+    const int ch = (n + BLU_STRIP - 1) / BLU_STRIP;
+    if (q < ch) {
+      i = r;
+      p0 = q * BLU_STRIP;
+      len = min(BLU_STRIP, n - p0);
+      break;
+    }
+    q -= ch;
+  }
+  if (i < 0 || len <= 0) return;
+  const bool low = i > k;      // roles 1 and 2
+  const bool ldiag = i == k;   // role 3 on row k: the left factor is D_k
+  {
+    T vl[16], vd[16];
+    tile_fetch<T>(vl, ldiag ? Dk : (low ? tileptr(b.A, Np, i, k) : tileptr(b.V, Np, i, k)), ldiag ? 64 : Np);
+    if (!ldiag) tile_fetch<T>(vd, Dk, 64);
+    tile_put<T>(S0, vl);
+    if (!ldiag) tile_put<T>(S1, vd);
+    __syncthreads();
+    if (!ldiag) {
+      acc_zero(acc);
+      mfma_tile(S0, S1, acc);
+      __syncthreads();
+      acc_to_lds(acc, S0, 0, T(1));   // S0 = L
+      __syncthreads();
+    }
+  }
+  if (!low && p0 == 0) tile_store<T, T>(S0, tileptr(b.Z, Np, i, k), Np);   // Z_ik = L (Z_kk = D_k)
+  for (int p = p0; p < p0 + len; ++p) {
+    // the tile (i, j) of position p
+    int j;
+    if (!low) {
+      j = k + 1 + p;
+    } else {
+      const int nrt = (i == k + 1) ? nt - 1 : nt;   // tiles right of column k in this row
+      const int jr0 = (i == k + 1) ? k + 2 : k + 1;
+      j = p < nrt ? jr0 + p : p - nrt;
+    }
+    const bool role2 = low && j <= k;
+    if (role2 && j == k) {   // X_ik = -L (final)
+      tile_store<T, T>(S0, tileptr(b.X, Np, i, k), Np, 64, T(-1));
+      continue;
+    }
+    const bool vfirst = ldiag;   // V_kj = -D_k A_kj: nothing to accumulate into
+    T* dst = role2 ? tileptr(b.X, Np, i, j) : (low ? tileptr(b.A, Np, i, j) : tileptr(b.V, Np, i, j));
+    T vr[16], vc[16];
+    tile_fetch<T>(vr, role2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j), Np);
+    if (!vfirst) tile_fetch<T>(vc, dst, Np);
+    __syncthreads();   // S1 is free (the previous tile's product has been stored)
+    tile_put<T>(S1, vr);
+    __syncthreads();
+    acc_zero(acc);
+    mfma_tile(S0, S1, acc);
+    __syncthreads();
+    acc_to_lds(acc, S1, 0, T(-1));   // S1 = -L R
+    __syncthreads();
+    if (vfirst)
+      tile_store<T, T>(S1, dst, Np);
+    else
+      tile_store_sum<T>(S1, vc, dst, Np);
+  }
 }
 
 // last column block of Z: Z_i,nb-1 = V_i,nb-1 D_nb-1 (i < nb - 1)
 template <typename T>
-__global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs<T> b) {
+__global__ __launch_bounds__(WW_NT) void k_blu_final(BluGroup<T> g) {
   extern __shared__ double sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
   T* As = sm;
   T* Bs = sm + TILE_DBL;
+  const BluBufs<T> b = blu_pick(g, (int)(blockIdx.x % g.count));
   const int Np = b.Np, nb = Np / WW_TB;
-  const int i = blockIdx.x, k = nb - 1;
+  const int i = blockIdx.x / g.count, k = nb - 1;
   tile_load<T, T>(As, tileptr(b.V, Np, i, k), Np);
   tile_load<T, T>(Bs, b.Dinv + (size_t)k * 4096, 64);
   __syncthreads();
@@ -933,6 +1042,65 @@ __global__ __launch_bounds__(WW_NT) void k_blu_final(BluBufs<T> b) {
   __syncthreads();
   tile_store<T, T>(As, tileptr(b.Z, Np, i, k), Np);
   if (b.Zr) tile_store_rm<T>(As, rmptr(b.Zr, Np, i, k), Np);
+}
+
+// -------------------------------------------------------------------------------------
+// Explicit inverse from the block LU: A^{-1} = Ut^{-1} Lt^{-1} = Z (I + X), written
+// row-major (the one-vector products read it along rows, the column products read
+// row-major tiles), so that every later solve is one product.  Output tile (i, j):
+//   [i <= j] Z_ij + sum_{m = max(i, j+1)}^{nb-1} Z_im X_mj,
+// one workgroup per tile, the sum in increasing m (fixed order); tiles with the longest
+// sums have the lowest block indices (dispatched first).  The next pair of tiles is in
+// flight in registers during the MFMAs of the current one.
+// -------------------------------------------------------------------------------------
+// Matrices of a group: grid z (Z, X, Mr of matrix z).
+template <typename T>
+struct MinvGroup {
+  const T* Z[BLU_GMAX];
+  const T* X[BLU_GMAX];
+  T* Mr[BLU_GMAX];
+};
+template <typename T>
+__global__ __launch_bounds__(WW_NT) void k_minv(MinvGroup<T> gr, int Np) {
+  extern __shared__ double sm_raw[];
+  T* sm = reinterpret_cast<T*>(sm_raw);
+  T* As = sm;
+  T* Bs = sm + TILE_DBL;
+  const int z = blockIdx.z;
+  const T* __restrict__ Z = z == 0 ? gr.Z[0] : z == 1 ? gr.Z[1] : z == 2 ? gr.Z[2] : gr.Z[3];
+  const T* __restrict__ X = z == 0 ? gr.X[0] : z == 1 ? gr.X[1] : z == 2 ? gr.X[2] : gr.X[3];
+  T* __restrict__ Mr = z == 0 ? gr.Mr[0] : z == 1 ? gr.Mr[1] : z == 2 ? gr.Mr[2] : gr.Mr[3];
+  const int nb = Np / WW_TB;
+  const int j = blockIdx.x, i = blockIdx.y;
+  const int m0 = max(i, j + 1);
+  Acc64<T> acc;
+  acc_zero(acc);
+  T za[16], xb[16];
+  if (m0 < nb) {
+    tile_fetch<T>(za, tileptr(Z, Np, i, m0), Np);
+    tile_fetch<T>(xb, tileptr(X, Np, m0, j), Np);
+  }
+  for (int m = m0; m < nb; ++m) {
+    __syncthreads();
+    tile_put<T>(As, za);
+    tile_put<T>(Bs, xb);
+    __syncthreads();
+    if (m + 1 < nb) {
+      tile_fetch<T>(za, tileptr(Z, Np, i, m + 1), Np);
+      tile_fetch<T>(xb, tileptr(X, Np, m + 1, j), Np);
+    }
+    mfma_tile(As, Bs, acc);
+  }
+  __syncthreads();
+  if (i <= j) {
+    tile_load<T, T>(As, tileptr(Z, Np, i, j), Np);
+    __syncthreads();
+    acc_to_lds(acc, As, 1, T(1));
+  } else {
+    acc_to_lds(acc, As, 0, T(1));
+  }
+  __syncthreads();
+  tile_store_rm<T>(As, rmptr(Mr, Np, i, j), Np);
 }
 
 // -------------------------------------------------------------------------------------
@@ -1051,99 +1219,106 @@ __global__ __launch_bounds__(WW_NT) void k_gemv_row(const T* __restrict__ Mr, in
                                                     const double* __restrict__ x, const double* __restrict__ add,
                                                     double sgn, double* __restrict__ y) {
   const int row = (blockIdx.x * WW_NT + threadIdx.x) >> 6;
-  const int lane = threadIdx.x & 63;
   if (row >= Np) return;
-  const int rb = row / WW_TB;
-  const int lo = (mode == 2) ? rb * WW_TB : 0;
-  const int hi = (mode == 1) ? rb * WW_TB : Np;
-  const T* mr = Mr + (size_t)row * Np;
-  double s0 = 0.0, s1 = 0.0;
-  int j = lo + lane;
-  for (; j + 7 * 64 < hi; j += 8 * 64) {
-    T m[8];
-    double xv[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      m[q] = mr[j + 64 * q];
-      xv[q] = x[j + 64 * q];
-    }
-#pragma unroll
-    for (int q = 0; q < 8; q += 2) {
-      s0 = fma((double)m[q], xv[q], s0);
-      s1 = fma((double)m[q + 1], xv[q + 1], s1);
-    }
-  }
-  for (; j < hi; j += 64) s0 = fma((double)mr[j], x[j], s0);
-  double s = s0 + s1;
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if (lane == 0) y[row] = (add ? add[row] : 0.0) + sgn * s;
+  gemv_row_wave<T>(Mr, Np, mode, x, add, sgn, y, row, threadIdx.x & 63);
 }
 
+
 // -------------------------------------------------------------------------------------
-// Blocked GEMM with split K: part[s] = sum over the k-tiles of chunk s of
-// M(rb, kt) * B(kt, :), 64 x 64 output tiles; M has element type T (double, or float
-// for the FP32 factors), B and the partials are double (B is rounded to T on load).
-// mode 0: all k-tiles;  mode 1: kt < rb (strictly lower X);  mode 2: kt >= rb (upper Z).
-// k_gemm_reduce: out = add + sgn * sum_s part[s]  (add may be null).
+// Product with a row-major matrix for R right-hand sides:  out = add + sgn * M B
+// (M: Np x Np row-major, element type T; B, add, out: Np x R column-major doubles,
+// ld Np; B is rounded to T on load).  One workgroup of 16 waves per 32 x 32 output
+// tile: the inner dimension is split over four wave groups (group g takes the 64-wide
+// steps g, g + 4, ...), in each group wave w computes the 16 x 16 quadrant
+// (w >> 1, w & 1) with 16 x 16 x 4 MFMAs, the next step's operands in flight in
+// registers during the MFMAs; the four partial tiles are summed in LDS in a fixed
+// order, ((g0 + g1) + g2) + g3, so each entry is one deterministic sum (no partials
+// in memory, no second launch).  The result is stored along the columns.
 // -------------------------------------------------------------------------------------
+#define GT 32           // output tile edge
+#define GK 64           // inner step
+#define GSPLIT 4        // wave groups splitting the inner dimension
+#define GEMM_NT (64 * 4 * GSPLIT)
+#define GA_LD (GK + 1)  // LDS pitch of the M tile (32 rows x 64) and of the B tile (32 columns x 64)
 template <typename T>
-__global__ __launch_bounds__(WW_NT) void k_gemm_part(const T* __restrict__ Mt, int Np, int mode,
-                                                     const double* __restrict__ B, int R,
-                                                     double* __restrict__ part, int kchunk) {
-  extern __shared__ double sm_raw[];
-  T* sm = reinterpret_cast<T*>(sm_raw);
-  T* As = sm;
-  T* Bs = sm + TILE_DBL;
-  const size_t ld = Np;
-  const int rb = blockIdx.x;
-  const int c0 = blockIdx.y * 64;
-  const int s = blockIdx.z;
-  const int ncol = min(64, R - c0);
-  const int nkt = Np / WW_TB;
-  int lo = s * kchunk, hi = min(nkt, lo + kchunk);
-  if (mode == 1) hi = min(hi, rb);
-  if (mode == 2) lo = max(lo, rb);
-  Acc64<T> acc;
-  acc_zero(acc);
-  T ra[16];
-  double rbv[16];
-  auto fetch = [&](int kt) {
-    const T* Tt = Mt + (size_t)kt * WW_TB * ld + (size_t)rb * WW_TB;
-    const double* Bt = B + (size_t)c0 * ld + (size_t)kt * WW_TB;
+__global__ __launch_bounds__(GEMM_NT) void k_gemm_rm(const T* __restrict__ M, int Np, const double* __restrict__ B,
+                                                     int R, const double* __restrict__ add, double sgn,
+                                                     double* __restrict__ out) {
+  // operand tiles of the four groups; after the inner loop the same memory holds the
+  // four partial output tiles
+  constexpr int OPER = 2 * GSPLIT * GT * GA_LD * (int)sizeof(T);
+  constexpr int PART = GSPLIT * GT * (GT + 1) * (int)sizeof(double);
+  __shared__ double smem[(OPER > PART ? OPER : PART) / 8];
+  T (*As)[GT * GA_LD] = reinterpret_cast<T (*)[GT * GA_LD]>(smem);
+  T (*Bs)[GT * GA_LD] = As + GSPLIT;
+  double (*Cs)[GT * (GT + 1)] = reinterpret_cast<double (*)[GT * (GT + 1)]>(smem);
+  typedef typename Mfma<T>::V V;
+  const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
+  const int tid = threadIdx.x;
+  const int grp = tid >> 8, gt = tid & 255;   // wave group and thread within it
+  const int lane = gt & 63, w = gt >> 6;
+  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+  const int li = lane & 15, lk = lane >> 4;
+  T* as = As[grp];
+  T* bs = Bs[grp];
+  // loads of one inner step by the 256 threads of a group: 8 entries of the M tile
+  // (rows r0.., columns k0..) and 8 of the B tile: row/column gt >> 6 + 4 m, inner gt & 63
+  T ma[8];
+  double bv[8];
+  auto fetch = [&](int k0) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int idx = threadIdx.x + WW_NT * m;
-      const int c = idx >> 6;
-      ra[m] = Tt[(size_t)c * ld + (idx & 63)];
-      rbv[m] = (c < ncol) ? Bt[(size_t)c * ld + (idx & 63)] : 0.0;
+    for (int m = 0; m < 8; ++m) {
+      const int rr = (gt >> 6) + 4 * m, kk = gt & 63;
+      ma[m] = M[(size_t)(r0 + rr) * Np + k0 + kk];
+      const int cc = c0 + rr;
+      bv[m] = cc < R ? B[(size_t)cc * Np + k0 + kk] : 0.0;
     }
   };
-  if (lo < hi) fetch(lo);
-  for (int kt = lo; kt < hi; ++kt) {
+  V acc = V{T(0), T(0), T(0), T(0)};
+  const int nsteps = Np / GK;
+  if (grp < nsteps) fetch(grp * GK);
+  // every group runs the same number of iterations (barriers are workgroup-wide); a
+  // group without a step in an iteration only waits
+  for (int it = 0; it * GSPLIT < nsteps; ++it) {
+    const int st = it * GSPLIT + grp;
+    const bool have = st < nsteps;
     __syncthreads();
+    if (have) {
 #pragma unroll
-    for (int m = 0; m < 16; ++m) {
-      const int idx = threadIdx.x + WW_NT * m;
-      As[(idx & 63) * TLD + (idx >> 6)] = ra[m];
-      Bs[(idx & 63) * TLD + (idx >> 6)] = (T)rbv[m];
+      for (int m = 0; m < 8; ++m) {
+        const int rr = (gt >> 6) + 4 * m, kk = gt & 63;
+        as[rr * GA_LD + kk] = ma[m];
+        bs[rr * GA_LD + kk] = (T)bv[m];
+      }
     }
     __syncthreads();
-    if (kt + 1 < hi) fetch(kt + 1);   // next tiles in flight during the MFMAs
-    mfma_tile(As, Bs, acc);
+    if (have && st + GSPLIT < nsteps) fetch((st + GSPLIT) * GK);
+    if (have) {
+#pragma unroll
+      for (int k = 0; k < GK; k += 4) {
+        const T a = as[(wr + li) * GA_LD + k + lk];
+        const T b = bs[(wc + li) * GA_LD + k + lk];
+        acc = Mfma<T>::step(a, b, acc);
+      }
+    }
   }
+  __syncthreads();   // every group is done with its operand tiles
+#pragma unroll
+  for (int i = 0; i < 4; ++i) Cs[grp][(wc + li) * (GT + 1) + wr + Mfma<T>::row(i, lk)] = (double)acc[i];
   __syncthreads();
-  acc_to_lds(acc, As, 0, T(1));
-  __syncthreads();
-  tile_store<T, double>(As, part + (size_t)s * ld * R + (size_t)c0 * ld + (size_t)rb * WW_TB, ld, ncol);
-}
-
-__global__ void k_gemm_reduce(const double* __restrict__ part, int nsplit, const double* __restrict__ add,
-                              double sgn, double* __restrict__ out, int Np, int R) {
-  const size_t n = (size_t)Np * R;
-  for (size_t idx = blockIdx.x * (size_t)blockDim.x + threadIdx.x; idx < n; idx += (size_t)gridDim.x * blockDim.x) {
-    double s = 0.0;
-    for (int p = 0; p < nsplit; ++p) s += part[(size_t)p * n + idx];
-    out[idx] = (add ? add[idx] : 0.0) + sgn * s;
+  if (grp == 0) {
+    // column c0 + (gt >> 3), rows r0 + 4 (gt & 7) .. + 3
+    const int cc = c0 + (gt >> 3);
+    if (cc < R) {
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = 4 * (gt & 7) + q;
+        const int e = (gt >> 3) * (GT + 1) + rr;
+        const double s = ((Cs[0][e] + Cs[1][e]) + Cs[2][e]) + Cs[3][e];
+        const size_t o = (size_t)cc * Np + r0 + rr;
+        out[o] = (add ? add[o] : 0.0) + sgn * s;
+      }
+    }
   }
 }
 
@@ -1196,7 +1371,7 @@ __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, 
     S[t] = pack_pair(sym_deriv(B, k, N), cscale(B, hk));
   }
   fft_lds(W, Z, tws, P, +1);
-  fft_lds(S, Z, tws, P, +1);
+  if (hasb) fft_lds(S, Z, tws, P, +1);
   for (int t = tid; t < Np; t += WW_NT) {
     const bool in = t < N;
     Gam[(size_t)ca * Np + t] = in ? W[t].x : 0.0;
@@ -1209,6 +1384,130 @@ __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, 
 }
 
 // -------------------------------------------------------------------------------------
+// Base DtN output of a lagged-factor stage in one launch (eq. (G)): every workgroup
+// forms gamma = d mu/d alpha and (1/2) H gamma of the base density mu in LDS (one
+// forward and one inverse FFT of its own), then, for its rows i (one wave per row),
+//   G phi_i = (1/2) H gamma_i + sum_j Gm_ij gamma_j          (row-major Gm)
+//   r_i     = psi_i - sum_j A_ij mu_j                          (row-major A)
+// the FP64 residual of the refined solve.  The convergence test of that solve
+// (max |r| <= tol max |psi|) needs both maxima over all rows: each wave folds its own
+// into chk[0] = max |r|, chk[1] = max |psi| with an atomic maximum on the bit patterns
+// (non-negative doubles order like their bits; a NaN residual is larger than any
+// finite one), and the next kernel on the stream (k_base_rhs) takes the decision and
+// clears chk.  Rows N..Np-1 of Gphi are zero.  Dynamic LDS: 4 N complex.
+// -------------------------------------------------------------------------------------
+#define DTN_ROWS 8                 // rows per workgroup (two per wave)
+#define DTN_NR (WW_NMAX / 64)      // entries of a row per lane
+__global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ mu, const double* __restrict__ psi,
+                                                    const double* __restrict__ Gmr, const double* __restrict__ Ar,
+                                                    int Np, const cplx* __restrict__ tw, int N,
+                                                    double* __restrict__ Gphi,
+                                                    unsigned long long* __restrict__ chk) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* tws = lds + 2 * N;
+  double* xs = reinterpret_cast<double*>(lds + 3 * N);   // mu (N doubles)
+  double* gs = xs + N;                                   // gamma (N doubles)
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  // a row's entries of Gm and A, all in flight at once (clamped, unconditional loads);
+  // the first row's loads are issued before the transforms, which they do not need
+  double gv[DTN_NR], av[DTN_NR];
+  auto load_row = [&](int row) {
+    const int rr = row < N ? row : N - 1;
+    const double* gr = Gmr + (size_t)rr * Np;
+    const double* ar = Ar + (size_t)rr * Np;
+#pragma unroll
+    for (int m = 0; m < DTN_NR; ++m) {
+      const int j = lane + 64 * m;
+      const int jj = j < N ? j : N - 1;
+      gv[m] = gr[jj];
+      av[m] = ar[jj];
+    }
+  };
+  const int row0 = blockIdx.x * DTN_ROWS + wv;
+  load_row(row0);
+  const FftPlan P = make_plan(N);
+  load_twiddles(tws, tw, N);
+  {
+    double va[NPT];
+    gload(va, mu, N);
+    pin(va);
+#pragma unroll
+    for (int m = 0; m < NPT; ++m) {
+      const int t = tidx(m);
+      if (t < N) {
+        Z[t] = cmk(va[m], 0.0);
+        xs[t] = va[m];
+      }
+    }
+  }
+  fft_lds(Z, W, tws, P, -1);
+  for (int t = tid; t < N; t += WW_NT) {
+    const int k = wavenum(t, N);
+    const double hk = (k == 0 || 2 * k == N || 2 * k == -N) ? 0.0 : 0.5 * fabs((double)k);
+    // Z holds the spectrum of the real signal mu: gamma_hat = i k mu_hat, (H gamma / 2)_hat
+    // = |k| mu_hat / 2; both real signals travel as one complex signal
+    W[t] = pack_pair(sym_deriv(Z[t], k, N), cscale(Z[t], hk));
+  }
+  fft_lds(W, Z, tws, P, +1);
+  for (int t = tid; t < N; t += WW_NT) gs[t] = W[t].x;
+  __syncthreads();
+  double mr = 0.0, mb = 0.0;
+  for (int q = 0; q < DTN_ROWS / 4; ++q) {
+    const int row = blockIdx.x * DTN_ROWS + q * 4 + wv;
+    if (row >= Np) break;
+    if (q > 0) load_row(row);
+    if (row >= N) {
+      if (lane == 0) Gphi[row] = 0.0;
+      continue;
+    }
+    double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
+#pragma unroll
+    for (int m = 0; m < DTN_NR; m += 2) {
+      const int j0 = lane + 64 * m, j1 = j0 + 64;
+      if (j0 < N) {
+        s0 = fma(gv[m], gs[j0], s0);
+        t0 = fma(av[m], xs[j0], t0);
+      }
+      if (j1 < N) {
+        s1 = fma(gv[m + 1], gs[j1], s1);
+        t1 = fma(av[m + 1], xs[j1], t1);
+      }
+    }
+    double s = s0 + s1, t = t0 + t1;
+    for (int off = 32; off > 0; off >>= 1) {
+      s += __shfl_down(s, off, 64);
+      t += __shfl_down(t, off, 64);
+    }
+    if (lane == 0) {
+      Gphi[row] = W[row].y + s;
+      const double r = psi[row] - t;
+      mr = fmax(mr, fabs(r));
+      if (r != r) mr = INFINITY;
+      mb = fmax(mb, fabs(psi[row]));
+    }
+  }
+  if (lane == 0 && chk) {
+    atomicMax(chk, (unsigned long long)__double_as_longlong(mr));
+    atomicMax(chk + 1, (unsigned long long)__double_as_longlong(mb));
+  }
+}
+
+// The convergence test of a lagged-factor solve from the maxima left by k_base_dtn
+// (one thread), then the maxima are cleared for the next stage.
+__device__ __forceinline__ void lagged_check(unsigned long long* __restrict__ chk, double tol, int* __restrict__ status,
+                                             int flag) {
+  if (!chk || threadIdx.x != 0) return;
+  const double mr = __longlong_as_double((long long)chk[0]);
+  const double mb = __longlong_as_double((long long)chk[1]);
+  if (!(mr <= tol * mb)) atomicOr(status, flag);
+  chk[0] = 0ull;
+  chk[1] = 0ull;
+}
+
+// -------------------------------------------------------------------------------------
 // Base right-hand side (Sec. 2.1 eq. (ww), (uv:from:G)), one workgroup:
 //   u = (varphi' - eta_x G phi)/(1 + eta_x^2),  v = (eta_x varphi' + G phi)/(1 + eta_x^2)
 //   eta_t = G phi
@@ -1217,6 +1516,8 @@ __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, 
 // -------------------------------------------------------------------------------------
 __global__ __launch_bounds__(WW_NT) void k_base_rhs(const double* __restrict__ Ys, const double* __restrict__ Gphi,
                                                     double* __restrict__ aux, int nmax, double* __restrict__ Kout,
+                                                    unsigned long long* __restrict__ chk, double chk_tol,
+                                                    int* __restrict__ status,
                                                     const cplx* __restrict__ tw, const double* __restrict__ sig,
                                                     int N, double g, double tau) {
   extern __shared__ cplx lds[];
@@ -1226,6 +1527,7 @@ __global__ __launch_bounds__(WW_NT) void k_base_rhs(const double* __restrict__ Y
   cplx* tws = lds + 3 * N;
   const FftPlan P = make_plan(N);
   const int tid = threadIdx.x;
+  lagged_check(chk, chk_tol, status, 32);
   load_twiddles(tws, tw, N);
   {
     double exv[NPT], psv[NPT], Gv[NPT], etv[NPT];
@@ -1430,6 +1732,8 @@ __global__ void k_status_reset(int* __restrict__ status) {
     status[0] = 0;
     status[1] = 0;
     status[2] = 0x7fffffff;
+    // status[4..7]: the two maxima of the lagged-solve test (k_base_dtn, k_base_rhs)
+    status[4] = status[5] = status[6] = status[7] = 0;
   }
 }
 
@@ -1454,18 +1758,33 @@ __global__ void k_outputs(const double* __restrict__ y, const double* __restrict
   }
 }
 
-// f = r.r / 2: one workgroup, FP64 wavefront reduction
-__global__ __launch_bounds__(WW_NT) void k_objective(const double* __restrict__ r, int N, double* __restrict__ f) {
-  __shared__ double red[WW_NT / 64];
-  double s = 0.0;
-  for (int i = threadIdx.x; i < N; i += WW_NT) s += r[i] * r[i];
-  for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = s;
+// f = r.r / 2 and, when d is given, df/dT = r.d (Sec. 3.2 eq. (dfdT) with d = dr/dT)
+// into f[1]: one workgroup, FP64 wavefront reductions in a fixed order
+__global__ __launch_bounds__(WW_NT) void k_objective(const double* __restrict__ r, int N, double* __restrict__ f,
+                                                     const double* __restrict__ d) {
+  __shared__ double red[2][WW_NT / 64];
+  double s = 0.0, t = 0.0;
+  for (int i = threadIdx.x; i < N; i += WW_NT) {
+    s += r[i] * r[i];
+    if (d) t += r[i] * d[i];
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    s += __shfl_down(s, off, 64);
+    t += __shfl_down(t, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    red[0][threadIdx.x >> 6] = s;
+    red[1][threadIdx.x >> 6] = t;
+  }
   __syncthreads();
   if (threadIdx.x == 0) {
-    double t = 0.0;
-    for (int w = 0; w < WW_NT / 64; ++w) t += red[w];
-    f[0] = 0.5 * t;
+    double a = 0.0, b = 0.0;
+    for (int w = 0; w < WW_NT / 64; ++w) {
+      a += red[0][w];
+      b += red[1][w];
+    }
+    f[0] = 0.5 * a;
+    if (d) f[1] = b;
   }
 }
 

@@ -300,10 +300,15 @@ class Context:
     def profile_read(self, phase: int) -> float:
         """Mean duration (ms) of a phase over every stage of every step replayed since
         the last profile(True): 0 block LU, 1 base chain, 2 column chain."""
+        return self.profile_stats(phase)[0]
+
+    def profile_stats(self, phase: int):
+        """(mean duration in ms, number of intervals) of a phase since the last
+        profile(True)."""
         ms = ctypes.c_double(0.0)
         n = ctypes.c_int(0)
         _check(self.lib.ww_profile_read(self.ptr, phase, ctypes.byref(ms), ctypes.byref(n)))
-        return ms.value
+        return ms.value, n.value
 
     def shoot_adjoint(self, params: torch.Tensor, T: float, nsteps: int, ckpt_every: int = 16):
         M = self.M

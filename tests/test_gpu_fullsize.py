@@ -1,6 +1,27 @@
 """GPU path at the full sizes of the benchmark workloads against stored oracle results
-(tests/golden/*_oracle.npz, written by tests/golden/make_oracle_fixtures.py, which
-calls only the CPU oracle)."""
+(tests/golden/<name>_oracle.npz, written by tests/golden/make_oracle_fixtures.py, which
+calls only the CPU oracle), every Jacobian column compared element by element.
+
+Bounds.  The metric's bar is 1e-12 relative.  Where the FP64 rounding floor of the
+workload exceeds it, the GPU is held to twice that floor.  The floor is the largest
+spread between the oracle and three alternate FP64 roundings of the same scheme
+(cosh/sinh from the math library, the full complex FFT, reversed summation order),
+stored with the fixture.  At C1 and C2 the double-double run shows that this spread
+brackets the oracle's true error (tests/test_oracle_dd.py), which is what lets it stand
+for the floor at C3, C4 and the batched instances:
+  * r, f, dr/dT, the gradient J^T r and J (Frobenius): relative 2-norms, each held to
+    max(1e-12, 2 floor) of its own quantity (dr/dT: 1e-12 times the operator scale,
+    since it is one right-hand-side evaluation at the final state);
+  * J column by column: the largest element error of column k held to
+    max(1e-12 s_k, 2 floor_k), floor_k the largest element spread of that column over
+    the alternates and s_k the column's scale (its largest entry, or its linear-theory
+    amplitude where the mode is near a node at T/4; the largest column for null
+    columns such as the Nyquist mode).
+The mixed form (FP32 LU on MFMA, FP64 refinement) is held to the same bounds: every
+one of its solves ends with a relative FP64 residual below 2^-43 (else the call falls
+back to FP64 factors), which is the normwise backward error an FP64 LU solve has at
+N = 1024 (about N u), and cond(A) <= 2 on these surfaces.
+"""
 import math
 import os
 
@@ -13,12 +34,35 @@ pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 TOL = 1e-12
 
+# prefixes of batched continuation instances at the largest grids: (instance, steps)
+C5_PREFIX = {"c5_16x3": (16, 3), "c5_02x3": (2, 3)}
+# batched instances marched to T/4 with full oracle runs
+C5_FULL = {"c5_00": 0, "c5_07": 7, "c5_08": 8, "c5_26": 26, "c5_27": 27}
+
 
 def _load(name):
     p = os.path.join(GOLDEN, f"{name}_oracle.npz")
     if not os.path.exists(p):
         pytest.skip(f"fixture {p} not generated")
-    return np.load(p)
+    fx = np.load(p)
+    if "J" not in fx.files or "alt_Jcol" not in fx.files:
+        pytest.skip(f"fixture {p} has no full J and floor (regenerate it)")
+    return fx
+
+
+def workload(name):
+    if name in C5_PREFIX:
+        idx, steps = C5_PREFIX[name]
+        w = W.c5()[idx]
+        return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T * steps / w.nsteps, steps, w.params, w.basis,
+                          w.q_fixed)
+    if name in C5_FULL:
+        return W.c5()[C5_FULL[name]]
+    return W.CONFIGS[name]()
+
+
+def _np(res):
+    return {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
 
 
 def _run(name, mixed=False):
@@ -26,23 +70,23 @@ def _run(name, mixed=False):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1210_5672_amd import ww
-    w = W.CONFIGS[name]()
+    w = workload(name)
     ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     res = ctx.shoot_eval(ww.to_dev(w.params), w.T, w.nsteps)
-    return w, {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in res.items()}
+    return w, _np(res), ctx.fallbacks()
 
 
 def lin_amp(w, k):
     """Amplitude of column k of J over the march in linear theory: the seed cos(k x)
-    in eta oscillates with phidot amplitude sqrt((g + tau k^2) / (k tanh kh)), and
-    J carries the weight 1/sqrt(N) (norm sqrt(N/2) for cos(k x)).  Columns that are
-    small at T/4 (the mode is near a node of its oscillation there) are compared on
-    this scale; the Nyquist column (k = N/2, annihilated by d/dx) has none."""
+    in eta oscillates with phidot amplitude sqrt((g + tau k^2) / (k tanh kh)), times
+    the weight 1/sqrt(N).  Columns that are small at T/4 (the mode is near a node of its
+    oscillation there) are compared on this scale; the Nyquist column (k = N/2,
+    annihilated by d/dx) has none."""
     if 2 * k >= w.N:
         return 0.0
     th = 1.0 if math.isinf(w.h) else math.tanh(k * w.h)
-    return math.sqrt(0.5 * (w.g + w.tau * k * k) / (k * th))
+    return math.sqrt((w.g + w.tau * k * k) / (k * th)) / math.sqrt(w.N)
 
 
 def kappa_F(w):
@@ -54,132 +98,115 @@ def kappa_F(w):
                for k in range(1, N // 2))
 
 
-def _floor(name):
-    """FP64 rounding floor of the march at a workload: the spread between the oracle
-    and the same oracle with an alternative (equally valid) rounding of cosh/sinh
-    (<name>_oracle_alt.npz).  None if that run has not been stored."""
-    fx = _load(name)
-    p = os.path.join(GOLDEN, f"{name}_oracle_alt.npz")
-    if not os.path.exists(p):
-        return None
-    fa = np.load(p)
-    rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    return {"r": rel(fa["r"], fx["r"]), "f": abs(float(fa["f"]) - float(fx["f"])) / abs(float(fx["f"])),
-            "J_sampled_frob": rel(fa["Jcols"], fx["Jcols"]),
-            "Jnorms": float(np.abs(fa["Jnorms"] - fx["Jnorms"]).max() / fx["Jnorms"].max()),
-            "grad": rel(fa["grad"], fx["grad"]), "drdT": rel(fa["drdT"], fx["drdT"])}
+def floors(fx):
+    return {k: float(np.max(fx[f"alt_{k}"])) for k in ("r", "f", "drdT", "grad", "Jfro")}
 
 
-def check(fx, w, res, tol, floor=None):
-    """r, f, J (Frobenius over the sampled columns, and all column norms), the
-    gradient J^T r: relative error below tol, or below twice the FP64 rounding floor
-    of the workload when that floor (oracle vs oracle with another rounding) exceeds
-    tol.  Per column, the error on the column's linear-theory amplitude (or, for null
-    columns, on the largest column) is reported and held to 100 tol.  drdT: tol times
-    the operator scale, or twice its floor."""
+def check(fx, w, res, tol=TOL):
     rel = lambda a, b: float(np.linalg.norm(a - b) / np.linalg.norm(b))
-    J = res["J"]
-    cols = fx["cols"]
-    jmax = fx["Jnorms"].max()
-    percol = 0.0
-    for n, c in enumerate(cols):
-        null = fx["Jnorms"][c] < 1e-10 * jmax and lin_amp(w, c + 1) == 0.0
-        scale = jmax if null else max(fx["Jnorms"][c], lin_amp(w, c + 1))
-        percol = max(percol, float(np.linalg.norm(J[:, c] - fx["Jcols"][:, n]) / scale))
-    e = {
-        "r": rel(res["r"], fx["r"]),
-        "f": abs(res["f"] - float(fx["f"])) / abs(float(fx["f"])),
-        "J_sampled_frob": rel(J[:, cols], fx["Jcols"]),
-        "Jnorms": float(np.abs(np.linalg.norm(J, axis=0) - fx["Jnorms"]).max() / jmax),
-        "grad": rel(J.T @ res["r"], fx["grad"]),
-    }
-    e_drdT = rel(res["drdT"], fx["drdT"])
-    bound = {k: max(tol, 2 * floor[k]) if floor else tol for k in e}
-    if floor:
-        # grad = J^T r is a linear image of r: its floor is taken as the larger of the
-        # two single-sample floors (the alternate rounding gives one sample of each)
-        bound["grad"] = max(tol, 2 * floor["grad"], 2 * floor["r"])
-    b_drdT = max(tol * kappa_F(w), 2 * floor["drdT"]) if floor else tol * kappa_F(w)
-    print(w.name, "errors", e, "bounds", bound, "per-column", percol, "drdT", e_drdT, "bound", b_drdT,
-          "floor", floor, flush=True)
+    fl = floors(fx)
+    J, Jo = res["J"], fx["J"]
+    e = {"r": rel(res["r"], fx["r"]), "f": abs(res["f"] - float(fx["f"])) / abs(float(fx["f"])),
+         "drdT": rel(res["drdT"], fx["drdT"]), "grad": rel(J.T @ res["r"], fx["grad"]), "Jfro": rel(J, Jo)}
+    bound = {k: max(tol, 2 * fl[k]) for k in e}
+    bound["drdT"] = max(tol * kappa_F(w), 2 * fl["drdT"])
+    # every column, element by element
+    colmax = np.abs(Jo).max(axis=0)
+    jmax = colmax.max()
+    err_col = np.abs(J - Jo).max(axis=0)
+    floor_col = fx["alt_Jcol"].max(axis=0)
+    scale = np.array([max(colmax[k], lin_amp(w, k + 1)) if lin_amp(w, k + 1) > 0 or colmax[k] > 1e-10 * jmax
+                      else jmax for k in range(J.shape[1])])
+    bcol = np.maximum(tol * scale, 2 * floor_col)
+    worst = int(np.argmax(err_col / bcol))
+    print(w.name, "errors", e, "bounds", bound, "floors", fl,
+          f"columns: worst {worst} err {err_col[worst]:.2e} bound {bcol[worst]:.2e} "
+          f"(1e-12 scale {tol * scale[worst]:.2e}, 2 floor {2 * floor_col[worst]:.2e}); "
+          f"columns above 1e-12 of their scale: {int(np.sum(err_col > tol * scale))} of {J.shape[1]}", flush=True)
     for k in e:
         assert e[k] < bound[k], (k, e[k], bound[k])
-    assert percol < 100 * max(tol, 2 * floor["J_sampled_frob"] if floor else tol), percol
-    assert e_drdT < b_drdT, e_drdT
+    assert np.all(err_col <= bcol), (worst, err_col[worst], bcol[worst])
 
 
 def test_config2_full_fp64():
     fx = _load("c2")
     print("full-size parity c2", flush=True)
-    w, res = _run("c2")
-    check(fx, w, res, TOL)
-
-
-def test_config4_full_fp64_jacobian():
-    fx = _load("c4")
-    print("full-size parity c4", flush=True)
-    w, res = _run("c4")
-    check(fx, w, res, TOL, _floor("c4"))
-
-
-def test_config3_full_fp64():
-    fx = _load("c3")
-    print("full-size parity c3", flush=True)
-    w, res = _run("c3")
-    check(fx, w, res, TOL, _floor("c3"))
-
-
-def test_config3_full_mixed_precision():
-    """Precision form: FP32 block LU on MFMA + FP64 refinement of every solve, against
-    the FP64 oracle; the stated tolerance is the FP64 one, 1e-12."""
-    fx = _load("c3")
-    print("full-size parity c3 mixed", flush=True)
-    w, res = _run("c3", mixed=True)
-    check(fx, w, res, TOL, _floor("c3"))
+    w, res, fb = _run("c2")
+    check(fx, w, res)
 
 
 def test_config2_full_mixed_precision():
     fx = _load("c2")
     print("full-size parity c2 mixed", flush=True)
-    w, res = _run("c2", mixed=True)
-    check(fx, w, res, TOL)
+    w, res, fb = _run("c2", mixed=True)
+    check(fx, w, res)
 
 
-# 3-step prefixes of two batched continuation instances (tests/golden/make_oracle_fixtures.py)
-C5_PREFIX = {"c5_16x3": (16, 3), "c5_02x3": (2, 3)}
+def test_config4_full_fp64_jacobian():
+    fx = _load("c4")
+    print("full-size parity c4", flush=True)
+    w, res, fb = _run("c4")
+    check(fx, w, res)
 
 
-def _c5_prefix(name):
-    idx, steps = C5_PREFIX[name]
-    w = W.c5()[idx]
-    return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T * steps / w.nsteps, steps, w.params, w.basis,
-                      w.q_fixed)
+def test_config3_full_fp64():
+    fx = _load("c3")
+    print("full-size parity c3", flush=True)
+    w, res, fb = _run("c3")
+    check(fx, w, res)
+    assert fb == 0, fb
+
+
+def test_config3_full_mixed_precision():
+    """Precision form: FP32 block LU on MFMA + FP64 refinement of every solve, against
+    the FP64 oracle, held to the FP64 bounds (see the module docstring)."""
+    fx = _load("c3")
+    print("full-size parity c3 mixed", flush=True)
+    w, res, fb = _run("c3", mixed=True)
+    check(fx, w, res)
+    assert fb == 0, fb
+
+
+def _batch(names, mixed=False):
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    ws = [workload(n) for n in names]
+    ctxs, params = [], []
+    for w in ws:
+        c = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed, stream=torch.cuda.Stream())
+        c.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        ctxs.append(c)
+        params.append(ww.to_dev(w.params))
+    torch.cuda.synchronize()
+    outs = ww.shoot_eval_batch(ctxs, params, [w.T for w in ws], [w.nsteps for w in ws])
+    torch.cuda.synchronize()
+    return ws, [_np(o) for o in outs], [c.fallbacks() for c in ctxs]
 
 
 def test_batched_instances_at_the_largest_grids():
     """N = 2048 (the largest grid, 32 block-LU steps) and N = 1536 (radix-3 FFT passes),
     finite depth with surface tension and ragged M, run together through
-    shoot_eval_batch (each on its own context and stream) and each against the oracle,
-    at the instance's own dt.  Both FP64.  With tau k^2 up to 3e4 on the resolved band
-    the FP64 floor of r exceeds 1e-12 at N = 2048; it is measured by the alternate-
-    rounding oracle run and the bound is twice it where it exceeds 1e-12."""
-    import torch
-    if not torch.cuda.is_available():
-        pytest.skip("no GPU")
-    from paper_1210_5672_amd import ww
+    shoot_eval_batch (each on its own context and stream), 3-step prefixes at the
+    instance's own dt, FP64."""
     names = list(C5_PREFIX)
     fxs = [_load(n) for n in names]
-    ws = [_c5_prefix(n) for n in names]
-    ctxs, params = [], []
-    for w in ws:
-        c = ww.Context(n_max=w.N, r_max=w.M + 1, stream=torch.cuda.Stream())
-        c.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
-        ctxs.append(c)
-        params.append(ww.to_dev(w.params))
-    print("batched instances", [(w.N, w.M) for w in ws], flush=True)
-    torch.cuda.synchronize()
-    outs = ww.shoot_eval_batch(ctxs, params, [w.T for w in ws], [w.nsteps for w in ws])
-    torch.cuda.synchronize()
-    for name, fx, w, o in zip(names, fxs, ws, outs):
-        res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in o.items()}
-        check(fx, w, res, TOL, _floor(name))
+    print("batched instances at the largest grids", flush=True)
+    ws, outs, fbs = _batch(names)
+    for fx, w, o in zip(fxs, ws, outs):
+        check(fx, w, o)
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_batched_instances_to_quarter_period(mixed):
+    """Five of the batched continuation instances marched to T/4 together (N = 256 to
+    512 with the radix-3 N = 384, infinite and shallow depth h = 0.198 and 0.254,
+    tension, ragged M, 16 to 140 steps), in one shoot_eval_batch call, each against its
+    full oracle run, in both precision forms."""
+    names = list(C5_FULL)
+    fxs = [_load(n) for n in names]
+    print(f"batched instances to T/4 mixed={mixed}", flush=True)
+    ws, outs, fbs = _batch(names, mixed=mixed)
+    for fx, w, o, fb in zip(fxs, ws, outs, fbs):
+        check(fx, w, o)

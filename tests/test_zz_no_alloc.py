@@ -50,7 +50,7 @@ def test_noalloc_solve_rejects_sizes_beyond_its_workspace():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1210_5672_amd import ww
-    N, nrhs = 2048, 257          # 8 * 2048 * 257 doubles = 33.7 MB > 32 MiB
+    N, nrhs = 2048, 300          # 7 * 2048 * 300 doubles = 34.4 MB > 32 MiB
     print("noalloc size limit", flush=True)
     ctx = ww.Context(n_max=N, r_max=nrhs)
     ctx.dtn_setup(ww.to_dev(W.random_surface(N, seed=3, amp=0.03)), float("inf"))
@@ -59,7 +59,7 @@ def test_noalloc_solve_rejects_sizes_beyond_its_workspace():
         ctx.dtn_solve_multi(rhs, noalloc=True)
     assert ei.value.name == "WW_EINVAL" and "fixed workspace" in str(ei.value)
     # within the limit on the same context: matches the allocating entry point
-    small = ww.to_dev(W.random_rhs(N, 200, seed=6))
+    small = ww.to_dev(W.random_rhs(N, 292, seed=6))
     e = _rel(ctx.dtn_solve_multi(small, noalloc=True), ctx.dtn_solve_multi(small))
-    print(f"  N=2048 nrhs=200: rel diff {e:.2e}", flush=True)
+    print(f"  N=2048 nrhs=292: rel diff {e:.2e}", flush=True)
     assert e < TOL
