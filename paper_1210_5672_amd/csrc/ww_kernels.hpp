@@ -471,22 +471,33 @@ __device__ inline void acc_zero(Acc64<T>& acc) {
     for (int b = 0; b < 2; ++b) acc.v[a][b] = typename Mfma<T>::V{T(0), T(0), T(0), T(0)};
 }
 
+// The operands of a wave are read from LDS a quarter of the inner dimension at a time,
+// all reads of a quarter issued before its MFMAs, so that the MFMAs run back to back
+// instead of each waiting for its own LDS read.
 template <typename T>
 __device__ inline void mfma_tile(const T* As, const T* Bs, Acc64<T>& acc) {
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
-#pragma unroll 4
-  for (int k = 0; k < 64; k += 4) {
-    const T a0 = As[(r0 + li) * TLD + k + lk];
-    const T a1 = As[(r0 + 16 + li) * TLD + k + lk];
-    const T b0 = Bs[(k + lk) * TLD + c0 + li];
-    const T b1 = Bs[(k + lk) * TLD + c0 + 16 + li];
-    acc.v[0][0] = Mfma<T>::step(a0, b0, acc.v[0][0]);
-    acc.v[0][1] = Mfma<T>::step(a0, b1, acc.v[0][1]);
-    acc.v[1][0] = Mfma<T>::step(a1, b0, acc.v[1][0]);
-    acc.v[1][1] = Mfma<T>::step(a1, b1, acc.v[1][1]);
+#pragma unroll
+  for (int h = 0; h < 64; h += 16) {
+    T a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = h + 4 * q;
+      a0[q] = As[(r0 + li) * TLD + k + lk];
+      a1[q] = As[(r0 + 16 + li) * TLD + k + lk];
+      b0[q] = Bs[(k + lk) * TLD + c0 + li];
+      b1[q] = Bs[(k + lk) * TLD + c0 + 16 + li];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc.v[0][0] = Mfma<T>::step(a0[q], b0[q], acc.v[0][0]);
+      acc.v[0][1] = Mfma<T>::step(a0[q], b1[q], acc.v[0][1]);
+      acc.v[1][0] = Mfma<T>::step(a1[q], b0[q], acc.v[1][0]);
+      acc.v[1][1] = Mfma<T>::step(a1[q], b1[q], acc.v[1][1]);
+    }
   }
 }
 
@@ -506,6 +517,83 @@ __device__ inline void acc_to_lds(const Acc64<T>& acc, T* Ts, int mode, T s) {
         if (mode == 0) Ts[rr * TLD + cc] = s * acc.v[a][b][i];
         else Ts[rr * TLD + cc] += s * acc.v[a][b][i];
       }
+}
+
+// The same product with the operands' roles swapped (the MFMA computes (A B)^T), which
+// leaves the result in the column layout: lane (cl = lane & 15, rq = lane >> 4) of wave w
+// holds in acc.v[a][b][i] the entry (r0 + 16 a + cl, c0 + 16 b + Mfma<T>::row(i, rq)),
+// r0 = 32 (w >> 1), c0 = 32 (w & 1).  In that layout the 16 lanes of a row group hold 16
+// consecutive rows of one column, so a column-major tile is read and written straight
+// from and to the accumulators, 128-byte segments per row group.
+template <typename T>
+__device__ inline void mfma_tile_t(const T* As, const T* Bs, Acc64<T>& acc) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int h = 0; h < 64; h += 16) {
+    T a0[4], a1[4], b0[4], b1[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = h + 4 * q;
+      a0[q] = As[(r0 + li) * TLD + k + lk];
+      a1[q] = As[(r0 + 16 + li) * TLD + k + lk];
+      b0[q] = Bs[(k + lk) * TLD + c0 + li];
+      b1[q] = Bs[(k + lk) * TLD + c0 + 16 + li];
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      acc.v[0][0] = Mfma<T>::step(b0[q], a0[q], acc.v[0][0]);
+      acc.v[0][1] = Mfma<T>::step(b1[q], a0[q], acc.v[0][1]);
+      acc.v[1][0] = Mfma<T>::step(b0[q], a1[q], acc.v[1][0]);
+      acc.v[1][1] = Mfma<T>::step(b1[q], a1[q], acc.v[1][1]);
+    }
+  }
+}
+
+// column-major 64 x 64 global tile (leading dimension ld) <-> column-layout accumulators
+template <typename T>
+__device__ inline void acc_load_cm(Acc64<T>& acc, const T* __restrict__ G, size_t ld) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  const int cl = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        acc.v[a][b][i] = G[(size_t)(c0 + 16 * b + Mfma<T>::row(i, rq)) * ld + r0 + 16 * a + cl];
+}
+template <typename T>
+__device__ inline void acc_store_cm(const Acc64<T>& acc, T* __restrict__ G, size_t ld) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  const int cl = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        G[(size_t)(c0 + 16 * b + Mfma<T>::row(i, rq)) * ld + r0 + 16 * a + cl] = acc.v[a][b][i];
+}
+// column-layout accumulators into an LDS tile: T = acc
+template <typename T>
+__device__ inline void acc_t_to_lds(const Acc64<T>& acc, T* Ts) {
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int r0 = (w >> 1) * 32, c0 = (w & 1) * 32;
+  const int cl = lane & 15, rq = lane >> 4;
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int i = 0; i < 4; ++i) Ts[(r0 + 16 * a + cl) * TLD + c0 + 16 * b + Mfma<T>::row(i, rq)] = acc.v[a][b][i];
 }
 
 // -------------------------------------------------------------------------------------
@@ -806,10 +894,24 @@ struct BluGroup {
   BluBufs<T> m[BLU_GMAX];
   int count;
 };
+// Field by field, each a select among kernel-argument values: selecting whole structs
+// makes the compiler copy the argument block into per-lane scratch memory.
 template <typename T>
 __device__ __forceinline__ BluBufs<T> blu_pick(const BluGroup<T>& g, int m) {
-  // uniform selection (no dynamically indexed copy of the argument block)
-  return m == 0 ? g.m[0] : m == 1 ? g.m[1] : m == 2 ? g.m[2] : g.m[3];
+#define BLU_SEL(f) (m == 0 ? g.m[0].f : m == 1 ? g.m[1].f : m == 2 ? g.m[2].f : g.m[3].f)
+  BluBufs<T> b;
+  b.A = BLU_SEL(A);
+  b.X = BLU_SEL(X);
+  b.Z = BLU_SEL(Z);
+  b.V = BLU_SEL(V);
+  b.Dinv = BLU_SEL(Dinv);
+  b.Xr = BLU_SEL(Xr);
+  b.Zr = BLU_SEL(Zr);
+  b.status = BLU_SEL(status);
+  b.Np = BLU_SEL(Np);
+  b.pivguard = BLU_SEL(pivguard);
+#undef BLU_SEL
+  return b;
 }
 
 template <typename T>
@@ -905,9 +1007,11 @@ __host__ __device__ inline int blu_step_tasks(int nb, int k) {
   return n;
 }
 
-// Two LDS tiles per workgroup (two workgroups share a CU): S0 holds the left factor,
-// S1 the right factor of the current tile and then the product.  The result is
-// C + (-(L R)), the same rounding as C - L R accumulated into C.
+// Two LDS tiles per workgroup (two workgroups share a CU): S0 holds the negated left
+// factor -L, S1 the right factor R of the current tile.  The tile C being updated goes
+// from global memory straight into the MFMA accumulators (column layout), which then
+// accumulate -L R and are stored straight back: C - L R summed into C in increasing
+// inner index.  The next tile's R and C are in flight during the current product.
 template <typename T>
 __global__ __launch_bounds__(WW_NT) void k_blu_step(BluGroup<T> g, int k) {
   extern __shared__ double sm_raw[];
@@ -923,27 +1027,23 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluGroup<T> g, int k) {
   if (q == 0) {
     // the next diagonal tile: L = A_{k+1,k} D_k, A_{k+1,k+1} -= L A_{k,k+1}, then its
     // inverse D_{k+1} (the inverse's scratch overlays both slots)
-    T vl[16], vd[16], vr[16], vc[16];
+    T vl[16], vd[16], vr[16];
     tile_fetch<T>(vl, tileptr(b.A, Np, k + 1, k), Np);
     tile_fetch<T>(vd, Dk, 64);
     tile_fetch<T>(vr, tileptr(b.A, Np, k, k + 1), Np);
-    tile_fetch<T>(vc, tileptr(b.A, Np, k + 1, k + 1), Np);
     tile_put<T>(S0, vl);
     tile_put<T>(S1, vd);
     __syncthreads();
     acc_zero(acc);
     mfma_tile(S0, S1, acc);
     __syncthreads();
-    acc_to_lds(acc, S0, 0, T(1));
+    acc_to_lds(acc, S0, 0, T(-1));   // S0 = -L
     tile_put<T>(S1, vr);
+    acc_load_cm<T>(acc, tileptr(b.A, Np, k + 1, k + 1), Np);
     __syncthreads();
-    acc_zero(acc);
-    mfma_tile(S0, S1, acc);
+    mfma_tile_t(S0, S1, acc);
     __syncthreads();
-    acc_to_lds(acc, S0, 0, T(-1));
-    __syncthreads();
-    tile_add_own<T>(S0, vc);
-    __syncthreads();
+    acc_t_to_lds(acc, S0);
     const double mp = blk_gj_inverse<T>(S0, sm);
     if (threadIdx.x == 0 && !(mp >= b.pivguard)) atomicOr(b.status, 1);
     store_dinv<T>(S0, b.Dinv + (size_t)(k + 1) * 4096);   // Z_{k+1,k+1} is stored one step later
@@ -966,10 +1066,40 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluGroup<T> g, int k) {
   if (i < 0 || len <= 0) return;
   const bool low = i > k;      // roles 1 and 2
   const bool ldiag = i == k;   // role 3 on row k: the left factor is D_k
+  const bool vfirst = ldiag;   // V_kj = -D_k A_kj: nothing to accumulate into
+  // the tile (i, j) of position p
+  auto col_of = [&](int p) {
+    if (!low) return k + 1 + p;
+    const int nrt = (i == k + 1) ? nt - 1 : nt;   // tiles right of column k in this row
+    const int jr0 = (i == k + 1) ? k + 2 : k + 1;
+    return p < nrt ? jr0 + p : p - nrt;
+  };
+  auto dst_of = [&](int j) {
+    return (low && j <= k) ? tileptr(b.X, Np, i, j) : (low ? tileptr(b.A, Np, i, j) : tileptr(b.V, Np, i, j));
+  };
+  // right factor (registers) and current value (accumulator layout) of the tile at
+  // position p; the X_ik = -L position reads nothing
+  auto fetch = [&](int p, T (&vr)[16], Acc64<T>& cn) {
+    const int j = col_of(p);
+    const bool role2 = low && j <= k;
+    if (role2 && j == k) return;
+    tile_fetch<T>(vr, role2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j), Np);
+    if (vfirst)
+      acc_zero(cn);
+    else
+      acc_load_cm<T>(cn, dst_of(j), Np);
+  };
+  T vr[16];
+  Acc64<T> cn;
   {
     T vl[16], vd[16];
     tile_fetch<T>(vl, ldiag ? Dk : (low ? tileptr(b.A, Np, i, k) : tileptr(b.V, Np, i, k)), ldiag ? 64 : Np);
     if (!ldiag) tile_fetch<T>(vd, Dk, 64);
+    fetch(p0, vr, cn);
+    if (ldiag) {
+#pragma unroll
+      for (int m = 0; m < 16; ++m) vl[m] = -vl[m];
+    }
     tile_put<T>(S0, vl);
     if (!ldiag) tile_put<T>(S1, vd);
     __syncthreads();
@@ -977,43 +1107,27 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluGroup<T> g, int k) {
       acc_zero(acc);
       mfma_tile(S0, S1, acc);
       __syncthreads();
-      acc_to_lds(acc, S0, 0, T(1));   // S0 = L
-      __syncthreads();
+      acc_to_lds(acc, S0, 0, T(-1));   // S0 = -L
     }
   }
-  if (!low && p0 == 0) tile_store<T, T>(S0, tileptr(b.Z, Np, i, k), Np);   // Z_ik = L (Z_kk = D_k)
+  if (!low && p0 == 0) {
+    __syncthreads();
+    tile_store<T, T>(S0, tileptr(b.Z, Np, i, k), Np, 64, T(-1));   // Z_ik = L (Z_kk = D_k)
+  }
   for (int p = p0; p < p0 + len; ++p) {
-    // the tile (i, j) of position p
-    int j;
-    if (!low) {
-      j = k + 1 + p;
-    } else {
-      const int nrt = (i == k + 1) ? nt - 1 : nt;   // tiles right of column k in this row
-      const int jr0 = (i == k + 1) ? k + 2 : k + 1;
-      j = p < nrt ? jr0 + p : p - nrt;
-    }
-    const bool role2 = low && j <= k;
-    if (role2 && j == k) {   // X_ik = -L (final)
-      tile_store<T, T>(S0, tileptr(b.X, Np, i, k), Np, 64, T(-1));
+    const int j = col_of(p);
+    if (low && j == k) {   // X_ik = -L (final); the last position of its row
+      __syncthreads();
+      tile_store<T, T>(S0, tileptr(b.X, Np, i, k), Np);
       continue;
     }
-    const bool vfirst = ldiag;   // V_kj = -D_k A_kj: nothing to accumulate into
-    T* dst = role2 ? tileptr(b.X, Np, i, j) : (low ? tileptr(b.A, Np, i, j) : tileptr(b.V, Np, i, j));
-    T vr[16], vc[16];
-    tile_fetch<T>(vr, role2 ? tileptr(b.X, Np, k, j) : tileptr(b.A, Np, k, j), Np);
-    if (!vfirst) tile_fetch<T>(vc, dst, Np);
-    __syncthreads();   // S1 is free (the previous tile's product has been stored)
+    __syncthreads();   // S1 is free (every wave is done with the previous product)
     tile_put<T>(S1, vr);
+    acc = cn;
     __syncthreads();
-    acc_zero(acc);
-    mfma_tile(S0, S1, acc);
-    __syncthreads();
-    acc_to_lds(acc, S1, 0, T(-1));   // S1 = -L R
-    __syncthreads();
-    if (vfirst)
-      tile_store<T, T>(S1, dst, Np);
-    else
-      tile_store_sum<T>(S1, vc, dst, Np);
+    if (p + 1 < p0 + len) fetch(p + 1, vr, cn);
+    mfma_tile_t(S0, S1, acc);
+    acc_store_cm<T>(acc, dst_of(j), Np);
   }
 }
 
