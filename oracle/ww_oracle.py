@@ -210,10 +210,26 @@ class ArithAltSum(Arith):
         return scipy.linalg.lu_solve(lu, np.ascontiguousarray(B[::-1]))[::-1]
 
 
+class ArithAltInv(Arith):
+    """The same FP64 arithmetic with every dense solve A x = b done through the explicit
+    inverse, x = inv(A) b (inv from the same pivoted LU): mathematically the same
+    solution, rounded differently (the inverse's own rounding, then one product).  Used
+    only to measure the FP64 rounding floor."""
+
+    name = "f64altinv"
+
+    def lu_factor(self, A):
+        return scipy.linalg.inv(A)
+
+    def lu_solve(self, lu, B):
+        return lu @ B
+
+
 F64 = Arith()
 F64ALT = ArithAlt()
 F64ALT_FFT = ArithAltFFT()
 F64ALT_SUM = ArithAltSum()
+F64ALT_INV = ArithAltInv()
 
 
 # --------------------------------------------------------------------------------

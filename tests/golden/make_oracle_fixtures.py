@@ -12,6 +12,7 @@ tests/golden/raw/NAME_ARITH[_A-B].npz (r, J, drdT, f):
   alt_cs  FP64 with cosh/sinh from the math library instead of from exp(+-y);
   alt_fft FP64 with the Fourier multipliers through the full complex FFT;
   alt_sum FP64 with the summation order of products and of the solve reversed;
+  alt_inv FP64 with every dense solve done through the explicit inverse;
   dd      double-double (about 32 digits), for C1 and C2: the FP64 oracle's error
           itself.  A:B runs Jacobian columns A..B-1 only (the initial state is that of
           all parameters; the columns of the variational march are independent), so
@@ -22,8 +23,8 @@ relative 2-norm differences of r, f, drdT, grad, J (Frobenius) and, per column o
 the largest absolute difference; where a double-double run exists, the same measures
 of the FP64 oracle's error against it (and NAME_dd.npz holds the double-double
 results rounded to doubles).
-`all` runs every job of the listed workloads (default: all of them) in parallel
-processes, one thread each, then combines.  The full set takes about two hours on
+`all` runs every job of the listed workloads (default: all of them) that has no stored
+raw result yet, in parallel processes, one thread each, then combines.  The full set takes about two hours on
 8 cores (C3: 7200 dense N = 1024 solves per run, four runs).
 
 Workloads: c1, c2, c3, c4; c5_IIxS, the first S steps of batched instance II (the
@@ -45,7 +46,7 @@ sys.path.insert(0, ROOT)
 from oracle import ww_oracle as O                 # noqa: E402
 from paper_1210_5672_amd import workloads as W   # noqa: E402
 
-ALTS = ("alt_cs", "alt_fft", "alt_sum")
+ALTS = ("alt_cs", "alt_fft", "alt_sum", "alt_inv")
 
 # prefixes of batched continuation instances at the largest sizes: (instance, steps);
 # the march uses the instance's own dt (T scaled with the step count)
@@ -76,7 +77,8 @@ def arith(tag):
     if tag == "dd":
         from oracle import dd
         return dd.DDArith()
-    return {"f64": O.F64, "alt_cs": O.F64ALT, "alt_fft": O.F64ALT_FFT, "alt_sum": O.F64ALT_SUM}[tag]
+    return {"f64": O.F64, "alt_cs": O.F64ALT, "alt_fft": O.F64ALT_FFT, "alt_sum": O.F64ALT_SUM,
+            "alt_inv": O.F64ALT_INV}[tag]
 
 
 def _raw_path(name, tag, cols=None):
@@ -174,7 +176,8 @@ def jobs_of(name):
 
 
 def run_all(names, nproc):
-    jobs = [j for n in names for j in jobs_of(n)]
+    # runs already stored are kept
+    jobs = [j for n in names for j in jobs_of(n) if not os.path.exists(_raw_path(*j))]
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     running = []
     while jobs or running:

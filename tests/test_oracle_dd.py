@@ -152,7 +152,7 @@ def test_alternate_roundings_bracket_the_fp64_error_at_config1():
     spread = {k: 0.0 for k in true}
     col_true = np.abs(ref["J"] - ddr["J"]).max(axis=0)
     col_spread = np.zeros_like(col_true)
-    for ar in (O.F64ALT, O.F64ALT_FFT, O.F64ALT_SUM):
+    for ar in (O.F64ALT, O.F64ALT_FFT, O.F64ALT_SUM, O.F64ALT_INV):
         alt = run(ar)
         for k, v in _fp64_vs_dd(alt, ref).items():
             spread[k] = max(spread[k], v)
