@@ -156,6 +156,8 @@ struct ww_ctx {
   // stages factored together by one LU launch sequence (environment WW_LU_GROUP,
   // 1..BLU_GMAX; at most the lag)
   int lu_group = 2;
+  int minv_wgs = 1 << 20;                  // workgroup cap of the explicit-inverse launch
+  int graph_parts = 10;                    // parts of a march stage replayed from graphs (bit per part)
   // LU streams (stage s on stream s mod nlus), at most lag; environment WW_LU_STREAMS,
   // by default 3 with the column chains on them, 2 beside the column stream
   int nlus = 3;
@@ -403,6 +405,10 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     if (ns) c->nlus = std::max(1, std::min(PIPE_MAXLUS, std::atoi(ns)));
     const char* lg = std::getenv("WW_LU_GROUP");
     if (lg) c->lu_group = std::max(1, std::min(BLU_GMAX, std::atoi(lg)));
+    const char* gp = std::getenv("WW_GRAPH_PARTS");
+    if (gp) c->graph_parts = std::atoi(gp) & 15;
+    const char* mw = std::getenv("WW_MINV_WGS");
+    if (mw) c->minv_wgs = std::max(1, std::atoi(mw));
     // streams: the working ones first, the capture stream (which never executes) last.
     // HIP shares its few hardware queues among a process's streams, each new stream
     // taking the least-used queue: created in this order, the caller's stream and the
@@ -657,6 +663,8 @@ static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar, const Fac* Fo
 // inverses and the explicit inverse Mi = Z (I + X); with a row order, first the
 // partial-pivoting order and A := P A.  A group (count > 1: consecutive stages of a
 // lagged-factor march, never pivoted) shares every launch of the sequence.
+static int minv_grid(const ww_ctx* c, int ntask) { return std::max(1, std::min(ntask, c->minv_wgs)); }
+
 static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
   int rc;
   if (count < 1 || count > BLU_GMAX) return fail(WW_EHIP, "internal: LU group size");
@@ -675,8 +683,9 @@ static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
     }
     g.count = count;
     if ((rc = enqueue_blu<float>(c, g))) return rc;
-    hipLaunchKernelGGL(k_minv<float>, dim3(nb, nb, count), dim3(WW_NT), 2 * TILE_DBL * sizeof(float), c->stream, mg,
-                       c->Np);
+    mg.count = count;
+    hipLaunchKernelGGL(k_minv<float>, dim3(minv_grid(c, nb * nb * count)), dim3(WW_NT), 2 * TILE_DBL * sizeof(float),
+                       c->stream, mg, c->Np);
   } else {
     BluGroup<double> g{};
     MinvGroup<double> mg{};
@@ -689,8 +698,9 @@ static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
     }
     g.count = count;
     if ((rc = enqueue_blu<double>(c, g))) return rc;
-    hipLaunchKernelGGL(k_minv<double>, dim3(nb, nb, count), dim3(WW_NT), 2 * TILE_DBL * sizeof(double), c->stream,
-                       mg, c->Np);
+    mg.count = count;
+    hipLaunchKernelGGL(k_minv<double>, dim3(minv_grid(c, nb * nb * count)), dim3(WW_NT), 2 * TILE_DBL * sizeof(double),
+                       c->stream, mg, c->Np);
   }
   LAUNCHCHK();
   return prof_mark(c, 0, 1);
@@ -1010,7 +1020,10 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
     hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys, c->coef,
                        s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
     LAUNCHCHK();
-    return enqueue_assemble(c, F, true, &Fo, c->rhs0, c->mu0);
+    // the march reads Gm only row-major (base and column chains): no column-major copy
+    Fac Fa = F;
+    Fa.Gm = nullptr;
+    return enqueue_assemble(c, Fa, true, &Fo, c->rhs0, c->mu0);
   }
   if (part == PP_LU) {
     // the group that ends at this stage (stages of a group are never pivoted)
@@ -1133,7 +1146,7 @@ static int ensure_pipe_graphs(ww_ctx* c) {
 // s - lag + nst of the step before.  The main stream joins the other streams
 // (pipe_join) before the march's outputs are read.
 static int pipe_launch(ww_ctx* c, int s, int part, hipStream_t st, bool graphed) {
-  if (graphed) {
+  if (graphed && (part < 0 || ((c->graph_parts >> part) & 1))) {
     HIPCHK(hipGraphLaunch(part < 0 ? (part == -1 ? c->pgend : c->pgendc) : c->pgx[s][part], st));
     return 0;
   }
@@ -1153,9 +1166,15 @@ static int pipe_step(ww_ctx* c, bool graphed) {
   for (int s = 0; s < nst; ++s) {
     hipStream_t ls = lu_stream(c, s);
     const bool last = s == grp_last(c, s);
-    HIPCHK(hipStreamWaitEvent(s0, c->pcols ? c->evC[s] : c->evL[s], 0));
+    // Each wait is a barrier packet that the command processor takes microseconds to
+    // clear even when its event has long completed, and these sit on the critical path:
+    // a group's sets are released together (its column chains run in stage order, and
+    // its LU records the events of all its stages at once), so the first stage of a
+    // group waits for the whole group and the others wait for nothing.
+    const int q = (s - L + nst) % nst;   // the stage whose factors the lagged solve reads
+    if (s == grp_first(c, s)) HIPCHK(hipStreamWaitEvent(s0, c->pcols ? c->evC[grp_last(c, s)] : c->evL[grp_last(c, s)], 0));
     // the prep part already applies the lagged inverse (the first solve)
-    HIPCHK(hipStreamWaitEvent(s0, c->evL[(s - L + nst) % nst], 0));
+    if (s == 0 || q == grp_first(c, q)) HIPCHK(hipStreamWaitEvent(s0, c->evL[grp_last(c, q)], 0));
     if ((rc = pipe_launch(c, s, PP_PREP, s0, graphed))) return rc;
     if (last) {
       // the LU group of stages grp_first .. s, once the last of them is assembled

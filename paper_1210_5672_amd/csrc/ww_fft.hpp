@@ -15,7 +15,7 @@
 #define WW_NMAX 2048
 #endif
 
-struct cplx {
+struct __attribute__((aligned(16))) cplx {
   double x, y;
 };
 
@@ -125,13 +125,69 @@ __device__ __forceinline__ void fft_pass(const cplx* src, cplx* dst, const cplx*
   }
 }
 
+// The same transform with N a compile-time power of two (the sizes up to WW_NMAX) and
+// 256 threads: the passes are unrolled with their span, radix and layout flags as
+// constants, so that the index arithmetic folds away; the last pass works in place
+// (all of its inputs are read before a barrier, then written), which saves the copy of
+// an odd pass count, and carries the 1/N of the inverse.  Same passes, same butterflies
+// and the same twiddles as fft_lds, hence the same result.
+template <int N, int R, int Ns>
+__device__ __forceinline__ void fft_pass_fixed(const cplx* src, cplx* dst, const cplx* twp, int dir, bool rsw,
+                                               bool wsw, bool inplace, double sc) {
+  constexpr int nb = N / R;
+  constexpr int per = (nb + 255) / 256;   // butterflies per thread
+  cplx v[per][R];
+#pragma unroll
+  for (int u = 0; u < per; ++u) {
+    const int j = threadIdx.x + 256 * u;
+    if (j < nb) fft_load<R>(src, twp, nb, j, j & (Ns - 1), Ns, dir, rsw, v[u]);
+  }
+  if (inplace) __syncthreads();   // every input of the pass has been read
+#pragma unroll
+  for (int u = 0; u < per; ++u) {
+    const int j = threadIdx.x + 256 * u;
+    if (j < nb) {
+      fft_bfly<R>(v[u], dir);
+      const int jm = j & (Ns - 1);
+      const int idxD = (j - jm) * R + jm;
+#pragma unroll
+      for (int q = 0; q < R; ++q) dst[fft_swz(idxD + q * Ns, wsw)] = sc == 1.0 ? v[u][q] : cscale(v[u][q], sc);
+    }
+  }
+}
+
+template <int N, int Ns>
+__device__ __forceinline__ void fft_fixed_from(cplx* a, cplx* b, const cplx* tw, int dir, bool first) {
+  if constexpr (Ns < N) {
+    constexpr int R = (N / Ns) % 4 == 0 ? 4 : 2;
+    constexpr bool last = Ns * R == N;
+    constexpr bool sw = (N & 7) == 0;
+    const cplx* twp = tw + (Ns - 1);
+    // ping-pong a -> b -> a ...; the last pass lands in a (in place when it reads a)
+    constexpr int p = __builtin_ctz(Ns) / 2;   // passes before this one (radix 4 first)
+    const bool from_a = (p & 1) == 0;
+    cplx* src = from_a ? a : b;
+    cplx* dst = last ? a : (from_a ? b : a);
+    const double sc = (last && dir > 0) ? 1.0 / (double)N : 1.0;
+    fft_pass_fixed<N, R, Ns>(src, dst, twp, dir, sw && !first, sw && !last, last && from_a, sc);
+    __syncthreads();
+    fft_fixed_from<N, Ns * R>(a, b, tw, dir, false);
+  }
+}
+
+template <int N>
+__device__ __forceinline__ void fft_fixed(cplx* a, cplx* b, const cplx* tw, int dir) {
+  __syncthreads();
+  fft_fixed_from<N, 1>(a, b, tw, dir, true);
+}
+
 // Transform `a` (N complex in LDS) in place; `b` is LDS scratch of N complex.
 // tw: twiddle table in LDS (load_twiddles) in pass order: the pass with radix R that
 // starts at span Ns reads the N_s R - N_s entries from offset Ns - 1 (the offsets
 // telescope: the table holds N - 1 entries).
 // dir = -1 forward, +1 inverse (inverse also scales by 1/N).
 // Must be called by all threads of the workgroup.  Ends with a barrier.
-__device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& P, int dir) {
+__device__ inline void fft_lds_general(cplx* a, cplx* b, const cplx* tw, const FftPlan& P, int dir) {
   const int N = P.n;
   const int nt = blockDim.x;
   const int tid = threadIdx.x;
@@ -167,6 +223,21 @@ __device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& 
     for (int t = tid; t < N; t += nt) a[t] = cscale(a[t], sc);
   }
   __syncthreads();
+}
+
+// Power-of-two sizes with 256 threads take the unrolled passes, the others the general
+// ones.
+__device__ inline void fft_lds(cplx* a, cplx* b, const cplx* tw, const FftPlan& P, int dir) {
+  if (blockDim.x == 256) {
+    switch (P.n) {
+      case 256: fft_fixed<256>(a, b, tw, dir); return;
+      case 512: fft_fixed<512>(a, b, tw, dir); return;
+      case 1024: fft_fixed<1024>(a, b, tw, dir); return;
+      case 2048: fft_fixed<2048>(a, b, tw, dir); return;
+      default: break;
+    }
+  }
+  fft_lds_general(a, b, tw, P, dir);
 }
 
 // Copy the global twiddle table into LDS (once per kernel, before the first FFT).

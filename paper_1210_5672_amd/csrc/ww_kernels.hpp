@@ -1163,58 +1163,89 @@ __global__ __launch_bounds__(WW_NT) void k_blu_final(BluGroup<T> g) {
 // row-major (the one-vector products read it along rows, the column products read
 // row-major tiles), so that every later solve is one product.  Output tile (i, j):
 //   [i <= j] Z_ij + sum_{m = max(i, j+1)}^{nb-1} Z_im X_mj,
-// one workgroup per tile, the sum in increasing m (fixed order); tiles with the longest
-// sums have the lowest block indices (dispatched first).  The next pair of tiles is in
+// one tile per task, the sum in increasing m (fixed order).  The next pair of tiles is in
 // flight in registers during the MFMAs of the current one.
 // -------------------------------------------------------------------------------------
-// Matrices of a group: grid z (Z, X, Mr of matrix z).
+// Matrices of a group (Z, X, Mr of matrix z).
 template <typename T>
 struct MinvGroup {
   const T* Z[BLU_GMAX];
   const T* X[BLU_GMAX];
   T* Mr[BLU_GMAX];
+  int count;
 };
+
+// Tile of rank r in decreasing order of work: level m = max(i, j + 1) holds the 2m
+// tiles (m, 0..m-1) and (0..m-1, m-1) with nb - m products each (m < nb), level nb the
+// nb tiles (0..nb-1, nb-1) with none; level m starts at rank m (m - 1).
+__host__ __device__ inline void minv_tile(int r, int nb, int& i, int& j) {
+  if (r >= nb * (nb - 1)) {
+    i = r - nb * (nb - 1);
+    j = nb - 1;
+    return;
+  }
+  int m = (int)((1.0 + sqrt(1.0 + 4.0 * (double)r)) * 0.5);
+  while (m > 1 && m * (m - 1) > r) --m;
+  while ((m + 1) * m <= r) ++m;
+  const int idx = r - m * (m - 1);
+  if (idx < m) {
+    i = m;
+    j = idx;
+  } else {
+    i = idx - m;
+    j = m - 1;
+  }
+}
+
+// A fixed grid works through the tiles of every matrix of the group, longest sums
+// first, so that the launch occupies a bounded number of compute units: the inverse is
+// not on the critical path of the march (it is first read `lag` stages later) and the
+// units it leaves free serve the latency-bound base chain.
 template <typename T>
 __global__ __launch_bounds__(WW_NT) void k_minv(MinvGroup<T> gr, int Np) {
   extern __shared__ double sm_raw[];
   T* sm = reinterpret_cast<T*>(sm_raw);
   T* As = sm;
   T* Bs = sm + TILE_DBL;
-  const int z = blockIdx.z;
-  const T* __restrict__ Z = z == 0 ? gr.Z[0] : z == 1 ? gr.Z[1] : z == 2 ? gr.Z[2] : gr.Z[3];
-  const T* __restrict__ X = z == 0 ? gr.X[0] : z == 1 ? gr.X[1] : z == 2 ? gr.X[2] : gr.X[3];
-  T* __restrict__ Mr = z == 0 ? gr.Mr[0] : z == 1 ? gr.Mr[1] : z == 2 ? gr.Mr[2] : gr.Mr[3];
   const int nb = Np / WW_TB;
-  const int j = blockIdx.x, i = blockIdx.y;
-  const int m0 = max(i, j + 1);
-  Acc64<T> acc;
-  acc_zero(acc);
-  T za[16], xb[16];
-  if (m0 < nb) {
-    tile_fetch<T>(za, tileptr(Z, Np, i, m0), Np);
-    tile_fetch<T>(xb, tileptr(X, Np, m0, j), Np);
-  }
-  for (int m = m0; m < nb; ++m) {
-    __syncthreads();
-    tile_put<T>(As, za);
-    tile_put<T>(Bs, xb);
-    __syncthreads();
-    if (m + 1 < nb) {
-      tile_fetch<T>(za, tileptr(Z, Np, i, m + 1), Np);
-      tile_fetch<T>(xb, tileptr(X, Np, m + 1, j), Np);
+  const int ntask = nb * nb * gr.count;
+  for (int task = blockIdx.x; task < ntask; task += gridDim.x) {
+    const int z = task % gr.count;
+    int i, j;
+    minv_tile(task / gr.count, nb, i, j);
+    const T* __restrict__ Z = z == 0 ? gr.Z[0] : z == 1 ? gr.Z[1] : z == 2 ? gr.Z[2] : gr.Z[3];
+    const T* __restrict__ X = z == 0 ? gr.X[0] : z == 1 ? gr.X[1] : z == 2 ? gr.X[2] : gr.X[3];
+    T* __restrict__ Mr = z == 0 ? gr.Mr[0] : z == 1 ? gr.Mr[1] : z == 2 ? gr.Mr[2] : gr.Mr[3];
+    const int m0 = max(i, j + 1);
+    Acc64<T> acc;
+    acc_zero(acc);
+    T za[16], xb[16];
+    if (m0 < nb) {
+      tile_fetch<T>(za, tileptr(Z, Np, i, m0), Np);
+      tile_fetch<T>(xb, tileptr(X, Np, m0, j), Np);
     }
-    mfma_tile(As, Bs, acc);
-  }
-  __syncthreads();
-  if (i <= j) {
-    tile_load<T, T>(As, tileptr(Z, Np, i, j), Np);
+    for (int m = m0; m < nb; ++m) {
+      __syncthreads();
+      tile_put<T>(As, za);
+      tile_put<T>(Bs, xb);
+      __syncthreads();
+      if (m + 1 < nb) {
+        tile_fetch<T>(za, tileptr(Z, Np, i, m + 1), Np);
+        tile_fetch<T>(xb, tileptr(X, Np, m + 1, j), Np);
+      }
+      mfma_tile(As, Bs, acc);
+    }
     __syncthreads();
-    acc_to_lds(acc, As, 1, T(1));
-  } else {
-    acc_to_lds(acc, As, 0, T(1));
+    if (i <= j) {
+      tile_load<T, T>(As, tileptr(Z, Np, i, j), Np);
+      __syncthreads();
+      acc_to_lds(acc, As, 1, T(1));
+    } else {
+      acc_to_lds(acc, As, 0, T(1));
+    }
+    __syncthreads();
+    tile_store_rm<T>(As, rmptr(Mr, Np, i, j), Np);
   }
-  __syncthreads();
-  tile_store_rm<T>(As, rmptr(Mr, Np, i, j), Np);
 }
 
 // -------------------------------------------------------------------------------------
