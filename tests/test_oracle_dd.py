@@ -5,9 +5,10 @@ The backend is pinned against mpmath at 40-50 digits: the elementary operations 
 functions, the Fourier multipliers, the dense solve and a whole short march.  Then
 the FP64 reference is held against the stored double-double march of C1 (all 8
 columns, 64 steps, written by tests/golden/make_oracle_fixtures.py) and, where that
-run has been stored, of C2 (64 columns, 300 steps): the measured floor.  The three
+run has been stored, of C2 (64 columns, 300 steps): the measured floor.  The four
 alternate FP64 roundings (cosh/sinh from the math library, the full complex FFT,
-reversed summation order) are shown to spread about as far as the true FP64 error,
+reversed summation order, solves through the explicit inverse) are shown to spread
+about as far as the true FP64 error,
 which is what lets them stand in for the floor on the workloads too large for a
 double-double run (C3, C4, the batched instances).
 """
@@ -137,7 +138,7 @@ def test_fp64_floor_at_config1_against_double_double():
 
 def test_alternate_roundings_bracket_the_fp64_error_at_config1():
     """Each alternate FP64 rounding differs from the reference by about as much as the
-    reference differs from double-double: the largest spread over the three lies
+    reference differs from double-double: the largest spread over the four lies
     within a factor 10 of the true error, in r, J, f, dr/dT and the gradient, and twice
     it bounds the true error, also per column of J (there up to one rounding of the
     largest entry, 2e-16 of max |J|, where a column's spread happens to vanish)."""
