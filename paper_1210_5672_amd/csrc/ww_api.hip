@@ -445,7 +445,9 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
                              big - (int)fa.sharedSizeBytes));
   }
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
-  CCHK(hipFuncSetAttribute((const void*)k_base_dtn, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_base_rhs_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_base_dtn<16>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_base_dtn<WW_NMAX / 64>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_col_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_step_end, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_adj_pre, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -1017,9 +1019,11 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
     // spectral prep; assembly, and in the same launch the first lagged solve
     // x0 = Mi_old psi, which does not need this stage's matrix
     if ((rc = prof_mark(c, 1, 0))) return rc;
-    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys, c->coef,
-                       s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
-    LAUNCHCHK();
+    if (s == 0) {   // later stages are prepared by the base chain of the stage before
+      hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->y, c->K, c->Ys,
+                         c->coef, s, kstride(c), F.aux, c->n_max, c->rhs0, c->Np, c->tw, c->N, c->hsurf, c->status);
+      LAUNCHCHK();
+    }
     // the march reads Gm only row-major (base and column chains): no column-major copy
     Fac Fa = F;
     Fa.Gm = nullptr;
@@ -1045,12 +1049,22 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
     // gamma, (1/2) H gamma, G phi and the residual of the convergence test in one
     // launch; the test's decision is taken at the start of k_base_rhs
     unsigned long long* chk = (unsigned long long*)(c->status + 4);
-    hipLaunchKernelGGL(k_base_dtn, dim3((c->Np + DTN_ROWS - 1) / DTN_ROWS), dim3(WW_NT), fft_lds_bytes(c->N, 4),
+    hipLaunchKernelGGL(c->N <= 1024 ? k_base_dtn<16> : k_base_dtn<WW_NMAX / 64>, dim3((c->Np + DTN_ROWS - 1) / DTN_ROWS),
+                       dim3(WW_NT), fft_lds_bytes(c->N, 4),
                        c->stream, c->mu0, c->rhs0, F.Gmr, F.Ar, c->Np, c->tw, c->N, c->gphi0, chk);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
-                       c->n_max, c->K + (size_t)s * kstride(c), chk, REFINE_TOL, c->status, c->tw, c->sig, c->N,
-                       c->g, c->tau);
+    if (s + 1 < nst) {
+      // this stage's right-hand side and the next stage's prep in one launch
+      const Fac Fn = pipe_set(c, s + 1, false);
+      hipLaunchKernelGGL(k_base_rhs_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->gphi0, F.aux,
+                         c->K + (size_t)s * kstride(c), chk, REFINE_TOL, c->sig, c->g, c->tau, c->y, c->K, c->Ys,
+                         c->coef, s + 1, kstride(c), Fn.aux, c->rhs0, c->Np, c->hsurf, c->n_max, c->tw, c->N,
+                         c->status);
+    } else {
+      hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
+                         c->n_max, c->K + (size_t)s * kstride(c), chk, REFINE_TOL, c->status, c->tw, c->sig, c->N,
+                         c->g, c->tau);
+    }
     LAUNCHCHK();
     return prof_mark(c, 1, 1);
   }

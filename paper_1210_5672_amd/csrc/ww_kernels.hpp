@@ -136,18 +136,13 @@ __global__ void k_init_state(double* __restrict__ y, const double* __restrict__ 
 // data varphi into column 0 of the solve array (rows N..Np-1 zero).
 // Dynamic LDS: 4 N complex (three work buffers and the twiddles).
 // -------------------------------------------------------------------------------------
-__global__ __launch_bounds__(WW_NT) void k_base_prep(
-    const double* __restrict__ y, const double* __restrict__ K, double* __restrict__ Ys,
-    const double* __restrict__ coef, int stage, size_t kstride, double* __restrict__ aux, int nmax,
-    double* __restrict__ rhs0, int Np, const cplx* __restrict__ tw, int N, double hsurf, int* __restrict__ status) {
-  extern __shared__ cplx lds[];
-  cplx* Z = lds;
-  cplx* W = lds + N;
-  cplx* S = lds + 2 * N;
-  cplx* tws = lds + 3 * N;
-  const FftPlan P = make_plan(N);
+// The prep of one stage on LDS work buffers Z, W, S and the twiddles tws (loaded).
+__device__ inline void base_prep_stage(cplx* Z, cplx* W, cplx* S, const cplx* tws, const FftPlan& P,
+                                       const double* __restrict__ y, const double* __restrict__ K,
+                                       double* __restrict__ Ys, const double* __restrict__ coef, int stage,
+                                       size_t kstride, double* __restrict__ aux, int nmax, double* __restrict__ rhs0,
+                                       int Np, int N, double hsurf, int* __restrict__ status) {
   const int tid = threadIdx.x;
-  load_twiddles(tws, tw, N);
   double ev[NPT], pv[NPT];
   stage_combine_vec(ev, y, K, kstride, 0, coef + stage * 16, stage, N);
   stage_combine_vec(pv, y, K, kstride, N, coef + stage * 16, stage, N);
@@ -198,6 +193,21 @@ __global__ __launch_bounds__(WW_NT) void k_base_prep(
     atomicOr(status, (bad ? 2 : 0) | (bed ? 16 : 0));
     atomicMin(status + 2, status[1] * 16 + stage);
   }
+}
+
+__global__ __launch_bounds__(WW_NT) void k_base_prep(
+    const double* __restrict__ y, const double* __restrict__ K, double* __restrict__ Ys,
+    const double* __restrict__ coef, int stage, size_t kstride, double* __restrict__ aux, int nmax,
+    double* __restrict__ rhs0, int Np, const cplx* __restrict__ tw, int N, double hsurf, int* __restrict__ status) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* S = lds + 2 * N;
+  cplx* tws = lds + 3 * N;
+  const FftPlan P = make_plan(N);
+  const int tid = threadIdx.x;
+  load_twiddles(tws, tw, N);
+  base_prep_stage(Z, W, S, tws, P, y, K, Ys, coef, stage, kstride, aux, nmax, rhs0, Np, N, hsurf, status);
 }
 
 // -------------------------------------------------------------------------------------
@@ -1542,7 +1552,9 @@ __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, 
 // clears chk.  Rows N..Np-1 of Gphi are zero.  Dynamic LDS: 4 N complex.
 // -------------------------------------------------------------------------------------
 #define DTN_ROWS 8                 // rows per workgroup (two per wave)
-#define DTN_NR (WW_NMAX / 64)      // entries of a row per lane
+// NR: entries of a row per lane, N <= 64 NR (16 up to N = 1024, 32 above), so that the
+// row prefetch holds no more registers than the grid needs.
+template <int NR>
 __global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ mu, const double* __restrict__ psi,
                                                     const double* __restrict__ Gmr, const double* __restrict__ Ar,
                                                     int Np, const cplx* __restrict__ tw, int N,
@@ -1558,13 +1570,13 @@ __global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ m
   const int lane = tid & 63, wv = tid >> 6;
   // a row's entries of Gm and A, all in flight at once (clamped, unconditional loads);
   // the first row's loads are issued before the transforms, which they do not need
-  double gv[DTN_NR], av[DTN_NR];
+  double gv[NR], av[NR];
   auto load_row = [&](int row) {
     const int rr = row < N ? row : N - 1;
     const double* gr = Gmr + (size_t)rr * Np;
     const double* ar = Ar + (size_t)rr * Np;
 #pragma unroll
-    for (int m = 0; m < DTN_NR; ++m) {
+    for (int m = 0; m < NR; ++m) {
       const int j = lane + 64 * m;
       const int jj = j < N ? j : N - 1;
       gv[m] = gr[jj];
@@ -1610,7 +1622,7 @@ __global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ m
     }
     double s0 = 0.0, s1 = 0.0, t0 = 0.0, t1 = 0.0;
 #pragma unroll
-    for (int m = 0; m < DTN_NR; m += 2) {
+    for (int m = 0; m < NR; m += 2) {
       const int j0 = lane + 64 * m, j1 = j0 + 64;
       if (j0 < N) {
         s0 = fma(gv[m], gs[j0], s0);
@@ -1659,21 +1671,12 @@ __device__ __forceinline__ void lagged_check(unsigned long long* __restrict__ ch
 //   varphi_t = P[v eta_t - u^2/2 - v^2/2 - g eta + tau d/dx(eta_x/sqrt(1 + eta_x^2))]
 // both filtered; u, v, (1 + eta_x^2)^{3/2} are kept for the variational columns.
 // -------------------------------------------------------------------------------------
-__global__ __launch_bounds__(WW_NT) void k_base_rhs(const double* __restrict__ Ys, const double* __restrict__ Gphi,
-                                                    double* __restrict__ aux, int nmax, double* __restrict__ Kout,
-                                                    unsigned long long* __restrict__ chk, double chk_tol,
-                                                    int* __restrict__ status,
-                                                    const cplx* __restrict__ tw, const double* __restrict__ sig,
-                                                    int N, double g, double tau) {
-  extern __shared__ cplx lds[];
-  cplx* Z = lds;
-  cplx* W = lds + N;
-  cplx* S = lds + 2 * N;
-  cplx* tws = lds + 3 * N;
-  const FftPlan P = make_plan(N);
+// The right-hand side of one stage on LDS work buffers Z, W, S and the twiddles tws.
+__device__ inline void base_rhs_stage(cplx* Z, cplx* W, cplx* S, const cplx* tws, const FftPlan& P,
+                                      const double* __restrict__ Ys, const double* __restrict__ Gphi,
+                                      double* __restrict__ aux, int nmax, double* __restrict__ Kout,
+                                      const double* __restrict__ sig, int N, double g, double tau) {
   const int tid = threadIdx.x;
-  lagged_check(chk, chk_tol, status, 32);
-  load_twiddles(tws, tw, N);
   {
     double exv[NPT], psv[NPT], Gv[NPT], etv[NPT];
     gload(exv, aux + AUX_EX * nmax, N);
@@ -1717,6 +1720,47 @@ __global__ __launch_bounds__(WW_NT) void k_base_rhs(const double* __restrict__ Y
     Kout[t] = W[t].x;
     Kout[N + t] = W[t].y;
   }
+}
+
+__global__ __launch_bounds__(WW_NT) void k_base_rhs(const double* __restrict__ Ys, const double* __restrict__ Gphi,
+                                                    double* __restrict__ aux, int nmax, double* __restrict__ Kout,
+                                                    unsigned long long* __restrict__ chk, double chk_tol,
+                                                    int* __restrict__ status,
+                                                    const cplx* __restrict__ tw, const double* __restrict__ sig,
+                                                    int N, double g, double tau) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* S = lds + 2 * N;
+  cplx* tws = lds + 3 * N;
+  const FftPlan P = make_plan(N);
+  const int tid = threadIdx.x;
+  lagged_check(chk, chk_tol, status, 32);
+  load_twiddles(tws, tw, N);
+  base_rhs_stage(Z, W, S, tws, P, Ys, Gphi, aux, nmax, Kout, sig, N, g, tau);
+}
+
+// The right-hand side of stage s and, in the same workgroup, the prep of stage s + 1
+// (s + 1 < stages of the step): one launch and one twiddle load fewer on the march's
+// critical path.  The prep reads K_s through global memory after a barrier.
+__global__ __launch_bounds__(WW_NT) void k_base_rhs_prep(
+    const double* __restrict__ Gphi, double* __restrict__ aux_cur, double* __restrict__ Kcur,
+    unsigned long long* __restrict__ chk, double chk_tol, const double* __restrict__ sig, double g, double tau,
+    const double* __restrict__ y, const double* __restrict__ K, double* __restrict__ Ys,
+    const double* __restrict__ coef, int stage_next, size_t kstride, double* __restrict__ aux_next,
+    double* __restrict__ rhs0, int Np, double hsurf, int nmax, const cplx* __restrict__ tw, int N,
+    int* __restrict__ status) {
+  extern __shared__ cplx lds[];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* S = lds + 2 * N;
+  cplx* tws = lds + 3 * N;
+  const FftPlan P = make_plan(N);
+  lagged_check(chk, chk_tol, status, 32);
+  load_twiddles(tws, tw, N);
+  base_rhs_stage(Z, W, S, tws, P, Ys, Gphi, aux_cur, nmax, Kcur, sig, N, g, tau);
+  __syncthreads();   // K_s (global) and the LDS buffers are complete
+  base_prep_stage(Z, W, S, tws, P, y, K, Ys, coef, stage_next, kstride, aux_next, nmax, rhs0, Np, N, hsurf, status);
 }
 
 // -------------------------------------------------------------------------------------
