@@ -1429,7 +1429,10 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_rm(const T* __restrict__ M, in
       bv[m] = cc < R ? B[(size_t)cc * Np + k0 + kk] : 0.0;
     }
   };
+  // two accumulators (even and odd 4-steps of the inner dimension): two independent
+  // MFMA chains per wave, summed once at the end
   V acc = V{T(0), T(0), T(0), T(0)};
+  V acc1 = V{T(0), T(0), T(0), T(0)};
   const int nsteps = Np / GK;
   if (grp < nsteps) fetch(grp * GK);
   // every group runs the same number of iterations (barriers are workgroup-wide); a
@@ -1450,13 +1453,23 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_rm(const T* __restrict__ M, in
     if (have && st + GSPLIT < nsteps) fetch((st + GSPLIT) * GK);
     if (have) {
 #pragma unroll
-      for (int k = 0; k < GK; k += 4) {
-        const T a = as[(wr + li) * GA_LD + k + lk];
-        const T b = bs[(wc + li) * GA_LD + k + lk];
-        acc = Mfma<T>::step(a, b, acc);
+      for (int h = 0; h < GK; h += 32) {
+        T a[8], b[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          a[q] = as[(wr + li) * GA_LD + h + 4 * q + lk];
+          b[q] = bs[(wc + li) * GA_LD + h + 4 * q + lk];
+        }
+#pragma unroll
+        for (int q = 0; q < 8; q += 2) {
+          acc = Mfma<T>::step(a[q], b[q], acc);
+          acc1 = Mfma<T>::step(a[q + 1], b[q + 1], acc1);
+        }
       }
     }
   }
+#pragma unroll
+  for (int i = 0; i < 4; ++i) acc[i] += acc1[i];
   __syncthreads();   // every group is done with its operand tiles
 #pragma unroll
   for (int i = 0; i < 4; ++i) Cs[grp][(wc + li) * (GT + 1) + wr + Mfma<T>::row(i, lk)] = (double)acc[i];
