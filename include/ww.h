@@ -367,6 +367,34 @@ int ww_bfgs(ww_ctx *ctx, double *c, int nsteps, const ww_bfgs_opts *opts, ww_bfg
  */
 unsigned ww_next_fallback(unsigned flags, unsigned fb, int status);
 
+/*
+ * Launch and scheduling choices of a context (none changes what is computed, only how
+ * the work is cut into launches and streams; the defaults are those of ww_create, or of
+ * the WW_* environment knobs read there).  The project's autotuner
+ * (paper_1210_5672_amd/autotune.py) times short marches over these choices and keeps
+ * the fastest per (N, M, precision, GPU architecture) in a JSON cache.
+ *   lag          lagged-factor march: the base solve of stage s uses the explicit
+ *                inverse of stage s - lag (0: each stage's own factors), 0..11
+ *   lu_group     consecutive stages factored by one launch sequence, 1..4 (<= lag)
+ *   lu_streams   streams the LU groups rotate over, 1..6
+ *   graph_parts  march parts replayed from HIP graphs, one bit each: 1 prep and
+ *                assembly, 2 LU, 4 base chain, 8 column chain (the rest launched
+ *                directly), 0..15
+ *   minv_wgs     workgroup cap of the explicit-inverse launch, >= 1
+ *   blu_strip    64-tiles per task of a block-LU step, 1..16
+ *   dtn_rows     rows per workgroup of the base DtN launch, 4..32, a multiple of 4
+ *   gemm_split   wave groups splitting the inner dimension of a column product, 2 or 4
+ *   asm_cw       columns per assembly workgroup, 16 or 32
+ * ww_set_tuning validates every field and applies them together (captured graphs are
+ * re-captured at the next march); ww_get_tuning reads the current choices.  Host only.
+ * Errors: WW_EINVAL (null argument, a field out of range).
+ */
+typedef struct ww_tuning {
+  int lag, lu_group, lu_streams, graph_parts, minv_wgs, blu_strip, dtn_rows, gemm_split, asm_cw;
+} ww_tuning;
+int ww_get_tuning(ww_ctx *ctx, ww_tuning *t);
+int ww_set_tuning(ww_ctx *ctx, const ww_tuning *t);
+
 /* thread-local message of the last failure on this thread ("" if none) */
 const char *ww_last_error(void);
 

@@ -158,6 +158,12 @@ struct ww_ctx {
   int lu_group = 2;
   int minv_wgs = 1 << 20;                  // workgroup cap of the explicit-inverse launch
   int graph_parts = 10;                    // parts of a march stage replayed from graphs (bit per part)
+  int blu_strip = 4;                       // tiles per strip task of a block-LU step
+  int dtn_rows = 8;                        // rows per workgroup of the base DtN launch
+  int gemm_split = 4;                      // wave groups splitting the inner dimension of a product
+  int asm_cw = 16;                         // columns per assembly workgroup
+  int tune_gen = 0;                        // bumped by ww_set_tuning (graphs are re-captured)
+  int gtune = -1;                          // tune_gen of the captured step graph
   // LU streams (stage s on stream s mod nlus), at most lag; environment WW_LU_STREAMS,
   // by default 3 with the column chains on them, 2 beside the column stream
   int nlus = 3;
@@ -490,6 +496,44 @@ void ww_destroy(ww_ctx* c) {
   delete c;
 }
 
+int ww_get_tuning(ww_ctx* c, ww_tuning* t) {
+  if (!c || !t) return fail(WW_EINVAL, "null argument");
+  t->lag = c->lag;
+  t->lu_group = c->lu_group;
+  t->lu_streams = c->nlus;
+  t->graph_parts = c->graph_parts;
+  t->minv_wgs = c->minv_wgs;
+  t->blu_strip = c->blu_strip;
+  t->dtn_rows = c->dtn_rows;
+  t->gemm_split = c->gemm_split;
+  t->asm_cw = c->asm_cw;
+  return 0;
+}
+
+int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
+  if (!c || !t) return fail(WW_EINVAL, "null argument");
+  if (t->lag < 0 || t->lag > PIPE_MAXLAG) return fail(WW_EINVAL, "tuning: lag out of range");
+  if (t->lu_group < 1 || t->lu_group > BLU_GMAX) return fail(WW_EINVAL, "tuning: lu_group out of range");
+  if (t->lu_streams < 1 || t->lu_streams > PIPE_MAXLUS) return fail(WW_EINVAL, "tuning: lu_streams out of range");
+  if (t->graph_parts < 0 || t->graph_parts > 15) return fail(WW_EINVAL, "tuning: graph_parts out of range");
+  if (t->minv_wgs < 1) return fail(WW_EINVAL, "tuning: minv_wgs out of range");
+  if (t->blu_strip < 1 || t->blu_strip > BLU_STRIP_MAX) return fail(WW_EINVAL, "tuning: blu_strip out of range");
+  if (t->dtn_rows < 4 || t->dtn_rows > 32 || t->dtn_rows % 4) return fail(WW_EINVAL, "tuning: dtn_rows out of range");
+  if (t->gemm_split != 2 && t->gemm_split != 4) return fail(WW_EINVAL, "tuning: gemm_split must be 2 or 4");
+  if (t->asm_cw != 16 && t->asm_cw != 32) return fail(WW_EINVAL, "tuning: asm_cw must be 16 or 32");
+  c->lag = t->lag;
+  c->lu_group = t->lu_group;
+  c->nlus = t->lu_streams;
+  c->graph_parts = t->graph_parts;
+  c->minv_wgs = t->minv_wgs;
+  c->blu_strip = t->blu_strip;
+  c->dtn_rows = t->dtn_rows;
+  c->gemm_split = t->gemm_split;
+  c->asm_cw = t->asm_cw;
+  ++c->tune_gen;
+  return 0;
+}
+
 int ww_set_stream(ww_ctx* c, void* s) {
   if (!c) return fail(WW_EINVAL, "ctx is null");
   c->stream = (hipStream_t)s;
@@ -545,7 +589,7 @@ static int enqueue_blu(ww_ctx* c, const BluGroup<T>& g) {
   hipLaunchKernelGGL(k_blu_init<T>, dim3(g.count), dim3(WW_NT), (TILE_DBL + GJ_SCR) * es, c->stream, g);
   LAUNCHCHK();
   for (int k = 0; k + 1 < nb; ++k) {
-    const int nblk = blu_step_tasks(nb, k);
+    const int nblk = blu_step_tasks(nb, k, g.strip);
     hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk * g.count), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, g, k);
     LAUNCHCHK();
   }
@@ -653,10 +697,11 @@ static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar, const Fac* Fo
   const double* mx64 = (Fo && !Fo->use32) ? Fo->Mi : nullptr;
   const float* mx32 = (Fo && Fo->use32) ? Fo->Mi32 : nullptr;
   if (Fo && !(mx64 || mx32)) return fail(WW_EHIP, "internal: lagged first solve without its inverse");
-  const int gy = c->Np / ASM_CW + (Fo ? 16 : 0);
-  hipLaunchKernelGGL(k_assemble, dim3(nb, gy), dim3(WW_NT), 0, c->stream, F.aux, c->n_max, c->cosT, c->sinT, c->c0T,
-                     F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, (F.use32 || want_ar) ? F.Ar : nullptr, c->N, c->Np,
-                     c->finite, mx64, mx32, psi, x0);
+  const int cw = c->asm_cw == 32 ? 32 : 16;
+  const int gy = c->Np / cw + (Fo ? 16 : 0);
+  hipLaunchKernelGGL(cw == 32 ? k_assemble<32> : k_assemble<16>, dim3(nb, gy), dim3(WW_NT), 0, c->stream, F.aux,
+                     c->n_max, c->cosT, c->sinT, c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr,
+                     (F.use32 || want_ar) ? F.Ar : nullptr, c->N, c->Np, c->finite, mx64, mx32, psi, x0);
   LAUNCHCHK();
   return 0;
 }
@@ -684,6 +729,7 @@ static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
       mg.Mr[q] = F[q].Mi32;
     }
     g.count = count;
+    g.strip = c->blu_strip;
     if ((rc = enqueue_blu<float>(c, g))) return rc;
     mg.count = count;
     hipLaunchKernelGGL(k_minv<float>, dim3(minv_grid(c, nb * nb * count)), dim3(WW_NT), 2 * TILE_DBL * sizeof(float),
@@ -699,6 +745,7 @@ static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
       mg.Mr[q] = F[q].Mi;
     }
     g.count = count;
+    g.strip = c->blu_strip;
     if ((rc = enqueue_blu<double>(c, g))) return rc;
     mg.count = count;
     hipLaunchKernelGGL(k_minv<double>, dim3(minv_grid(c, nb * nb * count)), dim3(WW_NT), 2 * TILE_DBL * sizeof(double),
@@ -730,7 +777,11 @@ static int enqueue_gemm(ww_ctx* c, const T* Mr, int mode, const double* B, const
     return 0;
   }
   if (mode & 3) return fail(WW_EHIP, "internal: triangular product of several columns");
-  hipLaunchKernelGGL(k_gemm_rm<T>, dim3(c->Np / GT, (R + GT - 1) / GT), dim3(GEMM_NT), 0, c->stream, Mr, c->Np, B, R,
+  if (c->gemm_split == 2)
+    hipLaunchKernelGGL((k_gemm_rm<T, 2>), dim3(c->Np / GT, (R + GT - 1) / GT), dim3(512), 0, c->stream, Mr, c->Np, B, R,
+                     add, sgn, out);
+  else
+    hipLaunchKernelGGL((k_gemm_rm<T, 4>), dim3(c->Np / GT, (R + GT - 1) / GT), dim3(1024), 0, c->stream, Mr, c->Np, B, R,
                      add, sgn, out);
   LAUNCHCHK();
   return 0;
@@ -1049,9 +1100,9 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
     // gamma, (1/2) H gamma, G phi and the residual of the convergence test in one
     // launch; the test's decision is taken at the start of k_base_rhs
     unsigned long long* chk = (unsigned long long*)(c->status + 4);
-    hipLaunchKernelGGL(c->N <= 1024 ? k_base_dtn<16> : k_base_dtn<WW_NMAX / 64>, dim3((c->Np + DTN_ROWS - 1) / DTN_ROWS),
-                       dim3(WW_NT), fft_lds_bytes(c->N, 4),
-                       c->stream, c->mu0, c->rhs0, F.Gmr, F.Ar, c->Np, c->tw, c->N, c->gphi0, chk);
+    hipLaunchKernelGGL(c->N <= 1024 ? k_base_dtn<16> : k_base_dtn<WW_NMAX / 64>,
+                       dim3((c->Np + c->dtn_rows - 1) / c->dtn_rows), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream,
+                       c->mu0, c->rhs0, F.Gmr, F.Ar, c->Np, c->tw, c->N, c->gphi0, chk, c->dtn_rows);
     LAUNCHCHK();
     if (s + 1 < nst) {
       // this stage's right-hand side and the next stage's prep in one launch
@@ -1105,8 +1156,8 @@ static int capture_part(ww_ctx* c, int s, int part, hipGraphExec_t* out) {
 }
 
 static long long pipe_key(const ww_ctx* c) {
-  return ((((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 16 + c->lag) * 8 + lu_group(c)) * 2 + (c->prof ? 1 : 0)) *
-             16 + c->fb;
+  return (((((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 16 + c->lag) * 8 + lu_group(c)) * 2 + (c->prof ? 1 : 0)) *
+              16 + c->fb) * 1024 + (c->tune_gen & 1023);
 }
 
 static int ensure_pipe_graphs(ww_ctx* c) {
@@ -1278,7 +1329,8 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
 // coefficients live in device memory, so T and the parameters may change freely.
 static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   if (c->step_exec && c->gN == c->N && c->gM == c->M && c->gcols == (int)cols && c->gnst == c->nst &&
-      c->gtwo == (int)two_streams && c->gfb == c->fb && c->ggm == (c->gm_active ? c->gm_m : 0))
+      c->gtwo == (int)two_streams && c->gfb == c->fb && c->ggm == (c->gm_active ? c->gm_m : 0) &&
+      c->gtune == c->tune_gen)
     return 0;
   if (c->step_exec) {
     HIPCHK(hipDeviceSynchronize());   // every branch of its last replay has ended
@@ -1307,6 +1359,7 @@ static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   c->gnst = c->nst;
   c->gfb = c->fb;
   c->ggm = c->gm_active ? c->gm_m : 0;
+  c->gtune = c->tune_gen;
   return 0;
 }
 

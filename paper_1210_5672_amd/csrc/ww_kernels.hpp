@@ -276,13 +276,14 @@ __device__ __forceinline__ void cot_half_branch(double cx, double sx, double chy
   }
 }
 
-// Launch: grid (Np / 64, Np / 16): one workgroup per strip of 64 rows x 16 columns,
-// four workgroups per 64-tile, so that enough waves are resident to hide the latency
-// of the dependent FP64 chains (divisions of the cot branch formula).
-#define ASM_CW 16   // columns per assembly workgroup
+// Launch: grid (Np / 64, Np / ASM_CW): one workgroup per strip of 64 rows x ASM_CW
+// columns, several workgroups per 64-tile, so that enough waves are resident to hide
+// the latency of the dependent FP64 chains (divisions of the cot branch formula).
 // With a lagged inverse (Mx64 or Mx32, row-major), 16 more rows of workgroups follow
 // the assembly grid: they form x0 = Mx psi (the first solve of the lagged-factor base
 // chain, which does not need this stage's matrix), one wave per row.
+// ASM_CW: columns per assembly workgroup (16 or 32)
+template <int ASM_CW>
 __global__ __launch_bounds__(WW_NT) void k_assemble(
     const double* __restrict__ aux, int nmax, const double* __restrict__ cosT,
     const double* __restrict__ sinT, const double* __restrict__ c0T, double* __restrict__ A,
@@ -903,6 +904,7 @@ template <typename T>
 struct BluGroup {
   BluBufs<T> m[BLU_GMAX];
   int count;
+  int strip;   // tiles per strip task of a step (1..BLU_STRIP_MAX)
 };
 // Field by field, each a select among kernel-argument values: selecting whole structs
 // makes the compiler copy the argument block into per-lane scratch memory.
@@ -1000,20 +1002,20 @@ __device__ inline void tile_store_sum(const T* Ts, const T (&v)[16], T* __restri
 
 // Tasks of step k (per matrix of a group).  Task 0 updates the next diagonal tile
 // (k+1, k+1) and inverts it (the critical path of the factorisation).  Every other task
-// is a strip of at most BLU_STRIP tiles of one row i: it forms the row's left factor
+// is a strip of at most `strip` tiles of one row i: it forms the row's left factor
 // once (A_ik D_k for i > k; V_ik D_k for i < k; D_k itself for i = k) and applies it to
 // each tile of its strip, so no product is repeated across the tiles of a row.  Row i
 // > k runs over j = k+1 .. nb-1 (role 1: A_ij -= L A_kj; row k+1 without the diagonal
 // tile) and then j = 0 .. k (role 2: X_ik = -L, X_ij -= L X_kj); row i <= k over
 // j = k+1 .. nb-1 (role 3: V_ij -= L A_kj, V_kj = -D_k A_kj; the strip starting at
 // j = k+1 also stores Z_ik = L).
-#define BLU_STRIP 4
+#define BLU_STRIP_MAX 16
 __host__ __device__ inline int blu_row_len(int nb, int k, int i) {
   return i > k ? (i == k + 1 ? nb - 1 : nb) : nb - k - 1;
 }
-__host__ __device__ inline int blu_step_tasks(int nb, int k) {
+__host__ __device__ inline int blu_step_tasks(int nb, int k, int strip) {
   int n = 1;
-  for (int i = 0; i < nb; ++i) n += (blu_row_len(nb, k, i) + BLU_STRIP - 1) / BLU_STRIP;
+  for (int i = 0; i < nb; ++i) n += (blu_row_len(nb, k, i) + strip - 1) / strip;
   return n;
 }
 
@@ -1064,11 +1066,11 @@ __global__ __launch_bounds__(WW_NT) void k_blu_step(BluGroup<T> g, int k) {
   int i = -1, p0 = 0, len = 0;
   for (int r = 0; r < nb; ++r) {
     const int n = blu_row_len(nb, k, r);
-    const int ch = (n + BLU_STRIP - 1) / BLU_STRIP;
+    const int ch = (n + g.strip - 1) / g.strip;
     if (q < ch) {
       i = r;
-      p0 = q * BLU_STRIP;
-      len = min(BLU_STRIP, n - p0);
+      p0 = q * g.strip;
+      len = min(g.strip, n - p0);
       break;
     }
     q -= ch;
@@ -1382,21 +1384,20 @@ __global__ __launch_bounds__(WW_NT) void k_gemv_row(const T* __restrict__ Mr, in
 // -------------------------------------------------------------------------------------
 // Product with a row-major matrix for R right-hand sides:  out = add + sgn * M B
 // (M: Np x Np row-major, element type T; B, add, out: Np x R column-major doubles,
-// ld Np; B is rounded to T on load).  One workgroup of 16 waves per 32 x 32 output
-// tile: the inner dimension is split over four wave groups (group g takes the 64-wide
-// steps g, g + 4, ...), in each group wave w computes the 16 x 16 quadrant
+// ld Np; B is rounded to T on load).  One workgroup of 4 GSPLIT waves per 32 x 32
+// output tile: the inner dimension is split over GSPLIT wave groups (group g takes the
+// 64-wide steps g, g + GSPLIT, ...), in each group wave w computes the 16 x 16 quadrant
 // (w >> 1, w & 1) with 16 x 16 x 4 MFMAs, the next step's operands in flight in
-// registers during the MFMAs; the four partial tiles are summed in LDS in a fixed
-// order, ((g0 + g1) + g2) + g3, so each entry is one deterministic sum (no partials
-// in memory, no second launch).  The result is stored along the columns.
+// registers during the MFMAs; the partial tiles are summed in LDS in a fixed order,
+// ((g0 + g1) + g2) + g3, so each entry is one deterministic sum (no partials in
+// memory, no second launch).  The result is stored along the columns.
 // -------------------------------------------------------------------------------------
 #define GT 32           // output tile edge
 #define GK 64           // inner step
-#define GSPLIT 4        // wave groups splitting the inner dimension
-#define GEMM_NT (64 * 4 * GSPLIT)
 #define GA_LD (GK + 1)  // LDS pitch of the M tile (32 rows x 64) and of the B tile (32 columns x 64)
-template <typename T>
-__global__ __launch_bounds__(GEMM_NT) void k_gemm_rm(const T* __restrict__ M, int Np, const double* __restrict__ B,
+// GSPLIT: wave groups splitting the inner dimension (2 or 4), 256 GSPLIT threads
+template <typename T, int GSPLIT>
+__global__ __launch_bounds__(256 * GSPLIT) void k_gemm_rm(const T* __restrict__ M, int Np, const double* __restrict__ B,
                                                      int R, const double* __restrict__ add, double sgn,
                                                      double* __restrict__ out) {
   // operand tiles of the four groups; after the inner loop the same memory holds the
@@ -1482,7 +1483,9 @@ __global__ __launch_bounds__(GEMM_NT) void k_gemm_rm(const T* __restrict__ M, in
       for (int q = 0; q < 4; ++q) {
         const int rr = 4 * (gt & 7) + q;
         const int e = (gt >> 3) * (GT + 1) + rr;
-        const double s = ((Cs[0][e] + Cs[1][e]) + Cs[2][e]) + Cs[3][e];
+        double s = Cs[0][e];
+#pragma unroll
+        for (int g2 = 1; g2 < GSPLIT; ++g2) s += Cs[g2][e];
         const size_t o = (size_t)cc * Np + r0 + rr;
         out[o] = (add ? add[o] : 0.0) + sgn * s;
       }
@@ -1562,9 +1565,9 @@ __global__ __launch_bounds__(WW_NT) void k_gamma(const double* __restrict__ Mu, 
 // into chk[0] = max |r|, chk[1] = max |psi| with an atomic maximum on the bit patterns
 // (non-negative doubles order like their bits; a NaN residual is larger than any
 // finite one), and the next kernel on the stream (k_base_rhs) takes the decision and
-// clears chk.  Rows N..Np-1 of Gphi are zero.  Dynamic LDS: 4 N complex.
+// clears chk.  Rows N..Np-1 of Gphi are zero.  Dynamic LDS: 4 N complex.  A workgroup
+// takes `rows` consecutive rows (a multiple of 4; grid ceil(Np / rows)).
 // -------------------------------------------------------------------------------------
-#define DTN_ROWS 8                 // rows per workgroup (two per wave)
 // NR: entries of a row per lane, N <= 64 NR (16 up to N = 1024, 32 above), so that the
 // row prefetch holds no more registers than the grid needs.
 template <int NR>
@@ -1572,7 +1575,7 @@ __global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ m
                                                     const double* __restrict__ Gmr, const double* __restrict__ Ar,
                                                     int Np, const cplx* __restrict__ tw, int N,
                                                     double* __restrict__ Gphi,
-                                                    unsigned long long* __restrict__ chk) {
+                                                    unsigned long long* __restrict__ chk, int rows) {
   extern __shared__ cplx lds[];
   cplx* Z = lds;
   cplx* W = lds + N;
@@ -1596,7 +1599,7 @@ __global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ m
       av[m] = ar[jj];
     }
   };
-  const int row0 = blockIdx.x * DTN_ROWS + wv;
+  const int row0 = blockIdx.x * rows + wv;
   load_row(row0);
   const FftPlan P = make_plan(N);
   load_twiddles(tws, tw, N);
@@ -1625,8 +1628,8 @@ __global__ __launch_bounds__(WW_NT) void k_base_dtn(const double* __restrict__ m
   for (int t = tid; t < N; t += WW_NT) gs[t] = W[t].x;
   __syncthreads();
   double mr = 0.0, mb = 0.0;
-  for (int q = 0; q < DTN_ROWS / 4; ++q) {
-    const int row = blockIdx.x * DTN_ROWS + q * 4 + wv;
+  for (int q = 0; q < rows / 4; ++q) {
+    const int row = blockIdx.x * rows + q * 4 + wv;
     if (row >= Np) break;
     if (q > 0) load_row(row);
     if (row >= N) {

@@ -51,6 +51,15 @@ class BfgsReport(ctypes.Structure):
 BFGS_REASONS = {1: "f_tol", 2: "g_tol", 3: "c unchanged", 4: "line search", 5: "max_iter"}
 
 
+class Tuning(ctypes.Structure):
+    """Launch and scheduling choices of a context (ww_tuning)."""
+    _fields_ = [(n, ctypes.c_int) for n in ("lag", "lu_group", "lu_streams", "graph_parts", "minv_wgs",
+                                             "blu_strip", "dtn_rows", "gemm_split", "asm_cw")]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class LmReport(ctypes.Structure):
     _fields_ = [("f", ctypes.c_double), ("delta", ctypes.c_double), ("evals_r", ctypes.c_int),
                 ("evals_J", ctypes.c_int), ("reason", ctypes.c_int), ("n_hist", ctypes.c_int),
@@ -60,7 +69,7 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
-           "dtn_solve_multi_noalloc", "ww_next_fallback"]
+           "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning"]
 
 
 class WWError(RuntimeError):
@@ -92,6 +101,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.dtn_solve_multi.argtypes = [P, P, I, P, P]
     lib.dtn_solve_multi_noalloc.argtypes = [P, P, I, P, P]
     lib.ww_next_fallback.argtypes = [U, U, I]
+    lib.ww_get_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
+    lib.ww_set_tuning.argtypes = [P, ctypes.POINTER(Tuning)]
     lib.ww_next_fallback.restype = U
     lib.shoot_setup.argtypes = [P, I, D, D, D, P, P, I]
     lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
@@ -293,6 +304,23 @@ class Context:
         return dict(c=c, f=rep.f, gnorm=rep.gnorm, iters=rep.iters, evals=rep.evals,
                     reason=BFGS_REASONS.get(rep.reason, rep.reason),
                     history=h[:min(rep.n_hist, hist_cap)] if hist_cap > 0 else None)
+
+    def tuning(self) -> dict:
+        """The context's launch and scheduling choices (ww_get_tuning)."""
+        t = Tuning()
+        _check(self.lib.ww_get_tuning(self.ptr, ctypes.byref(t)))
+        return t.as_dict()
+
+    def set_tuning(self, **choices):
+        """Change some of the launch and scheduling choices (ww_set_tuning; the others
+        keep their current values)."""
+        cur = self.tuning()
+        unknown = set(choices) - set(cur)
+        if unknown:
+            raise ValueError(f"unknown tuning fields {sorted(unknown)}")
+        cur.update(choices)
+        t = Tuning(**{k: int(v) for k, v in cur.items()})
+        _check(self.lib.ww_set_tuning(self.ptr, ctypes.byref(t)))
 
     def profile(self, enable: bool = True):
         _check(self.lib.ww_profile(self.ptr, 1 if enable else 0))

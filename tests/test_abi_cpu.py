@@ -131,3 +131,10 @@ def test_noalloc_solve_rejects_bad_arguments_without_gpu():
     ww, lib = _lib()
     assert lib.dtn_solve_multi_noalloc(None, None, 1, None, None) == -1
     assert b"null" in lib.ww_last_error()
+
+
+def test_tuning_calls_reject_null_arguments_without_gpu():
+    ww, lib = _lib()
+    t = ww.Tuning()
+    assert lib.ww_get_tuning(None, ctypes.byref(t)) == -1   # WW_EINVAL
+    assert lib.ww_set_tuning(None, ctypes.byref(t)) == -1
