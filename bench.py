@@ -68,13 +68,15 @@ def cpu_baseline(w, nsteps_sample: int):
                       f"({nsteps_sample * 12 + 1} dense DtN evaluations with J, {t:.1f} s)"}
 
 
-def run(w, nsteps, T, mixed, steps, warmup, profile):
+def run(w, nsteps, T, mixed, steps, warmup, profile, tuned=True):
     """Time `steps` evaluations of shoot_eval after `warmup` ones, without the profiling
     stamps; then, when asked, one more evaluation with the in-graph timestamp nodes for
-    the phase durations (which the stamps themselves lengthen a little)."""
+    the phase durations (which the stamps themselves lengthen a little).  With `tuned`,
+    the context takes the autotuner's cached choices for this workload, if any."""
     import torch
-    from paper_1210_5672_amd import ww
+    from paper_1210_5672_amd import autotune, ww
     ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
+    from_cache = bool(autotune.apply(ctx, w.N, w.M)) if tuned else False
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     params = ww.to_dev(w.params)
     tag = "mixed" if mixed else "fp64"
@@ -115,7 +117,7 @@ def run(w, nsteps, T, mixed, steps, warmup, profile):
                   "profiled_eval_ms": prof_ms}
         print(f"# {tag} profiled evaluation done", file=sys.stderr, flush=True)
     timing = {"median_ms": statistics.median(each), "min_ms": min(each), "max_ms": max(each),
-              "first_call_ms": first_ms}
+              "first_call_ms": first_ms, "tuning": ctx.tuning(), "tuning_from_cache": from_cache}
     return t, res, phases, timing
 
 
@@ -191,18 +193,22 @@ def stage_roofline(N, M, nst, stage_ms):
     return {"t_roof_us": 1e6 * t_roof, "t_meas_us": 1e3 * stage_ms, "frac": t_roof / (stage_ms * 1e-3)}
 
 
-def run_batch(window: int = 64, reps: int = 1):
+def run_batch(window: int = 64, reps: int = 1, tuned: bool = True):
     """Batched form: the 32 continuation instances of uneven N, depth, tension, M (each
     its own context and stream), every instance marched over a fixed window of
     `window` steps at its own dt, all issued together by shoot_eval_batch.
     Column-steps/s = sum_i M_i * window / wall time."""
     import torch
+    from paper_1210_5672_amd import autotune
     from paper_1210_5672_amd import workloads as W
     from paper_1210_5672_amd import ww
     ws = W.c5()
+    cached = autotune.lookup(max(w.N for w in ws), max(w.M for w in ws), False, batch=True) if tuned else None
     ctxs, params, Ts = [], [], []
     for w in ws:
         c = ww.Context(n_max=w.N, r_max=w.M + 1, stream=torch.cuda.Stream())
+        if cached:
+            c.set_tuning(**cached)
         c.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
         ctxs.append(c)
         params.append(ww.to_dev(w.params))
@@ -222,7 +228,8 @@ def run_batch(window: int = 64, reps: int = 1):
     cols = sum(w.M for w in ws) * window
     return {"workload": f"{len(ws)} continuation instances (N 256..2048, M 32..256), {window}-step window each",
             "value": cols / t, "unit": "column-steps/s", "ms": 1e3 * t,
-            "first_call_ms": 1e3 * t_first, "instances": len(ws),
+            "first_call_ms": 1e3 * t_first, "instances": len(ws), "tuning": ctxs[0].tuning(),
+            "tuning_from_cache": bool(cached),
             "N": [w.N for w in ws], "M": [w.M for w in ws]}
 
 
@@ -353,6 +360,7 @@ def main():
     ap.add_argument("--no-lm", action="store_true", help="skip the Levenberg-Marquardt measurement")
     ap.add_argument("--no-f-only", action="store_true", help="skip the f-only (GMRES) measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (C4)")
+    ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner's cached choices")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -370,7 +378,7 @@ def main():
     T = w.T if nsteps == w.nsteps else w.T * nsteps / w.nsteps   # same dt for a prefix
     print(f"# workload {w.name}: N={w.N} M={w.M} nsteps={nsteps}", file=sys.stderr, flush=True)
     profile = not args.no_profile
-    t, res, phases, timing = run(w, nsteps, T, False, args.steps, args.warmup, profile)
+    t, res, phases, timing = run(w, nsteps, T, False, args.steps, args.warmup, profile, not args.no_tuning)
     ms = 1000.0 * t / args.steps
     value = w.M * nsteps * args.steps / t
     n3 = float(w.N) ** 3
@@ -402,7 +410,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "shoot_eval h=0.5 tau=0.02 N=1024 M=128 nsteps=600 (precision form)",
-                   "N": w.N, "M": w.M, "nsteps": nsteps, "f": res["f"]},
+                   "N": w.N, "M": w.M, "nsteps": nsteps, "f": res["f"], "tuning": timing["tuning"]},
         "roofline": roofline,
         "cpu_baseline": None,
         "timing": timing,
@@ -413,7 +421,7 @@ def main():
         out["err_vs_oracle"] = err_vs_oracle(res, fx)
     if not args.no_mixed:
         import numpy as np
-        tm, resm, phm, timm = run(w, nsteps, T, True, args.steps, args.warmup, profile)
+        tm, resm, phm, timm = run(w, nsteps, T, True, args.steps, args.warmup, profile, not args.no_tuning)
         r64, rm = res["r"].cpu().numpy(), resm["r"].cpu().numpy()
         J64, Jm = res["J"].cpu().numpy(), resm["J"].cpu().numpy()
         out["mixed"] = {
@@ -439,7 +447,7 @@ def main():
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
     if not args.no_batch:
-        out["batch"] = run_batch()
+        out["batch"] = run_batch(tuned=not args.no_tuning)
     if args.copy_probe:
         # a plain copy of known size: its FETCH_SIZE / WRITE_SIZE under a counter run
         # give the scale between the counters and the bytes actually moved
