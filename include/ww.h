@@ -384,13 +384,15 @@ unsigned ww_next_fallback(unsigned flags, unsigned fb, int status);
  *   blu_strip    64-tiles per task of a block-LU step, 1..16
  *   dtn_rows     rows per workgroup of the base DtN launch, 4..32, a multiple of 4
  *   gemm_split   wave groups splitting the inner dimension of a column product, 2 or 4
+ *   gemm_rows    rows of a column product's output tile, 16 or 32 (16: twice the
+ *                workgroups for the same columns)
  *   asm_cw       columns per assembly workgroup, 16 or 32
  * ww_set_tuning validates every field and applies them together (captured graphs are
  * re-captured at the next march); ww_get_tuning reads the current choices.  Host only.
  * Errors: WW_EINVAL (null argument, a field out of range).
  */
 typedef struct ww_tuning {
-  int lag, lu_group, lu_streams, graph_parts, minv_wgs, blu_strip, dtn_rows, gemm_split, asm_cw;
+  int lag, lu_group, lu_streams, graph_parts, minv_wgs, blu_strip, dtn_rows, gemm_split, asm_cw, gemm_rows;
 } ww_tuning;
 int ww_get_tuning(ww_ctx *ctx, ww_tuning *t);
 int ww_set_tuning(ww_ctx *ctx, const ww_tuning *t);

@@ -3,8 +3,9 @@
 None of the choices changes what is computed: they decide how the work of a march is
 cut into launches and streams (LU group size and streams, the lag of the base solve,
 which parts replay from graphs, the strip length of a block-LU step, rows per
-workgroup of the base DtN launch, the inner-dimension split of the column products,
-the assembly strip width, the workgroup cap of the explicit inverse).  The tuner times
+workgroup of the base DtN launch, the inner-dimension split and the output-tile rows
+of the column products, the assembly strip width, the workgroup cap of the explicit
+inverse).  The tuner times
 short marches of a workload, one fresh context per candidate, and improves one choice
 at a time (coordinate descent, a few passes); the winner is stored in a JSON cache
 keyed by GPU architecture, N, M and precision form, and `apply` hands it to a context.
@@ -39,6 +40,7 @@ SPACE = {
     "dtn_rows": [8, 4, 16],
     "gemm_split": [4, 2],
     "asm_cw": [16, 32],
+    "gemm_rows": [32, 16],
 }
 # choices that matter only to the lagged-factor march (a batch runs each instance's
 # own step graph)

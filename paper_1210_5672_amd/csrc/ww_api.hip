@@ -161,6 +161,7 @@ struct ww_ctx {
   int blu_strip = 4;                       // tiles per strip task of a block-LU step
   int dtn_rows = 8;                        // rows per workgroup of the base DtN launch
   int gemm_split = 4;                      // wave groups splitting the inner dimension of a product
+  int gemm_rows = 32;                      // rows of a column product's output tile (16 or 32)
   int asm_cw = 16;                         // columns per assembly workgroup
   int tune_gen = 0;                        // bumped by ww_set_tuning (graphs are re-captured)
   int gtune = -1;                          // tune_gen of the captured step graph
@@ -506,6 +507,7 @@ int ww_get_tuning(ww_ctx* c, ww_tuning* t) {
   t->blu_strip = c->blu_strip;
   t->dtn_rows = c->dtn_rows;
   t->gemm_split = c->gemm_split;
+  t->gemm_rows = c->gemm_rows;
   t->asm_cw = c->asm_cw;
   return 0;
 }
@@ -521,6 +523,7 @@ int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
   if (t->dtn_rows < 4 || t->dtn_rows > 32 || t->dtn_rows % 4) return fail(WW_EINVAL, "tuning: dtn_rows out of range");
   if (t->gemm_split != 2 && t->gemm_split != 4) return fail(WW_EINVAL, "tuning: gemm_split must be 2 or 4");
   if (t->asm_cw != 16 && t->asm_cw != 32) return fail(WW_EINVAL, "tuning: asm_cw must be 16 or 32");
+  if (t->gemm_rows != 16 && t->gemm_rows != 32) return fail(WW_EINVAL, "tuning: gemm_rows must be 16 or 32");
   c->lag = t->lag;
   c->lu_group = t->lu_group;
   c->nlus = t->lu_streams;
@@ -529,6 +532,7 @@ int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
   c->blu_strip = t->blu_strip;
   c->dtn_rows = t->dtn_rows;
   c->gemm_split = t->gemm_split;
+  c->gemm_rows = t->gemm_rows;
   c->asm_cw = t->asm_cw;
   ++c->tune_gen;
   return 0;
@@ -777,12 +781,18 @@ static int enqueue_gemm(ww_ctx* c, const T* Mr, int mode, const double* B, const
     return 0;
   }
   if (mode & 3) return fail(WW_EHIP, "internal: triangular product of several columns");
-  if (c->gemm_split == 2)
-    hipLaunchKernelGGL((k_gemm_rm<T, 2>), dim3(c->Np / GT, (R + GT - 1) / GT), dim3(512), 0, c->stream, Mr, c->Np, B, R,
-                     add, sgn, out);
-  else
-    hipLaunchKernelGGL((k_gemm_rm<T, 4>), dim3(c->Np / GT, (R + GT - 1) / GT), dim3(1024), 0, c->stream, Mr, c->Np, B, R,
-                     add, sgn, out);
+  const dim3 g32(c->Np / GT, (R + GT - 1) / GT), g16(c->Np / 16, (R + GT - 1) / GT);
+  if (c->gemm_rows == 16) {
+    if (c->gemm_split == 2)
+      hipLaunchKernelGGL((k_gemm_rm<T, 2, 16>), g16, dim3(256), 0, c->stream, Mr, c->Np, B, R, add, sgn, out);
+    else
+      hipLaunchKernelGGL((k_gemm_rm<T, 4, 16>), g16, dim3(512), 0, c->stream, Mr, c->Np, B, R, add, sgn, out);
+  } else {
+    if (c->gemm_split == 2)
+      hipLaunchKernelGGL((k_gemm_rm<T, 2, 32>), g32, dim3(512), 0, c->stream, Mr, c->Np, B, R, add, sgn, out);
+    else
+      hipLaunchKernelGGL((k_gemm_rm<T, 4, 32>), g32, dim3(1024), 0, c->stream, Mr, c->Np, B, R, add, sgn, out);
+  }
   LAUNCHCHK();
   return 0;
 }

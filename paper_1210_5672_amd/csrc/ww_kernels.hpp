@@ -1384,49 +1384,56 @@ __global__ __launch_bounds__(WW_NT) void k_gemv_row(const T* __restrict__ Mr, in
 // -------------------------------------------------------------------------------------
 // Product with a row-major matrix for R right-hand sides:  out = add + sgn * M B
 // (M: Np x Np row-major, element type T; B, add, out: Np x R column-major doubles,
-// ld Np; B is rounded to T on load).  One workgroup of 4 GSPLIT waves per 32 x 32
-// output tile: the inner dimension is split over GSPLIT wave groups (group g takes the
-// 64-wide steps g, g + GSPLIT, ...), in each group wave w computes the 16 x 16 quadrant
-// (w >> 1, w & 1) with 16 x 16 x 4 MFMAs, the next step's operands in flight in
+// ld Np; B is rounded to T on load).  One workgroup per TR x 32 output tile: the inner
+// dimension is split over GSPLIT wave groups (group g takes the 64-wide steps g,
+// g + GSPLIT, ...), in each group every wave computes one 16 x 16 block with
+// 16 x 16 x 4 MFMAs, the next step's operands in flight in
 // registers during the MFMAs; the partial tiles are summed in LDS in a fixed order,
 // ((g0 + g1) + g2) + g3, so each entry is one deterministic sum (no partials in
 // memory, no second launch).  The result is stored along the columns.
 // -------------------------------------------------------------------------------------
 #define GT 32           // output tile edge
 #define GK 64           // inner step
-#define GA_LD (GK + 1)  // LDS pitch of the M tile (32 rows x 64) and of the B tile (32 columns x 64)
-// GSPLIT: wave groups splitting the inner dimension (2 or 4), 256 GSPLIT threads
-template <typename T, int GSPLIT>
-__global__ __launch_bounds__(256 * GSPLIT) void k_gemm_rm(const T* __restrict__ M, int Np, const double* __restrict__ B,
-                                                     int R, const double* __restrict__ add, double sgn,
-                                                     double* __restrict__ out) {
-  // operand tiles of the four groups; after the inner loop the same memory holds the
-  // four partial output tiles
-  constexpr int OPER = 2 * GSPLIT * GT * GA_LD * (int)sizeof(T);
-  constexpr int PART = GSPLIT * GT * (GT + 1) * (int)sizeof(double);
+#define GA_LD (GK + 1)  // LDS pitch of the M tile (TR rows x 64) and of the B tile (32 columns x 64)
+// GSPLIT: wave groups splitting the inner dimension (2 or 4); TR: rows of the output
+// tile (32, or 16 for twice the workgroups at the same columns); a group has TR / 8
+// waves, each computing one 16 x 16 block of the TR x 32 tile.
+template <typename T, int GSPLIT, int TR>
+__global__ __launch_bounds__(8 * TR * GSPLIT) void k_gemm_rm(const T* __restrict__ M, int Np,
+                                                          const double* __restrict__ B, int R,
+                                                          const double* __restrict__ add, double sgn,
+                                                          double* __restrict__ out) {
+  constexpr int WPG = TR / 8;         // waves per group
+  constexpr int TPG = 64 * WPG;       // threads per group
+  constexpr int MA = TR * 64 / TPG;   // M-tile entries per thread and step (8)
+  constexpr int MB = 32 * 64 / TPG;   // B-tile entries per thread and step (8 or 16)
+  // operand tiles of the groups; after the inner loop the same memory holds the
+  // partial output tiles
+  constexpr int OPER = GSPLIT * (TR + GT) * GA_LD * (int)sizeof(T);
+  constexpr int PART = GSPLIT * GT * (TR + 1) * (int)sizeof(double);
   __shared__ double smem[(OPER > PART ? OPER : PART) / 8];
-  T (*As)[GT * GA_LD] = reinterpret_cast<T (*)[GT * GA_LD]>(smem);
-  T (*Bs)[GT * GA_LD] = As + GSPLIT;
-  double (*Cs)[GT * (GT + 1)] = reinterpret_cast<double (*)[GT * (GT + 1)]>(smem);
+  T* const tiles = reinterpret_cast<T*>(smem);
+  double (*Cs)[GT * (TR + 1)] = reinterpret_cast<double (*)[GT * (TR + 1)]>(smem);
   typedef typename Mfma<T>::V V;
-  const int r0 = blockIdx.x * GT, c0 = blockIdx.y * GT;
+  const int r0 = blockIdx.x * TR, c0 = blockIdx.y * GT;
   const int tid = threadIdx.x;
-  const int grp = tid >> 8, gt = tid & 255;   // wave group and thread within it
+  const int grp = tid / TPG, gt = tid % TPG;   // wave group and thread within it
   const int lane = gt & 63, w = gt >> 6;
-  const int wr = (w >> 1) * 16, wc = (w & 1) * 16;
+  const int wr = (TR == 32 ? (w >> 1) : 0) * 16, wc = (w & 1) * 16;
   const int li = lane & 15, lk = lane >> 4;
-  T* as = As[grp];
-  T* bs = Bs[grp];
-  // loads of one inner step by the 256 threads of a group: 8 entries of the M tile
-  // (rows r0.., columns k0..) and 8 of the B tile: row/column gt >> 6 + 4 m, inner gt & 63
-  T ma[8];
-  double bv[8];
+  T* as = tiles + (size_t)grp * (TR + GT) * GA_LD;
+  T* bs = as + TR * GA_LD;
+  // loads of one inner step by the threads of a group: MA entries of the M tile (rows
+  // r0 + w + WPG m, columns k0..) and MB of the B tile (columns c0 + w + WPG m)
+  T ma[MA];
+  double bv[MB];
   auto fetch = [&](int k0) {
+    const int kk = gt & 63;
 #pragma unroll
-    for (int m = 0; m < 8; ++m) {
-      const int rr = (gt >> 6) + 4 * m, kk = gt & 63;
-      ma[m] = M[(size_t)(r0 + rr) * Np + k0 + kk];
-      const int cc = c0 + rr;
+    for (int m = 0; m < MA; ++m) ma[m] = M[(size_t)(r0 + (gt >> 6) + WPG * m) * Np + k0 + kk];
+#pragma unroll
+    for (int m = 0; m < MB; ++m) {
+      const int cc = c0 + (gt >> 6) + WPG * m;
       bv[m] = cc < R ? B[(size_t)cc * Np + k0 + kk] : 0.0;
     }
   };
@@ -1443,12 +1450,11 @@ __global__ __launch_bounds__(256 * GSPLIT) void k_gemm_rm(const T* __restrict__ 
     const bool have = st < nsteps;
     __syncthreads();
     if (have) {
+      const int kk = gt & 63;
 #pragma unroll
-      for (int m = 0; m < 8; ++m) {
-        const int rr = (gt >> 6) + 4 * m, kk = gt & 63;
-        as[rr * GA_LD + kk] = ma[m];
-        bs[rr * GA_LD + kk] = (T)bv[m];
-      }
+      for (int m = 0; m < MA; ++m) as[((gt >> 6) + WPG * m) * GA_LD + kk] = ma[m];
+#pragma unroll
+      for (int m = 0; m < MB; ++m) bs[((gt >> 6) + WPG * m) * GA_LD + kk] = (T)bv[m];
     }
     __syncthreads();
     if (have && st + GSPLIT < nsteps) fetch((st + GSPLIT) * GK);
@@ -1473,16 +1479,16 @@ __global__ __launch_bounds__(256 * GSPLIT) void k_gemm_rm(const T* __restrict__ 
   for (int i = 0; i < 4; ++i) acc[i] += acc1[i];
   __syncthreads();   // every group is done with its operand tiles
 #pragma unroll
-  for (int i = 0; i < 4; ++i) Cs[grp][(wc + li) * (GT + 1) + wr + Mfma<T>::row(i, lk)] = (double)acc[i];
+  for (int i = 0; i < 4; ++i) Cs[grp][(wc + li) * (TR + 1) + wr + Mfma<T>::row(i, lk)] = (double)acc[i];
   __syncthreads();
   if (grp == 0) {
-    // column c0 + (gt >> 3), rows r0 + 4 (gt & 7) .. + 3
-    const int cc = c0 + (gt >> 3);
+    // column c0 + gt / (TR / 4), rows r0 + 4 (gt % (TR / 4)) .. + 3
+    const int cc = c0 + gt / (TR / 4);
     if (cc < R) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int rr = 4 * (gt & 7) + q;
-        const int e = (gt >> 3) * (GT + 1) + rr;
+        const int rr = 4 * (gt % (TR / 4)) + q;
+        const int e = (gt / (TR / 4)) * (TR + 1) + rr;
         double s = Cs[0][e];
 #pragma unroll
         for (int g2 = 1; g2 < GSPLIT; ++g2) s += Cs[g2][e];
