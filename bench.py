@@ -24,12 +24,13 @@ FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (vector and MFMA)
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 
-# HBM bytes of one FP64 block-LU launch sequence (N = 1024), from the FETCH_SIZE and
-# WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md, calibrated with a
-# plain 256 MiB copy.  Valid only for the kernel source it was measured on: reported as
-# null once the kernels header changes.
-LU_TRAFFIC_BYTES = 266.5e6
-LU_TRAFFIC_SOURCE_SHA256 = "a51d552ad83d578b6f25c53177e7249737797ba829ade75408df29f1d991d6ff"
+# HBM bytes per FP64 factorisation (N = 1024) of the block-LU launch sequence (init, 15
+# steps, final, explicit inverse; a sequence factors two stages and moves twice this),
+# from the FETCH_SIZE and WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md,
+# calibrated with a plain 256 MiB copy.  Valid only for the kernel source it was measured
+# on: reported as null once the kernels header changes.
+LU_TRAFFIC_BYTES = 241.7e6
+LU_TRAFFIC_SOURCE_SHA256 = "eb9526a191b8180c88a244a185bcc2e710f3b7aef715387df5a1285bc436bdf7"
 
 
 def lu_traffic():
