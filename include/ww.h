@@ -386,13 +386,19 @@ unsigned ww_next_fallback(unsigned flags, unsigned fb, int status);
  *   gemm_split   wave groups splitting the inner dimension of a column product, 2 or 4
  *   gemm_rows    rows of a column product's output tile, 16 or 32 (16: twice the
  *                workgroups for the same columns)
+ *   lag_fp32     FP64 form, lagged-factor march: 1 makes the lagged base solve (its
+ *                first solve and the corrections of its refinement sweeps) read an FP32
+ *                copy of the lagged inverse, written by the same launch as the FP64 one;
+ *                the residuals stay FP64 and the solve still ends with the 2^-43 test, so
+ *                only the contraction per sweep changes (half the bytes per product)
  *   asm_cw       columns per assembly workgroup, 16 or 32
  * ww_set_tuning validates every field and applies them together (captured graphs are
  * re-captured at the next march); ww_get_tuning reads the current choices.  Host only.
  * Errors: WW_EINVAL (null argument, a field out of range).
  */
 typedef struct ww_tuning {
-  int lag, lu_group, lu_streams, graph_parts, minv_wgs, blu_strip, dtn_rows, gemm_split, asm_cw, gemm_rows;
+  int lag, lu_group, lu_streams, graph_parts, minv_wgs, blu_strip, dtn_rows, gemm_split, asm_cw, gemm_rows,
+      lag_fp32;
 } ww_tuning;
 int ww_get_tuning(ww_ctx *ctx, ww_tuning *t);
 int ww_set_tuning(ww_ctx *ctx, const ww_tuning *t);

@@ -5,7 +5,7 @@ cut into launches and streams (LU group size and streams, the lag of the base so
 which parts replay from graphs, the strip length of a block-LU step, rows per
 workgroup of the base DtN launch, the inner-dimension split and the output-tile rows
 of the column products, the assembly strip width, the workgroup cap of the explicit
-inverse).  The tuner times
+inverse, an FP32 copy of the lagged inverse for the base solve's products).  The tuner times
 short marches of a workload, one fresh context per candidate, and improves one choice
 at a time (coordinate descent, a few passes); the winner is stored in a JSON cache
 keyed by GPU architecture, N, M and precision form, and `apply` hands it to a context.
@@ -41,10 +41,11 @@ SPACE = {
     "gemm_split": [4, 2],
     "asm_cw": [16, 32],
     "gemm_rows": [32, 16],
+    "lag_fp32": [0, 1],
 }
 # choices that matter only to the lagged-factor march (a batch runs each instance's
 # own step graph)
-MARCH_ONLY = ("graph_parts", "lu_group", "lu_streams", "lag", "dtn_rows")
+MARCH_ONLY = ("graph_parts", "lu_group", "lu_streams", "lag", "dtn_rows", "lag_fp32")
 
 
 def cache_path(path: str | None = None) -> str:

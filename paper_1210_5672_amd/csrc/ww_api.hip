@@ -162,6 +162,7 @@ struct ww_ctx {
   int dtn_rows = 8;                        // rows per workgroup of the base DtN launch
   int gemm_split = 4;                      // wave groups splitting the inner dimension of a product
   int gemm_rows = 32;                      // rows of a column product's output tile (16 or 32)
+  int lag32 = 0;                           // FP64 form: lagged solves read an FP32 copy of the inverse
   int asm_cw = 16;                         // columns per assembly workgroup
   int tune_gen = 0;                        // bumped by ww_set_tuning (graphs are re-captured)
   int gtune = -1;                          // tune_gen of the captured step graph
@@ -508,6 +509,7 @@ int ww_get_tuning(ww_ctx* c, ww_tuning* t) {
   t->dtn_rows = c->dtn_rows;
   t->gemm_split = c->gemm_split;
   t->gemm_rows = c->gemm_rows;
+  t->lag_fp32 = c->lag32;
   t->asm_cw = c->asm_cw;
   return 0;
 }
@@ -524,6 +526,7 @@ int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
   if (t->gemm_split != 2 && t->gemm_split != 4) return fail(WW_EINVAL, "tuning: gemm_split must be 2 or 4");
   if (t->asm_cw != 16 && t->asm_cw != 32) return fail(WW_EINVAL, "tuning: asm_cw must be 16 or 32");
   if (t->gemm_rows != 16 && t->gemm_rows != 32) return fail(WW_EINVAL, "tuning: gemm_rows must be 16 or 32");
+  if (t->lag_fp32 != 0 && t->lag_fp32 != 1) return fail(WW_EINVAL, "tuning: lag_fp32 must be 0 or 1");
   c->lag = t->lag;
   c->lu_group = t->lu_group;
   c->nlus = t->lu_streams;
@@ -533,6 +536,7 @@ int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
   c->dtn_rows = t->dtn_rows;
   c->gemm_split = t->gemm_split;
   c->gemm_rows = t->gemm_rows;
+  c->lag32 = t->lag_fp32;
   c->asm_cw = t->asm_cw;
   ++c->tune_gen;
   return 0;
@@ -634,6 +638,7 @@ struct Fac {
   double *Mi, *Gmr, *Ar;
   float* Mi32;
   int* perm;   // partial-pivoting row order of this set, or null (no interchanges)
+  bool lag32 = false;   // FP64 factors whose lagged solves read the FP32 copy Mi32 of Mi
 };
 // factor set of parity `p`; `cols` selects the column chain's GEMM partials
 static Fac fac_set(ww_ctx* c, int p, bool cols) {
@@ -698,8 +703,9 @@ static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar, const Fac* Fo = nullptr,
                             const double* psi = nullptr, double* x0 = nullptr) {
   const int nb = c->Np / WW_TB;
-  const double* mx64 = (Fo && !Fo->use32) ? Fo->Mi : nullptr;
-  const float* mx32 = (Fo && Fo->use32) ? Fo->Mi32 : nullptr;
+  const bool f32 = Fo && (Fo->use32 || Fo->lag32);
+  const double* mx64 = (Fo && !f32) ? Fo->Mi : nullptr;
+  const float* mx32 = f32 ? Fo->Mi32 : nullptr;
   if (Fo && !(mx64 || mx32)) return fail(WW_EHIP, "internal: lagged first solve without its inverse");
   const int cw = c->asm_cw == 32 ? 32 : 16;
   const int gy = c->Np / cw + (Fo ? 16 : 0);
@@ -747,6 +753,7 @@ static int enqueue_lu_group(ww_ctx* c, const Fac* F, int count) {
       mg.Z[q] = F[q].Z;
       mg.X[q] = F[q].X;
       mg.Mr[q] = F[q].Mi;
+      mg.Mr32[q] = F[q].lag32 ? F[q].Mi32 : nullptr;
     }
     g.count = count;
     g.strip = c->blu_strip;
@@ -1015,8 +1022,9 @@ static int ensure_pipe(ww_ctx* c) {
       if ((rc = dalloc(c, (void**)q, nn * 8))) return rc;
     if ((rc = dalloc(c, (void**)&r.Dinv, nbm * 4096 * 8))) return rc;
     if ((rc = dalloc(c, (void**)&r.aux, (size_t)AUX_COUNT * c->n_max * 8))) return rc;
+    if ((rc = dalloc(c, (void**)&r.Mi32, nn * 4))) return rc;   // also the FP64 form's FP32 copy
     if (mixed(c)) {
-      float** f[] = {&r.A32, &r.X32, &r.Z32, &r.V32, &r.Mi32};
+      float** f[] = {&r.A32, &r.X32, &r.Z32, &r.V32};
       for (float** q : f)
         if ((rc = dalloc(c, (void**)q, nn * 4))) return rc;
       if ((rc = dalloc(c, (void**)&r.Dinv32, nbm * 4096 * 4))) return rc;
@@ -1034,6 +1042,7 @@ static Fac pipe_set(ww_ctx* c, int s, bool cols) {
   F.Ar = r.Ar;
   F.Mi32 = r.Mi32;
   F.perm = nullptr;
+  F.lag32 = c->lag32 && !F.use32 && r.Mi32;
   return F;
 }
 
@@ -1051,9 +1060,9 @@ static int pipe_prologue(ww_ctx* c) {
   const size_t nn = (size_t)c->Np * c->Np;
   for (int q = nst - L + 1; q < nst; ++q) {
     const RingSet &a = c->ring[nst - L], &b = c->ring[q];
-    if (use32(c))
+    if (use32(c) || P0.lag32)
       HIPCHK(hipMemcpyAsync(b.Mi32, a.Mi32, nn * 4, hipMemcpyDeviceToDevice, c->stream));
-    else
+    if (!use32(c))
       HIPCHK(hipMemcpyAsync(b.Mi, a.Mi, nn * 8, hipMemcpyDeviceToDevice, c->stream));
   }
   // the first step of the per-branch graphs waits, at stage s, for the column chain of
@@ -1103,7 +1112,7 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
     const int nref = c->nref_lag >= 0 ? c->nref_lag : c->nref;
     for (int it = 0; it < nref; ++it) {
       if ((rc = enqueue_gemm<double>(c, F.Ar, 0, c->mu0, c->rhs0, -1.0, c->rr0, 1))) return rc;
-      rc = Fo.use32 ? enqueue_gemm<float>(c, Fo.Mi32, 0, c->rr0, c->mu0, 1.0, c->mu0, 1)
+      rc = (Fo.use32 || Fo.lag32) ? enqueue_gemm<float>(c, Fo.Mi32, 0, c->rr0, c->mu0, 1.0, c->mu0, 1)
                     : enqueue_gemm<double>(c, Fo.Mi, 0, c->rr0, c->mu0, 1.0, c->mu0, 1);
       if (rc) return rc;
     }

@@ -1184,6 +1184,7 @@ struct MinvGroup {
   const T* Z[BLU_GMAX];
   const T* X[BLU_GMAX];
   T* Mr[BLU_GMAX];
+  float* Mr32[BLU_GMAX];   // optional FP32 row-major copy of the inverse (null: none)
   int count;
 };
 
@@ -1228,6 +1229,7 @@ __global__ __launch_bounds__(WW_NT) void k_minv(MinvGroup<T> gr, int Np) {
     const T* __restrict__ Z = z == 0 ? gr.Z[0] : z == 1 ? gr.Z[1] : z == 2 ? gr.Z[2] : gr.Z[3];
     const T* __restrict__ X = z == 0 ? gr.X[0] : z == 1 ? gr.X[1] : z == 2 ? gr.X[2] : gr.X[3];
     T* __restrict__ Mr = z == 0 ? gr.Mr[0] : z == 1 ? gr.Mr[1] : z == 2 ? gr.Mr[2] : gr.Mr[3];
+    float* __restrict__ Mr32 = z == 0 ? gr.Mr32[0] : z == 1 ? gr.Mr32[1] : z == 2 ? gr.Mr32[2] : gr.Mr32[3];
     const int m0 = max(i, j + 1);
     Acc64<T> acc;
     acc_zero(acc);
@@ -1257,6 +1259,15 @@ __global__ __launch_bounds__(WW_NT) void k_minv(MinvGroup<T> gr, int Np) {
     }
     __syncthreads();
     tile_store_rm<T>(As, rmptr(Mr, Np, i, j), Np);
+    if (Mr32) {
+      float* G = rmptr(Mr32, Np, i, j);
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int idx = threadIdx.x + WW_NT * m;
+        const int r = idx >> 6, c = idx & 63;
+        G[(size_t)r * Np + c] = (float)As[r * TLD + c];
+      }
+    }
   }
 }
 
