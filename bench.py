@@ -24,24 +24,36 @@ FP64_PEAK_TFLOPS = 78.6    # MI355X dense FP64 (vector and MFMA)
 FP32_PEAK_TFLOPS = 157.3   # MI355X dense FP32 MFMA
 HBM_PEAK_GBS = 8000.0      # MI355X HBM3E
 
-# HBM bytes per FP64 factorisation (N = 1024) of the block-LU launch sequence (init, 15
-# steps, final, explicit inverse; a sequence factors two stages and moves twice this),
-# from the FETCH_SIZE and WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md,
-# calibrated with a plain 256 MiB copy.  Valid only for the kernel source it was measured
-# on: reported as null once the kernels header changes.
-LU_TRAFFIC_BYTES = 241.7e6
-LU_TRAFFIC_SOURCE_SHA256 = "eb9526a191b8180c88a244a185bcc2e710f3b7aef715387df5a1285bc436bdf7"
+# HBM bytes of the block LU at N = 1024, FP64, LU groups of two stages, from the
+# FETCH_SIZE and WRITE_SIZE counter passes in profiles/block_lu_c3_hbm_counters.md,
+# calibrated with a plain 256 MiB copy: per k_blu_step launch (averaged over the 15
+# steps of a sequence) and per launch sequence (init, 15 steps, final, explicit
+# inverse).  Valid only for the kernel source they were measured on: reported as null
+# once the kernels header changes.
+BLU_STEP_TRAFFIC_BYTES = 26.57e6
+LU_SEQ_TRAFFIC_BYTES = 483.3e6
+LU_TRAFFIC_SOURCE_SHA256 = "020bbe7fa62336249d1675eb422202b8b7a861eb98a99b27e83be4f92382c65f"
+LU_TRAFFIC_GROUP = 2
 
 
-def lu_traffic():
+def lu_traffic_valid():
     import hashlib
     path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "paper_1210_5672_amd", "csrc", "ww_kernels.hpp")
     try:
         with open(path, "rb") as fh:
-            ok = hashlib.sha256(fh.read()).hexdigest() == LU_TRAFFIC_SOURCE_SHA256
+            return hashlib.sha256(fh.read()).hexdigest() == LU_TRAFFIC_SOURCE_SHA256
     except OSError:
-        ok = False
-    return LU_TRAFFIC_BYTES if ok else None
+        return False
+
+
+def blu_step_flops(N: int, b: int = 64) -> float:
+    """Algorithmic LU flops of the k_blu_step launches of one factorisation: step k
+    forms the m = nb - k - 1 left factors L_ik = A_ik D_k (2 b^3 each) and updates the
+    m^2 trailing tiles (2 b^3 each), i.e. 2 b^3 (m^2 + m); summed over the steps this is
+    2/3 N^3 up to the diagonal-block inversions.  The accumulation of the block-triangular
+    inverses that the same launches carry is not counted."""
+    nb = N // b
+    return sum(2.0 * b ** 3 * (m * m + m) for m in range(1, nb))
 
 
 def blas_threads() -> int:
@@ -102,19 +114,24 @@ def run(w, nsteps, T, mixed, steps, warmup, profile, tuned=True):
     t = time.perf_counter() - t0
     phases = None
     if profile:
-        ctx.profile(True)
+        ctx.profile(True, kernel_events=True)
         ctx.shoot_eval(params, T, nsteps)   # captures the graphs with the stamp nodes
-        ctx.profile(True)                   # clear the sums
+        ctx.profile(True, kernel_events=True)   # clear the sums
         ta = time.perf_counter()
         ctx.shoot_eval(params, T, nsteps)
         prof_ms = 1e3 * (time.perf_counter() - ta)
         lu_ms, lu_n = ctx.profile_stats(0)
+        try:   # HIP events around every k_blu_step launched outside a graph
+            step_ms, step_n = ctx.profile_stats(4)
+        except ww.WWError:
+            step_ms, step_n = None, 0
         phases = {"block_lu_ms": lu_ms, "base_chain_ms": ctx.profile_read(1),
                   "column_chain_ms": ctx.profile_read(2),
                   "host_enqueue_ms_per_step": ctx.profile_read(3),
                   # stages factored per LU launch sequence (the lagged march factors
                   # consecutive stages together)
                   "lu_stages_per_sequence": nsteps * 12 / lu_n,
+                  "blu_step_ms": step_ms, "blu_step_launches": step_n,
                   "profiled_eval_ms": prof_ms}
         print(f"# {tag} profiled evaluation done", file=sys.stderr, flush=True)
     timing = {"median_ms": statistics.median(each), "min_ms": min(each), "max_ms": max(each),
@@ -385,18 +402,33 @@ def main():
     n3 = float(w.N) ** 3
     roofline = None
     if phases:
-        # dominant kernel family: the block LU (k_blu_init, k_blu_step x 15, k_blu_final,
-        # k_minv), one launch sequence factoring G consecutive stages; algorithmic work
-        # 2/3 N^3 flops per factorisation
-        lu_s = phases["block_lu_ms"] * 1e-3
+        # dominant kernel: k_blu_step (15 launches per LU sequence; each launch carries
+        # the tasks of the G stages of a group).  Achieved = algorithmic LU flops per
+        # launch (the sequence's step flops / launches) over the mean launch duration
+        # from HIP events on the launching stream.
         G = phases["lu_stages_per_sequence"]
-        ach = G * (2.0 / 3.0) * n3 / lu_s / 1e12
-        tr = lu_traffic() if w.N == 1024 else None
-        roofline = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
-                    "frac": ach / FP64_PEAK_TFLOPS, "traffic": tr * G if tr else None,
-                    "kernel": f"block LU launch sequence (k_blu_*, k_minv) factoring {G:g} stages, "
-                              "2/3 N^3 flops per factorisation",
-                    "phases_ms": phases}
+        nb = w.N // 64
+        seq_flops = G * blu_step_flops(w.N)
+        valid = lu_traffic_valid() and w.N == 1024 and timing["tuning"]["lu_group"] == LU_TRAFFIC_GROUP
+        seq = {"kernels": "k_blu_init, 15 x k_blu_step, k_blu_final, k_minv",
+               "stages": G, "ms": phases["block_lu_ms"],
+               "achieved": G * (2.0 / 3.0) * n3 / (phases["block_lu_ms"] * 1e-3) / 1e12,
+               "traffic": LU_SEQ_TRAFFIC_BYTES if valid else None}
+        if phases.get("blu_step_launches"):
+            step_s = phases["blu_step_ms"] * 1e-3
+            ach = seq_flops / (nb - 1) / step_s / 1e12
+            roofline = {"bound": "mfma", "achieved": ach, "peak": FP64_PEAK_TFLOPS, "unit": "TFLOP/s",
+                        "frac": ach / FP64_PEAK_TFLOPS, "traffic": BLU_STEP_TRAFFIC_BYTES if valid else None,
+                        "kernel": f"k_blu_step<double>, one launch per block step of a group of {G:g} stages",
+                        "flops_per_launch": seq_flops / (nb - 1),
+                        "launch_us": phases["blu_step_ms"] * 1e3,
+                        "launches_timed": phases["blu_step_launches"],
+                        "sequence": seq, "phases_ms": phases}
+        else:   # every LU replayed from a graph: no per-launch events, sequence figure only
+            roofline = {"bound": "mfma", "achieved": seq["achieved"], "peak": FP64_PEAK_TFLOPS,
+                        "unit": "TFLOP/s", "frac": seq["achieved"] / FP64_PEAK_TFLOPS,
+                        "traffic": seq["traffic"], "kernel": "block LU launch sequence",
+                        "sequence": seq, "phases_ms": phases}
     out = {
         "metric": "Jacobian column-steps/s at N=1024",
         "value": value,

@@ -242,10 +242,15 @@ int shoot_adjoint(ww_ctx *ctx, const double *params, double T, int nsteps, int c
  * and the explicit inverse), 1: the whole base chain (spectral prep, assembly, base
  * solve, base DtN, base right-hand side), 2: the column chain (the M variational
  * columns) -- and clears the accumulated sums (stream-ordered); phase 3 is the host
- * time spent enqueueing one step (graph launches and event operations).
+ * time spent enqueueing one step (graph launches and event operations).  With 2 added
+ * to `enable` (enable = 3), every block-LU step kernel (k_blu_step) that a march step
+ * launches directly (not from a graph) also carries a pair of HIP events attached to its
+ * dispatch on its stream (hipExtLaunchKernel), which take the kernel's own start and end
+ * times; phase 4 reads their mean elapsed time (the kernel's average launch duration,
+ * over at most the first 16384 launches of the interval).
  * ww_profile_read returns in *avg_ms the mean duration of `phase` over every interval
- * since the last ww_profile(ctx, 1) (per step for phase 3), and in *count the number of
- * intervals (synchronises the stream).  Errors: WW_EINVAL (profiling off, nothing
+ * since the last ww_profile(ctx, 1) (per step for phase 3, per launch for phase 4), and
+ * in *count the number of intervals (synchronises the stream).  Errors: WW_EINVAL (profiling off, nothing
  * replayed yet), WW_EHIP.
  */
 int ww_profile(ww_ctx *ctx, int enable);

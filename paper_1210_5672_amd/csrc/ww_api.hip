@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/ww.h: context and workspace, the
 // per-stage kernel sequence, the march to T/4 and the outputs.
 #include <hip/hip_runtime.h>
+#include <hip/hip_ext.h>
 
 #include <cmath>
 #include <cstdio>
@@ -121,6 +122,9 @@ struct ww_ctx {
   // replayed step are read back by ww_profile_read
   bool prof = false;
   int prof_stage = -1;   // stage being enqueued (marks are taken only inside a step)
+  bool prof_kev = false;   // time every directly launched block-LU step with HIP events
+  std::vector<hipEvent_t> kev_a, kev_b;
+  size_t kev_n = 0;
   unsigned long long* stamps = nullptr;   // [phase][stage] x {start, sum, count}
   // host time spent enqueueing the steps of profiled marches (phase 3), and their count
   double host_enq_ms = 0.0;
@@ -477,6 +481,8 @@ void ww_destroy(ww_ctx* c) {
   if (c->pgend) (void)hipGraphExecDestroy(c->pgend);
   if (c->pgendc) (void)hipGraphExecDestroy(c->pgendc);
   if (c->evE) (void)hipEventDestroy(c->evE);
+  for (hipEvent_t e : c->kev_a) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->kev_b) (void)hipEventDestroy(e);
   if (c->stamps) (void)hipFree(c->stamps);
   if (c->ckpt) (void)hipFree(c->ckpt);
   if (c->seg) (void)hipFree(c->seg);
@@ -590,15 +596,54 @@ static BluBufs<T> blu_bufs(ww_ctx* c, T* A, T* X, T* Z, T* V, T* D, double guard
   return b;
 }
 
+// measurement hook: a pair of HIP events attached to one kernel dispatch on the current
+// stream (hipExtLaunchKernel: the events take the dispatch's own start and end times),
+// only inside a march step, where the phase marks are taken too, outside stream capture,
+// and at most KEV_MAX pairs per profiled interval; *a = *b = null when off
+static const size_t KEV_MAX = 1u << 14;
+static int kev_pair(ww_ctx* c, hipEvent_t* a, hipEvent_t* b) {
+  *a = *b = nullptr;
+  if (!c->prof_kev || c->prof_stage < 0 || c->kev_n >= KEV_MAX) return 0;
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  HIPCHK(hipStreamIsCapturing(c->stream, &cs));
+  if (cs != hipStreamCaptureStatusNone) return 0;
+  if (c->kev_n == c->kev_a.size()) {
+    hipEvent_t ea = nullptr, eb = nullptr;
+    HIPCHK(hipEventCreate(&ea));
+    const hipError_t e = hipEventCreate(&eb);
+    if (e != hipSuccess) {
+      (void)hipEventDestroy(ea);
+      HIPCHK(e);
+    }
+    c->kev_a.push_back(ea);
+    c->kev_b.push_back(eb);
+  }
+  *a = c->kev_a[c->kev_n];
+  *b = c->kev_b[c->kev_n];
+  return 0;
+}
+
 template <typename T>
 static int enqueue_blu(ww_ctx* c, const BluGroup<T>& g) {
   const int nb = c->Np / WW_TB;
   const size_t es = sizeof(T);
+  int rc;
   hipLaunchKernelGGL(k_blu_init<T>, dim3(g.count), dim3(WW_NT), (TILE_DBL + GJ_SCR) * es, c->stream, g);
   LAUNCHCHK();
   for (int k = 0; k + 1 < nb; ++k) {
     const int nblk = blu_step_tasks(nb, k, g.strip);
-    hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk * g.count), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, g, k);
+    hipEvent_t ea, eb;
+    if ((rc = kev_pair(c, &ea, &eb))) return rc;
+    if (ea) {
+      BluGroup<T> ga = g;
+      int ka = k;
+      void* args[] = {&ga, &ka};
+      HIPCHK(hipExtLaunchKernel(reinterpret_cast<const void*>(&k_blu_step<T>), dim3(nblk * g.count), dim3(WW_NT),
+                                args, 2 * TILE_DBL * es, c->stream, ea, eb, 0));
+      ++c->kev_n;
+    } else {
+      hipLaunchKernelGGL(k_blu_step<T>, dim3(nblk * g.count), dim3(WW_NT), 2 * TILE_DBL * es, c->stream, g, k);
+    }
     LAUNCHCHK();
   }
   if (nb > 1) {
@@ -1521,6 +1566,8 @@ int dtn_solve_multi_noalloc(ww_ctx* c, const double* rhs, int nrhs, double* dtn_
 
 int ww_profile(ww_ctx* c, int enable) {
   if (!c) return fail(WW_EINVAL, "null argument");
+  c->prof_kev = (enable & 2) != 0;
+  c->kev_n = 0;
   if (enable && !c->stamps) HIPCHK(hipMalloc(&c->stamps, 3 * 16 * 3 * sizeof(unsigned long long)));
   if (enable) HIPCHK(hipMemsetAsync(c->stamps, 0, 3 * 16 * 3 * sizeof(unsigned long long), c->stream));
   if (enable) {
@@ -1535,8 +1582,21 @@ int ww_profile(ww_ctx* c, int enable) {
 }
 
 int ww_profile_read(ww_ctx* c, int phase, double* avg_ms, int* count) {
-  if (!c || !avg_ms || phase < 0 || phase > 3) return fail(WW_EINVAL, "bad argument");
+  if (!c || !avg_ms || phase < 0 || phase > 4) return fail(WW_EINVAL, "bad argument");
   if (!c->prof || !c->stamps) return fail(WW_EINVAL, "profiling is off");
+  if (phase == 4) {
+    if (c->kev_n == 0) return fail(WW_EINVAL, "no block-LU step launched outside graphs since ww_profile");
+    double sum = 0.0;
+    for (size_t i = 0; i < c->kev_n; ++i) {
+      HIPCHK(hipEventSynchronize(c->kev_b[i]));
+      float ms = 0.0f;
+      HIPCHK(hipEventElapsedTime(&ms, c->kev_a[i], c->kev_b[i]));
+      sum += ms;
+    }
+    *avg_ms = sum / (double)c->kev_n;
+    if (count) *count = (int)c->kev_n;
+    return 0;
+  }
   if (phase == 3) {
     if (c->host_enq_steps == 0) return fail(WW_EINVAL, "no profiled step");
     *avg_ms = c->host_enq_ms / (double)c->host_enq_steps;

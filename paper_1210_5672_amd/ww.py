@@ -322,8 +322,10 @@ class Context:
         t = Tuning(**{k: int(v) for k, v in cur.items()})
         _check(self.lib.ww_set_tuning(self.ptr, ctypes.byref(t)))
 
-    def profile(self, enable: bool = True):
-        _check(self.lib.ww_profile(self.ptr, 1 if enable else 0))
+    def profile(self, enable: bool = True, kernel_events: bool = False):
+        """Timestamps around the phases of every stage; with kernel_events, also HIP
+        events around every block-LU step launched outside a graph (phase 4)."""
+        _check(self.lib.ww_profile(self.ptr, (1 if enable else 0) | (2 if enable and kernel_events else 0)))
 
     def profile_read(self, phase: int) -> float:
         """Mean duration (ms) of a phase over every stage of every step replayed since

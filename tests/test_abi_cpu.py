@@ -138,3 +138,24 @@ def test_tuning_calls_reject_null_arguments_without_gpu():
     t = ww.Tuning()
     assert lib.ww_get_tuning(None, ctypes.byref(t)) == -1   # WW_EINVAL
     assert lib.ww_set_tuning(None, ctypes.byref(t)) == -1
+
+
+def test_blu_step_flop_count_is_the_lu_count():
+    """The per-launch flop figure of the block-LU step: summed over the steps, the left
+    factors and the trailing updates of a right-looking block LU come to
+    2/3 (N^3 - N b^2), i.e. 2/3 N^3 less the work of the diagonal-block inversions;
+    brute-force count over the tiles at small sizes."""
+    import importlib.util
+    spec = importlib.util.spec_from_file_location("bench_mod", os.path.join(ROOT, "bench.py"))
+    bench = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(bench)
+    for N, b in ((64, 64), (256, 64), (1024, 64), (96, 8)):
+        nb = N // b
+        brute = 0
+        for k in range(nb - 1):
+            for i in range(k + 1, nb):
+                brute += 2 * b ** 3          # L_ik = A_ik D_k
+                for j in range(k + 1, nb):
+                    brute += 2 * b ** 3      # A_ij -= L_ik A_kj
+        assert bench.blu_step_flops(N, b) == brute
+        assert abs(brute - (2.0 / 3.0) * (N ** 3 - N * b * b)) < 1e-6 * N ** 3

@@ -131,6 +131,35 @@ def test_phase_profile_in_the_lagged_march():
     assert ctx.fallbacks() == 0
 
 
+def test_block_lu_step_events():
+    """Kernel events (ww_profile bit 2, phase 4): every block-LU step launched directly
+    is timed, nb - 1 launches per LU sequence; none while the LU is replayed from graphs."""
+    ww, torch = _ww()
+    w = W.c2()
+    nsteps = 24
+    T = w.T * nsteps / w.nsteps
+    nb = w.N // 64
+    for parts, timed in ((0, True), (10, False)):
+        ctx = ww.Context(n_max=w.N, r_max=w.M + 1)
+        ctx.set_tuning(graph_parts=parts)
+        ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+        ctx.profile(True, kernel_events=True)
+        ctx.shoot_eval(ww.to_dev(w.params), T, nsteps)
+        seq_ms, seq_n = ctx.profile_stats(0)
+        print("graph_parts", parts, "sequences", seq_n, "mean", seq_ms, flush=True)
+        assert ctx.fallbacks() == 0 and seq_n > 0
+        if timed:
+            step_ms, step_n = ctx.profile_stats(4)
+            print("step launches", step_n, "mean ms", step_ms, flush=True)
+            assert step_n == (nb - 1) * seq_n
+            assert 0 < step_ms < seq_ms
+        else:
+            with pytest.raises(ww.WWError):
+                ctx.profile_stats(4)
+        ctx.profile(False)
+        ctx.close()
+
+
 def _ctx_env(ww, n_max, r_max, env):
     """A context created under the given environment variables (read by ww_create)."""
     import os
