@@ -8,6 +8,9 @@ and the two share no code.
                  the passage of the paper it follows.
   xprec.py     : the same reference run in 34-digit mpmath arithmetic, to measure
                  the FP64 rounding floor on small problems.
+  mesh_oracle.py : the non-uniform mesh x = xi(alpha) and the time segments with
+                 regridding (Sec. 2.2 eq. (xi), (rho:def)), pinned by
+                 tests/test_mesh_oracle.py.
 
 Parity status: every function is pinned by tests/test_oracle_pins.py (closed forms,
 printed linear periods, invariants, central differences, extended precision).
