@@ -202,6 +202,48 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
                double *drdT, double *f);
 
 /*
+ * Time segments on non-uniform meshes (Sec. 2.2 eq. (xi), (rho:def)).  The march to T/4
+ * is split into segments l = 0..nseg-1 of theta_l T / 4 each (the theta_l sum to 1),
+ * segment l with its own grid of N_l points and nsteps_l steps of theta_l T / (4
+ * nsteps_l), on the mesh x = xi_l(alpha), alpha_j = 2 pi j / N_l:
+ *   E_l = xi_l' = 1 - P[A_l sin^4(alpha/2)]   (refine_at = WW_REFINE_PI: finest at x = pi)
+ *   E_l = xi_l' = 1 - P[A_l cos^4(alpha/2)]   (refine_at = WW_REFINE_ZERO: finest at x = 0)
+ *   A_l = 8 (1 - rho_l) / (5 + 3 rho_l),  rho_l = min E_l / max E_l in (0, 1] (1: uniform)
+ * The state and the Jacobian columns hold values at x_j = xi_l(alpha_j).  On the mapped
+ * grid the kernels use zeta = xi + i eta (zeta' = E + i eta_alpha), x-derivatives
+ * (1/E) d/dalpha, the DtN output divided by E, and the zero-mean projection in x (the
+ * E-weighted mean); the filter acts in alpha.  Between segments every state column is
+ * carried to the next mesh by its trigonometric interpolant in alpha evaluated at
+ * xi_l^{-1}(xi_{l+1}(alpha_j)).  Mesh rule: if rho_{l+1} < rho_l then
+ * N_{l+1} / N_l >= (5 + 3 rho_l) / (5 + 3 rho_{l+1}).
+ */
+#define WW_REFINE_PI 0
+#define WW_REFINE_ZERO 1
+typedef struct ww_segment {
+  int N;          /* grid points (even, 2^a 3^b, 16 <= N <= n_max) */
+  int nsteps;     /* steps of the segment (>= 1) */
+  double theta;   /* fraction of T/4 (> 0; the fractions sum to 1 within 1e-12) */
+  double rho;     /* mesh ratio, 0 < rho <= 1 */
+  int refine_at;  /* WW_REFINE_PI or WW_REFINE_ZERO */
+} ww_segment;
+
+/*
+ * shoot_eval_segments: shoot_eval over the segments segs[0..nseg-1] (1 <= nseg <= 64;
+ * host array).  segs[0].N must equal shoot_setup's N: the basis and q_fixed are values
+ * on the first segment's mesh.  Outputs on the last segment's grid (N = segs[nseg-1].N;
+ * device, caller-owned), with the weights w_i = sqrt(E_i / N) of the mesh spacing:
+ *   r (N) = w varphi(T/4),  J (N x M) = w phidot(T/4) or NULL,
+ *   drdT (N) = w varphi_t(T/4) / 4 or NULL,  f (host) = r.r / 2 or NULL.
+ * Every stage solves with its own factors (no lagged factors, no GMRES base solves);
+ * the fallbacks of shoot_eval apply to the whole segmented march.  Synchronises.
+ * Errors: WW_ENOSETUP, WW_EINVAL (a segment out of range, fractions not summing to 1,
+ * the mesh rule, segs[0].N differing from shoot_setup's N), WW_EPIVOT, WW_ENONFINITE,
+ * WW_EDOMAIN, WW_EREFINE (WW_STRICT), WW_EHIP.
+ */
+int shoot_eval_segments(ww_ctx *ctx, const double *params, double T, int nseg, const ww_segment *segs,
+                        double *r, double *J, double *drdT, double *f);
+
+/*
  * shoot_eval_batch: shoot_eval for n_inst independent instances (continuation
  * instances of uneven N, depth, tension, M and step count), each with its own context
  * (distinct contexts; give them distinct streams for the instances to overlap).  Each

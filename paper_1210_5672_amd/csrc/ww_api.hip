@@ -12,6 +12,7 @@
 
 #include "ww.h"
 #include "ww_kernels.hpp"
+#include "ww_mesh.hpp"
 #include "ww_svd.hpp"
 #include "ww_gmres.hpp"
 
@@ -109,6 +110,12 @@ struct ww_ctx {
   double *basis = nullptr, *qfix = nullptr;
   double* coef = nullptr;
   double* fdev = nullptr;
+  // non-uniform mesh of the segmented march (shoot_eval_segments only): while `mapped`,
+  // the assembly, right-hand sides and outputs take the mapped-grid kernels and read
+  // the per-point tables of the current segment (MESH_COUNT x n_max doubles)
+  bool mapped = false;
+  double* mesh = nullptr;
+  int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
   // adjoint: checkpoints, per-stage factor storage of one segment, work vectors
@@ -456,6 +463,12 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     CCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize,
                              big - (int)fa.sharedSizeBytes));
   }
+  for (const void* fn : {(const void*)k_base_rhs_map, (const void*)k_col_rhs_map}) {
+    // static LDS (a reduction buffer) besides the dynamic transform buffers
+    hipFuncAttributes fa;
+    CCHK(hipFuncGetAttributes(&fa, fn));
+    CCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, big - (int)fa.sharedSizeBytes));
+  }
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_dtn<16>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -748,6 +761,14 @@ static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar, const Fac* Fo = nullptr,
                             const double* psi = nullptr, double* x0 = nullptr) {
   const int nb = c->Np / WW_TB;
+  if (c->mapped) {
+    if (Fo) return fail(WW_EHIP, "internal: lagged solve on the mapped grid");
+    hipLaunchKernelGGL(k_assemble_map, dim3(nb, c->Np / 16), dim3(WW_NT), 0, c->stream, F.aux, c->mesh, c->n_max,
+                       c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, (F.use32 || want_ar) ? F.Ar : nullptr,
+                       c->N, c->Np, c->finite);
+    LAUNCHCHK();
+    return 0;
+  }
   const bool f32 = Fo && (Fo->use32 || Fo->lag32);
   const double* mx64 = (Fo && !f32) ? Fo->Mi : nullptr;
   const float* mx32 = f32 ? Fo->Mi32 : nullptr;
@@ -1003,9 +1024,13 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
     if ((rc = enqueue_assemble_lu(c, F))) return rc;
     if ((rc = enqueue_dtn_cols(c, F, c->rhs0, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
   }
-  hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
-                     c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
-                     c->tau);
+  if (c->mapped)
+    hipLaunchKernelGGL(k_base_rhs_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0,
+                       F.aux, c->mesh, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+  else
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
+                       c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
+                       c->tau);
   LAUNCHCHK();
   return prof_mark(c, 1, 1);
 }
@@ -1020,8 +1045,13 @@ static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
                      F.aux, c->n_max, c->Psi, c->Np, c->N, M);
   LAUNCHCHK();
   if ((rc = enqueue_dtn_cols(c, F, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
-  hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
-                     F.aux, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
+  if (c->mapped)
+    hipLaunchKernelGGL(k_col_rhs_map, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi,
+                       c->Np, F.aux, c->mesh, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g,
+                       c->tau);
+  else
+    hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
+                       F.aux, c->n_max, c->K + (size_t)s * kstride(c), c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
   return prof_mark(c, 2, 1);
 }
@@ -1035,7 +1065,7 @@ static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
 // uses the exact factors of its stage.
 static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
   (void)cols;   // with or without Jacobian columns (c->pcols)
-  return c->lag > 0 && two_streams && c->fb == 0 && c->nst > c->lag && !c->gm_active;
+  return c->lag > 0 && two_streams && c->fb == 0 && c->nst > c->lag && !c->gm_active && !c->mapped;
 }
 
 // a march without columns keeps to two LU streams: they carry its LUs, and a third
@@ -1394,7 +1424,7 @@ static int enqueue_step(ww_ctx* c, bool cols, bool two_streams) {
 static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   if (c->step_exec && c->gN == c->N && c->gM == c->M && c->gcols == (int)cols && c->gnst == c->nst &&
       c->gtwo == (int)two_streams && c->gfb == c->fb && c->ggm == (c->gm_active ? c->gm_m : 0) &&
-      c->gtune == c->tune_gen)
+      c->gtune == c->tune_gen && c->gmap == (int)c->mapped)
     return 0;
   if (c->step_exec) {
     HIPCHK(hipDeviceSynchronize());   // every branch of its last replay has ended
@@ -1424,6 +1454,7 @@ static int ensure_step_graph(ww_ctx* c, bool cols, bool two_streams) {
   c->gfb = c->fb;
   c->ggm = c->gm_active ? c->gm_m : 0;
   c->gtune = c->tune_gen;
+  c->gmap = (int)c->mapped;
   return 0;
 }
 
@@ -1651,6 +1682,17 @@ int shoot_setup(ww_ctx* c, int N, double h, double tau, double g, const double* 
 // the pivoting fallback launches two kernels per column of A and runs without a graph
 static bool graphed(const ww_ctx* c) { return c->use_graph && !pivoted(c); }
 
+// step coefficients a_sj dt, b_s dt and dt of nsteps steps over T/4
+static void coef_fill(const ww_ctx* c, double T, int nsteps, double* coef) {
+  std::memset(coef, 0, COEF_SIZE * sizeof(double));
+  const double dt = T / (4.0 * nsteps);
+  for (int s = 0; s < c->nst; ++s) {
+    for (int j = 0; j < s; ++j) coef[s * 16 + j] = c->ta[s * 16 + j] * dt;
+    coef[COEF_B + s] = c->tb[s] * dt;
+  }
+  coef[COEF_DT] = dt;
+}
+
 // shoot_eval in three parts so that shoot_eval_batch can interleave instances:
 // prepare (coefficients, initial state, step graph), one step, finish (outputs).
 static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, bool cols, bool two_streams) {
@@ -1663,13 +1705,7 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   c->dtn_ready = false;   // the factor arrays are reused by the march
   const int N = c->N, M = c->M;
   double coef[COEF_SIZE];
-  std::memset(coef, 0, sizeof(coef));
-  const double dt = T / (4.0 * nsteps);
-  for (int s = 0; s < c->nst; ++s) {
-    for (int j = 0; j < s; ++j) coef[s * 16 + j] = c->ta[s * 16 + j] * dt;
-    coef[COEF_B + s] = c->tb[s] * dt;
-  }
-  coef[COEF_DT] = dt;
+  coef_fill(c, T, nsteps, coef);
   HIPCHK(hipMemcpyAsync(c->coef, coef, sizeof(coef), hipMemcpyHostToDevice, c->stream));
   hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
   LAUNCHCHK();
@@ -1677,7 +1713,7 @@ static int shoot_prepare(ww_ctx* c, const double* params, double T, int nsteps, 
   const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_init_state, dim3(blocks), dim3(256), 0, c->stream, c->y, c->basis, c->qfix, params, N, M);
   LAUNCHCHK();
-  c->gm_active = (c->flags & WW_GMRES) && !cols && c->fb == 0;
+  c->gm_active = (c->flags & WW_GMRES) && !cols && c->fb == 0 && !c->mapped;
   if (c->gm_active) {
     if ((rc = ensure_gmres(c))) return rc;
     if (!c->gm_fixed && (rc = gmres_calibrate(c))) return rc;
@@ -1723,8 +1759,12 @@ static int shoot_finish(ww_ctx* c, bool cols, double* r, double* J, double* drdT
   {
     const size_t tot = (size_t)N * (M + 1);
     const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_outputs, dim3(blocks), dim3(256), 0, c->stream, c->y, c->Kx, r, cols ? J : nullptr, drdT, N,
-                       cols ? M : 0);
+    if (c->mapped)
+      hipLaunchKernelGGL(k_outputs_map, dim3(blocks), dim3(256), 0, c->stream, c->y, c->Kx, c->mesh, c->n_max, r,
+                         cols ? J : nullptr, drdT, N, cols ? M : 0);
+    else
+      hipLaunchKernelGGL(k_outputs, dim3(blocks), dim3(256), 0, c->stream, c->y, c->Kx, r, cols ? J : nullptr, drdT,
+                         N, cols ? M : 0);
     LAUNCHCHK();
   }
   hipLaunchKernelGGL(k_objective, dim3(1), dim3(WW_NT), 0, c->stream, r, N, c->fdev, (const double*)nullptr);
@@ -1827,12 +1867,115 @@ static int shoot_eval_fb(ww_ctx* c, const double* params, double T, int nsteps, 
   }
 }
 
+// ----- segmented march on non-uniform meshes (Sec. 2.2 eq. (xi), (rho:def)) -----
+#define WW_MAX_SEGMENTS 64
+static double mesh_coef(double rho) { return 8.0 * (1.0 - rho) / (5.0 + 3.0 * rho); }
+
+static int seg_check(const ww_ctx* c, int nseg, const ww_segment* sg) {
+  if (nseg < 1 || nseg > WW_MAX_SEGMENTS || !sg) return fail(WW_EINVAL, "1 <= nseg <= 64 segments required");
+  double tsum = 0.0;
+  for (int l = 0; l < nseg; ++l) {
+    const ww_segment& q = sg[l];
+    if (!valid_n(q.N) || q.N > c->n_max) return fail(WW_EINVAL, "segment N must be even, 2^a 3^b, 16 <= N <= n_max");
+    if (q.nsteps < 1) return fail(WW_EINVAL, "segment nsteps >= 1 required");
+    if (!(q.theta > 0.0) || !std::isfinite(q.theta)) return fail(WW_EINVAL, "segment theta must be positive");
+    if (!(q.rho > 0.0 && q.rho <= 1.0)) return fail(WW_EINVAL, "segment rho must lie in (0, 1]");
+    if (q.refine_at != WW_REFINE_PI && q.refine_at != WW_REFINE_ZERO) return fail(WW_EINVAL, "bad refine_at");
+    tsum += q.theta;
+    if (l > 0) {
+      const ww_segment& p = sg[l - 1];
+      if (q.rho < p.rho && q.N * (5.0 + 3.0 * q.rho) < p.N * (5.0 + 3.0 * p.rho) * (1.0 - 1e-15))
+        return fail(WW_EINVAL, "refining the mesh needs N_l+1 / N_l >= (5 + 3 rho_l) / (5 + 3 rho_l+1)");
+    }
+  }
+  if (std::fabs(tsum - 1.0) > 1e-12) return fail(WW_EINVAL, "the segment fractions theta must sum to 1");
+  if (sg[0].N != c->shootN) return fail(WW_EINVAL, "the first segment's N must be shoot_setup's N (the basis grid)");
+  return 0;
+}
+
+// one segmented march in the current fallback mode: segment 0 starts from the initial
+// state on its mesh; at each later segment the state (and the Jacobian columns) is
+// regridded to the new mesh, then the segment marches its steps of theta_l T / (4
+// nsteps_l) each; the outputs are taken on the last mesh
+static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* sg, double* r, double* J,
+                   double* drdT, double* f, int* st, int* where) {
+  const bool cols = (J != nullptr) && c->M > 0;
+  const bool two = c->overlap && !pivoted(c);
+  int rc;
+  if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
+  if (!c->mesh && (rc = dalloc(c, (void**)&c->mesh, (size_t)MESH_COUNT * c->n_max * 8))) return rc;
+  for (int l = 0; l < nseg; ++l) {
+    const double Tl = sg[l].theta * T;
+    const double Al = mesh_coef(sg[l].rho);
+    if (l == 0) {
+      if ((rc = shoot_prepare(c, params, Tl, sg[0].nsteps, cols, two))) return rc;
+    } else {
+      const int No = c->N, Nn = sg[l].N;
+      const int ncols = 2 * (cols ? c->M + 1 : 1);
+      // interpolation weights (row-major Nn x No, in the A buffer of the default factor
+      // set, free between segments), then the old state to the stage buffer
+      hipLaunchKernelGGL(k_regrid_w, dim3(Nn), dim3(WW_NT), 0, c->stream, c->A, Nn, No, Al, sg[l].refine_at,
+                         mesh_coef(sg[l - 1].rho), sg[l - 1].refine_at);
+      LAUNCHCHK();
+      HIPCHK(hipMemcpyAsync(c->Ys, c->y, (size_t)ncols * No * 8, hipMemcpyDeviceToDevice, c->stream));
+      if ((rc = set_grid(c, Nn, c->shootH))) return rc;
+      hipLaunchKernelGGL(k_regrid_apply, dim3((Nn + 63) / 64, (ncols + 63) / 64), dim3(WW_NT), 0, c->stream, c->A,
+                         c->Ys, c->y, Nn, No, ncols);
+      LAUNCHCHK();
+      double coef[COEF_SIZE];
+      coef_fill(c, Tl, sg[l].nsteps, coef);
+      HIPCHK(hipStreamSynchronize(c->stream));
+      HIPCHK(hipMemcpy(c->coef, coef, sizeof(coef), hipMemcpyHostToDevice));
+      if (graphed(c) && (rc = ensure_step_graph(c, cols, two))) return rc;
+    }
+    hipLaunchKernelGGL(k_mesh_tables, dim3((sg[l].N + 255) / 256), dim3(256), 0, c->stream, c->mesh, c->n_max,
+                       sg[l].N, Al, sg[l].refine_at);
+    LAUNCHCHK();
+    for (int n = 0; n < sg[l].nsteps; ++n)
+      if ((rc = shoot_one_step(c, cols, two))) return rc;
+  }
+  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
+    const std::string msg = g_err;
+    (void)hipStreamSynchronize(c->stream);
+    g_err = msg;
+    return rc;
+  }
+  return read_status(c, st, where);
+}
+
 extern "C" {
 
 int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
                double* f) {
   if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
   return shoot_eval_fb(c, params, T, nsteps, r, J, drdT, f, c->lag_off ? WW_FB_DIRECT : 0);
+}
+
+int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,
+                        double* J, double* drdT, double* f) {
+  if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
+  if (int rj = pipe_join(c)) return rj;
+  if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_eval_segments before shoot_setup");
+  if (!std::isfinite(T)) return fail(WW_EINVAL, "finite T required");
+  int rc;
+  if ((rc = seg_check(c, nseg, segs))) return rc;
+  struct Mapped {   // the mapped-grid kernels for this call only
+    ww_ctx* c;
+    explicit Mapped(ww_ctx* cc) : c(cc) { c->mapped = true; }
+    ~Mapped() { c->mapped = false; }
+  } mapped_scope(c);
+  c->fb = 0;
+  for (;;) {
+    int st = 0, where = 0;
+    if ((rc = seg_run(c, params, T, nseg, segs, r, J, drdT, f, &st, &where))) return rc;
+    const unsigned nf = next_fallback(c, st);
+    if (!nf) {
+      if ((rc = status_error(c, st, where))) return rc;
+      c->fb_last = c->fb;
+      return 0;
+    }
+    c->fb |= nf;
+  }
 }
 
 int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params, const double* T,

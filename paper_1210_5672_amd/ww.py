@@ -60,6 +60,15 @@ class Tuning(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class Segment(ctypes.Structure):
+    """One time segment on a non-uniform mesh (ww_segment)."""
+    _fields_ = [("N", ctypes.c_int), ("nsteps", ctypes.c_int), ("theta", ctypes.c_double),
+                ("rho", ctypes.c_double), ("refine_at", ctypes.c_int)]
+
+
+REFINE_PI, REFINE_ZERO = 0, 1
+
+
 class LmReport(ctypes.Structure):
     _fields_ = [("f", ctypes.c_double), ("delta", ctypes.c_double), ("evals_r", ctypes.c_int),
                 ("evals_J", ctypes.c_int), ("reason", ctypes.c_int), ("n_hist", ctypes.c_int),
@@ -69,7 +78,8 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "dtn_solve_multi", "shoot_setup", "shoot_eval", "shoot_adjoint", "ww_last_error",
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
-           "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning"]
+           "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning",
+           "shoot_eval_segments"]
 
 
 class WWError(RuntimeError):
@@ -107,6 +117,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_setup.argtypes = [P, I, D, D, D, P, P, I]
     lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
     lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]
+    lib.shoot_eval_segments.argtypes = [P, P, D, I, ctypes.POINTER(Segment), P, P, P, DP]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.shoot_eval_batch.argtypes = [I, PP, PP, DP, ctypes.POINTER(ctypes.c_int), PP, PP, PP, DP]
     lib.shoot_eval_batch.restype = I
@@ -246,6 +257,24 @@ class Context:
         f = ctypes.c_double(0.0)
         _check(self.lib.shoot_eval(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
                                    _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
+        return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
+
+    def shoot_eval_segments(self, params: torch.Tensor, T: float, segments, jacobian: bool = True,
+                            drdT: bool = True):
+        """The march over time segments on non-uniform meshes (shoot_eval_segments).
+        segments: dicts with N, nsteps, theta, rho and refine_at (REFINE_PI default);
+        the outputs live on the last segment's grid."""
+        segs = (Segment * len(segments))(*[Segment(int(q["N"]), int(q["nsteps"]), float(q["theta"]),
+                                                   float(q["rho"]), int(q.get("refine_at", REFINE_PI)))
+                                           for q in segments])
+        N, M = int(segments[-1]["N"]), (self.M if self.M is not None else 0)
+        dev = params.device
+        r = torch.empty(N, dtype=torch.float64, device=dev)
+        Jc = torch.empty((M, N), dtype=torch.float64, device=dev) if jacobian else None
+        d = torch.empty(N, dtype=torch.float64, device=dev) if drdT else None
+        f = ctypes.c_double(0.0)
+        _check(self.lib.shoot_eval_segments(self.ptr, _ptr(params.contiguous()), float(T), len(segments), segs,
+                                            _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
 
     def fallbacks(self) -> int:
