@@ -196,6 +196,39 @@ def run_adjoint(reps: int = 2):
             "f_ms": 1e3 * tf, "grad_ms": 1e3 * tg, "grad_over_f": tg / tf}
 
 
+def run_mesh(reps: int = 2, tuned: bool = True):
+    """Time segments on non-uniform meshes (the C6 workload: two segments, N 768 then
+    1024 with the mesh refined near x = pi, 24 + 144 steps, 200 parameters):
+    shoot_eval_segments, column-steps/s = M x (total steps) / wall time, with the error
+    against the stored oracle run when present."""
+    import torch
+    from paper_1210_5672_amd import autotune, workloads as W
+    from paper_1210_5672_amd import ww
+    w = W.c6()
+    nmax = max(q["N"] for q in w.segments)
+    ctx = ww.Context(n_max=nmax, r_max=w.M + 1)
+    from_cache = bool(autotune.apply(ctx, nmax, w.M, segments=True)) if tuned else False
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    p = ww.to_dev(w.params)
+    res = ctx.shoot_eval_segments(p, w.T, w.segments)   # captures the step graphs
+    torch.cuda.synchronize()
+    each = []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        res = ctx.shoot_eval_segments(p, w.T, w.segments)
+        each.append(time.perf_counter() - t0)
+    print("# mesh segments timed", file=sys.stderr, flush=True)
+    steps = sum(q["nsteps"] for q in w.segments)
+    t = statistics.median(each)
+    out = {"workload": w.description, "value": w.M * steps / t, "unit": "column-steps/s", "ms": 1e3 * t,
+           "fallbacks": ctx.fallbacks(), "tuning": ctx.tuning(), "tuning_from_cache": from_cache}
+    fx = oracle_fixture("c6")
+    if fx is not None:
+        out["err_vs_oracle"] = err_vs_oracle(res, fx)
+    ctx.close()
+    return out
+
+
 def stage_roofline(N, M, nst, stage_ms):
     """Whole-stage roofline: the algorithmic work of one stage at the FP64 MFMA peak and
     the HBM bandwidth, summed phase by phase (each phase at its own bound), against the
@@ -379,6 +412,7 @@ def main():
     ap.add_argument("--no-f-only", action="store_true", help="skip the f-only (GMRES) measurement")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (C4)")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner's cached choices")
+    ap.add_argument("--no-mesh", action="store_true", help="skip the segmented non-uniform-mesh march (C6)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -479,6 +513,8 @@ def main():
         out["f_only"] = run_f_only(w, nsteps, T)
     if not args.no_adjoint:
         out["adjoint"] = run_adjoint()
+    if not args.no_mesh:
+        out["mesh"] = run_mesh(tuned=not args.no_tuning)
     if not args.no_batch:
         out["batch"] = run_batch(tuned=not args.no_tuning)
     if args.copy_probe:

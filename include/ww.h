@@ -439,13 +439,17 @@ unsigned ww_next_fallback(unsigned flags, unsigned fb, int status);
  *                the residuals stay FP64 and the solve still ends with the 2^-43 test, so
  *                only the contraction per sweep changes (half the bytes per product)
  *   asm_cw       columns per assembly workgroup, 16 or 32
+ *   lag_sweeps   refinement sweeps of a lagged-factor base solve, 1..8 (default 2, or
+ *                WW_NREF_LAG); each sweep multiplies the error by about
+ *                ||A_old^-1 A - I||, so marches whose matrix moves faster per step need
+ *                more of them to pass the 2^-43 test (else they fall back)
  * ww_set_tuning validates every field and applies them together (captured graphs are
  * re-captured at the next march); ww_get_tuning reads the current choices.  Host only.
  * Errors: WW_EINVAL (null argument, a field out of range).
  */
 typedef struct ww_tuning {
   int lag, lu_group, lu_streams, graph_parts, minv_wgs, blu_strip, dtn_rows, gemm_split, asm_cw, gemm_rows,
-      lag_fp32;
+      lag_fp32, lag_sweeps;
 } ww_tuning;
 int ww_get_tuning(ww_ctx *ctx, ww_tuning *t);
 int ww_set_tuning(ww_ctx *ctx, const ww_tuning *t);

@@ -4,8 +4,8 @@ DOP853 march on the mapped grid x = xi(alpha), and the regridding between time
 segments.
 
 TEST INFRASTRUCTURE ONLY, like oracle/ww_oracle.py (whose spectral operators, cot
-branch formula and tableau it uses); it shares no code with the GPU library.  FP64
-numpy only.
+branch formula, tableau and FP64 arithmetic backends it uses); it shares no code with
+the GPU library.  FP64 numpy backends only (the default and the alternate roundings).
 
 What is computed (N points alpha_j = 2 pi j / N on segment l, the state eta, varphi
 and the Jacobian columns held at x_j = xi(alpha_j)):
@@ -114,14 +114,14 @@ def check_segments(segments):
 # DtN on the mapped grid, Sec. 2.1-2.2 and App. A
 # --------------------------------------------------------------------------------
 
-def assemble_mapped(eta, h, mesh: Mesh):
+def assemble_mapped(eta, h, mesh: Mesh, ar=O.F64):
     """A = I/2 + K/N and Gm = G/N of eq. (fred) and (G) for the curve
     zeta = xi + i eta, with the (K1K2) kernels (reading R1 for the image terms)."""
     N = eta.shape[0]
     E, Ep, xi, alpha = mesh.E, mesh.Ep, mesh.xi, mesh.alpha
     et = O.surface_height(eta, h)
-    ex = O.deriv(eta)               # Im zeta'  (alpha-derivative)
-    exx = O.deriv(ex)               # Im zeta''
+    ex = O.deriv(eta, ar)           # Im zeta'  (alpha-derivative)
+    exx = O.deriv(ex, ar)           # Im zeta''
     x = xi[:, None] - xi[None, :]
     y = et[:, None] - et[None, :]
     xo = x.copy()
@@ -129,8 +129,8 @@ def assemble_mapped(eta, h, mesh: Mesh):
     for i in range(N):
         xo[i, i] = np.pi
         ao[i, i] = np.pi
-    cre, cim = O.cot_half(xo, y)
-    c0re, _ = O.cot_half(ao, 0 * ao)
+    cre, cim = O.cot_half(xo, y, ar)
+    c0re, _ = O.cot_half(ao, 0 * ao, ar)
     c0 = c0re / 2
     # K1 = Im{zeta'_j C}/2 with zeta'_j = E_j + i ex_j; G1 = Re{zeta'_i C}/2 - c0
     K = (E[None, :] * cim + ex[None, :] * cre) / 2
@@ -144,7 +144,7 @@ def assemble_mapped(eta, h, mesh: Mesh):
         G[i, i] = gd[i]
     if not math.isinf(h):
         yb = et[:, None] + et[None, :]
-        dre, dim = O.cot_half(x, yb)
+        dre, dim = O.cot_half(x, yb, ar)
         # K2 = -Im{conj(zeta'_j) D}/2, G2 = -Re{zeta'_i D}/2
         K = K - (E[None, :] * dim - ex[None, :] * dre) / 2
         G = G - (E[:, None] * dre - ex[:, None] * dim) / 2
@@ -155,25 +155,24 @@ def assemble_mapped(eta, h, mesh: Mesh):
 class DtNMapped:
     """Assemble, factor once, apply to any number of right-hand sides."""
 
-    def __init__(self, eta, h, mesh: Mesh):
-        import scipy.linalg
-        self.mesh = mesh
-        self.A, self.Gm = assemble_mapped(eta, h, mesh)
-        self.lu = scipy.linalg.lu_factor(self.A)
+    def __init__(self, eta, h, mesh: Mesh, ar=O.F64):
+        self.mesh, self.ar = mesh, ar
+        self.A, self.Gm = assemble_mapped(eta, h, mesh, ar)
+        self.lu = ar.lu_factor(self.A)
 
     def apply(self, psi):
         """G psi = [H gamma / 2 + Gm gamma] / E, gamma = d mu / d alpha, A mu = psi."""
-        import scipy.linalg
-        mu = scipy.linalg.lu_solve(self.lu, psi)
-        gam = O.deriv(mu)
-        out = O.hilbert(gam) / 2 + self.Gm @ gam
+        ar = self.ar
+        mu = ar.lu_solve(self.lu, psi)
+        gam = O.deriv(mu, ar)
+        out = O.hilbert(gam, ar) / 2 + ar.matmul(self.Gm, gam)
         E = self.mesh.E
         return (out / E[:, None] if out.ndim == 2 else out / E), mu
 
 
-def _dx(f, E):
+def _dx(f, E, ar=O.F64):
     """d/dx = (1/E) d/dalpha."""
-    d = O.deriv(f)
+    d = O.deriv(f, ar)
     return d / E[:, None] if d.ndim == 2 else d / E
 
 
@@ -185,34 +184,34 @@ def _proj_x(f, E):
     return f - np.dot(E, f) / N
 
 
-def rhs_mapped(eta, phi, Qe, Qp, h, tau, g, mesh: Mesh):
+def rhs_mapped(eta, phi, Qe, Qp, h, tau, g, mesh: Mesh, ar=O.F64):
     """F(q) and DF(q) Qdot on the mapped grid (eq. (ww), App. B), filtered (R7, M2)."""
     E = mesh.E
-    dtn = DtNMapped(eta, h, mesh)
-    ex = _dx(eta, E)
-    ps = _dx(phi, E)
+    dtn = DtNMapped(eta, h, mesh, ar)
+    ex = _dx(eta, E, ar)
+    ps = _dx(phi, E, ar)
     Gphi, _ = dtn.apply(phi)
     den = 1 + ex * ex
     u = (ps - ex * Gphi) / den
     v = (ex * ps + Gphi) / den
-    curv = _dx(ex / np.sqrt(den), E)
+    curv = _dx(ex / np.sqrt(den), E, ar)
     phi_t = _proj_x(v * Gphi - u * u / 2 - v * v / 2 - g * eta + tau * curv, E)
-    eta_t = O.filt(Gphi)
-    phi_t = O.filt(phi_t)
+    eta_t = O.filt(Gphi, ar)
+    phi_t = O.filt(phi_t, ar)
     if Qe is None:
         return eta_t, phi_t, None, None
     psid = Qp - v[:, None] * Qe                                    # (l4)
     Gpsid, _ = dtn.apply(psid)
-    Qe_t = Gpsid - _dx(Qe * u[:, None], E)                         # (l5a)
-    dpsid = _dx(psid, E)
+    Qe_t = Gpsid - _dx(Qe * u[:, None], E, ar)                     # (l5a)
+    dpsid = _dx(psid, E, ar)
     w3 = den * np.sqrt(den)
-    tens = _dx(_dx(Qe, E) / w3[:, None], E)
-    Qp_t = _proj_x(-_dx(Qe * (u * v)[:, None], E) - u[:, None] * dpsid
+    tens = _dx(_dx(Qe, E, ar) / w3[:, None], E, ar)
+    Qp_t = _proj_x(-_dx(Qe * (u * v)[:, None], E, ar) - u[:, None] * dpsid
                    + v[:, None] * Gpsid - g * Qe + tau * tens, E)  # (l6), (l6a)
-    return eta_t, phi_t, O.filt(Qe_t), O.filt(Qp_t)
+    return eta_t, phi_t, O.filt(Qe_t, ar), O.filt(Qp_t, ar)
 
 
-def march_mapped(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, mesh: Mesh, tableau=None):
+def march_mapped(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, mesh: Mesh, tableau=None, ar=O.F64):
     """nsteps fixed DOP853 steps of dt = T / (4 nsteps) on one mesh (T here is the
     simulated span times 4, as in oracle.ww_oracle.march)."""
     a, b, c = tableau if tableau is not None else O.dop853_tableau()
@@ -226,12 +225,12 @@ def march_mapped(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, mesh: Mesh, tableau
             for j in range(i):
                 if a[i, j] != 0.0:
                     Y = [Y[q] + a[i, j] * dt * ks[j][q] if Y[q] is not None else None for q in range(4)]
-            ks.append(rhs_mapped(Y[0], Y[1], Y[2], Y[3], h, tau, g, mesh))
+            ks.append(rhs_mapped(Y[0], Y[1], Y[2], Y[3], h, tau, g, mesh, ar))
         yn = list(y)
         for i in range(s):
             if b[i] != 0.0:
                 yn = [yn[q] + b[i] * dt * ks[i][q] if yn[q] is not None else None for q in range(4)]
-        y = [O.filt(v) if v is not None else None for v in yn]
+        y = [O.filt(v, ar) if v is not None else None for v in yn]
     return y
 
 
@@ -263,11 +262,14 @@ def regrid(values, old: Mesh, new: Mesh):
 # the segmented march and its outputs
 # --------------------------------------------------------------------------------
 
-def shoot_eval_segments(N, h, tau, g, basis, q_fixed, params, T, segments, jacobian=True, tableau=None):
+def shoot_eval_segments(N, h, tau, g, basis, q_fixed, params, T, segments, jacobian=True, tableau=None,
+                        ar=O.F64):
     """r, J, dr/dT, f after marching the segments to T/4 (readings M1-M5).
 
     segments: dicts with N (segments[0]["N"] == N), nsteps, theta, rho, refine_at.
-    basis (2N, M) and q_fixed (2N,) are values on the first segment's mesh."""
+    basis (2N, M) and q_fixed (2N,) are values on the first segment's mesh.  `ar`: one of
+    the FP64 backends of ww_oracle (the alternates round the same scheme differently,
+    to measure the rounding floor)."""
     check_segments(segments)
     if segments[0]["N"] != N:
         raise ValueError("the basis lives on the first segment's grid")
@@ -283,10 +285,10 @@ def shoot_eval_segments(N, h, tau, g, basis, q_fixed, params, T, segments, jacob
             if jacobian:
                 Qe, Qp = regrid(Qe, mesh, new), regrid(Qp, mesh, new)
         mesh = new
-        eta, phi, Qe, Qp = march_mapped(eta, phi, Qe, Qp, h, tau, g, seg["theta"] * T, seg["nsteps"], mesh, tableau)
+        eta, phi, Qe, Qp = march_mapped(eta, phi, Qe, Qp, h, tau, g, seg["theta"] * T, seg["nsteps"], mesh, tableau, ar)
     w = np.sqrt(mesh.E / mesh.N)
     r = w * phi
-    _, phi_t, _, _ = rhs_mapped(eta, phi, None, None, h, tau, g, mesh)
+    _, phi_t, _, _ = rhs_mapped(eta, phi, None, None, h, tau, g, mesh, ar)
     return dict(r=r, J=(w[:, None] * Qp) if jacobian else None, drdT=w * phi_t / 4,
                 f=math.fsum(r * r) / 2, eta=eta, phi=phi, mesh=mesh)
 

@@ -5,7 +5,8 @@ cut into launches and streams (LU group size and streams, the lag of the base so
 which parts replay from graphs, the strip length of a block-LU step, rows per
 workgroup of the base DtN launch, the inner-dimension split and the output-tile rows
 of the column products, the assembly strip width, the workgroup cap of the explicit
-inverse, an FP32 copy of the lagged inverse for the base solve's products).  The tuner times
+inverse, an FP32 copy of the lagged inverse for the base solve's products, the
+refinement sweeps of a lagged solve).  The tuner times
 short marches of a workload, one fresh context per candidate, and improves one choice
 at a time (coordinate descent, a few passes); the winner is stored in a JSON cache
 keyed by GPU architecture, N, M and precision form, and `apply` hands it to a context.
@@ -16,6 +17,7 @@ sweeps to converge) is discarded: its time is that of another path.
 Command line (on the GPU):
     python -m paper_1210_5672_amd.autotune c3 [--mixed] [--steps 6] [--cache PATH]
     python -m paper_1210_5672_amd.autotune c5 --batch        (the batched instances)
+    python -m paper_1210_5672_amd.autotune c6                 (time segments, whole march)
 """
 from __future__ import annotations
 
@@ -35,6 +37,7 @@ SPACE = {
     "lu_group": [2, 1, 3, 4],
     "lu_streams": [3, 2, 4],
     "lag": [8, 6, 10],
+    "lag_sweeps": [2, 3, 4],
     "blu_strip": [4, 2, 3, 6, 8],
     "minv_wgs": [1 << 20, 256, 128],
     "dtn_rows": [8, 4, 16],
@@ -45,7 +48,7 @@ SPACE = {
 }
 # choices that matter only to the lagged-factor march (a batch runs each instance's
 # own step graph)
-MARCH_ONLY = ("graph_parts", "lu_group", "lu_streams", "lag", "dtn_rows", "lag_fp32")
+MARCH_ONLY = ("graph_parts", "lu_group", "lu_streams", "lag", "dtn_rows", "lag_fp32", "lag_sweeps")
 
 
 def cache_path(path: str | None = None) -> str:
@@ -57,8 +60,9 @@ def arch_name() -> str:
     return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
-def key(N: int, M: int, mixed: bool, arch: str | None = None, batch: bool = False) -> str:
-    return f"{arch or arch_name()}/N{N}/M{M}/{'mixed' if mixed else 'fp64'}{'/batch' if batch else ''}"
+def key(N: int, M: int, mixed: bool, arch: str | None = None, batch: bool = False, segments: bool = False) -> str:
+    sfx = "/batch" if batch else "/segments" if segments else ""
+    return f"{arch or arch_name()}/N{N}/M{M}/{'mixed' if mixed else 'fp64'}{sfx}"
 
 
 def load(path: str | None = None) -> dict:
@@ -86,14 +90,15 @@ def save(cache: dict, path: str | None = None) -> str:
 
 
 def lookup(N: int, M: int, mixed: bool, path: str | None = None, arch: str | None = None,
-           batch: bool = False) -> dict | None:
-    entry = load(path).get(key(N, M, mixed, arch, batch))
+           batch: bool = False, segments: bool = False) -> dict | None:
+    entry = load(path).get(key(N, M, mixed, arch, batch, segments))
     return dict(entry["tuning"]) if entry else None
 
 
-def apply(ctx, N: int, M: int, path: str | None = None, batch: bool = False) -> dict | None:
-    """Give `ctx` the cached choices for (N, M, its precision form), if any; returns them."""
-    t = lookup(N, M, ctx.mixed, path, batch=batch)
+def apply(ctx, N: int, M: int, path: str | None = None, batch: bool = False, segments: bool = False) -> dict | None:
+    """Give `ctx` the cached choices for (N, M, its precision form), if any; returns them.
+    Segmented marches (shoot_eval_segments) are keyed by their largest N."""
+    t = lookup(N, M, ctx.mixed, path, batch=batch, segments=segments)
     if t:
         ctx.set_tuning(**t)
     return t
@@ -105,11 +110,19 @@ def candidates(cur: dict, name: str) -> list:
 
 def descend(measure, start: dict, names, passes: int = 2, min_gain: float = 0.01, log=print):
     """Coordinate descent: `measure(choices) -> seconds or None` (None: rejected).
-    Returns (best choices, best time, history)."""
+    When the starting choices themselves fall back, their time on the fallback path
+    (`measure(choices, allow_fallback=True)`, the path those choices really take) is the
+    baseline that a candidate must beat.  Returns (best choices, best time, history)."""
     best = dict(start)
     t_best = measure(best)
     if t_best is None:
-        raise RuntimeError("the starting choices fall back")
+        try:
+            t_best = measure(best, allow_fallback=True)
+        except TypeError:
+            t_best = None
+        if t_best is None:
+            raise RuntimeError("the starting choices fall back")
+        log(f"  the starting choices fall back: baseline {t_best * 1e3:.3f} ms on the fallback path")
     hist = [(dict(best), t_best)]
     for _ in range(passes):
         improved = False
@@ -131,23 +144,29 @@ def _march_measure(w, mixed: bool, nsteps: int, reps: int):
     from . import ww
     T = w.T * nsteps / w.nsteps
     basis, qfix, params = ww.to_dev(w.basis), ww.to_dev(w.q_fixed), ww.to_dev(w.params)
+    segs = w.segments
+    nmax = max(q["N"] for q in segs) if segs else w.N
 
-    def measure(choices):
-        ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
+    def march(ctx):
+        # a segmented workload is timed whole (its segments are short)
+        return ctx.shoot_eval_segments(params, w.T, segs) if segs else ctx.shoot_eval(params, T, nsteps)
+
+    def measure(choices, allow_fallback=False):
+        ctx = ww.Context(n_max=nmax, r_max=w.M + 1, mixed=mixed)
         try:
             ctx.set_tuning(**choices)
             ctx.shoot_setup(w.N, w.h, w.tau, w.g, basis, qfix)
-            ctx.shoot_eval(params, T, nsteps)          # captures the graphs
-            if ctx.fallbacks():
+            march(ctx)                                 # captures the graphs
+            if ctx.fallbacks() and not allow_fallback:
                 return None
             ts = []
             for _ in range(reps):
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                ctx.shoot_eval(params, T, nsteps)
+                march(ctx)
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
-                if ctx.fallbacks():
+                if ctx.fallbacks() and not allow_fallback:
                     return None
             return statistics.median(ts)
         finally:
@@ -215,7 +234,7 @@ def store(k: str, best: dict, t: float, note: str, path: str | None = None) -> s
 def main(argv=None):
     from . import workloads as W
     ap = argparse.ArgumentParser(description=__doc__.split("\n\n")[0])
-    ap.add_argument("workload", help="c1..c4, or c5 with --batch")
+    ap.add_argument("workload", help="c1..c4, c6 (time segments), or c5 with --batch")
     ap.add_argument("--mixed", action="store_true")
     ap.add_argument("--batch", action="store_true", help="tune the batched instances (c5)")
     ap.add_argument("--steps", type=int, default=6, help="steps of the timed march prefix")
@@ -235,10 +254,12 @@ def main(argv=None):
         note = f"{len(ws)} batched instances, {a.steps}-step prefixes"
     else:
         w = W.CONFIGS[a.workload]()
-        print(f"tuning {w.name}, {'mixed' if a.mixed else 'fp64'}, {a.steps}-step prefix", flush=True)
+        segs = w.segments
+        print(f"tuning {w.name}, {'mixed' if a.mixed else 'fp64'}, "
+              f"{'whole segmented march' if segs else f'{a.steps}-step prefix'}", flush=True)
         best, t, _ = tune(w, a.mixed, a.steps, a.reps, a.passes)
-        k = key(w.N, w.M, a.mixed)
-        note = f"{w.name}, {a.steps}-step prefix"
+        k = key(max(q["N"] for q in segs) if segs else w.N, w.M, a.mixed, segments=bool(segs))
+        note = f"{w.name}, " + ("whole segmented march" if segs else f"{a.steps}-step prefix")
     p = store(k, best, t, note, a.cache)
     print(json.dumps({"key": k, "tuning": best, "seconds": t, "cache": p}), flush=True)
 

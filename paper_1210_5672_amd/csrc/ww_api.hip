@@ -463,7 +463,7 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     CCHK(hipFuncSetAttribute((const void*)k_gamma, hipFuncAttributeMaxDynamicSharedMemorySize,
                              big - (int)fa.sharedSizeBytes));
   }
-  for (const void* fn : {(const void*)k_base_rhs_map, (const void*)k_col_rhs_map}) {
+  for (const void* fn : {(const void*)k_base_rhs_map, (const void*)k_col_rhs_map, (const void*)k_base_rhs_prep_map}) {
     // static LDS (a reduction buffer) besides the dynamic transform buffers
     hipFuncAttributes fa;
     CCHK(hipFuncGetAttributes(&fa, fn));
@@ -530,6 +530,7 @@ int ww_get_tuning(ww_ctx* c, ww_tuning* t) {
   t->gemm_rows = c->gemm_rows;
   t->lag_fp32 = c->lag32;
   t->asm_cw = c->asm_cw;
+  t->lag_sweeps = c->nref_lag >= 0 ? c->nref_lag : c->nref;
   return 0;
 }
 
@@ -546,6 +547,7 @@ int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
   if (t->asm_cw != 16 && t->asm_cw != 32) return fail(WW_EINVAL, "tuning: asm_cw must be 16 or 32");
   if (t->gemm_rows != 16 && t->gemm_rows != 32) return fail(WW_EINVAL, "tuning: gemm_rows must be 16 or 32");
   if (t->lag_fp32 != 0 && t->lag_fp32 != 1) return fail(WW_EINVAL, "tuning: lag_fp32 must be 0 or 1");
+  if (t->lag_sweeps < 1 || t->lag_sweeps > 8) return fail(WW_EINVAL, "tuning: lag_sweeps out of range");
   c->lag = t->lag;
   c->lu_group = t->lu_group;
   c->nlus = t->lu_streams;
@@ -557,6 +559,7 @@ int ww_set_tuning(ww_ctx* c, const ww_tuning* t) {
   c->gemm_rows = t->gemm_rows;
   c->lag32 = t->lag_fp32;
   c->asm_cw = t->asm_cw;
+  c->nref_lag = t->lag_sweeps;
   ++c->tune_gen;
   return 0;
 }
@@ -761,18 +764,17 @@ static Fac fac_default(ww_ctx* c) { return fac_set(c, 0, false); }
 static int enqueue_assemble(ww_ctx* c, const Fac& F, bool want_ar, const Fac* Fo = nullptr,
                             const double* psi = nullptr, double* x0 = nullptr) {
   const int nb = c->Np / WW_TB;
-  if (c->mapped) {
-    if (Fo) return fail(WW_EHIP, "internal: lagged solve on the mapped grid");
-    hipLaunchKernelGGL(k_assemble_map, dim3(nb, c->Np / 16), dim3(WW_NT), 0, c->stream, F.aux, c->mesh, c->n_max,
-                       c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr, (F.use32 || want_ar) ? F.Ar : nullptr,
-                       c->N, c->Np, c->finite);
-    LAUNCHCHK();
-    return 0;
-  }
   const bool f32 = Fo && (Fo->use32 || Fo->lag32);
   const double* mx64 = (Fo && !f32) ? Fo->Mi : nullptr;
   const float* mx32 = f32 ? Fo->Mi32 : nullptr;
   if (Fo && !(mx64 || mx32)) return fail(WW_EHIP, "internal: lagged first solve without its inverse");
+  if (c->mapped) {
+    hipLaunchKernelGGL(k_assemble_map, dim3(nb, c->Np / 16 + (Fo ? 16 : 0)), dim3(WW_NT), 0, c->stream, F.aux,
+                       c->mesh, c->n_max, c->c0T, F.A, F.Gm, F.use32 ? F.A32 : nullptr, F.Gmr,
+                       (F.use32 || want_ar) ? F.Ar : nullptr, c->N, c->Np, c->finite, mx64, mx32, psi, x0);
+    LAUNCHCHK();
+    return 0;
+  }
   const int cw = c->asm_cw == 32 ? 32 : 16;
   const int gy = c->Np / cw + (Fo ? 16 : 0);
   hipLaunchKernelGGL(cw == 32 ? k_assemble<32> : k_assemble<16>, dim3(nb, gy), dim3(WW_NT), 0, c->stream, F.aux,
@@ -1026,7 +1028,8 @@ static int enqueue_base_chain(ww_ctx* c, const double* ysrc, int s, double* kout
   }
   if (c->mapped)
     hipLaunchKernelGGL(k_base_rhs_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0,
-                       F.aux, c->mesh, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+                       F.aux, c->mesh, c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw,
+                       c->sig, c->N, c->g, c->tau);
   else
     hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0, F.aux,
                        c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
@@ -1065,7 +1068,7 @@ static int enqueue_col_chain(ww_ctx* c, int s, const Fac& F) {
 // uses the exact factors of its stage.
 static bool pipelined(const ww_ctx* c, bool cols, bool two_streams) {
   (void)cols;   // with or without Jacobian columns (c->pcols)
-  return c->lag > 0 && two_streams && c->fb == 0 && c->nst > c->lag && !c->gm_active && !c->mapped;
+  return c->lag > 0 && two_streams && c->fb == 0 && c->nst > c->lag && !c->gm_active;
 }
 
 // a march without columns keeps to two LU streams: they carry its LUs, and a third
@@ -1198,7 +1201,17 @@ static int enqueue_pipe_part(ww_ctx* c, int s, int part) {
                        dim3((c->Np + c->dtn_rows - 1) / c->dtn_rows), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream,
                        c->mu0, c->rhs0, F.Gmr, F.Ar, c->Np, c->tw, c->N, c->gphi0, chk, c->dtn_rows);
     LAUNCHCHK();
-    if (s + 1 < nst) {
+    if (s + 1 < nst && c->mapped) {
+      const Fac Fn = pipe_set(c, s + 1, false);
+      hipLaunchKernelGGL(k_base_rhs_prep_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->gphi0,
+                         F.aux, c->K + (size_t)s * kstride(c), chk, REFINE_TOL, c->sig, c->g, c->tau, c->y, c->K,
+                         c->Ys, c->coef, s + 1, kstride(c), Fn.aux, c->rhs0, c->Np, c->hsurf, c->n_max, c->tw, c->N,
+                         c->status, c->mesh);
+    } else if (c->mapped) {
+      hipLaunchKernelGGL(k_base_rhs_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->gphi0,
+                         F.aux, c->mesh, c->n_max, c->K + (size_t)s * kstride(c), chk, REFINE_TOL, c->status, c->tw,
+                         c->sig, c->N, c->g, c->tau);
+    } else if (s + 1 < nst) {
       // this stage's right-hand side and the next stage's prep in one launch
       const Fac Fn = pipe_set(c, s + 1, false);
       hipLaunchKernelGGL(k_base_rhs_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->gphi0, F.aux,
@@ -1250,8 +1263,8 @@ static int capture_part(ww_ctx* c, int s, int part, hipGraphExec_t* out) {
 }
 
 static long long pipe_key(const ww_ctx* c) {
-  return (((((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 16 + c->lag) * 8 + lu_group(c)) * 2 + (c->prof ? 1 : 0)) *
-              16 + c->fb) * 1024 + (c->tune_gen & 1023);
+  return ((((((((long long)c->N * 4096 + c->M) * 32 + c->nst) * 16 + c->lag) * 8 + lu_group(c)) * 2 + (c->prof ? 1 : 0)) *
+              16 + c->fb) * 1024 + (c->tune_gen & 1023)) * 2 + (c->mapped ? 1 : 0);
 }
 
 static int ensure_pipe_graphs(ww_ctx* c) {
@@ -1907,9 +1920,20 @@ static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww
   for (int l = 0; l < nseg; ++l) {
     const double Tl = sg[l].theta * T;
     const double Al = mesh_coef(sg[l].rho);
+    // this segment's mesh tables, before anything of the segment is enqueued (the
+    // lagged march's prologue assembles the segment's first surface)
+    auto tables = [&]() -> int {
+      hipLaunchKernelGGL(k_mesh_tables, dim3((sg[l].N + 255) / 256), dim3(256), 0, c->stream, c->mesh, c->n_max,
+                         sg[l].N, Al, sg[l].refine_at);
+      LAUNCHCHK();
+      return 0;
+    };
     if (l == 0) {
+      if ((rc = pipe_join(c))) return rc;   // a previous march's streams
+      if ((rc = tables())) return rc;
       if ((rc = shoot_prepare(c, params, Tl, sg[0].nsteps, cols, two))) return rc;
     } else {
+      if ((rc = pipe_join(c))) return rc;   // the lagged march's LU and column streams
       const int No = c->N, Nn = sg[l].N;
       const int ncols = 2 * (cols ? c->M + 1 : 1);
       // interpolation weights (row-major Nn x No, in the A buffer of the default factor
@@ -1926,16 +1950,23 @@ static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww
       coef_fill(c, Tl, sg[l].nsteps, coef);
       HIPCHK(hipStreamSynchronize(c->stream));
       HIPCHK(hipMemcpy(c->coef, coef, sizeof(coef), hipMemcpyHostToDevice));
-      if (graphed(c) && (rc = ensure_step_graph(c, cols, two))) return rc;
+      if ((rc = tables())) return rc;
+      if (pipelined(c, cols, two)) {
+        // lagged factors restart on the new mesh: the prologue factors the segment's
+        // first surface into the sets its first stages read
+        if ((rc = ensure_pipe(c))) return rc;
+        if ((rc = pipe_prologue(c))) return rc;
+        if (graphed(c) && (rc = ensure_pipe_graphs(c))) return rc;
+      } else if (graphed(c) && (rc = ensure_step_graph(c, cols, two))) {
+        return rc;
+      }
     }
-    hipLaunchKernelGGL(k_mesh_tables, dim3((sg[l].N + 255) / 256), dim3(256), 0, c->stream, c->mesh, c->n_max,
-                       sg[l].N, Al, sg[l].refine_at);
-    LAUNCHCHK();
     for (int n = 0; n < sg[l].nsteps; ++n)
       if ((rc = shoot_one_step(c, cols, two))) return rc;
   }
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
     const std::string msg = g_err;
+    (void)pipe_join(c);
     (void)hipStreamSynchronize(c->stream);
     g_err = msg;
     return rc;
@@ -1964,11 +1995,12 @@ int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, con
     explicit Mapped(ww_ctx* cc) : c(cc) { c->mapped = true; }
     ~Mapped() { c->mapped = false; }
   } mapped_scope(c);
-  c->fb = 0;
+  c->fb = c->lag_off ? WW_FB_DIRECT : 0;
   for (;;) {
     int st = 0, where = 0;
     if ((rc = seg_run(c, params, T, nseg, segs, r, J, drdT, f, &st, &where))) return rc;
     const unsigned nf = next_fallback(c, st);
+    if ((st & 32) && !strict(c)) c->lag_off = true;
     if (!nf) {
       if ((rc = status_error(c, st, where))) return rc;
       c->fb_last = c->fb;

@@ -58,13 +58,28 @@ __global__ void k_mesh_tables(double* __restrict__ mesh, int nmax, int N, double
 // The regularising cot((alpha_i - alpha_j)/2)/2 stays on the uniform alpha grid (the
 // circulant table).  cos x_ij and sin x_ij are evaluated per entry.  One strip of 64
 // rows x 16 columns per workgroup (grid Np/64 x Np/16); writes what k_assemble writes.
+// With a lagged inverse (Mx64 or Mx32, row-major) 16 more rows of workgroups form
+// x0 = Mx psi, the first solve of the lagged-factor base chain, one wave per row.
 // -------------------------------------------------------------------------------------
 __global__ __launch_bounds__(WW_NT) void k_assemble_map(const double* __restrict__ aux, const double* __restrict__ mesh,
                                                         int nmax, const double* __restrict__ c0T,
                                                         double* __restrict__ A, double* __restrict__ Gm,
                                                         float* __restrict__ A32, double* __restrict__ Gmr,
-                                                        double* __restrict__ Ar, int N, int Np, int finite) {
+                                                        double* __restrict__ Ar, int N, int Np, int finite,
+                                                        const double* __restrict__ Mx64, const float* __restrict__ Mx32,
+                                                        const double* __restrict__ psi, double* __restrict__ x0) {
   constexpr int CW = 16;
+  if (blockIdx.y >= (unsigned)(Np / CW)) {
+    // (uniform per workgroup: no barrier below is reached by these blocks)
+    const int g = (blockIdx.y - Np / CW) * gridDim.x + blockIdx.x;
+    const int row = g * (WW_NT / 64) + (threadIdx.x >> 6);
+    if (row >= Np) return;
+    if (Mx32)
+      gemv_row_wave<float>(Mx32, Np, 0, psi, nullptr, 1.0, x0, row, threadIdx.x & 63);
+    else if (Mx64)
+      gemv_row_wave<double>(Mx64, Np, 0, psi, nullptr, 1.0, x0, row, threadIdx.x & 63);
+    return;
+  }
   __shared__ double rt[WW_TB][CW + 1];
   __shared__ double rq[7][WW_TB];   // eta', eta'', exp(s), exp(-s), xi, E, E' of the rows
   __shared__ double cq[5][CW];      // eta', exp(s), exp(-s), xi, E of the columns
@@ -179,19 +194,13 @@ __device__ inline double block_sum_fixed(double v, double* red) {
 // filtered in alpha.  Gphi holds H gamma/2 + Gm gamma (without the 1/E).
 // Dynamic LDS: 4 N complex.
 // -------------------------------------------------------------------------------------
-__global__ __launch_bounds__(WW_NT) void k_base_rhs_map(const double* __restrict__ Ys, const double* __restrict__ Gphi,
-                                                        double* __restrict__ aux, const double* __restrict__ mesh,
-                                                        int nmax, double* __restrict__ Kout,
-                                                        const cplx* __restrict__ tw, const double* __restrict__ sig,
-                                                        int N, double g, double tau) {
-  extern __shared__ cplx lds[];
-  __shared__ double red[WW_NT / 64];
-  cplx* Z = lds;
-  cplx* W = lds + N;
-  cplx* tws = lds + 3 * N;
-  const FftPlan P = make_plan(N);
+// The right-hand side of one stage on LDS work buffers Z, W and the twiddles tws.
+__device__ inline void base_rhs_map_stage(cplx* Z, cplx* W, const cplx* tws, const FftPlan& P, double* red,
+                                          const double* __restrict__ Ys, const double* __restrict__ Gphi,
+                                          double* __restrict__ aux, const double* __restrict__ mesh, int nmax,
+                                          double* __restrict__ Kout, const double* __restrict__ sig, int N, double g,
+                                          double tau) {
   const int tid = threadIdx.x;
-  load_twiddles(tws, tw, N);
   double Gv[NPT], pre[NPT], iv[NPT];
   {
     double exv[NPT], psv[NPT], etv[NPT];
@@ -245,6 +254,44 @@ __global__ __launch_bounds__(WW_NT) void k_base_rhs_map(const double* __restrict
     Kout[t] = Z[t].x;
     Kout[N + t] = Z[t].y;
   }
+}
+
+// chk (optional): the two maxima of a lagged-factor solve's test (see k_base_dtn)
+__global__ __launch_bounds__(WW_NT) void k_base_rhs_map(const double* __restrict__ Ys, const double* __restrict__ Gphi,
+                                                        double* __restrict__ aux, const double* __restrict__ mesh,
+                                                        int nmax, double* __restrict__ Kout,
+                                                        unsigned long long* __restrict__ chk, double chk_tol,
+                                                        int* __restrict__ status, const cplx* __restrict__ tw,
+                                                        const double* __restrict__ sig, int N, double g, double tau) {
+  extern __shared__ cplx lds[];
+  __shared__ double red[WW_NT / 64];
+  const FftPlan P = make_plan(N);
+  lagged_check(chk, chk_tol, status, 32);
+  load_twiddles(lds + 3 * N, tw, N);
+  base_rhs_map_stage(lds, lds + N, lds + 3 * N, P, red, Ys, Gphi, aux, mesh, nmax, Kout, sig, N, g, tau);
+}
+
+// The right-hand side of stage s and the prep of stage s + 1 in one launch (the mapped
+// counterpart of k_base_rhs_prep).
+__global__ __launch_bounds__(WW_NT) void k_base_rhs_prep_map(
+    const double* __restrict__ Gphi, double* __restrict__ aux_cur, double* __restrict__ Kcur,
+    unsigned long long* __restrict__ chk, double chk_tol, const double* __restrict__ sig, double g, double tau,
+    const double* __restrict__ y, const double* __restrict__ K, double* __restrict__ Ys,
+    const double* __restrict__ coef, int stage_next, size_t kstride, double* __restrict__ aux_next,
+    double* __restrict__ rhs0, int Np, double hsurf, int nmax, const cplx* __restrict__ tw, int N,
+    int* __restrict__ status, const double* __restrict__ mesh) {
+  extern __shared__ cplx lds[];
+  __shared__ double red[WW_NT / 64];
+  cplx* Z = lds;
+  cplx* W = lds + N;
+  cplx* S = lds + 2 * N;
+  cplx* tws = lds + 3 * N;
+  const FftPlan P = make_plan(N);
+  lagged_check(chk, chk_tol, status, 32);
+  load_twiddles(tws, tw, N);
+  base_rhs_map_stage(Z, W, tws, P, red, Ys, Gphi, aux_cur, mesh, nmax, Kcur, sig, N, g, tau);
+  __syncthreads();   // K_s (global) and the LDS buffers are complete
+  base_prep_stage(Z, W, S, tws, P, y, K, Ys, coef, stage_next, kstride, aux_next, nmax, rhs0, Np, N, hsurf, status);
 }
 
 // -------------------------------------------------------------------------------------

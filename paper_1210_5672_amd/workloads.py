@@ -45,6 +45,9 @@ class Workload:
     q_fixed: np.ndarray = field(repr=False)  # (2N,)
     ckpt_every: int = 16
     description: str = ""
+    # time segments on non-uniform meshes (dicts with N, nsteps, theta, rho, refine_at;
+    # the first N is the basis grid), or None for one uniform segment
+    segments: list | None = field(default=None, repr=False)
 
     @property
     def R(self) -> int:
@@ -127,6 +130,22 @@ def c4() -> Workload:
                                 "800 steps, adjoint with checkpoints every 16 steps")
 
 
+def c6() -> Workload:
+    """Two time segments on non-uniform meshes, sized like the double-precision mesh
+    parameters of Table tab:param:OA (solution A there: theta = (0.2, 0.8), rho = (1.0,
+    0.4), 768 then 1024 grid points, 24 then 144 steps, 200 parameters); the mesh of the
+    second segment is finest near x = pi.  Infinite depth, a1 = 0.15 with the seeded modes
+    2..16, T = 2 pi."""
+    rng = np.random.default_rng(1210 + 6)
+    N, M = 768, 200
+    segs = [dict(N=768, nsteps=24, theta=0.2, rho=1.0, refine_at=0),
+            dict(N=1024, nsteps=144, theta=0.8, rho=0.4, refine_at=0)]
+    return Workload("c6_inf_N768-1024_M200_segments", N, INF, 0.0, 1.0, M, 2.0 * math.pi, 168,
+                    _modes(rng, 0.15, M), cosine_basis(N, M), np.zeros(2 * N), segments=segs,
+                    description="two segments (theta 0.2, 0.8; rho 1.0, 0.4; N 768, 1024; 24 + 144 "
+                                "steps), infinite depth, a1=0.15, M=200")
+
+
 C5_SIZES = (256, 384, 512, 768, 1024, 1536, 2048)
 
 
@@ -163,7 +182,7 @@ def c5(n_inst: int = 32, seed: int = 1210 + 5, nsteps_cap: int | None = None) ->
     return out
 
 
-CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4}
+CONFIGS = {"c1": c1, "c2": c2, "c3": c3, "c4": c4, "c6": c6}
 
 
 def initial_state(w: Workload) -> tuple[np.ndarray, np.ndarray]:

@@ -54,7 +54,8 @@ BFGS_REASONS = {1: "f_tol", 2: "g_tol", 3: "c unchanged", 4: "line search", 5: "
 class Tuning(ctypes.Structure):
     """Launch and scheduling choices of a context (ww_tuning)."""
     _fields_ = [(n, ctypes.c_int) for n in ("lag", "lu_group", "lu_streams", "graph_parts", "minv_wgs",
-                                             "blu_strip", "dtn_rows", "gemm_split", "asm_cw", "gemm_rows", "lag_fp32")]
+                                             "blu_strip", "dtn_rows", "gemm_split", "asm_cw", "gemm_rows", "lag_fp32",
+                                             "lag_sweeps")]
 
     def as_dict(self):
         return {n: getattr(self, n) for n, _ in self._fields_}

@@ -29,7 +29,8 @@ raw result yet, in parallel processes, one thread each, then combines.  The full
 
 Workloads: c1, c2, c3, c4; c5_IIxS, the first S steps of batched instance II (the
 largest grids); c5_II, batched instance II marched to T/4 (instances whose oracle
-run is affordable).
+run is affordable); c6, the two time segments on non-uniform meshes (the mesh oracle,
+oracle/mesh_oracle.py, with the same FP64 alternates).
 """
 import os
 import subprocess
@@ -43,6 +44,7 @@ ROOT = os.path.dirname(os.path.dirname(HERE))
 RAW = os.path.join(HERE, "raw")
 sys.path.insert(0, ROOT)
 
+from oracle import mesh_oracle as MO              # noqa: E402
 from oracle import ww_oracle as O                 # noqa: E402
 from paper_1210_5672_amd import workloads as W   # noqa: E402
 
@@ -57,7 +59,7 @@ C5_FULL = {"c5_00": 0, "c5_07": 7, "c5_08": 8, "c5_26": 26, "c5_27": 27}
 
 # workloads with a double-double run, and the column split of that run
 DD_SPLIT = {"c1": 1, "c2": 4}
-ALL = ("c1", "c2", "c4", "c3", *C5_FULL, *C5_PREFIX)
+ALL = ("c1", "c2", "c4", "c3", *C5_FULL, *C5_PREFIX, "c6")
 
 
 def workload(name):
@@ -90,7 +92,11 @@ def run(name, tag, cols=None):
     w = workload(name)
     ar = arith(tag)
     t0 = time.time()
-    if cols is None:
+    if w.segments is not None:
+        if cols is not None:
+            raise SystemExit("column splits are for uniform-mesh workloads")
+        res = MO.shoot_eval_segments(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.segments, ar=ar)
+    elif cols is None:
         res = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps, ar=ar)
     else:
         # columns a..b-1 only: the initial state of all parameters, formed in the run's

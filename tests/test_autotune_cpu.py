@@ -11,6 +11,7 @@ def test_cache_roundtrip_and_lookup(tmp_path):
     k = A.key(1024, 128, False, arch="gfx950")
     assert k == "gfx950/N1024/M128/fp64"
     assert A.key(512, 40, True, arch="gfx950", batch=True) == "gfx950/N512/M40/mixed/batch"
+    assert A.key(1024, 200, False, arch="gfx950", segments=True) == "gfx950/N1024/M200/fp64/segments"
     t = {"lag": 8, "lu_group": 2, "lu_streams": 3, "graph_parts": 10, "minv_wgs": 256, "blu_strip": 4,
          "dtn_rows": 8, "gemm_split": 4, "asm_cw": 16, "gemm_rows": 32, "lag_fp32": 0}
     A.store(k, t, 0.0123, "test", p)
@@ -51,6 +52,7 @@ def test_defaults_of_the_library_are_candidates():
     is never worse than no tuning at all (the descent starts from the defaults)."""
     defaults = {"lag": 8, "lu_group": 2, "lu_streams": 3, "graph_parts": 10, "minv_wgs": 1 << 20,
                 "blu_strip": 4, "dtn_rows": 8, "gemm_split": 4, "asm_cw": 16,
-                 "gemm_rows": 32, "lag_fp32": 0}
+                 "gemm_rows": 32, "lag_fp32": 0, "lag_sweeps": 2}
+    assert set(defaults) == set(A.SPACE)
     for n, v in defaults.items():
         assert A.SPACE[n][0] == v, n

@@ -187,6 +187,30 @@ def test_config3_full_mixed_precision():
     assert fb == 0, fb
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_segments_on_non_uniform_meshes(mixed):
+    """C6: two time segments (N 768 uniform, then N 1024 on the mesh with rho = 0.4
+    refined near x = pi; 24 + 144 steps; 200 parameters) through shoot_eval_segments,
+    against the mesh oracle's stored run, with the same bounds (the floor from the same
+    four alternate roundings of the mapped-grid scheme)."""
+    import dataclasses
+
+    import torch
+    fx = _load("c6")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    print(f"full-size parity c6 (segments) mixed={mixed}", flush=True)
+    w = W.c6()
+    ctx = ww.Context(n_max=max(q["N"] for q in w.segments), r_max=w.M + 1, mixed=mixed)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    res = _np(ctx.shoot_eval_segments(ww.to_dev(w.params), w.T, w.segments))
+    assert ctx.fallbacks() == 0
+    # the outputs live on the last segment's grid
+    check(fx, dataclasses.replace(w, N=w.segments[-1]["N"]), res)
+    ctx.close()
+
+
 def _batch(names, mixed=False):
     import torch
     if not torch.cuda.is_available():

@@ -17,7 +17,7 @@ ALTERNATIVES = [
     {"blu_strip": 2}, {"blu_strip": 8}, {"dtn_rows": 16}, {"dtn_rows": 4}, {"gemm_split": 2},
     {"asm_cw": 32}, {"gemm_rows": 16}, {"gemm_rows": 16, "gemm_split": 2}, {"lu_group": 1},
     {"lu_group": 3, "lu_streams": 2}, {"graph_parts": 0}, {"graph_parts": 15}, {"lag": 6}, {"minv_wgs": 64},
-    {"lag_fp32": 1}, {"lag_fp32": 1, "lag": 6, "graph_parts": 0},
+    {"lag_fp32": 1}, {"lag_fp32": 1, "lag": 6, "graph_parts": 0}, {"lag_sweeps": 3},
     {"blu_strip": 3, "gemm_split": 2, "asm_cw": 32, "dtn_rows": 4, "graph_parts": 0},
 ]
 
@@ -35,10 +35,10 @@ def test_tuning_defaults_and_validation():
     t = ctx.tuning()
     assert t == {"lag": 8, "lu_group": 2, "lu_streams": 3, "graph_parts": 10, "minv_wgs": 1 << 20,
                  "blu_strip": 4, "dtn_rows": 8, "gemm_split": 4, "asm_cw": 16,
-                 "gemm_rows": 32, "lag_fp32": 0}, t
+                 "gemm_rows": 32, "lag_fp32": 0, "lag_sweeps": 2}, t
     for bad in ({"lag": 12}, {"lu_group": 0}, {"lu_streams": 7}, {"graph_parts": 16}, {"minv_wgs": 0},
                 {"blu_strip": 17}, {"dtn_rows": 6}, {"dtn_rows": 36}, {"gemm_split": 3}, {"asm_cw": 24},
-                {"gemm_rows": 8}, {"lag_fp32": 2}):
+                {"gemm_rows": 8}, {"lag_fp32": 2}, {"lag_sweeps": 0}, {"lag_sweeps": 9}):
         with pytest.raises(ww.WWError) as e:
             ctx.set_tuning(**bad)
         assert e.value.name == "WW_EINVAL", bad
