@@ -202,6 +202,36 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
                double *drdT, double *f);
 
 /*
+ * Double-double DtN (the GPU part of the quadruple-precision workflow: Sec. 2.2 on
+ * quadruple precision, Sec. 3.3; residuals in extended precision by matrix products,
+ * corrections from double-precision factors).  Values are unevaluated sums hi + lo of two
+ * doubles (about 32 digits); every array is passed as a hi plane and a lo plane.
+ * dtn_setup_dd: the surface eta = surface_hi + surface_lo (device, N each; surface_lo
+ * may be NULL for zero) at depth h (as dtn_setup; h is a double): eta', eta'' by
+ * double-double FFTs, exp(+-height) in double-double, A = I/2 + K/N and Gm = G/N of
+ * eq. (fred), (G), (K1K2) assembled in double-double from double-double circulant
+ * tables, and the FP64 factors (block LU and explicit inverse) of the leading part of A.
+ * N must be a power of two, 16 <= N <= min(n_max, 1024).  The FP64 factors of an earlier
+ * dtn_setup are replaced (dtn_solve_multi then needs a new dtn_setup).  Synchronises.
+ * Errors: WW_EINVAL, WW_EDOMAIN (finite depth, h + eta <= 0), WW_ENONFINITE, WW_EPIVOT
+ * (a pivot below the guard: there is no pivoted double-double form), WW_EHIP.
+ */
+int dtn_setup_dd(ww_ctx *ctx, const double *surface_hi, const double *surface_lo, double h, int N);
+
+/*
+ * dtn_solve_multi_dd: G psi for nrhs columns (rhs_hi/rhs_lo: N x nrhs column-major,
+ * device; rhs_lo may be NULL) in double-double: mu = A^{-1} psi from the FP64 inverse,
+ * then three refinement sweeps r = psi - A mu (double-double products), mu += A_hi^{-1} r;
+ * gamma = mu' and H gamma / 2 by double-double FFTs; G psi = H gamma / 2 + Gm gamma.
+ * out_hi/out_lo (N x nrhs, caller-owned), and mu_hi/mu_lo (both or neither). The call
+ * synchronises and checks the final residual: max |r| <= 2^-96 max |psi|, else
+ * WW_EREFINE.  Errors: WW_EINVAL (null, nrhs out of 1..r_max), WW_ENOSETUP, WW_EREFINE,
+ * WW_EHIP.
+ */
+int dtn_solve_multi_dd(ww_ctx *ctx, const double *rhs_hi, const double *rhs_lo, int nrhs, double *out_hi,
+                       double *out_lo, double *mu_hi, double *mu_lo);
+
+/*
  * Time segments on non-uniform meshes (Sec. 2.2 eq. (xi), (rho:def)).  The march to T/4
  * is split into segments l = 0..nseg-1 of theta_l T / 4 each (the theta_l sum to 1),
  * segment l with its own grid of N_l points and nsteps_l steps of theta_l T / (4

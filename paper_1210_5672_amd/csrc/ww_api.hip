@@ -13,6 +13,7 @@
 #include "ww.h"
 #include "ww_kernels.hpp"
 #include "ww_mesh.hpp"
+#include "ww_dd.hpp"
 #include "ww_svd.hpp"
 #include "ww_gmres.hpp"
 
@@ -115,6 +116,17 @@ struct ww_ctx {
   // the per-point tables of the current segment (MESH_COUNT x n_max doubles)
   bool mapped = false;
   double* mesh = nullptr;
+  // double-double DtN (dtn_setup_dd, dtn_solve_multi_dd), allocated at first use:
+  // circulant tables (cos, sin of 2 pi d/N, cot(pi d/N)/2; 3 planes of n_max) and FFT
+  // twiddles for grid dd_N, per-point surface quantities (4 planes), A and Gm (Np x Np,
+  // hi and lo planes), and the solve's work planes (DD_WORK planes of np_max x r_max)
+  int dd_N = 0;
+  bool dd_ready = false;
+  double *dd_tab_hi = nullptr, *dd_tab_lo = nullptr;
+  cdd* dd_tw = nullptr;
+  double *dd_pt_hi = nullptr, *dd_pt_lo = nullptr;
+  double *dd_Ah = nullptr, *dd_Al = nullptr, *dd_Gh = nullptr, *dd_Gl = nullptr;
+  double* dd_w = nullptr;
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -470,6 +482,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     CCHK(hipFuncSetAttribute(fn, hipFuncAttributeMaxDynamicSharedMemorySize, big - (int)fa.sharedSizeBytes));
   }
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_dd_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_dd_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_dtn<16>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_dtn<WW_NMAX / 64>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -1606,6 +1620,207 @@ int dtn_solve_multi_noalloc(ww_ctx* c, const double* rhs, int nrhs, double* dtn_
   double* s = c->scratch;
   const SolveWork w{s, s + blk, s + 2 * blk, s + 3 * blk, s + 4 * blk, s + 5 * blk, s + 6 * blk};
   return dtn_solve_impl(c, rhs, nrhs, dtn_out, mu_out, w);
+}
+
+}  // extern "C"
+
+// ----- double-double DtN -----
+// sin and cos of 2 pi d / n in double-double (host, for the tables): the angle is
+// reduced exactly to [0, pi/4] with integer arithmetic (quadrant, then the complement),
+// and both Taylor series are summed until a term falls below 1e-34.
+static void dd_sincos_2pi(long d, long n, dd* s_out, dd* c_out) {
+  d %= n;
+  if (d < 0) d += n;
+  const long q = (4 * d) / n;               // quadrant
+  const long r4 = 4 * d - q * n;            // 4 d - q n in [0, n): angle 2 pi r4 / (4 n)
+  const bool comp = 2 * r4 > n;             // beyond pi/4: use the complement
+  const long num = comp ? n - r4 : r4;      // angle 2 pi num / (4 n) = pi num / (2 n)
+  const dd pi = dd{DD_PI_HI, DD_PI_LO};
+  const dd x = dd_div_d(dd_mul_d(pi, (double)num), 2.0 * (double)n);
+  const dd x2 = dd_mul(x, x);
+  dd sn = x, term = x;
+  for (int k = 1; k < 40; ++k) {
+    term = dd_div_d(dd_mul(term, x2), -(double)((2 * k) * (2 * k + 1)));
+    sn = dd_add(sn, term);
+    if (std::fabs(term.hi) < 1e-34) break;
+  }
+  dd cs = dd_of(1.0);
+  term = dd_of(1.0);
+  for (int k = 1; k < 40; ++k) {
+    term = dd_div_d(dd_mul(term, x2), -(double)((2 * k - 1) * (2 * k)));
+    cs = dd_add(cs, term);
+    if (std::fabs(term.hi) < 1e-34) break;
+  }
+  if (comp) std::swap(sn, cs);
+  dd so, co;
+  switch (q) {
+    case 0: so = sn; co = cs; break;
+    case 1: so = cs; co = dd_neg(sn); break;
+    case 2: so = dd_neg(sn); co = dd_neg(cs); break;
+    default: so = dd_neg(cs); co = sn; break;
+  }
+  *s_out = so;
+  *c_out = co;
+}
+
+#define DD_WORK 13
+#define DD_SWEEPS 3
+static const double DD_TOL = 1.2621774483536189e-29;   // 2^-96
+static int ensure_dd(ww_ctx* c) {
+  if (c->dd_w) return 0;
+  int rc;
+  const size_t nm = c->n_max, np = c->np_max;
+  double** planes[] = {&c->dd_tab_hi, &c->dd_tab_lo};
+  for (double** q : planes)
+    if ((rc = dalloc(c, (void**)q, 3 * nm * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->dd_tw, nm / 2 * sizeof(cdd)))) return rc;
+  if ((rc = dalloc(c, (void**)&c->dd_pt_hi, 4 * nm * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->dd_pt_lo, 4 * nm * 8))) return rc;
+  double** mats[] = {&c->dd_Ah, &c->dd_Al, &c->dd_Gh, &c->dd_Gl};
+  for (double** q : mats)
+    if ((rc = dalloc(c, (void**)q, np * np * 8))) return rc;
+  return dalloc(c, (void**)&c->dd_w, (size_t)DD_WORK * np * c->r_max * 8);
+}
+
+static int dd_tables(ww_ctx* c, int N) {
+  if (c->dd_N == N) return 0;
+  HIPCHK(hipStreamSynchronize(c->stream));   // queued work may still read the old tables
+  std::vector<double> th(3 * N), tl(3 * N);
+  std::vector<cdd> tw(N / 2);
+  for (int d = 0; d < N; ++d) {
+    dd sn, cs;
+    dd_sincos_2pi(d, N, &sn, &cs);
+    th[d] = cs.hi;
+    tl[d] = cs.lo;
+    th[N + d] = sn.hi;
+    tl[N + d] = sn.lo;
+    if (d < N / 2) tw[d] = cdd{cs, dd_neg(sn)};
+    dd c0 = dd_of(0.0);
+    if (d > 0) {   // cot(pi d / N) / 2 = cos / (2 sin) of 2 pi d / (2 N)
+      dd sh, ch;
+      dd_sincos_2pi(d, 2L * N, &sh, &ch);
+      c0 = dd_div(ch, dd_mul_d(sh, 2.0));
+    }
+    th[2 * N + d] = c0.hi;
+    tl[2 * N + d] = c0.lo;
+  }
+  HIPCHK(hipMemcpy(c->dd_tab_hi, th.data(), 3 * N * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->dd_tab_lo, tl.data(), 3 * N * 8, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->dd_tw, tw.data(), (N / 2) * sizeof(cdd), hipMemcpyHostToDevice));
+  c->dd_N = N;
+  return 0;
+}
+
+static size_t dd_lds_bytes(int N) { return (size_t)(3 * N + N / 2) * sizeof(cdd); }
+
+extern "C" {
+
+int dtn_setup_dd(ww_ctx* c, const double* surface_hi, const double* surface_lo, double h, int N) {
+  if (!c || !surface_hi) return fail(WW_EINVAL, "null argument");
+  c->dd_ready = false;
+  c->dtn_ready = false;   // the FP64 factor buffers are reused
+  if (N < 16 || (N & (N - 1)) || N > c->n_max || N > 1024)
+    return fail(WW_EINVAL, "double-double DtN: N must be a power of two, 16 <= N <= min(n_max, 1024)");
+  int rc;
+  if ((rc = set_grid(c, N, h))) return rc;
+  if ((rc = check_domain(c, surface_hi))) return rc;
+  if ((rc = ensure_dd(c))) return rc;
+  if ((rc = dd_tables(c, N))) return rc;
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dd_prep, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, surface_hi, surface_lo, c->hsurf,
+                     c->dd_tw, N, c->n_max, c->dd_pt_hi, c->dd_pt_lo);
+  LAUNCHCHK();
+  const int Np = c->Np;
+  hipLaunchKernelGGL(k_dd_assemble, dim3(Np / WW_TB, Np / 16), dim3(WW_NT), 0, c->stream, c->dd_pt_hi, c->dd_pt_lo,
+                     c->n_max, c->dd_tab_hi, c->dd_tab_lo, N, Np, c->finite, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl,
+                     c->A);
+  LAUNCHCHK();
+  // FP64 factors (block LU and explicit inverse) of the leading part of A
+  Fac F = fac_default(c);
+  F.use32 = false;
+  F.lag32 = false;
+  F.perm = nullptr;
+  if ((rc = enqueue_lu(c, F))) return rc;
+  int st = 0;
+  if ((rc = read_status(c, &st))) return rc;
+  if (st & 2) return fail(WW_ENONFINITE, "non-finite surface");
+  if (st & (1 | 8)) return fail(WW_EPIVOT, "double-double DtN: pivot below the guard (no pivoted form)");
+  c->dd_ready = true;
+  return 0;
+}
+
+int dtn_solve_multi_dd(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, int nrhs, double* out_hi,
+                       double* out_lo, double* mu_hi, double* mu_lo) {
+  if (!c || !rhs_hi || !out_hi || !out_lo || (!mu_hi != !mu_lo)) return fail(WW_EINVAL, "null argument");
+  if (!c->dd_ready) return fail(WW_ENOSETUP, "dtn_solve_multi_dd before dtn_setup_dd");
+  if (nrhs < 1 || nrhs > c->r_max) return fail(WW_EINVAL, "1 <= nrhs <= r_max required");
+  const int N = c->N, Np = c->Np;
+  const size_t blk = (size_t)Np * nrhs, pl = (size_t)c->np_max * c->r_max;
+  double* w = c->dd_w;
+  double *psh = w, *psl = w + pl, *muh = w + 2 * pl, *mul = w + 3 * pl, *rh = w + 4 * pl, *rl = w + 5 * pl;
+  double *del = w + 6 * pl, *gh = w + 7 * pl, *gl = w + 8 * pl, *hh = w + 9 * pl, *hl = w + 10 * pl;
+  double *oh = w + 11 * pl, *ol = w + 12 * pl;
+  const int blocks = (int)std::min<size_t>((blk + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs_hi, N, psh, Np, N, Np, nrhs);
+  LAUNCHCHK();
+  if (rhs_lo)
+    hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, rhs_lo, N, psl, Np, N, Np, nrhs);
+  else
+    hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, psl, Np, 0, Np, nrhs);
+  LAUNCHCHK();
+  int rc;
+  // mu = Mi psi (FP64), then refinement: r = psi - A mu (double-double), mu += Mi r_hi
+  if ((rc = enqueue_gemm<double>(c, c->Mi, 0, psh, nullptr, 1.0, muh, nrhs))) return rc;
+  hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, mul, Np, 0, Np, nrhs);
+  LAUNCHCHK();
+  const dim3 gg(Np / 64, (nrhs + 3) / 4);
+  for (int sweep = 0; sweep < DD_SWEEPS; ++sweep) {
+    hipLaunchKernelGGL(k_dd_gemm, gg, dim3(WW_NT), 0, c->stream, c->dd_Ah, c->dd_Al, Np, muh, mul, psh, psl, -1.0, rh,
+                       rl, nrhs);
+    LAUNCHCHK();
+    if ((rc = enqueue_gemm<double>(c, c->Mi, 0, rh, nullptr, 1.0, del, nrhs))) return rc;
+    hipLaunchKernelGGL(k_dd_correct, dim3(blocks), dim3(256), 0, c->stream, muh, mul, del, blk);
+    LAUNCHCHK();
+  }
+  // the final residual against the test
+  hipLaunchKernelGGL(k_dd_gemm, gg, dim3(WW_NT), 0, c->stream, c->dd_Ah, c->dd_Al, Np, muh, mul, psh, psl, -1.0, rh, rl,
+                     nrhs);
+  LAUNCHCHK();
+  unsigned long long* mx = (unsigned long long*)(c->status + 4);
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dd_maxabs, dim3(std::min(blocks, 256)), dim3(256), 0, c->stream, rh, psh, N, Np, nrhs, mx);
+  LAUNCHCHK();
+  // G psi = H gamma / 2 + Gm gamma, gamma = mu'
+  hipLaunchKernelGGL(k_dd_gamma, dim3(nrhs), dim3(WW_NT), dd_lds_bytes(N), c->stream, muh, mul, Np, c->dd_tw, N, gh,
+                     gl, hh, hl);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dd_gemm, gg, dim3(WW_NT), 0, c->stream, c->dd_Gh, c->dd_Gl, Np, gh, gl, hh, hl, 1.0, oh, ol,
+                     nrhs);
+  LAUNCHCHK();
+  const size_t tot = (size_t)N * nrhs;
+  const int ob = (int)std::min<size_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, oh, Np, out_hi, N, Np, N, nrhs);
+  hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, ol, Np, out_lo, N, Np, N, nrhs);
+  if (mu_hi) {
+    hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, muh, Np, mu_hi, N, Np, N, nrhs);
+    hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, mul, Np, mu_lo, N, Np, N, nrhs);
+  }
+  LAUNCHCHK();
+  unsigned long long m[2] = {0, 0};
+  HIPCHK(hipMemcpyAsync(m, mx, sizeof(m), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  double mr, mb;
+  std::memcpy(&mr, &m[0], 8);
+  std::memcpy(&mb, &m[1], 8);
+  if (!(mr <= DD_TOL * mb)) {
+    char msg[160];
+    std::snprintf(msg, sizeof msg, "double-double DtN: residual %.3e of the right-hand side after the sweeps (above 2^-96)",
+                  mb > 0.0 ? mr / mb : mr);
+    return fail(WW_EREFINE, msg);
+  }
+  return 0;
 }
 
 int ww_profile(ww_ctx* c, int enable) {

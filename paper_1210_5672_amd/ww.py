@@ -80,7 +80,7 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
            "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning",
-           "shoot_eval_segments"]
+           "shoot_eval_segments", "dtn_setup_dd", "dtn_solve_multi_dd"]
 
 
 class WWError(RuntimeError):
@@ -119,6 +119,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
     lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]
     lib.shoot_eval_segments.argtypes = [P, P, D, I, ctypes.POINTER(Segment), P, P, P, DP]
+    lib.dtn_setup_dd.argtypes = [P, P, P, D, I]
+    lib.dtn_solve_multi_dd.argtypes = [P, P, P, I, P, P, P, P]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.shoot_eval_batch.argtypes = [I, PP, PP, DP, ctypes.POINTER(ctypes.c_int), PP, PP, PP, DP]
     lib.shoot_eval_batch.restype = I
@@ -277,6 +279,26 @@ class Context:
         _check(self.lib.shoot_eval_segments(self.ptr, _ptr(params.contiguous()), float(T), len(segments), segs,
                                             _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
+
+    def dtn_setup_dd(self, surface_hi: torch.Tensor, surface_lo: torch.Tensor | None, h: float):
+        """Double-double DtN set-up (dtn_setup_dd): surface = hi + lo planes."""
+        hi = self._keep(surface_hi.contiguous())
+        lo = self._keep(surface_lo.contiguous()) if surface_lo is not None else None
+        _check(self.lib.dtn_setup_dd(self.ptr, _ptr(hi), _ptr(lo), float(h), int(hi.shape[0])))
+        self.dN = int(hi.shape[0])
+
+    def dtn_solve_multi_dd(self, rhs_hi: torch.Tensor, rhs_lo: torch.Tensor | None, want_mu: bool = False):
+        """G psi in double-double for rhs (N, nrhs) given as hi and lo planes: returns
+        (out_hi, out_lo) or (out_hi, out_lo, mu_hi, mu_lo)."""
+        N, R = rhs_hi.shape
+        hi = self._keep(rhs_hi.t().contiguous())
+        lo = self._keep(rhs_lo.t().contiguous()) if rhs_lo is not None else None
+        mk = lambda: torch.empty((R, N), dtype=torch.float64, device=rhs_hi.device)
+        oh, ol = mk(), mk()
+        mh, ml = (mk(), mk()) if want_mu else (None, None)
+        _check(self.lib.dtn_solve_multi_dd(self.ptr, _ptr(hi), _ptr(lo), R, _ptr(oh), _ptr(ol), _ptr(mh), _ptr(ml)))
+        out = (oh.t(), ol.t())
+        return out + (mh.t(), ml.t()) if want_mu else out
 
     def fallbacks(self) -> int:
         """WW_FB_* bits behind the results of the last call on this context."""
