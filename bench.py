@@ -229,6 +229,43 @@ def run_mesh(reps: int = 2, tuned: bool = True):
     return out
 
 
+def run_dd(reps: int = 3, N: int = 1024, R: int = 129):
+    """Double-double DtN (dtn_setup_dd, dtn_solve_multi_dd) on the C3 surface with R
+    right-hand sides: set-up time (double-double assembly and FFTs, FP64 LU) and solve
+    time (three refinement sweeps and the final residual, each a double-double product
+    of A with the R columns, the FFTs and the Gm product).  The products' rate is given
+    in FP64 operations at 29 per double-double multiply-add (two-product 2, cross terms
+    4, renormalisation 3, accurate addition 20), against the FP64 vector peak."""
+    import numpy as np
+    import torch
+    from paper_1210_5672_amd import workloads as W
+    from paper_1210_5672_amd import ww
+    w = W.c3()
+    eta, _ = W.initial_state(w)
+    rhs = np.ascontiguousarray(W.random_rhs(N, R, seed=1210))
+    ctx = ww.Context(n_max=N, r_max=R)
+    s_hi, r_hi = ww.to_dev(eta), ww.to_dev(rhs)
+    ctx.dtn_setup_dd(s_hi, None, w.h)
+    ctx.dtn_solve_multi_dd(r_hi, None)
+    torch.cuda.synchronize()
+    ts, tv = [], []
+    for _ in range(reps):
+        t0 = time.perf_counter()
+        ctx.dtn_setup_dd(s_hi, None, w.h)
+        t1 = time.perf_counter()
+        ctx.dtn_solve_multi_dd(r_hi, None)
+        t2 = time.perf_counter()
+        ts.append(t1 - t0)
+        tv.append(t2 - t1)
+    print("# double-double DtN timed", file=sys.stderr, flush=True)
+    solve = statistics.median(tv)
+    madds = 5.0 * N * N * R   # four residual products and the Gm product
+    ctx.close()
+    return {"workload": f"C3 surface, N={N}, {R} right-hand sides", "setup_ms": 1e3 * statistics.median(ts),
+            "solve_ms": 1e3 * solve, "products_fp64_tflops_equiv": 29.0 * madds / solve / 1e12,
+            "fp64_vector_peak_tflops": FP64_PEAK_TFLOPS}
+
+
 def stage_roofline(N, M, nst, stage_ms):
     """Whole-stage roofline: the algorithmic work of one stage at the FP64 MFMA peak and
     the HBM bandwidth, summed phase by phase (each phase at its own bound), against the
@@ -413,6 +450,7 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint-gradient timing (C4)")
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner's cached choices")
     ap.add_argument("--no-mesh", action="store_true", help="skip the segmented non-uniform-mesh march (C6)")
+    ap.add_argument("--no-dd", action="store_true", help="skip the double-double DtN timing")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -515,6 +553,8 @@ def main():
         out["adjoint"] = run_adjoint()
     if not args.no_mesh:
         out["mesh"] = run_mesh(tuned=not args.no_tuning)
+    if not args.no_dd:
+        out["dd"] = run_dd()
     if not args.no_batch:
         out["batch"] = run_batch(tuned=not args.no_tuning)
     if args.copy_probe:
