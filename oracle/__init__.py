@@ -11,6 +11,8 @@ and the two share no code.
   mesh_oracle.py : the non-uniform mesh x = xi(alpha) and the time segments with
                  regridding (Sec. 2.2 eq. (xi), (rho:def)), pinned by
                  tests/test_mesh_oracle.py.
+  sdc_oracle.py : the SDC15 time stepper (Radau IIa nodes, RK4 predictor, Picard
+                 sweeps; Sec. 2.2), pinned by tests/test_sdc_oracle.py.
 
 Parity status: every function is pinned by tests/test_oracle_pins.py (closed forms,
 printed linear periods, invariants, central differences, extended precision).

@@ -1,0 +1,52 @@
+"""Pins of the SDC15 oracle (oracle/sdc_oracle.py, Sec. 2.2): the Radau IIa nodes and
+integration weights against the exactness that defines them, the order of one step on a
+linear equation (15, with 10 sweeps; 4 + sweeps + 1 in general, so a wrong predictor or
+sweep count shows), and agreement with the DOP853 march on a small standing wave."""
+import math
+
+import numpy as np
+
+from oracle import sdc_oracle as S
+from oracle import ww_oracle as O
+from paper_1210_5672_amd import workloads as W
+
+
+def test_radau_iia_nodes_and_weights():
+    c = S.radau_iia_nodes()
+    M = S.integration_matrix(c)
+    assert len(c) == 8 and c[-1] == 1.0 and np.all(np.diff(c) > 0) and c[0] > 0
+    b = M[-1]
+    # Radau quadrature with 8 nodes: exact up to degree 14, not 15
+    assert max(abs(np.dot(b, c ** k) - 1 / (k + 1)) for k in range(15)) < 1e-15
+    assert abs(np.dot(b, c ** 15) - 1 / 16) > 1e-11
+    # every row integrates the interpolant of degree 7 exactly
+    assert max(np.abs(M @ c ** k - c ** (k + 1) / (k + 1)).max() for k in range(8)) < 1e-15
+
+
+def _local_order(sweeps):
+    lam = -1.0 + 2.0j
+    F = lambda y: [lam * y[0]]
+    errs = []
+    dts = (1.2, 0.9)
+    for dt in dts:
+        y1 = S.sdc_step([np.array([1.0 + 0j])], F, dt, sweeps=sweeps)[0][0]
+        errs.append(abs(y1 - np.exp(lam * dt)))
+    return math.log(errs[0] / errs[1]) / math.log(dts[0] / dts[1]), errs
+
+
+def test_local_order_of_one_step():
+    p, errs = _local_order(10)
+    print("10 sweeps: local order", p, errs)
+    assert p > 15.0          # local error O(dt^16)
+    p3, errs3 = _local_order(3)
+    print("3 sweeps: local order", p3, errs3)
+    assert 7.0 < p3 < 10.0   # 4 (predictor) + 3 (sweeps) + 1: local error O(dt^9)
+
+
+def test_sdc_march_agrees_with_dop853():
+    w = W.c1()
+    M = 2
+    a = S.shoot_eval_sdc(w.N, w.h, w.tau, w.g, w.basis[:, :M], w.q_fixed, w.params[:M], w.T, 8)
+    b = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis[:, :M], w.q_fixed, w.params[:M], w.T, 64)
+    assert np.abs(a["r"] - b["r"]).max() < 1e-11 * np.abs(b["r"]).max()
+    assert np.abs(a["J"] - b["J"]).max() < 1e-11 * np.abs(b["J"]).max()
