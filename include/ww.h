@@ -202,6 +202,20 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
                double *drdT, double *f);
 
 /*
+ * shoot_eval_sdc: shoot_eval marched with the 15th-order spectral deferred correction
+ * of Sec. 2.2 instead of DOP853: per step of dt = T / (4 nsteps), eight Radau IIa nodes
+ * (zeros of P_8 - P_7 on (0, 1]), initial values at the nodes by classical RK4 from node
+ * to node, ten Picard sweeps Y_m <- y_0 + dt sum_j S_mj F(Y_j) (S: integrals of the
+ * nodes' Lagrange polynomials), and the final integration with the weights of the last
+ * node: 113 right-hand-side evaluations per step (every stage on its own factors, the
+ * Jacobian columns with the base state of the same stage), the filter after every step.
+ * Outputs, fallbacks and errors as shoot_eval.  Synchronises.  Work arrays are
+ * allocated at the first call: 113 x 2 n_max r_max doubles of stage slopes.
+ */
+int shoot_eval_sdc(ww_ctx *ctx, const double *params, double T, int nsteps, double *r, double *J,
+                   double *drdT, double *f);
+
+/*
  * Double-double DtN (the GPU part of the quadruple-precision workflow: Sec. 2.2 on
  * quadruple precision, Sec. 3.3; residuals in extended precision by matrix products,
  * corrections from double-precision factors).  Values are unevaluated sums hi + lo of two

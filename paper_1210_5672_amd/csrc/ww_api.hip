@@ -14,6 +14,7 @@
 #include "ww_kernels.hpp"
 #include "ww_mesh.hpp"
 #include "ww_dd.hpp"
+#include "ww_sdc.hpp"
 #include "ww_svd.hpp"
 #include "ww_gmres.hpp"
 
@@ -127,6 +128,13 @@ struct ww_ctx {
   double *dd_pt_hi = nullptr, *dd_pt_lo = nullptr;
   double *dd_Ah = nullptr, *dd_Al = nullptr, *dd_Gh = nullptr, *dd_Gl = nullptr;
   double* dd_w = nullptr;
+  // SDC15 (shoot_eval_sdc), allocated at first use: the stage slopes of one step
+  // (SDC_STAGES slots of 2 n_max r_max), the stage state, and the sparse stage rows
+  // (SDC_STAGES + 1 rows of SDC_MAXNZ slot indices and weights; the last row is the
+  // step's final combination)
+  double *sdc_K = nullptr, *sdc_y = nullptr, *sdc_w = nullptr;
+  int* sdc_j = nullptr;
+  int sdc_cnt[SDC_STAGES + 1] = {};
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -2189,12 +2197,259 @@ static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww
   return read_status(c, st, where);
 }
 
+// ----- SDC15 time stepping (Sec. 2.2) -----
+// Legendre polynomial P_n(x) and its derivative by the three-term recurrence
+static void legendre(int n, double x, double* p, double* dp) {
+  double p0 = 1.0, p1 = x;
+  if (n == 0) {
+    *p = 1.0;
+    *dp = 0.0;
+    return;
+  }
+  for (int k = 2; k <= n; ++k) {
+    const double p2 = ((2 * k - 1) * x * p1 - (k - 1) * p0) / k;
+    p0 = p1;
+    p1 = p2;
+  }
+  *p = p1;
+  *dp = n * (x * p1 - p0) / (x * x - 1.0);
+}
+
+// Radau IIa nodes on (0, 1]: zeros of P_8(x) - P_7(x), x = 2c - 1, found by a sign scan
+// and bisection to the last bit; the last node is c = 1
+static void radau_nodes(double* c) {
+  auto f = [](double x) {
+    double a, b, da, db;
+    legendre(SDC_NODES, x, &a, &da);
+    legendre(SDC_NODES - 1, x, &b, &db);
+    return a - b;
+  };
+  int n = 0;
+  const int grid = 4096;
+  double xl = -1.0, fl = f(xl);
+  for (int g = 1; g < grid && n < SDC_NODES - 1; ++g) {
+    const double xr = -1.0 + 2.0 * g / grid, fr = f(xr);
+    if ((fl < 0) != (fr < 0)) {
+      double a = xl, b = xr, fa = fl;
+      for (int it = 0; it < 200; ++it) {
+        const double m = 0.5 * (a + b);
+        if (m == a || m == b) break;
+        const double fm = f(m);
+        if ((fm < 0) == (fa < 0)) {
+          a = m;
+          fa = fm;
+        } else {
+          b = m;
+        }
+      }
+      c[n++] = 0.5 * (0.5 * (a + b) + 1.0);
+    }
+    xl = xr;
+    fl = fr;
+  }
+  c[SDC_NODES - 1] = 1.0;
+}
+
+// S[m][j] = integral from 0 to c_m of node j's Lagrange polynomial, by 16-point
+// Gauss-Legendre quadrature (nodes by Newton's method on P_16)
+static void radau_integration(const double* c, double S[SDC_NODES][SDC_NODES]) {
+  const int ng = 16;
+  double xg[ng], wg[ng];
+  for (int i = 0; i < ng; ++i) {
+    double x = std::cos(M_PI * (i + 0.75) / (ng + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(ng, x, &p, &dp);
+      const double dx = p / dp;
+      x -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    double p, dp;
+    legendre(ng, x, &p, &dp);
+    xg[i] = x;
+    wg[i] = 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  for (int m = 0; m < SDC_NODES; ++m)
+    for (int j = 0; j < SDC_NODES; ++j) {
+      double acc = 0.0;
+      for (int q = 0; q < ng; ++q) {
+        const double x = 0.5 * c[m] * (xg[q] + 1.0);
+        double ell = 1.0;
+        for (int k = 0; k < SDC_NODES; ++k)
+          if (k != j) ell *= (x - c[k]) / (c[j] - c[k]);
+        acc += wg[q] * ell;
+      }
+      S[m][j] = 0.5 * c[m] * acc;
+    }
+}
+
+// The SDC15 step as an explicit method: rows 0..SDC_STAGES-1 give stage s's state
+// y_0 + dt sum w K_j (slots j < s), row SDC_STAGES the step's result.  Slots: RK4 from
+// node to node (4 per node), F at the last predicted node, then F at the nodes of each
+// of the ten sweeps.
+static void sdc_rows(int* cnt, int (*jt)[SDC_MAXNZ], double (*wt)[SDC_MAXNZ]) {
+  double c[SDC_NODES], S[SDC_NODES][SDC_NODES];
+  radau_nodes(c);
+  radau_integration(c, S);
+  std::vector<double> cur(SDC_STAGES, 0.0);   // the running state's weights on the slots
+  auto put = [&](int row, const std::vector<double>& v) {
+    int n = 0;
+    for (int j = 0; j < SDC_STAGES; ++j)
+      if (v[j] != 0.0) {
+        jt[row][n] = j;
+        wt[row][n] = v[j];
+        ++n;
+      }
+    cnt[row] = n;
+  };
+  int slot = 0;
+  double t = 0.0;
+  int fnode[SDC_NODES];   // slot holding F at each node of the current iterate
+  for (int m = 0; m < SDC_NODES; ++m) {
+    const double h = c[m] - t;
+    const int s1 = slot++, s2 = slot++, s3 = slot++, s4 = slot++;
+    std::vector<double> v = cur;
+    put(s1, v);
+    v = cur;
+    v[s1] += h / 2;
+    put(s2, v);
+    v = cur;
+    v[s2] += h / 2;
+    put(s3, v);
+    v = cur;
+    v[s3] += h;
+    put(s4, v);
+    cur[s1] += h / 6;
+    cur[s2] += h / 3;
+    cur[s3] += h / 3;
+    cur[s4] += h / 6;
+    if (m > 0) fnode[m - 1] = s1;   // F at the node just reached (k1 of the next interval)
+    t = c[m];
+  }
+  fnode[SDC_NODES - 1] = slot;
+  put(slot++, cur);
+  for (int k = 0; k < SDC_SWEEPS; ++k) {
+    int nf[SDC_NODES];
+    for (int m = 0; m < SDC_NODES; ++m) {
+      std::vector<double> v(SDC_STAGES, 0.0);
+      for (int j = 0; j < SDC_NODES; ++j) v[fnode[j]] += S[m][j];
+      nf[m] = slot;
+      put(slot++, v);
+    }
+    for (int m = 0; m < SDC_NODES; ++m) fnode[m] = nf[m];
+  }
+  std::vector<double> v(SDC_STAGES, 0.0);
+  for (int j = 0; j < SDC_NODES; ++j) v[fnode[j]] += S[SDC_NODES - 1][j];
+  put(SDC_STAGES, v);
+}
+
+static int ensure_sdc(ww_ctx* c) {
+  if (c->sdc_K) return 0;
+  int rc;
+  const size_t st = (size_t)2 * c->n_max * c->r_max;
+  if ((rc = dalloc(c, (void**)&c->sdc_K, (size_t)SDC_STAGES * st * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->sdc_y, st * 8))) return rc;
+  if ((rc = dalloc(c, (void**)&c->sdc_j, (SDC_STAGES + 1) * SDC_MAXNZ * sizeof(int)))) return rc;
+  if ((rc = dalloc(c, (void**)&c->sdc_w, (SDC_STAGES + 1) * SDC_MAXNZ * 8))) return rc;
+  std::vector<int> jt((SDC_STAGES + 1) * SDC_MAXNZ, 0);
+  std::vector<double> wt((SDC_STAGES + 1) * SDC_MAXNZ, 0.0);
+  sdc_rows(c->sdc_cnt, reinterpret_cast<int(*)[SDC_MAXNZ]>(jt.data()), reinterpret_cast<double(*)[SDC_MAXNZ]>(wt.data()));
+  HIPCHK(hipMemcpy(c->sdc_j, jt.data(), jt.size() * sizeof(int), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(c->sdc_w, wt.data(), wt.size() * 8, hipMemcpyHostToDevice));
+  return 0;
+}
+
+// the column chain of a stage whose state is ysrc (no stage combination), slopes to kout
+static int enqueue_col_chain_at(ww_ctx* c, const double* ysrc, double* kout, const Fac& F) {
+  int rc;
+  const int M = c->M;
+  const size_t tot = (size_t)c->Np * M;
+  const int blocks = (int)std::min<size_t>((tot + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_col_pre, dim3(blocks), dim3(256), 0, c->stream, ysrc, c->K, c->Ys, c->coef, 0, kstride(c),
+                     F.aux, c->n_max, c->Psi, c->Np, c->N, M);
+  LAUNCHCHK();
+  if ((rc = enqueue_dtn_cols(c, F, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
+  hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
+                     F.aux, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+  LAUNCHCHK();
+  return 0;
+}
+
+// one SDC15 step of dt: every stage's state by k_sdc_combine, its base chain and column
+// chain on the context's stream (each stage on its own factors), then the step's
+// combination in place and the filter
+static int enqueue_sdc_step(ww_ctx* c, bool cols, double dt) {
+  int rc;
+  const size_t ks = kstride(c);
+  const size_t n = (size_t)2 * c->N * (cols ? c->M + 1 : 1);
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  const Fac F = fac_default(c);
+  for (int s = 0; s <= SDC_STAGES; ++s) {
+    double* dst = s < SDC_STAGES ? c->sdc_y : c->y;
+    hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y, c->sdc_K, ks,
+                       c->sdc_j + s * SDC_MAXNZ, c->sdc_w + s * SDC_MAXNZ, c->sdc_cnt[s], dt, dst, n);
+    LAUNCHCHK();
+    if (s == SDC_STAGES) break;
+    double* kout = c->sdc_K + (size_t)s * ks;
+    if ((rc = enqueue_base_chain(c, c->sdc_y, 0, kout, F))) return rc;
+    if (cols && (rc = enqueue_col_chain_at(c, c->sdc_y, kout, F))) return rc;
+  }
+  // the filter (no stage terms) and the step count
+  hipLaunchKernelGGL(k_step_end, dim3(cols ? c->M + 1 : 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y,
+                     c->K, ks, 0, c->coef, c->tw, c->sig, c->N, 0, c->status);
+  LAUNCHCHK();
+  return 0;
+}
+
+static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
+                   double* f, int* st, int* where) {
+  const bool cols = (J != nullptr) && c->M > 0;
+  int rc;
+  if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
+  if ((rc = ensure_sdc(c))) return rc;
+  const bool ug = c->use_graph;
+  c->use_graph = false;   // the Runge-Kutta step graph is not used here
+  rc = shoot_prepare(c, params, T, nsteps, cols, false);
+  c->use_graph = ug;
+  if (rc) return rc;
+  const double dt = T / (4.0 * nsteps);
+  for (int n = 0; n < nsteps; ++n)
+    if ((rc = enqueue_sdc_step(c, cols, dt))) return rc;
+  if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
+    const std::string msg = g_err;
+    (void)hipStreamSynchronize(c->stream);
+    g_err = msg;
+    return rc;
+  }
+  return read_status(c, st, where);
+}
+
 extern "C" {
 
 int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
                double* f) {
   if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
   return shoot_eval_fb(c, params, T, nsteps, r, J, drdT, f, c->lag_off ? WW_FB_DIRECT : 0);
+}
+
+int shoot_eval_sdc(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
+                   double* f) {
+  if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
+  if (int rj = pipe_join(c)) return rj;
+  if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_eval_sdc before shoot_setup");
+  if (nsteps < 1 || !std::isfinite(T)) return fail(WW_EINVAL, "nsteps >= 1 and finite T required");
+  c->fb = 0;
+  for (;;) {
+    int st = 0, where = 0, rc;
+    if ((rc = sdc_run(c, params, T, nsteps, r, J, drdT, f, &st, &where))) return rc;
+    const unsigned nf = next_fallback(c, st);
+    if (!nf) {
+      if ((rc = status_error(c, st, where))) return rc;
+      c->fb_last = c->fb;
+      return 0;
+    }
+    c->fb |= nf;
+  }
 }
 
 int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,

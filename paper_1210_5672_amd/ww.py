@@ -80,7 +80,7 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
            "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning",
-           "shoot_eval_segments", "dtn_setup_dd", "dtn_solve_multi_dd"]
+           "shoot_eval_segments", "dtn_setup_dd", "dtn_solve_multi_dd", "shoot_eval_sdc"]
 
 
 class WWError(RuntimeError):
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]
     lib.shoot_eval_segments.argtypes = [P, P, D, I, ctypes.POINTER(Segment), P, P, P, DP]
     lib.dtn_setup_dd.argtypes = [P, P, P, D, I]
+    lib.shoot_eval_sdc.argtypes = [P, P, D, I, P, P, P, DP]
     lib.dtn_solve_multi_dd.argtypes = [P, P, P, I, P, P, P, P]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.shoot_eval_batch.argtypes = [I, PP, PP, DP, ctypes.POINTER(ctypes.c_int), PP, PP, PP, DP]
@@ -260,6 +261,19 @@ class Context:
         f = ctypes.c_double(0.0)
         _check(self.lib.shoot_eval(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
                                    _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
+        return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
+
+    def shoot_eval_sdc(self, params: torch.Tensor, T: float, nsteps: int, jacobian: bool = True,
+                       drdT: bool = True):
+        """shoot_eval marched with SDC15 (shoot_eval_sdc)."""
+        N, M = self.N, self.M
+        dev = params.device
+        r = torch.empty(N, dtype=torch.float64, device=dev)
+        Jc = torch.empty((M, N), dtype=torch.float64, device=dev) if jacobian else None
+        d = torch.empty(N, dtype=torch.float64, device=dev) if drdT else None
+        f = ctypes.c_double(0.0)
+        _check(self.lib.shoot_eval_sdc(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
+                                       _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
 
     def shoot_eval_segments(self, params: torch.Tensor, T: float, segments, jacobian: bool = True,

@@ -1,0 +1,76 @@
+"""SDC15 on the GPU (shoot_eval_sdc, Sec. 2.2) against the SDC15 oracle
+(oracle/sdc_oracle.py), element by element through the C ABI: infinite depth, finite
+depth with tension on a padded grid (N = 96 in 128-row tiles), both precision forms, a
+base-only march, and the argument checks."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sdc_oracle as S
+from paper_1210_5672_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-12
+
+
+def _ww():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    return ww, torch
+
+
+def relerr(a, b):
+    a, b = np.asarray(a), np.asarray(b)
+    return float(np.abs(a - b).max() / max(np.abs(b).max(), 1e-300))
+
+
+# steps small enough for the explicit scheme's stability on the filtered spectrum (3 steps of the
+# finite-depth case with tension 0.01 are not: rounding then grows by orders of magnitude)
+CASES = [(64, math.inf, 0.0, 3, 4, 2 * math.pi), (96, 0.8, 0.005, 3, 12, 7.0)]
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("N,h,tau,M,nsteps,T", CASES)
+def test_sdc_march_matches_the_oracle(N, h, tau, M, nsteps, T, mixed):
+    ww, torch = _ww()
+    print(f"sdc N={N} h={h} mixed={mixed}", flush=True)
+    basis = W.cosine_basis(N, M)
+    p = np.zeros(M)
+    p[0] = 0.03
+    p[1:] = 1e-3 * np.arange(1, M)
+    qf = np.zeros(2 * N)
+    ctx = ww.Context(n_max=max(N, 64), r_max=M + 1, mixed=mixed)
+    ctx.shoot_setup(N, h, tau, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    out = ctx.shoot_eval_sdc(ww.to_dev(p), T, nsteps)
+    ref = S.shoot_eval_sdc(N, h, tau, 1.0, basis, qf, p, T, nsteps)
+    e = {k: relerr(out[k].cpu().numpy(), ref[k]) for k in ("r", "J")}
+    # dr/dT (one right-hand side at the final state, a near-cancellation) on the scale of
+    # its rounding sensitivity, as for shoot_eval
+    op = max(math.exp(-36.0 * (k / (N / 2)) ** 36) * (1.0 + tau * k * k) for k in range(N // 2))
+    sc = max(np.abs(ref["drdT"]).max(), 0.25 * 0.03 / math.sqrt(N) * op)
+    e["drdT"] = float(np.abs(out["drdT"].cpu().numpy() - ref["drdT"]).max() / sc)
+    e["f"] = abs(out["f"] - ref["f"]) / ref["f"]
+    print("errors", e, "fallbacks", ctx.fallbacks(), flush=True)
+    assert max(e.values()) < TOL
+    assert ctx.fallbacks() == 0
+    ctx.close()
+
+
+def test_sdc_base_only_and_arguments():
+    ww, torch = _ww()
+    N, M = 64, 2
+    basis = W.cosine_basis(N, M)
+    p = np.array([0.02, 0.001])
+    ctx = ww.Context(n_max=N, r_max=M + 1)
+    ctx.shoot_setup(N, math.inf, 0.0, 1.0, ww.to_dev(basis), ww.to_dev(np.zeros(2 * N)))
+    for bad in ((6.0, 0), (math.inf, 2)):
+        with pytest.raises(ww.WWError) as e:
+            ctx.shoot_eval_sdc(ww.to_dev(p), *bad)
+        assert e.value.name == "WW_EINVAL"
+    out = ctx.shoot_eval_sdc(ww.to_dev(p), 2 * math.pi, 2, jacobian=False)
+    ref = S.shoot_eval_sdc(N, math.inf, 0.0, 1.0, basis, np.zeros(2 * N), p, 2 * math.pi, 2, jacobian=False)
+    assert relerr(out["r"].cpu().numpy(), ref["r"]) < TOL
+    ctx.close()
