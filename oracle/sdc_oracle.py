@@ -94,28 +94,30 @@ def sdc_step(y, F, dt, c=None, S=None, sweeps=SWEEPS):
     return out
 
 
-def march_sdc(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, sweeps=SWEEPS):
+def march_sdc(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, sweeps=SWEEPS, ar=O.F64):
     """nsteps SDC15 steps of dt = T / (4 nsteps) for (q, Qdot), the filter applied to the
-    state after every step."""
+    state after every step.  ar: one of ww_oracle's FP64 backends (the right-hand sides
+    and the filter run in it; the step's combinations are plain FP64)."""
     c = radau_iia_nodes()
     S = integration_matrix(c)
     dt = T / (4 * nsteps)
-    F = lambda y: list(O.rhs(y[0], y[1], y[2], y[3], h, tau, g))
+    F = lambda y: list(O.rhs(y[0], y[1], y[2], y[3], h, tau, g, ar))
     y = [eta0, phi0, Qe0, Qp0]
     for _ in range(nsteps):
         y = sdc_step(y, F, dt, c, S, sweeps)
-        y = [O.filt(v) if v is not None else None for v in y]
+        y = [O.filt(v, ar) if v is not None else None for v in y]
     return y
 
 
-def shoot_eval_sdc(N, h, tau, g, basis, q_fixed, params, T, nsteps, jacobian=True, sweeps=SWEEPS):
-    """r, J, dr/dT, f as oracle.ww_oracle.shoot_eval, marched with SDC15."""
+def shoot_eval_sdc(N, h, tau, g, basis, q_fixed, params, T, nsteps, jacobian=True, sweeps=SWEEPS, ar=O.F64):
+    """r, J, dr/dT, f as oracle.ww_oracle.shoot_eval, marched with SDC15 (ar: as for
+    march_sdc)."""
     basis = np.asarray(basis, dtype=float)
-    q0 = np.asarray(q_fixed, dtype=float) + basis @ np.asarray(params, dtype=float)
+    q0 = np.asarray(q_fixed, dtype=float) + ar.matmul(basis, np.asarray(params, dtype=float))
     Qe, Qp = (basis[:N], basis[N:]) if jacobian else (None, None)
-    eta, phi, Qe, Qp = march_sdc(q0[:N], q0[N:], Qe, Qp, h, tau, g, T, nsteps, sweeps)
+    eta, phi, Qe, Qp = march_sdc(q0[:N], q0[N:], Qe, Qp, h, tau, g, T, nsteps, sweeps, ar)
     w = 1 / math.sqrt(N)
-    _, phi_t, _, _ = O.rhs(eta, phi, None, None, h, tau, g)
+    _, phi_t, _, _ = O.rhs(eta, phi, None, None, h, tau, g, ar)
     r = w * phi
     return dict(r=r, J=(w * Qp) if jacobian else None, drdT=w * phi_t / 4, f=math.fsum(r * r) / 2,
                 eta=eta, phi=phi)

@@ -135,6 +135,10 @@ struct ww_ctx {
   double *sdc_K = nullptr, *sdc_y = nullptr, *sdc_w = nullptr;
   int* sdc_j = nullptr;
   int sdc_cnt[SDC_STAGES + 1] = {};
+  // the nodes of a correction sweep, evaluated together: per node the stage state, its
+  // stage-state copy and the base Dirichlet data (SDC_NODES each); the LU stream's event
+  double *sdc_yn = nullptr, *sdc_ysn = nullptr, *sdc_rhsn = nullptr;
+  hipEvent_t sdc_ev = nullptr;
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -516,6 +520,7 @@ void ww_destroy(ww_ctx* c) {
   if (c->pgend) (void)hipGraphExecDestroy(c->pgend);
   if (c->pgendc) (void)hipGraphExecDestroy(c->pgendc);
   if (c->evE) (void)hipEventDestroy(c->evE);
+  if (c->sdc_ev) (void)hipEventDestroy(c->sdc_ev);
   for (hipEvent_t e : c->kev_a) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->kev_b) (void)hipEventDestroy(e);
   if (c->stamps) (void)hipFree(c->stamps);
@@ -1104,18 +1109,12 @@ static int grp_first(const ww_ctx* c, int s) { return s / lu_group(c) * lu_group
 static int grp_last(const ww_ctx* c, int s) { return std::min(c->nst, grp_first(c, s) + lu_group(c)) - 1; }
 static hipStream_t lu_stream(const ww_ctx* c, int s) { return c->lus[(s / lu_group(c)) % lu_count(c)]; }
 
-static int ensure_pipe(ww_ctx* c) {
+// the first n factor sets of the ring (each for n_max)
+static int ensure_ring(ww_ctx* c, int n) {
   int rc;
-  for (int i = 0; i < lu_count(c); ++i)
-    if (!c->lus[i]) HIPCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
-  for (int i = 0; i < 16; ++i) {
-    if (!c->evA[i]) HIPCHK(hipEventCreateWithFlags(&c->evA[i], hipEventDisableTiming));
-    if (!c->evL[i]) HIPCHK(hipEventCreateWithFlags(&c->evL[i], hipEventDisableTiming));
-  }
-  if (!c->evE) HIPCHK(hipEventCreateWithFlags(&c->evE, hipEventDisableTiming));
   const size_t np = c->np_max, nn = np * np;
   const size_t nbm = np / WW_TB;
-  while (c->ring_n < c->nst) {
+  while (c->ring_n < n) {
     RingSet& r = c->ring[c->ring_n];
     double** d[] = {&r.A, &r.Gm, &r.X, &r.Z, &r.V, &r.Mi, &r.Gmr, &r.Ar};
     for (double** q : d)
@@ -1132,6 +1131,17 @@ static int ensure_pipe(ww_ctx* c) {
     ++c->ring_n;
   }
   return 0;
+}
+
+static int ensure_pipe(ww_ctx* c) {
+  for (int i = 0; i < lu_count(c); ++i)
+    if (!c->lus[i]) HIPCHK(hipStreamCreateWithFlags(&c->lus[i], hipStreamNonBlocking));
+  for (int i = 0; i < 16; ++i) {
+    if (!c->evA[i]) HIPCHK(hipEventCreateWithFlags(&c->evA[i], hipEventDisableTiming));
+    if (!c->evL[i]) HIPCHK(hipEventCreateWithFlags(&c->evL[i], hipEventDisableTiming));
+  }
+  if (!c->evE) HIPCHK(hipEventCreateWithFlags(&c->evE, hipEventDisableTiming));
+  return ensure_ring(c, c->nst);
 }
 
 static Fac pipe_set(ww_ctx* c, int s, bool cols) {
@@ -2347,15 +2357,103 @@ static int ensure_sdc(ww_ctx* c) {
   if (c->sdc_K) return 0;
   int rc;
   const size_t st = (size_t)2 * c->n_max * c->r_max;
-  if ((rc = dalloc(c, (void**)&c->sdc_K, (size_t)SDC_STAGES * st * 8))) return rc;
-  if ((rc = dalloc(c, (void**)&c->sdc_y, st * 8))) return rc;
-  if ((rc = dalloc(c, (void**)&c->sdc_j, (SDC_STAGES + 1) * SDC_MAXNZ * sizeof(int)))) return rc;
-  if ((rc = dalloc(c, (void**)&c->sdc_w, (SDC_STAGES + 1) * SDC_MAXNZ * 8))) return rc;
+  // each buffer once (a failed call leaves the others for the next)
+  if (!c->sdc_y && (rc = dalloc(c, (void**)&c->sdc_y, st * 8))) return rc;
+  if (!c->sdc_yn && (rc = dalloc(c, (void**)&c->sdc_yn, SDC_NODES * st * 8))) return rc;
+  if (!c->sdc_ysn && (rc = dalloc(c, (void**)&c->sdc_ysn, SDC_NODES * st * 8))) return rc;
+  if (!c->sdc_rhsn && (rc = dalloc(c, (void**)&c->sdc_rhsn, (size_t)SDC_NODES * c->np_max * 8))) return rc;
+  if (!c->sdc_j && (rc = dalloc(c, (void**)&c->sdc_j, (SDC_STAGES + 1) * SDC_MAXNZ * sizeof(int)))) return rc;
+  if (!c->sdc_w && (rc = dalloc(c, (void**)&c->sdc_w, (SDC_STAGES + 1) * SDC_MAXNZ * 8))) return rc;
   std::vector<int> jt((SDC_STAGES + 1) * SDC_MAXNZ, 0);
   std::vector<double> wt((SDC_STAGES + 1) * SDC_MAXNZ, 0.0);
   sdc_rows(c->sdc_cnt, reinterpret_cast<int(*)[SDC_MAXNZ]>(jt.data()), reinterpret_cast<double(*)[SDC_MAXNZ]>(wt.data()));
   HIPCHK(hipMemcpy(c->sdc_j, jt.data(), jt.size() * sizeof(int), hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(c->sdc_w, wt.data(), wt.size() * 8, hipMemcpyHostToDevice));
+  // sdc_K last: its presence marks the set-up as complete
+  return dalloc(c, (void**)&c->sdc_K, (size_t)SDC_STAGES * st * 8);
+}
+
+// the factor sets and the LU stream of the grouped sweeps (first use)
+static int ensure_sdc_groups(ww_ctx* c) {
+  if (!c->lus[0]) HIPCHK(hipStreamCreateWithFlags(&c->lus[0], hipStreamNonBlocking));
+  if (!c->sdc_ev) HIPCHK(hipEventCreateWithFlags(&c->sdc_ev, hipEventDisableTiming));
+  return ensure_ring(c, SDC_NODES);
+}
+
+// The nodes of one correction sweep (stages s0 .. s0 + SDC_NODES - 1) read only slopes
+// of earlier sweeps, so they are evaluated together: every node's state, spectral prep
+// and assembly into its own factor set, the LUs in two groups of four (the second
+// group on the LU stream, beside the first group and its chains), then every node's
+// base and column chains on its own factors.  The kernels and factors are those of the
+// stage-by-stage form, so the results are the same bit for bit.
+static int enqueue_sdc_sweep(ww_ctx* c, bool cols, double dt, int s0) {
+  static_assert(SDC_NODES == 2 * BLU_GMAX, "a sweep is factored in two groups");
+  int rc;
+  const size_t ks = kstride(c), n = (size_t)2 * c->N * (cols ? c->M + 1 : 1);
+  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+  Fac F[SDC_NODES];
+  for (int m = 0; m < SDC_NODES; ++m) {
+    F[m] = pipe_set(c, m, false);
+    F[m].lag32 = false;
+    F[m].Gm = nullptr;   // the chains read Gm row-major only
+  }
+  const hipStream_t main = c->stream, ls = c->lus[0];
+  auto prep = [&](int m) -> int {
+    double* ym = c->sdc_yn + m * ks;
+    hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y, c->sdc_K, ks,
+                       c->sdc_j + (s0 + m) * SDC_MAXNZ, c->sdc_w + (s0 + m) * SDC_MAXNZ, c->sdc_cnt[s0 + m], dt, ym,
+                       n);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ym, c->K,
+                       c->sdc_ysn + m * ks, c->coef, 0, ks, F[m].aux, c->n_max, c->sdc_rhsn + (size_t)m * c->Np,
+                       c->Np, c->tw, c->N, c->hsurf, c->status);
+    LAUNCHCHK();
+    return enqueue_assemble(c, F[m], false);
+  };
+  auto chain = [&](int m) -> int {
+    double* ym = c->sdc_yn + m * ks;
+    double* ysm = c->sdc_ysn + m * ks;
+    double* kout = c->sdc_K + (size_t)(s0 + m) * ks;
+    int e;
+    if ((e = enqueue_dtn_cols(c, F[m], c->sdc_rhsn + (size_t)m * c->Np, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0,
+                              c->rr0, 1)))
+      return e;
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysm, c->gphi0, F[m].aux,
+                       c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
+                       c->tau);
+    LAUNCHCHK();
+    if (!cols) return 0;
+    const int M = c->M;
+    const size_t tot = (size_t)c->Np * M;
+    const int cb = (int)std::min<size_t>((tot + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_col_pre, dim3(cb), dim3(256), 0, c->stream, ym, c->K, ysm, c->coef, 0, ks, F[m].aux,
+                       c->n_max, c->Psi, c->Np, c->N, M);
+    LAUNCHCHK();
+    if ((e = enqueue_dtn_cols(c, F[m], c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return e;
+    hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysm, c->Gpsi, c->Np,
+                       F[m].aux, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+    LAUNCHCHK();
+    return 0;
+  };
+  const int G = BLU_GMAX;
+  // the second group first, so that its LU runs beside the first group's work
+  for (int m = G; m < SDC_NODES; ++m)
+    if ((rc = prep(m))) return rc;
+  HIPCHK(hipEventRecord(c->sdc_ev, main));
+  HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
+  c->stream = ls;
+  rc = enqueue_lu_group(c, F + G, G);
+  c->stream = main;
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(c->sdc_ev, ls));
+  for (int m = 0; m < G; ++m)
+    if ((rc = prep(m))) return rc;
+  if ((rc = enqueue_lu_group(c, F, G))) return rc;
+  for (int m = 0; m < G; ++m)
+    if ((rc = chain(m))) return rc;
+  HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
+  for (int m = G; m < SDC_NODES; ++m)
+    if ((rc = chain(m))) return rc;
   return 0;
 }
 
@@ -2378,13 +2476,18 @@ static int enqueue_col_chain_at(ww_ctx* c, const double* ysrc, double* kout, con
 // one SDC15 step of dt: every stage's state by k_sdc_combine, its base chain and column
 // chain on the context's stream (each stage on its own factors), then the step's
 // combination in place and the filter
-static int enqueue_sdc_step(ww_ctx* c, bool cols, double dt) {
+static int enqueue_sdc_step(ww_ctx* c, bool cols, double dt, bool grouped) {
   int rc;
   const size_t ks = kstride(c);
   const size_t n = (size_t)2 * c->N * (cols ? c->M + 1 : 1);
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
   const Fac F = fac_default(c);
   for (int s = 0; s <= SDC_STAGES; ++s) {
+    if (grouped && s >= SDC_FIRST_SWEEP && s < SDC_STAGES) {
+      if ((rc = enqueue_sdc_sweep(c, cols, dt, s))) return rc;
+      s += SDC_NODES - 1;
+      continue;
+    }
     double* dst = s < SDC_STAGES ? c->sdc_y : c->y;
     hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y, c->sdc_K, ks,
                        c->sdc_j + s * SDC_MAXNZ, c->sdc_w + s * SDC_MAXNZ, c->sdc_cnt[s], dt, dst, n);
@@ -2412,9 +2515,13 @@ static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double
   rc = shoot_prepare(c, params, T, nsteps, cols, false);
   c->use_graph = ug;
   if (rc) return rc;
+  // the sweeps' nodes together, except in the pivoted and GMRES forms (one row order,
+  // one Krylov workspace per context) and in a one-stream context
+  const bool grouped = c->overlap && !pivoted(c) && !c->gm_active;
+  if (grouped && (rc = ensure_sdc_groups(c))) return rc;
   const double dt = T / (4.0 * nsteps);
   for (int n = 0; n < nsteps; ++n)
-    if ((rc = enqueue_sdc_step(c, cols, dt))) return rc;
+    if ((rc = enqueue_sdc_step(c, cols, dt, grouped))) return rc;
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
     const std::string msg = g_err;
     (void)hipStreamSynchronize(c->stream);

@@ -30,7 +30,8 @@ raw result yet, in parallel processes, one thread each, then combines.  The full
 Workloads: c1, c2, c3, c4; c5_IIxS, the first S steps of batched instance II (the
 largest grids); c5_II, batched instance II marched to T/4 (instances whose oracle
 run is affordable); c6, the two time segments on non-uniform meshes (the mesh oracle,
-oracle/mesh_oracle.py, with the same FP64 alternates).
+oracle/mesh_oracle.py, with the same FP64 alternates); c4s, C4 marched to T/4 with 12
+steps of SDC15 (the SDC oracle, oracle/sdc_oracle.py, with the same FP64 alternates).
 """
 import os
 import subprocess
@@ -45,6 +46,7 @@ RAW = os.path.join(HERE, "raw")
 sys.path.insert(0, ROOT)
 
 from oracle import mesh_oracle as MO              # noqa: E402
+from oracle import sdc_oracle as SO               # noqa: E402
 from oracle import ww_oracle as O                 # noqa: E402
 from paper_1210_5672_amd import workloads as W   # noqa: E402
 
@@ -59,7 +61,9 @@ C5_FULL = {"c5_00": 0, "c5_07": 7, "c5_08": 8, "c5_26": 26, "c5_27": 27}
 
 # workloads with a double-double run, and the column split of that run
 DD_SPLIT = {"c1": 1, "c2": 4}
-ALL = ("c1", "c2", "c4", "c3", *C5_FULL, *C5_PREFIX, "c6")
+# workloads marched with SDC15: (base workload, SDC steps to T/4)
+SDC_RUNS = {"c4s": ("c4", 12)}
+ALL = ("c1", "c2", "c4", "c3", *C5_FULL, *C5_PREFIX, "c6", *SDC_RUNS)
 
 
 def workload(name):
@@ -72,6 +76,11 @@ def workload(name):
         w = W.c5()[C5_FULL[name]]
         return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T, w.nsteps, w.params, w.basis, w.q_fixed,
                           description=f"batched instance {C5_FULL[name]} to T/4")
+    if name in SDC_RUNS:
+        base, steps = SDC_RUNS[name]
+        w = W.CONFIGS[base]()
+        return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T, steps, w.params, w.basis, w.q_fixed,
+                          description=f"{base} to T/4 with {steps} SDC15 steps")
     return W.CONFIGS[name]()
 
 
@@ -92,7 +101,11 @@ def run(name, tag, cols=None):
     w = workload(name)
     ar = arith(tag)
     t0 = time.time()
-    if w.segments is not None:
+    if name in SDC_RUNS:
+        if cols is not None or tag == "dd":
+            raise SystemExit("SDC15 runs are FP64 runs of all columns")
+        res = SO.shoot_eval_sdc(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps, ar=ar)
+    elif w.segments is not None:
         if cols is not None:
             raise SystemExit("column splits are for uniform-mesh workloads")
         res = MO.shoot_eval_segments(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.segments, ar=ar)

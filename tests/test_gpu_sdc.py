@@ -74,3 +74,30 @@ def test_sdc_base_only_and_arguments():
     ref = S.shoot_eval_sdc(N, math.inf, 0.0, 1.0, basis, np.zeros(2 * N), p, 2 * math.pi, 2, jacobian=False)
     assert relerr(out["r"].cpu().numpy(), ref["r"]) < TOL
     ctx.close()
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_grouped_sweeps_equal_the_stage_by_stage_form(mixed, monkeypatch):
+    """The nodes of a correction sweep factored in two groups of four on two streams give
+    the same bits as every stage on its own (a context created with WW_NO_OVERLAP=1):
+    the same kernels on the same factors."""
+    ww, torch = _ww()
+    N, M, nsteps, T = 96, 5, 2, 7.0
+    basis = W.cosine_basis(N, M)
+    p = np.linspace(0.03, 0.002, M)
+    outs = []
+    for serial in (False, True):
+        if serial:
+            monkeypatch.setenv("WW_NO_OVERLAP", "1")
+        else:
+            monkeypatch.delenv("WW_NO_OVERLAP", raising=False)
+        ctx = ww.Context(n_max=128, r_max=M + 1, mixed=mixed)
+        ctx.shoot_setup(N, 0.9, 0.002, 1.0, ww.to_dev(basis), ww.to_dev(np.zeros(2 * N)))
+        o = ctx.shoot_eval_sdc(ww.to_dev(p), T * nsteps / 24, nsteps)
+        torch.cuda.synchronize()
+        outs.append({k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in o.items()})
+        assert ctx.fallbacks() == 0
+        ctx.close()
+    for k in ("r", "J", "drdT"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    assert outs[0]["f"] == outs[1]["f"]
