@@ -229,6 +229,61 @@ def run_mesh(reps: int = 2, tuned: bool = True):
     return out
 
 
+def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
+    """SDC15 (shoot_eval_sdc) on C4 (N 512, infinite depth, no tension, 256 parameters)
+    to T/4 in `sdc_steps` steps (113 right-hand-side evaluations each) against the DOP853
+    march of the same workload (800 steps of 12 evaluations), each timed with the
+    Jacobian and without (f-only), and the two marches' differences: r, dr/dT and the
+    Jacobian columns of modes 1..low_modes agree to about 1e-12 (the base march and the
+    low modes are resolved by both step sizes); the higher modes carry SDC's larger
+    time-discretisation error at this step (omega dt up to 2 at mode 256) and are
+    damped by the per-step filter 12 times instead of 800.  With the SDC march's error
+    against the stored SDC oracle run when present."""
+    import torch
+    from paper_1210_5672_amd import workloads as W
+    from paper_1210_5672_amd import ww
+    w = W.c4()
+    ctx = ww.Context(n_max=w.N, r_max=w.M + 1)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    p = ww.to_dev(w.params)
+
+    def timed(fn, n):
+        fn()   # first call: work arrays, factor sets, step graphs
+        torch.cuda.synchronize()
+        each = []
+        for _ in range(n):
+            t0 = time.perf_counter()
+            res = fn()
+            each.append(time.perf_counter() - t0)
+        return res, statistics.median(each)
+
+    sdc, t_sdc = timed(lambda: ctx.shoot_eval_sdc(p, w.T, sdc_steps), reps)
+    fb = ctx.fallbacks()
+    sdc_f, t_sdc_f = timed(lambda: ctx.shoot_eval_sdc(p, w.T, sdc_steps, jacobian=False), reps)
+    rk, t_rk = timed(lambda: ctx.shoot_eval(p, w.T, w.nsteps), 1)
+    rk_f, t_rk_f = timed(lambda: ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False), 1)
+    print("# SDC15 march timed", file=sys.stderr, flush=True)
+    ev = 113 * sdc_steps
+    rel = lambda a, b: float(torch.linalg.norm(a - b) / torch.linalg.norm(b))
+    L = low_modes
+    out = {"workload": f"C4: N={w.N}, h=inf, M={w.M}, to T/4 in {sdc_steps} SDC15 steps ({ev} evaluations) "
+                       f"vs {w.nsteps} DOP853 steps ({12 * w.nsteps})",
+           "with_jacobian": {"sdc_ms": 1e3 * t_sdc, "dop853_ms": 1e3 * t_rk, "speedup": t_rk / t_sdc,
+                             "us_per_evaluation": 1e6 * t_sdc / ev},
+           "f_only": {"sdc_ms": 1e3 * t_sdc_f, "dop853_ms": 1e3 * t_rk_f, "speedup": t_rk_f / t_sdc_f,
+                      "us_per_evaluation": 1e6 * t_sdc_f / ev},
+           "fallbacks": fb,
+           "sdc_vs_dop853": {"r": rel(sdc["r"], rk["r"]), "drdT": rel(sdc["drdT"], rk["drdT"]),
+                             "r_f_only": rel(sdc_f["r"], rk_f["r"]),
+                             f"J_modes_1_{L}": rel(sdc["J"][:, :L], rk["J"][:, :L]),
+                             "J_all_modes": rel(sdc["J"], rk["J"])}}
+    fx = oracle_fixture("c4s")
+    if fx is not None:
+        out["err_vs_oracle"] = err_vs_oracle(sdc, fx)
+    ctx.close()
+    return out
+
+
 def run_dd(reps: int = 3, N: int = 1024, R: int = 129):
     """Double-double DtN (dtn_setup_dd, dtn_solve_multi_dd) on the C3 surface with R
     right-hand sides: set-up time (double-double assembly and FFTs, FP64 LU) and solve
@@ -451,6 +506,7 @@ def main():
     ap.add_argument("--no-tuning", action="store_true", help="ignore the autotuner's cached choices")
     ap.add_argument("--no-mesh", action="store_true", help="skip the segmented non-uniform-mesh march (C6)")
     ap.add_argument("--no-dd", action="store_true", help="skip the double-double DtN timing")
+    ap.add_argument("--no-sdc", action="store_true", help="skip the SDC15 march (C4)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -555,6 +611,8 @@ def main():
         out["mesh"] = run_mesh(tuned=not args.no_tuning)
     if not args.no_dd:
         out["dd"] = run_dd()
+    if not args.no_sdc:
+        out["sdc"] = run_sdc()
     if not args.no_batch:
         out["batch"] = run_batch(tuned=not args.no_tuning)
     if args.copy_probe:

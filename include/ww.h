@@ -209,8 +209,14 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
  * nodes' Lagrange polynomials), and the final integration with the weights of the last
  * node: 113 right-hand-side evaluations per step (every stage on its own factors, the
  * Jacobian columns with the base state of the same stage), the filter after every step.
- * Outputs, fallbacks and errors as shoot_eval.  Synchronises.  Work arrays are
- * allocated at the first call: 113 x 2 n_max r_max doubles of stage slopes.
+ * The scheme is explicit: dt must resolve the largest frequency the filter passes (with
+ * surface tension that is far smaller than DOP853's step).  The eight nodes of each
+ * correction sweep are factored together and the column chains run on a second stream
+ * (results bitwise those of one stream, which a context created with WW_NO_OVERLAP=1
+ * and the pivoted and GMRES forms use).  Outputs, fallbacks and errors as shoot_eval;
+ * a failure's location names the step (its stage field is 0).  Synchronises.  Work
+ * arrays are allocated at the first call: 113 x 2 n_max r_max doubles of stage slopes,
+ * 17 x 2 n_max r_max doubles of stage states, and eight factor sets of n_max^2 size.
  */
 int shoot_eval_sdc(ww_ctx *ctx, const double *params, double T, int nsteps, double *r, double *J,
                    double *drdT, double *f);

@@ -139,6 +139,9 @@ struct ww_ctx {
   // stage-state copy and the base Dirichlet data (SDC_NODES each); the LU stream's event
   double *sdc_yn = nullptr, *sdc_ysn = nullptr, *sdc_rhsn = nullptr;
   hipEvent_t sdc_ev = nullptr;
+  // per lane (SDC_NODES lanes: a factor set of the ring and the per-node buffers above):
+  // the base chain that last used it (main stream), its column chain (column stream)
+  hipEvent_t sdc_evB[SDC_NODES] = {}, sdc_evC[SDC_NODES] = {};
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -521,6 +524,10 @@ void ww_destroy(ww_ctx* c) {
   if (c->pgendc) (void)hipGraphExecDestroy(c->pgendc);
   if (c->evE) (void)hipEventDestroy(c->evE);
   if (c->sdc_ev) (void)hipEventDestroy(c->sdc_ev);
+  for (int i = 0; i < SDC_NODES; ++i) {
+    if (c->sdc_evB[i]) (void)hipEventDestroy(c->sdc_evB[i]);
+    if (c->sdc_evC[i]) (void)hipEventDestroy(c->sdc_evC[i]);
+  }
   for (hipEvent_t e : c->kev_a) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->kev_b) (void)hipEventDestroy(e);
   if (c->stamps) (void)hipFree(c->stamps);
@@ -2373,89 +2380,158 @@ static int ensure_sdc(ww_ctx* c) {
   return dalloc(c, (void**)&c->sdc_K, (size_t)SDC_STAGES * st * 8);
 }
 
-// the factor sets and the LU stream of the grouped sweeps (first use)
+// the factor sets, the LU and column streams and the lane events of the two-stream form
+// (first use)
 static int ensure_sdc_groups(ww_ctx* c) {
   if (!c->lus[0]) HIPCHK(hipStreamCreateWithFlags(&c->lus[0], hipStreamNonBlocking));
+  if (!c->side) HIPCHK(hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking));
   if (!c->sdc_ev) HIPCHK(hipEventCreateWithFlags(&c->sdc_ev, hipEventDisableTiming));
+  for (int i = 0; i < SDC_NODES; ++i) {
+    if (!c->sdc_evB[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evB[i], hipEventDisableTiming));
+    if (!c->sdc_evC[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evC[i], hipEventDisableTiming));
+  }
   return ensure_ring(c, SDC_NODES);
 }
 
-// The nodes of one correction sweep (stages s0 .. s0 + SDC_NODES - 1) read only slopes
-// of earlier sweeps, so they are evaluated together: every node's state, spectral prep
-// and assembly into its own factor set, the LUs in two groups of four (the second
-// group on the LU stream, beside the first group and its chains), then every node's
-// base and column chains on its own factors.  The kernels and factors are those of the
-// stage-by-stage form, so the results are the same bit for bit.
-static int enqueue_sdc_sweep(ww_ctx* c, bool cols, double dt, int s0) {
-  static_assert(SDC_NODES == 2 * BLU_GMAX, "a sweep is factored in two groups");
-  int rc;
-  const size_t ks = kstride(c), n = (size_t)2 * c->N * (cols ? c->M + 1 : 1);
-  const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+// The two-stream form of an SDC15 step.  Stage s runs in lane q (predictor stages
+// s mod SDC_NODES, the nodes of a sweep their node index): the lane's factor set of the
+// ring, stage state, stage-state copy and base Dirichlet data.  The main stream forms
+// the base column of the stage state, the spectral prep, the assembly, the LU and the
+// base chain; the column stream then forms the Jacobian columns of the stage state and
+// runs the column chain, overlapping the next stages' base chains and LUs.  A lane is
+// taken again only after its column chain has ended.  The nodes of a correction sweep
+// read only slopes of earlier sweeps: they are assembled together and factored in two
+// groups of four, the second on the LU stream.  Per element the kernels and their order
+// are those of the one-stream form, so the results are the same bit for bit.
+struct SdcStep {
+  ww_ctx* c;
+  bool cols;
+  double dt;
+  size_t ks;
   Fac F[SDC_NODES];
-  for (int m = 0; m < SDC_NODES; ++m) {
-    F[m] = pipe_set(c, m, false);
-    F[m].lag32 = false;
-    F[m].Gm = nullptr;   // the chains read Gm row-major only
+  int lastq = -1;   // lane of the last column chain
+
+  SdcStep(ww_ctx* cc, bool cl, double d) : c(cc), cols(cl), dt(d), ks(kstride(cc)) {
+    for (int m = 0; m < SDC_NODES; ++m) {
+      F[m] = pipe_set(c, m, false);
+      F[m].lag32 = false;
+      F[m].Gm = nullptr;   // the chains read Gm row-major only
+    }
   }
-  const hipStream_t main = c->stream, ls = c->lus[0];
-  auto prep = [&](int m) -> int {
-    double* ym = c->sdc_yn + m * ks;
-    hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y, c->sdc_K, ks,
-                       c->sdc_j + (s0 + m) * SDC_MAXNZ, c->sdc_w + (s0 + m) * SDC_MAXNZ, c->sdc_cnt[s0 + m], dt, ym,
-                       n);
+  double* yn(int q) const { return c->sdc_yn + q * ks; }
+  double* ysn(int q) const { return c->sdc_ysn + q * ks; }
+  double* rhsn(int q) const { return c->sdc_rhsn + (size_t)q * c->Np; }
+
+  // combination of row s into lane q: the base column (part 0) or the Jacobian columns
+  int combine(int s, int q, bool colpart) {
+    const size_t off = colpart ? (size_t)2 * c->N : 0;
+    const size_t n = (size_t)2 * c->N * (colpart ? c->M : 1);
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y + off, c->sdc_K + off, ks,
+                       c->sdc_j + s * SDC_MAXNZ, c->sdc_w + s * SDC_MAXNZ, c->sdc_cnt[s], dt, yn(q) + off, n);
     LAUNCHCHK();
-    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ym, c->K,
-                       c->sdc_ysn + m * ks, c->coef, 0, ks, F[m].aux, c->n_max, c->sdc_rhsn + (size_t)m * c->Np,
-                       c->Np, c->tw, c->N, c->hsurf, c->status);
+    return 0;
+  }
+  // main stream: the lane is free, the stage state's base column, prep, assembly
+  int front(int s, int q) {
+    int rc;
+    HIPCHK(hipStreamWaitEvent(c->stream, c->sdc_evC[q], 0));
+    if ((rc = combine(s, q, false))) return rc;
+    hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, yn(q), c->K, ysn(q),
+                       c->coef, 0, ks, F[q].aux, c->n_max, rhsn(q), c->Np, c->tw, c->N, c->hsurf, c->status);
     LAUNCHCHK();
-    return enqueue_assemble(c, F[m], false);
-  };
-  auto chain = [&](int m) -> int {
-    double* ym = c->sdc_yn + m * ks;
-    double* ysm = c->sdc_ysn + m * ks;
-    double* kout = c->sdc_K + (size_t)(s0 + m) * ks;
-    int e;
-    if ((e = enqueue_dtn_cols(c, F[m], c->sdc_rhsn + (size_t)m * c->Np, c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0,
-                              c->rr0, 1)))
-      return e;
-    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysm, c->gphi0, F[m].aux,
-                       c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
-                       c->tau);
+    return enqueue_assemble(c, F[q], false);
+  }
+  // main stream: the base solve and right-hand side (slot s), then the column chain on
+  // the column stream
+  int chains(int s, int q) {
+    int rc;
+    double* kout = c->sdc_K + (size_t)s * ks;
+    if ((rc = enqueue_dtn_cols(c, F[q], rhsn(q), c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysn(q), c->gphi0,
+                       F[q].aux, c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N,
+                       c->g, c->tau);
     LAUNCHCHK();
     if (!cols) return 0;
+    HIPCHK(hipEventRecord(c->sdc_evB[q], c->stream));
+    const hipStream_t main = c->stream;
+    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evB[q], 0));
+    c->stream = c->side;
+    rc = col_chain(s, q, kout);
+    c->stream = main;
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(c->sdc_evC[q], c->side));
+    lastq = q;
+    return 0;
+  }
+  int col_chain(int s, int q, double* kout) {
+    int rc;
+    if ((rc = combine(s, q, true))) return rc;
     const int M = c->M;
     const size_t tot = (size_t)c->Np * M;
     const int cb = (int)std::min<size_t>((tot + 255) / 256, 4096);
-    hipLaunchKernelGGL(k_col_pre, dim3(cb), dim3(256), 0, c->stream, ym, c->K, ysm, c->coef, 0, ks, F[m].aux,
+    hipLaunchKernelGGL(k_col_pre, dim3(cb), dim3(256), 0, c->stream, yn(q), c->K, ysn(q), c->coef, 0, ks, F[q].aux,
                        c->n_max, c->Psi, c->Np, c->N, M);
     LAUNCHCHK();
-    if ((e = enqueue_dtn_cols(c, F[m], c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return e;
-    hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysm, c->Gpsi, c->Np,
-                       F[m].aux, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+    if ((rc = enqueue_dtn_cols(c, F[q], c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
+    hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysn(q), c->Gpsi, c->Np,
+                       F[q].aux, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
     LAUNCHCHK();
     return 0;
-  };
-  const int G = BLU_GMAX;
-  // the second group first, so that its LU runs beside the first group's work
-  for (int m = G; m < SDC_NODES; ++m)
-    if ((rc = prep(m))) return rc;
-  HIPCHK(hipEventRecord(c->sdc_ev, main));
-  HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
-  c->stream = ls;
-  rc = enqueue_lu_group(c, F + G, G);
-  c->stream = main;
-  if (rc) return rc;
-  HIPCHK(hipEventRecord(c->sdc_ev, ls));
-  for (int m = 0; m < G; ++m)
-    if ((rc = prep(m))) return rc;
-  if ((rc = enqueue_lu_group(c, F, G))) return rc;
-  for (int m = 0; m < G; ++m)
-    if ((rc = chain(m))) return rc;
-  HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
-  for (int m = G; m < SDC_NODES; ++m)
-    if ((rc = chain(m))) return rc;
-  return 0;
-}
+  }
+  int sweep(int s0) {
+    static_assert(SDC_NODES == 2 * BLU_GMAX, "a sweep is factored in two groups");
+    int rc;
+    const int G = BLU_GMAX;
+    const hipStream_t main = c->stream, ls = c->lus[0];
+    // the second group first, so that its LU runs beside the first group's work
+    for (int m = G; m < SDC_NODES; ++m)
+      if ((rc = front(s0 + m, m))) return rc;
+    HIPCHK(hipEventRecord(c->sdc_ev, main));
+    HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
+    c->stream = ls;
+    rc = enqueue_lu_group(c, F + G, G);
+    c->stream = main;
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(c->sdc_ev, ls));
+    for (int m = 0; m < G; ++m)
+      if ((rc = front(s0 + m, m))) return rc;
+    if ((rc = enqueue_lu_group(c, F, G))) return rc;
+    for (int m = 0; m < G; ++m)
+      if ((rc = chains(s0 + m, m))) return rc;
+    HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
+    for (int m = G; m < SDC_NODES; ++m)
+      if ((rc = chains(s0 + m, m))) return rc;
+    return 0;
+  }
+  int step() {
+    int rc;
+    for (int s = 0; s < SDC_STAGES;) {
+      if (s >= SDC_FIRST_SWEEP) {
+        if ((rc = sweep(s))) return rc;
+        s += SDC_NODES;
+        continue;
+      }
+      const int q = s % SDC_NODES;
+      if ((rc = front(s, q))) return rc;
+      if ((rc = enqueue_lu(c, F[q]))) return rc;
+      if ((rc = chains(s, q))) return rc;
+      ++s;
+    }
+    // the step's combination in place (after the last column chain) and the filter
+    if (lastq >= 0) HIPCHK(hipStreamWaitEvent(c->stream, c->sdc_evC[lastq], 0));
+    const size_t n = (size_t)2 * c->N * (cols ? c->M + 1 : 1);
+    const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y, c->sdc_K, ks,
+                       c->sdc_j + SDC_STAGES * SDC_MAXNZ, c->sdc_w + SDC_STAGES * SDC_MAXNZ, c->sdc_cnt[SDC_STAGES],
+                       dt, c->y, n);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_step_end, dim3(cols ? c->M + 1 : 1), dim3(WW_NT), fft_lds_bytes(c->N, 3), c->stream, c->y,
+                       c->K, ks, 0, c->coef, c->tw, c->sig, c->N, 0, c->status);
+    LAUNCHCHK();
+    return 0;
+  }
+};
 
 // the column chain of a stage whose state is ysrc (no stage combination), slopes to kout
 static int enqueue_col_chain_at(ww_ctx* c, const double* ysrc, double* kout, const Fac& F) {
@@ -2476,18 +2552,13 @@ static int enqueue_col_chain_at(ww_ctx* c, const double* ysrc, double* kout, con
 // one SDC15 step of dt: every stage's state by k_sdc_combine, its base chain and column
 // chain on the context's stream (each stage on its own factors), then the step's
 // combination in place and the filter
-static int enqueue_sdc_step(ww_ctx* c, bool cols, double dt, bool grouped) {
+static int enqueue_sdc_step(ww_ctx* c, bool cols, double dt) {
   int rc;
   const size_t ks = kstride(c);
   const size_t n = (size_t)2 * c->N * (cols ? c->M + 1 : 1);
   const int blocks = (int)std::min<size_t>((n + 255) / 256, 4096);
   const Fac F = fac_default(c);
   for (int s = 0; s <= SDC_STAGES; ++s) {
-    if (grouped && s >= SDC_FIRST_SWEEP && s < SDC_STAGES) {
-      if ((rc = enqueue_sdc_sweep(c, cols, dt, s))) return rc;
-      s += SDC_NODES - 1;
-      continue;
-    }
     double* dst = s < SDC_STAGES ? c->sdc_y : c->y;
     hipLaunchKernelGGL(k_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->y, c->sdc_K, ks,
                        c->sdc_j + s * SDC_MAXNZ, c->sdc_w + s * SDC_MAXNZ, c->sdc_cnt[s], dt, dst, n);
@@ -2515,13 +2586,22 @@ static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double
   rc = shoot_prepare(c, params, T, nsteps, cols, false);
   c->use_graph = ug;
   if (rc) return rc;
-  // the sweeps' nodes together, except in the pivoted and GMRES forms (one row order,
-  // one Krylov workspace per context) and in a one-stream context
-  const bool grouped = c->overlap && !pivoted(c) && !c->gm_active;
-  if (grouped && (rc = ensure_sdc_groups(c))) return rc;
+  // the two-stream form, except in the pivoted and GMRES forms (one row order, one
+  // Krylov workspace per context) and in a one-stream context
+  const bool two = c->overlap && !pivoted(c) && !c->gm_active;
+  if (two && (rc = ensure_sdc_groups(c))) return rc;
   const double dt = T / (4.0 * nsteps);
-  for (int n = 0; n < nsteps; ++n)
-    if ((rc = enqueue_sdc_step(c, cols, dt, grouped))) return rc;
+  if (two) {
+    // every lane starts free
+    for (int q = 0; q < SDC_NODES; ++q) HIPCHK(hipEventRecord(c->sdc_evC[q], c->stream));
+    for (int n = 0; n < nsteps; ++n) {
+      SdcStep st(c, cols, dt);
+      if ((rc = st.step())) return rc;
+    }
+  } else {
+    for (int n = 0; n < nsteps; ++n)
+      if ((rc = enqueue_sdc_step(c, cols, dt))) return rc;
+  }
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
     const std::string msg = g_err;
     (void)hipStreamSynchronize(c->stream);

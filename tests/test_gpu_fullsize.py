@@ -48,6 +48,8 @@ TOL = 1e-12
 C5_PREFIX = {"c5_16x3": (16, 3), "c5_02x3": (2, 3)}
 # batched instances marched to T/4 with full oracle runs
 C5_FULL = {"c5_00": 0, "c5_07": 7, "c5_08": 8, "c5_26": 26, "c5_27": 27}
+# workloads marched with SDC15: (base workload, SDC steps to T/4)
+SDC_RUNS = {"c4s": ("c4", 12)}
 
 
 def _load(name):
@@ -68,6 +70,10 @@ def workload(name):
                           w.q_fixed)
     if name in C5_FULL:
         return W.c5()[C5_FULL[name]]
+    if name in SDC_RUNS:
+        base, steps = SDC_RUNS[name]
+        w = W.CONFIGS[base]()
+        return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T, steps, w.params, w.basis, w.q_fixed)
     return W.CONFIGS[name]()
 
 
@@ -185,6 +191,26 @@ def test_config3_full_mixed_precision():
     w, res, fb = _run("c3", mixed=True)
     check(fx, w, res)
     assert fb == 0, fb
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sdc15_config4_full(mixed):
+    """C4 (N 512, 256 parameters) to T/4 in 12 steps of SDC15 (shoot_eval_sdc, 1356
+    right-hand-side evaluations) against the SDC oracle's stored run, every column, with
+    the same bounds (the floor from the same four alternate roundings of the SDC march)."""
+    import torch
+    fx = _load("c4s")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    print(f"full-size parity c4s (SDC15) mixed={mixed}", flush=True)
+    w = workload("c4s")
+    ctx = ww.Context(n_max=w.N, r_max=w.M + 1, mixed=mixed)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    res = _np(ctx.shoot_eval_sdc(ww.to_dev(w.params), w.T, w.nsteps))
+    assert ctx.fallbacks() == 0, ctx.fallbacks()
+    check(fx, w, res)
+    ctx.close()
 
 
 @pytest.mark.parametrize("mixed", [False, True])

@@ -77,10 +77,11 @@ def test_sdc_base_only_and_arguments():
 
 
 @pytest.mark.parametrize("mixed", [False, True])
-def test_grouped_sweeps_equal_the_stage_by_stage_form(mixed, monkeypatch):
-    """The nodes of a correction sweep factored in two groups of four on two streams give
-    the same bits as every stage on its own (a context created with WW_NO_OVERLAP=1):
-    the same kernels on the same factors."""
+def test_two_stream_form_equals_the_one_stream_form(mixed, monkeypatch):
+    """The two-stream form (column chains on the column stream beside the next stages'
+    base chains; the nodes of a correction sweep factored in two groups of four, one on
+    the LU stream) gives the same bits as every stage in turn on one stream (a context
+    created with WW_NO_OVERLAP=1): the same kernels on the same factors."""
     ww, torch = _ww()
     N, M, nsteps, T = 96, 5, 2, 7.0
     basis = W.cosine_basis(N, M)
