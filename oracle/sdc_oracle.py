@@ -60,9 +60,36 @@ def integration_matrix(c: np.ndarray) -> np.ndarray:
     return S
 
 
+def nodes_and_matrix_mp(dps: int = 40):
+    """The Radau IIa nodes and the integration matrix in mpmath at `dps` digits: the
+    nodes by Newton's method on P_8(x) - P_7(x) from the double-precision roots, S_mj by
+    mpmath's quadrature of the Lagrange polynomial of node j over [0, c_m]."""
+    import mpmath
+    c0 = radau_iia_nodes()
+    with mpmath.workdps(dps):
+        f = lambda x: mpmath.legendre(NODES, x) - mpmath.legendre(NODES - 1, x)
+        c = [(mpmath.findroot(f, mpmath.mpf(2 * ci - 1)) + 1) / 2 for ci in c0[:-1]] + [mpmath.mpf(1)]
+
+        def ell(j):
+            return lambda t: mpmath.fprod((t - c[k]) / (c[j] - c[k]) for k in range(NODES) if k != j)
+
+        S = [[mpmath.quad(ell(j), [0, c[m]]) for j in range(NODES)] for m in range(NODES)]
+        return c, S
+
+
+def nodes_and_matrix_dd():
+    """The nodes and the integration matrix as double-double scalars (the march in
+    double-double needs its weights to about 32 digits)."""
+    from . import dd as D
+    c, S = nodes_and_matrix_mp()
+    return [D.from_mp(v) for v in c], [[D.from_mp(v) for v in row] for row in S]
+
+
 def sdc_step(y, F, dt, c=None, S=None, sweeps=SWEEPS):
     """One SDC15 step of y' = F(y) for a state given as a list of arrays (None entries
-    pass through); returns the new state (unfiltered)."""
+    pass through); returns the new state (unfiltered).  c, S: the nodes and the
+    integration matrix (numpy, or lists of double-double scalars for a double-double
+    march)."""
     c = radau_iia_nodes() if c is None else c
     S = integration_matrix(c) if S is None else S
     add = lambda a, b, s: [ai + s * bi if ai is not None else None for ai, bi in zip(a, b)]
@@ -84,13 +111,13 @@ def sdc_step(y, F, dt, c=None, S=None, sweeps=SWEEPS):
         for m in range(len(c)):
             acc = list(y)
             for j in range(len(c)):
-                acc = add(acc, FY[j], dt * S[m, j])
+                acc = add(acc, FY[j], dt * S[m][j])
             newY.append(acc)
         Y = newY
     FY = [F(Ym) for Ym in Y]
     out = list(y)
     for j in range(len(c)):
-        out = add(out, FY[j], dt * S[-1, j])
+        out = add(out, FY[j], dt * S[-1][j])
     return out
 
 
@@ -121,3 +148,25 @@ def shoot_eval_sdc(N, h, tau, g, basis, q_fixed, params, T, nsteps, jacobian=Tru
     r = w * phi
     return dict(r=r, J=(w * Qp) if jacobian else None, drdT=w * phi_t / 4, f=math.fsum(r * r) / 2,
                 eta=eta, phi=phi)
+
+
+def shoot_eval_sdc_dd(N, h, tau, g, eta0, phi0, T, nsteps, sweeps=SWEEPS):
+    """The base march (no Jacobian) in double-double with SDC15 (the paper's quadruple-
+    precision workflow, Sec. 2.2): eta0, phi0 and T double-doubles (oracle.dd.DD), the
+    right-hand sides, filter and step in double-double, the nodes and weights to about
+    32 digits.  Returns r, dr/dT, f (double-double) as shoot_eval_sdc."""
+    from . import dd as D
+    ar = D.DDArith()
+    c, S = nodes_and_matrix_dd()
+    T = D._dd(T)
+    dt = T / (4 * nsteps)
+    F = lambda y: list(O.rhs(y[0], y[1], None, None, h, tau, g, ar))[:2] + [None, None]
+    y = [D._dd(eta0), D._dd(phi0), None, None]
+    for _ in range(nsteps):
+        y = sdc_step(y, F, dt, c, S, sweeps)
+        y = [O.filt(v, ar) if v is not None else None for v in y]
+    eta, phi = y[0], y[1]
+    w = 1 / D.sqrt(D.DD(float(N)))
+    _, phi_t, _, _ = O.rhs(eta, phi, None, None, h, tau, g, ar)
+    r = w * phi
+    return dict(r=r, drdT=w * phi_t / 4, f=D.dd_sum(r * r) / 2, eta=eta, phi=phi)
