@@ -222,6 +222,29 @@ int shoot_eval_sdc(ww_ctx *ctx, const double *params, double T, int nsteps, doub
                    double *drdT, double *f);
 
 /*
+ * shoot_eval_sdc_dd: the base march (no Jacobian) in double-double with SDC15, the
+ * march of the quadruple-precision workflow (Sec. 2.2 on SDC and quadruple precision,
+ * Sec. 3.3): every stage state, right-hand side of eq. (ww) (velocities of eq.
+ * (uv:from:G), tension, zero-mean projection), the filter of eq. (filter) and the step's
+ * combinations in double-double (about 32 digits), the nodes and weights to the same
+ * precision; the DtN of each stage is dtn_setup_dd / dtn_solve_multi_dd (double-double
+ * assembly and residuals, refinement from FP64 factors).  Its own grid: N a power of
+ * two, 16 <= N <= min(n_max, 1024); depth h (INFINITY for infinite depth), tension tau,
+ * gravity g.  q0_hi, q0_lo: the initial state [eta | phi], 2N doubles each on the
+ * device (q0_lo may be NULL for zero).  T = T_hi + T_lo, the full period (the march
+ * runs nsteps steps of T / (4 nsteps) to T/4).  Outputs (device): r = phi(T/4)/sqrt(N)
+ * as r_hi + r_lo (N each), dr/dT likewise (drdT_hi and drdT_lo both NULL to skip it;
+ * it costs one more right-hand side); f (host, 2 doubles: hi, lo) = r.r/2.  Errors:
+ * WW_EINVAL (arguments), WW_EDOMAIN (a stage surface through the bottom), WW_EPIVOT,
+ * WW_EREFINE (a stage's solve misses its 2^-96 residual test), WW_ENONFINITE.
+ * Synchronises (three times per stage).  Replaces the context's FP64 DtN factors and
+ * grid (call dtn_setup or shoot_setup again before their entry points).
+ */
+int shoot_eval_sdc_dd(ww_ctx *ctx, int N, double h, double tau, double g, const double *q0_hi,
+                      const double *q0_lo, double T_hi, double T_lo, int nsteps, double *r_hi,
+                      double *r_lo, double *drdT_hi, double *drdT_lo, double *f);
+
+/*
  * Double-double DtN (the GPU part of the quadruple-precision workflow: Sec. 2.2 on
  * quadruple precision, Sec. 3.3; residuals in extended precision by matrix products,
  * corrections from double-precision factors).  Values are unevaluated sums hi + lo of two

@@ -142,6 +142,15 @@ struct ww_ctx {
   // per lane (SDC_NODES lanes: a factor set of the ring and the per-node buffers above):
   // the base chain that last used it (main stream), its column chain (column stream)
   hipEvent_t sdc_evB[SDC_NODES] = {}, sdc_evC[SDC_NODES] = {};
+  // the base march in double-double (shoot_eval_sdc_dd), allocated at first use: state
+  // and stage state (2 n_max, hi and lo), the slopes (SDC_STAGES + 1 slots: the last
+  // for the right-hand side at the final state), G phi, the filter symbol, the sparse
+  // stage rows with double-double weights, f
+  double *sdd_yh = nullptr, *sdd_yl = nullptr, *sdd_Yh = nullptr, *sdd_Yl = nullptr;
+  double *sdd_Kh = nullptr, *sdd_Kl = nullptr, *sdd_Gh = nullptr, *sdd_Gl = nullptr;
+  double *sdd_fh = nullptr, *sdd_fl = nullptr, *sdd_wh = nullptr, *sdd_wl = nullptr, *sdd_fo = nullptr;
+  int* sdd_j = nullptr;
+  int sdd_cnt[SDC_STAGES + 1] = {};
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -2611,6 +2620,170 @@ static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double
   return read_status(c, st, where);
 }
 
+// ----- the base march in double-double (SDC15 of the quadruple-precision workflow) -----
+// P_n and P_{n-1} at x in double-double (three-term recurrence)
+static void legendre_dd(int n, dd x, dd* pn, dd* pn1) {
+  dd p0 = dd_of(1.0), p1 = x;
+  for (int k = 2; k <= n; ++k) {
+    const dd p2 = dd_div_d(dd_sub(dd_mul_d(dd_mul(x, p1), 2.0 * k - 1.0), dd_mul_d(p0, k - 1.0)), (double)k);
+    p0 = p1;
+    p1 = p2;
+  }
+  *pn = p1;
+  *pn1 = p0;
+}
+
+// The Radau IIa nodes and the integration matrix to about 32 digits: the double nodes
+// (and the double Gauss-Legendre rule) refined by Newton steps on the double-double
+// polynomial values, then S_mj = (c_m / 2) sum_q w_q l_j(c_m (x_q + 1) / 2) in
+// double-double
+static void radau_dd(dd* c, dd S[SDC_NODES][SDC_NODES]) {
+  double c0[SDC_NODES];
+  radau_nodes(c0);
+  for (int m = 0; m < SDC_NODES - 1; ++m) {
+    dd x = dd_of(2.0 * c0[m] - 1.0);
+    for (int it = 0; it < 3; ++it) {
+      dd p8, p7;
+      legendre_dd(SDC_NODES, x, &p8, &p7);
+      double a, b, da, db;
+      legendre(SDC_NODES, x.hi, &a, &da);
+      legendre(SDC_NODES - 1, x.hi, &b, &db);
+      x = dd_add_d(x, -dd_sub(p8, p7).hi / (da - db));
+    }
+    c[m] = dd_mul_d(dd_add_d(x, 1.0), 0.5);
+  }
+  c[SDC_NODES - 1] = dd_of(1.0);
+  const int ng = 16;
+  dd xg[ng], wg[ng];
+  for (int i = 0; i < ng; ++i) {
+    double x0 = std::cos(M_PI * (i + 0.75) / (ng + 0.5));
+    for (int it = 0; it < 100; ++it) {
+      double p, dp;
+      legendre(ng, x0, &p, &dp);
+      const double dx = p / dp;
+      x0 -= dx;
+      if (std::fabs(dx) < 1e-17) break;
+    }
+    dd x = dd_of(x0), pn, pn1;
+    for (int it = 0; it < 3; ++it) {
+      legendre_dd(ng, x, &pn, &pn1);
+      double p, dp;
+      legendre(ng, x.hi, &p, &dp);
+      x = dd_add_d(x, -pn.hi / dp);
+    }
+    legendre_dd(ng, x, &pn, &pn1);
+    const dd x2m1 = dd_add_d(dd_mul(x, x), -1.0);   // x^2 - 1
+    const dd dp = dd_div(dd_mul_d(dd_sub(dd_mul(x, pn), pn1), (double)ng), x2m1);
+    xg[i] = x;
+    wg[i] = dd_div(dd_of(2.0), dd_mul(dd_neg(x2m1), dd_mul(dp, dp)));   // 2 / ((1 - x^2) P'^2)
+  }
+  for (int m = 0; m < SDC_NODES; ++m)
+    for (int j = 0; j < SDC_NODES; ++j) {
+      dd acc = dd_of(0.0);
+      for (int q = 0; q < ng; ++q) {
+        const dd x = dd_mul(dd_mul_d(c[m], 0.5), dd_add_d(xg[q], 1.0));
+        dd ell = dd_of(1.0);
+        for (int k = 0; k < SDC_NODES; ++k)
+          if (k != j) ell = dd_mul(ell, dd_div(dd_sub(x, c[k]), dd_sub(c[j], c[k])));
+        acc = dd_add(acc, dd_mul(wg[q], ell));
+      }
+      S[m][j] = dd_mul(dd_mul_d(c[m], 0.5), acc);
+    }
+}
+
+// The stage rows of sdc_rows with double-double weights, each times dt
+static void sdc_rows_dd(dd dt, int* cnt, int (*jt)[SDC_MAXNZ], double (*wh)[SDC_MAXNZ], double (*wl)[SDC_MAXNZ]) {
+  dd c[SDC_NODES], S[SDC_NODES][SDC_NODES];
+  radau_dd(c, S);
+  const dd zero = dd_of(0.0);
+  std::vector<dd> cur(SDC_STAGES, zero);
+  auto put = [&](int row, const std::vector<dd>& v) {
+    int n = 0;
+    for (int j = 0; j < SDC_STAGES; ++j)
+      if (v[j].hi != 0.0) {
+        const dd w = dd_mul(v[j], dt);
+        jt[row][n] = j;
+        wh[row][n] = w.hi;
+        wl[row][n] = w.lo;
+        ++n;
+      }
+    cnt[row] = n;
+  };
+  int slot = 0;
+  dd t = zero;
+  int fnode[SDC_NODES];
+  for (int m = 0; m < SDC_NODES; ++m) {
+    const dd h = dd_sub(c[m], t);
+    const dd h2 = dd_mul_d(h, 0.5), h3 = dd_div_d(h, 3.0), h6 = dd_div_d(h, 6.0);
+    const int s1 = slot++, s2 = slot++, s3 = slot++, s4 = slot++;
+    std::vector<dd> v = cur;
+    put(s1, v);
+    v = cur;
+    v[s1] = dd_add(v[s1], h2);
+    put(s2, v);
+    v = cur;
+    v[s2] = dd_add(v[s2], h2);
+    put(s3, v);
+    v = cur;
+    v[s3] = dd_add(v[s3], h);
+    put(s4, v);
+    cur[s1] = dd_add(cur[s1], h6);
+    cur[s2] = dd_add(cur[s2], h3);
+    cur[s3] = dd_add(cur[s3], h3);
+    cur[s4] = dd_add(cur[s4], h6);
+    if (m > 0) fnode[m - 1] = s1;
+    t = c[m];
+  }
+  fnode[SDC_NODES - 1] = slot;
+  put(slot++, cur);
+  for (int k = 0; k < SDC_SWEEPS; ++k) {
+    int nf[SDC_NODES];
+    for (int m = 0; m < SDC_NODES; ++m) {
+      std::vector<dd> v(SDC_STAGES, zero);
+      for (int j = 0; j < SDC_NODES; ++j) v[fnode[j]] = dd_add(v[fnode[j]], S[m][j]);
+      nf[m] = slot;
+      put(slot++, v);
+    }
+    for (int m = 0; m < SDC_NODES; ++m) fnode[m] = nf[m];
+  }
+  std::vector<dd> v(SDC_STAGES, zero);
+  for (int j = 0; j < SDC_NODES; ++j) v[fnode[j]] = dd_add(v[fnode[j]], S[SDC_NODES - 1][j]);
+  put(SDC_STAGES, v);
+}
+
+static int ensure_sdc_dd(ww_ctx* c) {
+  if (c->sdd_fo) return 0;
+  int rc;
+  const size_t n2 = (size_t)2 * c->n_max, nm = c->n_max, rows = (size_t)(SDC_STAGES + 1) * SDC_MAXNZ;
+  double** st[] = {&c->sdd_yh, &c->sdd_yl, &c->sdd_Yh, &c->sdd_Yl};
+  for (double** q : st)
+    if (!*q && (rc = dalloc(c, (void**)q, n2 * 8))) return rc;
+  double** sl[] = {&c->sdd_Kh, &c->sdd_Kl};
+  for (double** q : sl)
+    if (!*q && (rc = dalloc(c, (void**)q, (SDC_STAGES + 1) * n2 * 8))) return rc;
+  double** pt[] = {&c->sdd_Gh, &c->sdd_Gl, &c->sdd_fh, &c->sdd_fl};
+  for (double** q : pt)
+    if (!*q && (rc = dalloc(c, (void**)q, nm * 8))) return rc;
+  double** wr[] = {&c->sdd_wh, &c->sdd_wl};
+  for (double** q : wr)
+    if (!*q && (rc = dalloc(c, (void**)q, rows * 8))) return rc;
+  if (!c->sdd_j && (rc = dalloc(c, (void**)&c->sdd_j, rows * sizeof(int)))) return rc;
+  return dalloc(c, (void**)&c->sdd_fo, 64);   // last: its presence marks the set-up as complete
+}
+
+// the base right-hand side in double-double at the state (yh, yl) into (kh, kl)
+static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double h, double tau, double g, double* kh,
+                  double* kl) {
+  int rc;
+  const int N = c->N;
+  if ((rc = dtn_setup_dd(c, yh, yl, h, N))) return rc;
+  if ((rc = dtn_solve_multi_dd(c, yh + N, yl + N, 1, c->sdd_Gh, c->sdd_Gl, nullptr, nullptr))) return rc;
+  hipLaunchKernelGGL(k_dd_base_rhs, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, yh, yl, c->sdd_Gh, c->sdd_Gl,
+                     c->sdd_fh, c->sdd_fl, c->dd_tw, N, g, tau, kh, kl);
+  LAUNCHCHK();
+  return 0;
+}
+
 extern "C" {
 
 int shoot_eval(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
@@ -2637,6 +2810,73 @@ int shoot_eval_sdc(ww_ctx* c, const double* params, double T, int nsteps, double
     }
     c->fb |= nf;
   }
+}
+
+int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const double* q0_hi, const double* q0_lo,
+                      double T_hi, double T_lo, int nsteps, double* r_hi, double* r_lo, double* drdT_hi,
+                      double* drdT_lo, double* f) {
+  if (!c || !q0_hi || !r_hi || !r_lo || !f || (!drdT_hi != !drdT_lo)) return fail(WW_EINVAL, "null argument");
+  if (N < 16 || (N & (N - 1)) || N > c->n_max || N > 1024)
+    return fail(WW_EINVAL, "double-double march: N must be a power of two, 16 <= N <= min(n_max, 1024)");
+  if (nsteps < 1 || !std::isfinite(T_hi) || !std::isfinite(T_lo) || !std::isfinite(g) || !(tau >= 0.0) ||
+      !std::isfinite(tau) || !(h > 0.0))
+    return fail(WW_EINVAL, "nsteps >= 1, finite T and g, finite tau >= 0 and h > 0 required");
+  if (int rj = pipe_join(c)) return rj;
+  int rc;
+  if ((rc = set_grid(c, N, h))) return rc;
+  if ((rc = ensure_dd(c))) return rc;
+  if ((rc = dd_tables(c, N))) return rc;
+  if ((rc = ensure_sdc_dd(c))) return rc;
+  // the stage rows with this call's dt, the filter symbol, the initial state
+  {
+    const int rows = SDC_STAGES + 1;
+    std::vector<int> jt((size_t)rows * SDC_MAXNZ, 0), cnt(rows, 0);
+    std::vector<double> wh((size_t)rows * SDC_MAXNZ, 0.0), wl((size_t)rows * SDC_MAXNZ, 0.0);
+    const dd dt = dd_div_d(dd_two_sum(T_hi, T_lo), 4.0 * nsteps);
+    sdc_rows_dd(dt, cnt.data(), reinterpret_cast<int(*)[SDC_MAXNZ]>(jt.data()),
+                reinterpret_cast<double(*)[SDC_MAXNZ]>(wh.data()), reinterpret_cast<double(*)[SDC_MAXNZ]>(wl.data()));
+    HIPCHK(hipStreamSynchronize(c->stream));   // queued work of an earlier call may still read the rows
+    HIPCHK(hipMemcpy(c->sdd_j, jt.data(), jt.size() * sizeof(int), hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->sdd_wh, wh.data(), wh.size() * 8, hipMemcpyHostToDevice));
+    HIPCHK(hipMemcpy(c->sdd_wl, wl.data(), wl.size() * 8, hipMemcpyHostToDevice));
+    for (int q = 0; q < rows; ++q) c->sdd_cnt[q] = cnt[q];
+  }
+  hipLaunchKernelGGL(k_dd_filter_tab, dim3((N / 2 + 256) / 256), dim3(256), 0, c->stream, N, c->sdd_fh, c->sdd_fl);
+  LAUNCHCHK();
+  const size_t n2 = (size_t)2 * N;
+  HIPCHK(hipMemcpyAsync(c->sdd_yh, q0_hi, n2 * 8, hipMemcpyDeviceToDevice, c->stream));
+  if (q0_lo)
+    HIPCHK(hipMemcpyAsync(c->sdd_yl, q0_lo, n2 * 8, hipMemcpyDeviceToDevice, c->stream));
+  else
+    HIPCHK(hipMemsetAsync(c->sdd_yl, 0, n2 * 8, c->stream));
+  const int blocks = (int)std::min<size_t>((n2 + 255) / 256, 4096);
+  auto combine = [&](int row, double* oh, double* ol) -> int {
+    hipLaunchKernelGGL(k_dd_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->sdd_yh, c->sdd_yl, c->sdd_Kh,
+                       c->sdd_Kl, n2, c->sdd_j + row * SDC_MAXNZ, c->sdd_wh + row * SDC_MAXNZ,
+                       c->sdd_wl + row * SDC_MAXNZ, c->sdd_cnt[row], oh, ol, n2);
+    LAUNCHCHK();
+    return 0;
+  };
+  for (int n = 0; n < nsteps; ++n) {
+    for (int s = 0; s < SDC_STAGES; ++s) {
+      if ((rc = combine(s, c->sdd_Yh, c->sdd_Yl))) return rc;
+      if ((rc = dd_rhs(c, c->sdd_Yh, c->sdd_Yl, h, tau, g, c->sdd_Kh + s * n2, c->sdd_Kl + s * n2))) return rc;
+    }
+    if ((rc = combine(SDC_STAGES, c->sdd_yh, c->sdd_yl))) return rc;
+    hipLaunchKernelGGL(k_dd_filter_state, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, c->sdd_yh, c->sdd_yl,
+                       c->sdd_fh, c->sdd_fl, c->dd_tw, N);
+    LAUNCHCHK();
+  }
+  // the right-hand side at the final state (dr/dT), then the outputs
+  double* kfh = c->sdd_Kh + SDC_STAGES * n2;
+  double* kfl = c->sdd_Kl + SDC_STAGES * n2;
+  if (drdT_hi && (rc = dd_rhs(c, c->sdd_yh, c->sdd_yl, h, tau, g, kfh, kfl))) return rc;
+  hipLaunchKernelGGL(k_dd_outputs, dim3(1), dim3(WW_NT), 0, c->stream, c->sdd_yh, c->sdd_yl, kfh, kfl, N, r_hi, r_lo,
+                     drdT_hi, drdT_lo, c->sdd_fo);
+  LAUNCHCHK();
+  HIPCHK(hipMemcpyAsync(f, c->sdd_fo, 2 * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return 0;
 }
 
 int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,

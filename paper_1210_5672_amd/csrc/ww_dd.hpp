@@ -392,3 +392,160 @@ __global__ void k_dd_maxabs(const double* __restrict__ r, const double* __restri
   atomicMax(mx, (unsigned long long)__double_as_longlong(mr));
   atomicMax(mx + 1, (unsigned long long)__double_as_longlong(mb));
 }
+
+// =====================================================================================
+// The base march in double-double (SDC15, the quadruple-precision workflow of Sec. 2.2):
+// the right-hand side of eq. (ww) with the velocities of eq. (uv:from:G), the filter of
+// eq. (filter) and the zero-mean projection, stage combinations and the outputs of eq.
+// (f:phi) and (dfdT), every quantity a double-double.  States are 2N values [eta | phi]
+// in hi and lo planes.
+// =====================================================================================
+
+// filter symbol exp(-36 (k / k_max)^36) for k = 0 .. N/2 (k_max = N/2, a power of two:
+// k / k_max is exact; its 36th power by squarings in double-double)
+__global__ void k_dd_filter_tab(int N, double* __restrict__ f_hi, double* __restrict__ f_lo) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k > N / 2) return;
+  const dd x = dd_of((double)k / (double)(N / 2));
+  const dd x2 = dd_mul(x, x), x4 = dd_mul(x2, x2), x8 = dd_mul(x4, x4);
+  const dd x16 = dd_mul(x8, x8), x32 = dd_mul(x16, x16);
+  const dd e = dd_exp(dd_mul_d(dd_mul(x32, x4), -36.0));
+  f_hi[k] = e.hi;
+  f_lo[k] = e.lo;
+}
+
+__device__ inline dd dd_ld(const double* __restrict__ h, const double* __restrict__ l, int i) {
+  return dd{h[i], l[i]};
+}
+__device__ inline void dd_st(double* __restrict__ h, double* __restrict__ l, int i, dd v) {
+  h[i] = v.hi;
+  l[i] = v.lo;
+}
+// the filter symbol of wavenumber index t (0 .. N-1)
+__device__ inline dd dd_filt_at(const double* __restrict__ f_hi, const double* __restrict__ f_lo, int t, int N) {
+  const int k = t <= N / 2 ? t : N - t;
+  return dd{f_hi[k], f_lo[k]};
+}
+
+// out = y0 + sum_t w_t K_{j_t} over n entries (the weights carry dt), double-double, the
+// terms added in increasing t
+__global__ void k_dd_sdc_combine(const double* __restrict__ y0h, const double* __restrict__ y0l,
+                                 const double* __restrict__ Kh, const double* __restrict__ Kl, size_t kstride,
+                                 const int* __restrict__ jt, const double* __restrict__ wh,
+                                 const double* __restrict__ wl, int cnt, double* __restrict__ oh,
+                                 double* __restrict__ ol, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x) {
+    dd acc = dd{y0h[e], y0l[e]};
+    for (int t = 0; t < cnt; ++t) {
+      const size_t o = (size_t)jt[t] * kstride + e;
+      acc = dd_add(acc, dd_mul(dd{wh[t], wl[t]}, dd{Kh[o], Kl[o]}));
+    }
+    oh[e] = acc.hi;
+    ol[e] = acc.lo;
+  }
+}
+
+// The base right-hand side at the state y (one workgroup): eta' and phi' by one packed
+// transform (both real, the multiplier i k is odd), G phi given (double-double DtN);
+//   u = (phi' - eta' G)/(1 + eta'^2),  v = (eta' phi' + G)/(1 + eta'^2),
+//   eta_t = G phi,  phi_t = P[v eta_t - u^2/2 - v^2/2 - g eta + tau d/dx(eta'/sqrt(1 + eta'^2))],
+// both filtered by one packed transform (the filter is even and real; P zeroes the mean
+// of phi_t only: the imaginary part of mode 0).  Dynamic LDS: 3.5 N complex
+// double-doubles.
+__global__ __launch_bounds__(WW_NT) void k_dd_base_rhs(const double* __restrict__ yh, const double* __restrict__ yl,
+                                                       const double* __restrict__ gh, const double* __restrict__ gl,
+                                                       const double* __restrict__ f_hi, const double* __restrict__ f_lo,
+                                                       const cdd* __restrict__ twg, int N, double g, double tau,
+                                                       double* __restrict__ kh, double* __restrict__ kl) {
+  extern __shared__ cdd ldsd[];
+  cdd* Z = ldsd;
+  cdd* W = ldsd + N;
+  cdd* S = ldsd + 2 * N;
+  cdd* tw = ldsd + 3 * N;
+  const dd zero = dd_of(0.0);
+  for (int t = threadIdx.x; t < N / 2; t += WW_NT) tw[t] = twg[t];
+  for (int t = threadIdx.x; t < N; t += WW_NT) Z[t] = cdd{dd_ld(yh, yl, t), dd_ld(yh, yl, N + t)};
+  dd_fft(Z, W, tw, N, -1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) Z[t] = dd_ik(Z[t], t <= N / 2 ? t : t - N, N);
+  dd_fft(Z, W, tw, N, +1);   // Z = eta' + i phi'
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    const dd ex = Z[t].re, ps = Z[t].im, G = dd_ld(gh, gl, t);
+    const dd den = dd_add_d(dd_mul(ex, ex), 1.0);
+    const dd u = dd_div(dd_sub(ps, dd_mul(ex, G)), den);
+    const dd v = dd_div(dd_add(dd_mul(ex, ps), G), den);
+    dd s = dd_sub(dd_mul(v, G), dd_mul_d(dd_add(dd_mul(u, u), dd_mul(v, v)), 0.5));
+    s = dd_sub(s, dd_mul_d(dd_ld(yh, yl, t), g));
+    W[t] = cdd{s, zero};
+    S[t] = cdd{dd_div(ex, dd_sqrt(den)), zero};
+  }
+  dd_fft(S, Z, tw, N, -1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) S[t] = dd_ik(S[t], t <= N / 2 ? t : t - N, N);
+  dd_fft(S, Z, tw, N, +1);   // S.re = d/dx(eta'/sqrt(1 + eta'^2))
+  for (int t = threadIdx.x; t < N; t += WW_NT)
+    Z[t] = cdd{dd_ld(gh, gl, t), dd_add(W[t].re, dd_mul_d(S[t].re, tau))};
+  dd_fft(Z, W, tw, N, -1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    const dd f = dd_filt_at(f_hi, f_lo, t, N);
+    cdd v = cdd{dd_mul(Z[t].re, f), dd_mul(Z[t].im, f)};
+    if (t == 0) v.im = zero;   // P: the mean of phi_t
+    Z[t] = v;
+  }
+  dd_fft(Z, W, tw, N, +1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    dd_st(kh, kl, t, Z[t].re);
+    dd_st(kh, kl, N + t, Z[t].im);
+  }
+}
+
+// the filter on the state after a step (eta and phi packed), in place
+__global__ __launch_bounds__(WW_NT) void k_dd_filter_state(double* __restrict__ yh, double* __restrict__ yl,
+                                                           const double* __restrict__ f_hi,
+                                                           const double* __restrict__ f_lo, const cdd* __restrict__ twg,
+                                                           int N) {
+  extern __shared__ cdd ldsd[];
+  cdd* Z = ldsd;
+  cdd* W = ldsd + N;
+  cdd* tw = ldsd + 3 * N;
+  for (int t = threadIdx.x; t < N / 2; t += WW_NT) tw[t] = twg[t];
+  for (int t = threadIdx.x; t < N; t += WW_NT) Z[t] = cdd{dd_ld(yh, yl, t), dd_ld(yh, yl, N + t)};
+  dd_fft(Z, W, tw, N, -1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    const dd f = dd_filt_at(f_hi, f_lo, t, N);
+    Z[t] = cdd{dd_mul(Z[t].re, f), dd_mul(Z[t].im, f)};
+  }
+  dd_fft(Z, W, tw, N, +1);
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    dd_st(yh, yl, t, Z[t].re);
+    dd_st(yh, yl, N + t, Z[t].im);
+  }
+}
+
+// r = w phi, dr/dT = w phi_t / 4 (phi_t: the phi half of a right-hand side at the final
+// state), f = r.r / 2 with w = 1/sqrt(N); one workgroup, the sum in a fixed order (each
+// thread its strided terms in increasing index, then a tree over the threads)
+__global__ __launch_bounds__(WW_NT) void k_dd_outputs(const double* __restrict__ yh, const double* __restrict__ yl,
+                                                      const double* __restrict__ kh, const double* __restrict__ kl, int N,
+                                                      double* __restrict__ rh, double* __restrict__ rl,
+                                                      double* __restrict__ dh, double* __restrict__ dl,
+                                                      double* __restrict__ fout) {
+  __shared__ dd part[WW_NT];
+  const dd w = dd_div(dd_of(1.0), dd_sqrt(dd_of((double)N)));
+  dd acc = dd_of(0.0);
+  for (int t = threadIdx.x; t < N; t += WW_NT) {
+    const dd r = dd_mul(w, dd_ld(yh, yl, N + t));
+    dd_st(rh, rl, t, r);
+    if (dh) dd_st(dh, dl, t, dd_mul_d(dd_mul(w, dd_ld(kh, kl, N + t)), 0.25));
+    acc = dd_add(acc, dd_mul(r, r));
+  }
+  part[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = WW_NT / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) part[threadIdx.x] = dd_add(part[threadIdx.x], part[threadIdx.x + s]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const dd f = dd_mul_d(part[0], 0.5);
+    fout[0] = f.hi;
+    fout[1] = f.lo;
+  }
+}

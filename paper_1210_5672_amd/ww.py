@@ -80,7 +80,8 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "ww_version", "ww_profile", "ww_profile_read", "shoot_eval_batch", "ww_fallbacks",
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
            "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning",
-           "shoot_eval_segments", "dtn_setup_dd", "dtn_solve_multi_dd", "shoot_eval_sdc"]
+           "shoot_eval_segments", "dtn_setup_dd", "dtn_solve_multi_dd", "shoot_eval_sdc",
+           "shoot_eval_sdc_dd"]
 
 
 class WWError(RuntimeError):
@@ -121,6 +122,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_eval_segments.argtypes = [P, P, D, I, ctypes.POINTER(Segment), P, P, P, DP]
     lib.dtn_setup_dd.argtypes = [P, P, P, D, I]
     lib.shoot_eval_sdc.argtypes = [P, P, D, I, P, P, P, DP]
+    lib.shoot_eval_sdc_dd.argtypes = [P, I, D, D, D, P, P, D, D, I, P, P, P, P, DP]
     lib.dtn_solve_multi_dd.argtypes = [P, P, P, I, P, P, P, P]
     PP = ctypes.POINTER(ctypes.c_void_p)
     lib.shoot_eval_batch.argtypes = [I, PP, PP, DP, ctypes.POINTER(ctypes.c_int), PP, PP, PP, DP]
@@ -275,6 +277,24 @@ class Context:
         _check(self.lib.shoot_eval_sdc(self.ptr, _ptr(params.contiguous()), float(T), int(nsteps),
                                        _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
+
+    def shoot_eval_sdc_dd(self, N: int, h: float, tau: float, g: float, q0_hi: torch.Tensor,
+                          q0_lo: torch.Tensor | None, T: float, nsteps: int, T_lo: float = 0.0,
+                          drdT: bool = True):
+        """The base march in double-double with SDC15 (shoot_eval_sdc_dd).  q0 = [eta | phi]
+        as hi (and lo) planes of 2N; returns r and dr/dT as (hi, lo) pairs of device
+        tensors and f as (hi, lo) floats."""
+        dev = q0_hi.device
+        e = lambda: torch.empty(N, dtype=torch.float64, device=dev)
+        rh, rl = e(), e()
+        dh, dl = (e(), e()) if drdT else (None, None)
+        f = (ctypes.c_double * 2)()
+        _check(self.lib.shoot_eval_sdc_dd(self.ptr, int(N), float(h), float(tau), float(g),
+                                          _ptr(q0_hi.contiguous()),
+                                          _ptr(q0_lo.contiguous()) if q0_lo is not None else None,
+                                          float(T), float(T_lo), int(nsteps), _ptr(rh), _ptr(rl), _ptr(dh),
+                                          _ptr(dl), f))
+        return dict(r=(rh, rl), drdT=(dh, dl) if drdT else None, f=(f[0], f[1]))
 
     def shoot_eval_segments(self, params: torch.Tensor, T: float, segments, jacobian: bool = True,
                             drdT: bool = True):
