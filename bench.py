@@ -284,6 +284,50 @@ def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
     return out
 
 
+def run_sdc_dd(steps=(12, 24, 48)):
+    """The base march in double-double with SDC15 (shoot_eval_sdc_dd) on C4's grid and
+    initial state (N 512, infinite depth, no tension) to T/4, at each step count in
+    `steps`: wall time, time per right-hand-side evaluation, the differences between
+    consecutive step counts (SDC15's convergence, followed below the FP64 rounding), and
+    the difference from the FP64 SDC march at the first step count."""
+    import numpy as np
+    import torch
+    from paper_1210_5672_amd import workloads as W
+    from paper_1210_5672_amd import ww
+    w = W.c4()
+    N = w.N
+    q0 = ww.to_dev(w.q_fixed + w.basis @ w.params)
+    ctx = ww.Context(n_max=N, r_max=2)
+    ctx.shoot_eval_sdc_dd(N, w.h, w.tau, w.g, q0, None, w.T / 12, 1)   # work arrays, tables
+    torch.cuda.synchronize()
+    runs = []
+    for ns in steps:
+        t0 = time.perf_counter()
+        o = ctx.shoot_eval_sdc_dd(N, w.h, w.tau, w.g, q0, None, w.T, ns)
+        t = time.perf_counter() - t0
+        runs.append((ns, t, o["r"][0].cpu().numpy(), o["r"][1].cpu().numpy(), o["f"]))
+    print("# double-double SDC15 march timed", file=sys.stderr, flush=True)
+    ctx.shoot_setup(N, w.h, w.tau, w.g, ww.to_dev(np.zeros((2 * N, 1))), q0)
+    r64 = ctx.shoot_eval_sdc(ww.to_dev(np.zeros(1)), w.T, steps[0], jacobian=False)["r"].cpu().numpy()
+    ctx.close()
+    scale = np.abs(runs[0][2]).max()
+    # differences of double-double values: the hi parts nearly cancel (exactly) plus the
+    # lo parts; the low-mode part (k <= 32) of a difference by an FFT of the difference
+    # itself (its own rounding is relative to the small difference)
+    d = lambda a, b: (a[2] - b[2]) + (a[3] - b[3])
+    diff = lambda a, b: float(np.abs(d(a, b)).max() / scale)
+    low = lambda a, b: float(np.abs(np.fft.rfft(d(a, b))[:33]).max() / np.abs(np.fft.rfft(runs[0][2])).max())
+    out = {"workload": f"C4 grid and initial state, base march to T/4 in double-double, N={N}",
+           "marches": [{"steps": ns, "ms": 1e3 * t, "us_per_evaluation": 1e6 * t / (113 * ns + 1), "f": list(f)}
+                       for ns, t, _, _, f in runs],
+           "r_change_when_halving_dt": [diff(runs[i], runs[i + 1]) for i in range(len(runs) - 1)],
+           "r_modes_0_32_change_when_halving_dt": [low(runs[i], runs[i + 1]) for i in range(len(runs) - 1)],
+           "f_change_when_halving_dt": [abs((runs[i][4][0] - runs[i + 1][4][0]) + (runs[i][4][1] - runs[i + 1][4][1]))
+                                        / runs[0][4][0] for i in range(len(runs) - 1)],
+           "r_vs_fp64_sdc": float(np.abs(runs[0][2] + runs[0][3] - r64).max() / scale)}
+    return out
+
+
 def run_dd(reps: int = 3, N: int = 1024, R: int = 129):
     """Double-double DtN (dtn_setup_dd, dtn_solve_multi_dd) on the C3 surface with R
     right-hand sides: set-up time (double-double assembly and FFTs, FP64 LU) and solve
@@ -507,6 +551,7 @@ def main():
     ap.add_argument("--no-mesh", action="store_true", help="skip the segmented non-uniform-mesh march (C6)")
     ap.add_argument("--no-dd", action="store_true", help="skip the double-double DtN timing")
     ap.add_argument("--no-sdc", action="store_true", help="skip the SDC15 march (C4)")
+    ap.add_argument("--no-sdc-dd", action="store_true", help="skip the double-double SDC15 base march (C4 grid)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 256 MiB device copy (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -613,6 +658,8 @@ def main():
         out["dd"] = run_dd()
     if not args.no_sdc:
         out["sdc"] = run_sdc()
+    if not args.no_sdc_dd:
+        out["sdc_dd"] = run_sdc_dd()
     if not args.no_batch:
         out["batch"] = run_batch(tuned=not args.no_tuning)
     if args.copy_probe:
