@@ -128,6 +128,7 @@ struct ww_ctx {
   double *dd_pt_hi = nullptr, *dd_pt_lo = nullptr;
   double *dd_Ah = nullptr, *dd_Al = nullptr, *dd_Gh = nullptr, *dd_Gl = nullptr;
   double* dd_w = nullptr;
+  double* dd_part = nullptr;   // chunk partials of the one-column double-double product
   // SDC15 (shoot_eval_sdc), allocated at first use: the stage slopes of one step
   // (SDC_STAGES slots of 2 n_max r_max), the stage state, and the sparse stage rows
   // (SDC_STAGES + 1 rows of SDC_MAXNZ slot indices and weights; the last row is the
@@ -508,6 +509,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_dd_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_dd_gamma, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_dd_base_rhs, hipFuncAttributeMaxDynamicSharedMemorySize, big));
+  CCHK(hipFuncSetAttribute((const void*)k_dd_filter_state, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_rhs_prep, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_dtn<16>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
   CCHK(hipFuncSetAttribute((const void*)k_base_dtn<WW_NMAX / 64>, hipFuncAttributeMaxDynamicSharedMemorySize, big));
@@ -1713,7 +1716,28 @@ static int ensure_dd(ww_ctx* c) {
   double** mats[] = {&c->dd_Ah, &c->dd_Al, &c->dd_Gh, &c->dd_Gl};
   for (double** q : mats)
     if ((rc = dalloc(c, (void**)q, np * np * 8))) return rc;
+  if (!c->dd_part && (rc = dalloc(c, (void**)&c->dd_part, (size_t)2 * DDGV_KS * np * 8))) return rc;
   return dalloc(c, (void**)&c->dd_w, (size_t)DD_WORK * np * c->r_max * 8);
+}
+
+// out = add + sgn A B in double-double for nrhs columns (ld Np): one column by the
+// inner-index split of k_dd_gemv_part / k_dd_gemv_sum, several by k_dd_gemm
+static int dd_gemm(ww_ctx* c, const double* Ah, const double* Al, const double* Bh, const double* Bl,
+                   const double* addh, const double* addl, double sgn, double* outh, double* outl, int nrhs) {
+  const int Np = c->Np;
+  if (nrhs == 1) {
+    double *Ph = c->dd_part, *Pl = c->dd_part + (size_t)DDGV_KS * c->np_max;
+    hipLaunchKernelGGL(k_dd_gemv_part, dim3(Np / 64, DDGV_KS), dim3(WW_NT), 0, c->stream, Ah, Al, Np, Bh, Bl, Ph, Pl);
+    LAUNCHCHK();
+    hipLaunchKernelGGL(k_dd_gemv_sum, dim3((Np + 255) / 256), dim3(256), 0, c->stream, Ph, Pl, DDGV_KS, Np, addh,
+                       addl, sgn, outh, outl);
+    LAUNCHCHK();
+    return 0;
+  }
+  hipLaunchKernelGGL(k_dd_gemm, dim3(Np / 64, (nrhs + 3) / 4), dim3(WW_NT), 0, c->stream, Ah, Al, Np, Bh, Bl, addh,
+                     addl, sgn, outh, outl, nrhs);
+  LAUNCHCHK();
+  return 0;
 }
 
 static int dd_tables(ww_ctx* c, int N) {
@@ -1747,48 +1771,31 @@ static int dd_tables(ww_ctx* c, int N) {
 
 static size_t dd_lds_bytes(int N) { return (size_t)(3 * N + N / 2) * sizeof(cdd); }
 
-extern "C" {
-
-int dtn_setup_dd(ww_ctx* c, const double* surface_hi, const double* surface_lo, double h, int N) {
-  if (!c || !surface_hi) return fail(WW_EINVAL, "null argument");
-  c->dd_ready = false;
-  c->dtn_ready = false;   // the FP64 factor buffers are reused
-  if (N < 16 || (N & (N - 1)) || N > c->n_max || N > 1024)
-    return fail(WW_EINVAL, "double-double DtN: N must be a power of two, 16 <= N <= min(n_max, 1024)");
-  int rc;
-  if ((rc = set_grid(c, N, h))) return rc;
-  if ((rc = check_domain(c, surface_hi))) return rc;
-  if ((rc = ensure_dd(c))) return rc;
-  if ((rc = dd_tables(c, N))) return rc;
-  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+// The double-double set-up of the grid's surface: per-point quantities, the
+// double-double assembly, the FP64 factors (block LU and explicit inverse) of A's
+// leading part.  domain (optional): status word for the finite-depth test h + eta > 0.
+static int dd_setup_enqueue(ww_ctx* c, const double* sh, const double* sl, int* domain) {
+  const int N = c->N, Np = c->Np;
+  hipLaunchKernelGGL(k_dd_prep, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, sh, sl, c->hsurf, c->dd_tw, N,
+                     c->n_max, c->dd_pt_hi, c->dd_pt_lo, c->finite ? domain : nullptr);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_dd_prep, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, surface_hi, surface_lo, c->hsurf,
-                     c->dd_tw, N, c->n_max, c->dd_pt_hi, c->dd_pt_lo);
-  LAUNCHCHK();
-  const int Np = c->Np;
   hipLaunchKernelGGL(k_dd_assemble, dim3(Np / WW_TB, Np / 16), dim3(WW_NT), 0, c->stream, c->dd_pt_hi, c->dd_pt_lo,
                      c->n_max, c->dd_tab_hi, c->dd_tab_lo, N, Np, c->finite, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl,
                      c->A);
   LAUNCHCHK();
-  // FP64 factors (block LU and explicit inverse) of the leading part of A
   Fac F = fac_default(c);
   F.use32 = false;
   F.lag32 = false;
   F.perm = nullptr;
-  if ((rc = enqueue_lu(c, F))) return rc;
-  int st = 0;
-  if ((rc = read_status(c, &st))) return rc;
-  if (st & 2) return fail(WW_ENONFINITE, "non-finite surface");
-  if (st & (1 | 8)) return fail(WW_EPIVOT, "double-double DtN: pivot below the guard (no pivoted form)");
-  c->dd_ready = true;
-  return 0;
+  return enqueue_lu(c, F);
 }
 
-int dtn_solve_multi_dd(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, int nrhs, double* out_hi,
-                       double* out_lo, double* mu_hi, double* mu_lo) {
-  if (!c || !rhs_hi || !out_hi || !out_lo || (!mu_hi != !mu_lo)) return fail(WW_EINVAL, "null argument");
-  if (!c->dd_ready) return fail(WW_ENOSETUP, "dtn_solve_multi_dd before dtn_setup_dd");
-  if (nrhs < 1 || nrhs > c->r_max) return fail(WW_EINVAL, "1 <= nrhs <= r_max required");
+// The double-double solve and DtN of nrhs columns with the set-up's factors: mu = Mi psi,
+// DD_SWEEPS sweeps r = psi - A mu (double-double), mu += Mi r_hi, the final residual's
+// and the right-hand side's largest entries into mx[0], mx[1] (zero on entry), then
+// gamma = mu', H gamma / 2 and G psi = H gamma / 2 + Gm gamma
+static int dd_solve_enqueue(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, int nrhs, double* out_hi,
+                            double* out_lo, double* mu_hi, double* mu_lo, unsigned long long* mx) {
   const int N = c->N, Np = c->Np;
   const size_t blk = (size_t)Np * nrhs, pl = (size_t)c->np_max * c->r_max;
   double* w = c->dd_w;
@@ -1804,35 +1811,22 @@ int dtn_solve_multi_dd(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, in
     hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, psl, Np, 0, Np, nrhs);
   LAUNCHCHK();
   int rc;
-  // mu = Mi psi (FP64), then refinement: r = psi - A mu (double-double), mu += Mi r_hi
   if ((rc = enqueue_gemm<double>(c, c->Mi, 0, psh, nullptr, 1.0, muh, nrhs))) return rc;
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, mul, Np, 0, Np, nrhs);
   LAUNCHCHK();
-  const dim3 gg(Np / 64, (nrhs + 3) / 4);
   for (int sweep = 0; sweep < DD_SWEEPS; ++sweep) {
-    hipLaunchKernelGGL(k_dd_gemm, gg, dim3(WW_NT), 0, c->stream, c->dd_Ah, c->dd_Al, Np, muh, mul, psh, psl, -1.0, rh,
-                       rl, nrhs);
-    LAUNCHCHK();
+    if ((rc = dd_gemm(c, c->dd_Ah, c->dd_Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
     if ((rc = enqueue_gemm<double>(c, c->Mi, 0, rh, nullptr, 1.0, del, nrhs))) return rc;
     hipLaunchKernelGGL(k_dd_correct, dim3(blocks), dim3(256), 0, c->stream, muh, mul, del, blk);
     LAUNCHCHK();
   }
-  // the final residual against the test
-  hipLaunchKernelGGL(k_dd_gemm, gg, dim3(WW_NT), 0, c->stream, c->dd_Ah, c->dd_Al, Np, muh, mul, psh, psl, -1.0, rh, rl,
-                     nrhs);
-  LAUNCHCHK();
-  unsigned long long* mx = (unsigned long long*)(c->status + 4);
-  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
-  LAUNCHCHK();
+  if ((rc = dd_gemm(c, c->dd_Ah, c->dd_Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
   hipLaunchKernelGGL(k_dd_maxabs, dim3(std::min(blocks, 256)), dim3(256), 0, c->stream, rh, psh, N, Np, nrhs, mx);
   LAUNCHCHK();
-  // G psi = H gamma / 2 + Gm gamma, gamma = mu'
   hipLaunchKernelGGL(k_dd_gamma, dim3(nrhs), dim3(WW_NT), dd_lds_bytes(N), c->stream, muh, mul, Np, c->dd_tw, N, gh,
                      gl, hh, hl);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_dd_gemm, gg, dim3(WW_NT), 0, c->stream, c->dd_Gh, c->dd_Gl, Np, gh, gl, hh, hl, 1.0, oh, ol,
-                     nrhs);
-  LAUNCHCHK();
+  if ((rc = dd_gemm(c, c->dd_Gh, c->dd_Gl, gh, gl, hh, hl, 1.0, oh, ol, nrhs))) return rc;
   const size_t tot = (size_t)N * nrhs;
   const int ob = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, oh, Np, out_hi, N, Np, N, nrhs);
@@ -1842,6 +1836,43 @@ int dtn_solve_multi_dd(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, in
     hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, mul, Np, mu_lo, N, Np, N, nrhs);
   }
   LAUNCHCHK();
+  return 0;
+}
+
+extern "C" {
+
+int dtn_setup_dd(ww_ctx* c, const double* surface_hi, const double* surface_lo, double h, int N) {
+  if (!c || !surface_hi) return fail(WW_EINVAL, "null argument");
+  c->dd_ready = false;
+  c->dtn_ready = false;   // the FP64 factor buffers are reused
+  if (N < 16 || (N & (N - 1)) || N > c->n_max || N > 1024)
+    return fail(WW_EINVAL, "double-double DtN: N must be a power of two, 16 <= N <= min(n_max, 1024)");
+  int rc;
+  if ((rc = set_grid(c, N, h))) return rc;
+  if ((rc = check_domain(c, surface_hi))) return rc;
+  if ((rc = ensure_dd(c))) return rc;
+  if ((rc = dd_tables(c, N))) return rc;
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
+  if ((rc = dd_setup_enqueue(c, surface_hi, surface_lo, nullptr))) return rc;
+  int st = 0;
+  if ((rc = read_status(c, &st))) return rc;
+  if (st & 2) return fail(WW_ENONFINITE, "non-finite surface");
+  if (st & (1 | 8)) return fail(WW_EPIVOT, "double-double DtN: pivot below the guard (no pivoted form)");
+  c->dd_ready = true;
+  return 0;
+}
+
+int dtn_solve_multi_dd(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, int nrhs, double* out_hi,
+                       double* out_lo, double* mu_hi, double* mu_lo) {
+  if (!c || !rhs_hi || !out_hi || !out_lo || (!mu_hi != !mu_lo)) return fail(WW_EINVAL, "null argument");
+  if (!c->dd_ready) return fail(WW_ENOSETUP, "dtn_solve_multi_dd before dtn_setup_dd");
+  if (nrhs < 1 || nrhs > c->r_max) return fail(WW_EINVAL, "1 <= nrhs <= r_max required");
+  unsigned long long* mx = (unsigned long long*)(c->status + 4);
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
+  int rc;
+  if ((rc = dd_solve_enqueue(c, rhs_hi, rhs_lo, nrhs, out_hi, out_lo, mu_hi, mu_lo, mx))) return rc;
   unsigned long long m[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(m, mx, sizeof(m), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -2771,13 +2802,29 @@ static int ensure_sdc_dd(ww_ctx* c) {
   return dalloc(c, (void**)&c->sdd_fo, 64);   // last: its presence marks the set-up as complete
 }
 
+// the status of the double-double march after step n (n < 0: at T/4), as an error
+static int dd_march_status(ww_ctx* c, int n) {
+  int st = 0, rc;
+  if ((rc = read_status(c, &st))) return rc;
+  const std::string at = n >= 0 ? " (double-double march, step " + std::to_string(n) + ")" : " (double-double march)";
+  if (st & 16) return fail(WW_EDOMAIN, "finite depth: surface height h + eta <= 0" + at);
+  if (st & 2) return fail(WW_ENONFINITE, "non-finite surface" + at);
+  if (st & (1 | 8)) return fail(WW_EPIVOT, "double-double DtN: pivot below the guard" + at);
+  if (st & 4) return fail(WW_EREFINE, "double-double DtN: residual above 2^-96 of the right-hand side" + at);
+  return 0;
+}
+
 // the base right-hand side in double-double at the state (yh, yl) into (kh, kl)
-static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double h, double tau, double g, double* kh,
-                  double* kl) {
+// (no host synchronisation: the domain, pivot and residual tests set bits of the status
+// word, read once per step)
+static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double tau, double g, double* kh, double* kl) {
   int rc;
   const int N = c->N;
-  if ((rc = dtn_setup_dd(c, yh, yl, h, N))) return rc;
-  if ((rc = dtn_solve_multi_dd(c, yh + N, yl + N, 1, c->sdd_Gh, c->sdd_Gl, nullptr, nullptr))) return rc;
+  unsigned long long* mx = (unsigned long long*)(c->sdd_fo + 2);
+  if ((rc = dd_setup_enqueue(c, yh, yl, c->status))) return rc;
+  if ((rc = dd_solve_enqueue(c, yh + N, yl + N, 1, c->sdd_Gh, c->sdd_Gl, nullptr, nullptr, mx))) return rc;
+  hipLaunchKernelGGL(k_dd_restest, dim3(1), dim3(64), 0, c->stream, mx, DD_TOL, c->status);
+  LAUNCHCHK();
   hipLaunchKernelGGL(k_dd_base_rhs, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, yh, yl, c->sdd_Gh, c->sdd_Gl,
                      c->sdd_fh, c->sdd_fl, c->dd_tw, N, g, tau, kh, kl);
   LAUNCHCHK();
@@ -2827,6 +2874,12 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   if ((rc = ensure_dd(c))) return rc;
   if ((rc = dd_tables(c, N))) return rc;
   if ((rc = ensure_sdc_dd(c))) return rc;
+  c->dd_ready = false;    // the march replaces the double-double and FP64 factors
+  c->dtn_ready = false;
+  hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dd_mx_reset, dim3(1), dim3(64), 0, c->stream, (unsigned long long*)(c->sdd_fo + 2));
+  LAUNCHCHK();
   // the stage rows with this call's dt, the filter symbol, the initial state
   {
     const int rows = SDC_STAGES + 1;
@@ -2860,17 +2913,19 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   for (int n = 0; n < nsteps; ++n) {
     for (int s = 0; s < SDC_STAGES; ++s) {
       if ((rc = combine(s, c->sdd_Yh, c->sdd_Yl))) return rc;
-      if ((rc = dd_rhs(c, c->sdd_Yh, c->sdd_Yl, h, tau, g, c->sdd_Kh + s * n2, c->sdd_Kl + s * n2))) return rc;
+      if ((rc = dd_rhs(c, c->sdd_Yh, c->sdd_Yl, tau, g, c->sdd_Kh + s * n2, c->sdd_Kl + s * n2))) return rc;
     }
     if ((rc = combine(SDC_STAGES, c->sdd_yh, c->sdd_yl))) return rc;
     hipLaunchKernelGGL(k_dd_filter_state, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, c->sdd_yh, c->sdd_yl,
                        c->sdd_fh, c->sdd_fl, c->dd_tw, N);
     LAUNCHCHK();
+    if ((rc = dd_march_status(c, n))) return rc;
   }
   // the right-hand side at the final state (dr/dT), then the outputs
   double* kfh = c->sdd_Kh + SDC_STAGES * n2;
   double* kfl = c->sdd_Kl + SDC_STAGES * n2;
-  if (drdT_hi && (rc = dd_rhs(c, c->sdd_yh, c->sdd_yl, h, tau, g, kfh, kfl))) return rc;
+  if (drdT_hi && (rc = dd_rhs(c, c->sdd_yh, c->sdd_yl, tau, g, kfh, kfl))) return rc;
+  if ((rc = dd_march_status(c, -1))) return rc;
   hipLaunchKernelGGL(k_dd_outputs, dim3(1), dim3(WW_NT), 0, c->stream, c->sdd_yh, c->sdd_yl, kfh, kfl, N, r_hi, r_lo,
                      drdT_hi, drdT_lo, c->sdd_fo);
   LAUNCHCHK();

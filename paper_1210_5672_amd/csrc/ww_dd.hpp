@@ -176,13 +176,15 @@ __device__ inline cdd dd_ik(cdd X, int k, int N) {
 // -------------------------------------------------------------------------------------
 // Per-point quantities of a surface (one workgroup): eta' and eta'' (spectral, d/dx
 // with the Nyquist mode set to zero, eta'' = d(eta')), exp(s) and exp(-s) of the
-// surface height s (h + eta at finite depth, eta otherwise).  pt_hi / pt_lo: 4 planes
+// surface height s (h + eta at finite depth, eta otherwise); domain (optional, finite
+// depth): status bit 16 where s <= 0.  pt_hi / pt_lo: 4 planes
 // of nmax values each: eta', eta'', exp(s), exp(-s).  Dynamic LDS: 3.5 N complex
 // double-doubles (data, two scratch buffers, N/2 twiddles).
 // -------------------------------------------------------------------------------------
 __global__ __launch_bounds__(WW_NT) void k_dd_prep(const double* __restrict__ eh, const double* __restrict__ el,
                                                    double hsurf, const cdd* __restrict__ twg, int N, int nmax,
-                                                   double* __restrict__ pt_hi, double* __restrict__ pt_lo) {
+                                                   double* __restrict__ pt_hi, double* __restrict__ pt_lo,
+                                                   int* __restrict__ domain) {
   extern __shared__ cdd ldsd[];
   cdd* Z = ldsd;
   cdd* W = ldsd + N;
@@ -207,6 +209,7 @@ __global__ __launch_bounds__(WW_NT) void k_dd_prep(const double* __restrict__ eh
     pt_hi[nmax + t] = S[t].re.hi;
     pt_lo[nmax + t] = S[t].re.lo;
     const dd sh = dd_add_d(dd{eh[t], el ? el[t] : 0.0}, hsurf);
+    if (domain && !(sh.hi > 0.0)) atomicOr(domain, 16);   // finite depth: h + eta > 0
     const dd ep = dd_exp(sh), em = dd_exp(dd_neg(sh));
     pt_hi[2 * nmax + t] = ep.hi;
     pt_lo[2 * nmax + t] = ep.lo;
@@ -333,6 +336,49 @@ __global__ __launch_bounds__(WW_NT) void k_dd_gemm(const double* __restrict__ A_
   out_lo[o] = r.lo;
 }
 
+// The one-column form of k_dd_gemm (one right-hand side: the double-double march), split
+// over the inner index: chunk s = blockIdx.y of Np / gridDim.y indices, 64 rows per
+// workgroup; thread (row r, lane q) sums A_ij x_j over j = j0 + q, j0 + q + 4, ... in
+// increasing order, then the four lanes' partials in order q = 0..3 give P[s][i]
+// (coalesced: the 64 rows of one column are consecutive)
+#define DDGV_KS 16
+__global__ __launch_bounds__(WW_NT) void k_dd_gemv_part(const double* __restrict__ A_hi,
+                                                        const double* __restrict__ A_lo, int Np,
+                                                        const double* __restrict__ x_hi,
+                                                        const double* __restrict__ x_lo,
+                                                        double* __restrict__ P_hi, double* __restrict__ P_lo) {
+  __shared__ dd part[4][64];
+  const int r = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int i = blockIdx.x * 64 + r;
+  const int len = Np / gridDim.y, j0 = blockIdx.y * len;
+  dd acc = dd_of(0.0);
+  for (int j = j0 + q; j < j0 + len; j += 4) {
+    const size_t o = (size_t)j * Np + i;
+    acc = dd_add(acc, dd_mul(dd{A_hi[o], A_lo[o]}, dd{x_hi[j], x_lo[j]}));
+  }
+  part[q][r] = acc;
+  __syncthreads();
+  if (q == 0) {
+    dd t = part[0][r];
+    for (int u = 1; u < 4; ++u) t = dd_add(t, part[u][r]);
+    P_hi[(size_t)blockIdx.y * Np + i] = t.hi;
+    P_lo[(size_t)blockIdx.y * Np + i] = t.lo;
+  }
+}
+// out = add + sgn sum_s P[s] (chunks in increasing order); add may be null
+__global__ void k_dd_gemv_sum(const double* __restrict__ P_hi, const double* __restrict__ P_lo, int ks, int Np,
+                              const double* __restrict__ add_hi, const double* __restrict__ add_lo, double sgn,
+                              double* __restrict__ out_hi, double* __restrict__ out_lo) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= Np) return;
+  dd t = dd_of(0.0);
+  for (int s = 0; s < ks; ++s) t = dd_add(t, dd{P_hi[(size_t)s * Np + i], P_lo[(size_t)s * Np + i]});
+  if (sgn < 0.0) t = dd_neg(t);
+  if (add_hi) t = dd_add(dd{add_hi[i], add_lo[i]}, t);
+  out_hi[i] = t.hi;
+  out_lo[i] = t.lo;
+}
+
 // mu += delta (double-double plus a double), n entries
 __global__ void k_dd_correct(double* __restrict__ mu_hi, double* __restrict__ mu_lo, const double* __restrict__ delta,
                              size_t n) {
@@ -374,6 +420,19 @@ __global__ __launch_bounds__(WW_NT) void k_dd_gamma(const double* __restrict__ m
     h_hi[off + t] = in ? S[t].re.hi : 0.0;
     h_lo[off + t] = in ? S[t].re.lo : 0.0;
   }
+}
+
+// the residual test of a double-double solve: status bit 4 unless max|r| <= tol max|b|
+// (mx from k_dd_maxabs); mx is cleared for the next solve
+__global__ void k_dd_restest(unsigned long long* __restrict__ mx, double tol, int* __restrict__ status) {
+  if (threadIdx.x != 0) return;
+  const double mr = __longlong_as_double((long long)mx[0]), mb = __longlong_as_double((long long)mx[1]);
+  if (!(mr <= tol * mb)) atomicOr(status, 4);
+  mx[0] = 0;
+  mx[1] = 0;
+}
+__global__ void k_dd_mx_reset(unsigned long long* __restrict__ mx) {
+  if (threadIdx.x == 0) mx[0] = mx[1] = 0;
 }
 
 // max |r| and max |b| over rows < N of ncols columns (ld Np) into mx[0], mx[1] by
