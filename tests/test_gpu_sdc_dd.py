@@ -64,14 +64,17 @@ def test_dd_march_matches_the_dd_oracle(N, h, tau, nsteps, T):
     ctx.close()
 
 
-def test_dd_march_agrees_with_the_fp64_march_at_c4_grid():
-    """C4's grid and initial state (N 512, infinite depth), one step of its 12-step dt:
-    the double-double march and the FP64 SDC march agree to the FP64 march's rounding."""
+@pytest.mark.parametrize("name,frac", [("c4", 1 / 12), ("c3", 1 / 1200)])
+def test_dd_march_agrees_with_the_fp64_march(name, frac):
+    """C4's grid and initial state (N 512, infinite depth; one step of its 12-step dt) and
+    C3's (N 1024, the largest grid of the double-double path: depth 0.5 and tension
+    0.02; one step of dt = T / 4800, within the explicit scheme's stability there): the
+    double-double march and the FP64 SDC march agree to the FP64 march's rounding."""
     ww, torch = _ww()
-    w = W.c4()
+    w = W.CONFIGS[name]()
     N = w.N
     q0 = w.q_fixed + w.basis @ w.params
-    T1 = w.T / 12   # one step of dt = T / 48
+    T1 = w.T * frac   # one step of dt = T frac / 4
     ctx = ww.Context(n_max=N, r_max=2)
     dd_out = ctx.shoot_eval_sdc_dd(N, w.h, w.tau, w.g, ww.to_dev(q0), None, T1, 1)
     ctx.shoot_setup(N, w.h, w.tau, w.g, ww.to_dev(np.zeros((2 * N, 1))), ww.to_dev(q0))
