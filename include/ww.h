@@ -236,9 +236,10 @@ int shoot_eval_sdc(ww_ctx *ctx, const double *params, double T, int nsteps, doub
  * as r_hi + r_lo (N each), dr/dT likewise (drdT_hi and drdT_lo both NULL to skip it;
  * it costs one more right-hand side); f (host, 2 doubles: hi, lo) = r.r/2.  Errors:
  * WW_EINVAL (arguments), WW_EDOMAIN (a stage surface through the bottom), WW_EPIVOT,
- * WW_EREFINE (a stage's solve misses its 2^-96 residual test), WW_ENONFINITE.
- * Synchronises (three times per stage).  Replaces the context's FP64 DtN factors and
- * grid (call dtn_setup or shoot_setup again before their entry points).
+ * WW_EREFINE (a stage's solve misses its 2^-96 residual test), WW_ENONFINITE; the tests
+ * run on the device and are read once per step (the error names the step).
+ * Synchronises once per step.  Replaces the context's FP64 DtN factors and grid (call
+ * dtn_setup or shoot_setup again before their entry points).
  */
 int shoot_eval_sdc_dd(ww_ctx *ctx, int N, double h, double tau, double g, const double *q0_hi,
                       const double *q0_lo, double T_hi, double T_lo, int nsteps, double *r_hi,

@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -152,6 +153,7 @@ struct ww_ctx {
   double *sdd_fh = nullptr, *sdd_fl = nullptr, *sdd_wh = nullptr, *sdd_wl = nullptr, *sdd_fo = nullptr;
   int* sdd_j = nullptr;
   int sdd_cnt[SDC_STAGES + 1] = {};
+  double* sdd_lane = nullptr;   // the grouped sweeps' lanes (SDC_NODES of them)
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -1771,31 +1773,55 @@ static int dd_tables(ww_ctx* c, int N) {
 
 static size_t dd_lds_bytes(int N) { return (size_t)(3 * N + N / 2) * sizeof(cdd); }
 
-// The double-double set-up of the grid's surface: per-point quantities, the
-// double-double assembly, the FP64 factors (block LU and explicit inverse) of A's
-// leading part.  domain (optional): status word for the finite-depth test h + eta > 0.
-static int dd_setup_enqueue(ww_ctx* c, const double* sh, const double* sl, int* domain) {
-  const int N = c->N, Np = c->Np;
-  hipLaunchKernelGGL(k_dd_prep, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, sh, sl, c->hsurf, c->dd_tw, N,
-                     c->n_max, c->dd_pt_hi, c->dd_pt_lo, c->finite ? domain : nullptr);
-  LAUNCHCHK();
-  hipLaunchKernelGGL(k_dd_assemble, dim3(Np / WW_TB, Np / 16), dim3(WW_NT), 0, c->stream, c->dd_pt_hi, c->dd_pt_lo,
-                     c->n_max, c->dd_tab_hi, c->dd_tab_lo, N, Np, c->finite, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl,
-                     c->A);
-  LAUNCHCHK();
-  Fac F = fac_default(c);
+// The buffers of one double-double DtN: per-point quantities, A and Gm (hi and lo
+// planes), and the FP64 factor set whose A receives A's leading part and whose Mi the
+// explicit inverse.  The context's own (dd_lane) serves dtn_setup_dd / dtn_solve_multi_dd
+// and the double-double march's predictor; the nodes of its correction sweeps take one
+// lane each (with the ring's factor sets).
+struct DdLane {
+  double *pt_hi, *pt_lo, *Ah, *Al, *Gh, *Gl;
+  Fac F;
+};
+static Fac fp64_fac(Fac F) {
   F.use32 = false;
   F.lag32 = false;
   F.perm = nullptr;
-  return enqueue_lu(c, F);
+  F.Gm = nullptr;
+  return F;
+}
+static DdLane dd_lane(ww_ctx* c) {
+  return DdLane{c->dd_pt_hi, c->dd_pt_lo, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl, fp64_fac(fac_default(c))};
+}
+
+// per-point quantities and the double-double assembly of the surface (sh, sl) into lane
+// L; domain (optional): status word for the finite-depth test h + eta > 0
+static int dd_prep_assemble(ww_ctx* c, const DdLane& L, const double* sh, const double* sl, int* domain) {
+  const int N = c->N, Np = c->Np;
+  hipLaunchKernelGGL(k_dd_prep, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, sh, sl, c->hsurf, c->dd_tw, N,
+                     c->n_max, L.pt_hi, L.pt_lo, c->finite ? domain : nullptr);
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dd_assemble, dim3(Np / WW_TB, Np / 16), dim3(WW_NT), 0, c->stream, L.pt_hi, L.pt_lo, c->n_max,
+                     c->dd_tab_hi, c->dd_tab_lo, N, Np, c->finite, L.Ah, L.Al, L.Gh, L.Gl, L.F.A);
+  LAUNCHCHK();
+  return 0;
+}
+
+// The double-double set-up of the grid's surface in the context's lane: per-point
+// quantities, the double-double assembly, the FP64 factors (block LU and explicit
+// inverse) of A's leading part
+static int dd_setup_enqueue(ww_ctx* c, const double* sh, const double* sl, int* domain) {
+  const DdLane L = dd_lane(c);
+  int rc;
+  if ((rc = dd_prep_assemble(c, L, sh, sl, domain))) return rc;
+  return enqueue_lu(c, L.F);
 }
 
 // The double-double solve and DtN of nrhs columns with the set-up's factors: mu = Mi psi,
 // DD_SWEEPS sweeps r = psi - A mu (double-double), mu += Mi r_hi, the final residual's
 // and the right-hand side's largest entries into mx[0], mx[1] (zero on entry), then
 // gamma = mu', H gamma / 2 and G psi = H gamma / 2 + Gm gamma
-static int dd_solve_enqueue(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, int nrhs, double* out_hi,
-                            double* out_lo, double* mu_hi, double* mu_lo, unsigned long long* mx) {
+static int dd_solve_enqueue(ww_ctx* c, const DdLane& L, const double* rhs_hi, const double* rhs_lo, int nrhs,
+                            double* out_hi, double* out_lo, double* mu_hi, double* mu_lo, unsigned long long* mx) {
   const int N = c->N, Np = c->Np;
   const size_t blk = (size_t)Np * nrhs, pl = (size_t)c->np_max * c->r_max;
   double* w = c->dd_w;
@@ -1811,22 +1837,22 @@ static int dd_solve_enqueue(ww_ctx* c, const double* rhs_hi, const double* rhs_l
     hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, psl, Np, 0, Np, nrhs);
   LAUNCHCHK();
   int rc;
-  if ((rc = enqueue_gemm<double>(c, c->Mi, 0, psh, nullptr, 1.0, muh, nrhs))) return rc;
+  if ((rc = enqueue_gemm<double>(c, L.F.Mi, 0, psh, nullptr, 1.0, muh, nrhs))) return rc;
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, mul, Np, 0, Np, nrhs);
   LAUNCHCHK();
   for (int sweep = 0; sweep < DD_SWEEPS; ++sweep) {
-    if ((rc = dd_gemm(c, c->dd_Ah, c->dd_Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
-    if ((rc = enqueue_gemm<double>(c, c->Mi, 0, rh, nullptr, 1.0, del, nrhs))) return rc;
+    if ((rc = dd_gemm(c, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
+    if ((rc = enqueue_gemm<double>(c, L.F.Mi, 0, rh, nullptr, 1.0, del, nrhs))) return rc;
     hipLaunchKernelGGL(k_dd_correct, dim3(blocks), dim3(256), 0, c->stream, muh, mul, del, blk);
     LAUNCHCHK();
   }
-  if ((rc = dd_gemm(c, c->dd_Ah, c->dd_Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
+  if ((rc = dd_gemm(c, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
   hipLaunchKernelGGL(k_dd_maxabs, dim3(std::min(blocks, 256)), dim3(256), 0, c->stream, rh, psh, N, Np, nrhs, mx);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_dd_gamma, dim3(nrhs), dim3(WW_NT), dd_lds_bytes(N), c->stream, muh, mul, Np, c->dd_tw, N, gh,
                      gl, hh, hl);
   LAUNCHCHK();
-  if ((rc = dd_gemm(c, c->dd_Gh, c->dd_Gl, gh, gl, hh, hl, 1.0, oh, ol, nrhs))) return rc;
+  if ((rc = dd_gemm(c, L.Gh, L.Gl, gh, gl, hh, hl, 1.0, oh, ol, nrhs))) return rc;
   const size_t tot = (size_t)N * nrhs;
   const int ob = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, oh, Np, out_hi, N, Np, N, nrhs);
@@ -1872,7 +1898,7 @@ int dtn_solve_multi_dd(ww_ctx* c, const double* rhs_hi, const double* rhs_lo, in
   hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
   LAUNCHCHK();
   int rc;
-  if ((rc = dd_solve_enqueue(c, rhs_hi, rhs_lo, nrhs, out_hi, out_lo, mu_hi, mu_lo, mx))) return rc;
+  if ((rc = dd_solve_enqueue(c, dd_lane(c), rhs_hi, rhs_lo, nrhs, out_hi, out_lo, mu_hi, mu_lo, mx))) return rc;
   unsigned long long m[2] = {0, 0};
   HIPCHK(hipMemcpyAsync(m, mx, sizeof(m), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -2636,7 +2662,15 @@ static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double
     for (int q = 0; q < SDC_NODES; ++q) HIPCHK(hipEventRecord(c->sdc_evC[q], c->stream));
     for (int n = 0; n < nsteps; ++n) {
       SdcStep st(c, cols, dt);
-      if ((rc = st.step())) return rc;
+      if ((rc = st.step())) {
+        // nothing of the march may still run on the column or LU stream
+        const std::string msg = g_err;
+        (void)hipStreamSynchronize(c->side);
+        (void)hipStreamSynchronize(c->lus[0]);
+        (void)hipStreamSynchronize(c->stream);
+        g_err = msg;
+        return rc;
+      }
     }
   } else {
     for (int n = 0; n < nsteps; ++n)
@@ -2817,17 +2851,86 @@ static int dd_march_status(ww_ctx* c, int n) {
 // the base right-hand side in double-double at the state (yh, yl) into (kh, kl)
 // (no host synchronisation: the domain, pivot and residual tests set bits of the status
 // word, read once per step)
-static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double tau, double g, double* kh, double* kl) {
+// the solve and right-hand side of a stage whose lane L is assembled and factored
+static int dd_rhs_tail(ww_ctx* c, const DdLane& L, const double* yh, const double* yl, double tau, double g,
+                       double* kh, double* kl) {
   int rc;
   const int N = c->N;
   unsigned long long* mx = (unsigned long long*)(c->sdd_fo + 2);
-  if ((rc = dd_setup_enqueue(c, yh, yl, c->status))) return rc;
-  if ((rc = dd_solve_enqueue(c, yh + N, yl + N, 1, c->sdd_Gh, c->sdd_Gl, nullptr, nullptr, mx))) return rc;
+  if ((rc = dd_solve_enqueue(c, L, yh + N, yl + N, 1, c->sdd_Gh, c->sdd_Gl, nullptr, nullptr, mx))) return rc;
   hipLaunchKernelGGL(k_dd_restest, dim3(1), dim3(64), 0, c->stream, mx, DD_TOL, c->status);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_dd_base_rhs, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, yh, yl, c->sdd_Gh, c->sdd_Gl,
                      c->sdd_fh, c->sdd_fl, c->dd_tw, N, g, tau, kh, kl);
   LAUNCHCHK();
+  return 0;
+}
+static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double tau, double g, double* kh, double* kl) {
+  int rc;
+  if ((rc = dd_setup_enqueue(c, yh, yl, c->status))) return rc;
+  return dd_rhs_tail(c, dd_lane(c), yh, yl, tau, g, kh, kl);
+}
+
+// the lanes of the grouped sweeps (first use): per node, double-double A and Gm, the
+// per-point quantities and the stage state; the ring's factor sets, the LU stream
+static int ensure_sdd_lanes(ww_ctx* c) {
+  int rc;
+  if ((rc = ensure_sdc_groups(c))) return rc;
+  if (c->sdd_lane) return 0;
+  const size_t np = c->np_max, nm = c->n_max;
+  const size_t per = 4 * np * np + 8 * nm + 4 * nm;   // A, Gm (hi, lo); 4 point planes (hi, lo); state (hi, lo)
+  return dalloc(c, (void**)&c->sdd_lane, SDC_NODES * per * 8);
+}
+static DdLane dd_sweep_lane(ww_ctx* c, int m, double** yh, double** yl) {
+  const size_t np = c->np_max, nm = c->n_max, nn = np * np;
+  double* b = c->sdd_lane + (size_t)m * (4 * nn + 12 * nm);
+  *yh = b + 4 * nn + 8 * nm;
+  *yl = *yh + 2 * nm;
+  return DdLane{b + 4 * nn, b + 4 * nn + 4 * nm, b, b + nn, b + 2 * nn, b + 3 * nn, fp64_fac(pipe_set(c, m, false))};
+}
+
+// The nodes of one correction sweep (stages s0 .. s0 + SDC_NODES - 1) read only slopes of
+// earlier sweeps: each node's stage state, per-point quantities and double-double
+// assembly in its lane, the FP64 LUs in two groups of four (the second on the LU stream,
+// beside the first group's LU and solves), then each node's solve and right-hand side.
+// The kernels per lane are those of the stage-by-stage form: the same bits.
+static int dd_sweep(ww_ctx* c, int s0, double tau, double g,
+                    const std::function<int(int, double*, double*)>& combine) {
+  static_assert(SDC_NODES == 2 * BLU_GMAX, "a sweep is factored in two groups");
+  int rc;
+  const int G = BLU_GMAX;
+  const size_t n2 = (size_t)2 * c->N;
+  DdLane L[SDC_NODES];
+  double *yh[SDC_NODES], *yl[SDC_NODES];
+  for (int m = 0; m < SDC_NODES; ++m) L[m] = dd_sweep_lane(c, m, &yh[m], &yl[m]);
+  auto front = [&](int m) -> int {
+    int e;
+    if ((e = combine(s0 + m, yh[m], yl[m]))) return e;
+    return dd_prep_assemble(c, L[m], yh[m], yl[m], c->status);
+  };
+  auto lu = [&](int m0) -> int {
+    Fac F[BLU_GMAX];
+    for (int q = 0; q < G; ++q) F[q] = L[m0 + q].F;
+    return enqueue_lu_group(c, F, G);
+  };
+  const hipStream_t main = c->stream, ls = c->lus[0];
+  for (int m = G; m < SDC_NODES; ++m)
+    if ((rc = front(m))) return rc;
+  HIPCHK(hipEventRecord(c->sdc_ev, main));
+  HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
+  c->stream = ls;
+  rc = lu(G);
+  c->stream = main;
+  if (rc) return rc;
+  HIPCHK(hipEventRecord(c->sdc_ev, ls));
+  for (int m = 0; m < G; ++m)
+    if ((rc = front(m))) return rc;
+  if ((rc = lu(0))) return rc;
+  for (int m = 0; m < SDC_NODES; ++m) {
+    if (m == G) HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
+    if ((rc = dd_rhs_tail(c, L[m], yh[m], yl[m], tau, g, c->sdd_Kh + (s0 + m) * n2, c->sdd_Kl + (s0 + m) * n2)))
+      return rc;
+  }
   return 0;
 }
 
@@ -2874,6 +2977,9 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   if ((rc = ensure_dd(c))) return rc;
   if ((rc = dd_tables(c, N))) return rc;
   if ((rc = ensure_sdc_dd(c))) return rc;
+  // the sweeps' nodes together (a one-stream context: stage by stage)
+  const bool grouped = c->overlap;
+  if (grouped && (rc = ensure_sdd_lanes(c))) return rc;
   c->dd_ready = false;    // the march replaces the double-double and FP64 factors
   c->dtn_ready = false;
   hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
@@ -2903,7 +3009,7 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   else
     HIPCHK(hipMemsetAsync(c->sdd_yl, 0, n2 * 8, c->stream));
   const int blocks = (int)std::min<size_t>((n2 + 255) / 256, 4096);
-  auto combine = [&](int row, double* oh, double* ol) -> int {
+  const std::function<int(int, double*, double*)> combine = [&](int row, double* oh, double* ol) -> int {
     hipLaunchKernelGGL(k_dd_sdc_combine, dim3(blocks), dim3(256), 0, c->stream, c->sdd_yh, c->sdd_yl, c->sdd_Kh,
                        c->sdd_Kl, n2, c->sdd_j + row * SDC_MAXNZ, c->sdd_wh + row * SDC_MAXNZ,
                        c->sdd_wl + row * SDC_MAXNZ, c->sdd_cnt[row], oh, ol, n2);
@@ -2912,6 +3018,17 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   };
   for (int n = 0; n < nsteps; ++n) {
     for (int s = 0; s < SDC_STAGES; ++s) {
+      if (grouped && s >= SDC_FIRST_SWEEP) {
+        if ((rc = dd_sweep(c, s, tau, g, combine))) {
+          const std::string msg = g_err;   // nothing may still run on the LU stream
+          (void)hipStreamSynchronize(c->lus[0]);
+          (void)hipStreamSynchronize(c->stream);
+          g_err = msg;
+          return rc;
+        }
+        s += SDC_NODES - 1;
+        continue;
+      }
       if ((rc = combine(s, c->sdd_Yh, c->sdd_Yl))) return rc;
       if ((rc = dd_rhs(c, c->sdd_Yh, c->sdd_Yl, tau, g, c->sdd_Kh + s * n2, c->sdd_Kl + s * n2))) return rc;
     }

@@ -45,7 +45,9 @@ def _err(hi, lo, ref):
     return float(np.abs(d.hi).max() / np.abs(ref.hi).max())
 
 
-@pytest.mark.parametrize("N,h,R", [(64, math.inf, 3), (64, 0.7, 5), (128, 1.5, 2), (256, math.inf, 4)])
+# R = 1: the one-column products (the inner-index split of the double-double march)
+@pytest.mark.parametrize("N,h,R", [(64, math.inf, 3), (64, 0.7, 5), (128, 1.5, 2), (256, math.inf, 4),
+                                   (128, 0.7, 1)])
 def test_dd_dtn_matches_the_dd_oracle(N, h, R):
     ww, torch = _ww()
     print(f"dd dtn N={N} h={h} R={R}", flush=True)

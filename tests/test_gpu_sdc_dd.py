@@ -111,3 +111,26 @@ def test_dd_march_without_drdT_and_arguments():
         ctx.shoot_eval_sdc_dd(N, 1.0, 0.0, 1.0, ww.to_dev(np.full(2 * N, -2.0)), None, 1.0, 1)
     assert e.value.name == "WW_EDOMAIN"
     ctx.close()
+
+
+def test_grouped_sweeps_equal_the_stage_by_stage_form(monkeypatch):
+    """The nodes of each correction sweep assembled in lanes of their own and factored in
+    two groups of four (one on the LU stream) give the same bits as every stage in turn
+    (a context created with WW_NO_OVERLAP=1)."""
+    ww, torch = _ww()
+    N = 64
+    qh, ql = _state(N, seed=11, amp=0.04)
+    outs = []
+    for serial in (False, True):
+        if serial:
+            monkeypatch.setenv("WW_NO_OVERLAP", "1")
+        else:
+            monkeypatch.delenv("WW_NO_OVERLAP", raising=False)
+        ctx = ww.Context(n_max=N, r_max=2)
+        o = ctx.shoot_eval_sdc_dd(N, 0.8, 0.005, 1.0, ww.to_dev(qh), ww.to_dev(ql), 4 * 7.0 / 48, 1)
+        torch.cuda.synchronize()
+        outs.append([o["r"][0].cpu().numpy(), o["r"][1].cpu().numpy(), o["drdT"][0].cpu().numpy(),
+                     o["drdT"][1].cpu().numpy(), np.array(o["f"])])
+        ctx.close()
+    for a, b in zip(*outs):
+        assert np.array_equal(a, b)
