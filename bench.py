@@ -306,6 +306,15 @@ def run_sdc_dd(steps=(12, 24, 48)):
         o = ctx.shoot_eval_sdc_dd(N, w.h, w.tau, w.g, q0, None, w.T, ns)
         t = time.perf_counter() - t0
         runs.append((ns, t, o["r"][0].cpu().numpy(), o["r"][1].cpu().numpy(), o["f"]))
+    # the same march with FP32 factors on MFMA for the corrections (a mixed context)
+    cm = ww.Context(n_max=N, r_max=2, mixed=True)
+    cm.shoot_eval_sdc_dd(N, w.h, w.tau, w.g, q0, None, w.T / 12, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    om = cm.shoot_eval_sdc_dd(N, w.h, w.tau, w.g, q0, None, w.T, steps[0])
+    t_mixed = time.perf_counter() - t0
+    cm.close()
+    mixed_run = (steps[0], t_mixed, om["r"][0].cpu().numpy(), om["r"][1].cpu().numpy(), om["f"])
     print("# double-double SDC15 march timed", file=sys.stderr, flush=True)
     ctx.shoot_setup(N, w.h, w.tau, w.g, ww.to_dev(np.zeros((2 * N, 1))), q0)
     r64 = ctx.shoot_eval_sdc(ww.to_dev(np.zeros(1)), w.T, steps[0], jacobian=False)["r"].cpu().numpy()
@@ -324,7 +333,10 @@ def run_sdc_dd(steps=(12, 24, 48)):
            "r_modes_0_32_change_when_halving_dt": [low(runs[i], runs[i + 1]) for i in range(len(runs) - 1)],
            "f_change_when_halving_dt": [abs((runs[i][4][0] - runs[i + 1][4][0]) + (runs[i][4][1] - runs[i + 1][4][1]))
                                         / runs[0][4][0] for i in range(len(runs) - 1)],
-           "r_vs_fp64_sdc": float(np.abs(runs[0][2] + runs[0][3] - r64).max() / scale)}
+           "r_vs_fp64_sdc": float(np.abs(runs[0][2] + runs[0][3] - r64).max() / scale),
+           "fp32_factors": {"steps": steps[0], "ms": 1e3 * t_mixed,
+                            "us_per_evaluation": 1e6 * t_mixed / (113 * steps[0] + 1),
+                            "r_vs_fp64_factors": diff(mixed_run, runs[0])}}
     return out
 
 

@@ -228,7 +228,8 @@ int shoot_eval_sdc(ww_ctx *ctx, const double *params, double T, int nsteps, doub
  * (uv:from:G), tension, zero-mean projection), the filter of eq. (filter) and the step's
  * combinations in double-double (about 32 digits), the nodes and weights to the same
  * precision; the DtN of each stage is dtn_setup_dd / dtn_solve_multi_dd (double-double
- * assembly and residuals, refinement from FP64 factors).  Its own grid: N a power of
+ * assembly and residuals, refinement from FP64 factors, or FP32 factors in a WW_MIXED
+ * context).  Its own grid: N a power of
  * two, 16 <= N <= min(n_max, 1024); depth h (INFINITY for infinite depth), tension tau,
  * gravity g.  q0_hi, q0_lo: the initial state [eta | phi], 2N doubles each on the
  * device (q0_lo may be NULL for zero).  T = T_hi + T_lo, the full period (the march
@@ -254,7 +255,8 @@ int shoot_eval_sdc_dd(ww_ctx *ctx, int N, double h, double tau, double g, const 
  * may be NULL for zero) at depth h (as dtn_setup; h is a double): eta', eta'' by
  * double-double FFTs, exp(+-height) in double-double, A = I/2 + K/N and Gm = G/N of
  * eq. (fred), (G), (K1K2) assembled in double-double from double-double circulant
- * tables, and the FP64 factors (block LU and explicit inverse) of the leading part of A.
+ * tables, and the FP64 factors (block LU and explicit inverse) of the leading part of A
+ * (in a WW_MIXED context: of its FP32 copy, on MFMA).
  * N must be a power of two, 16 <= N <= min(n_max, 1024).  The FP64 factors of an earlier
  * dtn_setup are replaced (dtn_solve_multi then needs a new dtn_setup).  Synchronises.
  * Errors: WW_EINVAL, WW_EDOMAIN (finite depth, h + eta <= 0), WW_ENONFINITE, WW_EPIVOT
@@ -265,7 +267,8 @@ int dtn_setup_dd(ww_ctx *ctx, const double *surface_hi, const double *surface_lo
 /*
  * dtn_solve_multi_dd: G psi for nrhs columns (rhs_hi/rhs_lo: N x nrhs column-major,
  * device; rhs_lo may be NULL) in double-double: mu = A^{-1} psi from the FP64 inverse,
- * then three refinement sweeps r = psi - A mu (double-double products), mu += A_hi^{-1} r;
+ * then three refinement sweeps r = psi - A mu (double-double products), mu += A_hi^{-1} r
+ * (a WW_MIXED context: the FP32 inverse and six sweeps);
  * gamma = mu' and H gamma / 2 by double-double FFTs; G psi = H gamma / 2 + Gm gamma.
  * out_hi/out_lo (N x nrhs, caller-owned), and mu_hi/mu_lo (both or neither). The call
  * synchronises and checks the final residual: max |r| <= 2^-96 max |psi|, else

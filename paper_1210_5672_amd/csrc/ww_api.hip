@@ -1704,6 +1704,7 @@ static void dd_sincos_2pi(long d, long n, dd* s_out, dd* c_out) {
 
 #define DD_WORK 13
 #define DD_SWEEPS 3
+#define DD_SWEEPS_32 6   // with FP32 factors: each sweep gains about 2^-24 cond(A)
 static const double DD_TOL = 1.2621774483536189e-29;   // 2^-96
 static int ensure_dd(ww_ctx* c) {
   if (c->dd_w) return 0;
@@ -1782,15 +1783,16 @@ struct DdLane {
   double *pt_hi, *pt_lo, *Ah, *Al, *Gh, *Gl;
   Fac F;
 };
-static Fac fp64_fac(Fac F) {
-  F.use32 = false;
+// the factors of the corrections: FP64, or FP32 on MFMA in a WW_MIXED context
+static Fac dd_fac(const ww_ctx* c, Fac F) {
+  F.use32 = mixed(c);
   F.lag32 = false;
   F.perm = nullptr;
   F.Gm = nullptr;
   return F;
 }
 static DdLane dd_lane(ww_ctx* c) {
-  return DdLane{c->dd_pt_hi, c->dd_pt_lo, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl, fp64_fac(fac_default(c))};
+  return DdLane{c->dd_pt_hi, c->dd_pt_lo, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl, dd_fac(c, fac_default(c))};
 }
 
 // per-point quantities and the double-double assembly of the surface (sh, sl) into lane
@@ -1803,6 +1805,13 @@ static int dd_prep_assemble(ww_ctx* c, const DdLane& L, const double* sh, const 
   hipLaunchKernelGGL(k_dd_assemble, dim3(Np / WW_TB, Np / 16), dim3(WW_NT), 0, c->stream, L.pt_hi, L.pt_lo, c->n_max,
                      c->dd_tab_hi, c->dd_tab_lo, N, Np, c->finite, L.Ah, L.Al, L.Gh, L.Gl, L.F.A);
   LAUNCHCHK();
+  if (L.F.use32) {
+    if (!L.F.A32) return fail(WW_EHIP, "internal: FP32 factors without their buffer");
+    const size_t nn = (size_t)Np * Np;
+    hipLaunchKernelGGL(k_dd_a32, dim3((int)std::min<size_t>((nn + 255) / 256, 4096)), dim3(256), 0, c->stream, L.F.A,
+                       L.F.A32, nn);
+    LAUNCHCHK();
+  }
   return 0;
 }
 
@@ -1837,12 +1846,18 @@ static int dd_solve_enqueue(ww_ctx* c, const DdLane& L, const double* rhs_hi, co
     hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, psl, Np, 0, Np, nrhs);
   LAUNCHCHK();
   int rc;
-  if ((rc = enqueue_gemm<double>(c, L.F.Mi, 0, psh, nullptr, 1.0, muh, nrhs))) return rc;
+  // corrections from the FP64 inverse, or from the FP32 one (a mixed context: more sweeps)
+  auto corr = [&](const double* B, double* X) -> int {
+    return L.F.use32 ? enqueue_gemm<float>(c, L.F.Mi32, 0, B, nullptr, 1.0, X, nrhs)
+                     : enqueue_gemm<double>(c, L.F.Mi, 0, B, nullptr, 1.0, X, nrhs);
+  };
+  const int sweeps = L.F.use32 ? DD_SWEEPS_32 : DD_SWEEPS;
+  if ((rc = corr(psh, muh))) return rc;
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, mul, Np, 0, Np, nrhs);
   LAUNCHCHK();
-  for (int sweep = 0; sweep < DD_SWEEPS; ++sweep) {
+  for (int sweep = 0; sweep < sweeps; ++sweep) {
     if ((rc = dd_gemm(c, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
-    if ((rc = enqueue_gemm<double>(c, L.F.Mi, 0, rh, nullptr, 1.0, del, nrhs))) return rc;
+    if ((rc = corr(rh, del))) return rc;
     hipLaunchKernelGGL(k_dd_correct, dim3(blocks), dim3(256), 0, c->stream, muh, mul, del, blk);
     LAUNCHCHK();
   }
@@ -2886,7 +2901,7 @@ static DdLane dd_sweep_lane(ww_ctx* c, int m, double** yh, double** yl) {
   double* b = c->sdd_lane + (size_t)m * (4 * nn + 12 * nm);
   *yh = b + 4 * nn + 8 * nm;
   *yl = *yh + 2 * nm;
-  return DdLane{b + 4 * nn, b + 4 * nn + 4 * nm, b, b + nn, b + 2 * nn, b + 3 * nn, fp64_fac(pipe_set(c, m, false))};
+  return DdLane{b + 4 * nn, b + 4 * nn + 4 * nm, b, b + nn, b + 2 * nn, b + 3 * nn, dd_fac(c, pipe_set(c, m, false))};
 }
 
 // The nodes of one correction sweep (stages s0 .. s0 + SDC_NODES - 1) read only slopes of

@@ -379,6 +379,12 @@ __global__ void k_dd_gemv_sum(const double* __restrict__ P_hi, const double* __r
   out_lo[i] = t.lo;
 }
 
+// the FP32 copy of the FP64 leading part of A (the mixed form factors it on MFMA)
+__global__ void k_dd_a32(const double* __restrict__ A, float* __restrict__ A32, size_t n) {
+  for (size_t e = blockIdx.x * (size_t)blockDim.x + threadIdx.x; e < n; e += (size_t)gridDim.x * blockDim.x)
+    A32[e] = (float)A[e];
+}
+
 // mu += delta (double-double plus a double), n entries
 __global__ void k_dd_correct(double* __restrict__ mu_hi, double* __restrict__ mu_lo, const double* __restrict__ delta,
                              size_t n) {

@@ -68,10 +68,12 @@ def test_dd_dtn_matches_the_dd_oracle(N, h, R):
     ctx.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("h", [math.inf, 0.7])
-def test_dd_dtn_against_40_digit_oracle(h):
+def test_dd_dtn_against_40_digit_oracle(h, mixed):
     """The same DtN in 40-digit mpmath arithmetic (oracle/xprec.py running ww_oracle's
-    DtN) at N = 64: the GPU's double-double result to 1e-30."""
+    DtN) at N = 64: the GPU's double-double result to 1e-30, with FP64 factors for the
+    corrections or (a WW_MIXED context) FP32 factors on MFMA and more sweeps."""
     ww, torch = _ww()
     import mpmath
     from oracle import xprec
@@ -80,7 +82,7 @@ def test_dd_dtn_against_40_digit_oracle(h):
     el = _lo(eh, 3)
     rh = np.ascontiguousarray(W.random_rhs(N, R, seed=9))
     rl = _lo(rh, 4)
-    ctx = ww.Context(n_max=N, r_max=R)
+    ctx = ww.Context(n_max=N, r_max=R, mixed=mixed)
     ctx.dtn_setup_dd(ww.to_dev(eh), ww.to_dev(el), h)
     oh, ol = ctx.dtn_solve_multi_dd(ww.to_dev(rh), ww.to_dev(rl))
     oh, ol = oh.cpu().numpy(), ol.cpu().numpy()

@@ -47,12 +47,13 @@ def _rel(hi, lo, ref: D.DD):
 CASES = [(32, math.inf, 0.0, 2, 2 * math.pi / 4), (64, 0.8, 0.005, 1, 4 * 7.0 / 48)]
 
 
-@pytest.mark.parametrize("N,h,tau,nsteps,T", CASES)
-def test_dd_march_matches_the_dd_oracle(N, h, tau, nsteps, T):
+# the second form: FP32 factors on MFMA for the corrections (a WW_MIXED context)
+@pytest.mark.parametrize("N,h,tau,nsteps,T,mixed", [c + (False,) for c in CASES] + [CASES[1] + (True,)])
+def test_dd_march_matches_the_dd_oracle(N, h, tau, nsteps, T, mixed):
     ww, torch = _ww()
-    print(f"dd sdc march N={N} h={h} tau={tau} steps={nsteps}", flush=True)
+    print(f"dd sdc march N={N} h={h} tau={tau} steps={nsteps} mixed={mixed}", flush=True)
     qh, ql = _state(N, seed=N, amp=0.04)
-    ctx = ww.Context(n_max=max(N, 64), r_max=2)
+    ctx = ww.Context(n_max=max(N, 64), r_max=2, mixed=mixed)
     out = ctx.shoot_eval_sdc_dd(N, h, tau, 1.0, ww.to_dev(qh), ww.to_dev(ql), T, nsteps)
     torch.cuda.synchronize()
     ref = S.shoot_eval_sdc_dd(N, h, tau, 1.0, D.DD(qh[:N], ql[:N]), D.DD(qh[N:], ql[N:]), D.DD(T), nsteps)
