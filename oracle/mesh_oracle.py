@@ -1,6 +1,6 @@
 """CPU reference ("oracle") for the non-uniform mesh with time segments of Wilkening &
 Yu (Sec. 2.2 eq. (xi), (rho:def)): the DtN operator, the right-hand sides and the
-DOP853 march on the mapped grid x = xi(alpha), and the regridding between time
+DOP853 (or SDC15) march on the mapped grid x = xi(alpha), and the regridding between time
 segments.
 
 TEST INFRASTRUCTURE ONLY, like oracle/ww_oracle.py (whose spectral operators, cot
@@ -234,6 +234,21 @@ def march_mapped(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, mesh: Mesh, tableau
     return y
 
 
+def march_mapped_sdc(eta0, phi0, Qe0, Qp0, h, tau, g, T, nsteps, mesh: Mesh, ar=O.F64):
+    """nsteps SDC15 steps of dt = T / (4 nsteps) on one mesh: the step of
+    oracle/sdc_oracle.py with the mapped right-hand sides, the filter after every step."""
+    from . import sdc_oracle as S
+    c = S.radau_iia_nodes()
+    Sm = S.integration_matrix(c)
+    dt = T / (4 * nsteps)
+    F = lambda y: list(rhs_mapped(y[0], y[1], y[2], y[3], h, tau, g, mesh, ar))
+    y = [eta0, phi0, Qe0, Qp0]
+    for _ in range(nsteps):
+        y = S.sdc_step(y, F, dt, c, Sm)
+        y = [O.filt(v, ar) if v is not None else None for v in y]
+    return y
+
+
 # --------------------------------------------------------------------------------
 # regridding between segments
 # --------------------------------------------------------------------------------
@@ -263,13 +278,15 @@ def regrid(values, old: Mesh, new: Mesh):
 # --------------------------------------------------------------------------------
 
 def shoot_eval_segments(N, h, tau, g, basis, q_fixed, params, T, segments, jacobian=True, tableau=None,
-                        ar=O.F64):
+                        ar=O.F64, scheme="dop853"):
     """r, J, dr/dT, f after marching the segments to T/4 (readings M1-M5).
 
     segments: dicts with N (segments[0]["N"] == N), nsteps, theta, rho, refine_at.
     basis (2N, M) and q_fixed (2N,) are values on the first segment's mesh.  `ar`: one of
     the FP64 backends of ww_oracle (the alternates round the same scheme differently,
-    to measure the rounding floor)."""
+    to measure the rounding floor).  scheme: "dop853" or "sdc" (SDC15 steps, Sec. 2.2)."""
+    if scheme not in ("dop853", "sdc"):
+        raise ValueError(scheme)
     check_segments(segments)
     if segments[0]["N"] != N:
         raise ValueError("the basis lives on the first segment's grid")
@@ -285,7 +302,11 @@ def shoot_eval_segments(N, h, tau, g, basis, q_fixed, params, T, segments, jacob
             if jacobian:
                 Qe, Qp = regrid(Qe, mesh, new), regrid(Qp, mesh, new)
         mesh = new
-        eta, phi, Qe, Qp = march_mapped(eta, phi, Qe, Qp, h, tau, g, seg["theta"] * T, seg["nsteps"], mesh, tableau, ar)
+        if scheme == "sdc":
+            eta, phi, Qe, Qp = march_mapped_sdc(eta, phi, Qe, Qp, h, tau, g, seg["theta"] * T, seg["nsteps"], mesh, ar)
+        else:
+            eta, phi, Qe, Qp = march_mapped(eta, phi, Qe, Qp, h, tau, g, seg["theta"] * T, seg["nsteps"], mesh,
+                                            tableau, ar)
     w = np.sqrt(mesh.E / mesh.N)
     r = w * phi
     _, phi_t, _, _ = rhs_mapped(eta, phi, None, None, h, tau, g, mesh, ar)

@@ -24,6 +24,7 @@ import pytest
 
 from oracle import mesh_oracle as MO
 from oracle import ww_oracle as O
+from paper_1210_5672_amd import workloads as W
 
 
 def test_mesh_closed_forms():
@@ -179,3 +180,35 @@ def test_linear_standing_wave_on_a_mapped_grid(h):
     m = res["mesh"]
     exact = -(g * a / om) * math.sin(om * T / 4) * np.cos(k * m.xi)
     assert np.max(np.abs(res["phi"] - exact)) < 10 * a * np.max(np.abs(exact))   # relative 10 a (P6)
+
+
+def test_sdc_on_one_uniform_segment_is_the_uniform_sdc_march():
+    """rho = 1 (E = 1): the mapped SDC15 march of one segment equals the uniform SDC15
+    oracle (a different right-hand-side code) to rounding."""
+    from oracle import sdc_oracle as S
+    N, M = 32, 2
+    basis = W.cosine_basis(N, M)
+    p = np.array([0.03, 0.002])
+    q = np.zeros(2 * N)
+    a = MO.shoot_eval_segments(N, math.inf, 0.0, 1.0, basis, q, p, 2 * math.pi,
+                               [dict(N=N, nsteps=2, theta=1.0, rho=1.0)], scheme="sdc")
+    b = S.shoot_eval_sdc(N, math.inf, 0.0, 1.0, basis, q, p, 2 * math.pi, 2)
+    for k in ("r", "J", "drdT"):
+        assert np.abs(a[k] - b[k]).max() < 1e-13 * np.abs(b[k]).max(), k
+
+
+def test_sdc_segments_agree_with_dop853_segments():
+    """Two segments (the second refined, rho = 0.6) marched by SDC15 and by DOP853 at steps
+    that resolve the solution: the two time integrators agree."""
+    N, M = 32, 2
+    basis = W.cosine_basis(N, M)
+    p = np.array([0.03, 0.002])
+    q = np.zeros(2 * N)
+    segs_s = [dict(N=32, nsteps=2, theta=0.3, rho=1.0), dict(N=48, nsteps=4, theta=0.7, rho=0.6)]
+    segs_r = [dict(N=32, nsteps=16, theta=0.3, rho=1.0), dict(N=48, nsteps=40, theta=0.7, rho=0.6)]
+    a = MO.shoot_eval_segments(N, math.inf, 0.0, 1.0, basis, q, p, 2 * math.pi, segs_s, scheme="sdc")
+    b = MO.shoot_eval_segments(N, math.inf, 0.0, 1.0, basis, q, p, 2 * math.pi, segs_r)
+    for k in ("r", "J"):
+        e = np.abs(a[k] - b[k]).max() / np.abs(b[k]).max()
+        print(k, e)
+        assert e < 1e-10, k
