@@ -321,6 +321,16 @@ int shoot_eval_segments(ww_ctx *ctx, const double *params, double T, int nseg, c
                         double *r, double *J, double *drdT, double *f);
 
 /*
+ * shoot_eval_segments_sdc: shoot_eval_segments with every segment's nsteps_l steps taken
+ * by SDC15 (as shoot_eval_sdc) instead of DOP853: the combination the paper uses for its
+ * sharp-crested waves (Sec. 2.2).  Arguments, regridding, outputs and errors as
+ * shoot_eval_segments; step counts as for shoot_eval_sdc (the explicit scheme's dt must
+ * resolve the largest frequency each segment's filter passes).  Synchronises.
+ */
+int shoot_eval_segments_sdc(ww_ctx *ctx, const double *params, double T, int nseg, const ww_segment *segs,
+                            double *r, double *J, double *drdT, double *f);
+
+/*
  * shoot_eval_batch: shoot_eval for n_inst independent instances (continuation
  * instances of uneven N, depth, tension, M and step count), each with its own context
  * (distinct contexts; give them distinct streams for the instances to overlap).  Each

@@ -2227,16 +2227,26 @@ static int seg_check(const ww_ctx* c, int nseg, const ww_segment* sg) {
   return 0;
 }
 
+// SDC15 (defined with the stepper below): work arrays, the two-stream form's set-up, and
+// nsteps steps of dt (two streams, or stage by stage)
+static int ensure_sdc(ww_ctx* c);
+static int ensure_sdc_groups(ww_ctx* c);
+static int sdc_steps(ww_ctx* c, bool cols, double dt, int nsteps, bool two);
+
 // one segmented march in the current fallback mode: segment 0 starts from the initial
 // state on its mesh; at each later segment the state (and the Jacobian columns) is
 // regridded to the new mesh, then the segment marches its steps of theta_l T / (4
 // nsteps_l) each; the outputs are taken on the last mesh
+// (sdc: every segment's steps by SDC15 instead of DOP853)
 static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* sg, double* r, double* J,
-                   double* drdT, double* f, int* st, int* where) {
+                   double* drdT, double* f, int* st, int* where, bool sdc) {
   const bool cols = (J != nullptr) && c->M > 0;
   const bool two = c->overlap && !pivoted(c);
+  const bool sdc_two = sdc && two && !c->gm_active;
   int rc;
   if (pivoted(c) && (rc = ensure_pivot_buffers(c))) return rc;
+  if (sdc && (rc = ensure_sdc(c))) return rc;
+  if (sdc_two && (rc = ensure_sdc_groups(c))) return rc;
   if (!c->mesh && (rc = dalloc(c, (void**)&c->mesh, (size_t)MESH_COUNT * c->n_max * 8))) return rc;
   for (int l = 0; l < nseg; ++l) {
     const double Tl = sg[l].theta * T;
@@ -2252,7 +2262,15 @@ static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww
     if (l == 0) {
       if ((rc = pipe_join(c))) return rc;   // a previous march's streams
       if ((rc = tables())) return rc;
-      if ((rc = shoot_prepare(c, params, Tl, sg[0].nsteps, cols, two))) return rc;
+      if (sdc) {   // the state only: no Runge-Kutta step graph
+        const bool ug = c->use_graph;
+        c->use_graph = false;
+        rc = shoot_prepare(c, params, Tl, sg[0].nsteps, cols, false);
+        c->use_graph = ug;
+        if (rc) return rc;
+      } else if ((rc = shoot_prepare(c, params, Tl, sg[0].nsteps, cols, two))) {
+        return rc;
+      }
     } else {
       if ((rc = pipe_join(c))) return rc;   // the lagged march's LU and column streams
       const int No = c->N, Nn = sg[l].N;
@@ -2267,6 +2285,9 @@ static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww
       hipLaunchKernelGGL(k_regrid_apply, dim3((Nn + 63) / 64, (ncols + 63) / 64), dim3(WW_NT), 0, c->stream, c->A,
                          c->Ys, c->y, Nn, No, ncols);
       LAUNCHCHK();
+      if (sdc) {
+        if ((rc = tables())) return rc;
+      } else {
       double coef[COEF_SIZE];
       coef_fill(c, Tl, sg[l].nsteps, coef);
       HIPCHK(hipStreamSynchronize(c->stream));
@@ -2281,9 +2302,14 @@ static int seg_run(ww_ctx* c, const double* params, double T, int nseg, const ww
       } else if (graphed(c) && (rc = ensure_step_graph(c, cols, two))) {
         return rc;
       }
+      }
     }
-    for (int n = 0; n < sg[l].nsteps; ++n)
-      if ((rc = shoot_one_step(c, cols, two))) return rc;
+    if (sdc) {
+      if ((rc = sdc_steps(c, cols, Tl / (4.0 * sg[l].nsteps), sg[l].nsteps, sdc_two))) return rc;
+    } else {
+      for (int n = 0; n < sg[l].nsteps; ++n)
+        if ((rc = shoot_one_step(c, cols, two))) return rc;
+    }
   }
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
     const std::string msg = g_err;
@@ -2461,6 +2487,31 @@ static int ensure_sdc(ww_ctx* c) {
   return dalloc(c, (void**)&c->sdc_K, (size_t)SDC_STAGES * st * 8);
 }
 
+// the base and column right-hand sides of an SDC stage (mapped-grid kernels on a
+// non-uniform mesh)
+static int sdc_base_rhs(ww_ctx* c, const double* Ys, double* aux, double* kout) {
+  if (c->mapped)
+    hipLaunchKernelGGL(k_base_rhs_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, c->gphi0, aux,
+                       c->mesh, c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N,
+                       c->g, c->tau);
+  else
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, c->gphi0, aux,
+                       c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
+                       c->tau);
+  LAUNCHCHK();
+  return 0;
+}
+static int sdc_col_rhs(ww_ctx* c, const double* Ys, const double* aux, double* kout) {
+  if (c->mapped)
+    hipLaunchKernelGGL(k_col_rhs_map, dim3(c->M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, c->Gpsi, c->Np,
+                       aux, c->mesh, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+  else
+    hipLaunchKernelGGL(k_col_rhs, dim3(c->M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, c->Gpsi, c->Np, aux,
+                       c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
+  LAUNCHCHK();
+  return 0;
+}
+
 // the factor sets, the LU and column streams and the lane events of the two-stream form
 // (first use)
 static int ensure_sdc_groups(ww_ctx* c) {
@@ -2529,10 +2580,7 @@ struct SdcStep {
     int rc;
     double* kout = c->sdc_K + (size_t)s * ks;
     if ((rc = enqueue_dtn_cols(c, F[q], rhsn(q), c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
-    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysn(q), c->gphi0,
-                       F[q].aux, c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N,
-                       c->g, c->tau);
-    LAUNCHCHK();
+    if ((rc = sdc_base_rhs(c, ysn(q), F[q].aux, kout))) return rc;
     if (!cols) return 0;
     HIPCHK(hipEventRecord(c->sdc_evB[q], c->stream));
     const hipStream_t main = c->stream;
@@ -2555,10 +2603,7 @@ struct SdcStep {
                        c->n_max, c->Psi, c->Np, c->N, M);
     LAUNCHCHK();
     if ((rc = enqueue_dtn_cols(c, F[q], c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
-    hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, ysn(q), c->Gpsi, c->Np,
-                       F[q].aux, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
-    LAUNCHCHK();
-    return 0;
+    return sdc_col_rhs(c, ysn(q), F[q].aux, kout);
   }
   int sweep(int s0) {
     static_assert(SDC_NODES == 2 * BLU_GMAX, "a sweep is factored in two groups");
@@ -2624,10 +2669,7 @@ static int enqueue_col_chain_at(ww_ctx* c, const double* ysrc, double* kout, con
                      F.aux, c->n_max, c->Psi, c->Np, c->N, M);
   LAUNCHCHK();
   if ((rc = enqueue_dtn_cols(c, F, c->Psi, c->Ytmp, c->Mu, c->Gam, c->HG, c->Gpsi, c->Rr, M))) return rc;
-  hipLaunchKernelGGL(k_col_rhs, dim3(M), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, c->Ys, c->Gpsi, c->Np,
-                     F.aux, c->n_max, kout, c->tw, c->sig, c->N, c->g, c->tau);
-  LAUNCHCHK();
-  return 0;
+  return sdc_col_rhs(c, c->Ys, F.aux, kout);
 }
 
 // one SDC15 step of dt: every stage's state by k_sdc_combine, its base chain and column
@@ -2656,6 +2698,30 @@ static int enqueue_sdc_step(ww_ctx* c, bool cols, double dt) {
   return 0;
 }
 
+static int sdc_steps(ww_ctx* c, bool cols, double dt, int nsteps, bool two) {
+  int rc;
+  if (!two) {
+    for (int n = 0; n < nsteps; ++n)
+      if ((rc = enqueue_sdc_step(c, cols, dt))) return rc;
+    return 0;
+  }
+  // every lane starts free
+  for (int q = 0; q < SDC_NODES; ++q) HIPCHK(hipEventRecord(c->sdc_evC[q], c->stream));
+  for (int n = 0; n < nsteps; ++n) {
+    SdcStep st(c, cols, dt);
+    if ((rc = st.step())) {
+      // nothing of the march may still run on the column or LU stream
+      const std::string msg = g_err;
+      (void)hipStreamSynchronize(c->side);
+      (void)hipStreamSynchronize(c->lus[0]);
+      (void)hipStreamSynchronize(c->stream);
+      g_err = msg;
+      return rc;
+    }
+  }
+  return 0;
+}
+
 static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double* r, double* J, double* drdT,
                    double* f, int* st, int* where) {
   const bool cols = (J != nullptr) && c->M > 0;
@@ -2671,26 +2737,7 @@ static int sdc_run(ww_ctx* c, const double* params, double T, int nsteps, double
   // Krylov workspace per context) and in a one-stream context
   const bool two = c->overlap && !pivoted(c) && !c->gm_active;
   if (two && (rc = ensure_sdc_groups(c))) return rc;
-  const double dt = T / (4.0 * nsteps);
-  if (two) {
-    // every lane starts free
-    for (int q = 0; q < SDC_NODES; ++q) HIPCHK(hipEventRecord(c->sdc_evC[q], c->stream));
-    for (int n = 0; n < nsteps; ++n) {
-      SdcStep st(c, cols, dt);
-      if ((rc = st.step())) {
-        // nothing of the march may still run on the column or LU stream
-        const std::string msg = g_err;
-        (void)hipStreamSynchronize(c->side);
-        (void)hipStreamSynchronize(c->lus[0]);
-        (void)hipStreamSynchronize(c->stream);
-        g_err = msg;
-        return rc;
-      }
-    }
-  } else {
-    for (int n = 0; n < nsteps; ++n)
-      if ((rc = enqueue_sdc_step(c, cols, dt))) return rc;
-  }
+  if ((rc = sdc_steps(c, cols, T / (4.0 * nsteps), nsteps, two))) return rc;
   if ((rc = shoot_finish(c, cols, r, J, drdT, f))) {
     const std::string msg = g_err;
     (void)hipStreamSynchronize(c->stream);
@@ -3066,8 +3113,11 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   return 0;
 }
 
-int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,
-                        double* J, double* drdT, double* f) {
+}   // extern "C"
+
+// the segmented march (DOP853, or SDC15 steps) with its fallbacks
+static int segments_eval(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,
+                         double* J, double* drdT, double* f, bool sdc) {
   if (!c || !r || (!params && c->M > 0)) return fail(WW_EINVAL, "null argument");
   if (int rj = pipe_join(c)) return rj;
   if (!c->shoot_ready) return fail(WW_ENOSETUP, "shoot_eval_segments before shoot_setup");
@@ -3079,10 +3129,10 @@ int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, con
     explicit Mapped(ww_ctx* cc) : c(cc) { c->mapped = true; }
     ~Mapped() { c->mapped = false; }
   } mapped_scope(c);
-  c->fb = c->lag_off ? WW_FB_DIRECT : 0;
+  c->fb = (c->lag_off && !sdc) ? WW_FB_DIRECT : 0;
   for (;;) {
     int st = 0, where = 0;
-    if ((rc = seg_run(c, params, T, nseg, segs, r, J, drdT, f, &st, &where))) return rc;
+    if ((rc = seg_run(c, params, T, nseg, segs, r, J, drdT, f, &st, &where, sdc))) return rc;
     const unsigned nf = next_fallback(c, st);
     if ((st & 32) && !strict(c)) c->lag_off = true;
     if (!nf) {
@@ -3092,6 +3142,18 @@ int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, con
     }
     c->fb |= nf;
   }
+}
+
+extern "C" {
+
+int shoot_eval_segments(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,
+                        double* J, double* drdT, double* f) {
+  return segments_eval(c, params, T, nseg, segs, r, J, drdT, f, false);
+}
+
+int shoot_eval_segments_sdc(ww_ctx* c, const double* params, double T, int nseg, const ww_segment* segs, double* r,
+                            double* J, double* drdT, double* f) {
+  return segments_eval(c, params, T, nseg, segs, r, J, drdT, f, true);
 }
 
 int shoot_eval_batch(int n_inst, ww_ctx* const* ctx, const double* const* params, const double* T,

@@ -81,7 +81,7 @@ EXPORTS = ["ww_create", "ww_destroy", "ww_set_stream", "ww_set_tableau", "dtn_se
            "ww_thin_svd", "ww_levmar", "ww_lm_default_opts", "ww_bfgs", "ww_bfgs_default_opts",
            "dtn_solve_multi_noalloc", "ww_next_fallback", "ww_get_tuning", "ww_set_tuning",
            "shoot_eval_segments", "dtn_setup_dd", "dtn_solve_multi_dd", "shoot_eval_sdc",
-           "shoot_eval_sdc_dd"]
+           "shoot_eval_sdc_dd", "shoot_eval_segments_sdc"]
 
 
 class WWError(RuntimeError):
@@ -120,6 +120,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib.shoot_eval.argtypes = [P, P, D, I, P, P, P, DP]
     lib.shoot_adjoint.argtypes = [P, P, D, I, I, P, DP, DP]
     lib.shoot_eval_segments.argtypes = [P, P, D, I, ctypes.POINTER(Segment), P, P, P, DP]
+    lib.shoot_eval_segments_sdc.argtypes = [P, P, D, I, ctypes.POINTER(Segment), P, P, P, DP]
     lib.dtn_setup_dd.argtypes = [P, P, P, D, I]
     lib.shoot_eval_sdc.argtypes = [P, P, D, I, P, P, P, DP]
     lib.shoot_eval_sdc_dd.argtypes = [P, I, D, D, D, P, P, D, D, I, P, P, P, P, DP]
@@ -296,8 +297,13 @@ class Context:
                                           _ptr(dl), f))
         return dict(r=(rh, rl), drdT=(dh, dl) if drdT else None, f=(f[0], f[1]))
 
+    def shoot_eval_segments_sdc(self, params: torch.Tensor, T: float, segments, jacobian: bool = True,
+                                drdT: bool = True):
+        """shoot_eval_segments with SDC15 steps (shoot_eval_segments_sdc)."""
+        return self.shoot_eval_segments(params, T, segments, jacobian, drdT, _fn=self.lib.shoot_eval_segments_sdc)
+
     def shoot_eval_segments(self, params: torch.Tensor, T: float, segments, jacobian: bool = True,
-                            drdT: bool = True):
+                            drdT: bool = True, _fn=None):
         """The march over time segments on non-uniform meshes (shoot_eval_segments).
         segments: dicts with N, nsteps, theta, rho and refine_at (REFINE_PI default);
         the outputs live on the last segment's grid."""
@@ -310,8 +316,9 @@ class Context:
         Jc = torch.empty((M, N), dtype=torch.float64, device=dev) if jacobian else None
         d = torch.empty(N, dtype=torch.float64, device=dev) if drdT else None
         f = ctypes.c_double(0.0)
-        _check(self.lib.shoot_eval_segments(self.ptr, _ptr(params.contiguous()), float(T), len(segments), segs,
-                                            _ptr(r), _ptr(Jc), _ptr(d), ctypes.byref(f)))
+        fn = _fn if _fn is not None else self.lib.shoot_eval_segments
+        _check(fn(self.ptr, _ptr(params.contiguous()), float(T), len(segments), segs, _ptr(r), _ptr(Jc), _ptr(d),
+                  ctypes.byref(f)))
         return dict(r=r, J=Jc.t() if jacobian else None, drdT=d, f=f.value)
 
     def dtn_setup_dd(self, surface_hi: torch.Tensor, surface_lo: torch.Tensor | None, h: float):

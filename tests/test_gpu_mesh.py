@@ -2,7 +2,9 @@
 (rho:def)) on the GPU against the mesh oracle, element by element, through the C ABI:
 regridded segments with ragged tiles (N = 48, 72, 96 pad to 64 and 128), infinite and
 finite depth with tension, both refinement sides, both precision forms, base-only
-marches, the reduction to shoot_eval at rho = 1, and the argument checks."""
+marches, the reduction to shoot_eval at rho = 1, and the argument checks; and the same
+segments marched by SDC15 (shoot_eval_segments_sdc) against the mesh oracle's SDC15
+march."""
 import math
 
 import numpy as np
@@ -214,3 +216,57 @@ def test_segment_argument_checks():
                                            dict(N=128, nsteps=3, theta=0.5, rho=0.5)])
     assert np.isfinite(out["r"].cpu().numpy()).all()
     ctx.close()
+
+
+# SDC15 on segments: far fewer steps than DOP853, each within the explicit scheme's
+# stability (omega_max dt <= 2 on every segment's grid)
+SDC_CASES = {
+    "deep2": dict(N=64, h=math.inf, tau=0.0, M=6, T=2 * math.pi,
+                  segs=[dict(N=64, nsteps=2, theta=0.3, rho=1.0, refine_at=0),
+                        dict(N=96, nsteps=4, theta=0.7, rho=0.5, refine_at=0)]),
+    "shallow2": dict(N=48, h=0.8, tau=0.005, M=4, T=7.0,
+                     segs=[dict(N=48, nsteps=4, theta=0.4, rho=1.0, refine_at=1),
+                           dict(N=72, nsteps=10, theta=0.6, rho=0.6, refine_at=1)]),
+}
+
+
+def _sdc_gpu(ww, c, basis, qf, params, mixed=False):
+    nmax = max(max(q["N"] for q in c["segs"]), 64)
+    ctx = ww.Context(n_max=nmax, r_max=c["M"] + 1, mixed=mixed)
+    ctx.shoot_setup(c["N"], c["h"], c["tau"], 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    return ctx, ctx.shoot_eval_segments_sdc(ww.to_dev(params), c["T"], c["segs"])
+
+
+@pytest.mark.parametrize("mixed", [False, True])
+@pytest.mark.parametrize("case", sorted(SDC_CASES))
+def test_sdc_segments_match_the_oracle(case, mixed):
+    ww, torch = _ww()
+    print(f"sdc segments {case} mixed={mixed}", flush=True)
+    c = SDC_CASES[case]
+    basis, qf, params = _problem(c["N"], c["M"], seed=len(case))
+    ref = MO.shoot_eval_segments(c["N"], c["h"], c["tau"], 1.0, basis, qf, params, c["T"], c["segs"], scheme="sdc")
+    ctx, out = _sdc_gpu(ww, c, basis, qf, params, mixed)
+    assert out["r"].shape[0] == c["segs"][-1]["N"]
+    _check(out, ref, (qf + basis @ params)[:c["N"]], tau=c["tau"])
+    assert ctx.fallbacks() == 0
+    ctx.close()
+
+
+def test_sdc_segments_two_streams_equal_one(monkeypatch):
+    """The two-stream SDC15 form on mapped grids gives the bits of the one-stream form."""
+    ww, torch = _ww()
+    c = SDC_CASES["shallow2"]
+    basis, qf, params = _problem(c["N"], c["M"], seed=3)
+    outs = []
+    for serial in (False, True):
+        if serial:
+            monkeypatch.setenv("WW_NO_OVERLAP", "1")
+        else:
+            monkeypatch.delenv("WW_NO_OVERLAP", raising=False)
+        ctx, o = _sdc_gpu(ww, c, basis, qf, params)
+        torch.cuda.synchronize()
+        outs.append({k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in o.items()})
+        ctx.close()
+    for k in ("r", "J", "drdT"):
+        assert np.array_equal(outs[0][k], outs[1][k]), k
+    assert outs[0]["f"] == outs[1]["f"]
