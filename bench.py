@@ -260,6 +260,12 @@ def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
     sdc, t_sdc = timed(lambda: ctx.shoot_eval_sdc(p, w.T, sdc_steps), reps)
     fb = ctx.fallbacks()
     sdc_f, t_sdc_f = timed(lambda: ctx.shoot_eval_sdc(p, w.T, sdc_steps, jacobian=False), reps)
+    # f-only on GMRES base solves (no LU): a WW_GMRES context
+    cg = ww.Context(n_max=w.N, r_max=w.M + 1, gmres=True)
+    cg.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    sdc_g, t_sdc_g = timed(lambda: cg.shoot_eval_sdc(p, w.T, sdc_steps, jacobian=False), reps)
+    fb_g = cg.fallbacks()
+    cg.close()
     rk, t_rk = timed(lambda: ctx.shoot_eval(p, w.T, w.nsteps), 1)
     rk_f, t_rk_f = timed(lambda: ctx.shoot_eval(p, w.T, w.nsteps, jacobian=False), 1)
     print("# SDC15 march timed", file=sys.stderr, flush=True)
@@ -271,7 +277,9 @@ def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
            "with_jacobian": {"sdc_ms": 1e3 * t_sdc, "dop853_ms": 1e3 * t_rk, "speedup": t_rk / t_sdc,
                              "us_per_evaluation": 1e6 * t_sdc / ev},
            "f_only": {"sdc_ms": 1e3 * t_sdc_f, "dop853_ms": 1e3 * t_rk_f, "speedup": t_rk_f / t_sdc_f,
-                      "us_per_evaluation": 1e6 * t_sdc_f / ev},
+                      "us_per_evaluation": 1e6 * t_sdc_f / ev,
+                      "gmres": {"sdc_ms": 1e3 * t_sdc_g, "us_per_evaluation": 1e6 * t_sdc_g / ev, "fallbacks": fb_g,
+                                "r_vs_lu": rel(sdc_g["r"], sdc_f["r"])}},
            "fallbacks": fb,
            "sdc_vs_dop853": {"r": rel(sdc["r"], rk["r"]), "drdT": rel(sdc["drdT"], rk["drdT"]),
                              "r_f_only": rel(sdc_f["r"], rk_f["r"]),

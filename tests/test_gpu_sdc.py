@@ -102,3 +102,20 @@ def test_two_stream_form_equals_the_one_stream_form(mixed, monkeypatch):
     for k in ("r", "J", "drdT"):
         assert np.array_equal(outs[0][k], outs[1][k]), k
     assert outs[0]["f"] == outs[1]["f"]
+
+
+def test_sdc_f_only_with_gmres_base_solves():
+    """A WW_GMRES context marches SDC15 without Jacobian columns on GMRES base solves (no
+    LU), each under the 2^-43 residual test: against the oracle's SDC15 march."""
+    ww, torch = _ww()
+    N, M = 64, 2
+    basis = W.cosine_basis(N, M)
+    p = np.array([0.03, 0.002])
+    ctx = ww.Context(n_max=N, r_max=M + 1, gmres=True)
+    ctx.shoot_setup(N, 0.8, 0.005, 1.0, ww.to_dev(basis), ww.to_dev(np.zeros(2 * N)))
+    out = ctx.shoot_eval_sdc(ww.to_dev(p), 7.0 / 3, 4, jacobian=False)
+    ref = S.shoot_eval_sdc(N, 0.8, 0.005, 1.0, basis, np.zeros(2 * N), p, 7.0 / 3, 4, jacobian=False)
+    e = relerr(out["r"].cpu().numpy(), ref["r"])
+    print(f"gmres sdc r {e:.2e}", flush=True)
+    assert e < TOL and ctx.fallbacks() == 0
+    ctx.close()
