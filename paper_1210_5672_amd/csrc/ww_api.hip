@@ -144,6 +144,8 @@ struct ww_ctx {
   // per lane (SDC_NODES lanes: a factor set of the ring and the per-node buffers above):
   // the base chain that last used it (main stream), its column chain (column stream)
   hipEvent_t sdc_evB[SDC_NODES] = {}, sdc_evC[SDC_NODES] = {};
+  // the base-chain scratch of the sweep nodes whose chains run on the LU stream (6 Np_max)
+  double* sdc_b2 = nullptr;
   // the base march in double-double (shoot_eval_sdc_dd), allocated at first use: state
   // and stage state (2 n_max, hi and lo), the slopes (SDC_STAGES + 1 slots: the last
   // for the right-hand side at the final state), G phi, the filter symbol, the sparse
@@ -2489,15 +2491,14 @@ static int ensure_sdc(ww_ctx* c) {
 
 // the base and column right-hand sides of an SDC stage (mapped-grid kernels on a
 // non-uniform mesh)
-static int sdc_base_rhs(ww_ctx* c, const double* Ys, double* aux, double* kout) {
+static int sdc_base_rhs(ww_ctx* c, const double* Ys, const double* gphi, double* aux, double* kout) {
   if (c->mapped)
-    hipLaunchKernelGGL(k_base_rhs_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, c->gphi0, aux,
+    hipLaunchKernelGGL(k_base_rhs_map, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, gphi, aux,
                        c->mesh, c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N,
                        c->g, c->tau);
   else
-    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, c->gphi0, aux,
-                       c->n_max, kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g,
-                       c->tau);
+    hipLaunchKernelGGL(k_base_rhs, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, Ys, gphi, aux, c->n_max,
+                       kout, (unsigned long long*)nullptr, 0.0, (int*)nullptr, c->tw, c->sig, c->N, c->g, c->tau);
   LAUNCHCHK();
   return 0;
 }
@@ -2522,6 +2523,8 @@ static int ensure_sdc_groups(ww_ctx* c) {
     if (!c->sdc_evB[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evB[i], hipEventDisableTiming));
     if (!c->sdc_evC[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evC[i], hipEventDisableTiming));
   }
+  int rc;
+  if (!c->sdc_b2 && (rc = dalloc(c, (void**)&c->sdc_b2, (size_t)6 * c->np_max * 8))) return rc;
   return ensure_ring(c, SDC_NODES);
 }
 
@@ -2542,6 +2545,11 @@ struct SdcStep {
   size_t ks;
   Fac F[SDC_NODES];
   int lastq = -1;   // lane of the last column chain
+  // base-chain scratch: the context's (main stream), and a second set for the chains
+  // that run on the LU stream
+  struct Bs {
+    double *y0t, *mu0, *gam0, *hg0, *gphi0, *rr0;
+  } bm, b2;
 
   SdcStep(ww_ctx* cc, bool cl, double d) : c(cc), cols(cl), dt(d), ks(kstride(cc)) {
     for (int m = 0; m < SDC_NODES; ++m) {
@@ -2549,6 +2557,10 @@ struct SdcStep {
       F[m].lag32 = false;
       F[m].Gm = nullptr;   // the chains read Gm row-major only
     }
+    bm = Bs{c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0};
+    const size_t np = c->np_max;
+    double* w = c->sdc_b2;
+    b2 = Bs{w, w + np, w + 2 * np, w + 3 * np, w + 4 * np, w + 5 * np};
   }
   double* yn(int q) const { return c->sdc_yn + q * ks; }
   double* ysn(int q) const { return c->sdc_ysn + q * ks; }
@@ -2574,13 +2586,13 @@ struct SdcStep {
     LAUNCHCHK();
     return enqueue_assemble(c, F[q], false);
   }
-  // main stream: the base solve and right-hand side (slot s), then the column chain on
-  // the column stream
-  int chains(int s, int q) {
+  // the base solve and right-hand side (slot s) on the current stream with scratch b,
+  // then the column chain on the column stream
+  int chains(int s, int q, const Bs& b) {
     int rc;
     double* kout = c->sdc_K + (size_t)s * ks;
-    if ((rc = enqueue_dtn_cols(c, F[q], rhsn(q), c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0, 1))) return rc;
-    if ((rc = sdc_base_rhs(c, ysn(q), F[q].aux, kout))) return rc;
+    if ((rc = enqueue_dtn_cols(c, F[q], rhsn(q), b.y0t, b.mu0, b.gam0, b.hg0, b.gphi0, b.rr0, 1))) return rc;
+    if ((rc = sdc_base_rhs(c, ysn(q), b.gphi0, F[q].aux, kout))) return rc;
     if (!cols) return 0;
     HIPCHK(hipEventRecord(c->sdc_evB[q], c->stream));
     const hipStream_t main = c->stream;
@@ -2611,12 +2623,14 @@ struct SdcStep {
     const int G = BLU_GMAX;
     const hipStream_t main = c->stream, ls = c->lus[0];
     // the second group first, so that its LU runs beside the first group's work
+    // (its base chains follow on the LU stream with the second scratch set)
     for (int m = G; m < SDC_NODES; ++m)
       if ((rc = front(s0 + m, m))) return rc;
     HIPCHK(hipEventRecord(c->sdc_ev, main));
     HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
     c->stream = ls;
     rc = enqueue_lu_group(c, F + G, G);
+    for (int m = G; m < SDC_NODES && !rc; ++m) rc = chains(s0 + m, m, b2);
     c->stream = main;
     if (rc) return rc;
     HIPCHK(hipEventRecord(c->sdc_ev, ls));
@@ -2624,10 +2638,9 @@ struct SdcStep {
       if ((rc = front(s0 + m, m))) return rc;
     if ((rc = enqueue_lu_group(c, F, G))) return rc;
     for (int m = 0; m < G; ++m)
-      if ((rc = chains(s0 + m, m))) return rc;
+      if ((rc = chains(s0 + m, m, bm))) return rc;
+    // the next stages read this sweep's slopes
     HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
-    for (int m = G; m < SDC_NODES; ++m)
-      if ((rc = chains(s0 + m, m))) return rc;
     return 0;
   }
   int step() {
@@ -2641,7 +2654,7 @@ struct SdcStep {
       const int q = s % SDC_NODES;
       if ((rc = front(s, q))) return rc;
       if ((rc = enqueue_lu(c, F[q]))) return rc;
-      if ((rc = chains(s, q))) return rc;
+      if ((rc = chains(s, q, bm))) return rc;
       ++s;
     }
     // the step's combination in place (after the last column chain) and the filter
