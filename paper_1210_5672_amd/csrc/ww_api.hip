@@ -156,6 +156,8 @@ struct ww_ctx {
   int* sdd_j = nullptr;
   int sdd_cnt[SDC_STAGES + 1] = {};
   double* sdd_lane = nullptr;   // the grouped sweeps' lanes (SDC_NODES of them)
+  // the second group's solve workspace, partials and G phi (hi, lo) of the grouped sweeps
+  double *sdd_w2 = nullptr, *sdd_part2 = nullptr, *sdd_G2 = nullptr;
   int gmap = -1;   // `mapped` of the captured step graph
   int* status = nullptr;
   std::vector<void*> allocs;
@@ -1727,11 +1729,11 @@ static int ensure_dd(ww_ctx* c) {
 
 // out = add + sgn A B in double-double for nrhs columns (ld Np): one column by the
 // inner-index split of k_dd_gemv_part / k_dd_gemv_sum, several by k_dd_gemm
-static int dd_gemm(ww_ctx* c, const double* Ah, const double* Al, const double* Bh, const double* Bl,
+static int dd_gemm(ww_ctx* c, double* part, const double* Ah, const double* Al, const double* Bh, const double* Bl,
                    const double* addh, const double* addl, double sgn, double* outh, double* outl, int nrhs) {
   const int Np = c->Np;
   if (nrhs == 1) {
-    double *Ph = c->dd_part, *Pl = c->dd_part + (size_t)DDGV_KS * c->np_max;
+    double *Ph = part, *Pl = part + (size_t)DDGV_KS * c->np_max;
     hipLaunchKernelGGL(k_dd_gemv_part, dim3(Np / 64, DDGV_KS), dim3(WW_NT), 0, c->stream, Ah, Al, Np, Bh, Bl, Ph, Pl);
     LAUNCHCHK();
     hipLaunchKernelGGL(k_dd_gemv_sum, dim3((Np + 255) / 256), dim3(256), 0, c->stream, Ph, Pl, DDGV_KS, Np, addh,
@@ -1784,6 +1786,7 @@ static size_t dd_lds_bytes(int N) { return (size_t)(3 * N + N / 2) * sizeof(cdd)
 struct DdLane {
   double *pt_hi, *pt_lo, *Ah, *Al, *Gh, *Gl;
   Fac F;
+  double *w, *part;   // the solve's workspace: DD_WORK planes, the one-column product's partials
 };
 // the factors of the corrections: FP64, or FP32 on MFMA in a WW_MIXED context
 static Fac dd_fac(const ww_ctx* c, Fac F) {
@@ -1794,7 +1797,8 @@ static Fac dd_fac(const ww_ctx* c, Fac F) {
   return F;
 }
 static DdLane dd_lane(ww_ctx* c) {
-  return DdLane{c->dd_pt_hi, c->dd_pt_lo, c->dd_Ah, c->dd_Al, c->dd_Gh, c->dd_Gl, dd_fac(c, fac_default(c))};
+  return DdLane{c->dd_pt_hi, c->dd_pt_lo, c->dd_Ah, c->dd_Al, c->dd_Gh,
+                c->dd_Gl,    dd_fac(c, fac_default(c)), c->dd_w, c->dd_part};
 }
 
 // per-point quantities and the double-double assembly of the surface (sh, sl) into lane
@@ -1835,7 +1839,7 @@ static int dd_solve_enqueue(ww_ctx* c, const DdLane& L, const double* rhs_hi, co
                             double* out_hi, double* out_lo, double* mu_hi, double* mu_lo, unsigned long long* mx) {
   const int N = c->N, Np = c->Np;
   const size_t blk = (size_t)Np * nrhs, pl = (size_t)c->np_max * c->r_max;
-  double* w = c->dd_w;
+  double* w = L.w;
   double *psh = w, *psl = w + pl, *muh = w + 2 * pl, *mul = w + 3 * pl, *rh = w + 4 * pl, *rl = w + 5 * pl;
   double *del = w + 6 * pl, *gh = w + 7 * pl, *gl = w + 8 * pl, *hh = w + 9 * pl, *hl = w + 10 * pl;
   double *oh = w + 11 * pl, *ol = w + 12 * pl;
@@ -1858,18 +1862,18 @@ static int dd_solve_enqueue(ww_ctx* c, const DdLane& L, const double* rhs_hi, co
   hipLaunchKernelGGL(k_pad_copy, dim3(blocks), dim3(256), 0, c->stream, psh, Np, mul, Np, 0, Np, nrhs);
   LAUNCHCHK();
   for (int sweep = 0; sweep < sweeps; ++sweep) {
-    if ((rc = dd_gemm(c, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
+    if ((rc = dd_gemm(c, L.part, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
     if ((rc = corr(rh, del))) return rc;
     hipLaunchKernelGGL(k_dd_correct, dim3(blocks), dim3(256), 0, c->stream, muh, mul, del, blk);
     LAUNCHCHK();
   }
-  if ((rc = dd_gemm(c, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
+  if ((rc = dd_gemm(c, L.part, L.Ah, L.Al, muh, mul, psh, psl, -1.0, rh, rl, nrhs))) return rc;
   hipLaunchKernelGGL(k_dd_maxabs, dim3(std::min(blocks, 256)), dim3(256), 0, c->stream, rh, psh, N, Np, nrhs, mx);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_dd_gamma, dim3(nrhs), dim3(WW_NT), dd_lds_bytes(N), c->stream, muh, mul, Np, c->dd_tw, N, gh,
                      gl, hh, hl);
   LAUNCHCHK();
-  if ((rc = dd_gemm(c, L.Gh, L.Gl, gh, gl, hh, hl, 1.0, oh, ol, nrhs))) return rc;
+  if ((rc = dd_gemm(c, L.part, L.Gh, L.Gl, gh, gl, hh, hl, 1.0, oh, ol, nrhs))) return rc;
   const size_t tot = (size_t)N * nrhs;
   const int ob = (int)std::min<size_t>((tot + 255) / 256, 4096);
   hipLaunchKernelGGL(k_pad_copy, dim3(ob), dim3(256), 0, c->stream, oh, Np, out_hi, N, Np, N, nrhs);
@@ -2927,23 +2931,24 @@ static int dd_march_status(ww_ctx* c, int n) {
 // (no host synchronisation: the domain, pivot and residual tests set bits of the status
 // word, read once per step)
 // the solve and right-hand side of a stage whose lane L is assembled and factored
+// (G phi into gh, gl; the residual maxima in mx)
 static int dd_rhs_tail(ww_ctx* c, const DdLane& L, const double* yh, const double* yl, double tau, double g,
-                       double* kh, double* kl) {
+                       double* kh, double* kl, double* gh, double* gl, unsigned long long* mx) {
   int rc;
   const int N = c->N;
-  unsigned long long* mx = (unsigned long long*)(c->sdd_fo + 2);
-  if ((rc = dd_solve_enqueue(c, L, yh + N, yl + N, 1, c->sdd_Gh, c->sdd_Gl, nullptr, nullptr, mx))) return rc;
+  if ((rc = dd_solve_enqueue(c, L, yh + N, yl + N, 1, gh, gl, nullptr, nullptr, mx))) return rc;
   hipLaunchKernelGGL(k_dd_restest, dim3(1), dim3(64), 0, c->stream, mx, DD_TOL, c->status);
   LAUNCHCHK();
-  hipLaunchKernelGGL(k_dd_base_rhs, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, yh, yl, c->sdd_Gh, c->sdd_Gl,
-                     c->sdd_fh, c->sdd_fl, c->dd_tw, N, g, tau, kh, kl);
+  hipLaunchKernelGGL(k_dd_base_rhs, dim3(1), dim3(WW_NT), dd_lds_bytes(N), c->stream, yh, yl, gh, gl, c->sdd_fh,
+                     c->sdd_fl, c->dd_tw, N, g, tau, kh, kl);
   LAUNCHCHK();
   return 0;
 }
 static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double tau, double g, double* kh, double* kl) {
   int rc;
   if ((rc = dd_setup_enqueue(c, yh, yl, c->status))) return rc;
-  return dd_rhs_tail(c, dd_lane(c), yh, yl, tau, g, kh, kl);
+  return dd_rhs_tail(c, dd_lane(c), yh, yl, tau, g, kh, kl, c->sdd_Gh, c->sdd_Gl,
+                     (unsigned long long*)(c->sdd_fo + 2));
 }
 
 // the lanes of the grouped sweeps (first use): per node, double-double A and Gm, the
@@ -2954,6 +2959,10 @@ static int ensure_sdd_lanes(ww_ctx* c) {
   if (c->sdd_lane) return 0;
   const size_t np = c->np_max, nm = c->n_max;
   const size_t per = 4 * np * np + 8 * nm + 4 * nm;   // A, Gm (hi, lo); 4 point planes (hi, lo); state (hi, lo)
+  // the second group's solve workspace (its solves run on the LU stream) and G phi
+  if (!c->sdd_w2 && (rc = dalloc(c, (void**)&c->sdd_w2, (size_t)DD_WORK * np * c->r_max * 8))) return rc;
+  if (!c->sdd_part2 && (rc = dalloc(c, (void**)&c->sdd_part2, (size_t)2 * DDGV_KS * np * 8))) return rc;
+  if (!c->sdd_G2 && (rc = dalloc(c, (void**)&c->sdd_G2, 2 * nm * 8))) return rc;
   return dalloc(c, (void**)&c->sdd_lane, SDC_NODES * per * 8);
 }
 static DdLane dd_sweep_lane(ww_ctx* c, int m, double** yh, double** yl) {
@@ -2961,7 +2970,10 @@ static DdLane dd_sweep_lane(ww_ctx* c, int m, double** yh, double** yl) {
   double* b = c->sdd_lane + (size_t)m * (4 * nn + 12 * nm);
   *yh = b + 4 * nn + 8 * nm;
   *yl = *yh + 2 * nm;
-  return DdLane{b + 4 * nn, b + 4 * nn + 4 * nm, b, b + nn, b + 2 * nn, b + 3 * nn, dd_fac(c, pipe_set(c, m, false))};
+  const bool second = m >= BLU_GMAX;   // the second group's workspace
+  return DdLane{b + 4 * nn, b + 4 * nn + 4 * nm,   b,
+                b + nn,     b + 2 * nn,            b + 3 * nn,
+                dd_fac(c, pipe_set(c, m, false)), second ? c->sdd_w2 : c->dd_w, second ? c->sdd_part2 : c->dd_part};
 }
 
 // The nodes of one correction sweep (stages s0 .. s0 + SDC_NODES - 1) read only slopes of
@@ -2989,23 +3001,30 @@ static int dd_sweep(ww_ctx* c, int s0, double tau, double g,
     return enqueue_lu_group(c, F, G);
   };
   const hipStream_t main = c->stream, ls = c->lus[0];
+  unsigned long long* mx1 = (unsigned long long*)(c->sdd_fo + 2);
+  unsigned long long* mx2 = (unsigned long long*)(c->sdd_fo + 4);
+  auto tail = [&](int m, double* gh, double* gl, unsigned long long* mx) {
+    return dd_rhs_tail(c, L[m], yh[m], yl[m], tau, g, c->sdd_Kh + (s0 + m) * n2, c->sdd_Kl + (s0 + m) * n2, gh, gl,
+                       mx);
+  };
+  // the second group first: its LU, solves and right-hand sides on the LU stream with
+  // the second workspace, beside the first group's on the main stream
   for (int m = G; m < SDC_NODES; ++m)
     if ((rc = front(m))) return rc;
   HIPCHK(hipEventRecord(c->sdc_ev, main));
   HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
   c->stream = ls;
   rc = lu(G);
+  for (int m = G; m < SDC_NODES && !rc; ++m) rc = tail(m, c->sdd_G2, c->sdd_G2 + c->n_max, mx2);
   c->stream = main;
   if (rc) return rc;
   HIPCHK(hipEventRecord(c->sdc_ev, ls));
   for (int m = 0; m < G; ++m)
     if ((rc = front(m))) return rc;
   if ((rc = lu(0))) return rc;
-  for (int m = 0; m < SDC_NODES; ++m) {
-    if (m == G) HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
-    if ((rc = dd_rhs_tail(c, L[m], yh[m], yl[m], tau, g, c->sdd_Kh + (s0 + m) * n2, c->sdd_Kl + (s0 + m) * n2)))
-      return rc;
-  }
+  for (int m = 0; m < G; ++m)
+    if ((rc = tail(m, c->sdd_Gh, c->sdd_Gl, mx1))) return rc;
+  HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));   // the next stages read this sweep's slopes
   return 0;
 }
 
@@ -3060,6 +3079,8 @@ int shoot_eval_sdc_dd(ww_ctx* c, int N, double h, double tau, double g, const do
   hipLaunchKernelGGL(k_status_reset, dim3(1), dim3(64), 0, c->stream, c->status);
   LAUNCHCHK();
   hipLaunchKernelGGL(k_dd_mx_reset, dim3(1), dim3(64), 0, c->stream, (unsigned long long*)(c->sdd_fo + 2));
+  LAUNCHCHK();
+  hipLaunchKernelGGL(k_dd_mx_reset, dim3(1), dim3(64), 0, c->stream, (unsigned long long*)(c->sdd_fo + 4));
   LAUNCHCHK();
   // the stage rows with this call's dt, the filter symbol, the initial state
   {
