@@ -229,7 +229,7 @@ def run_mesh(reps: int = 2, tuned: bool = True):
     return out
 
 
-def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
+def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32, tuned: bool = True):
     """SDC15 (shoot_eval_sdc) on C4 (N 512, infinite depth, no tension, 256 parameters)
     to T/4 in `sdc_steps` steps (113 right-hand-side evaluations each) against the DOP853
     march of the same workload (800 steps of 12 evaluations), each timed with the
@@ -240,10 +240,12 @@ def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
     damped by the per-step filter 12 times instead of 800.  With the SDC march's error
     against the stored SDC oracle run when present."""
     import torch
+    from paper_1210_5672_amd import autotune
     from paper_1210_5672_amd import workloads as W
     from paper_1210_5672_amd import ww
     w = W.c4()
     ctx = ww.Context(n_max=w.N, r_max=w.M + 1)
+    from_cache = bool(autotune.apply(ctx, w.N, w.M)) if tuned else False   # both marches use the choices
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     p = ww.to_dev(w.params)
 
@@ -262,6 +264,8 @@ def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
     sdc_f, t_sdc_f = timed(lambda: ctx.shoot_eval_sdc(p, w.T, sdc_steps, jacobian=False), reps)
     # f-only on GMRES base solves (no LU): a WW_GMRES context
     cg = ww.Context(n_max=w.N, r_max=w.M + 1, gmres=True)
+    if tuned:
+        autotune.apply(cg, w.N, w.M)
     cg.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     sdc_g, t_sdc_g = timed(lambda: cg.shoot_eval_sdc(p, w.T, sdc_steps, jacobian=False), reps)
     fb_g = cg.fallbacks()
@@ -280,7 +284,7 @@ def run_sdc(reps: int = 2, sdc_steps: int = 12, low_modes: int = 32):
                       "us_per_evaluation": 1e6 * t_sdc_f / ev,
                       "gmres": {"sdc_ms": 1e3 * t_sdc_g, "us_per_evaluation": 1e6 * t_sdc_g / ev, "fallbacks": fb_g,
                                 "r_vs_lu": rel(sdc_g["r"], sdc_f["r"])}},
-           "fallbacks": fb,
+           "fallbacks": fb, "tuning_from_cache": from_cache,
            "sdc_vs_dop853": {"r": rel(sdc["r"], rk["r"]), "drdT": rel(sdc["drdT"], rk["drdT"]),
                              "r_f_only": rel(sdc_f["r"], rk_f["r"]),
                              f"J_modes_1_{L}": rel(sdc["J"][:, :L], rk["J"][:, :L]),
@@ -677,7 +681,7 @@ def main():
     if not args.no_dd:
         out["dd"] = run_dd()
     if not args.no_sdc:
-        out["sdc"] = run_sdc()
+        out["sdc"] = run_sdc(tuned=not args.no_tuning)
     if not args.no_sdc_dd:
         out["sdc_dd"] = run_sdc_dd()
     if not args.no_batch:
