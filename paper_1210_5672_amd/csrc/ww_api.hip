@@ -146,6 +146,10 @@ struct ww_ctx {
   hipEvent_t sdc_evB[SDC_NODES] = {}, sdc_evC[SDC_NODES] = {};
   // the base-chain scratch of the sweep nodes whose chains run on the LU stream (6 Np_max)
   double* sdc_b2 = nullptr;
+  // lagged factors for the predictor's base solves (environment WW_SDC_LAG=0: off); the
+  // LU stream's event per lane (the lagged stages' own LUs, read by their column chains)
+  bool sdc_lag = true;
+  hipEvent_t sdc_evL[SDC_NODES] = {};
   // the base march in double-double (shoot_eval_sdc_dd), allocated at first use: state
   // and stage state (2 n_max, hi and lo), the slopes (SDC_STAGES + 1 slots: the last
   // for the right-hand side at the final state), G phi, the filter symbol, the sparse
@@ -449,6 +453,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->use_graph = !(ng && ng[0] == '1');
     const char* no = std::getenv("WW_NO_OVERLAP");
     c->overlap = !(no && no[0] == '1');
+    const char* sl = std::getenv("WW_SDC_LAG");
+    c->sdc_lag = !(sl && sl[0] == '0');
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
     const char* nl = std::getenv("WW_NREF_LAG");
@@ -545,6 +551,7 @@ void ww_destroy(ww_ctx* c) {
   for (int i = 0; i < SDC_NODES; ++i) {
     if (c->sdc_evB[i]) (void)hipEventDestroy(c->sdc_evB[i]);
     if (c->sdc_evC[i]) (void)hipEventDestroy(c->sdc_evC[i]);
+    if (c->sdc_evL[i]) (void)hipEventDestroy(c->sdc_evL[i]);
   }
   for (hipEvent_t e : c->kev_a) (void)hipEventDestroy(e);
   for (hipEvent_t e : c->kev_b) (void)hipEventDestroy(e);
@@ -2526,6 +2533,7 @@ static int ensure_sdc_groups(ww_ctx* c) {
   for (int i = 0; i < SDC_NODES; ++i) {
     if (!c->sdc_evB[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evB[i], hipEventDisableTiming));
     if (!c->sdc_evC[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evC[i], hipEventDisableTiming));
+    if (!c->sdc_evL[i]) HIPCHK(hipEventCreateWithFlags(&c->sdc_evL[i], hipEventDisableTiming));
   }
   int rc;
   if (!c->sdc_b2 && (rc = dalloc(c, (void**)&c->sdc_b2, (size_t)6 * c->np_max * 8))) return rc;
@@ -2555,12 +2563,15 @@ struct SdcStep {
     double *y0t, *mu0, *gam0, *hg0, *gphi0, *rr0;
   } bm, b2;
 
+  bool lag;   // lagged factors for the predictor's base solves (FP64 factors only)
+
   SdcStep(ww_ctx* cc, bool cl, double d) : c(cc), cols(cl), dt(d), ks(kstride(cc)) {
     for (int m = 0; m < SDC_NODES; ++m) {
       F[m] = pipe_set(c, m, false);
       F[m].lag32 = false;
       F[m].Gm = nullptr;   // the chains read Gm row-major only
     }
+    lag = c->sdc_lag && !F[0].use32 && !(c->fb & WW_FB_DIRECT);
     bm = Bs{c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0};
     const size_t np = c->np_max;
     double* w = c->sdc_b2;
@@ -2580,15 +2591,63 @@ struct SdcStep {
     LAUNCHCHK();
     return 0;
   }
-  // main stream: the lane is free, the stage state's base column, prep, assembly
-  int front(int s, int q) {
+  // main stream: the lane is free, the stage state's base column, prep, assembly (with
+  // the row-major FP64 A of the lagged solves' residuals when want_ar)
+  int front(int s, int q, bool want_ar = false) {
     int rc;
     HIPCHK(hipStreamWaitEvent(c->stream, c->sdc_evC[q], 0));
     if ((rc = combine(s, q, false))) return rc;
     hipLaunchKernelGGL(k_base_prep, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, yn(q), c->K, ysn(q),
                        c->coef, 0, ks, F[q].aux, c->n_max, rhsn(q), c->Np, c->tw, c->N, c->hsurf, c->status);
     LAUNCHCHK();
-    return enqueue_assemble(c, F[q], false);
+    return enqueue_assemble(c, F[q], want_ar);
+  }
+  // A predictor stage on lagged factors (lane q, the factors of lane qb): its own LU on
+  // the LU stream, read only by its column chain (so none without columns: the lane's
+  // next assembly then has nothing to wait for); the base solve x = Mi_b psi refined
+  // by LAG_SWEEPS sweeps r = psi - A x, x += Mi_b r against its own matrix, the 2^-43
+  // test on the final residual (status bit 32: the march is redone on direct factors),
+  // then gamma, G phi and the right-hand side as in the direct chain
+  int lagged(int s, int q, int qb) {
+    int rc;
+    if ((rc = front(s, q, true))) return rc;
+    const hipStream_t main = c->stream, ls = c->lus[0];
+    if (cols) {
+      HIPCHK(hipEventRecord(c->sdc_ev, main));
+      HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
+      c->stream = ls;
+      rc = enqueue_lu(c, F[q]);
+      c->stream = main;
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(c->sdc_evL[q], ls));
+    }
+    const Bs& b = bm;
+    const double* Mb = F[qb].Mi;
+    double* psi = rhsn(q);
+    if ((rc = enqueue_gemm<double>(c, Mb, 0, psi, nullptr, 1.0, b.mu0, 1))) return rc;
+    for (int it = 0; it < LAG_SWEEPS; ++it) {
+      if ((rc = enqueue_gemm<double>(c, F[q].Ar, 0, b.mu0, psi, -1.0, b.rr0, 1))) return rc;
+      if ((rc = enqueue_gemm<double>(c, Mb, 0, b.rr0, b.mu0, 1.0, b.mu0, 1))) return rc;
+    }
+    if ((rc = enqueue_gemm<double>(c, F[q].Ar, 0, b.mu0, psi, -1.0, b.rr0, 1))) return rc;
+    hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, b.mu0, c->Np, 1, b.gam0,
+                       b.hg0, c->tw, c->N, b.rr0, psi, REFINE_TOL, c->status, 32);
+    LAUNCHCHK();
+    if ((rc = enqueue_gemm<double>(c, F[q].Gmr, 0, b.gam0, b.hg0, 1.0, b.gphi0, 1))) return rc;
+    double* kout = c->sdc_K + (size_t)s * ks;
+    if ((rc = sdc_base_rhs(c, ysn(q), b.gphi0, F[q].aux, kout))) return rc;
+    if (!cols) return 0;
+    // the column chain: after the base chain and the stage's own LU
+    HIPCHK(hipEventRecord(c->sdc_evB[q], main));
+    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evB[q], 0));
+    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evL[q], 0));
+    c->stream = c->side;
+    rc = col_chain(s, q, kout);
+    c->stream = main;
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(c->sdc_evC[q], c->side));
+    lastq = q;
+    return 0;
   }
   // the base solve and right-hand side (slot s) on the current stream with scratch b,
   // then the column chain on the column stream
@@ -2656,9 +2715,17 @@ struct SdcStep {
         continue;
       }
       const int q = s % SDC_NODES;
-      if ((rc = front(s, q))) return rc;
-      if ((rc = enqueue_lu(c, F[q]))) return rc;
-      if ((rc = chains(s, q, bm))) return rc;
+      // the second and third RK4 stages of each node interval (half an interval from its
+      // first) solve with the first stage's factors when lagging; the others factor on
+      // the main stream
+      const int sb = s / 4 * 4;
+      if (lag && s < 4 * SDC_NODES && (s % 4 == 1 || s % 4 == 2)) {
+        if ((rc = lagged(s, q, sb % SDC_NODES))) return rc;
+      } else {
+        if ((rc = front(s, q))) return rc;
+        if ((rc = enqueue_lu(c, F[q]))) return rc;
+        if ((rc = chains(s, q, bm))) return rc;
+      }
       ++s;
     }
     // the step's combination in place (after the last column chain) and the filter

@@ -12,6 +12,8 @@
 // the first stage of the correction sweeps (after the predictor's RK4 stages and F at the
 // last predicted node)
 #define SDC_FIRST_SWEEP (4 * SDC_NODES + 1)
+// refinement sweeps of a predictor stage's base solve on lagged factors
+#define LAG_SWEEPS 4
 
 // out[e] = y0[e] + dt sum_{t < cnt} w[t] K[j[t] kstride + e], e < n, in increasing t
 // (out may be y0: every element is read before it is written, by the same thread)

@@ -258,6 +258,7 @@ def test_sdc_segments_two_streams_equal_one(monkeypatch):
     c = SDC_CASES["shallow2"]
     basis, qf, params = _problem(c["N"], c["M"], seed=3)
     outs = []
+    monkeypatch.setenv("WW_SDC_LAG", "0")   # the predictor on its own factors, as the one-stream form
     for serial in (False, True):
         if serial:
             monkeypatch.setenv("WW_NO_OVERLAP", "1")

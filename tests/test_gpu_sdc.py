@@ -87,6 +87,7 @@ def test_two_stream_form_equals_the_one_stream_form(mixed, monkeypatch):
     basis = W.cosine_basis(N, M)
     p = np.linspace(0.03, 0.002, M)
     outs = []
+    monkeypatch.setenv("WW_SDC_LAG", "0")   # the predictor on its own factors, as the one-stream form
     for serial in (False, True):
         if serial:
             monkeypatch.setenv("WW_NO_OVERLAP", "1")
@@ -118,4 +119,26 @@ def test_sdc_f_only_with_gmres_base_solves():
     e = relerr(out["r"].cpu().numpy(), ref["r"])
     print(f"gmres sdc r {e:.2e}", flush=True)
     assert e < TOL and ctx.fallbacks() == 0
+    ctx.close()
+
+
+@pytest.mark.parametrize("jacobian", [True, False])
+@pytest.mark.parametrize("N,h,tau,M,nsteps,T", CASES)
+def test_lagged_predictor_matches_the_oracle(N, h, tau, M, nsteps, T, jacobian):
+    """The two-stream form's predictor stages on lagged factors (the default, FP64
+    factors): against the oracle at the same bar, with no fallback to direct factors."""
+    ww, torch = _ww()
+    basis = W.cosine_basis(N, M)
+    p = np.zeros(M)
+    p[0] = 0.03
+    p[1:] = 1e-3 * np.arange(1, M)
+    qf = np.zeros(2 * N)
+    ctx = ww.Context(n_max=max(N, 64), r_max=M + 1)
+    ctx.shoot_setup(N, h, tau, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    out = ctx.shoot_eval_sdc(ww.to_dev(p), T, nsteps, jacobian=jacobian)
+    ref = S.shoot_eval_sdc(N, h, tau, 1.0, basis, qf, p, T, nsteps, jacobian=jacobian)
+    e = {k: relerr(out[k].cpu().numpy(), ref[k]) for k in (("r", "J") if jacobian else ("r",))}
+    print("lagged predictor errors", e, "fallbacks", ctx.fallbacks(), flush=True)
+    assert max(e.values()) < TOL
+    assert ctx.fallbacks() == 0
     ctx.close()
