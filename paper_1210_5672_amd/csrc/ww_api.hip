@@ -2548,8 +2548,11 @@ static int ensure_sdc_groups(ww_ctx* c) {
 // runs the column chain, overlapping the next stages' base chains and LUs.  A lane is
 // taken again only after its column chain has ended.  The nodes of a correction sweep
 // read only slopes of earlier sweeps: they are assembled together and factored in two
-// groups of four, the second on the LU stream.  Per element the kernels and their order
-// are those of the one-stream form, so the results are the same bit for bit.
+// groups of four, the second on the LU stream, where its base chains follow.  With FP64
+// factors, the predictor's second and third RK4 stages solve their base equations on
+// the factors of their interval's first stage (lagged(), below).  Without those lagged
+// solves (WW_SDC_LAG=0) the kernels and their order per element are those of the
+// one-stream form, and the results are the same bit for bit.
 struct SdcStep {
   ww_ctx* c;
   bool cols;
