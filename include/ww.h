@@ -213,9 +213,9 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
  * surface tension that is far smaller than DOP853's step).  The eight nodes of each
  * correction sweep are factored together and the column chains run on a second stream
  * (results bitwise those of one stream, which a context created with WW_NO_OVERLAP=1
- * and the pivoted and GMRES forms use).  In that two-stream form with FP64 factors, the
- * second and third RK4 stages of each predictor interval solve their base equations
- * with the interval's first factors, refined against their own matrix to the 2^-43
+ * and the pivoted and GMRES forms use).  In that two-stream form the second and third
+ * RK4 stages of each predictor interval solve their base equations with the interval's
+ * first factors, refined against their own matrix to the 2^-43
  * test (a miss redoes the march on direct factors: WW_FB_DIRECT; environment
  * WW_SDC_LAG=0 turns this off); every stage still factors its own matrix for its
  * Jacobian columns.  Outputs, fallbacks and errors as shoot_eval;

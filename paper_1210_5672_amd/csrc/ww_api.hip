@@ -2548,9 +2548,9 @@ static int ensure_sdc_groups(ww_ctx* c) {
 // runs the column chain, overlapping the next stages' base chains and LUs.  A lane is
 // taken again only after its column chain has ended.  The nodes of a correction sweep
 // read only slopes of earlier sweeps: they are assembled together and factored in two
-// groups of four, the second on the LU stream, where its base chains follow.  With FP64
-// factors, the predictor's second and third RK4 stages solve their base equations on
-// the factors of their interval's first stage (lagged(), below).  Without those lagged
+// groups of four, the second on the LU stream, where its base chains follow.  The
+// predictor's second and third RK4 stages solve their base equations on the factors of
+// their interval's first stage (lagged(), below).  Without those lagged
 // solves (WW_SDC_LAG=0) the kernels and their order per element are those of the
 // one-stream form, and the results are the same bit for bit.
 struct SdcStep {
@@ -2566,7 +2566,7 @@ struct SdcStep {
     double *y0t, *mu0, *gam0, *hg0, *gphi0, *rr0;
   } bm, b2;
 
-  bool lag;   // lagged factors for the predictor's base solves (FP64 factors only)
+  bool lag;   // lagged factors for the predictor's base solves
 
   SdcStep(ww_ctx* cc, bool cl, double d) : c(cc), cols(cl), dt(d), ks(kstride(cc)) {
     for (int m = 0; m < SDC_NODES; ++m) {
@@ -2574,7 +2574,7 @@ struct SdcStep {
       F[m].lag32 = false;
       F[m].Gm = nullptr;   // the chains read Gm row-major only
     }
-    lag = c->sdc_lag && !F[0].use32 && !(c->fb & WW_FB_DIRECT);
+    lag = c->sdc_lag && !(c->fb & WW_FB_DIRECT);
     bm = Bs{c->y0t, c->mu0, c->gam0, c->hg0, c->gphi0, c->rr0};
     const size_t np = c->np_max;
     double* w = c->sdc_b2;
@@ -2625,12 +2625,16 @@ struct SdcStep {
       HIPCHK(hipEventRecord(c->sdc_evL[q], ls));
     }
     const Bs& b = bm;
-    const double* Mb = F[qb].Mi;
     double* psi = rhsn(q);
-    if ((rc = enqueue_gemm<double>(c, Mb, 0, psi, nullptr, 1.0, b.mu0, 1))) return rc;
+    // x (+)= Mi_b B with the lagged inverse: FP64, or its FP32 copy in the mixed form
+    auto lag_mul = [&](const double* B, const double* add, double* out) {
+      return F[qb].use32 ? enqueue_gemm<float>(c, F[qb].Mi32, 0, B, add, 1.0, out, 1)
+                         : enqueue_gemm<double>(c, F[qb].Mi, 0, B, add, 1.0, out, 1);
+    };
+    if ((rc = lag_mul(psi, nullptr, b.mu0))) return rc;
     for (int it = 0; it < LAG_SWEEPS; ++it) {
       if ((rc = enqueue_gemm<double>(c, F[q].Ar, 0, b.mu0, psi, -1.0, b.rr0, 1))) return rc;
-      if ((rc = enqueue_gemm<double>(c, Mb, 0, b.rr0, b.mu0, 1.0, b.mu0, 1))) return rc;
+      if ((rc = lag_mul(b.rr0, b.mu0, b.mu0))) return rc;
     }
     if ((rc = enqueue_gemm<double>(c, F[q].Ar, 0, b.mu0, psi, -1.0, b.rr0, 1))) return rc;
     hipLaunchKernelGGL(k_gamma, dim3(1), dim3(WW_NT), fft_lds_bytes(c->N, 4), c->stream, b.mu0, c->Np, 1, b.gam0,

@@ -122,18 +122,20 @@ def test_sdc_f_only_with_gmres_base_solves():
     ctx.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
 @pytest.mark.parametrize("jacobian", [True, False])
 @pytest.mark.parametrize("N,h,tau,M,nsteps,T", CASES)
-def test_lagged_predictor_matches_the_oracle(N, h, tau, M, nsteps, T, jacobian):
-    """The two-stream form's predictor stages on lagged factors (the default, FP64
-    factors): against the oracle at the same bar, with no fallback to direct factors."""
+def test_lagged_predictor_matches_the_oracle(N, h, tau, M, nsteps, T, jacobian, mixed):
+    """The two-stream form's predictor stages on lagged factors (the default; FP64
+    factors, or FP32 ones in the mixed form): against the oracle at the same bar, with
+    no fallback to direct factors."""
     ww, torch = _ww()
     basis = W.cosine_basis(N, M)
     p = np.zeros(M)
     p[0] = 0.03
     p[1:] = 1e-3 * np.arange(1, M)
     qf = np.zeros(2 * N)
-    ctx = ww.Context(n_max=max(N, 64), r_max=M + 1)
+    ctx = ww.Context(n_max=max(N, 64), r_max=M + 1, mixed=mixed)
     ctx.shoot_setup(N, h, tau, 1.0, ww.to_dev(basis), ww.to_dev(qf))
     out = ctx.shoot_eval_sdc(ww.to_dev(p), T, nsteps, jacobian=jacobian)
     ref = S.shoot_eval_sdc(N, h, tau, 1.0, basis, qf, p, T, nsteps, jacobian=jacobian)
