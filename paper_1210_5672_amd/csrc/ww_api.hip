@@ -149,6 +149,7 @@ struct ww_ctx {
   // lagged factors for the predictor's base solves (environment WW_SDC_LAG=0: off); the
   // LU stream's event per lane (the lagged stages' own LUs, read by their column chains)
   bool sdc_lag = true;
+  int sdc_lag_sweeps = LAG_SWEEPS;   // environment WW_SDC_LAG_SWEEPS (0..8)
   hipEvent_t sdc_evL[SDC_NODES] = {};
   // the base march in double-double (shoot_eval_sdc_dd), allocated at first use: state
   // and stage state (2 n_max, hi and lo), the slopes (SDC_STAGES + 1 slots: the last
@@ -455,6 +456,8 @@ int ww_create(ww_ctx** out, int n_max, int r_max, unsigned flags, void* hip_stre
     c->overlap = !(no && no[0] == '1');
     const char* sl = std::getenv("WW_SDC_LAG");
     c->sdc_lag = !(sl && sl[0] == '0');
+    const char* ss = std::getenv("WW_SDC_LAG_SWEEPS");
+    if (ss) c->sdc_lag_sweeps = std::max(0, std::min(8, std::atoi(ss)));
     const char* nr = std::getenv("WW_NREF");
     if (nr) c->nref = std::max(0, std::min(8, std::atoi(nr)));
     const char* nl = std::getenv("WW_NREF_LAG");
@@ -2608,8 +2611,9 @@ struct SdcStep {
   // A predictor stage on lagged factors (lane q, the factors of lane qb): its own LU on
   // the LU stream, read only by its column chain (so none without columns: the lane's
   // next assembly then has nothing to wait for); the base solve x = Mi_b psi refined
-  // by LAG_SWEEPS sweeps r = psi - A x, x += Mi_b r against its own matrix, the 2^-43
-  // test on the final residual (status bit 32: the march is redone on direct factors),
+  // by LAG_SWEEPS sweeps (environment WW_SDC_LAG_SWEEPS) r = psi - A x, x += Mi_b r
+  // against its own matrix, the 2^-43 test on the final residual (status bit 32: the
+  // march is redone on direct factors),
   // then gamma, G phi and the right-hand side as in the direct chain
   int lagged(int s, int q, int qb) {
     int rc;
@@ -2632,7 +2636,7 @@ struct SdcStep {
                          : enqueue_gemm<double>(c, F[qb].Mi, 0, B, add, 1.0, out, 1);
     };
     if ((rc = lag_mul(psi, nullptr, b.mu0))) return rc;
-    for (int it = 0; it < LAG_SWEEPS; ++it) {
+    for (int it = 0; it < c->sdc_lag_sweeps; ++it) {
       if ((rc = enqueue_gemm<double>(c, F[q].Ar, 0, b.mu0, psi, -1.0, b.rr0, 1))) return rc;
       if ((rc = lag_mul(b.rr0, b.mu0, b.mu0))) return rc;
     }

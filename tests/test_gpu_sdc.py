@@ -144,3 +144,32 @@ def test_lagged_predictor_matches_the_oracle(N, h, tau, M, nsteps, T, jacobian, 
     assert max(e.values()) < TOL
     assert ctx.fallbacks() == 0
     ctx.close()
+
+
+def test_lagged_predictor_fallback_and_strict(monkeypatch):
+    """Failure handling of the lagged predictor solves, forced from the host: with no
+    refinement sweep (WW_SDC_LAG_SWEEPS=0) the lagged solves miss the 2^-43 test; the
+    march is redone on direct factors (WW_FB_DIRECT) and meets the oracle, and a
+    WW_STRICT context reports WW_EREFINE instead."""
+    ww, torch = _ww()
+    monkeypatch.setenv("WW_SDC_LAG_SWEEPS", "0")
+    N, h, tau, M, nsteps, T = CASES[1]
+    basis = W.cosine_basis(N, M)
+    p = np.zeros(M)
+    p[0] = 0.03
+    p[1:] = 1e-3 * np.arange(1, M)
+    qf = np.zeros(2 * N)
+    ref = S.shoot_eval_sdc(N, h, tau, 1.0, basis, qf, p, T, nsteps)
+    ctx = ww.Context(n_max=128, r_max=M + 1)
+    ctx.shoot_setup(N, h, tau, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    out = ctx.shoot_eval_sdc(ww.to_dev(p), T, nsteps)
+    assert ctx.fallbacks() == ww.WW_FB_DIRECT, ctx.fallbacks()
+    for k in ("r", "J"):
+        assert relerr(out[k].cpu().numpy(), ref[k]) < TOL, k
+    ctx.close()
+    ctx = ww.Context(n_max=128, r_max=M + 1, strict=True)
+    ctx.shoot_setup(N, h, tau, 1.0, ww.to_dev(basis), ww.to_dev(qf))
+    with pytest.raises(ww.WWError) as e:
+        ctx.shoot_eval_sdc(ww.to_dev(p), T, nsteps)
+    assert e.value.name == "WW_EREFINE"
+    ctx.close()
