@@ -3030,7 +3030,8 @@ static int dd_rhs(ww_ctx* c, const double* yh, const double* yl, double tau, dou
 }
 
 // the lanes of the grouped sweeps (first use): per node, double-double A and Gm, the
-// per-point quantities and the stage state; the ring's factor sets, the LU stream
+// per-point quantities and the stage state; the second group's solve workspace; the
+// ring's factor sets, the LU stream
 static int ensure_sdd_lanes(ww_ctx* c) {
   int rc;
   if ((rc = ensure_sdc_groups(c))) return rc;
@@ -3056,8 +3057,9 @@ static DdLane dd_sweep_lane(ww_ctx* c, int m, double** yh, double** yl) {
 
 // The nodes of one correction sweep (stages s0 .. s0 + SDC_NODES - 1) read only slopes of
 // earlier sweeps: each node's stage state, per-point quantities and double-double
-// assembly in its lane, the FP64 LUs in two groups of four (the second on the LU stream,
-// beside the first group's LU and solves), then each node's solve and right-hand side.
+// assembly in its lane, the FP64 (or FP32) LUs in two groups of four, then each node's
+// solve and right-hand side.  The second group's LU, solves and right-hand sides run on
+// the LU stream with the second workspace, beside the first group's on the main stream.
 // The kernels per lane are those of the stage-by-stage form: the same bits.
 static int dd_sweep(ww_ctx* c, int s0, double tau, double g,
                     const std::function<int(int, double*, double*)>& combine) {
