@@ -218,7 +218,8 @@ int shoot_eval(ww_ctx *ctx, const double *params, double T, int nsteps, double *
  * first factors, refined against their own matrix to the 2^-43
  * test (a miss redoes the march on direct factors: WW_FB_DIRECT; environment
  * WW_SDC_LAG=0 turns this off); every stage still factors its own matrix for its
- * Jacobian columns.  Outputs, fallbacks and errors as shoot_eval;
+ * Jacobian columns.  Without columns, the sweeps after the first solve each node on the
+ * factors the first sweep made for it, refined the same way.  Outputs, fallbacks and errors as shoot_eval;
  * a failure's location names the step (its stage field is 0).  Synchronises.  Work
  * arrays are allocated at the first call: 113 x 2 n_max r_max doubles of stage slopes,
  * 17 x 2 n_max r_max doubles of stage states, and eight factor sets of n_max^2 size.

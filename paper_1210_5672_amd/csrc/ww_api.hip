@@ -2628,7 +2628,26 @@ struct SdcStep {
       if (rc) return rc;
       HIPCHK(hipEventRecord(c->sdc_evL[q], ls));
     }
-    const Bs& b = bm;
+    if ((rc = lagged_base(s, q, qb, bm))) return rc;
+    double* kout = c->sdc_K + (size_t)s * ks;
+    if (!cols) return 0;
+    // the column chain: after the base chain and the stage's own LU
+    HIPCHK(hipEventRecord(c->sdc_evB[q], main));
+    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evB[q], 0));
+    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evL[q], 0));
+    c->stream = c->side;
+    rc = col_chain(s, q, kout);
+    c->stream = main;
+    if (rc) return rc;
+    HIPCHK(hipEventRecord(c->sdc_evC[q], c->side));
+    lastq = q;
+    return 0;
+  }
+  // The base solve of stage s (lane q, assembled with its row-major A) on the inverse of
+  // lane qb, refined against its own matrix (the 2^-43 test, status bit 32), then gamma,
+  // G phi and the right-hand side into slot s, on the current stream with scratch b
+  int lagged_base(int s, int q, int qb, const Bs& b) {
+    int rc;
     double* psi = rhsn(q);
     // x (+)= Mi_b B with the lagged inverse: FP64, or its FP32 copy in the mixed form
     auto lag_mul = [&](const double* B, const double* add, double* out) {
@@ -2645,20 +2664,7 @@ struct SdcStep {
                        b.hg0, c->tw, c->N, b.rr0, psi, REFINE_TOL, c->status, 32);
     LAUNCHCHK();
     if ((rc = enqueue_gemm<double>(c, F[q].Gmr, 0, b.gam0, b.hg0, 1.0, b.gphi0, 1))) return rc;
-    double* kout = c->sdc_K + (size_t)s * ks;
-    if ((rc = sdc_base_rhs(c, ysn(q), b.gphi0, F[q].aux, kout))) return rc;
-    if (!cols) return 0;
-    // the column chain: after the base chain and the stage's own LU
-    HIPCHK(hipEventRecord(c->sdc_evB[q], main));
-    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evB[q], 0));
-    HIPCHK(hipStreamWaitEvent(c->side, c->sdc_evL[q], 0));
-    c->stream = c->side;
-    rc = col_chain(s, q, kout);
-    c->stream = main;
-    if (rc) return rc;
-    HIPCHK(hipEventRecord(c->sdc_evC[q], c->side));
-    lastq = q;
-    return 0;
+    return sdc_base_rhs(c, ysn(q), b.gphi0, F[q].aux, c->sdc_K + (size_t)s * ks);
   }
   // the base solve and right-hand side (slot s) on the current stream with scratch b,
   // then the column chain on the column stream
@@ -2697,6 +2703,26 @@ struct SdcStep {
     const int G = BLU_GMAX;
     const hipStream_t main = c->stream, ls = c->lus[0];
     // the second group first, so that its LU runs beside the first group's work
+    // Without columns, the sweeps after the first solve each node on the factors the
+    // first sweep made for the same node (the node's surface moves only by the shrinking
+    // Picard corrections), refined to the 2^-43 test; no LU
+    if (!cols && lag && s0 > SDC_FIRST_SWEEP) {
+      for (int m = G; m < SDC_NODES; ++m)
+        if ((rc = front(s0 + m, m, true))) return rc;
+      HIPCHK(hipEventRecord(c->sdc_ev, main));
+      HIPCHK(hipStreamWaitEvent(ls, c->sdc_ev, 0));
+      c->stream = ls;
+      for (int m = G; m < SDC_NODES && !rc; ++m) rc = lagged_base(s0 + m, m, m, b2);
+      c->stream = main;
+      if (rc) return rc;
+      HIPCHK(hipEventRecord(c->sdc_ev, ls));
+      for (int m = 0; m < G; ++m) {
+        if ((rc = front(s0 + m, m, true))) return rc;
+        if ((rc = lagged_base(s0 + m, m, m, bm))) return rc;
+      }
+      HIPCHK(hipStreamWaitEvent(main, c->sdc_ev, 0));
+      return 0;
+    }
     // (its base chains follow on the LU stream with the second scratch set)
     for (int m = G; m < SDC_NODES; ++m)
       if ((rc = front(s0 + m, m))) return rc;

@@ -213,17 +213,20 @@ def test_sdc15_config4_full(mixed):
     ctx.close()
 
 
-def test_sdc15_config4_f_only_gmres():
-    """C4 to T/4 in 12 SDC15 steps without Jacobian columns, on GMRES base solves (a
-    WW_GMRES context): r, dr/dT and f against the stored SDC oracle run (the base march
-    does not depend on the columns) with the bounds of check()."""
+@pytest.mark.parametrize("gmres", [False, True])
+def test_sdc15_config4_f_only(gmres):
+    """C4 to T/4 in 12 SDC15 steps without Jacobian columns: on LU factors (the
+    predictor's lagged solves, and the sweeps after the first on the first sweep's
+    factors) or on GMRES base solves (a WW_GMRES context); r, dr/dT and f against the
+    stored SDC oracle run (the base march does not depend on the columns) with the
+    bounds of check(), no fallback."""
     import torch
     fx = _load("c4s")
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     from paper_1210_5672_amd import ww
     w = workload("c4s")
-    ctx = ww.Context(n_max=w.N, r_max=w.M + 1, gmres=True)
+    ctx = ww.Context(n_max=w.N, r_max=w.M + 1, gmres=gmres)
     ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
     res = _np(ctx.shoot_eval_sdc(ww.to_dev(w.params), w.T, w.nsteps, jacobian=False))
     assert ctx.fallbacks() == 0, ctx.fallbacks()
@@ -232,7 +235,7 @@ def test_sdc15_config4_f_only_gmres():
     e = {"r": rel(res["r"], fx["r"]), "drdT": rel(res["drdT"], fx["drdT"]),
          "f": abs(res["f"] - float(fx["f"])) / float(fx["f"])}
     bound = {"r": max(TOL, 2 * fl["r"]), "drdT": max(TOL * kappa_F(w), 2 * fl["drdT"]), "f": max(TOL, 2 * fl["f"])}
-    print("c4s f-only gmres errors", e, "bounds", bound, flush=True)
+    print(f"c4s f-only (gmres={gmres}) errors", e, "bounds", bound, flush=True)
     for k in e:
         assert e[k] < bound[k], (k, e[k], bound[k])
     ctx.close()
