@@ -31,7 +31,8 @@ Workloads: c1, c2, c3, c4; c5_IIxS, the first S steps of batched instance II (th
 largest grids); c5_II, batched instance II marched to T/4 (instances whose oracle
 run is affordable); c6, the two time segments on non-uniform meshes (the mesh oracle,
 oracle/mesh_oracle.py, with the same FP64 alternates); c4s, C4 marched to T/4 with 12
-steps of SDC15 (the SDC oracle, oracle/sdc_oracle.py, with the same FP64 alternates).
+steps of SDC15 (the SDC oracle, oracle/sdc_oracle.py, with the same FP64 alternates);
+c6s, the C6 segments marched by 4 + 15 SDC15 steps (the mesh oracle's SDC march).
 """
 import os
 import subprocess
@@ -63,7 +64,9 @@ C5_FULL = {"c5_00": 0, "c5_07": 7, "c5_08": 8, "c5_26": 26, "c5_27": 27}
 DD_SPLIT = {"c1": 1, "c2": 4}
 # workloads marched with SDC15: (base workload, SDC steps to T/4)
 SDC_RUNS = {"c4s": ("c4", 12)}
-ALL = ("c1", "c2", "c4", "c3", *C5_FULL, *C5_PREFIX, "c6", *SDC_RUNS)
+# segmented workloads marched with SDC15: (base workload, SDC steps of each segment)
+SDC_SEG_RUNS = {"c6s": ("c6", (4, 15))}
+ALL = ("c1", "c2", "c4", "c3", *C5_FULL, *C5_PREFIX, "c6", *SDC_RUNS, *SDC_SEG_RUNS)
 
 
 def workload(name):
@@ -81,6 +84,12 @@ def workload(name):
         w = W.CONFIGS[base]()
         return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T, steps, w.params, w.basis, w.q_fixed,
                           description=f"{base} to T/4 with {steps} SDC15 steps")
+    if name in SDC_SEG_RUNS:
+        base, steps = SDC_SEG_RUNS[name]
+        w = W.CONFIGS[base]()
+        segs = [dict(q, nsteps=n) for q, n in zip(w.segments, steps)]
+        return W.Workload(name, w.N, w.h, w.tau, w.g, w.M, w.T, sum(steps), w.params, w.basis, w.q_fixed,
+                          segments=segs, description=f"{base} segments with {steps} SDC15 steps")
     return W.CONFIGS[name]()
 
 
@@ -108,7 +117,8 @@ def run(name, tag, cols=None):
     elif w.segments is not None:
         if cols is not None:
             raise SystemExit("column splits are for uniform-mesh workloads")
-        res = MO.shoot_eval_segments(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.segments, ar=ar)
+        res = MO.shoot_eval_segments(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.segments, ar=ar,
+                                     scheme="sdc" if name in SDC_SEG_RUNS else "dop853")
     elif cols is None:
         res = O.shoot_eval(w.N, w.h, w.tau, w.g, w.basis, w.q_fixed, w.params, w.T, w.nsteps, ar=ar)
     else:

@@ -269,6 +269,31 @@ def test_segments_on_non_uniform_meshes(mixed):
     ctx.close()
 
 
+@pytest.mark.parametrize("mixed", [False, True])
+def test_sdc15_segments_c6_full(mixed):
+    """C6's two segments (N 768, then 1024 on the mesh refined near x = pi; 200
+    parameters) marched by 4 + 15 SDC15 steps (shoot_eval_segments_sdc) against the mesh
+    oracle's SDC march (tests/golden/c6s_oracle.npz), every column, with the bounds of
+    check() (the floor from the same four alternate roundings)."""
+    import dataclasses
+
+    import torch
+    fx = _load("c6s")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1210_5672_amd import ww
+    print(f"full-size parity c6s (SDC15 segments) mixed={mixed}", flush=True)
+    w = W.c6()
+    segs = [dict(q, nsteps=n) for q, n in zip(w.segments, (4, 15))]
+    ctx = ww.Context(n_max=max(q["N"] for q in segs), r_max=w.M + 1, mixed=mixed)
+    ctx.shoot_setup(w.N, w.h, w.tau, w.g, ww.to_dev(w.basis), ww.to_dev(w.q_fixed))
+    res = _np(ctx.shoot_eval_segments_sdc(ww.to_dev(w.params), w.T, segs))
+    print("fallbacks", ctx.fallbacks(), flush=True)
+    assert ctx.fallbacks() in (0, ww.WW_FB_DIRECT)
+    check(fx, dataclasses.replace(w, N=segs[-1]["N"]), res)
+    ctx.close()
+
+
 def _batch(names, mixed=False):
     import torch
     if not torch.cuda.is_available():
